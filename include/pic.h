@@ -1,0 +1,231 @@
+/* pic.h -- C-ABI of the particle-mesh hot path of an electrostatic IFE-PIC
+ * step on one AMD Instinct MI355X (gfx950).
+ *
+ * The library performs, for every macro-particle, the particle half of the PIC
+ * loop (§2.1): trilinear gather of the node electric field ("gather"),
+ * leapfrog push ("particle-push"), removal at the outer boundary (§3.1.3: the
+ * particle is absorbed and removed) or at the object / terrain (§5.2.2: the
+ * particle is collected and its charge accumulated for surface charging), and
+ * trilinear weighting of the charge back to the mesh nodes ("scatter"), whose
+ * result is the source term rho of eq. (2.1). The field solve of the loop (the
+ * IFE discretisation, PCG and domain decomposition of §2.3) is not part of the
+ * library: the node field is an input (pic_set_node_E).
+ *
+ * Units and mesh. The PIC mesh is globally uniform (§2.2) with nx*ny*nz cubic
+ * cells of edge h starting at `origin`; nodes are numbered
+ * node(i,j,k) = i + (nx+1)*(j + (ny+1)*k), x fastest. The domain is the
+ * half-open box [0, n*h) per axis. Normalised units as in §3.1.1 / §5.2.1.
+ *
+ * Step definition (one call of pic_step advances every particle by dt):
+ *   1. gather   E_p = sum_n W_n E[node_n], trilinear weights of the cell
+ *   2. kick     v  += (q/m) dt E_p          (v stored at half steps)
+ *   3. drift    x  += v dt
+ *   4. box      a particle outside the box is removed, counted per face
+ *               (faces 0..5 = x-, x+, y-, y+, z-, z+; first axis in x, y, z
+ *               order, lower face first). With the crater terrain, z < 0 is a
+ *               collection, not an escape.
+ *   5. object   sphere: |x - c| <= R; crater: z < 0, or z <= z_flat and the
+ *               point lies outside the bowl sphere of radius
+ *               Rc = (a^2 + d^2) / (2d) centred at height z_flat - d + Rc on the
+ *               crater axis (a flat plane at z_flat with a spherical bowl of
+ *               radius a and depth d, a height function z = z(x, y) as in
+ *               §5.2.1). A collected particle is removed and counted in its bin
+ *               (sphere: one bin; crater: the surface column
+ *               (clamp(floor x), clamp(floor y)), bin = ix + nx*iy).
+ *   6. deposit  rho is zeroed, then every remaining particle adds q*w*W_n to
+ *               its 8 cell nodes at its new position; rho = sum / h^3.
+ * Fixed-point deposit: each contribution is rounded half-to-even to an int64 at
+ * scale 2^32, corner 7 receiving llrint(q*w*2^32) minus the other seven, so the
+ * total is conserved exactly and the result is independent of summation order.
+ *
+ * Conventions.
+ *   - Every call validates its arguments before changing any state; on error the
+ *     state is unchanged and pic_last_error() describes the problem.
+ *   - Host pointers are borrowed for the duration of the call; the caller keeps
+ *     ownership. Device pointers (the *_dev calls) are read before the call
+ *     returns (the call synchronises its stream).
+ *   - A context is used from one host thread at a time.
+ *   - pic_step only enqueues work on the context's stream and returns; the
+ *     pic_get_* calls synchronise the stream and report device-side errors
+ *     (PIC_E_RANGE: a non-finite or runaway particle position) raised since
+ *     the last synchronising call.
+ *   - The library owns all device memory it allocates (hipMalloc) and frees it
+ *     in pic_destroy.
+ */
+#ifndef PIC_H_
+#define PIC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_MAX_SPECIES 4
+#define PIC_NUM_FACES 6
+
+typedef struct pic_ctx pic_ctx;
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_E_INVALID = -1, /* a bad argument; nothing changed */
+  PIC_E_NOMEM = -2,   /* device memory could not be allocated; nothing changed */
+  PIC_E_DEVICE = -3,  /* no usable GPU, or a HIP runtime error */
+  PIC_E_STATE = -4,   /* call out of order (e.g. pic_step before pic_set_node_E) */
+  PIC_E_RANGE = -5    /* a particle position became non-finite or moved > 2^20 cells */
+} pic_status;
+
+/* Particle representation on the device. */
+typedef enum {
+  PIC_REPR_FP64 = 0,      /* FP64 positions and velocities (48 B per particle) */
+  PIC_REPR_FP32_ABS = 1,  /* FP32 positions (cell units) and velocities (24 B) */
+  PIC_REPR_FP32_CELL = 2  /* int32 cell + FP32 in-cell offsets + FP32 velocities (28 B) */
+} pic_repr;
+
+/* Charge deposition arithmetic. */
+typedef enum {
+  PIC_DEP_FIXED64 = 0,     /* int64 fixed point, scale 2^32: deterministic */
+  PIC_DEP_ATOMIC_FP32 = 1, /* FP32 atomic sums: order-dependent rounding */
+  PIC_DEP_ATOMIC_FP64 = 2  /* FP64 atomic sums: order-dependent rounding */
+} pic_deposit;
+
+typedef enum { PIC_OBJ_NONE = 0, PIC_OBJ_SPHERE = 1, PIC_OBJ_CRATER = 2 } pic_object_kind;
+
+typedef struct {
+  int32_t kind;      /* pic_object_kind */
+  double center[3];  /* sphere centre; crater axis at (center[0], center[1]) */
+  double radius;     /* sphere radius */
+  double z_flat;     /* crater: height of the flat ground */
+  double rim_radius; /* crater: bowl radius at the flat level (a) */
+  double depth;      /* crater: bowl depth below the flat level (d > 0) */
+} pic_object;
+
+typedef struct {
+  double q;      /* charge of one physical particle */
+  double m;      /* mass (> 0) */
+  double weight; /* physical particles per macro-particle */
+} pic_species;
+
+typedef struct {
+  int32_t nx, ny, nz;  /* cells per axis, 1..1023 */
+  double h;            /* cell edge (> 0) */
+  double origin[3];    /* position of node (0,0,0) */
+  double dt;           /* time step (> 0) */
+  int32_t n_species;   /* 1..PIC_MAX_SPECIES */
+  pic_species species[PIC_MAX_SPECIES];
+  pic_object object;
+  int32_t repr;          /* pic_repr */
+  int32_t deposit;       /* pic_deposit */
+  int32_t sort_interval; /* K >= 1: particles are re-bucketed by tile every K steps;
+                            0 selects the default (4) */
+  int64_t capacity[PIC_MAX_SPECIES]; /* max particles per species (device memory is
+                                        reserved for this many, double-buffered) */
+  void *stream;          /* hipStream_t to enqueue on, or NULL for a library stream */
+} pic_config;
+
+/* Creates a context: validates cfg and allocates device memory for the mesh
+ * (node E, rho), tallies and per-species particle buffers of cfg->capacity.
+ * Returns PIC_E_NOMEM if the device cannot hold it. *out is set on success. */
+pic_status pic_create(const pic_config *cfg, pic_ctx **out);
+
+/* Frees the context and all its device memory (synchronises its stream). NULL is
+ * ignored. */
+void pic_destroy(pic_ctx *ctx);
+
+/* Replaces the particles of one species by n particles at physical positions
+ * (x, y, z) with velocities (vx, vy, vz) taken at t - dt/2 (the leapfrog
+ * stagger). Host arrays of n doubles. ids (nullable) are n int64 labels carried
+ * through sorting and returned by pic_get_particles; without ids the particle
+ * order is unspecified after a step. Every position must lie inside the box
+ * (PIC_E_INVALID otherwise); n must not exceed the species capacity. Loading a
+ * species resets its collected counts (tally column) and escape counters.
+ * Values are rounded to the representation (round to nearest). Synchronous. */
+pic_status pic_load_particles(pic_ctx *ctx, int32_t species, int64_t n, const double *x,
+                              const double *y, const double *z, const double *vx,
+                              const double *vy, const double *vz, const int64_t *ids);
+
+/* As pic_load_particles, from device arrays of n floats (and n int64 ids, or
+ * NULL) in the GPU's memory. Positions outside the box raise PIC_E_INVALID.
+ * Synchronous on the context's stream. */
+pic_status pic_load_particles_f32_dev(pic_ctx *ctx, int32_t species, int64_t n,
+                                      const float *x, const float *y, const float *z,
+                                      const float *vx, const float *vy, const float *vz,
+                                      const int64_t *ids);
+
+/* Sets the node electric field: three host arrays of (nx+1)(ny+1)(nz+1) doubles,
+ * x fastest. The FP32 representations round it to float. Non-finite values give
+ * PIC_E_INVALID. Synchronous. */
+pic_status pic_set_node_E(pic_ctx *ctx, const double *Ex, const double *Ey, const double *Ez);
+
+/* As pic_set_node_E, from three device arrays of floats. Synchronous. */
+pic_status pic_set_node_E_f32_dev(pic_ctx *ctx, const float *Ex, const float *Ey,
+                                  const float *Ez);
+
+/* Advances all particles by nsteps steps (enqueued on the context's stream; no
+ * host synchronisation). nsteps == 0 only deposits rho at the current positions
+ * (the initial scatter). rho always holds the deposit of the last step.
+ * PIC_E_STATE before pic_set_node_E. */
+pic_status pic_step(pic_ctx *ctx, int32_t nsteps);
+
+/* Blocks until the context's stream is idle; reports device-side errors. */
+pic_status pic_synchronize(pic_ctx *ctx);
+
+/* Charge density at the nodes (host array of (nx+1)(ny+1)(nz+1) doubles), and,
+ * in the fixed-point mode, the raw int64 sums at scale 2^32 (nullable; must be
+ * NULL in the other modes). rho = rho_fixed * 2^-32 / h^3. Synchronises. */
+pic_status pic_get_rho(pic_ctx *ctx, double *rho, int64_t *rho_fixed);
+
+/* Number of collection bins: 0 (no object), 1 (sphere), nx*ny (crater). */
+int64_t pic_num_bins(const pic_ctx *ctx);
+
+/* Collected charge per bin, sum over species of q*w*count, in FP64 (nbins
+ * doubles, nbins == pic_num_bins), and optionally the raw counts
+ * counts[bin*n_species + s] (nullable). Cumulative since the species were
+ * loaded. This is the surface charge that sets the non-homogeneous flux jump
+ * q(X) of eq. (2.5). Synchronises. */
+pic_status pic_get_surface_charge(pic_ctx *ctx, int64_t nbins, double *charge, int64_t *counts);
+
+/* Per-species counters (host arrays of n_species, n_species, 6*n_species int64,
+ * each nullable): particles alive, collected at the object, and escaped
+ * through face f (escaped[f*n_species + s]). Synchronises. */
+pic_status pic_get_counters(pic_ctx *ctx, int64_t *alive, int64_t *absorbed, int64_t *escaped);
+
+/* Copies the alive particles of one species to host arrays of capacity cap
+ * (physical positions and half-step velocities as doubles; ids nullable, and
+ * only available if ids were loaded). *n_out receives the number of alive
+ * particles; if it exceeds cap nothing is copied and PIC_E_INVALID is
+ * returned. Order is the device's memory order. Synchronises. */
+pic_status pic_get_particles(pic_ctx *ctx, int32_t species, int64_t cap, int64_t *n_out,
+                             double *x, double *y, double *z, double *vx, double *vy,
+                             double *vz, int64_t *ids);
+
+/* Kernel timing for measurement: when enabled, the library records HIP events
+ * around each launch of its kernels on the context's stream. */
+typedef struct {
+  int64_t step_launches;  /* fused gather/push/collect/deposit kernel */
+  double step_ms;         /* summed event time of those launches */
+  int64_t sort_launches;  /* re-bucketing passes (each: count, scan, scatter) */
+  double sort_ms;
+  int64_t clear_launches; /* rho clears */
+  double clear_ms;
+  int64_t particle_steps; /* particles alive at the start of each step, summed */
+} pic_profile;
+
+/* Enables (on != 0) or disables event timing and resets the totals. */
+pic_status pic_profile_enable(pic_ctx *ctx, int32_t on);
+/* Synchronises and returns the totals since pic_profile_enable. */
+pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
+
+/* Message of the last failed call on ctx (or of the last failed pic_create when
+ * ctx is NULL). Never NULL. */
+const char *pic_last_error(const pic_ctx *ctx);
+
+/* Static name of a status code. */
+const char *pic_status_string(pic_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H_ */

@@ -1,0 +1,245 @@
+"""ctypes binding of the CPU oracle (``oracle/pic_oracle.cpp``).
+
+Test infrastructure: only the tests, the smoke check and the CPU-baseline leg of
+the benchmark import this module. It imports nothing from the GPU package.
+
+The oracle runs the explicit PIC step of §2.1 (gather, leapfrog push, boundary
+and object removal of §3.1.3 / §5.2.2, trilinear charge deposit) on the CPU in
+FP64, or in one of two FP32 mirror forms with the same expression order.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "pic_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+REPR = {"fp64": 0, "fp32_abs": 1, "fp32_cell": 2}
+DEPOSIT = {"fixed64": 0, "fp32": 1, "fp64": 2}
+OBJECT = {"none": 0, "sphere": 1, "crater": 2}
+
+# -ffp-contract=off: no multiply-add is fused unless written as fma.
+CFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build() -> str:
+    """Compile the oracle shared library with g++ (always recompiles)."""
+    tmp = LIB + ".tmp"
+    subprocess.check_call(["g++", *CFLAGS, SRC, "-o", tmp])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("h", ctypes.c_double), ("origin", ctypes.c_double * 3), ("dt", ctypes.c_double),
+        ("n_species", ctypes.c_int32),
+        ("q", ctypes.c_double * 4), ("m", ctypes.c_double * 4), ("w", ctypes.c_double * 4),
+        ("obj_kind", ctypes.c_int32), ("center", ctypes.c_double * 3), ("radius", ctypes.c_double),
+        ("z_flat", ctypes.c_double), ("rim_radius", ctypes.c_double), ("depth", ctypes.c_double),
+        ("repr", ctypes.c_int32), ("deposit", ctypes.c_int32),
+    ]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [
+        ("x", _dp), ("y", _dp), ("z", _dp), ("vx", _dp), ("vy", _dp), ("vz", _dp),
+        ("fate", _i32p), ("where", _i32p), ("when", _i32p),
+        ("rho", _dp), ("rho_fixed", _i64p), ("tally", _i64p), ("escaped", _i64p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        L.orc_run.restype = ctypes.c_int
+        L.orc_run.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int64, _i32p] + [_dp] * 9 + [
+            ctypes.c_int32, ctypes.POINTER(_Out)]
+        L.orc_weights_f64.argtypes = [_dp, _dp]
+        L.orc_weights_f32.argtypes = [_fp, _fp]
+        L.orc_gather_f64.argtypes = [ctypes.c_int32] * 3 + [_dp] * 3 + [_i32p, _dp, _dp]
+        L.orc_fixed_contrib_f64.argtypes = [ctypes.c_double, _dp, _i64p]
+        L.orc_fixed_contrib_f32.argtypes = [ctypes.c_float, _fp, _i64p]
+        L.orc_object_hit.restype = ctypes.c_int32
+        L.orc_object_hit.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Problem:
+    """Mesh, species, object and numerics of one run (cell units when h = 1)."""
+    nx: int
+    ny: int
+    nz: int
+    dt: float
+    q: list
+    m: list
+    w: list = None
+    h: float = 1.0
+    origin: tuple = (0.0, 0.0, 0.0)
+    obj: str = "none"
+    center: tuple = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    z_flat: float = 0.0
+    rim_radius: float = 0.0
+    depth: float = 0.0
+    repr: str = "fp64"
+    deposit: str = "fixed64"
+
+    @property
+    def n_species(self):
+        return len(self.q)
+
+    @property
+    def nodes(self):
+        return (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+
+    @property
+    def nbins(self):
+        return self.nx * self.ny if self.obj == "crater" else 1
+
+    def cstruct(self) -> _Cfg:
+        c = _Cfg()
+        c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
+        c.h = self.h
+        c.origin[:] = list(self.origin)
+        c.dt = self.dt
+        c.n_species = self.n_species
+        w = self.w if self.w is not None else [1.0] * self.n_species
+        for s in range(self.n_species):
+            c.q[s], c.m[s], c.w[s] = self.q[s], self.m[s], w[s]
+        c.obj_kind = OBJECT[self.obj]
+        c.center[:] = list(self.center)
+        c.radius = self.radius
+        c.z_flat, c.rim_radius, c.depth = self.z_flat, self.rim_radius, self.depth
+        c.repr = REPR[self.repr]
+        c.deposit = DEPOSIT[self.deposit]
+        return c
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    v: np.ndarray          # (n, 3)
+    fate: np.ndarray       # 0 alive, 1 escaped, 2 absorbed
+    where: np.ndarray
+    when: np.ndarray
+    rho: np.ndarray
+    rho_fixed: np.ndarray  # None unless fixed-point mode
+    tally: np.ndarray      # (nbins, n_species)
+    escaped: np.ndarray    # (6, n_species)
+    extra: dict = field(default_factory=dict)
+
+    def charge(self, prob: Problem) -> np.ndarray:
+        """Collected charge per bin: sum over species of q*w*count, in FP64."""
+        w = prob.w if prob.w is not None else [1.0] * prob.n_species
+        chg = np.array([prob.q[s] * w[s] for s in range(prob.n_species)], dtype=np.float64)
+        return self.tally.astype(np.float64) @ chg
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def run(prob: Problem, species, x, v, E, nsteps: int) -> Result:
+    """Run the oracle. x, v: (n, 3) physical positions and half-step velocities;
+    E: (3, nodes) node field, x fastest; species: (n,) int."""
+    L = lib()
+    n = len(species)
+    sp = _c(species, np.int32)
+    x = _c(x, np.float64).reshape(n, 3)
+    v = _c(v, np.float64).reshape(n, 3)
+    cols = [_c(x[:, d], np.float64) for d in range(3)] + [_c(v[:, d], np.float64) for d in range(3)]
+    E = [_c(E[d], np.float64) for d in range(3)]
+    for e in E:
+        if e.size != prob.nodes:
+            raise ValueError("node field has the wrong size")
+    ox = [np.empty(n) for _ in range(6)]
+    fate = np.empty(n, np.int32)
+    where = np.empty(n, np.int32)
+    when = np.empty(n, np.int32)
+    rho = np.empty(prob.nodes)
+    rho_fixed = np.empty(prob.nodes, np.int64) if prob.deposit == "fixed64" else None
+    tally = np.zeros((prob.nbins, prob.n_species), np.int64)
+    esc = np.zeros((6, prob.n_species), np.int64)
+    out = _Out()
+    for name, arr in zip(("x", "y", "z", "vx", "vy", "vz"), ox):
+        setattr(out, name, arr.ctypes.data_as(_dp))
+    out.fate = fate.ctypes.data_as(_i32p)
+    out.where = where.ctypes.data_as(_i32p)
+    out.when = when.ctypes.data_as(_i32p)
+    out.rho = rho.ctypes.data_as(_dp)
+    out.rho_fixed = rho_fixed.ctypes.data_as(_i64p) if rho_fixed is not None else None
+    out.tally = tally.ctypes.data_as(_i64p)
+    out.escaped = esc.ctypes.data_as(_i64p)
+    cfg = prob.cstruct()
+    rc = L.orc_run(ctypes.byref(cfg), n, sp.ctypes.data_as(_i32p),
+                   *[c.ctypes.data_as(_dp) for c in cols], *[e.ctypes.data_as(_dp) for e in E],
+                   int(nsteps), ctypes.byref(out))
+    if rc != 0:
+        raise OracleError(f"oracle returned {rc}")
+    return Result(x=np.stack(ox[:3], 1), v=np.stack(ox[3:], 1), fate=fate, where=where,
+                  when=when, rho=rho, rho_fixed=rho_fixed, tally=tally, escaped=esc)
+
+
+def weights(f, dtype=np.float64) -> np.ndarray:
+    L = lib()
+    f = _c(f, dtype)
+    W = np.empty(8, dtype)
+    if dtype == np.float64:
+        L.orc_weights_f64(f.ctypes.data_as(_dp), W.ctypes.data_as(_dp))
+    else:
+        L.orc_weights_f32(f.ctypes.data_as(_fp), W.ctypes.data_as(_fp))
+    return W
+
+
+def gather(nx, ny, nz, E, i, f) -> np.ndarray:
+    L = lib()
+    E = [_c(E[d], np.float64) for d in range(3)]
+    ii = _c(i, np.int32)
+    ff = _c(f, np.float64)
+    out = np.empty(3)
+    L.orc_gather_f64(nx, ny, nz, *[e.ctypes.data_as(_dp) for e in E], ii.ctypes.data_as(_i32p),
+                     ff.ctypes.data_as(_dp), out.ctypes.data_as(_dp))
+    return out
+
+
+def fixed_contrib(chg, W, dtype=np.float64) -> np.ndarray:
+    L = lib()
+    W = _c(W, dtype)
+    C = np.empty(8, np.int64)
+    if dtype == np.float64:
+        L.orc_fixed_contrib_f64(float(chg), W.ctypes.data_as(_dp), C.ctypes.data_as(_i64p))
+    else:
+        L.orc_fixed_contrib_f32(float(chg), W.ctypes.data_as(_fp), C.ctypes.data_as(_i64p))
+    return C
+
+
+def object_hit(prob: Problem, x, y, z) -> int:
+    cfg = prob.cstruct()
+    return int(lib().orc_object_hit(ctypes.byref(cfg), float(x), float(y), float(z)))

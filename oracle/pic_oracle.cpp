@@ -1,0 +1,704 @@
+// PIC particle-mesh oracle: a plain, slow, single-threaded CPU implementation
+// of one explicit PIC step (gather -> push -> boundary/object -> deposit).
+//
+// THIS FILE IS TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the
+// CPU-baseline leg of the benchmark load it. The GPU library never links,
+// includes or calls it, and it shares no code with the GPU library.
+//
+// What it follows:
+//   * The PIC loop of §2.1: charge is weighted from particles to mesh nodes
+//     ("scatter"), the field is interpolated at particle positions ("gather"),
+//     and velocity and position are updated ("particle-push"). The field solve
+//     of the loop is not computed here: the node electric field is an input.
+//   * §3.1.3: particles hitting outer boundaries are absorbed and removed
+//     (the open-box reading: all six faces remove, counted per face).
+//   * §5.2.2 and the "other" phase of Table 1 (§3.3): particles hitting the
+//     object or the lunar surface are collected and their charge accumulated
+//     for surface charging (a per-bin count per species; charge = q*w*count).
+//   * §5.2.1: the terrain is a height function z = z(x, y); here a flat plane
+//     with a spherical-bowl crater.
+//   * §3.1.1 / §5.2.1: lengths are normalised so that the PIC cell has size h
+//     (unit cells in every workload).
+// The paper names neither the weighting order nor the integrator. This oracle
+// takes first-order (trilinear, cloud-in-cell) weighting with node-centred E
+// and rho, and the leapfrog push with velocities stored at half steps.
+//
+// The step, per particle, in index order (internal coordinates are cell units
+// g = (x - origin)/h, velocities u = v/h):
+//   1. locate: i = floor(g), f = g - i           (cell-relative form: stored)
+//   2. weights: w0 = 1 - f, w1 = f per axis; W[a+2b+4c] = (wx[a]*wy[b])*wz[c]
+//   3. gather: acc = W[0]*E[node 0]; acc = fma(W[n], E[node n], acc), n = 1..7
+//   4. kick:   u = fma(qmdt, E_p, u), qmdt = q/m*dt/h
+//   5. drift:  g = fma(u, dt, g)   (cell form: o' = fma(u,dt,o), s = floor(o'),
+//              o' -= s, if o' == 1 then o' = 0, s += 1; i += s)
+//   6. box:    first axis (x, y, z) with g < 0 (face 2d) or g >= n (face 2d+1)
+//              -> escaped. For the crater terrain, z < 0 is not an escape.
+//   7. object: sphere |g - c|^2 <= R^2, or crater (z < 0) or (z <= z_flat and
+//              |g - zc|^2 >= Rc^2) -> absorbed, counted in its bin.
+//   8. deposit (after all particles moved): rho is zeroed, then every alive
+//      particle adds its charge chg = q*w times W[n] at its new position.
+//      Fixed-point mode: C[n] = llrint(chg*W[n] * 2^32) for n < 7 and
+//      C[7] = llrint(chg * 2^32) - sum_{n<7} C[n], added to int64 rhoF;
+//      output rho = rhoF * 2^-32 / h^3.
+//
+// The arithmetic type T is double for the FP64 form and float for the two FP32
+// mirrors (absolute positions; int32 cell + float offset). The same expression
+// order is used in every form. Build with -ffp-contract=off so that no
+// multiply-add is fused unless written as fma.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+constexpr double kFix = 4294967296.0;  // 2^32
+constexpr int kMaxSpecies = 4;
+
+enum { REPR_FP64 = 0, REPR_FP32_ABS = 1, REPR_FP32_CELL = 2 };
+enum { DEP_FIXED64 = 0, DEP_FP32 = 1, DEP_FP64 = 2 };
+enum { OBJ_NONE = 0, OBJ_SPHERE = 1, OBJ_CRATER = 2 };
+enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_RANGE = -5 };
+
+}  // namespace
+
+extern "C" {
+
+typedef struct {
+  int32_t nx, ny, nz;
+  double h;
+  double origin[3];
+  double dt;
+  int32_t n_species;
+  double q[kMaxSpecies], m[kMaxSpecies], w[kMaxSpecies];
+  int32_t obj_kind;  // 0 none, 1 sphere, 2 crater
+  double center[3];  // sphere centre; crater axis at (center[0], center[1])
+  double radius;     // sphere radius
+  double z_flat, rim_radius, depth;  // crater: flat ground height, bowl radius, depth
+  int32_t repr;      // 0 FP64, 1 FP32 absolute, 2 FP32 cell-relative
+  int32_t deposit;   // 0 fixed-point int64, 1 FP32 sum, 2 FP64 sum
+} orc_config;
+
+typedef struct {
+  double *x, *y, *z, *vx, *vy, *vz;  // n: final state, physical units
+  int32_t *fate;                     // n: 0 alive, 1 escaped, 2 absorbed
+  int32_t *where;                    // n: face (escaped) or bin (absorbed), else -1
+  int32_t *when;                     // n: step of removal (0-based), else -1
+  double *rho;                       // nodes: charge density
+  int64_t *rho_fixed;                // nodes: fixed-point rho (fixed mode), may be null
+  int64_t *tally;                    // nbins * n_species: absorbed counts [bin][s]
+  int64_t *escaped;                  // 6 * n_species: escaped counts [face][s]
+} orc_out;
+
+}  // extern "C"
+
+namespace {
+
+inline float fma_t(float a, float b, float c) { return std::fmaf(a, b, c); }
+inline double fma_t(double a, double b, double c) { return std::fma(a, b, c); }
+inline float floor_t(float a) { return std::floor(a); }
+inline double floor_t(double a) { return std::floor(a); }
+
+// Trilinear (cloud-in-cell) weights of the 8 corners of a cell, corner
+// n = a + 2b + 4c at offset (a, b, c).
+template <class T>
+void weights(const T f[3], T W[8]) {
+  const T wx[2] = {T(1) - f[0], f[0]};
+  const T wy[2] = {T(1) - f[1], f[1]};
+  const T wz[2] = {T(1) - f[2], f[2]};
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) W[a + 2 * b + 4 * c] = (wx[a] * wy[b]) * wz[c];
+}
+
+struct Mesh {
+  int32_t n[3];
+  int64_t sx, sy;  // node strides: node(i,j,k) = i + sx*j + sy*k
+  int64_t nodes() const { return sy * (n[2] + 1); }
+  int64_t node(int64_t i, int64_t j, int64_t k) const { return i + sx * j + sy * k; }
+};
+
+Mesh make_mesh(const orc_config& c) {
+  Mesh m;
+  m.n[0] = c.nx; m.n[1] = c.ny; m.n[2] = c.nz;
+  m.sx = c.nx + 1;
+  m.sy = (int64_t)(c.nx + 1) * (c.ny + 1);
+  return m;
+}
+
+// Node indices of the 8 corners of cell (i, j, k), same corner order as weights().
+void corners(const Mesh& m, const int32_t i[3], int64_t idx[8]) {
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) idx[a + 2 * b + 4 * c] = m.node(i[0] + a, i[1] + b, i[2] + c);
+}
+
+template <class T>
+void gather(const T* E[3], const int64_t idx[8], const T W[8], T out[3]) {
+  for (int d = 0; d < 3; ++d) {
+    T acc = W[0] * E[d][idx[0]];
+    for (int n = 1; n < 8; ++n) acc = fma_t(W[n], E[d][idx[n]], acc);
+    out[d] = acc;
+  }
+}
+
+// Fixed-point contributions (scale 2^32) of one particle: round half to even,
+// and the remainder of the rounded total charge goes to corner 7 so that the
+// eight contributions sum exactly to llrint(chg * 2^32).
+template <class T>
+void fixed_contrib(T chg, const T W[8], int64_t C[8]) {
+  int64_t sum = 0;
+  for (int n = 0; n < 7; ++n) {
+    const T cw = chg * W[n];
+    C[n] = std::llrint((double)cw * kFix);
+    sum += C[n];
+  }
+  C[7] = std::llrint((double)chg * kFix) - sum;
+}
+
+// Per-species constants in the arithmetic type of the form.
+template <class T>
+struct SpeciesConst {
+  T qmdt;  // q/m * dt / h
+  T chg;   // q * w
+};
+
+// Object geometry in cell units, rounded to the arithmetic type of the form.
+template <class T>
+struct Geometry {
+  int kind;
+  T c[3];    // sphere centre / crater axis (x, y); c[2] = bowl sphere centre height
+  T r2;      // sphere R^2 / crater bowl-sphere Rc^2
+  T z_flat;  // crater flat ground
+  // integer + fractional split for the cell-relative form
+  int32_t ci[3];
+  T cf[3];
+  int32_t zfi;
+  T zff;
+};
+
+template <class T>
+Geometry<T> make_geometry(const orc_config& cfg) {
+  Geometry<T> g{};
+  g.kind = cfg.obj_kind;
+  double c[3] = {0, 0, 0}, r2 = 0, zf = 0;
+  if (cfg.obj_kind == OBJ_SPHERE) {
+    for (int d = 0; d < 3; ++d) c[d] = (cfg.center[d] - cfg.origin[d]) / cfg.h;
+    const double R = cfg.radius / cfg.h;
+    r2 = R * R;
+  } else if (cfg.obj_kind == OBJ_CRATER) {
+    // Spherical bowl of radius a (at the flat level) and depth d below the flat
+    // ground z_flat: its sphere has radius Rc = (a^2 + d^2) / (2d) and centre
+    // height zc = z_flat - d + Rc.
+    const double a = cfg.rim_radius / cfg.h, dep = cfg.depth / cfg.h;
+    zf = (cfg.z_flat - cfg.origin[2]) / cfg.h;
+    const double Rc = (a * a + dep * dep) / (2.0 * dep);
+    c[0] = (cfg.center[0] - cfg.origin[0]) / cfg.h;
+    c[1] = (cfg.center[1] - cfg.origin[1]) / cfg.h;
+    c[2] = zf - dep + Rc;
+    r2 = Rc * Rc;
+  }
+  for (int d = 0; d < 3; ++d) {
+    g.c[d] = (T)c[d];
+    g.ci[d] = (int32_t)std::floor(c[d]);
+    g.cf[d] = (T)(c[d] - g.ci[d]);
+  }
+  g.r2 = (T)r2;
+  g.z_flat = (T)zf;
+  g.zfi = (int32_t)std::floor(zf);
+  g.zff = (T)(zf - g.zfi);
+  return g;
+}
+
+// ---- object predicates ------------------------------------------------------
+
+template <class T>
+T dist2(const T d[3]) {
+  return fma_t(d[2], d[2], fma_t(d[1], d[1], d[0] * d[0]));
+}
+
+// Absolute-position forms. Returns the bin (>= 0) when absorbed, else -1.
+template <class T>
+int32_t object_hit_abs(const Geometry<T>& G, const Mesh& m, const T g[3]) {
+  if (G.kind == OBJ_SPHERE) {
+    const T d[3] = {g[0] - G.c[0], g[1] - G.c[1], g[2] - G.c[2]};
+    return dist2(d) <= G.r2 ? 0 : -1;
+  }
+  if (G.kind == OBJ_CRATER) {
+    bool hit = g[2] < T(0);
+    if (!hit && g[2] <= G.z_flat) {
+      const T d[3] = {g[0] - G.c[0], g[1] - G.c[1], g[2] - G.c[2]};
+      hit = dist2(d) >= G.r2;
+    }
+    if (!hit) return -1;
+    int64_t ix = (int64_t)floor_t(g[0]), iy = (int64_t)floor_t(g[1]);
+    ix = ix < 0 ? 0 : (ix > m.n[0] - 1 ? m.n[0] - 1 : ix);
+    iy = iy < 0 ? 0 : (iy > m.n[1] - 1 ? m.n[1] - 1 : iy);
+    return (int32_t)(ix + (int64_t)m.n[0] * iy);
+  }
+  return -1;
+}
+
+// Cell-relative form: a coordinate minus a constant c = ci + cf is
+// (float)(i - ci) + (o - cf).
+int32_t object_hit_cell(const Geometry<float>& G, const Mesh& m, const int32_t i[3],
+                        const float o[3]) {
+  if (G.kind == OBJ_SPHERE) {
+    float d[3];
+    for (int k = 0; k < 3; ++k) d[k] = (float)(i[k] - G.ci[k]) + (o[k] - G.cf[k]);
+    return dist2(d) <= G.r2 ? 0 : -1;
+  }
+  if (G.kind == OBJ_CRATER) {
+    bool hit = i[2] < 0;
+    if (!hit) {
+      const float zrel = (float)(i[2] - G.zfi) + (o[2] - G.zff);
+      if (zrel <= 0.0f) {
+        float d[3];
+        for (int k = 0; k < 3; ++k) d[k] = (float)(i[k] - G.ci[k]) + (o[k] - G.cf[k]);
+        hit = dist2(d) >= G.r2;
+      }
+    }
+    if (!hit) return -1;
+    int64_t ix = i[0] < 0 ? 0 : (i[0] > m.n[0] - 1 ? m.n[0] - 1 : i[0]);
+    int64_t iy = i[1] < 0 ? 0 : (i[1] > m.n[1] - 1 ? m.n[1] - 1 : i[1]);
+    return (int32_t)(ix + (int64_t)m.n[0] * iy);
+  }
+  return -1;
+}
+
+// ---- box exit ----------------------------------------------------------------
+
+// First offending axis in x, y, z order, lower face before upper face.
+// For the crater terrain the z-lower face is not an exit (absorbed instead).
+template <class T>
+int box_face_abs(const Mesh& m, const T g[3], bool crater) {
+  for (int d = 0; d < 3; ++d) {
+    if (g[d] < T(0) && !(crater && d == 2)) return 2 * d;
+    if (g[d] >= (T)m.n[d]) return 2 * d + 1;
+  }
+  return -1;
+}
+
+int box_face_cell(const Mesh& m, const int32_t i[3], bool crater) {
+  for (int d = 0; d < 3; ++d) {
+    if (i[d] < 0 && !(crater && d == 2)) return 2 * d;
+    if (i[d] >= m.n[d]) return 2 * d + 1;
+  }
+  return -1;
+}
+
+// ---- deposit -----------------------------------------------------------------
+
+struct RhoAcc {
+  int mode;
+  std::vector<int64_t> fixed;
+  std::vector<float> f32;
+  std::vector<double> f64;
+  void reset(int64_t nodes) {
+    if (mode == DEP_FIXED64) fixed.assign(nodes, 0);
+    if (mode == DEP_FP32) f32.assign(nodes, 0.0f);
+    if (mode == DEP_FP64) f64.assign(nodes, 0.0);
+  }
+  template <class T>
+  void add(const int64_t idx[8], const T W[8], T chg) {
+    if (mode == DEP_FIXED64) {
+      int64_t C[8];
+      fixed_contrib(chg, W, C);
+      for (int n = 0; n < 8; ++n) fixed[idx[n]] += C[n];
+    } else if (mode == DEP_FP32) {
+      for (int n = 0; n < 8; ++n) f32[idx[n]] += (float)(chg * W[n]);
+    } else {
+      for (int n = 0; n < 8; ++n) f64[idx[n]] += (double)(chg * W[n]);
+    }
+  }
+};
+
+// ---- particle state of each form -----------------------------------------------
+
+template <class T>
+struct AbsState {  // FP64 or FP32 absolute positions in cell units
+  std::vector<T> g[3], u[3];
+};
+
+struct CellState {  // int32 cell + FP32 offset in [0, 1)
+  std::vector<int32_t> i[3];
+  std::vector<float> o[3], u[3];
+};
+
+bool finite3(const double* a) {
+  return std::isfinite(a[0]) && std::isfinite(a[1]) && std::isfinite(a[2]);
+}
+
+// Shared driver bookkeeping: fates and counters.
+struct Book {
+  std::vector<int32_t> fate, where, when;
+  std::vector<int64_t> tally, escaped;
+};
+
+template <class T>
+int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* const xin[3],
+            const double* const vin[3], const double* const Ein[3], int32_t nsteps,
+            orc_out* out) {
+  const Mesh M = make_mesh(cfg);
+  const int64_t nodes = M.nodes();
+  const int ns = cfg.n_species;
+  const bool crater = cfg.obj_kind == OBJ_CRATER;
+  const Geometry<T> G = make_geometry<T>(cfg);
+  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny : 1;
+  std::vector<T> E[3];
+  for (int d = 0; d < 3; ++d) {
+    E[d].resize(nodes);
+    for (int64_t k = 0; k < nodes; ++k) E[d][k] = (T)Ein[d][k];
+  }
+  const T* Ep[3] = {E[0].data(), E[1].data(), E[2].data()};
+  SpeciesConst<T> S[kMaxSpecies];
+  for (int s = 0; s < ns; ++s) {
+    S[s].qmdt = (T)(cfg.q[s] / cfg.m[s] * cfg.dt / cfg.h);
+    S[s].chg = (T)(cfg.q[s] * cfg.w[s]);
+  }
+  const T dt = (T)cfg.dt;
+
+  AbsState<T> P;
+  for (int d = 0; d < 3; ++d) {
+    P.g[d].resize(n);
+    P.u[d].resize(n);
+    for (int64_t p = 0; p < n; ++p) {
+      P.g[d][p] = (T)((xin[d][p] - cfg.origin[d]) / cfg.h);
+      P.u[d][p] = (T)(vin[d][p] / cfg.h);
+    }
+  }
+  Book B;
+  B.fate.assign(n, 0);
+  B.where.assign(n, -1);
+  B.when.assign(n, -1);
+  B.tally.assign(nbins * ns, 0);
+  B.escaped.assign(6 * ns, 0);
+  RhoAcc rho;
+  rho.mode = cfg.deposit;
+
+  auto deposit_all = [&]() {
+    rho.reset(nodes);
+    for (int64_t p = 0; p < n; ++p) {
+      if (B.fate[p] != 0) continue;
+      T g[3] = {P.g[0][p], P.g[1][p], P.g[2][p]};
+      int32_t i[3];
+      T f[3];
+      for (int d = 0; d < 3; ++d) {
+        i[d] = (int32_t)floor_t(g[d]);
+        f[d] = g[d] - (T)i[d];
+      }
+      T W[8];
+      weights(f, W);
+      int64_t idx[8];
+      corners(M, i, idx);
+      rho.add(idx, W, S[sp[p]].chg);
+    }
+  };
+
+  for (int32_t step = 0; step < nsteps; ++step) {
+    for (int64_t p = 0; p < n; ++p) {
+      if (B.fate[p] != 0) continue;
+      const int s = sp[p];
+      T g[3] = {P.g[0][p], P.g[1][p], P.g[2][p]};
+      T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
+      int32_t i[3];
+      T f[3];
+      for (int d = 0; d < 3; ++d) {
+        i[d] = (int32_t)floor_t(g[d]);
+        f[d] = g[d] - (T)i[d];
+      }
+      T W[8];
+      weights(f, W);
+      int64_t idx[8];
+      corners(M, i, idx);
+      T Epart[3];
+      gather(Ep, idx, W, Epart);
+      for (int d = 0; d < 3; ++d) u[d] = fma_t(S[s].qmdt, Epart[d], u[d]);
+      for (int d = 0; d < 3; ++d) g[d] = fma_t(u[d], dt, g[d]);
+      const double gd[3] = {(double)g[0], (double)g[1], (double)g[2]};
+      if (!finite3(gd)) return ORC_E_RANGE;
+      for (int d = 0; d < 3; ++d) {
+        P.g[d][p] = g[d];
+        P.u[d][p] = u[d];
+      }
+      const int face = box_face_abs(M, g, crater);
+      if (face >= 0) {
+        B.fate[p] = 1;
+        B.where[p] = face;
+        B.when[p] = step;
+        B.escaped[face * ns + s] += 1;
+        continue;
+      }
+      const int32_t bin = object_hit_abs(G, M, g);
+      if (bin >= 0) {
+        B.fate[p] = 2;
+        B.where[p] = bin;
+        B.when[p] = step;
+        B.tally[(int64_t)bin * ns + s] += 1;
+      }
+    }
+    deposit_all();
+  }
+  if (nsteps == 0) deposit_all();
+
+  // outputs
+  for (int64_t p = 0; p < n; ++p) {
+    out->x[p] = cfg.origin[0] + (double)P.g[0][p] * cfg.h;
+    out->y[p] = cfg.origin[1] + (double)P.g[1][p] * cfg.h;
+    out->z[p] = cfg.origin[2] + (double)P.g[2][p] * cfg.h;
+    out->vx[p] = (double)P.u[0][p] * cfg.h;
+    out->vy[p] = (double)P.u[1][p] * cfg.h;
+    out->vz[p] = (double)P.u[2][p] * cfg.h;
+    out->fate[p] = B.fate[p];
+    out->where[p] = B.where[p];
+    out->when[p] = B.when[p];
+  }
+  const double h3 = cfg.h * cfg.h * cfg.h;
+  for (int64_t k = 0; k < nodes; ++k) {
+    if (cfg.deposit == DEP_FIXED64) {
+      out->rho[k] = ((double)rho.fixed[k] * (1.0 / kFix)) / h3;
+      if (out->rho_fixed) out->rho_fixed[k] = rho.fixed[k];
+    } else if (cfg.deposit == DEP_FP32) {
+      out->rho[k] = (double)rho.f32[k] / h3;
+    } else {
+      out->rho[k] = rho.f64[k] / h3;
+    }
+  }
+  std::memcpy(out->tally, B.tally.data(), sizeof(int64_t) * B.tally.size());
+  std::memcpy(out->escaped, B.escaped.data(), sizeof(int64_t) * B.escaped.size());
+  return ORC_OK;
+}
+
+int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* const xin[3],
+             const double* const vin[3], const double* const Ein[3], int32_t nsteps,
+             orc_out* out) {
+  typedef float T;
+  const Mesh M = make_mesh(cfg);
+  const int64_t nodes = M.nodes();
+  const int ns = cfg.n_species;
+  const bool crater = cfg.obj_kind == OBJ_CRATER;
+  const Geometry<T> G = make_geometry<T>(cfg);
+  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny : 1;
+  std::vector<T> E[3];
+  for (int d = 0; d < 3; ++d) {
+    E[d].resize(nodes);
+    for (int64_t k = 0; k < nodes; ++k) E[d][k] = (T)Ein[d][k];
+  }
+  const T* Ep[3] = {E[0].data(), E[1].data(), E[2].data()};
+  SpeciesConst<T> S[kMaxSpecies];
+  for (int s = 0; s < ns; ++s) {
+    S[s].qmdt = (T)(cfg.q[s] / cfg.m[s] * cfg.dt / cfg.h);
+    S[s].chg = (T)(cfg.q[s] * cfg.w[s]);
+  }
+  const T dt = (T)cfg.dt;
+
+  CellState P;
+  for (int d = 0; d < 3; ++d) {
+    P.i[d].resize(n);
+    P.o[d].resize(n);
+    P.u[d].resize(n);
+    for (int64_t p = 0; p < n; ++p) {
+      const double gd = (xin[d][p] - cfg.origin[d]) / cfg.h;
+      int32_t i = (int32_t)std::floor(gd);
+      float o = (float)(gd - (double)i);
+      if (o == 1.0f) {  // offset rounded up to the next cell
+        o = 0.0f;
+        i += 1;
+      }
+      P.i[d][p] = i;
+      P.o[d][p] = o;
+      P.u[d][p] = (T)(vin[d][p] / cfg.h);
+    }
+  }
+  Book B;
+  B.fate.assign(n, 0);
+  B.where.assign(n, -1);
+  B.when.assign(n, -1);
+  B.tally.assign(nbins * ns, 0);
+  B.escaped.assign(6 * ns, 0);
+  RhoAcc rho;
+  rho.mode = cfg.deposit;
+
+  auto deposit_all = [&]() {
+    rho.reset(nodes);
+    for (int64_t p = 0; p < n; ++p) {
+      if (B.fate[p] != 0) continue;
+      const int32_t i[3] = {P.i[0][p], P.i[1][p], P.i[2][p]};
+      const T f[3] = {P.o[0][p], P.o[1][p], P.o[2][p]};
+      T W[8];
+      weights(f, W);
+      int64_t idx[8];
+      corners(M, i, idx);
+      rho.add(idx, W, S[sp[p]].chg);
+    }
+  };
+
+  for (int32_t step = 0; step < nsteps; ++step) {
+    for (int64_t p = 0; p < n; ++p) {
+      if (B.fate[p] != 0) continue;
+      const int s = sp[p];
+      int32_t i[3] = {P.i[0][p], P.i[1][p], P.i[2][p]};
+      T o[3] = {P.o[0][p], P.o[1][p], P.o[2][p]};
+      T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
+      T W[8];
+      weights(o, W);
+      int64_t idx[8];
+      corners(M, i, idx);
+      T Epart[3];
+      gather(Ep, idx, W, Epart);
+      for (int d = 0; d < 3; ++d) u[d] = fma_t(S[s].qmdt, Epart[d], u[d]);
+      for (int d = 0; d < 3; ++d) {
+        T op = fma_t(u[d], dt, o[d]);
+        if (!std::isfinite(op)) return ORC_E_RANGE;
+        T sh = floor_t(op);
+        op = op - sh;
+        if (op == 1.0f) {  // a tiny negative offset rounded up to 1 after the shift
+          op = 0.0f;
+          sh = sh + 1.0f;
+        }
+        if (!(std::fabs(sh) <= 1048576.0f)) return ORC_E_RANGE;
+        o[d] = op;
+        i[d] += (int32_t)sh;
+      }
+      for (int d = 0; d < 3; ++d) {
+        P.i[d][p] = i[d];
+        P.o[d][p] = o[d];
+        P.u[d][p] = u[d];
+      }
+      const int face = box_face_cell(M, i, crater);
+      if (face >= 0) {
+        B.fate[p] = 1;
+        B.where[p] = face;
+        B.when[p] = step;
+        B.escaped[face * ns + s] += 1;
+        continue;
+      }
+      const int32_t bin = object_hit_cell(G, M, i, o);
+      if (bin >= 0) {
+        B.fate[p] = 2;
+        B.where[p] = bin;
+        B.when[p] = step;
+        B.tally[(int64_t)bin * ns + s] += 1;
+      }
+    }
+    deposit_all();
+  }
+  if (nsteps == 0) deposit_all();
+
+  for (int64_t p = 0; p < n; ++p) {
+    out->x[p] = cfg.origin[0] + ((double)P.i[0][p] + (double)P.o[0][p]) * cfg.h;
+    out->y[p] = cfg.origin[1] + ((double)P.i[1][p] + (double)P.o[1][p]) * cfg.h;
+    out->z[p] = cfg.origin[2] + ((double)P.i[2][p] + (double)P.o[2][p]) * cfg.h;
+    out->vx[p] = (double)P.u[0][p] * cfg.h;
+    out->vy[p] = (double)P.u[1][p] * cfg.h;
+    out->vz[p] = (double)P.u[2][p] * cfg.h;
+    out->fate[p] = B.fate[p];
+    out->where[p] = B.where[p];
+    out->when[p] = B.when[p];
+  }
+  const double h3 = cfg.h * cfg.h * cfg.h;
+  for (int64_t k = 0; k < nodes; ++k) {
+    if (cfg.deposit == DEP_FIXED64) {
+      out->rho[k] = ((double)rho.fixed[k] * (1.0 / kFix)) / h3;
+      if (out->rho_fixed) out->rho_fixed[k] = rho.fixed[k];
+    } else if (cfg.deposit == DEP_FP32) {
+      out->rho[k] = (double)rho.f32[k] / h3;
+    } else {
+      out->rho[k] = rho.f64[k] / h3;
+    }
+  }
+  std::memcpy(out->tally, B.tally.data(), sizeof(int64_t) * B.tally.size());
+  std::memcpy(out->escaped, B.escaped.data(), sizeof(int64_t) * B.escaped.size());
+  return ORC_OK;
+}
+
+bool valid(const orc_config& c, int64_t n, const int32_t* sp, const double* const x[3]) {
+  if (c.nx < 1 || c.ny < 1 || c.nz < 1 || !(c.h > 0) || !(c.dt > 0)) return false;
+  if (c.n_species < 1 || c.n_species > kMaxSpecies) return false;
+  if (c.repr < 0 || c.repr > 2 || c.deposit < 0 || c.deposit > 2) return false;
+  if (c.obj_kind < 0 || c.obj_kind > 2) return false;
+  if (c.obj_kind == OBJ_CRATER && !(c.depth > 0)) return false;
+  for (int s = 0; s < c.n_species; ++s)
+    if (!(c.m[s] > 0)) return false;
+  const int32_t nn[3] = {c.nx, c.ny, c.nz};
+  for (int64_t p = 0; p < n; ++p) {
+    if (sp[p] < 0 || sp[p] >= c.n_species) return false;
+    for (int d = 0; d < 3; ++d) {
+      const double g = (x[d][p] - c.origin[d]) / c.h;
+      if (!(g >= 0.0 && g < (double)nn[d])) return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Runs nsteps PIC steps on n particles (species index sp[p]); nsteps == 0 only
+// deposits the loaded positions. Velocities are those at t - dt/2. Node fields
+// are (nx+1)(ny+1)(nz+1) values, x fastest. Returns 0, -1 (invalid input) or
+// -5 (a non-finite or runaway position).
+int orc_run(const orc_config* cfg, int64_t n, const int32_t* sp, const double* x,
+            const double* y, const double* z, const double* vx, const double* vy,
+            const double* vz, const double* Ex, const double* Ey, const double* Ez,
+            int32_t nsteps, orc_out* out) {
+  const double* xin[3] = {x, y, z};
+  const double* vin[3] = {vx, vy, vz};
+  const double* Ein[3] = {Ex, Ey, Ez};
+  if (!cfg || !out || nsteps < 0 || n < 0 || !valid(*cfg, n, sp, xin)) return ORC_E_INVALID;
+  if (cfg->repr == REPR_FP64) return run_abs<double>(*cfg, n, sp, xin, vin, Ein, nsteps, out);
+  if (cfg->repr == REPR_FP32_ABS) return run_abs<float>(*cfg, n, sp, xin, vin, Ein, nsteps, out);
+  return run_cell(*cfg, n, sp, xin, vin, Ein, nsteps, out);
+}
+
+// Pieces of the step, exposed so that tests can pin them one by one.
+void orc_weights_f64(const double f[3], double W[8]) { weights(f, W); }
+void orc_weights_f32(const float f[3], float W[8]) { weights(f, W); }
+
+void orc_gather_f64(int32_t nx, int32_t ny, int32_t nz, const double* Ex, const double* Ey,
+                    const double* Ez, const int32_t i[3], const double f[3], double out[3]) {
+  orc_config c{};
+  c.nx = nx; c.ny = ny; c.nz = nz;
+  const Mesh M = make_mesh(c);
+  double W[8];
+  weights(f, W);
+  int64_t idx[8];
+  corners(M, i, idx);
+  const double* E[3] = {Ex, Ey, Ez};
+  gather(E, idx, W, out);
+}
+
+void orc_fixed_contrib_f64(double chg, const double W[8], int64_t C[8]) { fixed_contrib(chg, W, C); }
+void orc_fixed_contrib_f32(float chg, const float W[8], int64_t C[8]) { fixed_contrib(chg, W, C); }
+
+// Object predicate at one point (physical units), in the arithmetic of `repr`.
+// Returns the bin when the point is absorbed, else -1.
+int32_t orc_object_hit(const orc_config* cfg, double x, double y, double z) {
+  const Mesh M = make_mesh(*cfg);
+  const double gd[3] = {(x - cfg->origin[0]) / cfg->h, (y - cfg->origin[1]) / cfg->h,
+                        (z - cfg->origin[2]) / cfg->h};
+  if (cfg->repr == REPR_FP64) {
+    const Geometry<double> G = make_geometry<double>(*cfg);
+    return object_hit_abs(G, M, gd);
+  }
+  const Geometry<float> G = make_geometry<float>(*cfg);
+  if (cfg->repr == REPR_FP32_ABS) {
+    const float g[3] = {(float)gd[0], (float)gd[1], (float)gd[2]};
+    return object_hit_abs(G, M, g);
+  }
+  int32_t i[3];
+  float o[3];
+  for (int d = 0; d < 3; ++d) {
+    i[d] = (int32_t)std::floor(gd[d]);
+    o[d] = (float)(gd[d] - i[d]);
+    if (o[d] == 1.0f) {
+      o[d] = 0.0f;
+      i[d] += 1;
+    }
+  }
+  return object_hit_cell(G, M, i, o);
+}
+
+}  // extern "C"
