@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Throughput of the particle-mesh hot path (gather + leapfrog push + collection
++ trilinear deposit, with the periodic tile re-bucketing) on one MI355X.
+
+Default workload: the lunar-crater shape, one subdomain on one GPU:
+160 x 160 x 80 cells (2.05M), 2 x 260,000,000 particles, FP32 cell-relative
+state with int64 fixed-point deposition, re-bucketing every 4 steps.
+
+A step is one pass of the whole hot path over all particles; particle-steps
+count the particles alive at the start of each step. Inputs are generated on
+the host, loaded into HBM, and are resident before the timed region starts.
+
+Prints one JSON line (the last line of stdout). Progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (gather+push+deposit), % HBM roofline; p50/p99 req latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE_STEP = {"fp32_cell": 56, "fp32_abs": 48, "fp64": 96}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_10214_amd", "csrc", "pic_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel_crater_160.json")
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def host_info():
+    model = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem = round(int(line.split()[1]) / 2 ** 20, 1)
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"cpu": model, "logical_cpus": cores, "ram_gib": mem}
+
+
+def kernel_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_for(workload, repr_, deposit, launches_particles):
+    """HBM bytes per launch of the step kernel measured by rocprofv3 counters,
+    if the stored measurement was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("kernel_source_sha256") != kernel_hash() or t.get("workload") != workload
+            or t.get("repr") != repr_ or t.get("deposit") != deposit):
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, target_s):
+    """The FP64 oracle, single-threaded, on a bounded sample of the workload."""
+    import numpy as np
+
+    import synth
+    from oracle import oracle
+
+    per = 1 << 19
+    sp, xs, vs = [], [], []
+    for s in range(len(w.species)):
+        a = synth.particles(w, s, 0, per)
+        sp.append(np.full(per, s, np.int32))
+        xs.append(np.stack(a[:3], 1).astype(np.float64))
+        vs.append(np.stack(a[3:], 1).astype(np.float64))
+    sp, x, v = np.concatenate(sp), np.concatenate(xs), np.concatenate(vs)
+    E = synth.node_E(w)
+    prob = oracle.Problem(nx=w.nx, ny=w.ny, nz=w.nz, dt=w.dt, q=[s.q for s in w.species],
+                          m=[s.m for s in w.species], w=[s.w for s in w.species], obj=w.obj,
+                          center=w.center, radius=w.radius, z_flat=w.z_flat,
+                          rim_radius=w.rim_radius, depth=w.depth, repr="fp64", deposit="fixed64")
+    t0 = time.perf_counter()
+    oracle.run(prob, sp, x, v, E, 1)
+    one = time.perf_counter() - t0
+    steps = int(max(1, min(w.steps, target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    r = oracle.run(prob, sp, x, v, E, steps)
+    dt = time.perf_counter() - t0
+    ps = int(np.where(r.fate == 0, steps, r.when + 1).sum())
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {per} particles of each species of {w.name}, {steps} steps, "
+                       f"FP64 oracle with fixed-point deposit, single thread, {dt:.1f} s"),
+            "host": host_info()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="crater_160")
+    ap.add_argument("--repr", default="fp32_cell", choices=sorted(BYTES_PER_PARTICLE_STEP))
+    ap.add_argument("--deposit", default="fixed64", choices=["fixed64", "fp32", "fp64"])
+    ap.add_argument("--sort-interval", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: one MI355X holds the whole subdomain and the "
+              "path has no multi-GPU form in this build (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2011_10214_amd as pam
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]()
+    stream = torch.cuda.current_stream()
+    cfg = pam.config_from_workload(w, repr=args.repr, deposit=args.deposit,
+                                   sort_interval=args.sort_interval, stream=stream.cuda_stream)
+    log(f"workload {w.name}: {w.nx}x{w.ny}x{w.nz} cells, {w.n_particles} particles, "
+        f"{args.repr}/{args.deposit}, K={args.sort_interval}")
+    ctx = pam.Context(cfg)
+    t0 = time.perf_counter()
+    for s in range(len(w.species)):
+        cols = synth.particles(w, s)
+        log(f"species {s}: generated {len(cols[0])} particles ({time.perf_counter() - t0:.1f} s)")
+        dev = [torch.from_numpy(c).to("cuda") for c in cols]
+        del cols
+        ctx.load_particles_cols(s, dev)
+        del dev
+        torch.cuda.empty_cache()
+        log(f"species {s}: loaded ({time.perf_counter() - t0:.1f} s)")
+    E = [torch.from_numpy(e).to("cuda") for e in synth.node_E(w)]
+    ctx.set_node_E(E)
+    del E
+
+    log(f"warmup {args.warmup} steps")
+    ctx.step(args.warmup)
+    ctx.synchronize()
+    alive0, _, _ = ctx.get_counters()
+
+    ctx.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ctx.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = ctx.profile_read()
+    alive1, absorbed, escaped = ctx.get_counters()
+    log(f"timed {args.steps} steps: {ms:.2f} ms; step kernel {prof.step_ms / max(1, prof.step_launches):.3f} ms avg, "
+        f"sort {prof.sort_ms / max(1, prof.sort_launches):.3f} ms avg x{prof.sort_launches}")
+    ctx.close()
+
+    value = prof.particle_steps / (ms / 1e3)
+    bpp = BYTES_PER_PARTICLE_STEP[args.repr]
+    step_s = prof.step_ms / 1e3
+    achieved = bpp * prof.particle_steps / step_s / 1e9 if step_s > 0 else 0.0
+    per_launch_particles = prof.particle_steps / max(1, prof.step_launches)
+    traffic = traffic_for(w.name, args.repr, args.deposit, per_launch_particles)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.repr != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} cells, {w.n_particles} particles "
+                        f"({len(w.species)} species), crater terrain, dt {w.dt}",
+            "repr": args.repr,
+            "deposit": args.deposit + (" (int64 at 2^-32)" if args.deposit == "fixed64" else ""),
+            "sort_interval": args.sort_interval,
+            "particles_alive_start": int(alive0.sum()),
+            "particles_alive_end": int(alive1.sum()),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "step_kernel (gather+push+collect+deposit)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_particle_step": bpp,
+            "step_kernel_ms_avg": prof.step_ms / max(1, prof.step_launches),
+            "particles_per_launch": per_launch_particles,
+        },
+        "phases_ms_per_step": {
+            "step_kernel": prof.step_ms / args.steps,
+            "sort": prof.sort_ms / args.steps,
+            "rho_clear": prof.clear_ms / args.steps,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

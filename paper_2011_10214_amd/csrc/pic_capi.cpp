@@ -1,0 +1,899 @@
+// C-ABI of the particle-mesh hot path: context, validation, device memory,
+// orchestration of the kernels (pic_kernels.hip) and read-back.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr double kTwo32 = 4294967296.0;
+constexpr int kDefaultSort = 4;
+constexpr int64_t kMaxCapacity = 0x7fffffffLL - 1024;
+
+thread_local std::string g_create_error = "no error";
+
+int64_t particle_bytes(int repr) {
+  return repr == PIC_REPR_FP64 ? 48 : (repr == PIC_REPR_FP32_ABS ? 24 : 28);
+}
+int64_t elem_bytes(int repr) { return repr == PIC_REPR_FP64 ? 8 : 4; }
+int64_t rho_elem(int dep) { return dep == PIC_DEP_ATOMIC_FP32 ? 4 : 8; }
+int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+struct Layout {
+  int ns, nx, ny, nz, ntx, nty, ntz, ntiles;
+  int64_t nodes, nbins;
+};
+
+Layout layout_of(const pic_config &c) {
+  Layout L;
+  L.ns = c.n_species;
+  L.nx = c.nx;
+  L.ny = c.ny;
+  L.nz = c.nz;
+  L.ntx = (c.nx + kTile - 1) / kTile;
+  L.nty = (c.ny + kTile - 1) / kTile;
+  L.ntz = (c.nz + kTile - 1) / kTile;
+  L.ntiles = L.ntx * L.nty * L.ntz;
+  L.nodes = (int64_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
+  L.nbins = c.object.kind == PIC_OBJ_CRATER ? (int64_t)c.nx * c.ny
+                                             : (c.object.kind == PIC_OBJ_SPHERE ? 1 : 0);
+  return L;
+}
+
+// Device bytes of one species buffer (all arrays, 256-B aligned each).
+int64_t species_buffer_bytes(int repr, int64_t cap) {
+  const int64_t e = elem_bytes(repr);
+  int64_t b = 6 * align256(cap * e);
+  if (repr == PIC_REPR_FP32_CELL) b += align256(cap * 4);
+  return b;
+}
+
+int64_t mesh_bytes(const pic_config &c, const Layout &L) {
+  const int64_t e4 = c.repr == PIC_REPR_FP64 ? 32 : 16;
+  int64_t b = 2 * align256(L.nodes * e4);                      // node E + staging
+  b += align256(L.nodes * rho_elem(c.deposit));                 // rho
+  b += align256(L.nbins * L.ns * 8) + align256(6 * L.ns * 8);  // tallies
+  b += 2 * align256((int64_t)L.ns * (L.ntiles + 1) * 8);        // bucket offsets
+  b += 2 * align256((int64_t)L.ns * L.ntiles * 4);              // counts, cursors
+  b += align256((int64_t)L.ns * L.ntiles * kNeighbours * 4);    // per-tile histograms
+  b += 4096;                                                    // stats, flags
+  return b;
+}
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+const char *validate_config(const pic_config *c) {
+  if (!c) return "config is NULL";
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1 || c->nx > kMaxDim || c->ny > kMaxDim ||
+      c->nz > kMaxDim)
+    return "nx, ny, nz must be in 1..1023";
+  if (!(c->h > 0) || !is_finite(c->h)) return "h must be finite and > 0";
+  if (!(c->dt > 0) || !is_finite(c->dt)) return "dt must be finite and > 0";
+  for (int d = 0; d < 3; ++d)
+    if (!is_finite(c->origin[d])) return "origin must be finite";
+  if (c->n_species < 1 || c->n_species > PIC_MAX_SPECIES) return "n_species must be in 1..4";
+  for (int s = 0; s < c->n_species; ++s) {
+    const pic_species &sp = c->species[s];
+    if (!(sp.m > 0) || !is_finite(sp.m)) return "species mass must be finite and > 0";
+    if (!is_finite(sp.q) || !is_finite(sp.weight)) return "species charge and weight must be finite";
+    if (!(std::fabs(sp.q * sp.weight) <= 1048576.0)) return "|q*weight| must be <= 2^20";
+    if (c->capacity[s] < 0 || c->capacity[s] > kMaxCapacity)
+      return "capacity must be in 0..2^31-1025";
+  }
+  if (c->repr < 0 || c->repr > 2) return "repr must be a pic_repr";
+  if (c->deposit < 0 || c->deposit > 2) return "deposit must be a pic_deposit";
+  if (c->sort_interval < 0 || c->sort_interval > 1000000) return "sort_interval must be 0..1e6";
+  const pic_object &o = c->object;
+  if (o.kind < 0 || o.kind > 2) return "object.kind must be a pic_object_kind";
+  if (o.kind == PIC_OBJ_SPHERE) {
+    for (int d = 0; d < 3; ++d)
+      if (!is_finite(o.center[d])) return "sphere centre must be finite";
+    if (!(o.radius > 0) || !is_finite(o.radius)) return "sphere radius must be finite and > 0";
+  }
+  if (o.kind == PIC_OBJ_CRATER) {
+    if (!is_finite(o.center[0]) || !is_finite(o.center[1]) || !is_finite(o.z_flat))
+      return "crater centre and z_flat must be finite";
+    if (!(o.rim_radius > 0) || !is_finite(o.rim_radius)) return "crater rim_radius must be > 0";
+    if (!(o.depth > 0) || !is_finite(o.depth)) return "crater depth must be > 0";
+  }
+  return nullptr;
+}
+
+Geom geometry_of(const pic_config &c) {
+  Geom g{};
+  g.kind = c.object.kind;
+  double cc[3] = {0, 0, 0}, r2 = 0, zf = 0;
+  if (c.object.kind == PIC_OBJ_SPHERE) {
+    for (int d = 0; d < 3; ++d) cc[d] = (c.object.center[d] - c.origin[d]) / c.h;
+    const double R = c.object.radius / c.h;
+    r2 = R * R;
+  } else if (c.object.kind == PIC_OBJ_CRATER) {
+    // bowl sphere: radius Rc = (a^2 + d^2) / (2d), centre height z_flat - d + Rc
+    const double a = c.object.rim_radius / c.h, dep = c.object.depth / c.h;
+    zf = (c.object.z_flat - c.origin[2]) / c.h;
+    const double Rc = (a * a + dep * dep) / (2.0 * dep);
+    cc[0] = (c.object.center[0] - c.origin[0]) / c.h;
+    cc[1] = (c.object.center[1] - c.origin[1]) / c.h;
+    cc[2] = zf - dep + Rc;
+    r2 = Rc * Rc;
+  }
+  for (int d = 0; d < 3; ++d) {
+    g.c[d] = cc[d];
+    g.ci[d] = (int32_t)std::floor(cc[d]);
+    g.cf[d] = cc[d] - (double)g.ci[d];
+  }
+  g.r2 = r2;
+  g.z_flat = zf;
+  g.zfi = (int32_t)std::floor(zf);
+  g.zff = zf - (double)g.zfi;
+  return g;
+}
+
+int64_t footprint(const pic_config &c) {
+  const Layout L = layout_of(c);
+  int64_t b = mesh_bytes(c, L);
+  for (int s = 0; s < c.n_species; ++s) b += 2 * species_buffer_bytes(c.repr, c.capacity[s]);
+  return b;
+}
+
+struct Ev {
+  int kind;  // 0 step, 1 sort, 2 clear
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct pic_ctx {
+  pic_config cfg;
+  Layout L;
+  Geom geom;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  std::vector<void *> allocs;
+  void *E = nullptr, *E_spare = nullptr, *rho = nullptr;
+  int64_t *tally = nullptr, *escaped = nullptr, *stats = nullptr;
+  int32_t *err = nullptr, *bad = nullptr;
+  int64_t *off[2] = {nullptr, nullptr};
+  int32_t *count = nullptr, *cursor = nullptr, *hist = nullptr;
+  struct Species {
+    int64_t cap = 0;
+    int64_t n_buf = 0;  // entries in the current buffer (valid while unsorted)
+    int64_t loaded = 0;
+    bool ids = false;
+    void *mem[2] = {nullptr, nullptr};
+    int64_t *ids_mem[2] = {nullptr, nullptr};
+    PBuf buf[2];
+  } sp[PIC_MAX_SPECIES];
+  int cur = 0, cur_off = 0;
+  bool sorted = false;
+  bool E_set = false;
+  int since_sort = 0;
+  int K = kDefaultSort;
+  std::string msg = "no error";
+  bool prof = false;
+  std::vector<Ev> events;
+  std::vector<hipEvent_t> event_pool;
+  pic_profile acc{};
+};
+
+namespace {
+
+pic_status fail(pic_ctx *c, pic_status st, const std::string &m) {
+  if (c) c->msg = m;
+  else g_create_error = m;
+  return st;
+}
+
+pic_status hip_fail(pic_ctx *c, hipError_t e, const char *where) {
+  return fail(c, PIC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define PIC_HIP(ctx, call)                                  \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);  \
+  } while (0)
+
+void carve(PBuf &b, void *mem, int repr, int64_t cap) {
+  char *p = (char *)mem;
+  const int64_t a = align256(cap * elem_bytes(repr));
+  for (int d = 0; d < 3; ++d) {
+    b.pos[d] = p;
+    p += a;
+  }
+  for (int d = 0; d < 3; ++d) {
+    b.vel[d] = p;
+    p += a;
+  }
+  b.cell = repr == PIC_REPR_FP32_CELL ? (int32_t *)p : nullptr;
+  b.ids = nullptr;
+}
+
+void free_all(pic_ctx *c) {
+  for (void *p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  c->event_pool.clear();
+  for (Ev &e : c->events) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  c->events.clear();
+}
+
+hipError_t dmalloc(pic_ctx *c, void **p, int64_t bytes) {
+  *p = nullptr;
+  if (bytes <= 0) bytes = 256;
+  hipError_t e = hipMalloc(p, (size_t)bytes);
+  if (e == hipSuccess) c->allocs.push_back(*p);
+  return e;
+}
+
+hipEvent_t take_event(pic_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records a start event when profiling; returns its index or -1.
+int prof_begin(pic_ctx *c, int kind) {
+  if (!c->prof) return -1;
+  Ev ev{kind, take_event(c), take_event(c)};
+  if (!ev.a || !ev.b) return -1;
+  (void)hipEventRecord(ev.a, c->stream);
+  c->events.push_back(ev);
+  return (int)c->events.size() - 1;
+}
+
+void prof_end(pic_ctx *c, int idx) {
+  if (idx >= 0) (void)hipEventRecord(c->events[idx].b, c->stream);
+}
+
+// Folds recorded events into the totals (stream must be idle).
+void prof_collect(pic_ctx *c) {
+  for (Ev &e : c->events) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      if (e.kind == 0) {
+        c->acc.step_launches++;
+        c->acc.step_ms += ms;
+      } else if (e.kind == 1) {
+        c->acc.sort_launches++;
+        c->acc.sort_ms += ms;
+      } else {
+        c->acc.clear_launches++;
+        c->acc.clear_ms += ms;
+      }
+    }
+    c->event_pool.push_back(e.a);
+    c->event_pool.push_back(e.b);
+  }
+  c->events.clear();
+}
+
+pic_status check_ctx(pic_ctx *c) {
+  if (!c) return PIC_E_INVALID;
+  return PIC_OK;
+}
+
+// Synchronises, folds profiling events and reports device-side errors.
+pic_status sync_and_check(pic_ctx *c) {
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  if (c->prof) prof_collect(c);
+  int32_t err = 0;
+  PIC_HIP(c, hipMemcpy(&err, c->err, sizeof(err), hipMemcpyDeviceToHost));
+  if (err) {
+    const int32_t zero = 0;
+    PIC_HIP(c, hipMemcpy(c->err, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    return fail(c, PIC_E_RANGE, "a particle position became non-finite or moved > 2^20 cells");
+  }
+  return PIC_OK;
+}
+
+StepParams step_params(pic_ctx *c) {
+  StepParams P{};
+  const Layout &L = c->L;
+  for (int s = 0; s < L.ns; ++s) P.buf[s] = c->sp[s].buf[c->cur];
+  P.off = c->off[c->cur_off];
+  P.ns = L.ns;
+  P.nx = L.nx;
+  P.ny = L.ny;
+  P.nz = L.nz;
+  P.ntx = L.ntx;
+  P.nty = L.nty;
+  P.ntz = L.ntz;
+  P.ntiles = L.ntiles;
+  const bool f64 = c->cfg.repr == PIC_REPR_FP64;
+  for (int s = 0; s < L.ns; ++s) {
+    const pic_species &sp = c->cfg.species[s];
+    P.qmdt[s] = sp.q / sp.m * c->cfg.dt / c->cfg.h;
+    P.chg[s] = sp.q * sp.weight;
+    const double chgT = f64 ? P.chg[s] : (double)(float)P.chg[s];
+    P.chg_fixed[s] = std::llrint(chgT * kTwo32);
+  }
+  P.dt = c->cfg.dt;
+  P.geom = c->geom;
+  P.E = c->E;
+  P.rho = c->rho;
+  P.tally = c->tally;
+  P.escaped = c->escaped;
+  P.stats = c->stats;
+  P.err = c->err;
+  return P;
+}
+
+pic_status do_sort(pic_ctx *c) {
+  const Layout &L = c->L;
+  SortParams S{};
+  int64_t max_src = 0;
+  for (int s = 0; s < L.ns; ++s) {
+    S.src[s] = c->sp[s].buf[c->cur];
+    S.dst[s] = c->sp[s].buf[1 - c->cur];
+    S.n_src[s] = c->sp[s].n_buf;
+    if (c->sp[s].n_buf > max_src) max_src = c->sp[s].n_buf;
+    if (c->sp[s].ids) S.has_ids |= 1 << s;
+  }
+  S.off_src = c->sorted ? c->off[c->cur_off] : nullptr;
+  S.off_dst = c->off[1 - c->cur_off];
+  S.count = c->count;
+  S.cursor = c->cursor;
+  S.hist = c->hist;
+  S.ns = L.ns;
+  S.nx = L.nx;
+  S.ny = L.ny;
+  S.nz = L.nz;
+  S.ntx = L.ntx;
+  S.nty = L.nty;
+  S.ntz = L.ntz;
+  S.ntiles = L.ntiles;
+  const int pe = prof_begin(c, 1);
+  PIC_HIP(c, launch_sort_count(c->cfg.repr, S, max_src, c->stream));
+  PIC_HIP(c, launch_sort_scan(S, c->stream));
+  PIC_HIP(c, launch_sort_scatter(c->cfg.repr, S, max_src, c->stream));
+  prof_end(c, pe);
+  c->cur = 1 - c->cur;
+  c->cur_off = 1 - c->cur_off;
+  c->sorted = true;
+  c->since_sort = 0;
+  return PIC_OK;
+}
+
+pic_status clear_rho(pic_ctx *c) {
+  const int pe = prof_begin(c, 2);
+  PIC_HIP(c, launch_fill(c->rho, c->L.nodes * rho_elem(c->cfg.deposit), c->stream));
+  prof_end(c, pe);
+  return PIC_OK;
+}
+
+// Number of entries in the current buffer of each species (reads the bucket
+// end offsets when sorted).
+pic_status buffer_extents(pic_ctx *c, int64_t *n) {
+  const Layout &L = c->L;
+  if (!c->sorted) {
+    for (int s = 0; s < L.ns; ++s) n[s] = c->sp[s].n_buf;
+    return PIC_OK;
+  }
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  for (int s = 0; s < L.ns; ++s) {
+    int64_t v = 0;
+    PIC_HIP(c, hipMemcpy(&v, c->off[c->cur_off] + (int64_t)s * (L.ntiles + 1) + L.ntiles,
+                         sizeof(v), hipMemcpyDeviceToHost));
+    n[s] = v;
+  }
+  return PIC_OK;
+}
+
+// Resets the collected counts and escape counters of one species.
+pic_status reset_species_counters(pic_ctx *c, int s) {
+  const Layout &L = c->L;
+  std::vector<int64_t> t(L.nbins * L.ns), e(6 * L.ns);
+  if (L.nbins) PIC_HIP(c, hipMemcpy(t.data(), c->tally, t.size() * 8, hipMemcpyDeviceToHost));
+  PIC_HIP(c, hipMemcpy(e.data(), c->escaped, e.size() * 8, hipMemcpyDeviceToHost));
+  for (int64_t b = 0; b < L.nbins; ++b) t[b * L.ns + s] = 0;
+  for (int f = 0; f < 6; ++f) e[f * L.ns + s] = 0;
+  if (L.nbins) PIC_HIP(c, hipMemcpy(c->tally, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+  PIC_HIP(c, hipMemcpy(c->escaped, e.data(), e.size() * 8, hipMemcpyHostToDevice));
+  return PIC_OK;
+}
+
+// Makes the spare buffer of species s (just filled) its current buffer; the
+// other species keep theirs. Every species then goes through an unsorted
+// re-bucketing at the next step.
+pic_status commit_species(pic_ctx *c, int s, int64_t n, bool ids) {
+  int64_t ext[PIC_MAX_SPECIES] = {0, 0, 0, 0};
+  pic_status st = buffer_extents(c, ext);
+  if (st != PIC_OK) return st;
+  pic_ctx::Species &S = c->sp[s];
+  std::swap(S.mem[0], S.mem[1]);
+  std::swap(S.ids_mem[0], S.ids_mem[1]);
+  std::swap(S.buf[0], S.buf[1]);
+  for (int k = 0; k < c->L.ns; ++k) c->sp[k].n_buf = ext[k];
+  S.n_buf = n;
+  S.loaded = n;
+  S.ids = ids;
+  c->sorted = false;
+  return reset_species_counters(c, s);
+}
+
+pic_status ensure_ids(pic_ctx *c, int s) {
+  pic_ctx::Species &S = c->sp[s];
+  if (S.ids_mem[0]) return PIC_OK;
+  void *a = nullptr, *b = nullptr;
+  const int64_t bytes = align256(S.cap * 8);
+  if (dmalloc(c, &a, bytes) != hipSuccess) return fail(c, PIC_E_NOMEM, "no device memory for ids");
+  if (dmalloc(c, &b, bytes) != hipSuccess) return fail(c, PIC_E_NOMEM, "no device memory for ids");
+  S.ids_mem[0] = (int64_t *)a;
+  S.ids_mem[1] = (int64_t *)b;
+  S.buf[0].ids = S.ids_mem[0];
+  S.buf[1].ids = S.ids_mem[1];
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pic_status_string(pic_status s) {
+  switch (s) {
+    case PIC_OK: return "PIC_OK";
+    case PIC_E_INVALID: return "PIC_E_INVALID";
+    case PIC_E_NOMEM: return "PIC_E_NOMEM";
+    case PIC_E_DEVICE: return "PIC_E_DEVICE";
+    case PIC_E_STATE: return "PIC_E_STATE";
+    case PIC_E_RANGE: return "PIC_E_RANGE";
+  }
+  return "unknown pic_status";
+}
+
+const char *pic_last_error(const pic_ctx *ctx) {
+  return ctx ? ctx->msg.c_str() : g_create_error.c_str();
+}
+
+pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
+  if (!out) return fail(nullptr, PIC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (const char *m = validate_config(cfg)) return fail(nullptr, PIC_E_INVALID, m);
+  const int64_t need = footprint(*cfg);
+  if (const char *b = std::getenv("PIC_HBM_BUDGET_BYTES")) {
+    const long long budget = std::atoll(b);
+    if (budget > 0 && need > budget)
+      return fail(nullptr, PIC_E_NOMEM,
+                  "footprint " + std::to_string(need) + " B exceeds PIC_HBM_BUDGET_BYTES");
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, PIC_E_DEVICE, "no HIP device available");
+  pic_ctx *c = new pic_ctx();
+  c->cfg = *cfg;
+  c->L = layout_of(*cfg);
+  c->geom = geometry_of(*cfg);
+  c->K = cfg->sort_interval > 0 ? cfg->sort_interval : kDefaultSort;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, PIC_E_DEVICE, "hipGetDevice failed");
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)need > free_b) {
+    delete c;
+    return fail(nullptr, PIC_E_NOMEM,
+                "footprint " + std::to_string(need) + " B exceeds free device memory");
+  }
+  auto bail = [&](pic_status st, const std::string &m) {
+    free_all(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return fail(nullptr, st, m);
+  };
+  if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(PIC_E_DEVICE, "hipStreamCreate failed");
+    c->own_stream = true;
+  }
+  const Layout &L = c->L;
+  const int64_t e4 = cfg->repr == PIC_REPR_FP64 ? 32 : 16;
+  void *p = nullptr;
+  struct Req {
+    void **dst;
+    int64_t bytes;
+  } reqs[] = {
+      {&c->E, L.nodes * e4},
+      {&c->E_spare, L.nodes * e4},
+      {&c->rho, L.nodes * rho_elem(cfg->deposit)},
+      {(void **)&c->tally, L.nbins * L.ns * 8},
+      {(void **)&c->escaped, 6 * L.ns * 8},
+      {(void **)&c->stats, 64},
+      {(void **)&c->err, 64},
+      {(void **)&c->bad, 64},
+      {(void **)&c->off[0], (int64_t)L.ns * (L.ntiles + 1) * 8},
+      {(void **)&c->off[1], (int64_t)L.ns * (L.ntiles + 1) * 8},
+      {(void **)&c->count, (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->cursor, (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->hist, (int64_t)L.ns * L.ntiles * kNeighbours * 4},
+  };
+  for (Req &r : reqs) {
+    if (dmalloc(c, &p, r.bytes) != hipSuccess) return bail(PIC_E_NOMEM, "hipMalloc failed");
+    *r.dst = p;
+    if (hipMemset(p, 0, (size_t)(r.bytes > 0 ? r.bytes : 256)) != hipSuccess)
+      return bail(PIC_E_DEVICE, "hipMemset failed");
+  }
+  for (int s = 0; s < L.ns; ++s) {
+    pic_ctx::Species &S = c->sp[s];
+    S.cap = cfg->capacity[s];
+    for (int b = 0; b < 2; ++b) {
+      if (dmalloc(c, &S.mem[b], species_buffer_bytes(cfg->repr, S.cap)) != hipSuccess)
+        return bail(PIC_E_NOMEM, "hipMalloc of particle buffers failed");
+      carve(S.buf[b], S.mem[b], cfg->repr, S.cap);
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return bail(PIC_E_DEVICE, "device error at create");
+  *out = c;
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_all(ctx);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+pic_status pic_load_particles(pic_ctx *c, int32_t species, int64_t n, const double *x,
+                              const double *y, const double *z, const double *vx,
+                              const double *vy, const double *vz, const int64_t *ids) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
+  pic_ctx::Species &S = c->sp[species];
+  if (n < 0 || n > S.cap) return fail(c, PIC_E_INVALID, "n must be in 0..capacity");
+  if (n > 0 && (!x || !y || !z || !vx || !vy || !vz))
+    return fail(c, PIC_E_INVALID, "particle arrays must not be NULL");
+  const pic_config &cf = c->cfg;
+  const int repr = cf.repr;
+  const double *X[3] = {x, y, z}, *V[3] = {vx, vy, vz};
+  const int32_t n3[3] = {cf.nx, cf.ny, cf.nz};
+  const int64_t e = elem_bytes(repr);
+  std::vector<char> pos(3 * n * e + 1), vel(3 * n * e + 1);
+  std::vector<int32_t> cell(repr == PIC_REPR_FP32_CELL ? n : 0);
+  for (int64_t p = 0; p < n; ++p) {
+    int ci[3];
+    for (int d = 0; d < 3; ++d) {
+      const double g = (X[d][p] - cf.origin[d]) / cf.h;
+      if (!(g >= 0.0 && g < (double)n3[d]))
+        return fail(c, PIC_E_INVALID, "particle " + std::to_string(p) + " is outside the box");
+      const double u = V[d][p] / cf.h;
+      if (!is_finite(u)) return fail(c, PIC_E_INVALID, "velocities must be finite");
+      if (repr == PIC_REPR_FP64) {
+        ((double *)pos.data())[d * n + p] = g;
+        ((double *)vel.data())[d * n + p] = u;
+      } else if (repr == PIC_REPR_FP32_ABS) {
+        ((float *)pos.data())[d * n + p] = (float)g;
+        ((float *)vel.data())[d * n + p] = (float)u;
+      } else {
+        int i = (int)std::floor(g);
+        float o = (float)(g - (double)i);
+        if (o == 1.0f) {  // offset rounded up into the next cell
+          o = 0.0f;
+          i += 1;
+        }
+        if (i >= n3[d])
+          return fail(c, PIC_E_INVALID, "particle " + std::to_string(p) + " is outside the box");
+        ci[d] = i;
+        ((float *)pos.data())[d * n + p] = o;
+        ((float *)vel.data())[d * n + p] = (float)u;
+      }
+    }
+    if (repr == PIC_REPR_FP32_CELL)
+      cell[p] = ci[0] | (ci[1] << kCellBits) | (ci[2] << (2 * kCellBits));
+  }
+  if (ids) {
+    pic_status st = ensure_ids(c, species);
+    if (st != PIC_OK) return st;
+  }
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  const PBuf &B = S.buf[1 - c->cur];  // the spare buffer
+  for (int d = 0; d < 3 && n > 0; ++d) {
+    PIC_HIP(c, hipMemcpy(B.pos[d], pos.data() + d * n * e, n * e, hipMemcpyHostToDevice));
+    PIC_HIP(c, hipMemcpy(B.vel[d], vel.data() + d * n * e, n * e, hipMemcpyHostToDevice));
+  }
+  if (repr == PIC_REPR_FP32_CELL && n > 0)
+    PIC_HIP(c, hipMemcpy(B.cell, cell.data(), n * 4, hipMemcpyHostToDevice));
+  if (ids && n > 0) PIC_HIP(c, hipMemcpy(B.ids, ids, n * 8, hipMemcpyHostToDevice));
+  return commit_species(c, species, n, ids != nullptr);
+}
+
+pic_status pic_load_particles_f32_dev(pic_ctx *c, int32_t species, int64_t n, const float *x,
+                                      const float *y, const float *z, const float *vx,
+                                      const float *vy, const float *vz, const int64_t *ids) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
+  pic_ctx::Species &S = c->sp[species];
+  if (n < 0 || n > S.cap) return fail(c, PIC_E_INVALID, "n must be in 0..capacity");
+  if (n > 0 && (!x || !y || !z || !vx || !vy || !vz))
+    return fail(c, PIC_E_INVALID, "particle arrays must not be NULL");
+  if (ids) {
+    pic_status st = ensure_ids(c, species);
+    if (st != PIC_OK) return st;
+  }
+  LoadParams Lp{};
+  Lp.x[0] = x;
+  Lp.x[1] = y;
+  Lp.x[2] = z;
+  Lp.v[0] = vx;
+  Lp.v[1] = vy;
+  Lp.v[2] = vz;
+  Lp.ids = ids;
+  Lp.out = S.buf[1 - c->cur];
+  Lp.n = n;
+  for (int d = 0; d < 3; ++d) Lp.origin[d] = c->cfg.origin[d];
+  Lp.h = c->cfg.h;
+  Lp.nx = c->cfg.nx;
+  Lp.ny = c->cfg.ny;
+  Lp.nz = c->cfg.nz;
+  Lp.bad = c->bad;
+  PIC_HIP(c, launch_fill(c->bad, 4, c->stream));
+  PIC_HIP(c, launch_load_f32(c->cfg.repr, Lp, c->stream));
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  int32_t bad = 0;
+  PIC_HIP(c, hipMemcpy(&bad, c->bad, 4, hipMemcpyDeviceToHost));
+  if (bad) return fail(c, PIC_E_INVALID, std::to_string(bad) + " particles are outside the box");
+  return commit_species(c, species, n, ids != nullptr);
+}
+
+pic_status pic_set_node_E(pic_ctx *c, const double *Ex, const double *Ey, const double *Ez) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (!Ex || !Ey || !Ez) return fail(c, PIC_E_INVALID, "field arrays must not be NULL");
+  const int64_t nodes = c->L.nodes;
+  const bool f64 = c->cfg.repr == PIC_REPR_FP64;
+  std::vector<char> buf(nodes * (f64 ? 32 : 16));
+  for (int64_t i = 0; i < nodes; ++i) {
+    if (!is_finite(Ex[i]) || !is_finite(Ey[i]) || !is_finite(Ez[i]))
+      return fail(c, PIC_E_INVALID, "node field must be finite");
+    if (f64) {
+      double *d = (double *)buf.data() + 4 * i;
+      d[0] = Ex[i];
+      d[1] = Ey[i];
+      d[2] = Ez[i];
+      d[3] = 0;
+    } else {
+      float *f = (float *)buf.data() + 4 * i;
+      f[0] = (float)Ex[i];
+      f[1] = (float)Ey[i];
+      f[2] = (float)Ez[i];
+      f[3] = 0;
+    }
+  }
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  PIC_HIP(c, hipMemcpy(c->E, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  c->E_set = true;
+  return PIC_OK;
+}
+
+pic_status pic_set_node_E_f32_dev(pic_ctx *c, const float *Ex, const float *Ey, const float *Ez) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (!Ex || !Ey || !Ez) return fail(c, PIC_E_INVALID, "field arrays must not be NULL");
+  PIC_HIP(c, launch_fill(c->bad, 4, c->stream));
+  PIC_HIP(c, launch_node_E_f32(c->cfg.repr, Ex, Ey, Ez, c->E_spare, c->L.nodes, c->bad,
+                               c->stream));
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  int32_t bad = 0;
+  PIC_HIP(c, hipMemcpy(&bad, c->bad, 4, hipMemcpyDeviceToHost));
+  if (bad) return fail(c, PIC_E_INVALID, "node field must be finite");
+  std::swap(c->E, c->E_spare);
+  c->E_set = true;
+  return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx *c, int32_t nsteps) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (nsteps < 0) return fail(c, PIC_E_INVALID, "nsteps must be >= 0");
+  if (nsteps > 0 && !c->E_set) return fail(c, PIC_E_STATE, "pic_set_node_E has not been called");
+  pic_status st;
+  if (nsteps == 0) {
+    if (!c->sorted && (st = do_sort(c)) != PIC_OK) return st;
+    if ((st = clear_rho(c)) != PIC_OK) return st;
+    StepParams P = step_params(c);
+    const int pe = prof_begin(c, 0);
+    PIC_HIP(c, launch_step(c->cfg.repr, c->cfg.deposit, false, P, c->stream));
+    prof_end(c, pe);
+    return PIC_OK;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    if ((!c->sorted || c->since_sort >= c->K) && (st = do_sort(c)) != PIC_OK) return st;
+    if ((st = clear_rho(c)) != PIC_OK) return st;
+    StepParams P = step_params(c);
+    const int pe = prof_begin(c, 0);
+    PIC_HIP(c, launch_step(c->cfg.repr, c->cfg.deposit, true, P, c->stream));
+    prof_end(c, pe);
+    c->since_sort++;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_synchronize(pic_ctx *c) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  return sync_and_check(c);
+}
+
+pic_status pic_get_rho(pic_ctx *c, double *rho, int64_t *rho_fixed) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (!rho) return fail(c, PIC_E_INVALID, "rho must not be NULL");
+  if (rho_fixed && c->cfg.deposit != PIC_DEP_FIXED64)
+    return fail(c, PIC_E_INVALID, "rho_fixed is only defined for the fixed-point deposit");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  const int64_t nodes = c->L.nodes;
+  const double h3 = c->cfg.h * c->cfg.h * c->cfg.h;
+  if (c->cfg.deposit == PIC_DEP_FIXED64) {
+    std::vector<int64_t> v(nodes);
+    PIC_HIP(c, hipMemcpy(v.data(), c->rho, nodes * 8, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < nodes; ++i) rho[i] = ((double)v[i] * (1.0 / kTwo32)) / h3;
+    if (rho_fixed) std::memcpy(rho_fixed, v.data(), nodes * 8);
+  } else if (c->cfg.deposit == PIC_DEP_ATOMIC_FP32) {
+    std::vector<float> v(nodes);
+    PIC_HIP(c, hipMemcpy(v.data(), c->rho, nodes * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < nodes; ++i) rho[i] = (double)v[i] / h3;
+  } else {
+    std::vector<double> v(nodes);
+    PIC_HIP(c, hipMemcpy(v.data(), c->rho, nodes * 8, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < nodes; ++i) rho[i] = v[i] / h3;
+  }
+  return PIC_OK;
+}
+
+int64_t pic_num_bins(const pic_ctx *c) { return c ? c->L.nbins : 0; }
+
+pic_status pic_get_surface_charge(pic_ctx *c, int64_t nbins, double *charge, int64_t *counts) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (nbins != c->L.nbins) return fail(c, PIC_E_INVALID, "nbins must equal pic_num_bins");
+  if (nbins > 0 && !charge) return fail(c, PIC_E_INVALID, "charge must not be NULL");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  const int ns = c->L.ns;
+  std::vector<int64_t> t(nbins * ns);
+  if (nbins) PIC_HIP(c, hipMemcpy(t.data(), c->tally, t.size() * 8, hipMemcpyDeviceToHost));
+  for (int64_t b = 0; b < nbins; ++b) {
+    double q = 0;
+    for (int s = 0; s < ns; ++s) {
+      const pic_species &sp = c->cfg.species[s];
+      q += (sp.q * sp.weight) * (double)t[b * ns + s];
+    }
+    charge[b] = q;
+  }
+  if (counts && nbins) std::memcpy(counts, t.data(), t.size() * 8);
+  return PIC_OK;
+}
+
+pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64_t *escaped) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  const Layout &L = c->L;
+  std::vector<int64_t> t(L.nbins * L.ns), e(6 * L.ns);
+  if (L.nbins) PIC_HIP(c, hipMemcpy(t.data(), c->tally, t.size() * 8, hipMemcpyDeviceToHost));
+  PIC_HIP(c, hipMemcpy(e.data(), c->escaped, e.size() * 8, hipMemcpyDeviceToHost));
+  for (int s = 0; s < L.ns; ++s) {
+    int64_t a = 0, es = 0;
+    for (int64_t b = 0; b < L.nbins; ++b) a += t[b * L.ns + s];
+    for (int f = 0; f < 6; ++f) es += e[f * L.ns + s];
+    if (absorbed) absorbed[s] = a;
+    if (alive) alive[s] = c->sp[s].loaded - a - es;
+  }
+  if (escaped) std::memcpy(escaped, e.data(), e.size() * 8);
+  return PIC_OK;
+}
+
+pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *n_out, double *x,
+                             double *y, double *z, double *vx, double *vy, double *vz,
+                             int64_t *ids) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
+  if (!n_out) return fail(c, PIC_E_INVALID, "n_out must not be NULL");
+  pic_ctx::Species &S = c->sp[species];
+  if (ids && !S.ids) return fail(c, PIC_E_STATE, "no ids were loaded for this species");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  int64_t ext[PIC_MAX_SPECIES] = {0, 0, 0, 0};
+  if ((st = buffer_extents(c, ext)) != PIC_OK) return st;
+  const int64_t n = ext[species];
+  const int repr = c->cfg.repr;
+  const int64_t e = elem_bytes(repr);
+  const PBuf &B = S.buf[c->cur];
+  std::vector<char> pos(3 * n * e + 1), vel(3 * n * e + 1);
+  std::vector<int32_t> cell(repr == PIC_REPR_FP32_CELL ? n : 0);
+  std::vector<int64_t> id(S.ids ? n : 0);
+  for (int d = 0; d < 3 && n > 0; ++d) {
+    PIC_HIP(c, hipMemcpy(pos.data() + d * n * e, B.pos[d], n * e, hipMemcpyDeviceToHost));
+    PIC_HIP(c, hipMemcpy(vel.data() + d * n * e, B.vel[d], n * e, hipMemcpyDeviceToHost));
+  }
+  if (repr == PIC_REPR_FP32_CELL && n > 0)
+    PIC_HIP(c, hipMemcpy(cell.data(), B.cell, n * 4, hipMemcpyDeviceToHost));
+  if (S.ids && n > 0) PIC_HIP(c, hipMemcpy(id.data(), B.ids, n * 8, hipMemcpyDeviceToHost));
+  const pic_config &cf = c->cfg;
+  int64_t alive = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    const bool dead = repr == PIC_REPR_FP32_CELL
+                          ? cell[p] < 0
+                          : (repr == PIC_REPR_FP64 ? ((double *)pos.data())[p] < 0
+                                                   : ((float *)pos.data())[p] < 0);
+    if (!dead) ++alive;
+  }
+  *n_out = alive;
+  if (alive > cap) return fail(c, PIC_E_INVALID, "cap is smaller than the alive count");
+  if (alive > 0 && (!x || !y || !z || !vx || !vy || !vz))
+    return fail(c, PIC_E_INVALID, "output arrays must not be NULL");
+  double *X[3] = {x, y, z}, *V[3] = {vx, vy, vz};
+  int64_t k = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    double g[3], u[3];
+    if (repr == PIC_REPR_FP32_CELL) {
+      if (cell[p] < 0) continue;
+      const int ci[3] = {cell[p] & kMaxDim, (cell[p] >> kCellBits) & kMaxDim,
+                         cell[p] >> (2 * kCellBits)};
+      for (int d = 0; d < 3; ++d) {
+        g[d] = (double)ci[d] + (double)((float *)pos.data())[d * n + p];
+        u[d] = (double)((float *)vel.data())[d * n + p];
+      }
+    } else if (repr == PIC_REPR_FP32_ABS) {
+      if (((float *)pos.data())[p] < 0) continue;
+      for (int d = 0; d < 3; ++d) {
+        g[d] = (double)((float *)pos.data())[d * n + p];
+        u[d] = (double)((float *)vel.data())[d * n + p];
+      }
+    } else {
+      if (((double *)pos.data())[p] < 0) continue;
+      for (int d = 0; d < 3; ++d) {
+        g[d] = ((double *)pos.data())[d * n + p];
+        u[d] = ((double *)vel.data())[d * n + p];
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      X[d][k] = cf.origin[d] + g[d] * cf.h;
+      V[d][k] = u[d] * cf.h;
+    }
+    if (ids) ids[k] = id[p];
+    ++k;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_profile_enable(pic_ctx *c, int32_t on) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  if (c->prof) prof_collect(c);
+  c->prof = on != 0;
+  c->acc = pic_profile{};
+  PIC_HIP(c, hipMemset(c->stats, 0, 64));
+  return PIC_OK;
+}
+
+pic_status pic_profile_read(pic_ctx *c, pic_profile *out) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (!out) return fail(c, PIC_E_INVALID, "out must not be NULL");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  int64_t ps = 0;
+  PIC_HIP(c, hipMemcpy(&ps, c->stats, 8, hipMemcpyDeviceToHost));
+  *out = c->acc;
+  out->particle_steps = ps;
+  return PIC_OK;
+}
+
+}  // extern "C"

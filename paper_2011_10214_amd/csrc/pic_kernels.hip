@@ -1,0 +1,891 @@
+// HIP kernels of the particle-mesh hot path for gfx950 (CDNA4, wave64).
+//
+// step_kernel    one workgroup per tile of kTile^3 cells: stages the node field
+//                of the tile grown by one cell in LDS, keeps a private rho for
+//                the same region in LDS, and runs gather -> leapfrog push ->
+//                box / object removal -> trilinear deposit for every particle
+//                bucketed to the tile (the particle half of the PIC loop, §2.1;
+//                removal at the outer boundary, §3.1.3; collection at the
+//                object / terrain, §5.2.2). Particles that drifted outside the
+//                staged region take the global-memory path.
+// sort_*         re-bucket particles by tile every K steps (count -> scan ->
+//                scatter), dropping removed particles. The order inside a tile
+//                is whatever the atomics give: every result is invariant to it.
+// load / node_E  convert caller arrays into the device representation.
+//
+// Arithmetic is written with explicit fma and compiled with contraction off, in
+// the expression order of the method's definition, so that the FP64 form
+// reproduces an FP64 CPU evaluation of the same definition bit for bit (and the
+// FP32 forms an FP32 one).
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+template <int R>
+struct RealOf {
+  using T = float;
+};
+template <>
+struct RealOf<PIC_REPR_FP64> {
+  using T = double;
+};
+
+struct __align__(16) F4 {
+  float x, y, z, w;
+};
+struct __align__(16) D4 {
+  double x, y, z, w;
+};
+template <class T>
+struct Vec4Of;
+template <>
+struct Vec4Of<float> {
+  using type = F4;
+};
+template <>
+struct Vec4Of<double> {
+  using type = D4;
+};
+
+template <int D>
+struct AccOf;
+template <>
+struct AccOf<PIC_DEP_FIXED64> {
+  using type = unsigned long long;
+};
+template <>
+struct AccOf<PIC_DEP_ATOMIC_FP32> {
+  using type = float;
+};
+template <>
+struct AccOf<PIC_DEP_ATOMIC_FP64> {
+  using type = double;
+};
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float floorT(float a) { return __builtin_floorf(a); }
+__device__ __forceinline__ double floorT(double a) { return __builtin_floor(a); }
+__device__ __forceinline__ float rintT(float a) { return __builtin_rintf(a); }
+__device__ __forceinline__ double rintT(double a) { return __builtin_rint(a); }
+__device__ __forceinline__ bool finiteT(float a) { return __builtin_isfinite(a); }
+__device__ __forceinline__ bool finiteT(double a) { return __builtin_isfinite(a); }
+__device__ __forceinline__ float absT(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double absT(double a) { return __builtin_fabs(a); }
+template <class T>
+__device__ __forceinline__ T two32();
+template <>
+__device__ __forceinline__ float two32<float>() { return 4294967296.0f; }
+template <>
+__device__ __forceinline__ double two32<double>() { return 4294967296.0; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous run of tiles so that neighbouring tiles share its L2.
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int q = G >> 3, r = G & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+__device__ __forceinline__ int32_t pack_cell(int i, int j, int k) {
+  return i | (j << kCellBits) | (k << (2 * kCellBits));
+}
+
+// Trilinear weights, corner n = a + 2b + 4c at offset (a, b, c).
+template <class T>
+__device__ __forceinline__ void weights(const T f[3], T W[8]) {
+  const T wx0 = T(1) - f[0], wx1 = f[0];
+  const T wy0 = T(1) - f[1], wy1 = f[1];
+  const T wz0 = T(1) - f[2], wz1 = f[2];
+  const T p00 = wx0 * wy0, p10 = wx1 * wy0, p01 = wx0 * wy1, p11 = wx1 * wy1;
+  W[0] = p00 * wz0;
+  W[1] = p10 * wz0;
+  W[2] = p01 * wz0;
+  W[3] = p11 * wz0;
+  W[4] = p00 * wz1;
+  W[5] = p10 * wz1;
+  W[6] = p01 * wz1;
+  W[7] = p11 * wz1;
+}
+
+// Fixed-point contribution at scale 2^32, rounded half to even. cw * 2^32 is
+// exact in T and rint gives the integer nearest to it, so the value equals
+// llrint((double)cw * 2^32).
+template <class T>
+__device__ __forceinline__ long long fixq(T cw) {
+  return (long long)rintT(cw * two32<T>());
+}
+
+// Wave-aggregated LDS counter increment: every active lane adds 1 to
+// ctr[key]; returns the counter value before the wave's adds plus the lane's
+// rank among the active lanes with the same key. The loop runs over a
+// wave-uniform mask of lanes still pending, one distinct key per iteration,
+// so it terminates by construction (a loop that waits on a lane's own key
+// equalling readfirstlane(key) would spin without side effects for the other
+// lanes, and the compiler may assume it never does).
+__device__ __forceinline__ int agg_add(int32_t *ctr, int key) {
+  const int lane = __lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long pending = __ballot(1);
+  int ret = 0;
+  while (pending) {
+    const int leader = __ffsll(pending) - 1;
+    const int k0 = __shfl(key, leader);
+    const unsigned long long m = __ballot(key == k0) & pending;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&ctr[k0], (int)__popcll(m));
+    base = __shfl(base, leader);
+    if ((m >> lane) & 1ull) ret = base + (int)__popcll(m & below);
+    pending &= ~m;
+  }
+  return ret;
+}
+
+// ------------------------------------------------------------------ geometry
+
+template <class T>
+struct GeomT {
+  T c[3], r2, z_flat, cf[3], zff;
+  int ci[3], zfi, kind;
+};
+
+template <class T>
+__device__ __forceinline__ GeomT<T> geom_of(const Geom &g) {
+  GeomT<T> o;
+  o.kind = g.kind;
+  for (int d = 0; d < 3; ++d) {
+    o.c[d] = (T)g.c[d];
+    o.cf[d] = (T)g.cf[d];
+    o.ci[d] = g.ci[d];
+  }
+  o.r2 = (T)g.r2;
+  o.z_flat = (T)g.z_flat;
+  o.zff = (T)g.zff;
+  o.zfi = g.zfi;
+  return o;
+}
+
+template <class T>
+__device__ __forceinline__ T dist2(T dx, T dy, T dz) {
+  return fmaT(dz, dz, fmaT(dy, dy, dx * dx));
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Object test on an absolute position (cell units); bin or -1.
+template <class T>
+__device__ __forceinline__ int hit_abs(const GeomT<T> &G, int nx, int ny, const T g[3]) {
+  if (G.kind == PIC_OBJ_SPHERE) {
+    return dist2(g[0] - G.c[0], g[1] - G.c[1], g[2] - G.c[2]) <= G.r2 ? 0 : -1;
+  }
+  if (G.kind == PIC_OBJ_CRATER) {
+    bool hit = g[2] < T(0);
+    if (!hit && g[2] <= G.z_flat) hit = dist2(g[0] - G.c[0], g[1] - G.c[1], g[2] - G.c[2]) >= G.r2;
+    if (!hit) return -1;
+    const int ix = clampi((int)floorT(g[0]), 0, nx - 1), iy = clampi((int)floorT(g[1]), 0, ny - 1);
+    return ix + nx * iy;
+  }
+  return -1;
+}
+
+// Object test on a cell + offset position; a coordinate minus a constant
+// c = ci + cf is (float)(i - ci) + (o - cf).
+__device__ __forceinline__ int hit_cell(const GeomT<float> &G, int nx, int ny, const int i[3],
+                                        const float o[3]) {
+  if (G.kind == PIC_OBJ_SPHERE) {
+    const float dx = (float)(i[0] - G.ci[0]) + (o[0] - G.cf[0]);
+    const float dy = (float)(i[1] - G.ci[1]) + (o[1] - G.cf[1]);
+    const float dz = (float)(i[2] - G.ci[2]) + (o[2] - G.cf[2]);
+    return dist2(dx, dy, dz) <= G.r2 ? 0 : -1;
+  }
+  if (G.kind == PIC_OBJ_CRATER) {
+    bool hit = i[2] < 0;
+    if (!hit) {
+      const float zrel = (float)(i[2] - G.zfi) + (o[2] - G.zff);
+      if (zrel <= 0.0f) {
+        const float dx = (float)(i[0] - G.ci[0]) + (o[0] - G.cf[0]);
+        const float dy = (float)(i[1] - G.ci[1]) + (o[1] - G.cf[1]);
+        const float dz = (float)(i[2] - G.ci[2]) + (o[2] - G.cf[2]);
+        hit = dist2(dx, dy, dz) >= G.r2;
+      }
+    }
+    if (!hit) return -1;
+    return clampi(i[0], 0, nx - 1) + nx * clampi(i[1], 0, ny - 1);
+  }
+  return -1;
+}
+
+// First box face crossed (x, y, z order, lower first) or -1. The crater's
+// z-lower face is a collection, not an exit.
+__device__ __forceinline__ int box_face(const int i[3], int nx, int ny, int nz, bool crater) {
+  if (i[0] < 0) return 0;
+  if (i[0] >= nx) return 1;
+  if (i[1] < 0) return 2;
+  if (i[1] >= ny) return 3;
+  if (i[2] < 0 && !crater) return 4;
+  if (i[2] >= nz) return 5;
+  return -1;
+}
+
+template <class T>
+__device__ __forceinline__ int box_face_abs(const T g[3], int nx, int ny, int nz, bool crater) {
+  if (g[0] < T(0)) return 0;
+  if (g[0] >= (T)nx) return 1;
+  if (g[1] < T(0)) return 2;
+  if (g[1] >= (T)ny) return 3;
+  if (g[2] < T(0) && !crater) return 4;
+  if (g[2] >= (T)nz) return 5;
+  return -1;
+}
+
+// ------------------------------------------------------------------ step kernel
+
+template <int R, int D, bool PUSH>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
+  using T = typename RealOf<R>::T;
+  using V4 = typename Vec4Of<T>::type;
+  using A = typename AccOf<D>::type;
+  constexpr bool kCell = R == PIC_REPR_FP32_CELL;
+
+  __shared__ V4 sE[PUSH ? kRegNodes : 1];
+  __shared__ A sRho[kRegNodes];
+  __shared__ int32_t sEsc[6 * PIC_MAX_SPECIES];
+  __shared__ int32_t sAbs[PIC_MAX_SPECIES];
+  __shared__ int32_t sAlive;
+
+  const int nt = P.ntiles;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  int total = 0;
+  for (int s = 0; s < P.ns; ++s)
+    total += (int)(P.off[s * (nt + 1) + t + 1] - P.off[s * (nt + 1) + t]);
+  if (total == 0) return;  // uniform over the workgroup
+
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int sx = nx + 1, sy = (nx + 1) * (ny + 1);
+  const int tx = t % P.ntx, ty = (t / P.ntx) % P.nty, tz = t / (P.ntx * P.nty);
+  const int rx0 = tx * kTile - 1, ry0 = ty * kTile - 1, rz0 = tz * kTile - 1;
+  const V4 *__restrict__ gE = (const V4 *)P.E;
+  A *__restrict__ gRho = (A *)P.rho;
+
+  for (int n = threadIdx.x; n < kRegNodes; n += kBlock) {
+    const int a = n % kRegN, b = (n / kRegN) % kRegN, c = n / (kRegN * kRegN);
+    const int gi = rx0 + a, gj = ry0 + b, gk = rz0 + c;
+    if constexpr (PUSH) {
+      V4 e;
+      e.x = 0;
+      e.y = 0;
+      e.z = 0;
+      e.w = 0;
+      if (gi >= 0 && gi <= nx && gj >= 0 && gj <= ny && gk >= 0 && gk <= nz)
+        e = gE[gi + sx * gj + sy * gk];
+      sE[n] = e;
+    }
+    sRho[n] = A(0);
+  }
+  if (threadIdx.x < 6 * PIC_MAX_SPECIES) sEsc[threadIdx.x] = 0;
+  if (threadIdx.x < PIC_MAX_SPECIES) sAbs[threadIdx.x] = 0;
+  if (threadIdx.x == 0) sAlive = 0;
+  __syncthreads();
+
+  const GeomT<T> G = geom_of<T>(P.geom);
+  const bool crater = P.geom.kind == PIC_OBJ_CRATER;
+  const bool sphere = P.geom.kind == PIC_OBJ_SPHERE;
+  const T dt = (T)P.dt;
+  int alive_here = 0;
+
+  for (int s = 0; s < P.ns; ++s) {
+    const int p0 = (int)P.off[s * (nt + 1) + t], p1 = (int)P.off[s * (nt + 1) + t + 1];
+    if (p0 == p1) continue;
+    const T qmdt = (T)P.qmdt[s];
+    const T chg = (T)P.chg[s];
+    const long long chgF = P.chg_fixed[s];
+    T *__restrict__ X0 = (T *)P.buf[s].pos[0];
+    T *__restrict__ X1 = (T *)P.buf[s].pos[1];
+    T *__restrict__ X2 = (T *)P.buf[s].pos[2];
+    T *__restrict__ U0 = (T *)P.buf[s].vel[0];
+    T *__restrict__ U1 = (T *)P.buf[s].vel[1];
+    T *__restrict__ U2 = (T *)P.buf[s].vel[2];
+    int32_t *__restrict__ CELL = P.buf[s].cell;
+
+    for (int p = p0 + (int)threadIdx.x; p < p1; p += kBlock) {
+      int ci[3];
+      T f[3];   // in-cell offsets
+      T gp[3];  // absolute positions (absolute forms)
+      T u[3];
+      if constexpr (kCell) {
+        const int32_t cell = CELL[p];
+        f[0] = X0[p];
+        f[1] = X1[p];
+        f[2] = X2[p];
+        u[0] = U0[p];
+        u[1] = U1[p];
+        u[2] = U2[p];
+        if (cell < 0) continue;  // removed since the last re-bucketing
+        ci[0] = cell & kMaxDim;
+        ci[1] = (cell >> kCellBits) & kMaxDim;
+        ci[2] = cell >> (2 * kCellBits);
+      } else {
+        gp[0] = X0[p];
+        gp[1] = X1[p];
+        gp[2] = X2[p];
+        u[0] = U0[p];
+        u[1] = U1[p];
+        u[2] = U2[p];
+        if (gp[0] < T(0)) continue;  // removed (marked with x = -1)
+        for (int d = 0; d < 3; ++d) {
+          ci[d] = (int)floorT(gp[d]);
+          f[d] = gp[d] - (T)ci[d];
+        }
+      }
+      ++alive_here;
+
+      if constexpr (PUSH) {
+        T W[8];
+        weights(f, W);
+        T Ep[3];
+        const int li = ci[0] - rx0, lj = ci[1] - ry0, lk = ci[2] - rz0;
+#define PIC_ACC(n, e)             \
+  Ep[0] = fmaT(W[n], e.x, Ep[0]); \
+  Ep[1] = fmaT(W[n], e.y, Ep[1]); \
+  Ep[2] = fmaT(W[n], e.z, Ep[2]);
+        if ((unsigned)li < (unsigned)kReg && (unsigned)lj < (unsigned)kReg &&
+            (unsigned)lk < (unsigned)kReg) {
+          const int l0 = li + kRegN * (lj + kRegN * lk);
+          const V4 e0 = sE[l0], e1 = sE[l0 + 1], e2 = sE[l0 + kRegN], e3 = sE[l0 + kRegN + 1];
+          const V4 e4 = sE[l0 + kRegN * kRegN], e5 = sE[l0 + kRegN * kRegN + 1];
+          const V4 e6 = sE[l0 + kRegN * kRegN + kRegN], e7 = sE[l0 + kRegN * kRegN + kRegN + 1];
+          Ep[0] = W[0] * e0.x;
+          Ep[1] = W[0] * e0.y;
+          Ep[2] = W[0] * e0.z;
+          PIC_ACC(1, e1)
+          PIC_ACC(2, e2)
+          PIC_ACC(3, e3)
+          PIC_ACC(4, e4)
+          PIC_ACC(5, e5)
+          PIC_ACC(6, e6)
+          PIC_ACC(7, e7)
+        } else {
+          const int g0 = ci[0] + sx * ci[1] + sy * ci[2];
+          const V4 e0 = gE[g0], e1 = gE[g0 + 1], e2 = gE[g0 + sx], e3 = gE[g0 + sx + 1];
+          const V4 e4 = gE[g0 + sy], e5 = gE[g0 + sy + 1], e6 = gE[g0 + sy + sx],
+                   e7 = gE[g0 + sy + sx + 1];
+          Ep[0] = W[0] * e0.x;
+          Ep[1] = W[0] * e0.y;
+          Ep[2] = W[0] * e0.z;
+          PIC_ACC(1, e1)
+          PIC_ACC(2, e2)
+          PIC_ACC(3, e3)
+          PIC_ACC(4, e4)
+          PIC_ACC(5, e5)
+          PIC_ACC(6, e6)
+          PIC_ACC(7, e7)
+        }
+#undef PIC_ACC
+        // leapfrog: kick with the gathered field, then drift
+        u[0] = fmaT(qmdt, Ep[0], u[0]);
+        u[1] = fmaT(qmdt, Ep[1], u[1]);
+        u[2] = fmaT(qmdt, Ep[2], u[2]);
+        U0[p] = u[0];
+        U1[p] = u[1];
+        U2[p] = u[2];
+        bool bad = false;
+        if constexpr (kCell) {
+          for (int d = 0; d < 3; ++d) {
+            T op = fmaT(u[d], dt, f[d]);
+            T sh = floorT(op);
+            op = op - sh;
+            if (op == T(1)) {  // a tiny negative offset rounded up to 1 after the shift
+              op = T(0);
+              sh = sh + T(1);
+            }
+            bad |= !(absT(sh) <= T(1048576));  // also catches NaN / Inf
+            f[d] = op;
+            ci[d] += bad ? 0 : (int)sh;
+          }
+        } else {
+          for (int d = 0; d < 3; ++d) {
+            gp[d] = fmaT(u[d], dt, gp[d]);
+            bad |= !finiteT(gp[d]);
+          }
+        }
+        int face = -1, bin = -1;
+        if (!bad) {
+          if constexpr (kCell) {
+            face = box_face(ci, nx, ny, nz, crater);
+            if (face < 0) bin = hit_cell(G, nx, ny, ci, f);
+          } else {
+            face = box_face_abs(gp, nx, ny, nz, crater);
+            if (face < 0) bin = hit_abs(G, nx, ny, gp);
+          }
+        }
+        if (bad) atomicOr(P.err, kErrRange);
+        if (face >= 0) atomicAdd(&sEsc[face * PIC_MAX_SPECIES + s], 1);
+        if (sphere) {  // wave reduction of the collected count
+          const unsigned long long m = __ballot(bin >= 0);
+          if (m && __lane_id() == __ffsll(__ballot(1)) - 1) atomicAdd(&sAbs[s], (int)__popcll(m));
+        } else if (bin >= 0) {
+          atomicAdd((unsigned long long *)&P.tally[(long long)bin * P.ns + s], 1ull);
+        }
+        const bool removed = bad || face >= 0 || bin >= 0;
+        if constexpr (kCell) {
+          X0[p] = f[0];
+          X1[p] = f[1];
+          X2[p] = f[2];
+          CELL[p] = removed ? kDeadCell : pack_cell(ci[0], ci[1], ci[2]);
+        } else {
+          X0[p] = removed ? T(-1) : gp[0];
+          X1[p] = gp[1];
+          X2[p] = gp[2];
+        }
+        if (removed) continue;
+        if constexpr (!kCell) {
+          for (int d = 0; d < 3; ++d) {
+            ci[d] = (int)floorT(gp[d]);
+            f[d] = gp[d] - (T)ci[d];
+          }
+        }
+      }
+
+      // trilinear deposit at the (new) position
+      T W[8];
+      weights(f, W);
+      const int li = ci[0] - rx0, lj = ci[1] - ry0, lk = ci[2] - rz0;
+      const bool local = (unsigned)li < (unsigned)kReg && (unsigned)lj < (unsigned)kReg &&
+                         (unsigned)lk < (unsigned)kReg;
+      int idx[8];
+      if (local) {
+        const int l0 = li + kRegN * (lj + kRegN * lk);
+        idx[0] = l0;
+        idx[1] = l0 + 1;
+        idx[2] = l0 + kRegN;
+        idx[3] = l0 + kRegN + 1;
+        idx[4] = l0 + kRegN * kRegN;
+        idx[5] = l0 + kRegN * kRegN + 1;
+        idx[6] = l0 + kRegN * kRegN + kRegN;
+        idx[7] = l0 + kRegN * kRegN + kRegN + 1;
+      } else {
+        const int g0 = ci[0] + sx * ci[1] + sy * ci[2];
+        idx[0] = g0;
+        idx[1] = g0 + 1;
+        idx[2] = g0 + sx;
+        idx[3] = g0 + sx + 1;
+        idx[4] = g0 + sy;
+        idx[5] = g0 + sy + 1;
+        idx[6] = g0 + sy + sx;
+        idx[7] = g0 + sy + sx + 1;
+      }
+      A* dstRho = local ? sRho : gRho;
+      if constexpr (D == PIC_DEP_FIXED64) {
+        long long C[8];
+        long long sum = 0;
+#pragma unroll
+        for (int n = 0; n < 7; ++n) {
+          C[n] = fixq<T>(chg * W[n]);
+          sum += C[n];
+        }
+        C[7] = chgF - sum;
+#pragma unroll
+        for (int n = 0; n < 8; ++n) atomicAdd(&dstRho[idx[n]], (unsigned long long)C[n]);
+      } else if constexpr (D == PIC_DEP_ATOMIC_FP32) {
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+          const float c = (float)(chg * W[n]);
+          if (local) atomicAdd(&dstRho[idx[n]], c);
+          else unsafeAtomicAdd(&dstRho[idx[n]], c);
+        }
+      } else {
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+          const double c = (double)(chg * W[n]);
+          if (local) atomicAdd(&dstRho[idx[n]], c);
+          else unsafeAtomicAdd(&dstRho[idx[n]], c);
+        }
+      }
+    }
+  }
+
+  atomicAdd(&sAlive, alive_here);
+  __syncthreads();
+  for (int n = threadIdx.x; n < kRegNodes; n += kBlock) {
+    const A v = sRho[n];
+    if (v == A(0)) continue;
+    const int a = n % kRegN, b = (n / kRegN) % kRegN, c = n / (kRegN * kRegN);
+    const int gi = rx0 + a, gj = ry0 + b, gk = rz0 + c;
+    if (gi < 0 || gi > nx || gj < 0 || gj > ny || gk < 0 || gk > nz) continue;
+    if constexpr (D == PIC_DEP_FIXED64) atomicAdd(&gRho[gi + sx * gj + sy * gk], v);
+    else unsafeAtomicAdd(&gRho[gi + sx * gj + sy * gk], v);
+  }
+  if (threadIdx.x < 6 * PIC_MAX_SPECIES) {
+    const int face = threadIdx.x / PIC_MAX_SPECIES, s = threadIdx.x % PIC_MAX_SPECIES;
+    const int v = sEsc[threadIdx.x];
+    if (v) atomicAdd((unsigned long long *)&P.escaped[face * P.ns + s], (unsigned long long)v);
+  }
+  if (sphere && threadIdx.x < PIC_MAX_SPECIES && sAbs[threadIdx.x])
+    atomicAdd((unsigned long long *)&P.tally[threadIdx.x], (unsigned long long)sAbs[threadIdx.x]);
+  if (PUSH && threadIdx.x == 0 && sAlive)
+    atomicAdd((unsigned long long *)&P.stats[0], (unsigned long long)sAlive);
+}
+
+// ------------------------------------------------------------------ sort
+
+// Tile of a particle's current cell, or -1 if it was removed.
+template <int R>
+__device__ __forceinline__ int tile_of(const PBuf &B, int p, int ntx, int nty, int tc[3]) {
+  using T = typename RealOf<R>::T;
+  int i, j, k;
+  if constexpr (R == PIC_REPR_FP32_CELL) {
+    const int32_t cell = B.cell[p];
+    if (cell < 0) return -1;
+    i = cell & kMaxDim;
+    j = (cell >> kCellBits) & kMaxDim;
+    k = cell >> (2 * kCellBits);
+  } else {
+    const T x = ((const T *)B.pos[0])[p];
+    if (x < T(0)) return -1;
+    i = (int)floorT(x);
+    j = (int)floorT(((const T *)B.pos[1])[p]);
+    k = (int)floorT(((const T *)B.pos[2])[p]);
+  }
+  tc[0] = i >> kTileShift;
+  tc[1] = j >> kTileShift;
+  tc[2] = k >> kTileShift;
+  return tc[0] + ntx * (tc[1] + nty * tc[2]);
+}
+
+__device__ __forceinline__ int neighbour_rel(const int tc[3], int tx, int ty, int tz) {
+  const int dx = tc[0] - tx, dy = tc[1] - ty, dz = tc[2] - tz;
+  if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return -1;
+  return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+}
+
+__device__ __forceinline__ int neighbour_tile(int rel, int tx, int ty, int tz, int ntx, int nty) {
+  const int dx = rel % 3 - 1, dy = (rel / 3) % 3 - 1, dz = rel / 9 - 1;
+  return (tx + dx) + ntx * ((ty + dy) + nty * (tz + dz));
+}
+
+// Source range of a workgroup: a tile's bucket (sorted source) or a chunk.
+__device__ __forceinline__ void src_range(const SortParams &P, int s, int wg, int64_t chunk,
+                                          int &p0, int &p1, int &t) {
+  if (P.off_src) {
+    t = wg;
+    const int nt = P.ntiles;
+    p0 = (int)P.off_src[s * (nt + 1) + t];
+    p1 = (int)P.off_src[s * (nt + 1) + t + 1];
+  } else {
+    t = -1;
+    const int64_t a = (int64_t)wg * chunk;
+    const int64_t b = a + chunk < P.n_src[s] ? a + chunk : P.n_src[s];
+    p0 = (int)(a < P.n_src[s] ? a : P.n_src[s]);
+    p1 = (int)b;
+    if (p1 < p0) p1 = p0;
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void sort_count_kernel(SortParams P, int64_t chunk) {
+  __shared__ int32_t sH[kNeighbours];
+  const int s = blockIdx.y;
+  const int nt = P.ntiles;
+  if (P.off_src && (int)blockIdx.x >= nt) return;
+  int p0, p1, t;
+  src_range(P, s, blockIdx.x, chunk, p0, p1, t);
+  const bool sorted = t >= 0;
+  int tx = 0, ty = 0, tz = 0;
+  if (sorted) {
+    tx = t % P.ntx;
+    ty = (t / P.ntx) % P.nty;
+    tz = t / (P.ntx * P.nty);
+    if (threadIdx.x < kNeighbours) sH[threadIdx.x] = 0;
+    __syncthreads();
+  }
+  const PBuf B = P.src[s];
+  for (int p = p0 + (int)threadIdx.x; p < p1; p += kBlock) {
+    int tc[3];
+    const int ct = tile_of<R>(B, p, P.ntx, P.nty, tc);
+    if (ct < 0) continue;
+    const int rel = sorted ? neighbour_rel(tc, tx, ty, tz) : -1;
+    if (rel >= 0) agg_add(sH, rel);
+    else atomicAdd(&P.count[s * nt + ct], 1);
+  }
+  if (sorted) {
+    __syncthreads();
+    if (threadIdx.x < kNeighbours) {
+      const int h = sH[threadIdx.x];
+      P.hist[((int64_t)s * nt + t) * kNeighbours + threadIdx.x] = h;
+      if (h) atomicAdd(&P.count[s * nt + neighbour_tile(threadIdx.x, tx, ty, tz, P.ntx, P.nty)], h);
+    }
+  }
+}
+
+// Exclusive scan of the tile counts into bucket offsets; clears the counts and
+// cursors for the next pass. One workgroup per species.
+__global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
+  __shared__ long long sS[1024];
+  const int s = blockIdx.x;
+  const int nt = P.ntiles;
+  const int per = (nt + 1023) / 1024;
+  const int b = threadIdx.x * per;
+  const int e = b + per < nt ? b + per : nt;
+  long long local = 0;
+  for (int i = b; i < e; ++i) local += P.count[s * nt + i];
+  sS[threadIdx.x] = local;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long long v = threadIdx.x >= (unsigned)o ? sS[threadIdx.x - o] : 0;
+    __syncthreads();
+    sS[threadIdx.x] += v;
+    __syncthreads();
+  }
+  long long run = sS[threadIdx.x] - local;
+  for (int i = b; i < e; ++i) {
+    P.off_dst[s * (nt + 1) + i] = run;
+    run += P.count[s * nt + i];
+    P.count[s * nt + i] = 0;
+    P.cursor[s * nt + i] = 0;
+  }
+  if (threadIdx.x == 1023) P.off_dst[s * (nt + 1) + nt] = sS[1023];
+}
+
+template <int R>
+__device__ __forceinline__ void move_particle(const PBuf &S, const PBuf &Dd, int p, int64_t q,
+                                              bool ids) {
+  using T = typename RealOf<R>::T;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ((T *)Dd.pos[d])[q] = ((const T *)S.pos[d])[p];
+    ((T *)Dd.vel[d])[q] = ((const T *)S.vel[d])[p];
+  }
+  if constexpr (R == PIC_REPR_FP32_CELL) Dd.cell[q] = S.cell[p];
+  if (ids) Dd.ids[q] = S.ids[p];
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int64_t chunk) {
+  __shared__ long long sBase[kNeighbours];
+  __shared__ int32_t sCur[kNeighbours];
+  const int s = blockIdx.y;
+  const int nt = P.ntiles;
+  if (P.off_src && (int)blockIdx.x >= nt) return;
+  int p0, p1, t;
+  src_range(P, s, blockIdx.x, chunk, p0, p1, t);
+  const bool sorted = t >= 0;
+  int tx = 0, ty = 0, tz = 0;
+  if (sorted) {
+    tx = t % P.ntx;
+    ty = (t / P.ntx) % P.nty;
+    tz = t / (P.ntx * P.nty);
+    if (threadIdx.x < kNeighbours) {
+      const int h = P.hist[((int64_t)s * nt + t) * kNeighbours + threadIdx.x];
+      long long base = 0;
+      if (h) {
+        const int nb = neighbour_tile(threadIdx.x, tx, ty, tz, P.ntx, P.nty);
+        base = P.off_dst[s * (nt + 1) + nb] + atomicAdd(&P.cursor[s * nt + nb], h);
+      }
+      sBase[threadIdx.x] = base;
+      sCur[threadIdx.x] = 0;
+    }
+    __syncthreads();
+  }
+  const PBuf S = P.src[s], Dd = P.dst[s];
+  const bool ids = (P.has_ids >> s) & 1;
+  for (int p = p0 + (int)threadIdx.x; p < p1; p += kBlock) {
+    int tc[3];
+    const int ct = tile_of<R>(S, p, P.ntx, P.nty, tc);
+    if (ct < 0) continue;  // removed particles are dropped here
+    const int rel = sorted ? neighbour_rel(tc, tx, ty, tz) : -1;
+    long long q;
+    if (rel >= 0) {
+      q = sBase[rel] + agg_add(sCur, rel);
+    } else {
+      q = P.off_dst[s * (nt + 1) + ct] + atomicAdd(&P.cursor[s * nt + ct], 1);
+    }
+    move_particle<R>(S, Dd, p, q, ids);
+  }
+}
+
+// ------------------------------------------------------------------ utility
+
+__global__ void fill_kernel(uint32_t *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+template <int R>
+__global__ void load_f32_kernel(LoadParams L) {
+  using T = typename RealOf<R>::T;
+  const int32_t n3[3] = {L.nx, L.ny, L.nz};
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L.n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    bool bad = false;
+    int ci[3];
+    float o[3];
+    double g[3];
+    for (int d = 0; d < 3; ++d) {
+      g[d] = ((double)L.x[d][p] - L.origin[d]) / L.h;
+      bad |= !(g[d] >= 0.0 && g[d] < (double)n3[d]);
+      if constexpr (R == PIC_REPR_FP32_CELL) {
+        int i = bad ? 0 : (int)__builtin_floor(g[d]);
+        float oo = (float)(g[d] - (double)i);
+        if (oo == 1.0f) {
+          oo = 0.0f;
+          i += 1;
+        }
+        ci[d] = i;
+        o[d] = oo;
+      }
+    }
+    if (bad) {
+      atomicAdd(L.bad, 1);
+      continue;
+    }
+    if constexpr (R == PIC_REPR_FP32_CELL) {
+      // an offset rounded up into the next cell may leave the box
+      if (ci[0] >= L.nx || ci[1] >= L.ny || ci[2] >= L.nz) {
+        atomicAdd(L.bad, 1);
+        continue;
+      }
+      L.out.cell[p] = pack_cell(ci[0], ci[1], ci[2]);
+      for (int d = 0; d < 3; ++d) ((float *)L.out.pos[d])[p] = o[d];
+    } else {
+      for (int d = 0; d < 3; ++d) ((T *)L.out.pos[d])[p] = (T)g[d];
+    }
+    for (int d = 0; d < 3; ++d) ((T *)L.out.vel[d])[p] = (T)((double)L.v[d][p] / L.h);
+    if (L.ids) L.out.ids[p] = L.ids[p];
+  }
+}
+
+template <class V4>
+__global__ void node_E_kernel(const float *Ex, const float *Ey, const float *Ez, V4 *E,
+                              int64_t nodes, int32_t *bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nodes;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    V4 e;
+    e.x = Ex[i];
+    e.y = Ey[i];
+    e.z = Ez[i];
+    e.w = 0;
+    if (!(__builtin_isfinite(Ex[i]) && __builtin_isfinite(Ey[i]) && __builtin_isfinite(Ez[i])))
+      atomicAdd(bad, 1);
+    E[i] = e;
+  }
+}
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <int R, int D>
+hipError_t launch_step_rd(bool push, const StepParams &p, hipStream_t s) {
+  if (p.ntiles <= 0) return hipSuccess;
+  if (push)
+    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles), dim3(kBlock), 0, s, p);
+  else
+    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_step_r(int deposit, bool push, const StepParams &p, hipStream_t s) {
+  switch (deposit) {
+    case PIC_DEP_FIXED64: return launch_step_rd<R, PIC_DEP_FIXED64>(push, p, s);
+    case PIC_DEP_ATOMIC_FP32: return launch_step_rd<R, PIC_DEP_ATOMIC_FP32>(push, p, s);
+    case PIC_DEP_ATOMIC_FP64: return launch_step_rd<R, PIC_DEP_ATOMIC_FP64>(push, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+constexpr int64_t kChunk = 4096;
+
+int64_t sort_blocks(const SortParams &p, int64_t max_src) {
+  return p.off_src ? p.ntiles : (max_src + kChunk - 1) / kChunk;
+}
+
+}  // namespace
+
+hipError_t launch_step(int repr, int deposit, bool push, const StepParams &p, hipStream_t s) {
+  switch (repr) {
+    case PIC_REPR_FP64: return launch_step_r<PIC_REPR_FP64>(deposit, push, p, s);
+    case PIC_REPR_FP32_ABS: return launch_step_r<PIC_REPR_FP32_ABS>(deposit, push, p, s);
+    case PIC_REPR_FP32_CELL: return launch_step_r<PIC_REPR_FP32_CELL>(deposit, push, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sort_count(int repr, const SortParams &p, int64_t max_src, hipStream_t s) {
+  const int64_t nb = sort_blocks(p, max_src);
+  if (nb <= 0 || nb > 0x7fffffff) return nb <= 0 ? hipSuccess : hipErrorInvalidValue;
+  const dim3 grid((unsigned)nb, p.ns);
+  switch (repr) {
+    case PIC_REPR_FP64:
+      hipLaunchKernelGGL(sort_count_kernel<PIC_REPR_FP64>, grid, dim3(kBlock), 0, s, p, kChunk);
+      break;
+    case PIC_REPR_FP32_ABS:
+      hipLaunchKernelGGL(sort_count_kernel<PIC_REPR_FP32_ABS>, grid, dim3(kBlock), 0, s, p, kChunk);
+      break;
+    default:
+      hipLaunchKernelGGL(sort_count_kernel<PIC_REPR_FP32_CELL>, grid, dim3(kBlock), 0, s, p, kChunk);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_scan(const SortParams &p, hipStream_t s) {
+  hipLaunchKernelGGL(sort_scan_kernel, dim3(p.ns), dim3(1024), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s) {
+  const int64_t nb = sort_blocks(p, max_src);
+  if (nb <= 0 || nb > 0x7fffffff) return nb <= 0 ? hipSuccess : hipErrorInvalidValue;
+  const dim3 grid((unsigned)nb, p.ns);
+  switch (repr) {
+    case PIC_REPR_FP64:
+      hipLaunchKernelGGL(sort_scatter_kernel<PIC_REPR_FP64>, grid, dim3(kBlock), 0, s, p, kChunk);
+      break;
+    case PIC_REPR_FP32_ABS:
+      hipLaunchKernelGGL(sort_scatter_kernel<PIC_REPR_FP32_ABS>, grid, dim3(kBlock), 0, s, p, kChunk);
+      break;
+    default:
+      hipLaunchKernelGGL(sort_scatter_kernel<PIC_REPR_FP32_CELL>, grid, dim3(kBlock), 0, s, p, kChunk);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s) {
+  const int64_t n = bytes / 4;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, (uint32_t *)ptr, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s) {
+  if (p.n <= 0) return hipSuccess;
+  const dim3 grid(grid_for(p.n, 256));
+  switch (repr) {
+    case PIC_REPR_FP64:
+      hipLaunchKernelGGL(load_f32_kernel<PIC_REPR_FP64>, grid, dim3(256), 0, s, p);
+      break;
+    case PIC_REPR_FP32_ABS:
+      hipLaunchKernelGGL(load_f32_kernel<PIC_REPR_FP32_ABS>, grid, dim3(256), 0, s, p);
+      break;
+    default:
+      hipLaunchKernelGGL(load_f32_kernel<PIC_REPR_FP32_CELL>, grid, dim3(256), 0, s, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_node_E_f32(int repr, const float *Ex, const float *Ey, const float *Ez,
+                             void *E, int64_t nodes, int32_t *bad, hipStream_t s) {
+  const dim3 grid(grid_for(nodes, 256));
+  if (repr == PIC_REPR_FP64)
+    hipLaunchKernelGGL(node_E_kernel<D4>, grid, dim3(256), 0, s, Ex, Ey, Ez, (D4 *)E, nodes, bad);
+  else
+    hipLaunchKernelGGL(node_E_kernel<F4>, grid, dim3(256), 0, s, Ex, Ey, Ez, (F4 *)E, nodes, bad);
+  return hipGetLastError();
+}
+
+}  // namespace pic

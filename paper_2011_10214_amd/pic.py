@@ -1,0 +1,334 @@
+"""ctypes binding of the C-ABI declared in ``include/pic.h``.
+
+Argument marshalling only: every step of the particle-mesh path runs in the
+HIP library ``libpic.so``. There is no CPU fallback; if the library is missing
+the import fails loudly. PyTorch tensors (device memory) are accepted where the
+C-ABI takes device pointers, and a torch stream can be passed as the context's
+stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+MAX_SPECIES = 4
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_RANGE = 0, -1, -2, -3, -4, -5
+REPR = {"fp64": 0, "fp32_abs": 1, "fp32_cell": 2}
+DEPOSIT = {"fixed64": 0, "fp32": 1, "fp64": 2}
+OBJECT = {"none": 0, "sphere": 1, "crater": 2}
+
+
+class _Species(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("m", ctypes.c_double), ("weight", ctypes.c_double)]
+
+
+class _Object(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("center", ctypes.c_double * 3),
+                ("radius", ctypes.c_double), ("z_flat", ctypes.c_double),
+                ("rim_radius", ctypes.c_double), ("depth", ctypes.c_double)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("h", ctypes.c_double), ("origin", ctypes.c_double * 3), ("dt", ctypes.c_double),
+                ("n_species", ctypes.c_int32), ("species", _Species * MAX_SPECIES),
+                ("object", _Object), ("repr", ctypes.c_int32), ("deposit", ctypes.c_int32),
+                ("sort_interval", ctypes.c_int32), ("capacity", ctypes.c_int64 * MAX_SPECIES),
+                ("stream", ctypes.c_void_p)]
+
+
+class _Profile(ctypes.Structure):
+    _fields_ = [("step_launches", ctypes.c_int64), ("step_ms", ctypes.c_double),
+                ("sort_launches", ctypes.c_int64), ("sort_ms", ctypes.c_double),
+                ("clear_launches", ctypes.c_int64), ("clear_ms", ctypes.c_double),
+                ("particle_steps", ctypes.c_int64)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_st = ctypes.c_int
+
+# name -> (restype, argtypes); one entry per declaration of include/pic.h
+SIGNATURES = {
+    "pic_create": (_st, [ctypes.POINTER(_Config), ctypes.POINTER(_vp)]),
+    "pic_destroy": (None, [_vp]),
+    "pic_load_particles": (_st, [_vp, _i32, _i64] + [_vp] * 7),
+    "pic_load_particles_f32_dev": (_st, [_vp, _i32, _i64] + [_vp] * 7),
+    "pic_set_node_E": (_st, [_vp, _vp, _vp, _vp]),
+    "pic_set_node_E_f32_dev": (_st, [_vp, _vp, _vp, _vp]),
+    "pic_step": (_st, [_vp, _i32]),
+    "pic_synchronize": (_st, [_vp]),
+    "pic_get_rho": (_st, [_vp, _vp, _vp]),
+    "pic_num_bins": (_i64, [_vp]),
+    "pic_get_surface_charge": (_st, [_vp, _i64, _vp, _vp]),
+    "pic_get_counters": (_st, [_vp, _vp, _vp, _vp]),
+    "pic_get_particles": (_st, [_vp, _i32, _i64, _vp] + [_vp] * 7),
+    "pic_profile_enable": (_st, [_vp, _i32]),
+    "pic_profile_read": (_st, [_vp, ctypes.POINTER(_Profile)]),
+    "pic_last_error": (ctypes.c_char_p, [_vp]),
+    "pic_status_string": (ctypes.c_char_p, [_st]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class PicError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{lib().pic_status_string(status).decode()}: {message}")
+        self.status = status
+
+
+@dataclass
+class Config:
+    """Mirror of ``pic_config``."""
+    nx: int
+    ny: int
+    nz: int
+    dt: float
+    species: list                       # [(q, m, weight), ...]
+    capacity: list                      # max particles per species
+    h: float = 1.0
+    origin: tuple = (0.0, 0.0, 0.0)
+    obj: str = "none"
+    center: tuple = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    z_flat: float = 0.0
+    rim_radius: float = 0.0
+    depth: float = 0.0
+    repr: str = "fp32_cell"
+    deposit: str = "fixed64"
+    sort_interval: int = 0
+    stream: int = 0                     # hipStream_t handle (e.g. torch stream.cuda_stream)
+
+    @property
+    def nodes(self) -> int:
+        return (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+
+    def cstruct(self) -> _Config:
+        c = _Config()
+        c.nx, c.ny, c.nz = self.nx, self.ny, self.nz
+        c.h = self.h
+        c.origin[:] = list(self.origin)
+        c.dt = self.dt
+        c.n_species = len(self.species)
+        for s, (q, m, w) in enumerate(self.species):
+            c.species[s].q, c.species[s].m, c.species[s].weight = q, m, w
+        c.object.kind = OBJECT[self.obj]
+        c.object.center[:] = list(self.center)
+        c.object.radius = self.radius
+        c.object.z_flat, c.object.rim_radius, c.object.depth = (self.z_flat, self.rim_radius,
+                                                                self.depth)
+        c.repr = REPR[self.repr]
+        c.deposit = DEPOSIT[self.deposit]
+        c.sort_interval = self.sort_interval
+        for s in range(len(self.species)):
+            c.capacity[s] = int(self.capacity[s])
+        c.stream = self.stream or None
+        return c
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or a torch tensor (None passes NULL)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _is_device(a) -> bool:
+    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _device_sync():
+    """Device arrays handed to the library may still be in flight on torch's
+    stream: wait for them (loads are not on the hot path)."""
+    import torch
+
+    torch.cuda.synchronize()
+
+
+@dataclass
+class Profile:
+    step_launches: int
+    step_ms: float
+    sort_launches: int
+    sort_ms: float
+    clear_launches: int
+    clear_ms: float
+    particle_steps: int
+
+
+class Context:
+    """One ``pic_ctx``: the particle-mesh state of one subdomain on one GPU."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        self._c = cfg.cstruct()
+        h = _vp()
+        st = lib().pic_create(ctypes.byref(self._c), ctypes.byref(h))
+        if st != OK:
+            raise PicError(st, lib().pic_last_error(None).decode())
+        self._h = h
+        self.ns = len(cfg.species)
+
+    # -- plumbing
+    def _check(self, st):
+        if st != OK:
+            raise PicError(st, lib().pic_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pic_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls
+    def load_particles(self, species: int, x, v, ids=None):
+        """x, v: (n, 3) positions and half-step velocities. numpy (host, FP64)
+        or float32 CUDA tensors (device) -- see pic_load_particles(_f32_dev)."""
+        if _is_device(x):
+            _device_sync()
+            cols = [x[:, d].contiguous() for d in range(3)] + [v[:, d].contiguous() for d in range(3)]
+            idt = ids.contiguous() if ids is not None else None
+            n = x.shape[0]
+            self._check(lib().pic_load_particles_f32_dev(self._h, species, n,
+                                                         *[_ptr(c) for c in cols], _ptr(idt)))
+            return
+        x = _host(x, np.float64).reshape(-1, 3)
+        v = _host(v, np.float64).reshape(-1, 3)
+        cols = [_host(x[:, d], np.float64) for d in range(3)] + [_host(v[:, d], np.float64)
+                                                                 for d in range(3)]
+        idh = _host(ids, np.int64) if ids is not None else None
+        self._check(lib().pic_load_particles(self._h, species, x.shape[0],
+                                             *[_ptr(c) for c in cols], _ptr(idh)))
+
+    def load_particles_cols(self, species: int, cols, ids=None):
+        """cols: six float32 device tensors (x, y, z, vx, vy, vz) of equal length."""
+        n = int(cols[0].shape[0])
+        _device_sync()
+        self._check(lib().pic_load_particles_f32_dev(self._h, species, n,
+                                                     *[_ptr(c) for c in cols], _ptr(ids)))
+
+    def set_node_E(self, E):
+        """E: three arrays of (nx+1)(ny+1)(nz+1) values, x fastest: numpy (host,
+        FP64) or float32 CUDA tensors."""
+        if _is_device(E[0]):
+            Es = [e.contiguous() for e in E]
+            _device_sync()
+            self._check(lib().pic_set_node_E_f32_dev(self._h, *[_ptr(e) for e in Es]))
+            return
+        Es = [_host(e, np.float64) for e in E]
+        for e in Es:
+            if e.size != self.cfg.nodes:
+                raise ValueError("node field has the wrong size")
+        self._check(lib().pic_set_node_E(self._h, *[_ptr(e) for e in Es]))
+
+    def step(self, nsteps: int):
+        self._check(lib().pic_step(self._h, int(nsteps)))
+
+    def synchronize(self):
+        self._check(lib().pic_synchronize(self._h))
+
+    def get_rho(self):
+        rho = np.empty(self.cfg.nodes)
+        fixed = np.empty(self.cfg.nodes, np.int64) if self.cfg.deposit == "fixed64" else None
+        self._check(lib().pic_get_rho(self._h, _ptr(rho), _ptr(fixed)))
+        return rho, fixed
+
+    @property
+    def nbins(self) -> int:
+        return int(lib().pic_num_bins(self._h))
+
+    def get_surface_charge(self):
+        nb = self.nbins
+        charge = np.empty(nb)
+        counts = np.empty((nb, self.ns), np.int64)
+        self._check(lib().pic_get_surface_charge(self._h, nb, _ptr(charge) if nb else None,
+                                                 _ptr(counts) if nb else None))
+        return charge, counts
+
+    def get_counters(self):
+        alive = np.empty(self.ns, np.int64)
+        absorbed = np.empty(self.ns, np.int64)
+        escaped = np.empty((6, self.ns), np.int64)
+        self._check(lib().pic_get_counters(self._h, _ptr(alive), _ptr(absorbed), _ptr(escaped)))
+        return alive, absorbed, escaped
+
+    def get_particles(self, species: int, with_ids: bool = True):
+        n_out = ctypes.c_int64(0)
+        alive, _, _ = self.get_counters()
+        cap = int(alive[species])
+        for _ in range(2):
+            cols = [np.empty(cap) for _ in range(6)]
+            ids = np.empty(cap, np.int64) if with_ids else None
+            st = lib().pic_get_particles(self._h, species, cap, ctypes.byref(n_out),
+                                         *[_ptr(c) for c in cols], _ptr(ids))
+            if st == E_INVALID and n_out.value > cap:
+                cap = n_out.value
+                continue
+            self._check(st)
+            n = n_out.value
+            x = np.stack([c[:n] for c in cols[:3]], 1)
+            v = np.stack([c[:n] for c in cols[3:]], 1)
+            return x, v, (ids[:n] if ids is not None else None)
+        raise PicError(E_INVALID, "particle count changed during read-back")
+
+    def profile_enable(self, on: bool = True):
+        self._check(lib().pic_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> Profile:
+        p = _Profile()
+        self._check(lib().pic_profile_read(self._h, ctypes.byref(p)))
+        return Profile(p.step_launches, p.step_ms, p.sort_launches, p.sort_ms, p.clear_launches,
+                       p.clear_ms, p.particle_steps)
+
+
+def config_from_workload(w, repr="fp32_cell", deposit="fixed64", sort_interval=0, capacity=None,
+                         stream=0) -> Config:
+    """Config of a synthetic workload description (duck-typed: needs the mesh,
+    object, species q/m/w and dt attributes)."""
+    cap = capacity if capacity is not None else [s.count for s in w.species]
+    return Config(nx=w.nx, ny=w.ny, nz=w.nz, dt=w.dt, h=w.h, origin=w.origin,
+                  species=[(s.q, s.m, s.w) for s in w.species], capacity=cap, obj=w.obj,
+                  center=w.center, radius=w.radius, z_flat=w.z_flat, rim_radius=w.rim_radius,
+                  depth=w.depth, repr=repr, deposit=deposit, sort_interval=sort_interval,
+                  stream=stream)
