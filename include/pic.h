@@ -200,6 +200,17 @@ pic_status pic_get_particles(pic_ctx *ctx, int32_t species, int64_t cap, int64_t
                              double *x, double *y, double *z, double *vx, double *vy,
                              double *vz, int64_t *ids);
 
+/* Looks up particles of one species by id (ids must have been loaded with the
+ * species). ids_sorted: host array of n distinct ids in ascending order. For
+ * each k, found[k] = 1 and the particle's physical position and half-step
+ * velocity are written to x[k] .. vz[k] if a particle with that id is alive,
+ * else found[k] = 0 (outputs untouched). A device-side search, so sampled
+ * particles of a very large run can be read without copying the whole state.
+ * Synchronises. */
+pic_status pic_get_particles_by_id(pic_ctx *ctx, int32_t species, int64_t n,
+                                   const int64_t *ids_sorted, int32_t *found, double *x,
+                                   double *y, double *z, double *vx, double *vy, double *vz);
+
 /* Kernel timing for measurement: when enabled, the library records HIP events
  * around each launch of its kernels on the context's stream. */
 typedef struct {

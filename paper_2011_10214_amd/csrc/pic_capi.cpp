@@ -874,6 +874,58 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
   return PIC_OK;
 }
 
+pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
+                                   const int64_t *ids_sorted, int32_t *found, double *x,
+                                   double *y, double *z, double *vx, double *vy, double *vz) {
+  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
+  if (n < 0) return fail(c, PIC_E_INVALID, "n must be >= 0");
+  if (n > 0 && (!ids_sorted || !found || !x || !y || !z || !vx || !vy || !vz))
+    return fail(c, PIC_E_INVALID, "arrays must not be NULL");
+  for (int64_t k = 1; k < n; ++k)
+    if (!(ids_sorted[k - 1] < ids_sorted[k]))
+      return fail(c, PIC_E_INVALID, "ids must be distinct and ascending");
+  pic_ctx::Species &S = c->sp[species];
+  if (!S.ids) return fail(c, PIC_E_STATE, "no ids were loaded for this species");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  if (n == 0) return PIC_OK;
+  int64_t ext[PIC_MAX_SPECIES] = {0, 0, 0, 0};
+  if ((st = buffer_extents(c, ext)) != PIC_OK) return st;
+  void *d_ids = nullptr, *d_found = nullptr, *d_out = nullptr;
+  auto cleanup = [&]() {
+    if (d_ids) (void)hipFree(d_ids);
+    if (d_found) (void)hipFree(d_found);
+    if (d_out) (void)hipFree(d_out);
+  };
+  if (hipMalloc(&d_ids, n * 8) != hipSuccess || hipMalloc(&d_found, n * 4) != hipSuccess ||
+      hipMalloc(&d_out, n * 6 * 8) != hipSuccess) {
+    cleanup();
+    return fail(c, PIC_E_NOMEM, "no device memory for the id search");
+  }
+  hipError_t e = hipMemcpy(d_ids, ids_sorted, n * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(d_found, 0, n * 4);
+  if (e == hipSuccess)
+    e = launch_find_ids(c->cfg.repr, S.buf[c->cur], ext[species], (const int64_t *)d_ids, n,
+                        (int32_t *)d_found, (double *)d_out, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  std::vector<double> out(n * 6);
+  if (e == hipSuccess) e = hipMemcpy(found, d_found, n * 4, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(out.data(), d_out, n * 6 * 8, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) return hip_fail(c, e, "pic_get_particles_by_id");
+  const pic_config &cf = c->cfg;
+  double *X[3] = {x, y, z}, *V[3] = {vx, vy, vz};
+  for (int64_t k = 0; k < n; ++k) {
+    if (!found[k]) continue;
+    for (int d = 0; d < 3; ++d) {
+      X[d][k] = cf.origin[d] + out[d * n + k] * cf.h;
+      V[d][k] = out[(3 + d) * n + k] * cf.h;
+    }
+  }
+  return PIC_OK;
+}
+
 pic_status pic_profile_enable(pic_ctx *c, int32_t on) {
   if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
   PIC_HIP(c, hipStreamSynchronize(c->stream));

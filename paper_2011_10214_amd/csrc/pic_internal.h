@@ -98,6 +98,8 @@ hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
+hipError_t launch_find_ids(int repr, const PBuf &buf, int64_t n_buf, const int64_t *ids_sorted,
+                           int64_t n_ids, int32_t *found, double *out6, hipStream_t s);
 hipError_t launch_node_E_f32(int repr, const float *Ex, const float *Ey, const float *Ez,
                              void *E, int64_t nodes, int32_t *bad, hipStream_t s);
 

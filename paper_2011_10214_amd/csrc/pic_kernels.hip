@@ -475,7 +475,6 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
         idx[6] = g0 + sy + sx;
         idx[7] = g0 + sy + sx + 1;
       }
-      A* dstRho = local ? sRho : gRho;
       if constexpr (D == PIC_DEP_FIXED64) {
         long long C[8];
         long long sum = 0;
@@ -485,21 +484,24 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
           sum += C[n];
         }
         C[7] = chgF - sum;
+        if (local) {
 #pragma unroll
-        for (int n = 0; n < 8; ++n) atomicAdd(&dstRho[idx[n]], (unsigned long long)C[n]);
-      } else if constexpr (D == PIC_DEP_ATOMIC_FP32) {
+          for (int n = 0; n < 8; ++n) atomicAdd(&sRho[idx[n]], (unsigned long long)C[n]);
+        } else {
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
-          const float c = (float)(chg * W[n]);
-          if (local) atomicAdd(&dstRho[idx[n]], c);
-          else unsafeAtomicAdd(&dstRho[idx[n]], c);
+          for (int n = 0; n < 8; ++n) atomicAdd(&gRho[idx[n]], (unsigned long long)C[n]);
         }
       } else {
+        using C_t = typename AccOf<D>::type;
+        C_t C[8];
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
-          const double c = (double)(chg * W[n]);
-          if (local) atomicAdd(&dstRho[idx[n]], c);
-          else unsafeAtomicAdd(&dstRho[idx[n]], c);
+        for (int n = 0; n < 8; ++n) C[n] = (C_t)(chg * W[n]);
+        if (local) {
+#pragma unroll
+          for (int n = 0; n < 8; ++n) atomicAdd(&sRho[idx[n]], C[n]);
+        } else {
+#pragma unroll
+          for (int n = 0; n < 8; ++n) unsafeAtomicAdd(&gRho[idx[n]], C[n]);
         }
       }
     }
@@ -756,6 +758,41 @@ __global__ void load_f32_kernel(LoadParams L) {
   }
 }
 
+// Sampled read-back: for every alive particle whose id is in the sorted list,
+// write its state (cell units, FP64) to the list slot.
+template <int R>
+__global__ void find_ids_kernel(PBuf B, int64_t n_buf, const int64_t *ids, int64_t n_ids,
+                                int32_t *found, double *out) {
+  using T = typename RealOf<R>::T;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_buf;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    double g[3];
+    if constexpr (R == PIC_REPR_FP32_CELL) {
+      const int32_t cell = B.cell[p];
+      if (cell < 0) continue;
+      const int ci[3] = {cell & kMaxDim, (cell >> kCellBits) & kMaxDim, cell >> (2 * kCellBits)};
+      for (int d = 0; d < 3; ++d) g[d] = (double)ci[d] + (double)((const float *)B.pos[d])[p];
+    } else {
+      const T x = ((const T *)B.pos[0])[p];
+      if (x < T(0)) continue;
+      for (int d = 0; d < 3; ++d) g[d] = (double)((const T *)B.pos[d])[p];
+    }
+    const int64_t id = B.ids[p];
+    int64_t lo = 0, hi = n_ids;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ids[mid] < id) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= n_ids || ids[lo] != id) continue;
+    found[lo] = 1;
+    for (int d = 0; d < 3; ++d) {
+      out[d * n_ids + lo] = g[d];
+      out[(3 + d) * n_ids + lo] = (double)((const T *)B.vel[d])[p];
+    }
+  }
+}
+
 template <class V4>
 __global__ void node_E_kernel(const float *Ex, const float *Ey, const float *Ez, V4 *E,
                               int64_t nodes, int32_t *bad) {
@@ -874,6 +911,26 @@ hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s) {
       break;
     default:
       hipLaunchKernelGGL(load_f32_kernel<PIC_REPR_FP32_CELL>, grid, dim3(256), 0, s, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_find_ids(int repr, const PBuf &buf, int64_t n_buf, const int64_t *ids_sorted,
+                           int64_t n_ids, int32_t *found, double *out6, hipStream_t s) {
+  if (n_buf <= 0 || n_ids <= 0) return hipSuccess;
+  const dim3 grid(grid_for(n_buf, 256));
+  switch (repr) {
+    case PIC_REPR_FP64:
+      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP64>, grid, dim3(256), 0, s, buf, n_buf,
+                         ids_sorted, n_ids, found, out6);
+      break;
+    case PIC_REPR_FP32_ABS:
+      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_ABS>, grid, dim3(256), 0, s, buf, n_buf,
+                         ids_sorted, n_ids, found, out6);
+      break;
+    default:
+      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_CELL>, grid, dim3(256), 0, s, buf, n_buf,
+                         ids_sorted, n_ids, found, out6);
   }
   return hipGetLastError();
 }

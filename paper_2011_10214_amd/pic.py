@@ -70,6 +70,7 @@ SIGNATURES = {
     "pic_get_surface_charge": (_st, [_vp, _i64, _vp, _vp]),
     "pic_get_counters": (_st, [_vp, _vp, _vp, _vp]),
     "pic_get_particles": (_st, [_vp, _i32, _i64, _vp] + [_vp] * 7),
+    "pic_get_particles_by_id": (_st, [_vp, _i32, _i64, _vp, _vp] + [_vp] * 6),
     "pic_profile_enable": (_st, [_vp, _i32]),
     "pic_profile_read": (_st, [_vp, ctypes.POINTER(_Profile)]),
     "pic_last_error": (ctypes.c_char_p, [_vp]),
@@ -311,6 +312,23 @@ class Context:
             v = np.stack([c[:n] for c in cols[3:]], 1)
             return x, v, (ids[:n] if ids is not None else None)
         raise PicError(E_INVALID, "particle count changed during read-back")
+
+    def get_particles_by_id(self, species: int, ids):
+        """State of the particles with the given ids (any order). Returns
+        (found (n,) bool, x (n, 3), v (n, 3)) in the order of `ids`."""
+        ids = np.asarray(ids, dtype=np.int64)
+        order = np.argsort(ids, kind="stable")
+        srt = np.ascontiguousarray(ids[order])
+        n = len(srt)
+        found = np.zeros(n, np.int32)
+        cols = [np.full(n, np.nan) for _ in range(6)]
+        self._check(lib().pic_get_particles_by_id(self._h, species, n, _ptr(srt), _ptr(found),
+                                                  *[_ptr(c) for c in cols]))
+        inv = np.empty(n, np.int64)
+        inv[order] = np.arange(n)
+        x = np.stack(cols[:3], 1)[inv]
+        v = np.stack(cols[3:], 1)[inv]
+        return found[inv].astype(bool), x, v
 
     def profile_enable(self, on: bool = True):
         self._check(lib().pic_profile_enable(self._h, 1 if on else 0))
