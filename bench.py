@@ -78,6 +78,29 @@ def traffic_for(workload, repr_, deposit, launches_particles):
     return t.get("hbm_bytes_per_launch")
 
 
+def copy_ceiling(nbytes=4 << 30, reps=5):
+    """Measured HBM ceiling: a plain device-to-device copy of nbytes (read +
+    write), best of reps, in GB/s."""
+    import torch
+
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    best = 0.0
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        best = max(best, 2 * nbytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del x, y
+    torch.cuda.empty_cache()
+    return best
+
+
 def cpu_baseline(w, target_s):
     """The FP64 oracle, single-threaded, on a bounded sample of the workload."""
     import numpy as np
@@ -123,6 +146,8 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the plain copy kernel (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -139,9 +164,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_only:
+        print(json.dumps({"copy_ceiling_GBs": copy_ceiling(), "copy_bytes_each_way": 4 << 30}))
+        return
     torch.cuda.set_device(0)
     w = synth.WORKLOADS[args.workload]()
-    stream = torch.cuda.current_stream()
+    # a stream of torch's own (default priority) that the library enqueues on,
+    # so that the events below bracket exactly the library's work
+    stream = torch.cuda.Stream()
     cfg = pam.config_from_workload(w, repr=args.repr, deposit=args.deposit,
                                    sort_interval=args.sort_interval, stream=stream.cuda_stream)
     log(f"workload {w.name}: {w.nx}x{w.ny}x{w.nz} cells, {w.n_particles} particles, "
@@ -170,17 +200,21 @@ def main():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
     e0.record(stream)
     ctx.step(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
     ctx.synchronize()
     ms = e0.elapsed_time(e1)
     prof = ctx.profile_read()
     alive1, absorbed, escaped = ctx.get_counters()
-    log(f"timed {args.steps} steps: {ms:.2f} ms; step kernel {prof.step_ms / max(1, prof.step_launches):.3f} ms avg, "
+    log(f"timed {args.steps} steps: {ms:.2f} ms (host wall {wall_ms:.2f} ms); step kernel {prof.step_ms / max(1, prof.step_launches):.3f} ms avg, "
         f"sort {prof.sort_ms / max(1, prof.sort_launches):.3f} ms avg x{prof.sort_launches}")
     ctx.close()
+    copy_gbs = copy_ceiling()
+    log(f"copy ceiling {copy_gbs:.0f} GB/s")
 
     value = prof.particle_steps / (ms / 1e3)
     bpp = BYTES_PER_PARTICLE_STEP[args.repr]
@@ -209,6 +243,7 @@ def main():
             "sort_interval": args.sort_interval,
             "particles_alive_start": int(alive0.sum()),
             "particles_alive_end": int(alive1.sum()),
+            "timed_wall_ms": wall_ms,
         },
         "roofline": {
             "bound": "hbm",
@@ -221,6 +256,8 @@ def main():
             "bytes_per_particle_step": bpp,
             "step_kernel_ms_avg": prof.step_ms / max(1, prof.step_launches),
             "particles_per_launch": per_launch_particles,
+            "copy_ceiling_GBs": copy_gbs,
+            "frac_of_copy_ceiling": achieved / copy_gbs if copy_gbs else None,
         },
         "phases_ms_per_step": {
             "step_kernel": prof.step_ms / args.steps,

@@ -241,15 +241,38 @@ __device__ __forceinline__ int box_face_abs(const T g[3], int nx, int ny, int nz
 
 // ------------------------------------------------------------------ step kernel
 
+// rint(a) for 0 <= a < 2^52 as an unsigned 64-bit integer, split exactly into
+// 32-bit halves in the arithmetic type: hi = floor(r 2^-32), lo = r - hi 2^32
+// (both exact: r is an integer with at most 24 / 53 significant bits).
+template <class T>
+__device__ __forceinline__ unsigned long long fix_mag(T a) {
+  const T r = rintT(a);
+  const T hf = floorT(r * T(2.3283064365386963e-10));
+  const T lf = fmaT(hf, -two32<T>(), r);
+  const unsigned hi = (unsigned)hf, lo = (unsigned)lf;
+  return ((unsigned long long)hi << 32) | (unsigned long long)lo;
+}
+
+template <class T>
+struct Particle {
+  int32_t cell;  // packed cell (cell form)
+  T x[3];        // in-cell offsets (cell form) or positions in cell units
+  T u[3];
+};
+
 template <int R, int D, bool PUSH>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
   using T = typename RealOf<R>::T;
   using V4 = typename Vec4Of<T>::type;
   using A = typename AccOf<D>::type;
   constexpr bool kCell = R == PIC_REPR_FP32_CELL;
+  constexpr bool kFixed = D == PIC_DEP_FIXED64;
 
   __shared__ V4 sE[PUSH ? kRegNodes : 1];
-  __shared__ A sRho[kRegNodes];
+  // private rho of the staged region; the fixed-point mode keeps the charge
+  // magnitudes of positive and negative species apart (no sign handling per
+  // contribution) and subtracts them at the flush
+  __shared__ A sAcc[kFixed ? 2 : 1][kRegNodes];
   __shared__ int32_t sEsc[6 * PIC_MAX_SPECIES];
   __shared__ int32_t sAbs[PIC_MAX_SPECIES];
   __shared__ int32_t sAlive;
@@ -281,7 +304,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
         e = gE[gi + sx * gj + sy * gk];
       sE[n] = e;
     }
-    sRho[n] = A(0);
+    sAcc[0][n] = A(0);
+    if constexpr (kFixed) sAcc[1][n] = A(0);
   }
   if (threadIdx.x < 6 * PIC_MAX_SPECIES) sEsc[threadIdx.x] = 0;
   if (threadIdx.x < PIC_MAX_SPECIES) sAbs[threadIdx.x] = 0;
@@ -299,43 +323,51 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
     if (p0 == p1) continue;
     const T qmdt = (T)P.qmdt[s];
     const T chg = (T)P.chg[s];
-    const long long chgF = P.chg_fixed[s];
-    T *__restrict__ X0 = (T *)P.buf[s].pos[0];
-    T *__restrict__ X1 = (T *)P.buf[s].pos[1];
-    T *__restrict__ X2 = (T *)P.buf[s].pos[2];
-    T *__restrict__ U0 = (T *)P.buf[s].vel[0];
-    T *__restrict__ U1 = (T *)P.buf[s].vel[1];
-    T *__restrict__ U2 = (T *)P.buf[s].vel[2];
-    int32_t *__restrict__ CELL = P.buf[s].cell;
+    const bool neg = chg < T(0);
+    // |chg| 2^32 (exact scaling), and llrint(|chg| 2^32)
+    const T amag = absT(chg) * two32<T>();
+    const unsigned long long fmag =
+        (unsigned long long)(P.chg_fixed[s] < 0 ? -P.chg_fixed[s] : P.chg_fixed[s]);
+    A *__restrict__ sTile = sAcc[kFixed && neg ? 1 : 0];
+    // uniform bases at the bucket start; lanes index with a 32-bit offset
+    T *__restrict__ X0 = (T *)P.buf[s].pos[0] + p0;
+    T *__restrict__ X1 = (T *)P.buf[s].pos[1] + p0;
+    T *__restrict__ X2 = (T *)P.buf[s].pos[2] + p0;
+    T *__restrict__ U0 = (T *)P.buf[s].vel[0] + p0;
+    T *__restrict__ U1 = (T *)P.buf[s].vel[1] + p0;
+    T *__restrict__ U2 = (T *)P.buf[s].vel[2] + p0;
+    int32_t *__restrict__ CELL = kCell ? P.buf[s].cell + p0 : nullptr;
+    const unsigned np = (unsigned)(p1 - p0);
 
-    for (int p = p0 + (int)threadIdx.x; p < p1; p += kBlock) {
+    auto load = [&](unsigned p) {
+      Particle<T> q;
+      q.cell = kCell ? CELL[p] : 0;
+      q.x[0] = X0[p];
+      q.x[1] = X1[p];
+      q.x[2] = X2[p];
+      q.u[0] = U0[p];
+      q.u[1] = U1[p];
+      q.u[2] = U2[p];
+      return q;
+    };
+
+    auto process = [&](Particle<T> &q, unsigned p) {
       int ci[3];
-      T f[3];   // in-cell offsets
-      T gp[3];  // absolute positions (absolute forms)
-      T u[3];
+      T f[3];  // in-cell offsets
+      T *u = q.u;
       if constexpr (kCell) {
-        const int32_t cell = CELL[p];
-        f[0] = X0[p];
-        f[1] = X1[p];
-        f[2] = X2[p];
-        u[0] = U0[p];
-        u[1] = U1[p];
-        u[2] = U2[p];
-        if (cell < 0) continue;  // removed since the last re-bucketing
-        ci[0] = cell & kMaxDim;
-        ci[1] = (cell >> kCellBits) & kMaxDim;
-        ci[2] = cell >> (2 * kCellBits);
+        if (q.cell < 0) return;  // removed since the last re-bucketing
+        ci[0] = q.cell & kMaxDim;
+        ci[1] = (q.cell >> kCellBits) & kMaxDim;
+        ci[2] = q.cell >> (2 * kCellBits);
+        f[0] = q.x[0];
+        f[1] = q.x[1];
+        f[2] = q.x[2];
       } else {
-        gp[0] = X0[p];
-        gp[1] = X1[p];
-        gp[2] = X2[p];
-        u[0] = U0[p];
-        u[1] = U1[p];
-        u[2] = U2[p];
-        if (gp[0] < T(0)) continue;  // removed (marked with x = -1)
+        if (q.x[0] < T(0)) return;  // removed (marked with x = -1)
         for (int d = 0; d < 3; ++d) {
-          ci[d] = (int)floorT(gp[d]);
-          f[d] = gp[d] - (T)ci[d];
+          ci[d] = (int)floorT(q.x[d]);
+          f[d] = q.x[d] - (T)ci[d];
         }
       }
       ++alive_here;
@@ -390,6 +422,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
         U1[p] = u[1];
         U2[p] = u[2];
         bool bad = false;
+        T gp[3];
         if constexpr (kCell) {
           for (int d = 0; d < 3; ++d) {
             T op = fmaT(u[d], dt, f[d]);
@@ -405,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
           }
         } else {
           for (int d = 0; d < 3; ++d) {
-            gp[d] = fmaT(u[d], dt, gp[d]);
+            gp[d] = fmaT(u[d], dt, q.x[d]);
             bad |= !finiteT(gp[d]);
           }
         }
@@ -438,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
           X1[p] = gp[1];
           X2[p] = gp[2];
         }
-        if (removed) continue;
+        if (removed) return;
         if constexpr (!kCell) {
           for (int d = 0; d < 3; ++d) {
             ci[d] = (int)floorT(gp[d]);
@@ -454,68 +487,72 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
       const bool local = (unsigned)li < (unsigned)kReg && (unsigned)lj < (unsigned)kReg &&
                          (unsigned)lk < (unsigned)kReg;
       int idx[8];
-      if (local) {
-        const int l0 = li + kRegN * (lj + kRegN * lk);
-        idx[0] = l0;
-        idx[1] = l0 + 1;
-        idx[2] = l0 + kRegN;
-        idx[3] = l0 + kRegN + 1;
-        idx[4] = l0 + kRegN * kRegN;
-        idx[5] = l0 + kRegN * kRegN + 1;
-        idx[6] = l0 + kRegN * kRegN + kRegN;
-        idx[7] = l0 + kRegN * kRegN + kRegN + 1;
-      } else {
-        const int g0 = ci[0] + sx * ci[1] + sy * ci[2];
-        idx[0] = g0;
-        idx[1] = g0 + 1;
-        idx[2] = g0 + sx;
-        idx[3] = g0 + sx + 1;
-        idx[4] = g0 + sy;
-        idx[5] = g0 + sy + 1;
-        idx[6] = g0 + sy + sx;
-        idx[7] = g0 + sy + sx + 1;
+      {
+        const int b0 = local ? li + kRegN * (lj + kRegN * lk) : ci[0] + sx * ci[1] + sy * ci[2];
+        const int ox = local ? kRegN : sx, oz = local ? kRegN * kRegN : sy;
+        idx[0] = b0;
+        idx[1] = b0 + 1;
+        idx[2] = b0 + ox;
+        idx[3] = b0 + ox + 1;
+        idx[4] = b0 + oz;
+        idx[5] = b0 + oz + 1;
+        idx[6] = b0 + oz + ox;
+        idx[7] = b0 + oz + ox + 1;
       }
-      if constexpr (D == PIC_DEP_FIXED64) {
-        long long C[8];
-        long long sum = 0;
+      if constexpr (kFixed) {
+        // magnitudes rint(|chg| W 2^32) (sign symmetric), the remainder on
+        // corner 7; negative species go to the second tile
+        unsigned long long C[8];
+        unsigned long long sum = 0;
 #pragma unroll
         for (int n = 0; n < 7; ++n) {
-          C[n] = fixq<T>(chg * W[n]);
+          C[n] = fix_mag<T>(amag * W[n]);
           sum += C[n];
         }
-        C[7] = chgF - sum;
+        C[7] = fmag - sum;
         if (local) {
 #pragma unroll
-          for (int n = 0; n < 8; ++n) atomicAdd(&sRho[idx[n]], (unsigned long long)C[n]);
+          for (int n = 0; n < 8; ++n) atomicAdd(&sTile[idx[n]], C[n]);
         } else {
 #pragma unroll
-          for (int n = 0; n < 8; ++n) atomicAdd(&gRho[idx[n]], (unsigned long long)C[n]);
+          for (int n = 0; n < 8; ++n) atomicAdd(&gRho[idx[n]], neg ? 0ull - C[n] : C[n]);
         }
       } else {
-        using C_t = typename AccOf<D>::type;
-        C_t C[8];
+        A C[8];
 #pragma unroll
-        for (int n = 0; n < 8; ++n) C[n] = (C_t)(chg * W[n]);
+        for (int n = 0; n < 8; ++n) C[n] = (A)(chg * W[n]);
         if (local) {
 #pragma unroll
-          for (int n = 0; n < 8; ++n) atomicAdd(&sRho[idx[n]], C[n]);
+          for (int n = 0; n < 8; ++n) atomicAdd(&sTile[idx[n]], C[n]);
         } else {
 #pragma unroll
           for (int n = 0; n < 8; ++n) unsafeAtomicAdd(&gRho[idx[n]], C[n]);
         }
       }
+    };
+
+    // two particles per lane per iteration: both loads are issued before
+    // either is processed
+    for (unsigned p = threadIdx.x; p < np; p += 2 * kBlock) {
+      const unsigned p2 = p + kBlock;
+      const bool two = p2 < np;
+      Particle<T> a = load(p), b;
+      if (two) b = load(p2);
+      process(a, p);
+      if (two) process(b, p2);
     }
   }
 
   atomicAdd(&sAlive, alive_here);
   __syncthreads();
   for (int n = threadIdx.x; n < kRegNodes; n += kBlock) {
-    const A v = sRho[n];
+    A v = sAcc[0][n];
+    if constexpr (kFixed) v -= sAcc[1][n];
     if (v == A(0)) continue;
     const int a = n % kRegN, b = (n / kRegN) % kRegN, c = n / (kRegN * kRegN);
     const int gi = rx0 + a, gj = ry0 + b, gk = rz0 + c;
     if (gi < 0 || gi > nx || gj < 0 || gj > ny || gk < 0 || gk > nz) continue;
-    if constexpr (D == PIC_DEP_FIXED64) atomicAdd(&gRho[gi + sx * gj + sy * gk], v);
+    if constexpr (kFixed) atomicAdd(&gRho[gi + sx * gj + sy * gk], v);
     else unsafeAtomicAdd(&gRho[gi + sx * gj + sy * gk], v);
   }
   if (threadIdx.x < 6 * PIC_MAX_SPECIES) {
