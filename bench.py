@@ -4,7 +4,8 @@
 
 Default workload: the lunar-crater shape, one subdomain on one GPU:
 160 x 160 x 80 cells (2.05M), 2 x 260,000,000 particles, FP32 cell-relative
-state with int64 fixed-point deposition, re-bucketing every 4 steps.
+state with int64 fixed-point deposition; particles are re-bucketed by tile
+inside every step (full re-planning of the tile regions only on demand).
 
 A step is one pass of the whole hot path over all particles; particle-steps
 count the particles alive at the start of each step. Inputs are generated on
@@ -143,7 +144,8 @@ def main():
     ap.add_argument("--workload", default="crater_160")
     ap.add_argument("--repr", default="fp32_cell", choices=sorted(BYTES_PER_PARTICLE_STEP))
     ap.add_argument("--deposit", default="fixed64", choices=["fixed64", "fp32", "fp64"])
-    ap.add_argument("--sort-interval", type=int, default=4)
+    ap.add_argument("--sort-interval", type=int, default=0,
+                    help="re-plan the tile regions every K steps (0: on demand)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",

@@ -70,7 +70,8 @@ typedef struct pic_ctx pic_ctx;
 typedef enum {
   PIC_OK = 0,
   PIC_E_INVALID = -1, /* a bad argument; nothing changed */
-  PIC_E_NOMEM = -2,   /* device memory could not be allocated; nothing changed */
+  PIC_E_NOMEM = -2,   /* device memory could not be allocated (nothing changed), or
+                         particles did not fit the reserved regions (reported at sync) */
   PIC_E_DEVICE = -3,  /* no usable GPU, or a HIP runtime error */
   PIC_E_STATE = -4,   /* call out of order (e.g. pic_step before pic_set_node_E) */
   PIC_E_RANGE = -5    /* a particle position became non-finite or moved > 2^20 cells */
@@ -117,10 +118,14 @@ typedef struct {
   pic_object object;
   int32_t repr;          /* pic_repr */
   int32_t deposit;       /* pic_deposit */
-  int32_t sort_interval; /* K >= 1: particles are re-bucketed by tile every K steps;
-                            0 selects the default (4) */
+  int32_t sort_interval; /* particles are kept grouped by tile of 4^3 cells; every
+                            step moves each particle to its new tile's region.
+                            K >= 1 also re-plans the tile regions every K steps;
+                            0 (default) only after a load or when a tile's spare
+                            room runs out. Results do not depend on it. */
   int64_t capacity[PIC_MAX_SPECIES]; /* max particles per species (device memory is
-                                        reserved for this many, double-buffered) */
+                                        reserved for this many plus per-tile spare
+                                        room and an overflow list, double-buffered) */
   void *stream;          /* hipStream_t to enqueue on, or NULL for a library stream */
 } pic_config;
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -17,7 +18,7 @@ using namespace pic;
 namespace {
 
 constexpr double kTwo32 = 4294967296.0;
-constexpr int kDefaultSort = 4;
+constexpr int kDefaultSort = 0;  // re-bucket with fresh capacities only on demand
 constexpr int64_t kMaxCapacity = 0x7fffffffLL - 1024;
 
 thread_local std::string g_create_error = "no error";
@@ -29,13 +30,13 @@ int64_t elem_bytes(int repr) { return repr == PIC_REPR_FP64 ? 8 : 4; }
 int64_t rho_elem(int dep) { return dep == PIC_DEP_ATOMIC_FP32 ? 4 : 8; }
 int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
 
-struct Layout {
+struct Dims {
   int ns, nx, ny, nz, ntx, nty, ntz, ntiles;
   int64_t nodes, nbins;
 };
 
-Layout layout_of(const pic_config &c) {
-  Layout L;
+Dims dims_of(const pic_config &c) {
+  Dims L;
   L.ns = c.n_species;
   L.nx = c.nx;
   L.ny = c.ny;
@@ -50,20 +51,27 @@ Layout layout_of(const pic_config &c) {
   return L;
 }
 
+// Slots of one particle buffer of a species: the tile regions (with spare
+// room) followed by the overflow list.
+int64_t buffer_slots(int64_t cap, int64_t ntiles) {
+  return region_slots(cap, ntiles) + overflow_slots(cap);
+}
+
 // Device bytes of one species buffer (all arrays, 256-B aligned each).
-int64_t species_buffer_bytes(int repr, int64_t cap) {
+int64_t species_buffer_bytes(int repr, int64_t slots) {
   const int64_t e = elem_bytes(repr);
-  int64_t b = 6 * align256(cap * e);
-  if (repr == PIC_REPR_FP32_CELL) b += align256(cap * 4);
+  int64_t b = 6 * align256(slots * e);
+  if (repr == PIC_REPR_FP32_CELL) b += align256(slots * 4);
   return b;
 }
 
-int64_t mesh_bytes(const pic_config &c, const Layout &L) {
+int64_t mesh_bytes(const pic_config &c, const Dims &L) {
   const int64_t e4 = c.repr == PIC_REPR_FP64 ? 32 : 16;
   int64_t b = 2 * align256(L.nodes * e4);                      // node E + staging
   b += align256(L.nodes * rho_elem(c.deposit));                 // rho
   b += align256(L.nbins * L.ns * 8) + align256(6 * L.ns * 8);  // tallies
-  b += 2 * align256((int64_t)L.ns * (L.ntiles + 1) * 8);        // bucket offsets
+  b += 2 * align256((int64_t)L.ns * L.ntiles * 16);              // two tile layouts
+  b += 6 * align256((int64_t)L.ns * L.ntiles * 4);              // stayed / arrived counts
   b += 2 * align256((int64_t)L.ns * L.ntiles * 4);              // counts, cursors
   b += align256((int64_t)L.ns * L.ntiles * kNeighbours * 4);    // per-tile histograms
   b += 4096;                                                    // stats, flags
@@ -140,9 +148,10 @@ Geom geometry_of(const pic_config &c) {
 }
 
 int64_t footprint(const pic_config &c) {
-  const Layout L = layout_of(c);
+  const Dims L = dims_of(c);
   int64_t b = mesh_bytes(c, L);
-  for (int s = 0; s < c.n_species; ++s) b += 2 * species_buffer_bytes(c.repr, c.capacity[s]);
+  for (int s = 0; s < c.n_species; ++s)
+    b += 2 * species_buffer_bytes(c.repr, buffer_slots(c.capacity[s], L.ntiles));
   return b;
 }
 
@@ -155,7 +164,7 @@ struct Ev {
 
 struct pic_ctx {
   pic_config cfg;
-  Layout L;
+  Dims L;
   Geom geom;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -164,19 +173,27 @@ struct pic_ctx {
   void *E = nullptr, *E_spare = nullptr, *rho = nullptr;
   int64_t *tally = nullptr, *escaped = nullptr, *stats = nullptr;
   int32_t *err = nullptr, *bad = nullptr;
-  int64_t *off[2] = {nullptr, nullptr};
+  pic::Layout lay[2] = {};  // tile layouts (the one in use: lay[li])
+  int32_t *nst[2] = {nullptr, nullptr}, *arr[2] = {nullptr, nullptr}, *ovf[2] = {nullptr, nullptr};
+  int32_t *flags = nullptr;          // device: re-bucketing wanted
+  volatile int32_t *flag_host = nullptr;  // pinned copy, refreshed after each step
   int32_t *count = nullptr, *cursor = nullptr, *hist = nullptr;
   struct Species {
     int64_t cap = 0;
-    int64_t n_buf = 0;  // entries in the current buffer (valid while unsorted)
+    int64_t slots = 0;     // per buffer
+    int64_t ovf_base = 0;  // start of the overflow list (= tile region slots)
+    int32_t ovf_cap = 0;
+    int64_t n_buf = 0;  // entries of a freshly loaded (unsorted) species
+    bool unsorted = true;
     int64_t loaded = 0;
     bool ids = false;
     void *mem[2] = {nullptr, nullptr};
     int64_t *ids_mem[2] = {nullptr, nullptr};
     PBuf buf[2];
   } sp[PIC_MAX_SPECIES];
-  int cur = 0, cur_off = 0;
-  bool sorted = false;
+  int cur = 0;  // buffer holding the current state
+  int li = 0;   // layout in use
+  bool sorted = false;  // every species is binned
   bool E_set = false;
   int since_sort = 0;
   int K = kDefaultSort;
@@ -230,6 +247,8 @@ void free_all(pic_ctx *c) {
     (void)hipEventDestroy(e.b);
   }
   c->events.clear();
+  if (c->flag_host) (void)hipHostFree((void *)c->flag_host);
+  c->flag_host = nullptr;
 }
 
 hipError_t dmalloc(pic_ctx *c, void **p, int64_t bytes) {
@@ -301,16 +320,45 @@ pic_status sync_and_check(pic_ctx *c) {
   if (err) {
     const int32_t zero = 0;
     PIC_HIP(c, hipMemcpy(c->err, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    if (err & kErrCapacity)
+      return fail(c, PIC_E_NOMEM, "particles were lost: the tile regions and overflow list are full");
     return fail(c, PIC_E_RANGE, "a particle position became non-finite or moved > 2^20 cells");
   }
   return PIC_OK;
 }
 
+Bins bins_of(pic_ctx *c) {
+  Bins B{};
+  B.lay = c->lay[c->li];
+  for (int b = 0; b < 2; ++b) {
+    B.nst[b] = c->nst[b];
+    B.arr[b] = c->arr[b];
+    B.ovf[b] = c->ovf[b];
+  }
+  for (int s = 0; s < c->L.ns; ++s) {
+    B.ovf_base[s] = c->sp[s].ovf_base;
+    B.ovf_cap[s] = c->sp[s].ovf_cap;
+  }
+  B.flags = c->flags;
+  return B;
+}
+
+int32_t ids_mask(pic_ctx *c) {
+  int32_t m = 0;
+  for (int s = 0; s < c->L.ns; ++s)
+    if (c->sp[s].ids) m |= 1 << s;
+  return m;
+}
+
 StepParams step_params(pic_ctx *c) {
   StepParams P{};
-  const Layout &L = c->L;
-  for (int s = 0; s < L.ns; ++s) P.buf[s] = c->sp[s].buf[c->cur];
-  P.off = c->off[c->cur_off];
+  const Dims &L = c->L;
+  for (int s = 0; s < L.ns; ++s) {
+    P.in[s] = c->sp[s].buf[c->cur];
+    P.out[s] = c->sp[s].buf[1 - c->cur];
+  }
+  P.bins = bins_of(c);
+  P.cur = c->cur;
   P.ns = L.ns;
   P.nx = L.nx;
   P.ny = L.ny;
@@ -319,6 +367,7 @@ StepParams step_params(pic_ctx *c) {
   P.nty = L.nty;
   P.ntz = L.ntz;
   P.ntiles = L.ntiles;
+  P.has_ids = ids_mask(c);
   const bool f64 = c->cfg.repr == PIC_REPR_FP64;
   for (int s = 0; s < L.ns; ++s) {
     const pic_species &sp = c->cfg.species[s];
@@ -338,19 +387,27 @@ StepParams step_params(pic_ctx *c) {
   return P;
 }
 
+// Re-bucketing with fresh tile capacities: from the current buffer (tile
+// regions + overflow list, or the flat range of a freshly loaded species) into
+// the other buffer under a new layout.
 pic_status do_sort(pic_ctx *c) {
-  const Layout &L = c->L;
+  const Dims &L = c->L;
   SortParams S{};
   int64_t max_src = 0;
   for (int s = 0; s < L.ns; ++s) {
-    S.src[s] = c->sp[s].buf[c->cur];
-    S.dst[s] = c->sp[s].buf[1 - c->cur];
-    S.n_src[s] = c->sp[s].n_buf;
-    if (c->sp[s].n_buf > max_src) max_src = c->sp[s].n_buf;
-    if (c->sp[s].ids) S.has_ids |= 1 << s;
+    const pic_ctx::Species &sp = c->sp[s];
+    S.src[s] = sp.buf[c->cur];
+    S.dst[s] = sp.buf[1 - c->cur];
+    if (sp.unsorted) {
+      S.unsorted |= 1 << s;
+      S.n_src[s] = sp.n_buf;
+      if (sp.n_buf > max_src) max_src = sp.n_buf;
+    }
+    S.region_cap[s] = sp.ovf_base;
   }
-  S.off_src = c->sorted ? c->off[c->cur_off] : nullptr;
-  S.off_dst = c->off[1 - c->cur_off];
+  S.bins = bins_of(c);
+  S.dst_lay = c->lay[1 - c->li];
+  S.cur = c->cur;
   S.count = c->count;
   S.cursor = c->cursor;
   S.hist = c->hist;
@@ -362,15 +419,19 @@ pic_status do_sort(pic_ctx *c) {
   S.nty = L.nty;
   S.ntz = L.ntz;
   S.ntiles = L.ntiles;
+  S.has_ids = ids_mask(c);
+  S.err = c->err;
   const int pe = prof_begin(c, 1);
   PIC_HIP(c, launch_sort_count(c->cfg.repr, S, max_src, c->stream));
   PIC_HIP(c, launch_sort_scan(S, c->stream));
   PIC_HIP(c, launch_sort_scatter(c->cfg.repr, S, max_src, c->stream));
   prof_end(c, pe);
   c->cur = 1 - c->cur;
-  c->cur_off = 1 - c->cur_off;
+  c->li = 1 - c->li;
+  for (int s = 0; s < L.ns; ++s) c->sp[s].unsorted = false;
   c->sorted = true;
   c->since_sort = 0;
+  if (c->flag_host) *c->flag_host = 0;
   return PIC_OK;
 }
 
@@ -381,27 +442,9 @@ pic_status clear_rho(pic_ctx *c) {
   return PIC_OK;
 }
 
-// Number of entries in the current buffer of each species (reads the bucket
-// end offsets when sorted).
-pic_status buffer_extents(pic_ctx *c, int64_t *n) {
-  const Layout &L = c->L;
-  if (!c->sorted) {
-    for (int s = 0; s < L.ns; ++s) n[s] = c->sp[s].n_buf;
-    return PIC_OK;
-  }
-  PIC_HIP(c, hipStreamSynchronize(c->stream));
-  for (int s = 0; s < L.ns; ++s) {
-    int64_t v = 0;
-    PIC_HIP(c, hipMemcpy(&v, c->off[c->cur_off] + (int64_t)s * (L.ntiles + 1) + L.ntiles,
-                         sizeof(v), hipMemcpyDeviceToHost));
-    n[s] = v;
-  }
-  return PIC_OK;
-}
-
 // Resets the collected counts and escape counters of one species.
 pic_status reset_species_counters(pic_ctx *c, int s) {
-  const Layout &L = c->L;
+  const Dims &L = c->L;
   std::vector<int64_t> t(L.nbins * L.ns), e(6 * L.ns);
   if (L.nbins) PIC_HIP(c, hipMemcpy(t.data(), c->tally, t.size() * 8, hipMemcpyDeviceToHost));
   PIC_HIP(c, hipMemcpy(e.data(), c->escaped, e.size() * 8, hipMemcpyDeviceToHost));
@@ -412,30 +455,56 @@ pic_status reset_species_counters(pic_ctx *c, int s) {
   return PIC_OK;
 }
 
-// Makes the spare buffer of species s (just filled) its current buffer; the
-// other species keep theirs. Every species then goes through an unsorted
-// re-bucketing at the next step.
+// Makes the spare buffer of species s (just filled with n particles, unsorted)
+// its current buffer; the other species keep theirs. The next step re-buckets.
 pic_status commit_species(pic_ctx *c, int s, int64_t n, bool ids) {
-  int64_t ext[PIC_MAX_SPECIES] = {0, 0, 0, 0};
-  pic_status st = buffer_extents(c, ext);
-  if (st != PIC_OK) return st;
   pic_ctx::Species &S = c->sp[s];
   std::swap(S.mem[0], S.mem[1]);
   std::swap(S.ids_mem[0], S.ids_mem[1]);
   std::swap(S.buf[0], S.buf[1]);
-  for (int k = 0; k < c->L.ns; ++k) c->sp[k].n_buf = ext[k];
   S.n_buf = n;
+  S.unsorted = true;
   S.loaded = n;
   S.ids = ids;
   c->sorted = false;
   return reset_species_counters(c, s);
 }
 
+// Ranges [offset, offset + count) of the current buffer that hold species s
+// (tile regions and the overflow list). Re-buckets first if needed (the
+// re-bucketing does not change any result). Synchronises.
+pic_status species_ranges(pic_ctx *c, int s, std::vector<std::pair<int64_t, int64_t>> &out) {
+  pic_status st;
+  if (!c->sorted && (st = do_sort(c)) != PIC_OK) return st;
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  const int nt = c->L.ntiles;
+  std::vector<int64_t> base(nt);
+  std::vector<int32_t> cap(nt), sz(nt), nst(nt), arr(nt);
+  const int64_t o = (int64_t)s * nt;
+  const pic::Layout &lay = c->lay[c->li];
+  PIC_HIP(c, hipMemcpy(base.data(), lay.base + o, nt * 8, hipMemcpyDeviceToHost));
+  PIC_HIP(c, hipMemcpy(cap.data(), lay.cap + o, nt * 4, hipMemcpyDeviceToHost));
+  PIC_HIP(c, hipMemcpy(sz.data(), lay.sz + o, nt * 4, hipMemcpyDeviceToHost));
+  PIC_HIP(c, hipMemcpy(nst.data(), c->nst[c->cur] + o, nt * 4, hipMemcpyDeviceToHost));
+  PIC_HIP(c, hipMemcpy(arr.data(), c->arr[c->cur] + o, nt * 4, hipMemcpyDeviceToHost));
+  int32_t novf = 0;
+  PIC_HIP(c, hipMemcpy(&novf, c->ovf[c->cur] + s, 4, hipMemcpyDeviceToHost));
+  out.clear();
+  for (int t = 0; t < nt; ++t) {
+    const int64_t n1 = std::min(nst[t], sz[t]), na = std::min(arr[t], cap[t] - sz[t]);
+    if (n1 > 0) out.emplace_back(base[t], n1);
+    if (na > 0) out.emplace_back(base[t] + cap[t] - na, na);
+  }
+  const int64_t no = std::min(novf, c->sp[s].ovf_cap);
+  if (no > 0) out.emplace_back(c->sp[s].ovf_base, no);
+  return PIC_OK;
+}
+
 pic_status ensure_ids(pic_ctx *c, int s) {
   pic_ctx::Species &S = c->sp[s];
   if (S.ids_mem[0]) return PIC_OK;
   void *a = nullptr, *b = nullptr;
-  const int64_t bytes = align256(S.cap * 8);
+  const int64_t bytes = align256(S.slots * 8);
   if (dmalloc(c, &a, bytes) != hipSuccess) return fail(c, PIC_E_NOMEM, "no device memory for ids");
   if (dmalloc(c, &b, bytes) != hipSuccess) return fail(c, PIC_E_NOMEM, "no device memory for ids");
   S.ids_mem[0] = (int64_t *)a;
@@ -481,7 +550,7 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
     return fail(nullptr, PIC_E_DEVICE, "no HIP device available");
   pic_ctx *c = new pic_ctx();
   c->cfg = *cfg;
-  c->L = layout_of(*cfg);
+  c->L = dims_of(*cfg);
   c->geom = geometry_of(*cfg);
   c->K = cfg->sort_interval > 0 ? cfg->sort_interval : kDefaultSort;
   if (hipGetDevice(&c->device) != hipSuccess) {
@@ -507,7 +576,7 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
       return bail(PIC_E_DEVICE, "hipStreamCreate failed");
     c->own_stream = true;
   }
-  const Layout &L = c->L;
+  const Dims &L = c->L;
   const int64_t e4 = cfg->repr == PIC_REPR_FP64 ? 32 : 16;
   void *p = nullptr;
   struct Req {
@@ -522,8 +591,19 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
       {(void **)&c->stats, 64},
       {(void **)&c->err, 64},
       {(void **)&c->bad, 64},
-      {(void **)&c->off[0], (int64_t)L.ns * (L.ntiles + 1) * 8},
-      {(void **)&c->off[1], (int64_t)L.ns * (L.ntiles + 1) * 8},
+      {(void **)&c->lay[0].base, (int64_t)L.ns * L.ntiles * 8},
+      {(void **)&c->lay[1].base, (int64_t)L.ns * L.ntiles * 8},
+      {(void **)&c->lay[0].cap, (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->lay[1].cap, (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->lay[0].sz, (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->lay[1].sz, (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->nst[0], (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->nst[1], (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->arr[0], (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->arr[1], (int64_t)L.ns * L.ntiles * 4},
+      {(void **)&c->ovf[0], 64},
+      {(void **)&c->ovf[1], 64},
+      {(void **)&c->flags, 64},
       {(void **)&c->count, (int64_t)L.ns * L.ntiles * 4},
       {(void **)&c->cursor, (int64_t)L.ns * L.ntiles * 4},
       {(void **)&c->hist, (int64_t)L.ns * L.ntiles * kNeighbours * 4},
@@ -534,13 +614,21 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
     if (hipMemset(p, 0, (size_t)(r.bytes > 0 ? r.bytes : 256)) != hipSuccess)
       return bail(PIC_E_DEVICE, "hipMemset failed");
   }
+  void *fh = nullptr;
+  if (hipHostMalloc(&fh, 64, hipHostMallocDefault) != hipSuccess)
+    return bail(PIC_E_NOMEM, "hipHostMalloc failed");
+  c->flag_host = (volatile int32_t *)fh;
+  *c->flag_host = 0;
   for (int s = 0; s < L.ns; ++s) {
     pic_ctx::Species &S = c->sp[s];
     S.cap = cfg->capacity[s];
+    S.slots = buffer_slots(S.cap, L.ntiles);
+    S.ovf_base = region_slots(S.cap, L.ntiles);
+    S.ovf_cap = overflow_slots(S.cap);
     for (int b = 0; b < 2; ++b) {
-      if (dmalloc(c, &S.mem[b], species_buffer_bytes(cfg->repr, S.cap)) != hipSuccess)
+      if (dmalloc(c, &S.mem[b], species_buffer_bytes(cfg->repr, S.slots)) != hipSuccess)
         return bail(PIC_E_NOMEM, "hipMalloc of particle buffers failed");
-      carve(S.buf[b], S.mem[b], cfg->repr, S.cap);
+      carve(S.buf[b], S.mem[b], cfg->repr, S.slots);
     }
   }
   if (hipDeviceSynchronize() != hipSuccess) return bail(PIC_E_DEVICE, "device error at create");
@@ -716,12 +804,21 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
     return PIC_OK;
   }
   for (int k = 0; k < nsteps; ++k) {
-    if ((!c->sorted || c->since_sort >= c->K) && (st = do_sort(c)) != PIC_OK) return st;
+    // particles are re-bucketed by the step itself; a re-bucketing with fresh
+    // tile capacities runs after a load, every K steps if K > 0, and when a
+    // tile ran out of spare room (seen through the pinned flag, which may lag
+    // by a step: the overflow list keeps every particle in the meantime)
+    const bool want = !c->sorted || (c->K > 0 && c->since_sort >= c->K) ||
+                      (c->flag_host && *c->flag_host != 0);
+    if (want && (st = do_sort(c)) != PIC_OK) return st;
     if ((st = clear_rho(c)) != PIC_OK) return st;
     StepParams P = step_params(c);
     const int pe = prof_begin(c, 0);
     PIC_HIP(c, launch_step(c->cfg.repr, c->cfg.deposit, true, P, c->stream));
     prof_end(c, pe);
+    PIC_HIP(c, hipMemcpyAsync((void *)c->flag_host, c->flags, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, c->stream));
+    c->cur = 1 - c->cur;
     c->since_sort++;
   }
   return PIC_OK;
@@ -785,7 +882,7 @@ pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64
   if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
-  const Layout &L = c->L;
+  const Dims &L = c->L;
   std::vector<int64_t> t(L.nbins * L.ns), e(6 * L.ns);
   if (L.nbins) PIC_HIP(c, hipMemcpy(t.data(), c->tally, t.size() * 8, hipMemcpyDeviceToHost));
   PIC_HIP(c, hipMemcpy(e.data(), c->escaped, e.size() * 8, hipMemcpyDeviceToHost));
@@ -810,66 +907,67 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
   if (ids && !S.ids) return fail(c, PIC_E_STATE, "no ids were loaded for this species");
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
-  int64_t ext[PIC_MAX_SPECIES] = {0, 0, 0, 0};
-  if ((st = buffer_extents(c, ext)) != PIC_OK) return st;
-  const int64_t n = ext[species];
+  std::vector<std::pair<int64_t, int64_t>> rg;
+  if ((st = species_ranges(c, species, rg)) != PIC_OK) return st;
+  int64_t total = 0;
+  for (auto &r : rg) total += r.second;
+  *n_out = total;
+  if (total > cap) return fail(c, PIC_E_INVALID, "cap is smaller than the alive count");
+  if (total > 0 && (!x || !y || !z || !vx || !vy || !vz))
+    return fail(c, PIC_E_INVALID, "output arrays must not be NULL");
   const int repr = c->cfg.repr;
   const int64_t e = elem_bytes(repr);
   const PBuf &B = S.buf[c->cur];
-  std::vector<char> pos(3 * n * e + 1), vel(3 * n * e + 1);
-  std::vector<int32_t> cell(repr == PIC_REPR_FP32_CELL ? n : 0);
-  std::vector<int64_t> id(S.ids ? n : 0);
-  for (int d = 0; d < 3 && n > 0; ++d) {
-    PIC_HIP(c, hipMemcpy(pos.data() + d * n * e, B.pos[d], n * e, hipMemcpyDeviceToHost));
-    PIC_HIP(c, hipMemcpy(vel.data() + d * n * e, B.vel[d], n * e, hipMemcpyDeviceToHost));
-  }
-  if (repr == PIC_REPR_FP32_CELL && n > 0)
-    PIC_HIP(c, hipMemcpy(cell.data(), B.cell, n * 4, hipMemcpyDeviceToHost));
-  if (S.ids && n > 0) PIC_HIP(c, hipMemcpy(id.data(), B.ids, n * 8, hipMemcpyDeviceToHost));
   const pic_config &cf = c->cfg;
-  int64_t alive = 0;
-  for (int64_t p = 0; p < n; ++p) {
-    const bool dead = repr == PIC_REPR_FP32_CELL
-                          ? cell[p] < 0
-                          : (repr == PIC_REPR_FP64 ? ((double *)pos.data())[p] < 0
-                                                   : ((float *)pos.data())[p] < 0);
-    if (!dead) ++alive;
-  }
-  *n_out = alive;
-  if (alive > cap) return fail(c, PIC_E_INVALID, "cap is smaller than the alive count");
-  if (alive > 0 && (!x || !y || !z || !vx || !vy || !vz))
-    return fail(c, PIC_E_INVALID, "output arrays must not be NULL");
   double *X[3] = {x, y, z}, *V[3] = {vx, vy, vz};
+  std::vector<char> pos, vel;
+  std::vector<int32_t> cell;
+  std::vector<int64_t> id;
   int64_t k = 0;
-  for (int64_t p = 0; p < n; ++p) {
-    double g[3], u[3];
-    if (repr == PIC_REPR_FP32_CELL) {
-      if (cell[p] < 0) continue;
-      const int ci[3] = {cell[p] & kMaxDim, (cell[p] >> kCellBits) & kMaxDim,
-                         cell[p] >> (2 * kCellBits)};
-      for (int d = 0; d < 3; ++d) {
-        g[d] = (double)ci[d] + (double)((float *)pos.data())[d * n + p];
-        u[d] = (double)((float *)vel.data())[d * n + p];
-      }
-    } else if (repr == PIC_REPR_FP32_ABS) {
-      if (((float *)pos.data())[p] < 0) continue;
-      for (int d = 0; d < 3; ++d) {
-        g[d] = (double)((float *)pos.data())[d * n + p];
-        u[d] = (double)((float *)vel.data())[d * n + p];
-      }
-    } else {
-      if (((double *)pos.data())[p] < 0) continue;
-      for (int d = 0; d < 3; ++d) {
-        g[d] = ((double *)pos.data())[d * n + p];
-        u[d] = ((double *)vel.data())[d * n + p];
-      }
-    }
+  for (auto &r : rg) {
+    const int64_t o = r.first, n = r.second;
+    pos.resize(3 * n * e);
+    vel.resize(3 * n * e);
     for (int d = 0; d < 3; ++d) {
-      X[d][k] = cf.origin[d] + g[d] * cf.h;
-      V[d][k] = u[d] * cf.h;
+      PIC_HIP(c, hipMemcpy(pos.data() + d * n * e, (char *)B.pos[d] + o * e, n * e,
+                           hipMemcpyDeviceToHost));
+      PIC_HIP(c, hipMemcpy(vel.data() + d * n * e, (char *)B.vel[d] + o * e, n * e,
+                           hipMemcpyDeviceToHost));
     }
-    if (ids) ids[k] = id[p];
-    ++k;
+    if (repr == PIC_REPR_FP32_CELL) {
+      cell.resize(n);
+      PIC_HIP(c, hipMemcpy(cell.data(), B.cell + o, n * 4, hipMemcpyDeviceToHost));
+    }
+    if (ids) {
+      id.resize(n);
+      PIC_HIP(c, hipMemcpy(id.data(), B.ids + o, n * 8, hipMemcpyDeviceToHost));
+    }
+    for (int64_t p = 0; p < n; ++p, ++k) {
+      double g[3], u[3];
+      if (repr == PIC_REPR_FP32_CELL) {
+        const int ci[3] = {cell[p] & kMaxDim, (cell[p] >> kCellBits) & kMaxDim,
+                           cell[p] >> (2 * kCellBits)};
+        for (int d = 0; d < 3; ++d) {
+          g[d] = (double)ci[d] + (double)((float *)pos.data())[d * n + p];
+          u[d] = (double)((float *)vel.data())[d * n + p];
+        }
+      } else if (repr == PIC_REPR_FP32_ABS) {
+        for (int d = 0; d < 3; ++d) {
+          g[d] = (double)((float *)pos.data())[d * n + p];
+          u[d] = (double)((float *)vel.data())[d * n + p];
+        }
+      } else {
+        for (int d = 0; d < 3; ++d) {
+          g[d] = ((double *)pos.data())[d * n + p];
+          u[d] = ((double *)vel.data())[d * n + p];
+        }
+      }
+      for (int d = 0; d < 3; ++d) {
+        X[d][k] = cf.origin[d] + g[d] * cf.h;
+        V[d][k] = u[d] * cf.h;
+      }
+      if (ids) ids[k] = id[p];
+    }
   }
   return PIC_OK;
 }
@@ -890,8 +988,7 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
   if (n == 0) return PIC_OK;
-  int64_t ext[PIC_MAX_SPECIES] = {0, 0, 0, 0};
-  if ((st = buffer_extents(c, ext)) != PIC_OK) return st;
+  if (!c->sorted && (st = do_sort(c)) != PIC_OK) return st;
   void *d_ids = nullptr, *d_found = nullptr, *d_out = nullptr;
   auto cleanup = [&]() {
     if (d_ids) (void)hipFree(d_ids);
@@ -906,8 +1003,8 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
   hipError_t e = hipMemcpy(d_ids, ids_sorted, n * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(d_found, 0, n * 4);
   if (e == hipSuccess)
-    e = launch_find_ids(c->cfg.repr, S.buf[c->cur], ext[species], (const int64_t *)d_ids, n,
-                        (int32_t *)d_found, (double *)d_out, c->stream);
+    e = launch_find_ids(c->cfg.repr, S.buf[c->cur], bins_of(c), c->cur, species, c->L.ntiles,
+                        (const int64_t *)d_ids, n, (int32_t *)d_found, (double *)d_out, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   std::vector<double> out(n * 6);
   if (e == hipSuccess) e = hipMemcpy(found, d_found, n * 4, hipMemcpyDeviceToHost);

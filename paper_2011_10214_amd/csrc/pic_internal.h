@@ -22,8 +22,11 @@ constexpr int kCellBits = 10;  // packed cell: i | j << 10 | k << 20
 constexpr int32_t kDeadCell = -1;
 constexpr int kMaxDim = (1 << kCellBits) - 1;
 
-// Device error flags (bitwise or).
-enum : int32_t { kErrRange = 1 };
+// Device flags (bitwise or).
+enum : int32_t {
+  kErrRange = 1,     // a particle position became non-finite / ran away
+  kErrCapacity = 2,  // the overflow list itself overflowed (particles lost)
+};
 
 // Per-species particle arrays of one buffer. Positions: x/y/z (FP64, FP32
 // absolute: cell units) or in-cell offsets (FP32 cell form, with `cell`).
@@ -33,6 +36,42 @@ struct PBuf {
   int32_t *cell;  // FP32 cell form only
   int64_t *ids;   // only when ids were loaded
 };
+
+// Tile regions of the particle buffers, per species s and tile t (index
+// s * ntiles + t). A layout (base, cap, sz) is fixed between re-bucketings and
+// shared by both buffers; the counts describe one buffer's content:
+//   [base, base + nst)              particles that stayed in the tile
+//   [base + cap - arr, base + cap)   particles that arrived from other tiles
+// with nst <= sz (stay zone) and arr <= cap - sz (arrival zone). Particles
+// that found no room are kept in an overflow list at ovf_base[s].
+struct Layout {
+  int64_t *base;
+  int32_t *cap;
+  int32_t *sz;
+};
+
+struct Bins {
+  Layout lay;               // the layout in use
+  int32_t *nst[2];          // stayed counts, by buffer
+  int32_t *arr[2];          // arrival counts, by buffer
+  int32_t *ovf[2];          // [ns] overflow counts, by buffer
+  int64_t ovf_base[PIC_MAX_SPECIES];
+  int32_t ovf_cap[PIC_MAX_SPECIES];
+  int32_t *flags;           // [0]: re-bucketing wanted (spare room ran out)
+};
+
+// Tile capacities after a re-bucketing of cnt particles: a stay zone with
+// 1/16 spare and an arrival zone of 1/8 (+ constants for sparse tiles).
+__host__ __device__ inline int32_t stay_zone(int32_t cnt) { return cnt + cnt / 16 + 32; }
+__host__ __device__ inline int32_t arrival_zone(int32_t cnt) { return cnt / 8 + 64; }
+// Slots of one buffer for n particles over nt tiles (tile regions + overflow).
+__host__ inline int64_t region_slots(int64_t n, int64_t nt) {
+  return n + n / 16 + n / 8 + 96 * nt + 64;
+}
+__host__ inline int32_t overflow_slots(int64_t n) {
+  const int64_t o = n / 32 + 4096;
+  return (int32_t)(o > 0x3fffffff ? 0x3fffffff : o);
+}
 
 struct Geom {
   int32_t kind;
@@ -46,11 +85,14 @@ struct Geom {
 };
 
 struct StepParams {
-  PBuf buf[PIC_MAX_SPECIES];
-  const int64_t *off;      // [ns][ntiles + 1] particle range of each tile
+  PBuf in[PIC_MAX_SPECIES];   // state at the start of the step
+  PBuf out[PIC_MAX_SPECIES];  // state after the step (push only)
+  Bins bins;
+  int32_t cur;                // buffer index of `in` (selects arr / ovf counters)
   int32_t ns;
   int32_t nx, ny, nz;
   int32_t ntx, nty, ntz, ntiles;
+  int32_t has_ids;            // bit s: species s carries ids
   double qmdt[PIC_MAX_SPECIES];  // q/m*dt/h
   double chg[PIC_MAX_SPECIES];   // q*w
   int64_t chg_fixed[PIC_MAX_SPECIES];  // llrint(chg_T * 2^32), chg_T in the path's type
@@ -64,19 +106,26 @@ struct StepParams {
   int32_t *err;
 };
 
+// Re-bucketing: every particle of the source (tile regions and overflow list,
+// or an unsorted range [0, n_src) after a load) is written to the stay zone of
+// its tile in the destination buffer, and the tile regions are re-planned.
 struct SortParams {
   PBuf src[PIC_MAX_SPECIES];
   PBuf dst[PIC_MAX_SPECIES];
-  int64_t n_src[PIC_MAX_SPECIES];  // entries in the source buffer
-  const int64_t *off_src;   // [ns][ntiles + 1] (sorted source) or null (unsorted)
-  int64_t *off_dst;         // [ns][ntiles + 1]
+  int64_t n_src[PIC_MAX_SPECIES];  // unsorted source: entries
+  int32_t unsorted;         // bit s: species s is an unsorted range [0, n_src)
+  Bins bins;                // bins.lay: the source layout
+  Layout dst_lay;           // the new layout, planned by the scan
+  int32_t cur;              // buffer index of the source (its arr / ovf counters)
   int32_t *count;           // [ns][ntiles]
   int32_t *cursor;          // [ns][ntiles]
-  int32_t *hist;            // [ns][ntiles][27] per source tile
+  int32_t *hist;            // [ns][ntiles + 1][27] per source tile (+ overflow block)
+  int64_t region_cap[PIC_MAX_SPECIES];  // slots available for tile regions
   int32_t ns;
   int32_t nx, ny, nz;
   int32_t ntx, nty, ntz, ntiles;
   int32_t has_ids;          // bit s: species s carries ids
+  int32_t *err;
 };
 
 struct LoadParams {
@@ -98,8 +147,9 @@ hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
-hipError_t launch_find_ids(int repr, const PBuf &buf, int64_t n_buf, const int64_t *ids_sorted,
-                           int64_t n_ids, int32_t *found, double *out6, hipStream_t s);
+hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
+                           int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,
+                           int32_t *found, double *out6, hipStream_t st);
 hipError_t launch_node_E_f32(int repr, const float *Ex, const float *Ey, const float *Ez,
                              void *E, int64_t nodes, int32_t *bad, hipStream_t s);
 

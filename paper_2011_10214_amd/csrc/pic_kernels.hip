@@ -239,6 +239,80 @@ __device__ __forceinline__ int box_face_abs(const T g[3], int nx, int ny, int nz
   return -1;
 }
 
+// ------------------------------------------------------------------ tile regions
+
+// Source range of a workgroup: a tile's stayed + arrived particles, or (t ==
+// ntiles) the overflow list. Index k in [0, n1 + na) maps to base + off(k).
+struct Src {
+  int64_t base;
+  int32_t n1;   // stayed (tile) / listed (overflow)
+  int32_t na;   // arrived
+  int32_t gap;  // offset of the arrival zone's first entry minus n1
+};
+
+__device__ __forceinline__ Src src_of(const Bins &B, int cur, int s, int t, int nt) {
+  Src r;
+  if (t < nt) {
+    const int64_t i = (int64_t)s * nt + t;
+    r.base = B.lay.base[i];
+    const int32_t cap = B.lay.cap[i], sz = B.lay.sz[i];
+    const int32_t n1 = B.nst[cur][i], na = B.arr[cur][i];
+    r.n1 = n1 < sz ? n1 : sz;
+    r.na = na < cap - sz ? na : cap - sz;
+    r.gap = cap - r.na - r.n1;
+  } else {
+    r.base = B.ovf_base[s];
+    const int32_t n = B.ovf[cur][s];
+    r.n1 = n < B.ovf_cap[s] ? n : B.ovf_cap[s];
+    r.na = 0;
+    r.gap = 0;
+  }
+  return r;
+}
+
+__device__ __forceinline__ int32_t src_off(const Src &r, int32_t k) { return k < r.n1 ? k : k + r.gap; }
+
+__device__ __forceinline__ int tile_of_cell(const int ci[3], int ntx, int nty) {
+  return (ci[0] >> kTileShift) + ntx * ((ci[1] >> kTileShift) + nty * (ci[2] >> kTileShift));
+}
+
+template <class T>
+struct Particle {
+  int32_t cell;  // packed cell (cell form)
+  T x[3];        // in-cell offsets (cell form) or positions in cell units
+  T u[3];
+  int64_t id;
+};
+
+template <int R>
+__device__ __forceinline__ void store_particle(const PBuf &B, int64_t q, const Particle<typename RealOf<R>::T> &v,
+                                               bool ids) {
+  using T = typename RealOf<R>::T;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ((T *)B.pos[d])[q] = v.x[d];
+    ((T *)B.vel[d])[q] = v.u[d];
+  }
+  if constexpr (R == PIC_REPR_FP32_CELL) B.cell[q] = v.cell;
+  if (ids) B.ids[q] = v.id;
+}
+
+// Slot for a particle entering tile tn of the output buffer: its arrival zone,
+// else the overflow list (and re-bucketing is requested). -1 if even the
+// overflow list is full (the particle is lost; reported as an error).
+__device__ __forceinline__ int64_t arrival_slot(const Bins &B, int out, int s, int tn, int nt,
+                                                int32_t *err) {
+  const int64_t i = (int64_t)s * nt + tn;
+  const int32_t k = atomicAdd(&B.arr[out][i], 1);
+  const int32_t cap = B.lay.cap[i], room = cap - B.lay.sz[i];
+  if (k < room) return B.lay.base[i] + cap - 1 - k;
+  atomicOr(&B.flags[0], 1);
+  const int32_t o = atomicAdd(&B.ovf[out][s], 1);
+  if (o < B.ovf_cap[s]) return B.ovf_base[s] + o;
+  atomicOr(err, kErrCapacity);
+  return -1;
+}
+
 // ------------------------------------------------------------------ step kernel
 
 // rint(a) for 0 <= a < 2^52 as an unsigned 64-bit integer, split exactly into
@@ -253,13 +327,12 @@ __device__ __forceinline__ unsigned long long fix_mag(T a) {
   return ((unsigned long long)hi << 32) | (unsigned long long)lo;
 }
 
-template <class T>
-struct Particle {
-  int32_t cell;  // packed cell (cell form)
-  T x[3];        // in-cell offsets (cell form) or positions in cell units
-  T u[3];
-};
-
+// One workgroup per tile (plus one for the overflow list). With PUSH, every
+// particle is pushed and written to the output buffer: compacted into its
+// tile's stay zone if it stayed in the tile, into the arrival zone of its new
+// tile if it moved, nowhere if it was removed -- so the particles are
+// re-bucketed by tile at every step, in the same pass. Without PUSH only the
+// deposit of the current positions is made.
 template <int R, int D, bool PUSH>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
   using T = typename RealOf<R>::T;
@@ -275,19 +348,61 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
   __shared__ A sAcc[kFixed ? 2 : 1][kRegNodes];
   __shared__ int32_t sEsc[6 * PIC_MAX_SPECIES];
   __shared__ int32_t sAbs[PIC_MAX_SPECIES];
+  __shared__ int32_t sStay[PIC_MAX_SPECIES];
   __shared__ int32_t sAlive;
+  __shared__ Src sSrc[PIC_MAX_SPECIES];
+  __shared__ int32_t sTotal;
+  // movers of the current species, staged so that they leave the workgroup as
+  // contiguous runs per destination tile (one reservation per destination)
+  constexpr int kMovers = sizeof(T) == 4 ? 320 : 160;
+  __shared__ Particle<T> sMv[PUSH ? kMovers : 1];
+  __shared__ int32_t sMvDst[PUSH ? kMovers : 1];   // destination tile
+  __shared__ int16_t sMvRel[PUSH ? kMovers : 1];   // its 27-neighbour index, or -1
+  __shared__ int16_t sMvRank[PUSH ? kMovers : 1];  // rank among movers to it
+  __shared__ int32_t sMvN;
+  __shared__ int32_t sRelCnt[kNeighbours];
+  __shared__ int32_t sRelRes[kNeighbours];
 
   const int nt = P.ntiles;
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  int total = 0;
-  for (int s = 0; s < P.ns; ++s)
-    total += (int)(P.off[s * (nt + 1) + t + 1] - P.off[s * (nt + 1) + t]);
-  if (total == 0) return;  // uniform over the workgroup
+  const bool ovf_block = (int)blockIdx.x == nt;
+  const int t = ovf_block ? nt : xcd_remap(blockIdx.x, nt);
+  const int cur = P.cur, out = 1 - P.cur;
+  if (threadIdx.x == 0) {
+    int total = 0;
+    for (int s = 0; s < P.ns; ++s) {
+      sSrc[s] = src_of(P.bins, cur, s, t, nt);
+      total += sSrc[s].n1 + sSrc[s].na;
+    }
+    sTotal = total;
+  }
+  __syncthreads();
+  if (sTotal == 0) {  // uniform over the workgroup
+    // nothing stayed: the output's stayed counts of this tile are zero
+    if (PUSH && !ovf_block && threadIdx.x < P.ns) P.bins.nst[out][(int64_t)threadIdx.x * nt + t] = 0;
+    return;
+  }
+  if (PUSH && threadIdx.x == 0) {
+    // the input counters are consumed: they count the next step's arrivals
+    for (int s = 0; s < P.ns; ++s) {
+      if (ovf_block) P.bins.ovf[cur][s] = 0;
+      else P.bins.arr[cur][(int64_t)s * nt + t] = 0;
+    }
+  }
 
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int sx = nx + 1, sy = (nx + 1) * (ny + 1);
-  const int tx = t % P.ntx, ty = (t / P.ntx) % P.nty, tz = t / (P.ntx * P.nty);
-  const int rx0 = tx * kTile - 1, ry0 = ty * kTile - 1, rz0 = tz * kTile - 1;
+  int rx0, ry0, rz0;
+  int tx = -4, ty = -4, tz = -4;  // no neighbours for the overflow list
+  if (ovf_block) {  // nothing is staged: every access takes the global path
+    rx0 = ry0 = rz0 = -(1 << 20);
+  } else {
+    tx = t % P.ntx;
+    ty = (t / P.ntx) % P.nty;
+    tz = t / (P.ntx * P.nty);
+    rx0 = tx * kTile - 1;
+    ry0 = ty * kTile - 1;
+    rz0 = tz * kTile - 1;
+  }
   const V4 *__restrict__ gE = (const V4 *)P.E;
   A *__restrict__ gRho = (A *)P.rho;
 
@@ -308,19 +423,29 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
     if constexpr (kFixed) sAcc[1][n] = A(0);
   }
   if (threadIdx.x < 6 * PIC_MAX_SPECIES) sEsc[threadIdx.x] = 0;
-  if (threadIdx.x < PIC_MAX_SPECIES) sAbs[threadIdx.x] = 0;
-  if (threadIdx.x == 0) sAlive = 0;
+  if (threadIdx.x < PIC_MAX_SPECIES) {
+    sAbs[threadIdx.x] = 0;
+    sStay[threadIdx.x] = 0;
+  }
+  if (threadIdx.x == 0) {
+    sAlive = 0;
+    sMvN = 0;
+  }
+  if (threadIdx.x < kNeighbours) sRelCnt[threadIdx.x] = 0;
   __syncthreads();
 
   const GeomT<T> G = geom_of<T>(P.geom);
   const bool crater = P.geom.kind == PIC_OBJ_CRATER;
   const bool sphere = P.geom.kind == PIC_OBJ_SPHERE;
   const T dt = (T)P.dt;
+  const int lane = __lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
   int alive_here = 0;
 
   for (int s = 0; s < P.ns; ++s) {
-    const int p0 = (int)P.off[s * (nt + 1) + t], p1 = (int)P.off[s * (nt + 1) + t + 1];
-    if (p0 == p1) continue;
+    const Src src = sSrc[s];
+    const int32_t np = src.n1 + src.na;
+    if (np == 0) continue;
     const T qmdt = (T)P.qmdt[s];
     const T chg = (T)P.chg[s];
     const bool neg = chg < T(0);
@@ -329,34 +454,40 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
     const unsigned long long fmag =
         (unsigned long long)(P.chg_fixed[s] < 0 ? -P.chg_fixed[s] : P.chg_fixed[s]);
     A *__restrict__ sTile = sAcc[kFixed && neg ? 1 : 0];
-    // uniform bases at the bucket start; lanes index with a 32-bit offset
-    T *__restrict__ X0 = (T *)P.buf[s].pos[0] + p0;
-    T *__restrict__ X1 = (T *)P.buf[s].pos[1] + p0;
-    T *__restrict__ X2 = (T *)P.buf[s].pos[2] + p0;
-    T *__restrict__ U0 = (T *)P.buf[s].vel[0] + p0;
-    T *__restrict__ U1 = (T *)P.buf[s].vel[1] + p0;
-    T *__restrict__ U2 = (T *)P.buf[s].vel[2] + p0;
-    int32_t *__restrict__ CELL = kCell ? P.buf[s].cell + p0 : nullptr;
-    const unsigned np = (unsigned)(p1 - p0);
+    const bool ids = (P.has_ids >> s) & 1;
+    // uniform bases at the region start; lanes index with a 32-bit offset
+    const PBuf In = P.in[s];
+    const T *__restrict__ X0 = (const T *)In.pos[0] + src.base;
+    const T *__restrict__ X1 = (const T *)In.pos[1] + src.base;
+    const T *__restrict__ X2 = (const T *)In.pos[2] + src.base;
+    const T *__restrict__ U0 = (const T *)In.vel[0] + src.base;
+    const T *__restrict__ U1 = (const T *)In.vel[1] + src.base;
+    const T *__restrict__ U2 = (const T *)In.vel[2] + src.base;
+    const int32_t *__restrict__ CELL = kCell ? In.cell + src.base : nullptr;
+    const int64_t *__restrict__ ID = ids ? In.ids + src.base : nullptr;
+    const int64_t sbase = ovf_block ? 0 : P.bins.lay.base[(int64_t)s * nt + t];
+    const int32_t ssz = ovf_block ? 0 : P.bins.lay.sz[(int64_t)s * nt + t];
 
-    auto load = [&](unsigned p) {
+    auto load = [&](int32_t k) {
+      const int32_t o = src_off(src, k);
       Particle<T> q;
-      q.cell = kCell ? CELL[p] : 0;
-      q.x[0] = X0[p];
-      q.x[1] = X1[p];
-      q.x[2] = X2[p];
-      q.u[0] = U0[p];
-      q.u[1] = U1[p];
-      q.u[2] = U2[p];
+      q.cell = kCell ? CELL[o] : 0;
+      q.x[0] = X0[o];
+      q.x[1] = X1[o];
+      q.x[2] = X2[o];
+      q.u[0] = U0[o];
+      q.u[1] = U1[o];
+      q.u[2] = U2[o];
+      q.id = ids ? ID[o] : 0;
       return q;
     };
 
-    auto process = [&](Particle<T> &q, unsigned p) {
+    auto process = [&](Particle<T> &q) {
       int ci[3];
       T f[3];  // in-cell offsets
       T *u = q.u;
       if constexpr (kCell) {
-        if (q.cell < 0) return;  // removed since the last re-bucketing
+        if (q.cell < 0) return;  // not a particle (defensive: never written)
         ci[0] = q.cell & kMaxDim;
         ci[1] = (q.cell >> kCellBits) & kMaxDim;
         ci[2] = q.cell >> (2 * kCellBits);
@@ -364,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
         f[1] = q.x[1];
         f[2] = q.x[2];
       } else {
-        if (q.x[0] < T(0)) return;  // removed (marked with x = -1)
+        if (q.x[0] < T(0)) return;
         for (int d = 0; d < 3; ++d) {
           ci[d] = (int)floorT(q.x[d]);
           f[d] = q.x[d] - (T)ci[d];
@@ -418,11 +549,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
         u[0] = fmaT(qmdt, Ep[0], u[0]);
         u[1] = fmaT(qmdt, Ep[1], u[1]);
         u[2] = fmaT(qmdt, Ep[2], u[2]);
-        U0[p] = u[0];
-        U1[p] = u[1];
-        U2[p] = u[2];
         bool bad = false;
-        T gp[3];
         if constexpr (kCell) {
           for (int d = 0; d < 3; ++d) {
             T op = fmaT(u[d], dt, f[d]);
@@ -438,8 +565,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
           }
         } else {
           for (int d = 0; d < 3; ++d) {
-            gp[d] = fmaT(u[d], dt, q.x[d]);
-            bad |= !finiteT(gp[d]);
+            q.x[d] = fmaT(u[d], dt, q.x[d]);
+            bad |= !finiteT(q.x[d]);
           }
         }
         int face = -1, bin = -1;
@@ -448,36 +575,75 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
             face = box_face(ci, nx, ny, nz, crater);
             if (face < 0) bin = hit_cell(G, nx, ny, ci, f);
           } else {
-            face = box_face_abs(gp, nx, ny, nz, crater);
-            if (face < 0) bin = hit_abs(G, nx, ny, gp);
+            face = box_face_abs(q.x, nx, ny, nz, crater);
+            if (face < 0) bin = hit_abs(G, nx, ny, q.x);
           }
         }
         if (bad) atomicOr(P.err, kErrRange);
         if (face >= 0) atomicAdd(&sEsc[face * PIC_MAX_SPECIES + s], 1);
         if (sphere) {  // wave reduction of the collected count
           const unsigned long long m = __ballot(bin >= 0);
-          if (m && __lane_id() == __ffsll(__ballot(1)) - 1) atomicAdd(&sAbs[s], (int)__popcll(m));
+          if (m && lane == __ffsll(__ballot(1)) - 1) atomicAdd(&sAbs[s], (int)__popcll(m));
         } else if (bin >= 0) {
           atomicAdd((unsigned long long *)&P.tally[(long long)bin * P.ns + s], 1ull);
         }
         const bool removed = bad || face >= 0 || bin >= 0;
         if constexpr (kCell) {
-          X0[p] = f[0];
-          X1[p] = f[1];
-          X2[p] = f[2];
-          CELL[p] = removed ? kDeadCell : pack_cell(ci[0], ci[1], ci[2]);
-        } else {
-          X0[p] = removed ? T(-1) : gp[0];
-          X1[p] = gp[1];
-          X2[p] = gp[2];
-        }
-        if (removed) return;
-        if constexpr (!kCell) {
+          q.x[0] = f[0];
+          q.x[1] = f[1];
+          q.x[2] = f[2];
+          q.cell = pack_cell(ci[0], ci[1], ci[2]);
+        } else if (!removed) {
           for (int d = 0; d < 3; ++d) {
-            ci[d] = (int)floorT(gp[d]);
-            f[d] = gp[d] - (T)ci[d];
+            ci[d] = (int)floorT(q.x[d]);
+            f[d] = q.x[d] - (T)ci[d];
           }
         }
+        // re-bucket: stayed particles are compacted into the tile's stay zone
+        // (one LDS reservation per wave), movers go to their new tile
+        const int tn = removed ? -1 : tile_of_cell(ci, P.ntx, P.nty);
+        const bool stay = !ovf_block && tn == t;
+        const unsigned long long ms = __ballot(stay);
+        int64_t slot = -1;
+        if (ms) {
+          const int leader = __ffsll(__ballot(1)) - 1;
+          int wbase = 0;
+          if (lane == leader) wbase = atomicAdd(&sStay[s], (int)__popcll(ms));
+          wbase = __shfl(wbase, leader);
+          const int k = wbase + (int)__popcll(ms & below);
+          if (stay && k < ssz) slot = sbase + k;
+        }
+        const bool mover = !removed && !stay;
+        const unsigned long long mm = __ballot(mover);
+        if (mm) {  // stage the wave's movers in LDS (one reservation per wave)
+          const int leader = __ffsll(__ballot(1)) - 1;
+          int wbase = 0;
+          if (lane == leader) wbase = atomicAdd(&sMvN, (int)__popcll(mm));
+          wbase = __shfl(wbase, leader);
+          const int k = wbase + (int)__popcll(mm & below);
+          if (mover && k < kMovers) {
+            sMv[k] = q;
+            sMvDst[k] = tn;
+            int tc[3] = {ci[0] >> kTileShift, ci[1] >> kTileShift, ci[2] >> kTileShift};
+            const int dx = tc[0] - tx, dy = tc[1] - ty, dz = tc[2] - tz;
+            sMvRel[k] = (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1)
+                            ? (int16_t)-1
+                            : (int16_t)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+            slot = -2;  // staged
+          }
+        }
+        if (!removed && slot == -1) {
+          if (stay) {  // the stay zone is full
+            atomicOr(&P.bins.flags[0], 1);
+            const int32_t o = atomicAdd(&P.bins.ovf[out][s], 1);
+            if (o < P.bins.ovf_cap[s]) slot = P.bins.ovf_base[s] + o;
+            else atomicOr(P.err, kErrCapacity);
+          } else {  // the staging area is full: write it directly
+            slot = arrival_slot(P.bins, out, s, tn, nt, P.err);
+          }
+        }
+        if (slot >= 0) store_particle<R>(P.out[s], slot, q, ids);
+        if (removed) return;
       }
 
       // trilinear deposit at the (new) position
@@ -500,8 +666,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
         idx[7] = b0 + oz + ox + 1;
       }
       if constexpr (kFixed) {
-        // magnitudes rint(|chg| W 2^32) (sign symmetric), the remainder on
-        // corner 7; negative species go to the second tile
+        // magnitudes rint(|chg| W 2^32) (rounding is sign symmetric), the
+        // remainder on corner 7; negative species go to the second tile
         unsigned long long C[8];
         unsigned long long sum = 0;
 #pragma unroll
@@ -533,13 +699,60 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
 
     // two particles per lane per iteration: both loads are issued before
     // either is processed
-    for (unsigned p = threadIdx.x; p < np; p += 2 * kBlock) {
-      const unsigned p2 = p + kBlock;
-      const bool two = p2 < np;
-      Particle<T> a = load(p), b;
-      if (two) b = load(p2);
-      process(a, p);
-      if (two) process(b, p2);
+    for (int32_t k = threadIdx.x; k < np; k += 2 * kBlock) {
+      const int32_t k2 = k + kBlock;
+      const bool two = k2 < np;
+      Particle<T> a = load(k), b;
+      if (two) b = load(k2);
+      process(a);
+      if (two) process(b);
+    }
+
+    if constexpr (PUSH) {
+      // flush the staged movers: count them per destination, reserve one run
+      // per destination in its arrival zone, write the runs
+      __syncthreads();
+      const int nm = sMvN < kMovers ? sMvN : kMovers;
+      for (int i = threadIdx.x; i < nm; i += kBlock) {
+        const int rel = sMvRel[i];
+        if (rel >= 0) sMvRank[i] = (int16_t)agg_add(sRelCnt, rel);
+      }
+      __syncthreads();
+      if (threadIdx.x < kNeighbours) {
+        const int c = sRelCnt[threadIdx.x];
+        int r = 0;
+        if (c) {
+          const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
+          const int tn = (tx + dx) + P.ntx * ((ty + dy) + P.nty * (tz + dz));
+          r = atomicAdd(&P.bins.arr[out][(int64_t)s * nt + tn], c);
+        }
+        sRelRes[threadIdx.x] = r;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < nm; i += kBlock) {
+        const int rel = sMvRel[i], tn = sMvDst[i];
+        int64_t slot;
+        if (rel >= 0) {
+          const int64_t j = (int64_t)s * nt + tn;
+          const int32_t k = sRelRes[rel] + sMvRank[i];
+          const int32_t cap = P.bins.lay.cap[j], room = cap - P.bins.lay.sz[j];
+          if (k < room) {
+            slot = P.bins.lay.base[j] + cap - 1 - k;
+          } else {
+            atomicOr(&P.bins.flags[0], 1);
+            const int32_t o = atomicAdd(&P.bins.ovf[out][s], 1);
+            slot = o < P.bins.ovf_cap[s] ? P.bins.ovf_base[s] + o : -1;
+            if (slot < 0) atomicOr(P.err, kErrCapacity);
+          }
+        } else {
+          slot = arrival_slot(P.bins, out, s, tn, nt, P.err);
+        }
+        if (slot >= 0) store_particle<R>(P.out[s], slot, sMv[i], ids);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) sMvN = 0;
+      if (threadIdx.x < kNeighbours) sRelCnt[threadIdx.x] = 0;
+      __syncthreads();
     }
   }
 
@@ -562,15 +775,20 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
   }
   if (sphere && threadIdx.x < PIC_MAX_SPECIES && sAbs[threadIdx.x])
     atomicAdd((unsigned long long *)&P.tally[threadIdx.x], (unsigned long long)sAbs[threadIdx.x]);
+  if (PUSH && !ovf_block && threadIdx.x < P.ns) {
+    const int32_t sz = P.bins.lay.sz[(int64_t)threadIdx.x * nt + t];
+    const int32_t k = sStay[threadIdx.x];
+    P.bins.nst[out][(int64_t)threadIdx.x * nt + t] = k < sz ? k : sz;
+  }
   if (PUSH && threadIdx.x == 0 && sAlive)
     atomicAdd((unsigned long long *)&P.stats[0], (unsigned long long)sAlive);
 }
 
-// ------------------------------------------------------------------ sort
+// ------------------------------------------------------------------ re-bucketing
 
-// Tile of a particle's current cell, or -1 if it was removed.
+// Tile of a particle's current cell, or -1 if it is not a particle.
 template <int R>
-__device__ __forceinline__ int tile_of(const PBuf &B, int p, int ntx, int nty, int tc[3]) {
+__device__ __forceinline__ int tile_at(const PBuf &B, int64_t p, int ntx, int nty, int tc[3]) {
   using T = typename RealOf<R>::T;
   int i, j, k;
   if constexpr (R == PIC_REPR_FP32_CELL) {
@@ -603,22 +821,34 @@ __device__ __forceinline__ int neighbour_tile(int rel, int tx, int ty, int tz, i
   return (tx + dx) + ntx * ((ty + dy) + nty * (tz + dz));
 }
 
-// Source range of a workgroup: a tile's bucket (sorted source) or a chunk.
-__device__ __forceinline__ void src_range(const SortParams &P, int s, int wg, int64_t chunk,
-                                          int &p0, int &p1, int &t) {
-  if (P.off_src) {
-    t = wg;
-    const int nt = P.ntiles;
-    p0 = (int)P.off_src[s * (nt + 1) + t];
-    p1 = (int)P.off_src[s * (nt + 1) + t + 1];
-  } else {
-    t = -1;
+// The source entries of workgroup wg for species s: a chunk of an unsorted
+// range, or a tile's region (wg < ntiles; home tile wg) / the overflow list
+// (wg == ntiles). Returns false if the workgroup has no source.
+struct SortSrc {
+  Src r;
+  int home;  // home tile, or -1
+  bool any;
+};
+
+__device__ __forceinline__ SortSrc sort_src(const SortParams &P, int s, int wg, int64_t chunk) {
+  SortSrc o;
+  o.home = -1;
+  o.any = false;
+  if ((P.unsorted >> s) & 1) {
     const int64_t a = (int64_t)wg * chunk;
+    if (a >= P.n_src[s]) return o;
     const int64_t b = a + chunk < P.n_src[s] ? a + chunk : P.n_src[s];
-    p0 = (int)(a < P.n_src[s] ? a : P.n_src[s]);
-    p1 = (int)b;
-    if (p1 < p0) p1 = p0;
+    o.r.base = a;
+    o.r.n1 = (int32_t)(b - a);
+    o.r.na = 0;
+    o.r.gap = 0;
+  } else {
+    if (wg > P.ntiles) return o;
+    o.r = src_of(P.bins, P.cur, s, wg, P.ntiles);
+    o.home = wg < P.ntiles ? wg : -1;
   }
+  o.any = true;
+  return o;
 }
 
 template <int R>
@@ -626,48 +856,51 @@ __global__ __launch_bounds__(kBlock) void sort_count_kernel(SortParams P, int64_
   __shared__ int32_t sH[kNeighbours];
   const int s = blockIdx.y;
   const int nt = P.ntiles;
-  if (P.off_src && (int)blockIdx.x >= nt) return;
-  int p0, p1, t;
-  src_range(P, s, blockIdx.x, chunk, p0, p1, t);
-  const bool sorted = t >= 0;
+  const SortSrc so = sort_src(P, s, blockIdx.x, chunk);
+  if (!so.any) return;  // uniform
+  const int t = so.home;
   int tx = 0, ty = 0, tz = 0;
-  if (sorted) {
+  if (t >= 0) {
     tx = t % P.ntx;
     ty = (t / P.ntx) % P.nty;
     tz = t / (P.ntx * P.nty);
-    if (threadIdx.x < kNeighbours) sH[threadIdx.x] = 0;
-    __syncthreads();
   }
+  if (threadIdx.x < kNeighbours) sH[threadIdx.x] = 0;
+  __syncthreads();
   const PBuf B = P.src[s];
-  for (int p = p0 + (int)threadIdx.x; p < p1; p += kBlock) {
+  const int32_t np = so.r.n1 + so.r.na;
+  for (int32_t k = threadIdx.x; k < np; k += kBlock) {
     int tc[3];
-    const int ct = tile_of<R>(B, p, P.ntx, P.nty, tc);
+    const int ct = tile_at<R>(B, so.r.base + src_off(so.r, k), P.ntx, P.nty, tc);
     if (ct < 0) continue;
-    const int rel = sorted ? neighbour_rel(tc, tx, ty, tz) : -1;
+    const int rel = t >= 0 ? neighbour_rel(tc, tx, ty, tz) : -1;
     if (rel >= 0) agg_add(sH, rel);
     else atomicAdd(&P.count[s * nt + ct], 1);
   }
-  if (sorted) {
-    __syncthreads();
-    if (threadIdx.x < kNeighbours) {
-      const int h = sH[threadIdx.x];
-      P.hist[((int64_t)s * nt + t) * kNeighbours + threadIdx.x] = h;
-      if (h) atomicAdd(&P.count[s * nt + neighbour_tile(threadIdx.x, tx, ty, tz, P.ntx, P.nty)], h);
-    }
+  __syncthreads();
+  if (t >= 0 && threadIdx.x < kNeighbours) {
+    const int h = sH[threadIdx.x];
+    P.hist[((int64_t)s * nt + t) * kNeighbours + threadIdx.x] = h;
+    if (h) atomicAdd(&P.count[s * nt + neighbour_tile(threadIdx.x, tx, ty, tz, P.ntx, P.nty)], h);
   }
 }
 
-// Exclusive scan of the tile counts into bucket offsets; clears the counts and
-// cursors for the next pass. One workgroup per species.
+// Plans the new layout from the tile counts (stay zone + arrival zone per
+// tile, exclusive scan of the capacities); clears the counters for the
+// scatter pass. One workgroup per species.
 __global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
   __shared__ long long sS[1024];
   const int s = blockIdx.x;
   const int nt = P.ntiles;
+  const int out = 1 - P.cur;
   const int per = (nt + 1023) / 1024;
   const int b = threadIdx.x * per;
   const int e = b + per < nt ? b + per : nt;
   long long local = 0;
-  for (int i = b; i < e; ++i) local += P.count[s * nt + i];
+  for (int i = b; i < e; ++i) {
+    const int32_t c = P.count[s * nt + i];
+    local += stay_zone(c) + arrival_zone(c);
+  }
   sS[threadIdx.x] = local;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -677,26 +910,29 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
     __syncthreads();
   }
   long long run = sS[threadIdx.x] - local;
+  const bool flat = (P.unsorted >> s) & 1;
   for (int i = b; i < e; ++i) {
-    P.off_dst[s * (nt + 1) + i] = run;
-    run += P.count[s * nt + i];
-    P.count[s * nt + i] = 0;
-    P.cursor[s * nt + i] = 0;
+    const int64_t j = (int64_t)s * nt + i;
+    // a freshly loaded species has no valid counters in the source buffer
+    // either (the scatter clears them for binned species after reading)
+    if (flat) P.bins.arr[P.cur][j] = 0;
+    const int32_t c = P.count[j];
+    const int32_t sz = stay_zone(c), cap = sz + arrival_zone(c);
+    P.dst_lay.base[j] = run;
+    P.dst_lay.cap[j] = cap;
+    P.dst_lay.sz[j] = sz;
+    P.bins.nst[out][j] = c;
+    P.bins.arr[out][j] = 0;
+    run += cap;
+    P.count[j] = 0;
+    P.cursor[j] = 0;
   }
-  if (threadIdx.x == 1023) P.off_dst[s * (nt + 1) + nt] = sS[1023];
-}
-
-template <int R>
-__device__ __forceinline__ void move_particle(const PBuf &S, const PBuf &Dd, int p, int64_t q,
-                                              bool ids) {
-  using T = typename RealOf<R>::T;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    ((T *)Dd.pos[d])[q] = ((const T *)S.pos[d])[p];
-    ((T *)Dd.vel[d])[q] = ((const T *)S.vel[d])[p];
+  if (threadIdx.x == 1023) {
+    if (sS[1023] > P.region_cap[s]) atomicOr(P.err, kErrCapacity);
+    P.bins.ovf[out][s] = 0;
+    if (flat) P.bins.ovf[P.cur][s] = 0;
+    if (s == 0) P.bins.flags[0] = 0;
   }
-  if constexpr (R == PIC_REPR_FP32_CELL) Dd.cell[q] = S.cell[p];
-  if (ids) Dd.ids[q] = S.ids[p];
 }
 
 template <int R>
@@ -705,12 +941,11 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int6
   __shared__ int32_t sCur[kNeighbours];
   const int s = blockIdx.y;
   const int nt = P.ntiles;
-  if (P.off_src && (int)blockIdx.x >= nt) return;
-  int p0, p1, t;
-  src_range(P, s, blockIdx.x, chunk, p0, p1, t);
-  const bool sorted = t >= 0;
+  const SortSrc so = sort_src(P, s, blockIdx.x, chunk);
+  if (!so.any) return;  // uniform
+  const int t = so.home;
   int tx = 0, ty = 0, tz = 0;
-  if (sorted) {
+  if (t >= 0) {
     tx = t % P.ntx;
     ty = (t / P.ntx) % P.nty;
     tz = t / (P.ntx * P.nty);
@@ -719,27 +954,82 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int6
       long long base = 0;
       if (h) {
         const int nb = neighbour_tile(threadIdx.x, tx, ty, tz, P.ntx, P.nty);
-        base = P.off_dst[s * (nt + 1) + nb] + atomicAdd(&P.cursor[s * nt + nb], h);
+        base = P.dst_lay.base[(int64_t)s * nt + nb] + atomicAdd(&P.cursor[s * nt + nb], h);
       }
       sBase[threadIdx.x] = base;
       sCur[threadIdx.x] = 0;
     }
-    __syncthreads();
   }
+  __syncthreads();
   const PBuf S = P.src[s], Dd = P.dst[s];
   const bool ids = (P.has_ids >> s) & 1;
-  for (int p = p0 + (int)threadIdx.x; p < p1; p += kBlock) {
+  const int32_t np = so.r.n1 + so.r.na;
+  for (int32_t k = threadIdx.x; k < np; k += kBlock) {
+    const int64_t p = so.r.base + src_off(so.r, k);
     int tc[3];
-    const int ct = tile_of<R>(S, p, P.ntx, P.nty, tc);
-    if (ct < 0) continue;  // removed particles are dropped here
-    const int rel = sorted ? neighbour_rel(tc, tx, ty, tz) : -1;
+    const int ct = tile_at<R>(S, p, P.ntx, P.nty, tc);
+    if (ct < 0) continue;
+    const int rel = t >= 0 ? neighbour_rel(tc, tx, ty, tz) : -1;
     long long q;
     if (rel >= 0) {
       q = sBase[rel] + agg_add(sCur, rel);
     } else {
-      q = P.off_dst[s * (nt + 1) + ct] + atomicAdd(&P.cursor[s * nt + ct], 1);
+      q = P.dst_lay.base[(int64_t)s * nt + ct] + atomicAdd(&P.cursor[s * nt + ct], 1);
     }
-    move_particle<R>(S, Dd, p, q, ids);
+    using T = typename RealOf<R>::T;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      ((T *)Dd.pos[d])[q] = ((const T *)S.pos[d])[p];
+      ((T *)Dd.vel[d])[q] = ((const T *)S.vel[d])[p];
+    }
+    if constexpr (R == PIC_REPR_FP32_CELL) Dd.cell[q] = S.cell[p];
+    if (ids) Dd.ids[q] = S.ids[p];
+  }
+  // the source counters are consumed (the source buffer is the next output)
+  if (!((P.unsorted >> s) & 1)) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (t >= 0) P.bins.arr[P.cur][(int64_t)s * nt + t] = 0;
+      else P.bins.ovf[P.cur][s] = 0;
+    }
+  }
+}
+
+// Sampled read-back: for every particle whose id is in the sorted list, write
+// its state (cell units, FP64) to the list slot. One workgroup per tile region
+// (and one for the overflow list).
+template <int R>
+__global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32_t nt,
+                                const int64_t *ids, int64_t n_ids, int32_t *found, double *out) {
+  using T = typename RealOf<R>::T;
+  const Src r = src_of(bins, cur, s, blockIdx.x, nt);
+  const int32_t np = r.n1 + r.na;
+  for (int32_t k = threadIdx.x; k < np; k += blockDim.x) {
+    const int64_t p = r.base + src_off(r, k);
+    double g[3];
+    if constexpr (R == PIC_REPR_FP32_CELL) {
+      const int32_t cell = B.cell[p];
+      if (cell < 0) continue;
+      const int ci[3] = {cell & kMaxDim, (cell >> kCellBits) & kMaxDim, cell >> (2 * kCellBits)};
+      for (int d = 0; d < 3; ++d) g[d] = (double)ci[d] + (double)((const float *)B.pos[d])[p];
+    } else {
+      const T x = ((const T *)B.pos[0])[p];
+      if (x < T(0)) continue;
+      for (int d = 0; d < 3; ++d) g[d] = (double)((const T *)B.pos[d])[p];
+    }
+    const int64_t id = B.ids[p];
+    int64_t lo = 0, hi = n_ids;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ids[mid] < id) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= n_ids || ids[lo] != id) continue;
+    found[lo] = 1;
+    for (int d = 0; d < 3; ++d) {
+      out[d * n_ids + lo] = g[d];
+      out[(3 + d) * n_ids + lo] = (double)((const T *)B.vel[d])[p];
+    }
   }
 }
 
@@ -795,41 +1085,6 @@ __global__ void load_f32_kernel(LoadParams L) {
   }
 }
 
-// Sampled read-back: for every alive particle whose id is in the sorted list,
-// write its state (cell units, FP64) to the list slot.
-template <int R>
-__global__ void find_ids_kernel(PBuf B, int64_t n_buf, const int64_t *ids, int64_t n_ids,
-                                int32_t *found, double *out) {
-  using T = typename RealOf<R>::T;
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_buf;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    double g[3];
-    if constexpr (R == PIC_REPR_FP32_CELL) {
-      const int32_t cell = B.cell[p];
-      if (cell < 0) continue;
-      const int ci[3] = {cell & kMaxDim, (cell >> kCellBits) & kMaxDim, cell >> (2 * kCellBits)};
-      for (int d = 0; d < 3; ++d) g[d] = (double)ci[d] + (double)((const float *)B.pos[d])[p];
-    } else {
-      const T x = ((const T *)B.pos[0])[p];
-      if (x < T(0)) continue;
-      for (int d = 0; d < 3; ++d) g[d] = (double)((const T *)B.pos[d])[p];
-    }
-    const int64_t id = B.ids[p];
-    int64_t lo = 0, hi = n_ids;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (ids[mid] < id) lo = mid + 1;
-      else hi = mid;
-    }
-    if (lo >= n_ids || ids[lo] != id) continue;
-    found[lo] = 1;
-    for (int d = 0; d < 3; ++d) {
-      out[d * n_ids + lo] = g[d];
-      out[(3 + d) * n_ids + lo] = (double)((const T *)B.vel[d])[p];
-    }
-  }
-}
-
 template <class V4>
 __global__ void node_E_kernel(const float *Ex, const float *Ey, const float *Ez, V4 *E,
                               int64_t nodes, int32_t *bad) {
@@ -856,10 +1111,11 @@ int grid_for(int64_t n, int block) {
 template <int R, int D>
 hipError_t launch_step_rd(bool push, const StepParams &p, hipStream_t s) {
   if (p.ntiles <= 0) return hipSuccess;
+  // one workgroup per tile plus one for the overflow list
   if (push)
-    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles + 1), dim3(kBlock), 0, s, p);
   else
-    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles + 1), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
@@ -875,8 +1131,12 @@ hipError_t launch_step_r(int deposit, bool push, const StepParams &p, hipStream_
 
 constexpr int64_t kChunk = 4096;
 
+// Workgroups per species: tiles + overflow list for binned species, chunks for
+// unsorted ones (max_src: the largest unsorted range).
 int64_t sort_blocks(const SortParams &p, int64_t max_src) {
-  return p.off_src ? p.ntiles : (max_src + kChunk - 1) / kChunk;
+  const int64_t chunks = (max_src + kChunk - 1) / kChunk;
+  const int64_t binned = (p.unsorted != (1 << p.ns) - 1) ? (int64_t)p.ntiles + 1 : 0;
+  return chunks > binned ? chunks : binned;
 }
 
 }  // namespace
@@ -952,22 +1212,23 @@ hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_find_ids(int repr, const PBuf &buf, int64_t n_buf, const int64_t *ids_sorted,
-                           int64_t n_ids, int32_t *found, double *out6, hipStream_t s) {
-  if (n_buf <= 0 || n_ids <= 0) return hipSuccess;
-  const dim3 grid(grid_for(n_buf, 256));
+hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
+                           int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,
+                           int32_t *found, double *out6, hipStream_t st) {
+  if (n_ids <= 0) return hipSuccess;
+  const dim3 grid(ntiles + 1);
   switch (repr) {
     case PIC_REPR_FP64:
-      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP64>, grid, dim3(256), 0, s, buf, n_buf,
-                         ids_sorted, n_ids, found, out6);
+      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP64>, grid, dim3(256), 0, st, buf, bins, cur, s,
+                         ntiles, ids_sorted, n_ids, found, out6);
       break;
     case PIC_REPR_FP32_ABS:
-      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_ABS>, grid, dim3(256), 0, s, buf, n_buf,
-                         ids_sorted, n_ids, found, out6);
+      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_ABS>, grid, dim3(256), 0, st, buf, bins, cur,
+                         s, ntiles, ids_sorted, n_ids, found, out6);
       break;
     default:
-      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_CELL>, grid, dim3(256), 0, s, buf, n_buf,
-                         ids_sorted, n_ids, found, out6);
+      hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_CELL>, grid, dim3(256), 0, st, buf, bins, cur,
+                         s, ntiles, ids_sorted, n_ids, found, out6);
   }
   return hipGetLastError();
 }
