@@ -65,9 +65,11 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def traffic_for(workload, repr_, deposit, launches_particles):
-    """HBM bytes per launch of the step kernel measured by rocprofv3 counters,
-    if the stored measurement was taken on the current kernel source."""
+def traffic_for(workload, repr_, deposit, particles_per_launch):
+    """HBM bytes per launch of the step kernel from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE counters (calibrated against a plain copy of known size), scaled
+    to this run's particles per launch -- only if the stored measurement was
+    taken on the current kernel source, else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -76,7 +78,7 @@ def traffic_for(workload, repr_, deposit, launches_particles):
     if (t.get("kernel_source_sha256") != kernel_hash() or t.get("workload") != workload
             or t.get("repr") != repr_ or t.get("deposit") != deposit):
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t["hbm_bytes_per_particle_step"] * particles_per_launch
 
 
 def copy_ceiling(nbytes=4 << 30, reps=5):
