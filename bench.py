@@ -138,6 +138,174 @@ def cpu_baseline(w, target_s):
             "host": host_info()}
 
 
+def serving_run(args):
+    """Serving benchmark: a stream of independent sphere-charging requests
+    (grids 16^3..96^3, 8-64 particles per cell per species, 100-1000 steps)
+    served with continuous batching (pic_batch, captured graphs, admission by
+    HBM footprint) and, as the reference, one at a time through pic_step, with
+    the same Poisson arrivals at a load of `--load` times the one-at-a-time
+    service rate."""
+    import numpy as np
+    import torch
+
+    import paper_2011_10214_amd as pam
+    import synth
+    from paper_2011_10214_amd.serve import (BatchExecutor, Request, SequentialExecutor,
+                                            serve)
+
+    stream_w = synth.serving_stream(n_requests=args.requests, seed=4)
+    budget = int(args.budget_gb * (1 << 30))
+
+    def requests(arrivals):
+        out = []
+        for i, ((w, steps), t) in enumerate(zip(stream_w, arrivals)):
+            def loader(ctx, w=w):
+                for s in range(len(w.species)):
+                    ctx.load_particles_cols(s, synth.particles_dev(w, s))
+                ctx.set_node_E([e.astype(np.float64) for e in synth.node_E(w)])
+                torch.cuda.empty_cache()
+
+            def collect(ctx):
+                return ctx.get_counters()[0].sum()
+            out.append(Request(rid=i, arrival=float(t), steps=steps,
+                               cfg=pam.config_from_workload(w, repr="fp32_cell", deposit="fixed64"),
+                               loader=loader, particles=w.n_particles, collect=collect))
+        return out
+
+    log(f"serving: {len(stream_w)} requests, "
+        f"{sum(w.n_particles * s for w, s in stream_w) / 1e12:.2f}e12 particle-steps")
+    # one-at-a-time service rate with every request waiting at t = 0
+    seq0 = serve(requests([0.0] * len(stream_w)), SequentialExecutor(budget))
+    mu = seq0["throughput_req_per_s"]
+    log(f"one at a time, all queued: {seq0['wall_s']:.1f} s, {mu:.2f} req/s")
+    rate = args.load * mu
+    rng = np.random.default_rng(4)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(stream_w)))
+    arrivals -= arrivals[0]
+    seq = serve(requests(arrivals), SequentialExecutor(budget))
+    log(f"one at a time, Poisson {rate:.2f} req/s: p50 {seq['latency_p50_s']:.2f} s, "
+        f"p99 {seq['latency_p99_s']:.2f} s")
+    ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
+                       steps_per_run=args.steps_per_run, hbm_budget_bytes=budget)
+    try:
+        bat = serve(requests(arrivals), ex)
+    finally:
+        ex.close()
+    log(f"batched, Poisson {rate:.2f} req/s: p50 {bat['latency_p50_s']:.2f} s, "
+        f"p99 {bat['latency_p99_s']:.2f} s")
+    return {"requests": len(stream_w), "arrival_rate_req_per_s": rate, "load": args.load,
+            "service_rate_one_at_a_time_req_per_s": mu, "slots": args.slots,
+            "steps_per_run": args.steps_per_run, "hbm_budget_bytes": budget,
+            "batched": bat, "one_at_a_time": seq}
+
+
+PRECISION_FORMS = [("fp64", "fixed64"), ("fp64", "fp64"), ("fp32_abs", "fixed64"),
+                   ("fp32_abs", "fp32"), ("fp32_cell", "fixed64"), ("fp32_cell", "fp32")]
+
+
+def precision_study(args):
+    """Precision of every representation x deposit form on the crater shape
+    (seed 3) after `steps` steps: error of rho, sampled positions/velocities and
+    surface charge against the FP64 path (FP64 oracle on the sampled particles;
+    for the mesh quantities the FP64 GPU path with fixed-point deposit, which
+    reproduces the FP64 oracle bit for bit), and determinism over reruns."""
+    import hashlib as hl
+
+    import numpy as np
+    import torch
+
+    import paper_2011_10214_amd as pam
+    import synth
+    from oracle import oracle
+
+    w = synth.crater_160_precision()
+    if args.scale != 1.0:  # fewer particles, same mesh and geometry (quick runs)
+        w = w.with_counts([int(s.count * args.scale) for s in w.species])
+    steps = args.steps
+    rng = np.random.default_rng(3)
+    samples = [np.sort(rng.choice(s.count, args.sample, replace=False)) for s in w.species]
+    log(f"precision study: {w.name}, {w.n_particles} particles, {steps} steps, "
+        f"{args.reruns} reruns, sample {args.sample} per species")
+    host = [synth.particles(w, s) for s in range(len(w.species))]
+    E = synth.node_E(w)
+    stream = torch.cuda.Stream()
+
+    def one_run(repr_, dep):
+        cfg = pam.config_from_workload(w, repr=repr_, deposit=dep, stream=stream.cuda_stream)
+        with pam.Context(cfg) as ctx:
+            for s, spec in enumerate(w.species):
+                dev = [torch.from_numpy(c).to("cuda") for c in host[s]]
+                ids = torch.arange(spec.count, dtype=torch.int64, device="cuda")
+                ctx.load_particles_cols(s, dev, ids)
+                del dev, ids
+            ctx.set_node_E([torch.from_numpy(e).to("cuda") for e in E])
+            t0 = time.perf_counter()
+            ctx.step(steps)
+            ctx.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            rho, _ = ctx.get_rho()
+            charge, counts = ctx.get_surface_charge()
+            alive, _, _ = ctx.get_counters()
+            smp = [ctx.get_particles_by_id(s, samples[s]) for s in range(len(w.species))]
+        torch.cuda.empty_cache()
+        h = hl.sha256(rho.tobytes() + counts.tobytes())
+        for f, x, v in smp:
+            h.update(f.tobytes() + np.nan_to_num(x).tobytes() + np.nan_to_num(v).tobytes())
+        return dict(rho=rho, charge=charge, counts=counts, alive=alive, smp=smp, ms=ms,
+                    hash=h.hexdigest())
+
+    # the sampled particles through the FP64 oracle
+    sp = np.concatenate([np.full(args.sample, s, np.int32) for s in range(len(w.species))])
+    parts = [synth.particles(w, s, idx=samples[s]) for s in range(len(w.species))]
+    x0 = np.concatenate([np.stack(p[:3], 1) for p in parts]).astype(np.float64)
+    v0 = np.concatenate([np.stack(p[3:], 1) for p in parts]).astype(np.float64)
+    prob = oracle.Problem(nx=w.nx, ny=w.ny, nz=w.nz, dt=w.dt, q=[s.q for s in w.species],
+                          m=[s.m for s in w.species], w=[s.w for s in w.species], obj=w.obj,
+                          center=w.center, z_flat=w.z_flat, rim_radius=w.rim_radius,
+                          depth=w.depth, repr="fp64", deposit="fixed64")
+    ref = oracle.run(prob, sp, x0, v0, E, steps)
+    vth = np.where(sp == 0, w.species[0].vth, w.species[-1].vth)
+
+    table = []
+    base = None
+    for repr_, dep in PRECISION_FORMS:
+        runs = []
+        for k in range(args.reruns):
+            runs.append(one_run(repr_, dep))
+            log(f"{repr_}/{dep} run {k}: {runs[-1]['ms']:.2f} ms/step")
+        r = runs[0]
+        if base is None:
+            base = r
+        row = {"repr": repr_, "deposit": dep, "ms_per_step": r["ms"],
+               "distinct_results_over_reruns": len({q["hash"] for q in runs})}
+        drho = np.abs(r["rho"] - base["rho"])
+        big = np.abs(base["rho"]) > 1.0
+        row["rho_max_abs_err"] = float(drho.max())
+        row["rho_max_rel_err_where_abs_gt_1"] = float((drho[big] / np.abs(base["rho"][big])).max()) if big.any() else None
+        row["rho_rms_err"] = float(np.sqrt((drho ** 2).mean()))
+        dq = np.abs(r["charge"] - base["charge"])
+        row["surface_charge_max_abs_err_per_bin"] = float(dq.max())
+        row["surface_charge_total_rel_err"] = float(abs(r["charge"].sum() - base["charge"].sum()) /
+                                                    max(abs(base["charge"].sum()), 1.0))
+        found = np.concatenate([f for f, _, _ in r["smp"]])
+        gx = np.concatenate([x for _, x, _ in r["smp"]])
+        gv = np.concatenate([v for _, _, v in r["smp"]])
+        both = found & (ref.fate == 0)
+        row["sample_fate_mismatches"] = int((found != (ref.fate == 0)).sum())
+        dx = np.abs(gx[both] - ref.x[both]).max(axis=1)
+        dv = np.abs(gv[both] - ref.v[both]).max(axis=1)
+        row["x_max_abs_err"] = float(dx.max()) if both.any() else 0.0
+        row["x_max_rel_err"] = float((dx / np.maximum(np.abs(ref.x[both]).max(axis=1), 1.0)).max()) if both.any() else 0.0
+        row["v_max_rel_err"] = float((dv / np.maximum(np.abs(ref.v[both]).max(axis=1), vth[both])).max()) if both.any() else 0.0
+        table.append(row)
+        log(json.dumps(row))
+    print(json.dumps({"precision_study": w.name, "steps": steps, "particles": w.n_particles,
+                      "reruns": args.reruns, "sample_per_species": args.sample,
+                      "reference": "FP64 oracle on the sample; FP64 GPU path with fixed-point "
+                                   "deposit (bit-exact to the FP64 oracle) for rho and charge",
+                      "forms": table}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +320,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy kernel (counter calibration)")
+    ap.add_argument("--precision", action="store_true",
+                    help="precision study of all forms on the crater shape (seed 3)")
+    ap.add_argument("--reruns", type=int, default=5)
+    ap.add_argument("--sample", type=int, default=20000)
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark (continuous batching vs one at a time)")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--steps-per-run", type=int, default=16)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -170,6 +350,14 @@ def main():
         sys.exit(2)
     if args.copy_only:
         print(json.dumps({"copy_ceiling_GBs": copy_ceiling(), "copy_bytes_each_way": 4 << 30}))
+        return
+    if args.serve:
+        print(json.dumps({"serving": serving_run(args)}), flush=True)
+        return
+    if args.precision:
+        if args.steps == 50:
+            args.steps = 200
+        precision_study(args)
         return
     torch.cuda.set_device(0)
     w = synth.WORKLOADS[args.workload]()

@@ -233,6 +233,57 @@ pic_status pic_profile_enable(pic_ctx *ctx, int32_t on);
 /* Synchronises and returns the totals since pic_profile_enable. */
 pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
 
+/* ---- batched runs (serving many independent runs on one GPU) -------------
+ *
+ * A batch advances many contexts ("slots") together: one launch per step
+ * covers the tiles of every attached context, and the steps of one
+ * pic_batch_run are replayed from a captured HIP graph. Contexts are created,
+ * loaded and read as usual; attaching admits one to the batch if its device
+ * footprint fits the batch's budget and a slot is free. Each attached context
+ * gets exactly the same per-step computation as pic_step would give it, so
+ * its results do not depend on what else is in the batch. All attached
+ * contexts must use the batch's repr and deposit. While attached, a context
+ * accepts no other call but pic_batch_detach (other calls: PIC_E_STATE). */
+
+typedef struct pic_batch pic_batch;
+
+typedef struct {
+  int32_t max_slots;        /* contexts attached at once, 1..1024 */
+  int32_t repr, deposit;    /* of every attached context */
+  int32_t steps_per_run;    /* M >= 1: steps advanced by one pic_batch_run */
+  int64_t hbm_budget_bytes; /* admission limit on the summed footprints (> 0) */
+  void *stream;             /* hipStream_t, or NULL for a library stream */
+} pic_batch_config;
+
+/* Device bytes that pic_create allocates for cfg (without ids); -1 if cfg is
+ * invalid. The admission unit of a batch. */
+int64_t pic_footprint_bytes(const pic_config *cfg);
+
+pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out);
+
+/* Detaches every slot (the contexts stay valid) and frees the batch. */
+void pic_batch_destroy(pic_batch *b);
+
+/* Admits ctx for nsteps more steps into a free slot (*slot receives it).
+ * PIC_E_NOMEM: its footprint does not fit the remaining budget; PIC_E_STATE:
+ * no free slot, no node field set, or ctx already attached; PIC_E_INVALID:
+ * different repr / deposit, nsteps < 1. Nothing changes on error. */
+pic_status pic_batch_attach(pic_batch *b, pic_ctx *ctx, int64_t nsteps, int32_t *slot);
+
+/* Advances every attached context by min(M, its remaining steps) and
+ * synchronises. done_slots (capacity max_slots, nullable) receives the slots
+ * whose steps are now all done, *n_done their number. */
+pic_status pic_batch_run(pic_batch *b, int32_t *n_done, int32_t *done_slots);
+
+/* Releases a slot; its context is usable again (results via pic_get_*). */
+pic_status pic_batch_detach(pic_batch *b, int32_t slot);
+
+/* Summed footprints of the attached contexts. */
+int64_t pic_batch_used_bytes(const pic_batch *b);
+
+/* Message of the last failed call on a batch. Never NULL. */
+const char *pic_batch_last_error(const pic_batch *b);
+
 /* Message of the last failed call on ctx (or of the last failed pic_create when
  * ctx is NULL). Never NULL. */
 const char *pic_last_error(const pic_ctx *ctx);

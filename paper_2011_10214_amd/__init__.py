@@ -3,5 +3,5 @@
 The compute runs in the HIP library ``libpic.so`` (gfx950 kernels behind the
 C-ABI of ``include/pic.h``); this package is its Python binding.
 """
-from .pic import (Config, Context, PicError, Profile, config_from_workload, lib,  # noqa: F401
-                  DEPOSIT, OBJECT, REPR, SIGNATURES, LIB_PATH)
+from .pic import (Batch, Config, Context, PicError, Profile, config_from_workload,  # noqa: F401
+                  footprint_bytes, lib, DEPOSIT, OBJECT, REPR, SIGNATURES, LIB_PATH)

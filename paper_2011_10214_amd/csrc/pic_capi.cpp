@@ -202,6 +202,7 @@ struct pic_ctx {
   std::vector<Ev> events;
   std::vector<hipEvent_t> event_pool;
   pic_profile acc{};
+  pic_batch *batch = nullptr;  // attached to a batch
 };
 
 namespace {
@@ -308,6 +309,7 @@ void prof_collect(pic_ctx *c) {
 
 pic_status check_ctx(pic_ctx *c) {
   if (!c) return PIC_E_INVALID;
+  if (c->batch) return fail(c, PIC_E_STATE, "the context is attached to a batch");
   return PIC_OK;
 }
 
@@ -354,9 +356,10 @@ StepParams step_params(pic_ctx *c) {
   StepParams P{};
   const Dims &L = c->L;
   for (int s = 0; s < L.ns; ++s) {
-    P.in[s] = c->sp[s].buf[c->cur];
-    P.out[s] = c->sp[s].buf[1 - c->cur];
+    P.buf[0][s] = c->sp[s].buf[0];
+    P.buf[1][s] = c->sp[s].buf[1];
   }
+  P.remaining = 1;
   P.bins = bins_of(c);
   P.cur = c->cur;
   P.ns = L.ns;
@@ -647,7 +650,7 @@ void pic_destroy(pic_ctx *ctx) {
 pic_status pic_load_particles(pic_ctx *c, int32_t species, int64_t n, const double *x,
                               const double *y, const double *z, const double *vx,
                               const double *vy, const double *vz, const int64_t *ids) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
   pic_ctx::Species &S = c->sp[species];
   if (n < 0 || n > S.cap) return fail(c, PIC_E_INVALID, "n must be in 0..capacity");
@@ -710,7 +713,7 @@ pic_status pic_load_particles(pic_ctx *c, int32_t species, int64_t n, const doub
 pic_status pic_load_particles_f32_dev(pic_ctx *c, int32_t species, int64_t n, const float *x,
                                       const float *y, const float *z, const float *vx,
                                       const float *vy, const float *vz, const int64_t *ids) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
   pic_ctx::Species &S = c->sp[species];
   if (n < 0 || n > S.cap) return fail(c, PIC_E_INVALID, "n must be in 0..capacity");
@@ -746,7 +749,7 @@ pic_status pic_load_particles_f32_dev(pic_ctx *c, int32_t species, int64_t n, co
 }
 
 pic_status pic_set_node_E(pic_ctx *c, const double *Ex, const double *Ey, const double *Ez) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (!Ex || !Ey || !Ez) return fail(c, PIC_E_INVALID, "field arrays must not be NULL");
   const int64_t nodes = c->L.nodes;
   const bool f64 = c->cfg.repr == PIC_REPR_FP64;
@@ -775,7 +778,7 @@ pic_status pic_set_node_E(pic_ctx *c, const double *Ex, const double *Ey, const 
 }
 
 pic_status pic_set_node_E_f32_dev(pic_ctx *c, const float *Ex, const float *Ey, const float *Ez) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (!Ex || !Ey || !Ez) return fail(c, PIC_E_INVALID, "field arrays must not be NULL");
   PIC_HIP(c, launch_fill(c->bad, 4, c->stream));
   PIC_HIP(c, launch_node_E_f32(c->cfg.repr, Ex, Ey, Ez, c->E_spare, c->L.nodes, c->bad,
@@ -790,7 +793,7 @@ pic_status pic_set_node_E_f32_dev(pic_ctx *c, const float *Ex, const float *Ey, 
 }
 
 pic_status pic_step(pic_ctx *c, int32_t nsteps) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (nsteps < 0) return fail(c, PIC_E_INVALID, "nsteps must be >= 0");
   if (nsteps > 0 && !c->E_set) return fail(c, PIC_E_STATE, "pic_set_node_E has not been called");
   pic_status st;
@@ -825,12 +828,12 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
 }
 
 pic_status pic_synchronize(pic_ctx *c) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   return sync_and_check(c);
 }
 
 pic_status pic_get_rho(pic_ctx *c, double *rho, int64_t *rho_fixed) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (!rho) return fail(c, PIC_E_INVALID, "rho must not be NULL");
   if (rho_fixed && c->cfg.deposit != PIC_DEP_FIXED64)
     return fail(c, PIC_E_INVALID, "rho_fixed is only defined for the fixed-point deposit");
@@ -858,7 +861,7 @@ pic_status pic_get_rho(pic_ctx *c, double *rho, int64_t *rho_fixed) {
 int64_t pic_num_bins(const pic_ctx *c) { return c ? c->L.nbins : 0; }
 
 pic_status pic_get_surface_charge(pic_ctx *c, int64_t nbins, double *charge, int64_t *counts) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (nbins != c->L.nbins) return fail(c, PIC_E_INVALID, "nbins must equal pic_num_bins");
   if (nbins > 0 && !charge) return fail(c, PIC_E_INVALID, "charge must not be NULL");
   pic_status st = sync_and_check(c);
@@ -879,7 +882,7 @@ pic_status pic_get_surface_charge(pic_ctx *c, int64_t nbins, double *charge, int
 }
 
 pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64_t *escaped) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
   const Dims &L = c->L;
@@ -900,7 +903,7 @@ pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64
 pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *n_out, double *x,
                              double *y, double *z, double *vx, double *vy, double *vz,
                              int64_t *ids) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
   if (!n_out) return fail(c, PIC_E_INVALID, "n_out must not be NULL");
   pic_ctx::Species &S = c->sp[species];
@@ -975,7 +978,7 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
 pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
                                    const int64_t *ids_sorted, int32_t *found, double *x,
                                    double *y, double *z, double *vx, double *vy, double *vz) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
   if (n < 0) return fail(c, PIC_E_INVALID, "n must be >= 0");
   if (n > 0 && (!ids_sorted || !found || !x || !y || !z || !vx || !vy || !vz))
@@ -1024,7 +1027,7 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
 }
 
 pic_status pic_profile_enable(pic_ctx *c, int32_t on) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   PIC_HIP(c, hipStreamSynchronize(c->stream));
   if (c->prof) prof_collect(c);
   c->prof = on != 0;
@@ -1034,7 +1037,7 @@ pic_status pic_profile_enable(pic_ctx *c, int32_t on) {
 }
 
 pic_status pic_profile_read(pic_ctx *c, pic_profile *out) {
-  if (check_ctx(c) != PIC_OK) return PIC_E_INVALID;
+  if (const pic_status s0 = check_ctx(c)) return s0;
   if (!out) return fail(c, PIC_E_INVALID, "out must not be NULL");
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
@@ -1042,6 +1045,252 @@ pic_status pic_profile_read(pic_ctx *c, pic_profile *out) {
   PIC_HIP(c, hipMemcpy(&ps, c->stats, 8, hipMemcpyDeviceToHost));
   *out = c->acc;
   out->particle_steps = ps;
+  return PIC_OK;
+}
+
+int64_t pic_footprint_bytes(const pic_config *cfg) {
+  if (validate_config(cfg)) return -1;
+  return footprint(*cfg);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct pic_batch {
+  pic_batch_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  StepParams *d_slots = nullptr;
+  int32_t *d_prefix = nullptr;
+  std::vector<pic_ctx *> ctx;       // per slot, nullptr = free
+  std::vector<int64_t> remaining;   // per slot
+  std::vector<int64_t> bytes;       // per slot footprint
+  std::vector<StepParams> h_slots;
+  std::vector<int32_t> h_prefix;
+  int64_t used = 0;
+  hipGraphExec_t exec = nullptr;
+  int32_t graph_grid = 0;
+  std::string msg = "no error";
+};
+
+namespace {
+
+thread_local std::string g_batch_error = "no error";
+
+pic_status bfail(pic_batch *b, pic_status st, const std::string &m) {
+  if (b) b->msg = m;
+  else g_batch_error = m;
+  return st;
+}
+
+pic_status bhip(pic_batch *b, hipError_t e, const char *where) {
+  return bfail(b, PIC_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define PIC_BHIP(b, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return bhip(b, e_, #call);       \
+  } while (0)
+
+// Captures steps_per_run batched steps over a grid of at least `grid`
+// workgroups (the graph is re-captured only when a larger grid is needed).
+pic_status ensure_graph(pic_batch *b, int32_t grid) {
+  if (b->exec && grid <= b->graph_grid) return PIC_OK;
+  int32_t g = 256;
+  while (g < grid) g *= 2;
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  BatchTable T{b->d_slots, b->d_prefix, b->cfg.max_slots};
+  hipGraph_t graph = nullptr;
+  PIC_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < b->cfg.steps_per_run && le == hipSuccess; ++k)
+    le = launch_batch_step(b->cfg.repr, b->cfg.deposit, T, g, 1 << 16, b->stream);
+  hipError_t ce = hipStreamEndCapture(b->stream, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return bhip(b, le, "batched step launch");
+  }
+  if (ce != hipSuccess) return bhip(b, ce, "hipStreamEndCapture");
+  hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return bhip(b, ie, "hipGraphInstantiate");
+  b->graph_grid = g;
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pic_batch_last_error(const pic_batch *b) {
+  return b ? b->msg.c_str() : g_batch_error.c_str();
+}
+
+int64_t pic_batch_used_bytes(const pic_batch *b) { return b ? b->used : 0; }
+
+pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
+  if (!out) return bfail(nullptr, PIC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return bfail(nullptr, PIC_E_INVALID, "config is NULL");
+  if (cfg->max_slots < 1 || cfg->max_slots > 1024)
+    return bfail(nullptr, PIC_E_INVALID, "max_slots must be in 1..1024");
+  if (cfg->repr < 0 || cfg->repr > 2 || cfg->deposit < 0 || cfg->deposit > 2)
+    return bfail(nullptr, PIC_E_INVALID, "repr / deposit out of range");
+  if (cfg->steps_per_run < 1 || cfg->steps_per_run > 4096)
+    return bfail(nullptr, PIC_E_INVALID, "steps_per_run must be in 1..4096");
+  if (cfg->hbm_budget_bytes <= 0) return bfail(nullptr, PIC_E_INVALID, "hbm_budget_bytes must be > 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return bfail(nullptr, PIC_E_DEVICE, "no HIP device available");
+  pic_batch *b = new pic_batch();
+  b->cfg = *cfg;
+  auto bail = [&](pic_status st, const std::string &m) {
+    if (b->d_slots) (void)hipFree(b->d_slots);
+    if (b->d_prefix) (void)hipFree(b->d_prefix);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return bfail(nullptr, st, m);
+  };
+  if (cfg->stream) {
+    b->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(PIC_E_DEVICE, "hipStreamCreate failed");
+    b->own_stream = true;
+  }
+  const int n = cfg->max_slots;
+  if (hipMalloc(&b->d_slots, sizeof(StepParams) * n) != hipSuccess ||
+      hipMalloc(&b->d_prefix, sizeof(int32_t) * (n + 1)) != hipSuccess)
+    return bail(PIC_E_NOMEM, "hipMalloc failed");
+  b->ctx.assign(n, nullptr);
+  b->remaining.assign(n, 0);
+  b->bytes.assign(n, 0);
+  b->h_slots.assign(n, StepParams{});
+  b->h_prefix.assign(n + 1, 0);
+  if (hipMemcpy(b->d_slots, b->h_slots.data(), sizeof(StepParams) * n, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->d_prefix, b->h_prefix.data(), sizeof(int32_t) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return bail(PIC_E_DEVICE, "hipMemcpy failed");
+  *out = b;
+  return PIC_OK;
+}
+
+pic_status pic_batch_detach(pic_batch *b, int32_t slot) {
+  if (!b) return PIC_E_INVALID;
+  if (slot < 0 || slot >= b->cfg.max_slots || !b->ctx[slot])
+    return bfail(b, PIC_E_INVALID, "no context in this slot");
+  PIC_BHIP(b, hipStreamSynchronize(b->stream));
+  pic_ctx *c = b->ctx[slot];
+  c->batch = nullptr;
+  b->ctx[slot] = nullptr;
+  b->remaining[slot] = 0;
+  b->used -= b->bytes[slot];
+  b->bytes[slot] = 0;
+  return PIC_OK;
+}
+
+void pic_batch_destroy(pic_batch *b) {
+  if (!b) return;
+  for (int k = 0; k < b->cfg.max_slots; ++k)
+    if (b->ctx[k]) (void)pic_batch_detach(b, k);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  (void)hipFree(b->d_slots);
+  (void)hipFree(b->d_prefix);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *slot) {
+  if (!b) return PIC_E_INVALID;
+  if (!c || !slot) return bfail(b, PIC_E_INVALID, "ctx and slot must not be NULL");
+  if (nsteps < 1) return bfail(b, PIC_E_INVALID, "nsteps must be >= 1");
+  if (c->batch) return bfail(b, PIC_E_STATE, "the context is already attached");
+  if (c->cfg.repr != b->cfg.repr || c->cfg.deposit != b->cfg.deposit)
+    return bfail(b, PIC_E_INVALID, "repr / deposit differ from the batch's");
+  if (!c->E_set) return bfail(b, PIC_E_STATE, "the context has no node field");
+  int free_slot = -1;
+  for (int k = 0; k < b->cfg.max_slots && free_slot < 0; ++k)
+    if (!b->ctx[k]) free_slot = k;
+  if (free_slot < 0) return bfail(b, PIC_E_STATE, "no free slot");
+  const int64_t fp = footprint(c->cfg);
+  if (b->used + fp > b->cfg.hbm_budget_bytes)
+    return bfail(b, PIC_E_NOMEM, "the footprint does not fit the remaining budget");
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return bfail(b, PIC_E_DEVICE, "context stream failed");
+  if (!c->sorted) {
+    if (do_sort(c) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+      return bfail(b, PIC_E_DEVICE, "context stream failed");
+  }
+  b->ctx[free_slot] = c;
+  b->remaining[free_slot] = nsteps;
+  b->bytes[free_slot] = fp;
+  b->used += fp;
+  c->batch = b;
+  *slot = free_slot;
+  return PIC_OK;
+}
+
+pic_status pic_batch_run(pic_batch *b, int32_t *n_done, int32_t *done_slots) {
+  if (!b) return PIC_E_INVALID;
+  if (n_done) *n_done = 0;
+  const int n = b->cfg.max_slots, M = b->cfg.steps_per_run;
+  // re-plan the tile regions of contexts that ran out of spare room
+  for (int k = 0; k < n; ++k) {
+    pic_ctx *c = b->ctx[k];
+    if (!c || b->remaining[k] <= 0) continue;
+    int32_t flag = 0;
+    PIC_BHIP(b, hipMemcpy(&flag, c->flags, 4, hipMemcpyDeviceToHost));
+    if (flag || !c->sorted) {
+      if (do_sort(c) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
+      PIC_BHIP(b, hipStreamSynchronize(c->stream));
+    }
+  }
+  int32_t total = 0;
+  bool any = false;
+  for (int k = 0; k < n; ++k) {
+    pic_ctx *c = b->ctx[k];
+    b->h_prefix[k] = total;
+    StepParams &P = b->h_slots[k];
+    if (!c || b->remaining[k] <= 0) {
+      P = StepParams{};
+      continue;
+    }
+    P = step_params(c);
+    P.remaining = (int32_t)std::min<int64_t>(M, b->remaining[k]);
+    total += c->L.ntiles + 1;
+    any = true;
+  }
+  b->h_prefix[n] = total;
+  if (!any) return PIC_OK;
+  PIC_BHIP(b, hipMemcpyAsync(b->d_slots, b->h_slots.data(), sizeof(StepParams) * n,
+                             hipMemcpyHostToDevice, b->stream));
+  PIC_BHIP(b, hipMemcpyAsync(b->d_prefix, b->h_prefix.data(), sizeof(int32_t) * (n + 1),
+                             hipMemcpyHostToDevice, b->stream));
+  PIC_BHIP(b, hipStreamSynchronize(b->stream));
+  if (pic_status st = ensure_graph(b, total)) return st;
+  PIC_BHIP(b, hipGraphLaunch(b->exec, b->stream));
+  PIC_BHIP(b, hipStreamSynchronize(b->stream));
+  int32_t nd = 0;
+  for (int k = 0; k < n; ++k) {
+    pic_ctx *c = b->ctx[k];
+    if (!c || b->remaining[k] <= 0) continue;
+    const int32_t did = b->h_slots[k].remaining;
+    if (did & 1) c->cur = 1 - c->cur;
+    c->since_sort += did;
+    b->remaining[k] -= did;
+    if (b->remaining[k] == 0) {
+      if (done_slots) done_slots[nd] = k;
+      ++nd;
+    }
+  }
+  if (n_done) *n_done = nd;
   return PIC_OK;
 }
 

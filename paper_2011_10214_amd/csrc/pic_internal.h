@@ -85,10 +85,10 @@ struct Geom {
 };
 
 struct StepParams {
-  PBuf in[PIC_MAX_SPECIES];   // state at the start of the step
-  PBuf out[PIC_MAX_SPECIES];  // state after the step (push only)
+  PBuf buf[2][PIC_MAX_SPECIES];  // both particle buffers of every species
   Bins bins;
-  int32_t cur;                // buffer index of `in` (selects arr / ovf counters)
+  int32_t cur;                // buffer holding the state at the start of the step
+  int32_t remaining;          // batched runs: steps left (the step is skipped at 0)
   int32_t ns;
   int32_t nx, ny, nz;
   int32_t ntx, nty, ntz, ntiles;
@@ -140,8 +140,22 @@ struct LoadParams {
   int32_t *bad;             // count of positions outside the box
 };
 
+// Batched runs: many contexts (slots) advanced by one launch. Workgroup b
+// belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles + 1
+// workgroups per slot); the slot descriptors live in device memory so that a
+// captured graph can replay steps while the host changes the batch between
+// replays.
+struct BatchTable {
+  StepParams *slots;       // [max_slots]
+  const int32_t *prefix;   // [nslots + 1]
+  int32_t nslots;
+};
+
 // Launchers (return hipError_t of the launch).
 hipError_t launch_step(int repr, int deposit, bool push, const StepParams &p, hipStream_t s);
+// one batched step: clear rho of every running slot, step them, advance them
+hipError_t launch_batch_step(int repr, int deposit, const BatchTable &t, int32_t grid,
+                             int64_t max_rho_words, hipStream_t s);
 hipError_t launch_sort_count(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);

@@ -334,7 +334,7 @@ __device__ __forceinline__ unsigned long long fix_mag(T a) {
 // re-bucketed by tile at every step, in the same pass. Without PUSH only the
 // deposit of the current positions is made.
 template <int R, int D, bool PUSH>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
+__device__ __forceinline__ void step_block(const StepParams &P, const int block) {
   using T = typename RealOf<R>::T;
   using V4 = typename Vec4Of<T>::type;
   using A = typename AccOf<D>::type;
@@ -364,8 +364,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
   __shared__ int32_t sRelRes[kNeighbours];
 
   const int nt = P.ntiles;
-  const bool ovf_block = (int)blockIdx.x == nt;
-  const int t = ovf_block ? nt : xcd_remap(blockIdx.x, nt);
+  const bool ovf_block = block == nt;
+  const int t = ovf_block ? nt : xcd_remap(block, nt);
   const int cur = P.cur, out = 1 - P.cur;
   if (threadIdx.x == 0) {
     int total = 0;
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
     A *__restrict__ sTile = sAcc[kFixed && neg ? 1 : 0];
     const bool ids = (P.has_ids >> s) & 1;
     // uniform bases at the region start; lanes index with a 32-bit offset
-    const PBuf In = P.in[s];
+    const PBuf In = P.buf[cur][s];
     const T *__restrict__ X0 = (const T *)In.pos[0] + src.base;
     const T *__restrict__ X1 = (const T *)In.pos[1] + src.base;
     const T *__restrict__ X2 = (const T *)In.pos[2] + src.base;
@@ -642,7 +642,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
             slot = arrival_slot(P.bins, out, s, tn, nt, P.err);
           }
         }
-        if (slot >= 0) store_particle<R>(P.out[s], slot, q, ids);
+        if (slot >= 0) store_particle<R>(P.buf[out][s], slot, q, ids);
         if (removed) return;
       }
 
@@ -747,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
         } else {
           slot = arrival_slot(P.bins, out, s, tn, nt, P.err);
         }
-        if (slot >= 0) store_particle<R>(P.out[s], slot, sMv[i], ids);
+        if (slot >= 0) store_particle<R>(P.buf[out][s], slot, sMv[i], ids);
       }
       __syncthreads();
       if (threadIdx.x == 0) sMvN = 0;
@@ -782,6 +782,51 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
   }
   if (PUSH && threadIdx.x == 0 && sAlive)
     atomicAdd((unsigned long long *)&P.stats[0], (unsigned long long)sAlive);
+}
+
+template <int R, int D, bool PUSH>
+__global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
+  step_block<R, D, PUSH>(P, blockIdx.x);
+}
+
+// Batched step: workgroup -> (slot, block) through the prefix table.
+template <int R, int D>
+__global__ __launch_bounds__(kBlock) void batch_step_kernel(BatchTable B) {
+  const int b = blockIdx.x;
+  if (b >= B.prefix[B.nslots]) return;
+  int lo = 0, hi = B.nslots - 1;  // last slot with prefix <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (B.prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const StepParams &P = B.slots[lo];
+  if (P.remaining <= 0) return;
+  step_block<R, D, true>(P, b - B.prefix[lo]);
+}
+
+// Clears rho of every slot that will step (blockIdx.y = slot).
+__global__ void batch_clear_kernel(BatchTable B, int64_t elem_bytes) {
+  const int k = blockIdx.y;
+  if (k >= B.nslots) return;
+  const StepParams &P = B.slots[k];
+  if (P.remaining <= 0) return;
+  const int64_t n = (int64_t)(P.nx + 1) * (P.ny + 1) * (P.nz + 1) * elem_bytes / 4;
+  uint32_t *r = (uint32_t *)P.rho;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = 0u;
+}
+
+// After a batched step: every slot that stepped moves to its other buffer.
+__global__ void batch_advance_kernel(BatchTable B) {
+  for (int k = threadIdx.x; k < B.nslots; k += blockDim.x) {
+    StepParams &P = B.slots[k];
+    if (P.remaining > 0) {
+      P.cur = 1 - P.cur;
+      P.remaining -= 1;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ re-bucketing
@@ -1146,6 +1191,39 @@ hipError_t launch_step(int repr, int deposit, bool push, const StepParams &p, hi
     case PIC_REPR_FP64: return launch_step_r<PIC_REPR_FP64>(deposit, push, p, s);
     case PIC_REPR_FP32_ABS: return launch_step_r<PIC_REPR_FP32_ABS>(deposit, push, p, s);
     case PIC_REPR_FP32_CELL: return launch_step_r<PIC_REPR_FP32_CELL>(deposit, push, p, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int R, int D>
+hipError_t launch_batch_rd(const BatchTable &t, int32_t grid, int64_t max_rho_words, hipStream_t s) {
+  const int64_t eb = D == PIC_DEP_ATOMIC_FP32 ? 4 : 8;
+  int64_t cb = (max_rho_words + 255) / 256;
+  if (cb > 256) cb = 256;
+  if (cb < 1) cb = 1;
+  hipLaunchKernelGGL(batch_clear_kernel, dim3((unsigned)cb, t.nslots), dim3(256), 0, s, t, eb);
+  hipLaunchKernelGGL((batch_step_kernel<R, D>), dim3(grid), dim3(kBlock), 0, s, t);
+  hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_batch_r(int deposit, const BatchTable &t, int32_t grid, int64_t w, hipStream_t s) {
+  switch (deposit) {
+    case PIC_DEP_FIXED64: return launch_batch_rd<R, PIC_DEP_FIXED64>(t, grid, w, s);
+    case PIC_DEP_ATOMIC_FP32: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP32>(t, grid, w, s);
+    case PIC_DEP_ATOMIC_FP64: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP64>(t, grid, w, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_step(int repr, int deposit, const BatchTable &t, int32_t grid,
+                             int64_t max_rho_words, hipStream_t s) {
+  if (t.nslots <= 0 || grid <= 0) return hipSuccess;
+  switch (repr) {
+    case PIC_REPR_FP64: return launch_batch_r<PIC_REPR_FP64>(deposit, t, grid, max_rho_words, s);
+    case PIC_REPR_FP32_ABS: return launch_batch_r<PIC_REPR_FP32_ABS>(deposit, t, grid, max_rho_words, s);
+    case PIC_REPR_FP32_CELL: return launch_batch_r<PIC_REPR_FP32_CELL>(deposit, t, grid, max_rho_words, s);
   }
   return hipErrorInvalidValue;
 }

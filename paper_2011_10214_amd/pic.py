@@ -43,6 +43,12 @@ class _Config(ctypes.Structure):
                 ("stream", ctypes.c_void_p)]
 
 
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("repr", ctypes.c_int32),
+                ("deposit", ctypes.c_int32), ("steps_per_run", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+
+
 class _Profile(ctypes.Structure):
     _fields_ = [("step_launches", ctypes.c_int64), ("step_ms", ctypes.c_double),
                 ("sort_launches", ctypes.c_int64), ("sort_ms", ctypes.c_double),
@@ -75,6 +81,14 @@ SIGNATURES = {
     "pic_profile_read": (_st, [_vp, ctypes.POINTER(_Profile)]),
     "pic_last_error": (ctypes.c_char_p, [_vp]),
     "pic_status_string": (ctypes.c_char_p, [_st]),
+    "pic_footprint_bytes": (_i64, [ctypes.POINTER(_Config)]),
+    "pic_batch_create": (_st, [ctypes.POINTER(_BatchConfig), ctypes.POINTER(_vp)]),
+    "pic_batch_destroy": (None, [_vp]),
+    "pic_batch_attach": (_st, [_vp, _vp, _i64, ctypes.POINTER(_i32)]),
+    "pic_batch_run": (_st, [_vp, ctypes.POINTER(_i32), _vp]),
+    "pic_batch_detach": (_st, [_vp, _i32]),
+    "pic_batch_used_bytes": (_i64, [_vp]),
+    "pic_batch_last_error": (ctypes.c_char_p, [_vp]),
 }
 
 _lib = None
@@ -338,6 +352,65 @@ class Context:
         self._check(lib().pic_profile_read(self._h, ctypes.byref(p)))
         return Profile(p.step_launches, p.step_ms, p.sort_launches, p.sort_ms, p.clear_launches,
                        p.clear_ms, p.particle_steps)
+
+
+def footprint_bytes(cfg: Config) -> int:
+    """Device bytes pic_create allocates for cfg (without ids)."""
+    v = lib().pic_footprint_bytes(ctypes.byref(cfg.cstruct()))
+    if v < 0:
+        raise PicError(E_INVALID, "invalid configuration")
+    return int(v)
+
+
+class Batch:
+    """A ``pic_batch``: contexts advanced together by captured batched steps."""
+
+    def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
+                 hbm_budget_bytes: int, stream: int = 0):
+        c = _BatchConfig()
+        c.max_slots, c.repr, c.deposit = max_slots, REPR[repr], DEPOSIT[deposit]
+        c.steps_per_run, c.hbm_budget_bytes = steps_per_run, int(hbm_budget_bytes)
+        c.stream = stream or None
+        h = _vp()
+        st = lib().pic_batch_create(ctypes.byref(c), ctypes.byref(h))
+        if st != OK:
+            raise PicError(st, lib().pic_batch_last_error(None).decode())
+        self._h = h
+        self.max_slots = max_slots
+        self.budget = int(hbm_budget_bytes)
+
+    def _check(self, st):
+        if st != OK:
+            raise PicError(st, lib().pic_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def used_bytes(self) -> int:
+        return int(lib().pic_batch_used_bytes(self._h))
+
+    def attach(self, ctx: "Context", nsteps: int) -> int:
+        slot = ctypes.c_int32(-1)
+        self._check(lib().pic_batch_attach(self._h, ctx._h, int(nsteps), ctypes.byref(slot)))
+        return slot.value
+
+    def run(self) -> list:
+        n = ctypes.c_int32(0)
+        done = (ctypes.c_int32 * self.max_slots)()
+        self._check(lib().pic_batch_run(self._h, ctypes.byref(n), done))
+        return [done[i] for i in range(n.value)]
+
+    def detach(self, slot: int):
+        self._check(lib().pic_batch_detach(self._h, int(slot)))
 
 
 def config_from_workload(w, repr="fp32_cell", deposit="fixed64", sort_interval=0, capacity=None,

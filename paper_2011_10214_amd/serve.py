@@ -1,0 +1,186 @@
+"""Serving many independent charging runs on one GPU.
+
+A request is one run: a context configuration (mesh, object, species), a loader
+that fills a freshly created context with its particles and node field, and a
+number of steps. The server admits requests in arrival order (strict FIFO) as
+soon as a batch slot is free and the request's device footprint fits the HBM
+budget, and keeps the admitted runs stepping together (continuous batching:
+requests that arrive while others run join as slots and memory free up). The
+per-request latency is completion time minus arrival time.
+
+Executors:
+  BatchExecutor      -- all admitted runs advance together through pic_batch
+                        (batched step kernels replayed from a captured graph)
+  SequentialExecutor -- one run at a time through pic_step (the reference)
+Any object with the same four methods can stand in (the scheduler logic is
+tested on the CPU with a simulated executor).
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass
+from typing import Any, Callable, Optional
+
+import numpy as np
+
+from . import pic
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                      # seconds after the start of serving
+    steps: int
+    cfg: Any                            # pic.Config (or an executor-specific description)
+    loader: Optional[Callable] = None   # loader(ctx): loads particles and node field
+    particles: int = 0                  # particles at the start (for throughput)
+    footprint: int = 0                  # device bytes (filled by the executor)
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    result: Any = None
+    collect: Optional[Callable] = None  # collect(ctx) -> result, before the context is freed
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+class BatchExecutor:
+    """Continuous batching on one GPU through pic_batch."""
+
+    def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
+                 hbm_budget_bytes: int, stream: int = 0):
+        self.batch = pic.Batch(max_slots, repr, deposit, steps_per_run, hbm_budget_bytes, stream)
+        self.stream = stream
+        self.slots = {}   # slot -> (request, context)
+
+    def footprint(self, req: Request) -> int:
+        return pic.footprint_bytes(req.cfg)
+
+    def fits(self, req: Request) -> bool:
+        return (len(self.slots) < self.batch.max_slots and
+                self.batch.used_bytes + req.footprint <= self.batch.budget)
+
+    def admit(self, req: Request) -> None:
+        cfg = req.cfg
+        if self.stream and not cfg.stream:
+            cfg.stream = self.stream
+        ctx = pic.Context(cfg)
+        try:
+            req.loader(ctx)
+            slot = self.batch.attach(ctx, req.steps)
+        except Exception:
+            ctx.close()
+            raise
+        self.slots[slot] = (req, ctx)
+
+    def busy(self) -> bool:
+        return bool(self.slots)
+
+    def run(self) -> list:
+        done = []
+        for slot in self.batch.run():
+            req, ctx = self.slots.pop(slot)
+            self.batch.detach(slot)
+            if req.collect:
+                req.result = req.collect(ctx)
+            ctx.close()
+            done.append(req)
+        return done
+
+    def close(self):
+        for slot, (_, ctx) in list(self.slots.items()):
+            self.batch.detach(slot)
+            ctx.close()
+        self.slots.clear()
+        self.batch.close()
+
+
+class SequentialExecutor:
+    """One run at a time, each through pic_step (the unbatched reference)."""
+
+    def __init__(self, hbm_budget_bytes: int, stream: int = 0):
+        self.budget = int(hbm_budget_bytes)
+        self.stream = stream
+        self.current = None
+
+    def footprint(self, req: Request) -> int:
+        return pic.footprint_bytes(req.cfg)
+
+    def fits(self, req: Request) -> bool:
+        return self.current is None and req.footprint <= self.budget
+
+    def admit(self, req: Request) -> None:
+        cfg = req.cfg
+        if self.stream and not cfg.stream:
+            cfg.stream = self.stream
+        ctx = pic.Context(cfg)
+        try:
+            req.loader(ctx)
+        except Exception:
+            ctx.close()
+            raise
+        self.current = (req, ctx)
+
+    def busy(self) -> bool:
+        return self.current is not None
+
+    def run(self) -> list:
+        req, ctx = self.current
+        ctx.step(req.steps)
+        ctx.synchronize()
+        if req.collect:
+            req.result = req.collect(ctx)
+        ctx.close()
+        self.current = None
+        return [req]
+
+    def close(self):
+        if self.current:
+            self.current[1].close()
+            self.current = None
+
+
+def serve(requests: list, executor, clock: Callable[[], float] = time.perf_counter,
+          sleep: Callable[[float], None] = time.sleep, on_admit=None) -> dict:
+    """Serves `requests` (any order; arrival times relative to the start) with
+    strict FIFO admission. Returns latency and throughput statistics."""
+    queue = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+    for r in queue:
+        r.footprint = executor.footprint(r)
+    finished = []
+    t0 = clock()
+    while queue or executor.busy():
+        now = clock() - t0
+        while queue and queue[0].arrival <= now and executor.fits(queue[0]):
+            r = queue.popleft()
+            r.t_admit = clock() - t0
+            executor.admit(r)
+            if on_admit:
+                on_admit(r, executor)
+        if executor.busy():
+            for r in executor.run():
+                r.t_done = clock() - t0
+                finished.append(r)
+        elif queue:
+            if queue[0].arrival > now:
+                sleep(queue[0].arrival - now)
+            elif not executor.fits(queue[0]):
+                raise RuntimeError(f"request {queue[0].rid} can never be admitted "
+                                   f"(footprint {queue[0].footprint} B)")
+    return summarize(finished, clock() - t0)
+
+
+def summarize(finished: list, wall: float) -> dict:
+    lat = np.array([r.latency for r in finished]) if finished else np.zeros(0)
+    ps = sum(r.particles * r.steps for r in finished)
+    return {
+        "requests": len(finished),
+        "wall_s": wall,
+        "throughput_req_per_s": len(finished) / wall if wall > 0 else 0.0,
+        "throughput_particle_steps_per_s": ps / wall if wall > 0 else 0.0,
+        "latency_p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+        "latency_p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+        "latency_mean_s": float(lat.mean()) if len(lat) else None,
+    }

@@ -34,6 +34,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "synth.c")
 LIB = os.path.join(HERE, "libsynth.so")
+SRC_DEV = os.path.join(HERE, "synth_dev.hip")
+LIB_DEV = os.path.join(HERE, "libsynth_dev.so")
 
 
 def build() -> str:
@@ -41,6 +43,11 @@ def build() -> str:
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", SRC,
                            "-o", tmp, "-lm"])
     os.replace(tmp, LIB)
+    tmp = LIB_DEV + ".tmp"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-fPIC",
+                           "-shared", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           SRC_DEV, "-o", tmp], stderr=subprocess.DEVNULL)
+    os.replace(tmp, LIB_DEV)
     return LIB
 
 
@@ -164,6 +171,32 @@ def particles(w: Workload, s: int, start: int = 0, count: int | None = None, idx
     return out
 
 
+_lib_dev = None
+
+
+def particles_dev(w: Workload, s: int, stream: int = 0):
+    """Particles of species s generated on the GPU into six float32 torch
+    tensors (x, y, z, vx, vy, vz). Same draws as `particles`; velocities may
+    differ in the last bits (device log / sin / cos)."""
+    global _lib_dev
+    import torch
+
+    if _lib_dev is None:
+        L = ctypes.CDLL(LIB_DEV)
+        L.synth_particles_dev.restype = ctypes.c_int
+        L.synth_particles_dev.argtypes = [ctypes.POINTER(_Species), ctypes.c_int64,
+                                          ctypes.c_int64] + [ctypes.c_void_p] * 7
+        _lib_dev = L
+    n = w.species[s].count
+    out = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(6)]
+    spec = w._cspec(s)
+    rc = _lib_dev.synth_particles_dev(ctypes.byref(spec), 0, n, *[t.data_ptr() for t in out],
+                                      stream or None)
+    if rc != 0:
+        raise RuntimeError("device generator launch failed")
+    return out
+
+
 def node_E(w: Workload):
     """Node electric field (Ex, Ey, Ez), float32, (nx+1)(ny+1)(nz+1) each, x fastest."""
     L = lib()
@@ -242,6 +275,35 @@ def scaled(w: Workload, nx: int, ny: int, nz: int, ppc: float, steps: int | None
                    z_flat=w.z_flat * f, rim_radius=w.rim_radius * f, depth=w.depth * f,
                    charge=charge, sheath=(w.sheath[0] * f, w.sheath[1], w.sheath[2] * f),
                    steps=steps if steps is not None else w.steps)
+
+
+def serving_stream(n_requests: int = 256, seed: int = 4, n_min: int = 16, n_max: int = 96,
+                   ppc_min: int = 8, ppc_max: int = 64, steps_min: int = 100,
+                   steps_max: int = 1000):
+    """Independent sphere-charging requests: grid n^3 with n ~ U{n_min..n_max},
+    sphere radius n/8 at the centre, ppc ~ U{ppc_min..ppc_max} per species,
+    steps ~ U{steps_min..steps_max}; the per-request seed is drawn from the
+    master seed. Returns a list of (Workload, steps)."""
+    lib()
+    out = []
+    for r in range(n_requests):
+        def draw(k):
+            return synth_draw(seed, 7, r, k)
+        n = n_min + draw(0) % (n_max - n_min + 1)
+        ppc = ppc_min + draw(1) % (ppc_max - ppc_min + 1)
+        steps = steps_min + draw(2) % (steps_max - steps_min + 1)
+        rseed = draw(3) & 0x7FFFFFFF
+        R = n / 8.0
+        cnt = ppc * n ** 3
+        w = Workload(f"request_{r}_n{n}", n, n, n, [_electrons(cnt), _ions(cnt)], obj="sphere",
+                     center=(n / 2.0,) * 3, radius=R, field="coulomb",
+                     charge=-50.0 * (R / 3.0) ** 2, steps=int(steps), seed=int(rseed))
+        out.append((w, int(steps)))
+    return out
+
+
+def synth_draw(seed, stream, index, draw) -> int:
+    return int(lib().synth_draw_u64(seed, stream, index, draw))
 
 
 WORKLOADS = {

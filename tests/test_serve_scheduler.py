@@ -1,0 +1,124 @@
+"""The serving scheduler's logic on the CPU, with a simulated executor and a
+virtual clock: strict FIFO admission, the HBM budget is never exceeded, every
+request completes, latency accounting."""
+import numpy as np
+import pytest
+
+from paper_2011_10214_amd.serve import Request, serve
+
+
+class VClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def clock(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 0.0)
+
+
+class FakeBatch:
+    """Simulated batch: each run advances every admitted request by M steps;
+    a run costs dt_step * M * max(sum of the running requests' sizes, floor)
+    seconds (a device that small runs cannot fill costs its floor)."""
+
+    def __init__(self, vc, max_slots, budget, M=8, dt_step=1e-4, floor=0):
+        self.vc, self.max_slots, self.budget, self.M, self.dt = vc, max_slots, budget, M, dt_step
+        self.floor = floor
+        self.running = {}
+        self.used = 0
+        self.peak = 0
+        self.admitted = []
+
+    def footprint(self, req):
+        return req.cfg["bytes"]
+
+    def fits(self, req):
+        return len(self.running) < self.max_slots and self.used + req.footprint <= self.budget
+
+    def admit(self, req):
+        assert self.fits(req)
+        self.running[req.rid] = [req, req.steps]
+        self.used += req.footprint
+        self.peak = max(self.peak, self.used)
+        self.admitted.append(req.rid)
+
+    def busy(self):
+        return bool(self.running)
+
+    def run(self):
+        size = sum(r.cfg["size"] for r, _ in self.running.values())
+        self.vc.t += self.dt * self.M * max(size, self.floor)
+        done = []
+        for rid in list(self.running):
+            r, left = self.running[rid]
+            left -= self.M
+            if left <= 0:
+                del self.running[rid]
+                self.used -= r.footprint
+                done.append(r)
+            else:
+                self.running[rid][1] = left
+        return done
+
+
+def _requests(n, seed, rate, sizes=(1, 8)):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    reqs = []
+    for i in range(n):
+        size = int(rng.integers(*sizes))
+        reqs.append(Request(rid=i, arrival=float(t[i]), steps=int(rng.integers(10, 100)),
+                            cfg={"bytes": size * 100, "size": size}, particles=size))
+    return reqs
+
+
+@pytest.mark.parametrize("slots,budget", [(4, 1000), (16, 2500), (1, 10 ** 9)])
+def test_fifo_budget_and_completion(slots, budget):
+    vc = VClock()
+    ex = FakeBatch(vc, slots, budget)
+    reqs = _requests(200, 1, rate=20.0)
+    st = serve(reqs, ex, clock=vc.clock, sleep=vc.sleep)
+    assert st["requests"] == len(reqs)
+    assert ex.admitted == sorted(ex.admitted)          # admitted in arrival order
+    assert ex.peak <= budget                           # never over budget
+    for r in reqs:
+        assert r.arrival <= r.t_admit <= r.t_done
+        assert r.latency == r.t_done - r.arrival
+    lat = np.array([r.latency for r in reqs])
+    assert st["latency_p50_s"] == pytest.approx(np.percentile(lat, 50))
+    assert st["latency_p99_s"] == pytest.approx(np.percentile(lat, 99))
+
+
+def test_batching_beats_one_at_a_time_under_load():
+    # small runs that cannot fill the device alone: one run costs as much as a
+    # batch of up to `floor` units of work
+    reqs_a = _requests(100, 2, rate=10.0)
+    reqs_b = _requests(100, 2, rate=10.0)
+    vc = VClock()
+    one = serve(reqs_a, FakeBatch(vc, 1, 10 ** 9, floor=16), clock=vc.clock, sleep=vc.sleep)
+    vc = VClock()
+    many = serve(reqs_b, FakeBatch(vc, 16, 10 ** 9, floor=16), clock=vc.clock, sleep=vc.sleep)
+    assert many["latency_p99_s"] < one["latency_p99_s"]
+    assert many["wall_s"] <= one["wall_s"]
+
+
+def test_request_larger_than_budget_is_reported():
+    vc = VClock()
+    ex = FakeBatch(vc, 4, 100)
+    reqs = [Request(rid=0, arrival=0.0, steps=10, cfg={"bytes": 1000, "size": 1})]
+    with pytest.raises(RuntimeError):
+        serve(reqs, ex, clock=vc.clock, sleep=vc.sleep)
+
+
+def test_head_of_line_waits_for_memory():
+    # a big request blocks later small ones until memory frees up (strict FIFO)
+    vc = VClock()
+    ex = FakeBatch(vc, 8, 1000)
+    reqs = [Request(rid=0, arrival=0.0, steps=80, cfg={"bytes": 600, "size": 6}),
+            Request(rid=1, arrival=0.1, steps=80, cfg={"bytes": 600, "size": 6}),
+            Request(rid=2, arrival=0.2, steps=8, cfg={"bytes": 100, "size": 1})]
+    serve(reqs, ex, clock=vc.clock, sleep=vc.sleep)
+    assert ex.admitted == [0, 1, 2]
+    assert reqs[2].t_admit >= reqs[1].t_admit >= reqs[0].t_done

@@ -1,0 +1,98 @@
+"""Batched serving on the GPU: each request's result is the same in the batch
+(continuous batching through pic_batch, steps replayed from captured graphs)
+as when run alone through pic_step -- bit for bit with the fixed-point
+deposit."""
+import numpy as np
+import pytest
+
+import paper_2011_10214_amd as pam
+import synth
+from paper_2011_10214_amd.serve import BatchExecutor, Request, SequentialExecutor, serve
+
+pytestmark = pytest.mark.gpu
+
+
+def _loader(w):
+    def load(ctx):
+        for s in range(len(w.species)):
+            c = synth.particles(w, s)
+            ctx.load_particles(s, np.stack(c[:3], 1), np.stack(c[3:], 1))
+        ctx.set_node_E([e.astype(np.float64) for e in synth.node_E(w)])
+    return load
+
+
+def _collect(ctx):
+    rho, rf = ctx.get_rho()
+    charge, counts = ctx.get_surface_charge()
+    alive, absorbed, escaped = ctx.get_counters()
+    xs = []
+    for s in range(ctx.ns):
+        x, v, _ = ctx.get_particles(s, with_ids=False)
+        key = np.lexsort(np.concatenate([x, v], 1).T[::-1])
+        xs.append((x[key], v[key]))
+    return dict(rho_fixed=rf, counts=counts, alive=alive, escaped=escaped, particles=xs)
+
+
+def _requests(repr_, arrivals):
+    stream = synth.serving_stream(n_requests=len(arrivals), seed=11, n_min=12, n_max=28,
+                                  ppc_min=2, ppc_max=6, steps_min=9, steps_max=45)
+    reqs = []
+    for i, ((w, steps), t) in enumerate(zip(stream, arrivals)):
+        cfg = pam.config_from_workload(w, repr=repr_, deposit="fixed64")
+        reqs.append(Request(rid=i, arrival=t, steps=steps, cfg=cfg, loader=_loader(w),
+                            particles=w.n_particles, collect=_collect))
+    return reqs
+
+
+def _same(a, b):
+    assert np.array_equal(a["rho_fixed"], b["rho_fixed"])
+    assert np.array_equal(a["counts"], b["counts"])
+    assert np.array_equal(a["alive"], b["alive"]) and np.array_equal(a["escaped"], b["escaped"])
+    for (xa, va), (xb, vb) in zip(a["particles"], b["particles"]):
+        assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+
+
+@pytest.mark.parametrize("repr_", ["fp32_cell", "fp64"])
+def test_alone_and_in_the_mix_are_identical(repr_):
+    arrivals = [0.0, 0.0, 0.0, 0.05, 0.1, 0.1, 0.3]
+    mix = _requests(repr_, arrivals)
+    ex = BatchExecutor(max_slots=3, repr=repr_, deposit="fixed64", steps_per_run=4,
+                       hbm_budget_bytes=64 << 30)
+    try:
+        st = serve(mix, ex)
+    finally:
+        ex.close()
+    assert st["requests"] == len(mix)
+    alone = _requests(repr_, [0.0] * len(arrivals))
+    st1 = serve(alone, SequentialExecutor(hbm_budget_bytes=64 << 30))
+    assert st1["requests"] == len(alone)
+    for a, b in zip(sorted(mix, key=lambda r: r.rid), sorted(alone, key=lambda r: r.rid)):
+        _same(a.result, b.result)
+
+
+def test_batch_admission_respects_budget_and_slots():
+    reqs = _requests("fp32_cell", [0.0] * 5)
+    fps = [pam.footprint_bytes(r.cfg) for r in reqs]
+    budget = sum(sorted(fps)[:2]) + 1  # room for about two at a time
+    peak = []
+
+    def on_admit(r, ex):
+        peak.append(ex.batch.used_bytes)
+
+    ex = BatchExecutor(max_slots=4, repr="fp32_cell", deposit="fixed64", steps_per_run=8,
+                       hbm_budget_bytes=max(budget, max(fps)))
+    try:
+        st = serve(reqs, ex, on_admit=on_admit)
+    finally:
+        ex.close()
+    assert st["requests"] == 5
+    assert max(peak) <= max(budget, max(fps))
+    with pytest.raises(pam.PicError):
+        b = pam.Batch(2, "fp32_cell", "fixed64", 4, 1)  # a budget nothing fits in
+        ctx = pam.Context(reqs[0].cfg)
+        reqs[0].loader(ctx)
+        try:
+            b.attach(ctx, 5)
+        finally:
+            ctx.close()
+            b.close()
