@@ -141,12 +141,12 @@ def cpu_baseline(w, target_s):
 def serving_run(args):
     """Serving benchmark: a stream of independent sphere-charging requests
     (grids 16^3..96^3, 8-64 particles per cell per species, 100-1000 steps)
-    served with continuous batching (pic_batch, captured graphs, admission by
-    HBM footprint) and, as the reference, one at a time through pic_step, with
-    the same Poisson arrivals at a load of `--load` times the one-at-a-time
-    service rate."""
+    served with continuous batching (pic_batch: persistent step kernels
+    replayed from captured graphs, admission by HBM footprint, loading
+    overlapped with the running batch; two share policies) and, as the
+    reference, one at a time through pic_step, with the same Poisson arrivals
+    at a load of `--load` times the one-at-a-time service rate."""
     import numpy as np
-    import torch
 
     import paper_2011_10214_amd as pam
     import synth
@@ -163,7 +163,6 @@ def serving_run(args):
                 for s in range(len(w.species)):
                     ctx.load_particles_cols(s, synth.particles_dev(w, s))
                 ctx.set_node_E([e.astype(np.float64) for e in synth.node_E(w)])
-                torch.cuda.empty_cache()
 
             def collect(ctx):
                 return ctx.get_counters()[0].sum()
@@ -184,19 +183,25 @@ def serving_run(args):
     arrivals -= arrivals[0]
     seq = serve(requests(arrivals), SequentialExecutor(budget))
     log(f"one at a time, Poisson {rate:.2f} req/s: p50 {seq['latency_p50_s']:.2f} s, "
-        f"p99 {seq['latency_p99_s']:.2f} s")
-    ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
-                       steps_per_run=args.steps_per_run, hbm_budget_bytes=budget)
-    try:
-        bat = serve(requests(arrivals), ex)
-    finally:
-        ex.close()
-    log(f"batched, Poisson {rate:.2f} req/s: p50 {bat['latency_p50_s']:.2f} s, "
-        f"p99 {bat['latency_p99_s']:.2f} s")
+        f"p99 {seq['latency_p99_s']:.2f} s, mean {seq['latency_mean_s']:.2f} s")
+    batched = {}
+    # fair share: every running request gets an equal share of the particle-
+    # steps of a run; equal steps: every running request advances 16 steps
+    for name, M, P in [("fair_share", args.steps_per_run, int(args.ps_per_run)),
+                       ("equal_steps", 16, 0)]:
+        ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
+                           steps_per_run=M, hbm_budget_bytes=budget, particle_steps_per_run=P)
+        try:
+            st = serve(requests(arrivals), ex)
+        finally:
+            ex.close()
+        st.update(steps_per_run=M, particle_steps_per_run=P)
+        batched[name] = st
+        log(f"batched ({name}), Poisson {rate:.2f} req/s: p50 {st['latency_p50_s']:.2f} s, "
+            f"p99 {st['latency_p99_s']:.2f} s, mean {st['latency_mean_s']:.2f} s")
     return {"requests": len(stream_w), "arrival_rate_req_per_s": rate, "load": args.load,
             "service_rate_one_at_a_time_req_per_s": mu, "slots": args.slots,
-            "steps_per_run": args.steps_per_run, "hbm_budget_bytes": budget,
-            "batched": bat, "one_at_a_time": seq}
+            "hbm_budget_bytes": budget, "batched": batched, "one_at_a_time": seq}
 
 
 PRECISION_FORMS = [("fp64", "fixed64"), ("fp64", "fp64"), ("fp32_abs", "fixed64"),
@@ -329,14 +334,17 @@ def main():
                     help="serving benchmark (continuous batching vs one at a time)")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=16)
-    ap.add_argument("--steps-per-run", type=int, default=16)
+    ap.add_argument("--steps-per-run", type=int, default=64)
+    ap.add_argument("--ps-per-run", type=float, default=3e8,
+                    help="serving: particle-steps shared equally by the running requests "
+                         "per batched run (0: every request gets --steps-per-run steps)")
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: one MI355X holds the whole subdomain and the "
-              "path has no multi-GPU form in this build (--gpus must be 1)", file=sys.stderr)
+              "path has no multi-GPU form (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

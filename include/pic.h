@@ -236,8 +236,9 @@ pic_status pic_profile_read(pic_ctx *ctx, pic_profile *out);
 /* ---- batched runs (serving many independent runs on one GPU) -------------
  *
  * A batch advances many contexts ("slots") together: one launch per step
- * covers the tiles of every attached context, and the steps of one
- * pic_batch_run are replayed from a captured HIP graph. Contexts are created,
+ * covers the tiles of every attached context (persistent workgroups take
+ * (context, tile) items from a counter), and the steps of one pic_batch_run
+ * are replayed from a captured HIP graph. Contexts are created,
  * loaded and read as usual; attaching admits one to the batch if its device
  * footprint fits the batch's budget and a slot is free. Each attached context
  * gets exactly the same per-step computation as pic_step would give it, so
@@ -250,8 +251,14 @@ typedef struct pic_batch pic_batch;
 typedef struct {
   int32_t max_slots;        /* contexts attached at once, 1..1024 */
   int32_t repr, deposit;    /* of every attached context */
-  int32_t steps_per_run;    /* M >= 1: steps advanced by one pic_batch_run */
+  int32_t steps_per_run;    /* M >= 1: the most steps one pic_batch_run gives a context */
   int64_t hbm_budget_bytes; /* admission limit on the summed footprints (> 0) */
+  int64_t particle_steps_per_run; /* fair share: 0 -> every context gets M steps per
+                                     run; > 0 -> context k with n_k particles (at
+                                     attach) gets
+                                     clamp(P / (S n_k), 1, M) steps (S contexts
+                                     running), so each gets about the same GPU time
+                                     and small runs are not paced by large ones */
   void *stream;             /* hipStream_t, or NULL for a library stream */
 } pic_batch_config;
 
@@ -270,10 +277,21 @@ void pic_batch_destroy(pic_batch *b);
  * different repr / deposit, nsteps < 1. Nothing changes on error. */
 pic_status pic_batch_attach(pic_batch *b, pic_ctx *ctx, int64_t nsteps, int32_t *slot);
 
-/* Advances every attached context by min(M, its remaining steps) and
- * synchronises. done_slots (capacity max_slots, nullable) receives the slots
- * whose steps are now all done, *n_done their number. */
+/* Advances every attached context by min(its quota, its remaining steps)
+ * (quota: M, or the fair share above) and synchronises. done_slots (capacity
+ * max_slots, nullable) receives the slots whose steps are now all done,
+ * *n_done their number. */
 pic_status pic_batch_run(pic_batch *b, int32_t *n_done, int32_t *done_slots);
+
+/* pic_batch_run in two halves, so that the host can prepare and attach new
+ * contexts while a run executes: pic_batch_launch enqueues the run on the
+ * batch's stream and returns; pic_batch_wait synchronises and reports the
+ * finished slots as pic_batch_run does (n_done = 0 when nothing is in flight).
+ * While a run is in flight pic_batch_attach may be called (the new context
+ * joins the next run); pic_batch_launch and pic_batch_detach fail with
+ * PIC_E_STATE. */
+pic_status pic_batch_launch(pic_batch *b);
+pic_status pic_batch_wait(pic_batch *b, int32_t *n_done, int32_t *done_slots);
 
 /* Releases a slot; its context is usable again (results via pic_get_*). */
 pic_status pic_batch_detach(pic_batch *b, int32_t slot);

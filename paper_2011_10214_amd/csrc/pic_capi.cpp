@@ -614,8 +614,8 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
   for (Req &r : reqs) {
     if (dmalloc(c, &p, r.bytes) != hipSuccess) return bail(PIC_E_NOMEM, "hipMalloc failed");
     *r.dst = p;
-    if (hipMemset(p, 0, (size_t)(r.bytes > 0 ? r.bytes : 256)) != hipSuccess)
-      return bail(PIC_E_DEVICE, "hipMemset failed");
+    if (launch_fill(p, r.bytes > 0 ? r.bytes : 256, c->stream) != hipSuccess)
+      return bail(PIC_E_DEVICE, "clearing a new buffer failed");
   }
   void *fh = nullptr;
   if (hipHostMalloc(&fh, 64, hipHostMallocDefault) != hipSuccess)
@@ -634,7 +634,9 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
       carve(S.buf[b], S.mem[b], cfg->repr, S.slots);
     }
   }
-  if (hipDeviceSynchronize() != hipSuccess) return bail(PIC_E_DEVICE, "device error at create");
+  // (only this context's stream: work of other contexts may be in flight)
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(PIC_E_DEVICE, "device error at create");
   *out = c;
   return PIC_OK;
 }
@@ -1057,20 +1059,35 @@ int64_t pic_footprint_bytes(const pic_config *cfg) {
 
 // ------------------------------------------------------------------ batches
 
+namespace {
+// Persistent workgroups of a batched step (enough to fill 256 CUs at the step
+// kernel's occupancy; the ones that find no work exit at once).
+constexpr int32_t kBatchGrid = 2048;
+}  // namespace
+
 struct pic_batch {
   pic_batch_config cfg{};
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // device: the slot table (ordered by quota), its prefix, and a control block
+  // [istep, work, totals[M], flags[max_slots]]
   StepParams *d_slots = nullptr;
   int32_t *d_prefix = nullptr;
+  int32_t *d_ctrl = nullptr;
+  // pinned host mirrors (written only while no copy from them is pending)
+  StepParams *h_slots = nullptr;
+  int32_t *h_prefix = nullptr;
+  int32_t *h_ctrl = nullptr;
   std::vector<pic_ctx *> ctx;       // per slot, nullptr = free
   std::vector<int64_t> remaining;   // per slot
   std::vector<int64_t> bytes;       // per slot footprint
-  std::vector<StepParams> h_slots;
-  std::vector<int32_t> h_prefix;
+  std::vector<int64_t> work;        // per slot: particles at attach (the cost of one step)
+  std::vector<int32_t> want_sort;   // per slot: spare room ran out in the last run
+  std::vector<int32_t> order;       // table entry -> slot of the run in flight
+  std::vector<int32_t> quota;       // per slot: steps of the run in flight
+  bool inflight = false;            // launched, not yet waited for
   int64_t used = 0;
-  hipGraphExec_t exec = nullptr;
-  int32_t graph_grid = 0;
+  std::vector<hipGraphExec_t> exec; // [j]: a run of min(2^j, M) steps
   std::string msg = "no error";
 };
 
@@ -1094,33 +1111,59 @@ pic_status bhip(pic_batch *b, hipError_t e, const char *where) {
     if (e_ != hipSuccess) return bhip(b, e_, #call);       \
   } while (0)
 
-// Captures steps_per_run batched steps over a grid of at least `grid`
-// workgroups (the graph is re-captured only when a larger grid is needed).
-pic_status ensure_graph(pic_batch *b, int32_t grid) {
-  if (b->exec && grid <= b->graph_grid) return PIC_OK;
-  int32_t g = 256;
-  while (g < grid) g *= 2;
-  if (b->exec) {
-    (void)hipGraphExecDestroy(b->exec);
-    b->exec = nullptr;
-  }
-  BatchTable T{b->d_slots, b->d_prefix, b->cfg.max_slots};
+int32_t run_length(const pic_batch *b, int j) {
+  return std::min<int32_t>(1 << j, b->cfg.steps_per_run);
+}
+
+BatchTable table_of(const pic_batch *b) {
+  BatchTable T{};
+  T.slots = b->d_slots;
+  T.prefix = b->d_prefix;
+  T.istep = b->d_ctrl;
+  T.work = b->d_ctrl + 1;
+  T.totals = b->d_ctrl + 2;
+  T.nslots = b->cfg.max_slots;
+  return T;
+}
+
+// The graph of a run of run_length(j) batched steps followed by the read-back
+// of the slots' re-bucketing flags (captured on first use).
+pic_status ensure_graph(pic_batch *b, int j) {
+  if (b->exec[j]) return PIC_OK;
+  const BatchTable T = table_of(b);
+  int32_t *flags_out = b->d_ctrl + 2 + b->cfg.steps_per_run;
   hipGraph_t graph = nullptr;
   PIC_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
-  for (int k = 0; k < b->cfg.steps_per_run && le == hipSuccess; ++k)
-    le = launch_batch_step(b->cfg.repr, b->cfg.deposit, T, g, 1 << 16, b->stream);
+  for (int k = 0; k < run_length(b, j) && le == hipSuccess; ++k)
+    le = launch_batch_step(b->cfg.repr, b->cfg.deposit, T, kBatchGrid, b->stream);
+  if (le == hipSuccess) le = launch_batch_flags(T, flags_out, b->stream);
   hipError_t ce = hipStreamEndCapture(b->stream, &graph);
   if (le != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     return bhip(b, le, "batched step launch");
   }
   if (ce != hipSuccess) return bhip(b, ce, "hipStreamEndCapture");
-  hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+  hipError_t ie = hipGraphInstantiate(&b->exec[j], graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
-  if (ie != hipSuccess) return bhip(b, ie, "hipGraphInstantiate");
-  b->graph_grid = g;
+  if (ie != hipSuccess) {
+    b->exec[j] = nullptr;
+    return bhip(b, ie, "hipGraphInstantiate");
+  }
   return PIC_OK;
+}
+
+void free_batch(pic_batch *b) {
+  for (hipGraphExec_t &e : b->exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  if (b->d_slots) (void)hipFree(b->d_slots);
+  if (b->d_prefix) (void)hipFree(b->d_prefix);
+  if (b->d_ctrl) (void)hipFree(b->d_ctrl);
+  if (b->h_slots) (void)hipHostFree(b->h_slots);
+  if (b->h_prefix) (void)hipHostFree(b->h_prefix);
+  if (b->h_ctrl) (void)hipHostFree(b->h_ctrl);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
 }
 
 }  // namespace
@@ -1144,16 +1187,15 @@ pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
   if (cfg->steps_per_run < 1 || cfg->steps_per_run > 4096)
     return bfail(nullptr, PIC_E_INVALID, "steps_per_run must be in 1..4096");
   if (cfg->hbm_budget_bytes <= 0) return bfail(nullptr, PIC_E_INVALID, "hbm_budget_bytes must be > 0");
+  if (cfg->particle_steps_per_run < 0)
+    return bfail(nullptr, PIC_E_INVALID, "particle_steps_per_run must be >= 0");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return bfail(nullptr, PIC_E_DEVICE, "no HIP device available");
   pic_batch *b = new pic_batch();
   b->cfg = *cfg;
   auto bail = [&](pic_status st, const std::string &m) {
-    if (b->d_slots) (void)hipFree(b->d_slots);
-    if (b->d_prefix) (void)hipFree(b->d_prefix);
-    if (b->own_stream) (void)hipStreamDestroy(b->stream);
-    delete b;
+    free_batch(b);
     return bfail(nullptr, st, m);
   };
   if (cfg->stream) {
@@ -1163,20 +1205,31 @@ pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
       return bail(PIC_E_DEVICE, "hipStreamCreate failed");
     b->own_stream = true;
   }
-  const int n = cfg->max_slots;
+  const int n = cfg->max_slots, M = cfg->steps_per_run;
+  const size_t ctrl = sizeof(int32_t) * (2 + M + n);
   if (hipMalloc(&b->d_slots, sizeof(StepParams) * n) != hipSuccess ||
-      hipMalloc(&b->d_prefix, sizeof(int32_t) * (n + 1)) != hipSuccess)
+      hipMalloc(&b->d_prefix, sizeof(int32_t) * (n + 1)) != hipSuccess ||
+      hipMalloc(&b->d_ctrl, ctrl) != hipSuccess)
     return bail(PIC_E_NOMEM, "hipMalloc failed");
+  if (hipHostMalloc((void **)&b->h_slots, sizeof(StepParams) * n, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void **)&b->h_prefix, sizeof(int32_t) * (n + 1), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void **)&b->h_ctrl, ctrl, hipHostMallocDefault) != hipSuccess)
+    return bail(PIC_E_NOMEM, "hipHostMalloc failed");
+  for (int k = 0; k < n; ++k) b->h_slots[k] = StepParams{};
+  std::memset(b->h_prefix, 0, sizeof(int32_t) * (n + 1));
+  std::memset(b->h_ctrl, 0, ctrl);
   b->ctx.assign(n, nullptr);
   b->remaining.assign(n, 0);
   b->bytes.assign(n, 0);
-  b->h_slots.assign(n, StepParams{});
-  b->h_prefix.assign(n + 1, 0);
-  if (hipMemcpy(b->d_slots, b->h_slots.data(), sizeof(StepParams) * n, hipMemcpyHostToDevice) !=
-          hipSuccess ||
-      hipMemcpy(b->d_prefix, b->h_prefix.data(), sizeof(int32_t) * (n + 1),
-                hipMemcpyHostToDevice) != hipSuccess)
-    return bail(PIC_E_DEVICE, "hipMemcpy failed");
+  b->work.assign(n, 0);
+  b->want_sort.assign(n, 0);
+  b->order.clear();
+  b->quota.assign(n, 0);
+  int nj = 1;
+  while (run_length(b, nj - 1) < M) ++nj;
+  b->exec.assign(nj, nullptr);
   *out = b;
   return PIC_OK;
 }
@@ -1185,6 +1238,7 @@ pic_status pic_batch_detach(pic_batch *b, int32_t slot) {
   if (!b) return PIC_E_INVALID;
   if (slot < 0 || slot >= b->cfg.max_slots || !b->ctx[slot])
     return bfail(b, PIC_E_INVALID, "no context in this slot");
+  if (b->inflight) return bfail(b, PIC_E_STATE, "a run is in flight (pic_batch_wait first)");
   PIC_BHIP(b, hipStreamSynchronize(b->stream));
   pic_ctx *c = b->ctx[slot];
   c->batch = nullptr;
@@ -1192,18 +1246,18 @@ pic_status pic_batch_detach(pic_batch *b, int32_t slot) {
   b->remaining[slot] = 0;
   b->used -= b->bytes[slot];
   b->bytes[slot] = 0;
+  b->work[slot] = 0;
+  b->want_sort[slot] = 0;
   return PIC_OK;
 }
 
 void pic_batch_destroy(pic_batch *b) {
   if (!b) return;
+  (void)pic_batch_wait(b, nullptr, nullptr);
   for (int k = 0; k < b->cfg.max_slots; ++k)
     if (b->ctx[k]) (void)pic_batch_detach(b, k);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  (void)hipFree(b->d_slots);
-  (void)hipFree(b->d_prefix);
-  if (b->own_stream) (void)hipStreamDestroy(b->stream);
-  delete b;
+  (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
 }
 
 pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *slot) {
@@ -1228,70 +1282,116 @@ pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *s
     if (hipStreamSynchronize(c->stream) != hipSuccess)
       return bfail(b, PIC_E_DEVICE, "context stream failed");
   }
+  int64_t n = 0;
+  for (int s = 0; s < c->L.ns; ++s) n += c->sp[s].loaded;
   b->ctx[free_slot] = c;
   b->remaining[free_slot] = nsteps;
   b->bytes[free_slot] = fp;
+  b->work[free_slot] = std::max<int64_t>(n, 1);
+  b->want_sort[free_slot] = 0;
   b->used += fp;
   c->batch = b;
   *slot = free_slot;
   return PIC_OK;
 }
 
-pic_status pic_batch_run(pic_batch *b, int32_t *n_done, int32_t *done_slots) {
+pic_status pic_batch_launch(pic_batch *b) {
   if (!b) return PIC_E_INVALID;
-  if (n_done) *n_done = 0;
+  if (b->inflight) return bfail(b, PIC_E_STATE, "a run is in flight (pic_batch_wait first)");
   const int n = b->cfg.max_slots, M = b->cfg.steps_per_run;
-  // re-plan the tile regions of contexts that ran out of spare room
+  const int64_t P = b->cfg.particle_steps_per_run;
+  // re-plan the tile regions of contexts whose spare room ran out
+  std::vector<int32_t> &order = b->order;
+  order.clear();
   for (int k = 0; k < n; ++k) {
     pic_ctx *c = b->ctx[k];
     if (!c || b->remaining[k] <= 0) continue;
-    int32_t flag = 0;
-    PIC_BHIP(b, hipMemcpy(&flag, c->flags, 4, hipMemcpyDeviceToHost));
-    if (flag || !c->sorted) {
+    if (b->want_sort[k] || !c->sorted) {
       if (do_sort(c) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
       PIC_BHIP(b, hipStreamSynchronize(c->stream));
+      b->want_sort[k] = 0;
     }
+    order.push_back(k);
   }
+  const int S = (int)order.size();
+  if (S == 0) return PIC_OK;
+  // step quotas: M each, or an equal share of P particle-steps
+  for (int k : order) {
+    int64_t qk = M;
+    if (P > 0) qk = std::max<int64_t>(1, std::min<int64_t>(M, P / ((int64_t)S * b->work[k])));
+    b->quota[k] = (int32_t)std::min<int64_t>(qk, b->remaining[k]);
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return b->quota[x] > b->quota[y]; });
+  // the table: entry i holds slot order[i]; the work items of step t are
+  // those of the entries with quota > t, a prefix of the table
   int32_t total = 0;
-  bool any = false;
-  for (int k = 0; k < n; ++k) {
-    pic_ctx *c = b->ctx[k];
-    b->h_prefix[k] = total;
-    StepParams &P = b->h_slots[k];
-    if (!c || b->remaining[k] <= 0) {
-      P = StepParams{};
-      continue;
+  for (int i = 0; i < n; ++i) {
+    b->h_prefix[i] = total;
+    if (i < S) {
+      pic_ctx *c = b->ctx[order[i]];
+      b->h_slots[i] = step_params(c);
+      b->h_slots[i].remaining = b->quota[order[i]];
+      total += c->L.ntiles + 1;
+    } else {
+      b->h_slots[i] = StepParams{};
     }
-    P = step_params(c);
-    P.remaining = (int32_t)std::min<int64_t>(M, b->remaining[k]);
-    total += c->L.ntiles + 1;
-    any = true;
   }
   b->h_prefix[n] = total;
-  if (!any) return PIC_OK;
-  PIC_BHIP(b, hipMemcpyAsync(b->d_slots, b->h_slots.data(), sizeof(StepParams) * n,
+  int32_t *totals = b->h_ctrl + 2;
+  b->h_ctrl[0] = 0;
+  b->h_ctrl[1] = 0;
+  for (int t = 0, i = S; t < M; ++t) {
+    while (i > 0 && b->quota[order[i - 1]] <= t) --i;
+    totals[t] = b->h_prefix[i];
+  }
+  const int32_t len = b->quota[order[0]];
+  int j = 0;
+  while (run_length(b, j) < len) ++j;
+  if (pic_status st = ensure_graph(b, j)) return st;
+  PIC_BHIP(b, hipMemcpyAsync(b->d_slots, b->h_slots, sizeof(StepParams) * n,
                              hipMemcpyHostToDevice, b->stream));
-  PIC_BHIP(b, hipMemcpyAsync(b->d_prefix, b->h_prefix.data(), sizeof(int32_t) * (n + 1),
+  PIC_BHIP(b, hipMemcpyAsync(b->d_prefix, b->h_prefix, sizeof(int32_t) * (n + 1),
                              hipMemcpyHostToDevice, b->stream));
+  PIC_BHIP(b, hipMemcpyAsync(b->d_ctrl, b->h_ctrl, sizeof(int32_t) * (2 + M),
+                             hipMemcpyHostToDevice, b->stream));
+  PIC_BHIP(b, hipGraphLaunch(b->exec[j], b->stream));
+  PIC_BHIP(b, hipMemcpyAsync(b->h_ctrl + 2 + M, b->d_ctrl + 2 + M, sizeof(int32_t) * S,
+                             hipMemcpyDeviceToHost, b->stream));
+  b->inflight = true;
+  return PIC_OK;
+}
+
+pic_status pic_batch_wait(pic_batch *b, int32_t *n_done, int32_t *done_slots) {
+  if (!b) return PIC_E_INVALID;
+  if (n_done) *n_done = 0;
+  if (!b->inflight) return PIC_OK;
   PIC_BHIP(b, hipStreamSynchronize(b->stream));
-  if (pic_status st = ensure_graph(b, total)) return st;
-  PIC_BHIP(b, hipGraphLaunch(b->exec, b->stream));
-  PIC_BHIP(b, hipStreamSynchronize(b->stream));
+  b->inflight = false;
+  const int M = b->cfg.steps_per_run;
   int32_t nd = 0;
-  for (int k = 0; k < n; ++k) {
+  for (size_t i = 0; i < b->order.size(); ++i) {
+    const int k = b->order[i];
     pic_ctx *c = b->ctx[k];
-    if (!c || b->remaining[k] <= 0) continue;
-    const int32_t did = b->h_slots[k].remaining;
+    const int32_t did = b->quota[k];
     if (did & 1) c->cur = 1 - c->cur;
     c->since_sort += did;
     b->remaining[k] -= did;
+    b->want_sort[k] = b->h_ctrl[2 + M + i] != 0;
     if (b->remaining[k] == 0) {
       if (done_slots) done_slots[nd] = k;
       ++nd;
     }
   }
+  b->order.clear();
   if (n_done) *n_done = nd;
   return PIC_OK;
+}
+
+pic_status pic_batch_run(pic_batch *b, int32_t *n_done, int32_t *done_slots) {
+  if (n_done) *n_done = 0;
+  if (pic_status st = pic_batch_launch(b)) return st;
+  return pic_batch_wait(b, n_done, done_slots);
 }
 
 }  // extern "C"

@@ -140,14 +140,17 @@ struct LoadParams {
   int32_t *bad;             // count of positions outside the box
 };
 
-// Batched runs: many contexts (slots) advanced by one launch. Workgroup b
-// belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles + 1
-// workgroups per slot); the slot descriptors live in device memory so that a
-// captured graph can replay steps while the host changes the batch between
-// replays.
+// Batched runs: many contexts (slots) advanced by one launch per step. Work
+// item b belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles + 1
+// items per slot); persistent workgroups take items from a counter. The slot
+// descriptors live in device memory so that a captured graph can replay steps
+// while the host changes the batch between replays.
 struct BatchTable {
-  StepParams *slots;       // [max_slots]
+  StepParams *slots;       // [max_slots], ordered by step quota (descending)
   const int32_t *prefix;   // [nslots + 1]
+  const int32_t *totals;   // [steps per run]: work items of each step (a prefix of the table)
+  int32_t *istep;          // step of the run being executed
+  int32_t *work;           // next work item of the current step
   int32_t nslots;
 };
 
@@ -155,7 +158,9 @@ struct BatchTable {
 hipError_t launch_step(int repr, int deposit, bool push, const StepParams &p, hipStream_t s);
 // one batched step: clear rho of every running slot, step them, advance them
 hipError_t launch_batch_step(int repr, int deposit, const BatchTable &t, int32_t grid,
-                             int64_t max_rho_words, hipStream_t s);
+                             hipStream_t s);
+// the re-bucketing flags of the table's slots into out[nslots]
+hipError_t launch_batch_flags(const BatchTable &t, int32_t *out, hipStream_t s);
 hipError_t launch_sort_count(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);

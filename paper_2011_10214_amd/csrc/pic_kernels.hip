@@ -789,25 +789,44 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
   step_block<R, D, PUSH>(P, blockIdx.x);
 }
 
-// Batched step: workgroup -> (slot, block) through the prefix table.
+// Batched step (persistent): workgroups take work items (slot, block) from a
+// counter until the step's items are exhausted. Slots are ordered by quota, so
+// the items of the slots still stepping are a prefix of the table.
+// The slot table is not written while a step runs: read it through the
+// constant address space, so that the compiler may keep the descriptor of the
+// (wave-uniform) work item in scalar registers as it does for a kernel
+// argument.
+typedef const __attribute__((address_space(4))) StepParams ConstStep;
+typedef const __attribute__((address_space(4))) int32_t ConstI32;
+
 template <int R, int D>
-__global__ __launch_bounds__(kBlock) void batch_step_kernel(BatchTable B) {
-  const int b = blockIdx.x;
-  if (b >= B.prefix[B.nslots]) return;
-  int lo = 0, hi = B.nslots - 1;  // last slot with prefix <= b
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (B.prefix[mid] <= b) lo = mid;
-    else hi = mid - 1;
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == PIC_REPR_FP32_CELL ? 5 : 1))) void batch_step_kernel(BatchTable B) {
+  __shared__ int32_t sItem;
+  ConstStep *slots = (ConstStep *)B.slots;
+  ConstI32 *prefix = (ConstI32 *)B.prefix;
+  const int total = ((ConstI32 *)B.totals)[*(ConstI32 *)B.istep];
+  for (;;) {
+    if (threadIdx.x == 0) sItem = atomicAdd(B.work, 1);
+    __syncthreads();
+    const int b = __builtin_amdgcn_readfirstlane(sItem);
+    __syncthreads();
+    if (b >= total) return;  // uniform
+    int lo = 0, hi = B.nslots - 1;  // last slot with prefix <= b
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    const StepParams &P = *(const StepParams *)(slots + lo);
+    if (P.remaining > 0) step_block<R, D, true>(P, b - prefix[lo]);
   }
-  const StepParams &P = B.slots[lo];
-  if (P.remaining <= 0) return;
-  step_block<R, D, true>(P, b - B.prefix[lo]);
 }
 
-// Clears rho of every slot that will step (blockIdx.y = slot).
+// Clears rho of every slot that will step (blockIdx.y = slot) and resets the
+// work counter of the step.
 __global__ void batch_clear_kernel(BatchTable B, int64_t elem_bytes) {
   const int k = blockIdx.y;
+  if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) *B.work = 0;
   if (k >= B.nslots) return;
   const StepParams &P = B.slots[k];
   if (P.remaining <= 0) return;
@@ -816,6 +835,15 @@ __global__ void batch_clear_kernel(BatchTable B, int64_t elem_bytes) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     r[i] = 0u;
+}
+
+// After a batched run: the re-bucketing flag of every slot of the table, for
+// one read-back by the host.
+__global__ void batch_flags_kernel(BatchTable B, int32_t *out) {
+  for (int k = threadIdx.x; k < B.nslots; k += blockDim.x) {
+    const int32_t *f = B.slots[k].bins.flags;
+    out[k] = f ? f[0] : 0;
+  }
 }
 
 // After a batched step: every slot that stepped moves to its other buffer.
@@ -827,6 +855,7 @@ __global__ void batch_advance_kernel(BatchTable B) {
       P.remaining -= 1;
     }
   }
+  if (threadIdx.x == 0) *B.istep += 1;
 }
 
 // ------------------------------------------------------------------ re-bucketing
@@ -1196,34 +1225,36 @@ hipError_t launch_step(int repr, int deposit, bool push, const StepParams &p, hi
 }
 
 template <int R, int D>
-hipError_t launch_batch_rd(const BatchTable &t, int32_t grid, int64_t max_rho_words, hipStream_t s) {
+hipError_t launch_batch_rd(const BatchTable &t, int32_t grid, hipStream_t s) {
   const int64_t eb = D == PIC_DEP_ATOMIC_FP32 ? 4 : 8;
-  int64_t cb = (max_rho_words + 255) / 256;
-  if (cb > 256) cb = 256;
-  if (cb < 1) cb = 1;
-  hipLaunchKernelGGL(batch_clear_kernel, dim3((unsigned)cb, t.nslots), dim3(256), 0, s, t, eb);
+  hipLaunchKernelGGL(batch_clear_kernel, dim3(64, t.nslots), dim3(256), 0, s, t, eb);
   hipLaunchKernelGGL((batch_step_kernel<R, D>), dim3(grid), dim3(kBlock), 0, s, t);
   hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
 template <int R>
-hipError_t launch_batch_r(int deposit, const BatchTable &t, int32_t grid, int64_t w, hipStream_t s) {
+hipError_t launch_batch_r(int deposit, const BatchTable &t, int32_t grid, hipStream_t s) {
   switch (deposit) {
-    case PIC_DEP_FIXED64: return launch_batch_rd<R, PIC_DEP_FIXED64>(t, grid, w, s);
-    case PIC_DEP_ATOMIC_FP32: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP32>(t, grid, w, s);
-    case PIC_DEP_ATOMIC_FP64: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP64>(t, grid, w, s);
+    case PIC_DEP_FIXED64: return launch_batch_rd<R, PIC_DEP_FIXED64>(t, grid, s);
+    case PIC_DEP_ATOMIC_FP32: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP32>(t, grid, s);
+    case PIC_DEP_ATOMIC_FP64: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP64>(t, grid, s);
   }
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_batch_flags(const BatchTable &t, int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(batch_flags_kernel, dim3(1), dim3(256), 0, s, t, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_batch_step(int repr, int deposit, const BatchTable &t, int32_t grid,
-                             int64_t max_rho_words, hipStream_t s) {
+                             hipStream_t s) {
   if (t.nslots <= 0 || grid <= 0) return hipSuccess;
   switch (repr) {
-    case PIC_REPR_FP64: return launch_batch_r<PIC_REPR_FP64>(deposit, t, grid, max_rho_words, s);
-    case PIC_REPR_FP32_ABS: return launch_batch_r<PIC_REPR_FP32_ABS>(deposit, t, grid, max_rho_words, s);
-    case PIC_REPR_FP32_CELL: return launch_batch_r<PIC_REPR_FP32_CELL>(deposit, t, grid, max_rho_words, s);
+    case PIC_REPR_FP64: return launch_batch_r<PIC_REPR_FP64>(deposit, t, grid, s);
+    case PIC_REPR_FP32_ABS: return launch_batch_r<PIC_REPR_FP32_ABS>(deposit, t, grid, s);
+    case PIC_REPR_FP32_CELL: return launch_batch_r<PIC_REPR_FP32_CELL>(deposit, t, grid, s);
   }
   return hipErrorInvalidValue;
 }

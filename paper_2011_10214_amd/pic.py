@@ -46,7 +46,8 @@ class _Config(ctypes.Structure):
 class _BatchConfig(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("repr", ctypes.c_int32),
                 ("deposit", ctypes.c_int32), ("steps_per_run", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+                ("hbm_budget_bytes", ctypes.c_int64),
+                ("particle_steps_per_run", ctypes.c_int64), ("stream", ctypes.c_void_p)]
 
 
 class _Profile(ctypes.Structure):
@@ -86,6 +87,8 @@ SIGNATURES = {
     "pic_batch_destroy": (None, [_vp]),
     "pic_batch_attach": (_st, [_vp, _vp, _i64, ctypes.POINTER(_i32)]),
     "pic_batch_run": (_st, [_vp, ctypes.POINTER(_i32), _vp]),
+    "pic_batch_launch": (_st, [_vp]),
+    "pic_batch_wait": (_st, [_vp, ctypes.POINTER(_i32), _vp]),
     "pic_batch_detach": (_st, [_vp, _i32]),
     "pic_batch_used_bytes": (_i64, [_vp]),
     "pic_batch_last_error": (ctypes.c_char_p, [_vp]),
@@ -184,10 +187,11 @@ def _is_device(a) -> bool:
 
 def _device_sync():
     """Device arrays handed to the library may still be in flight on torch's
-    stream: wait for them (loads are not on the hot path)."""
+    current stream: wait for that stream (not the whole device, so that work of
+    other contexts keeps running)."""
     import torch
 
-    torch.cuda.synchronize()
+    torch.cuda.current_stream().synchronize()
 
 
 @dataclass
@@ -363,13 +367,16 @@ def footprint_bytes(cfg: Config) -> int:
 
 
 class Batch:
-    """A ``pic_batch``: contexts advanced together by captured batched steps."""
+    """A ``pic_batch``: contexts advanced together by captured batched steps.
+    ``particle_steps_per_run`` > 0 gives every context an equal share of that
+    many particle-steps per run (between 1 and ``steps_per_run`` steps)."""
 
     def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
-                 hbm_budget_bytes: int, stream: int = 0):
+                 hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0):
         c = _BatchConfig()
         c.max_slots, c.repr, c.deposit = max_slots, REPR[repr], DEPOSIT[deposit]
         c.steps_per_run, c.hbm_budget_bytes = steps_per_run, int(hbm_budget_bytes)
+        c.particle_steps_per_run = int(particle_steps_per_run)
         c.stream = stream or None
         h = _vp()
         st = lib().pic_batch_create(ctypes.byref(c), ctypes.byref(h))
@@ -407,6 +414,17 @@ class Batch:
         n = ctypes.c_int32(0)
         done = (ctypes.c_int32 * self.max_slots)()
         self._check(lib().pic_batch_run(self._h, ctypes.byref(n), done))
+        return [done[i] for i in range(n.value)]
+
+    def launch(self):
+        """Enqueues a run and returns at once (attach may be called meanwhile)."""
+        self._check(lib().pic_batch_launch(self._h))
+
+    def wait(self) -> list:
+        """Waits for the run in flight; returns the slots that finished."""
+        n = ctypes.c_int32(0)
+        done = (ctypes.c_int32 * self.max_slots)()
+        self._check(lib().pic_batch_wait(self._h, ctypes.byref(n), done))
         return [done[i] for i in range(n.value)]
 
     def detach(self, slot: int):

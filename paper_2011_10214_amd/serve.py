@@ -10,9 +10,11 @@ per-request latency is completion time minus arrival time.
 
 Executors:
   BatchExecutor      -- all admitted runs advance together through pic_batch
-                        (batched step kernels replayed from a captured graph)
+                        (batched step kernels replayed from a captured graph;
+                        new requests are loaded while a run executes)
   SequentialExecutor -- one run at a time through pic_step (the reference)
-Any object with the same four methods can stand in (the scheduler logic is
+Any object with the same methods (footprint, fits, admit, busy, run; optionally
+launch + wait for overlapped admission) can stand in (the scheduler logic is
 tested on the CPU with a simulated executor).
 """
 from __future__ import annotations
@@ -50,8 +52,9 @@ class BatchExecutor:
     """Continuous batching on one GPU through pic_batch."""
 
     def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
-                 hbm_budget_bytes: int, stream: int = 0):
-        self.batch = pic.Batch(max_slots, repr, deposit, steps_per_run, hbm_budget_bytes, stream)
+                 hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0):
+        self.batch = pic.Batch(max_slots, repr, deposit, steps_per_run, hbm_budget_bytes, stream,
+                               particle_steps_per_run)
         self.stream = stream
         self.slots = {}   # slot -> (request, context)
 
@@ -79,8 +82,16 @@ class BatchExecutor:
         return bool(self.slots)
 
     def run(self) -> list:
+        self.launch()
+        return self.wait()
+
+    def launch(self) -> None:
+        """Enqueues one run; admissions may proceed until wait()."""
+        self.batch.launch()
+
+    def wait(self) -> list:
         done = []
-        for slot in self.batch.run():
+        for slot in self.batch.wait():
             req, ctx = self.slots.pop(slot)
             self.batch.detach(slot)
             if req.collect:
@@ -151,7 +162,9 @@ def serve(requests: list, executor, clock: Callable[[], float] = time.perf_count
         r.footprint = executor.footprint(r)
     finished = []
     t0 = clock()
-    while queue or executor.busy():
+    overlap = hasattr(executor, "launch") and hasattr(executor, "wait")
+
+    def admit_arrived():
         now = clock() - t0
         while queue and queue[0].arrival <= now and executor.fits(queue[0]):
             r = queue.popleft()
@@ -159,8 +172,20 @@ def serve(requests: list, executor, clock: Callable[[], float] = time.perf_count
             executor.admit(r)
             if on_admit:
                 on_admit(r, executor)
+
+    while queue or executor.busy():
+        admit_arrived()
+        now = clock() - t0
         if executor.busy():
-            for r in executor.run():
+            if overlap:
+                # requests that arrive during a run are created, loaded and
+                # attached while it executes; they join the next run
+                executor.launch()
+                admit_arrived()
+                done = executor.wait()
+            else:
+                done = executor.run()
+            for r in done:
                 r.t_done = clock() - t0
                 finished.append(r)
         elif queue:

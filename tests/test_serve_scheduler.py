@@ -122,3 +122,61 @@ def test_head_of_line_waits_for_memory():
     serve(reqs, ex, clock=vc.clock, sleep=vc.sleep)
     assert ex.admitted == [0, 1, 2]
     assert reqs[2].t_admit >= reqs[1].t_admit >= reqs[0].t_done
+
+
+class FakeAsyncBatch(FakeBatch):
+    """FakeBatch split into launch / wait: requests admitted between the two
+    join the next run (as with pic_batch_launch / pic_batch_wait)."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.in_flight = None
+        self.admitted_in_flight = 0
+
+    def admit(self, req):
+        if self.in_flight is not None:
+            self.admitted_in_flight += 1
+        super().admit(req)
+
+    def launch(self):
+        assert self.in_flight is None
+        self.in_flight = set(self.running)
+
+    def wait(self):
+        ids = self.in_flight
+        self.in_flight = None
+        size = sum(self.running[i][0].cfg["size"] for i in ids)
+        self.vc.t += self.dt * self.M * max(size, self.floor)
+        done = []
+        for rid in ids:
+            r, left = self.running[rid]
+            left -= self.M
+            if left <= 0:
+                del self.running[rid]
+                self.used -= r.footprint
+                done.append(r)
+            else:
+                self.running[rid][1] = left
+        return done
+
+    def run(self):
+        raise AssertionError("the overlapped loop calls launch / wait")
+
+
+def test_overlapped_admission_keeps_fifo_and_budget():
+    vc = VClock()
+    ex = FakeAsyncBatch(vc, 8, 2500)
+
+    # admission itself costs time (creating and loading a context), so
+    # requests arrive while a run is in flight
+    def on_admit(r, e):
+        vc.t += 1e-3
+
+    reqs = _requests(200, 5, rate=40.0)
+    st = serve(reqs, ex, clock=vc.clock, sleep=vc.sleep, on_admit=on_admit)
+    assert st["requests"] == len(reqs)
+    assert ex.admitted == sorted(ex.admitted)
+    assert ex.peak <= 2500
+    assert ex.admitted_in_flight > 0
+    for r in reqs:
+        assert r.arrival <= r.t_admit <= r.t_done

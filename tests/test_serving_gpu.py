@@ -52,12 +52,15 @@ def _same(a, b):
         assert np.array_equal(xa, xb) and np.array_equal(va, vb)
 
 
-@pytest.mark.parametrize("repr_", ["fp32_cell", "fp64"])
-def test_alone_and_in_the_mix_are_identical(repr_):
+@pytest.mark.parametrize("repr_,ps_per_run", [("fp32_cell", 0), ("fp64", 0),
+                                              ("fp32_cell", 150_000), ("fp64", 150_000)])
+def test_alone_and_in_the_mix_are_identical(repr_, ps_per_run):
+    # ps_per_run > 0: unequal step quotas per run (fair share), so contexts of
+    # one run leave the persistent launches at different steps
     arrivals = [0.0, 0.0, 0.0, 0.05, 0.1, 0.1, 0.3]
     mix = _requests(repr_, arrivals)
     ex = BatchExecutor(max_slots=3, repr=repr_, deposit="fixed64", steps_per_run=4,
-                       hbm_budget_bytes=64 << 30)
+                       hbm_budget_bytes=64 << 30, particle_steps_per_run=ps_per_run)
     try:
         st = serve(mix, ex)
     finally:
@@ -96,3 +99,38 @@ def test_batch_admission_respects_budget_and_slots():
         finally:
             ctx.close()
             b.close()
+
+
+def test_launch_wait_protocol():
+    reqs = _requests("fp32_cell", [0.0] * 3)
+    b = pam.Batch(4, "fp32_cell", "fixed64", 4, 64 << 30, particle_steps_per_run=100_000)
+    ctxs = []
+    try:
+        for r in reqs[:2]:
+            c = pam.Context(r.cfg)
+            r.loader(c)
+            ctxs.append((c, b.attach(c, r.steps)))
+        assert b.wait() == []                     # nothing in flight
+        b.launch()
+        with pytest.raises(pam.PicError):
+            b.launch()                            # one run at a time
+        with pytest.raises(pam.PicError):
+            b.detach(ctxs[0][1])                  # not while in flight
+        c = pam.Context(reqs[2].cfg)              # attach while in flight
+        reqs[2].loader(c)
+        ctxs.append((c, b.attach(c, reqs[2].steps)))
+        finished = set(b.wait())
+        for _ in range(1000):
+            if len(finished) == len(ctxs):
+                break
+            b.launch()
+            finished |= set(b.wait())
+        assert finished == {slot for _, slot in ctxs}
+        for c, slot in ctxs:
+            b.detach(slot)
+            alive, _, _ = c.get_counters()
+            assert alive.sum() > 0
+    finally:
+        for c, _ in ctxs:
+            c.close()
+        b.close()
