@@ -253,12 +253,13 @@ typedef struct {
   int32_t repr, deposit;    /* of every attached context */
   int32_t steps_per_run;    /* M >= 1: the most steps one pic_batch_run gives a context */
   int64_t hbm_budget_bytes; /* admission limit on the summed footprints (> 0) */
-  int64_t particle_steps_per_run; /* fair share: 0 -> every context gets M steps per
-                                     run; > 0 -> context k with n_k particles (at
-                                     attach) gets
-                                     clamp(P / (S n_k), 1, M) steps (S contexts
-                                     running), so each gets about the same GPU time
-                                     and small runs are not paced by large ones */
+  int64_t particle_steps_per_run; /* P. 0 -> every context gets M steps per run;
+                                     > 0 -> shares: context k with n_k particles
+                                     (at attach) and weight w_k gets
+                                     clamp(floor(P w_k / (W n_k)), 1, M) steps,
+                                     W the sum of the running contexts' weights
+                                     (all 1: each gets about the same GPU time
+                                     and small runs are not paced by large ones) */
   void *stream;             /* hipStream_t, or NULL for a library stream */
 } pic_batch_config;
 
@@ -277,8 +278,14 @@ void pic_batch_destroy(pic_batch *b);
  * different repr / deposit, nsteps < 1. Nothing changes on error. */
 pic_status pic_batch_attach(pic_batch *b, pic_ctx *ctx, int64_t nsteps, int32_t *slot);
 
+/* Weight of an attached context in the share of P (default 1 at attach; used
+ * from the next run on). PIC_E_INVALID: no context in the slot, weight not in
+ * (0, 1e30). A scheduler sets weights to implement its policy (e.g. a larger
+ * weight for the oldest request). */
+pic_status pic_batch_set_weight(pic_batch *b, int32_t slot, double weight);
+
 /* Advances every attached context by min(its quota, its remaining steps)
- * (quota: M, or the fair share above) and synchronises. done_slots (capacity
+ * (quota: M, or its share of P above) and synchronises. done_slots (capacity
  * max_slots, nullable) receives the slots whose steps are now all done,
  * *n_done their number. */
 pic_status pic_batch_run(pic_batch *b, int32_t *n_done, int32_t *done_slots);

@@ -1082,6 +1082,7 @@ struct pic_batch {
   std::vector<int64_t> remaining;   // per slot
   std::vector<int64_t> bytes;       // per slot footprint
   std::vector<int64_t> work;        // per slot: particles at attach (the cost of one step)
+  std::vector<double> weight;       // per slot: share of a run's particle-steps (default 1)
   std::vector<int32_t> want_sort;   // per slot: spare room ran out in the last run
   std::vector<int32_t> order;       // table entry -> slot of the run in flight
   std::vector<int32_t> quota;       // per slot: steps of the run in flight
@@ -1224,6 +1225,7 @@ pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
   b->remaining.assign(n, 0);
   b->bytes.assign(n, 0);
   b->work.assign(n, 0);
+  b->weight.assign(n, 1.0);
   b->want_sort.assign(n, 0);
   b->order.clear();
   b->quota.assign(n, 0);
@@ -1231,6 +1233,15 @@ pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
   while (run_length(b, nj - 1) < M) ++nj;
   b->exec.assign(nj, nullptr);
   *out = b;
+  return PIC_OK;
+}
+
+pic_status pic_batch_set_weight(pic_batch *b, int32_t slot, double weight) {
+  if (!b) return PIC_E_INVALID;
+  if (slot < 0 || slot >= b->cfg.max_slots || !b->ctx[slot])
+    return bfail(b, PIC_E_INVALID, "no context in this slot");
+  if (!(weight > 0.0) || !(weight < 1e30)) return bfail(b, PIC_E_INVALID, "weight must be in (0, 1e30)");
+  b->weight[slot] = weight;
   return PIC_OK;
 }
 
@@ -1247,6 +1258,7 @@ pic_status pic_batch_detach(pic_batch *b, int32_t slot) {
   b->used -= b->bytes[slot];
   b->bytes[slot] = 0;
   b->work[slot] = 0;
+  b->weight[slot] = 1.0;
   b->want_sort[slot] = 0;
   return PIC_OK;
 }
@@ -1288,6 +1300,7 @@ pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *s
   b->remaining[free_slot] = nsteps;
   b->bytes[free_slot] = fp;
   b->work[free_slot] = std::max<int64_t>(n, 1);
+  b->weight[free_slot] = 1.0;
   b->want_sort[free_slot] = 0;
   b->used += fp;
   c->batch = b;
@@ -1315,10 +1328,15 @@ pic_status pic_batch_launch(pic_batch *b) {
   }
   const int S = (int)order.size();
   if (S == 0) return PIC_OK;
-  // step quotas: M each, or an equal share of P particle-steps
+  // step quotas: M each, or a weighted share of P particle-steps
+  double wsum = 0.0;
+  for (int k : order) wsum += b->weight[k];
   for (int k : order) {
     int64_t qk = M;
-    if (P > 0) qk = std::max<int64_t>(1, std::min<int64_t>(M, P / ((int64_t)S * b->work[k])));
+    if (P > 0) {
+      const double share = (double)P * (b->weight[k] / wsum) / (double)b->work[k];
+      qk = share >= (double)M ? M : std::max<int64_t>(1, (int64_t)share);
+    }
     b->quota[k] = (int32_t)std::min<int64_t>(qk, b->remaining[k]);
   }
   std::stable_sort(order.begin(), order.end(),

@@ -80,14 +80,6 @@ __device__ __forceinline__ float two32<float>() { return 4294967296.0f; }
 template <>
 __device__ __forceinline__ double two32<double>() { return 4294967296.0; }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous run of tiles so that neighbouring tiles share its L2.
-__device__ __forceinline__ int xcd_remap(int b, int G) {
-  const int q = G >> 3, r = G & 7;
-  const int x = b & 7, k = b >> 3;
-  return x * q + (x < r ? x : r) + k;
-}
-
 __device__ __forceinline__ int32_t pack_cell(int i, int j, int k) {
   return i | (j << kCellBits) | (k << (2 * kCellBits));
 }
@@ -365,7 +357,9 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
 
   const int nt = P.ntiles;
   const bool ovf_block = block == nt;
-  const int t = ovf_block ? nt : xcd_remap(block, nt);
+  // workgroups take tiles in the order of their regions in memory, so the
+  // workgroups resident at any time stream one contiguous window of HBM
+  const int t = block;
   const int cur = P.cur, out = 1 - P.cur;
   if (threadIdx.x == 0) {
     int total = 0;
@@ -688,8 +682,11 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
 #pragma unroll
         for (int n = 0; n < 8; ++n) C[n] = (A)(chg * W[n]);
         if (local) {
+          // workgroup-scope float add on the LDS tile (an LDS atomic; the
+          // device-scope atomicAdd would go through the flat path)
 #pragma unroll
-          for (int n = 0; n < 8; ++n) atomicAdd(&sTile[idx[n]], C[n]);
+          for (int n = 0; n < 8; ++n)
+            __hip_atomic_fetch_add(&sTile[idx[n]], C[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
 #pragma unroll
           for (int n = 0; n < 8; ++n) unsafeAtomicAdd(&gRho[idx[n]], C[n]);

@@ -88,6 +88,7 @@ SIGNATURES = {
     "pic_batch_attach": (_st, [_vp, _vp, _i64, ctypes.POINTER(_i32)]),
     "pic_batch_run": (_st, [_vp, ctypes.POINTER(_i32), _vp]),
     "pic_batch_launch": (_st, [_vp]),
+    "pic_batch_set_weight": (_st, [_vp, _i32, ctypes.c_double]),
     "pic_batch_wait": (_st, [_vp, ctypes.POINTER(_i32), _vp]),
     "pic_batch_detach": (_st, [_vp, _i32]),
     "pic_batch_used_bytes": (_i64, [_vp]),
@@ -104,6 +105,15 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(there is no CPU fallback)")
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system's. Loading torch first makes the library bind to that one
+        # runtime; loading the library first would bring in a second HIP/HSA
+        # runtime, after which torch finds no GPU (and device pointers and
+        # streams could not be shared).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -429,6 +439,10 @@ class Batch:
 
     def detach(self, slot: int):
         self._check(lib().pic_batch_detach(self._h, int(slot)))
+
+    def set_weight(self, slot: int, weight: float):
+        """Share weight of an attached context (default 1)."""
+        self._check(lib().pic_batch_set_weight(self._h, int(slot), float(weight)))
 
 
 def config_from_workload(w, repr="fp32_cell", deposit="fixed64", sort_interval=0, capacity=None,

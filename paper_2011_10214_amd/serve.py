@@ -49,13 +49,29 @@ class Request:
 
 
 class BatchExecutor:
-    """Continuous batching on one GPU through pic_batch."""
+    """Continuous batching on one GPU through pic_batch.
+
+    With ``particle_steps_per_run`` > 0 every run shares that many particle-
+    steps among the running requests by weight; ``policy`` sets the weights:
+      "fair" -- all equal (each request gets about the same GPU time)
+      "head" -- the oldest running request gets the fraction ``head_share``
+                of a run, the others share the rest equally (small requests
+                still pass big ones, and the oldest request keeps most of the
+                GPU, which bounds the tail latency)
+    """
 
     def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
-                 hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0):
+                 hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0,
+                 policy: str = "fair", head_share: float = 0.5):
+        if policy not in ("fair", "head"):
+            raise ValueError(f"unknown policy {policy!r}")
+        if not 0.0 < head_share < 1.0:
+            raise ValueError("head_share must be in (0, 1)")
+        self.head_share = head_share
         self.batch = pic.Batch(max_slots, repr, deposit, steps_per_run, hbm_budget_bytes, stream,
                                particle_steps_per_run)
         self.stream = stream
+        self.policy = policy
         self.slots = {}   # slot -> (request, context)
 
     def footprint(self, req: Request) -> int:
@@ -87,6 +103,12 @@ class BatchExecutor:
 
     def launch(self) -> None:
         """Enqueues one run; admissions may proceed until wait()."""
+        if self.policy == "head" and len(self.slots) > 1:
+            head = min(self.slots, key=lambda k: (self.slots[k][0].arrival, self.slots[k][0].rid))
+            others = len(self.slots) - 1
+            wh = self.head_share / (1.0 - self.head_share) * others
+            for k in self.slots:
+                self.batch.set_weight(k, wh if k == head else 1.0)
         self.batch.launch()
 
     def wait(self) -> list:

@@ -110,3 +110,18 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pic, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError):
         pic.lib()
+
+
+def test_binding_shares_one_hip_runtime_with_torch():
+    # the binding loaded first, torch second: one HIP runtime in the process
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2011_10214_amd import pic\n"
+        "pic.lib()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+        "print(len(libs))\n" % ROOT)
+    out = subprocess.run([os.sys.executable, "-c", code], capture_output=True, text=True,
+                         check=True, timeout=300).stdout.strip().splitlines()[-1]
+    assert out == "1"

@@ -52,15 +52,18 @@ def _same(a, b):
         assert np.array_equal(xa, xb) and np.array_equal(va, vb)
 
 
-@pytest.mark.parametrize("repr_,ps_per_run", [("fp32_cell", 0), ("fp64", 0),
-                                              ("fp32_cell", 150_000), ("fp64", 150_000)])
-def test_alone_and_in_the_mix_are_identical(repr_, ps_per_run):
+@pytest.mark.parametrize("repr_,ps_per_run,policy", [("fp32_cell", 0, "fair"), ("fp64", 0, "fair"),
+                                                     ("fp32_cell", 150_000, "fair"),
+                                                     ("fp64", 150_000, "fair"),
+                                                     ("fp32_cell", 150_000, "head")])
+def test_alone_and_in_the_mix_are_identical(repr_, ps_per_run, policy):
     # ps_per_run > 0: unequal step quotas per run (fair share), so contexts of
     # one run leave the persistent launches at different steps
     arrivals = [0.0, 0.0, 0.0, 0.05, 0.1, 0.1, 0.3]
     mix = _requests(repr_, arrivals)
     ex = BatchExecutor(max_slots=3, repr=repr_, deposit="fixed64", steps_per_run=4,
-                       hbm_budget_bytes=64 << 30, particle_steps_per_run=ps_per_run)
+                       hbm_budget_bytes=64 << 30, particle_steps_per_run=ps_per_run,
+                       policy=policy)
     try:
         st = serve(mix, ex)
     finally:
@@ -111,6 +114,11 @@ def test_launch_wait_protocol():
             r.loader(c)
             ctxs.append((c, b.attach(c, r.steps)))
         assert b.wait() == []                     # nothing in flight
+        with pytest.raises(pam.PicError):
+            b.set_weight(ctxs[0][1], 0.0)         # weights must be positive
+        with pytest.raises(pam.PicError):
+            b.set_weight(3, 1.0)                  # no context in slot 3
+        b.set_weight(ctxs[0][1], 4.0)
         b.launch()
         with pytest.raises(pam.PicError):
             b.launch()                            # one run at a time
