@@ -123,11 +123,43 @@ typedef struct {
                             K >= 1 also re-plans the tile regions every K steps;
                             0 (default) only after a load or when a tile's spare
                             room runs out. Results do not depend on it. */
+  int32_t reflect;       /* bit f: box face f (0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+)
+                            reflects instead of removing (the symmetry planes of
+                            the particle setups in §3.1.3 and §5.2.2): right after
+                            the drift, a particle beyond the face is mirrored about
+                            it and its normal velocity negated, axes x, y, z in
+                            turn; one that lands exactly on a max face is put just
+                            inside. The crater's z- face (the terrain) cannot. */
   int64_t capacity[PIC_MAX_SPECIES]; /* max particles per species (device memory is
                                         reserved for this many plus per-tile spare
                                         room and an overflow list, double-buffered) */
   void *stream;          /* hipStream_t to enqueue on, or NULL for a library stream */
 } pic_config;
+
+/* Ambient particles injected through box faces every step (the particle
+ * setups of §3.1.3 and §5.2.2 inject the ambient plasma at the open faces; the
+ * paper gives no method). Per step, after every particle was pushed and before
+ * the deposit, for each species s and injecting face: a ghost slab of
+ * thickness L = min(1, dt (max(0, u.n_in) + 6 vth)) cells outside each face
+ * cell holds floor(n L + U) ghost particles (n = density h^3 per cell, U a
+ * uniform draw) placed uniformly in the slab, with velocities u + vth N(0,1)
+ * per component (Marsaglia's polar method); each moves dt and is injected if it
+ * ends inside the box, rounded to the context's representation; it then meets
+ * the object test like a pushed particle (collected at once, or kept and
+ * deposited). Random numbers: SplitMix64 as a counter-based generator keyed by
+ * (seed, step index, species, face, face cell, ghost); the step index counts
+ * pic_step steps from pic_create. Only correctly rounded operations are used
+ * (ln by an atanh series), so the injected particles are fully determined by
+ * the inputs. Ghosts faster than u.n_in + 6 vth toward the face are not
+ * generated (a relative flux deficit below 1e-9). Injected particles take the
+ * id -1 in species that carry ids. */
+typedef struct {
+  int32_t faces;                    /* bit f: face f injects; 0 turns injection off */
+  uint64_t seed;
+  double density[PIC_MAX_SPECIES];  /* ambient particles per unit volume (>= 0) */
+  double vth[PIC_MAX_SPECIES];      /* thermal speed per component (>= 0) */
+  double drift[PIC_MAX_SPECIES][3]; /* drift velocity */
+} pic_injection;
 
 /* Creates a context: validates cfg and allocates device memory for the mesh
  * (node E, rho), tallies and per-species particle buffers of cfg->capacity.
@@ -195,6 +227,18 @@ pic_status pic_get_surface_charge(pic_ctx *ctx, int64_t nbins, double *charge, i
  * each nullable): particles alive, collected at the object, and escaped
  * through face f (escaped[f*n_species + s]). Synchronises. */
 pic_status pic_get_counters(pic_ctx *ctx, int64_t *alive, int64_t *absorbed, int64_t *escaped);
+
+/* Sets (inj non-NULL with faces != 0) or clears (NULL or faces == 0) the
+ * injection of ambient particles, from the next pic_step on (copied; the
+ * caller keeps inj). PIC_E_INVALID: a face bit beyond 5, an injecting face
+ * that reflects, the crater's z- face, a negative or non-finite density,
+ * thermal speed or drift; nothing changes on error. The particles must fit the
+ * species' capacity (PIC_E_NOMEM at the next sync otherwise). */
+pic_status pic_set_injection(pic_ctx *ctx, const pic_injection *inj);
+
+/* Synchronises; injected[s] (n_species values) receives the particles
+ * injected into species s since pic_create (collected at once included). */
+pic_status pic_get_injected(pic_ctx *ctx, int64_t *injected);
 
 /* Copies the alive particles of one species to host arrays of capacity cap
  * (physical positions and half-step velocities as doubles; ids nullable, and

@@ -45,6 +45,9 @@ class _Cfg(ctypes.Structure):
         ("obj_kind", ctypes.c_int32), ("center", ctypes.c_double * 3), ("radius", ctypes.c_double),
         ("z_flat", ctypes.c_double), ("rim_radius", ctypes.c_double), ("depth", ctypes.c_double),
         ("repr", ctypes.c_int32), ("deposit", ctypes.c_int32),
+        ("reflect", ctypes.c_int32), ("inj_faces", ctypes.c_int32), ("inj_seed", ctypes.c_uint64),
+        ("inj_density", ctypes.c_double * 4), ("inj_vth", ctypes.c_double * 4),
+        ("inj_drift", ctypes.c_double * 12),
     ]
 
 
@@ -59,6 +62,8 @@ class _Out(ctypes.Structure):
         ("x", _dp), ("y", _dp), ("z", _dp), ("vx", _dp), ("vy", _dp), ("vz", _dp),
         ("fate", _i32p), ("where", _i32p), ("when", _i32p),
         ("rho", _dp), ("rho_fixed", _i64p), ("tally", _i64p), ("escaped", _i64p),
+        ("cap", ctypes.c_int64), ("n_out", ctypes.c_int64), ("species", _i32p),
+        ("injected", _i64p),
     ]
 
 
@@ -79,6 +84,15 @@ def lib():
         L.orc_gather_f64.argtypes = [ctypes.c_int32] * 3 + [_dp] * 3 + [_i32p, _dp, _dp]
         L.orc_fixed_contrib_f64.argtypes = [ctypes.c_double, _dp, _i64p]
         L.orc_fixed_contrib_f32.argtypes = [ctypes.c_float, _fp, _i64p]
+        L.orc_splitmix_draw.restype = ctypes.c_uint64
+        L.orc_splitmix_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_inj_uniform.restype = ctypes.c_double
+        L.orc_inj_uniform.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_uint64]
+        L.orc_ln.restype = ctypes.c_double
+        L.orc_ln.argtypes = [ctypes.c_double]
+        L.orc_normals3.argtypes = [ctypes.c_uint64, _dp]
         L.orc_object_hit.restype = ctypes.c_int32
         L.orc_object_hit.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double]
@@ -106,6 +120,13 @@ class Problem:
     depth: float = 0.0
     repr: str = "fp64"
     deposit: str = "fixed64"
+    # global boundaries: face masks (bit f: face f = x-, x+, y-, y+, z-, z+)
+    reflect: int = 0
+    inj_faces: int = 0
+    inj_seed: int = 0
+    inj_density: list = None   # per species, particles per unit volume
+    inj_vth: list = None
+    inj_drift: list = None     # per species, 3 components
 
     @property
     def n_species(self):
@@ -135,7 +156,38 @@ class Problem:
         c.z_flat, c.rim_radius, c.depth = self.z_flat, self.rim_radius, self.depth
         c.repr = REPR[self.repr]
         c.deposit = DEPOSIT[self.deposit]
+        c.reflect = int(self.reflect)
+        c.inj_faces = int(self.inj_faces)
+        c.inj_seed = int(self.inj_seed) & (2 ** 64 - 1)
+        for s in range(self.n_species):
+            c.inj_density[s] = self.inj_density[s] if self.inj_density else 0.0
+            c.inj_vth[s] = self.inj_vth[s] if self.inj_vth else 0.0
+            for d in range(3):
+                c.inj_drift[3 * s + d] = self.inj_drift[s][d] if self.inj_drift else 0.0
         return c
+
+    def injection_bound(self, nsteps: int) -> int:
+        """Most particles that nsteps of injection can add (each face cell gets
+        at most floor(n L) + 1 ghosts per step and species)."""
+        if not self.inj_faces:
+            return 0
+        n = (self.nx, self.ny, self.nz)
+        tot = 0
+        for s in range(self.n_species):
+            dens = self.inj_density[s] if self.inj_density else 0.0
+            if dens <= 0:
+                continue
+            ncell = dens * (self.h * self.h * self.h)
+            vth = self.inj_vth[s] / self.h
+            for f in range(6):
+                if not (self.inj_faces >> f) & 1:
+                    continue
+                ax = f // 2
+                un = (self.inj_drift[s][ax] / self.h) * (-1.0 if f & 1 else 1.0)
+                L = min(1.0, self.dt * (max(0.0, un) + 6.0 * vth))
+                cells = n[0] * n[1] * n[2] // n[ax]
+                tot += cells * (int(ncell * L) + 1)
+        return tot * int(nsteps)
 
 
 class OracleError(RuntimeError):
@@ -153,6 +205,8 @@ class Result:
     rho_fixed: np.ndarray  # None unless fixed-point mode
     tally: np.ndarray      # (nbins, n_species)
     escaped: np.ndarray    # (6, n_species)
+    species: np.ndarray = None   # (n_out,) species of every particle (loaded, then injected)
+    injected: np.ndarray = None  # (n_species,) particles injected
     extra: dict = field(default_factory=dict)
 
     def charge(self, prob: Problem) -> np.ndarray:
@@ -179,10 +233,13 @@ def run(prob: Problem, species, x, v, E, nsteps: int) -> Result:
     for e in E:
         if e.size != prob.nodes:
             raise ValueError("node field has the wrong size")
-    ox = [np.empty(n) for _ in range(6)]
-    fate = np.empty(n, np.int32)
-    where = np.empty(n, np.int32)
-    when = np.empty(n, np.int32)
+    cap = n + prob.injection_bound(nsteps)
+    ox = [np.empty(cap) for _ in range(6)]
+    fate = np.empty(cap, np.int32)
+    where = np.empty(cap, np.int32)
+    when = np.empty(cap, np.int32)
+    spo = np.empty(cap, np.int32)
+    inj = np.zeros(prob.n_species, np.int64)
     rho = np.empty(prob.nodes)
     rho_fixed = np.empty(prob.nodes, np.int64) if prob.deposit == "fixed64" else None
     tally = np.zeros((prob.nbins, prob.n_species), np.int64)
@@ -197,14 +254,19 @@ def run(prob: Problem, species, x, v, E, nsteps: int) -> Result:
     out.rho_fixed = rho_fixed.ctypes.data_as(_i64p) if rho_fixed is not None else None
     out.tally = tally.ctypes.data_as(_i64p)
     out.escaped = esc.ctypes.data_as(_i64p)
+    out.cap = cap
+    out.species = spo.ctypes.data_as(_i32p)
+    out.injected = inj.ctypes.data_as(_i64p)
     cfg = prob.cstruct()
     rc = L.orc_run(ctypes.byref(cfg), n, sp.ctypes.data_as(_i32p),
                    *[c.ctypes.data_as(_dp) for c in cols], *[e.ctypes.data_as(_dp) for e in E],
                    int(nsteps), ctypes.byref(out))
     if rc != 0:
         raise OracleError(f"oracle returned {rc}")
-    return Result(x=np.stack(ox[:3], 1), v=np.stack(ox[3:], 1), fate=fate, where=where,
-                  when=when, rho=rho, rho_fixed=rho_fixed, tally=tally, escaped=esc)
+    k = int(out.n_out)
+    return Result(x=np.stack([a[:k] for a in ox[:3]], 1), v=np.stack([a[:k] for a in ox[3:]], 1),
+                  fate=fate[:k], where=where[:k], when=when[:k], rho=rho, rho_fixed=rho_fixed,
+                  tally=tally, escaped=esc, species=spo[:k], injected=inj)
 
 
 def weights(f, dtype=np.float64) -> np.ndarray:
@@ -243,3 +305,22 @@ def fixed_contrib(chg, W, dtype=np.float64) -> np.ndarray:
 def object_hit(prob: Problem, x, y, z) -> int:
     cfg = prob.cstruct()
     return int(lib().orc_object_hit(ctypes.byref(cfg), float(x), float(y), float(z)))
+
+
+def splitmix_draw(key: int, d: int) -> int:
+    """Raw 64-bit draw d of a key (the SplitMix64 output for state key + (d+1) gamma)."""
+    return int(lib().orc_splitmix_draw(key & (2 ** 64 - 1), d))
+
+
+def inj_uniform(seed, step, s, f, cell, j, d) -> float:
+    return float(lib().orc_inj_uniform(seed & (2 ** 64 - 1), step, s, f, cell, j, d))
+
+
+def ln(x: float) -> float:
+    return float(lib().orc_ln(float(x)))
+
+
+def normals3(key: int) -> np.ndarray:
+    z = np.empty(3)
+    lib().orc_normals3(key & (2 ** 64 - 1), z.ctypes.data_as(_dp))
+    return z

@@ -41,6 +41,28 @@
 //      C[7] = llrint(chg * 2^32) - sum_{n<7} C[n], added to int64 rhoF;
 //      output rho = rhoF * 2^-32 / h^3.
 //
+// Global boundaries (the particle setups of §3.1.3 and §5.2.2):
+//   * reflection: a face in the `reflect` mask mirrors a particle that crossed
+//     it (position about the face, normal velocity negated), right after the
+//     drift and before the box / object tests, axes x, y, z in turn;
+//   * injection: faces in `inj_faces` feed ambient particles of a drifting
+//     Maxwellian (density n, thermal speed vth, drift u per species) each step,
+//     after every loaded particle was pushed and before the deposit. The paper
+//     gives no method; this oracle uses a ghost layer: per face cell, a slab of
+//     thickness L = min(1, dt (max(0, u.n_in) + 6 vth)) outside the face holds
+//     floor(n L + U) ghost particles uniform in the slab with velocities drawn
+//     from the drifting Maxwellian; each moves dt (g' = fma(v, dt, g)) and is
+//     injected if it ends inside the box (the terrain's z < 0 counts as inside
+//     and is then collected), rounded to the form's representation and tested
+//     against the object like a pushed particle; it carries v as its half-step
+//     velocity.
+//   Random numbers: SplitMix64 (Steele, Lea and Flood, 2014) used as a
+//   counter-based generator keyed by (seed, step, species, face, face cell,
+//   ghost); uniforms (x >> 11) 2^-53; normals by Marsaglia's polar method with
+//   ln computed by ln x = e ln 2 + 2 atanh((m - 1)/(m + 1)), m in [sqrt(1/2),
+//   sqrt(2)), atanh by its Taylor series to s^23 -- only correctly rounded
+//   operations, so that any implementation of the same steps gives the same bits.
+//
 // The arithmetic type T is double for the FP64 form and float for the two FP32
 // mirrors (absolute positions; int32 cell + float offset). The same expression
 // order is used in every form. Build with -ffp-contract=off so that no
@@ -59,7 +81,7 @@ constexpr int kMaxSpecies = 4;
 enum { REPR_FP64 = 0, REPR_FP32_ABS = 1, REPR_FP32_CELL = 2 };
 enum { DEP_FIXED64 = 0, DEP_FP32 = 1, DEP_FP64 = 2 };
 enum { OBJ_NONE = 0, OBJ_SPHERE = 1, OBJ_CRATER = 2 };
-enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_RANGE = -5 };
+enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_CAPACITY = -2, ORC_E_RANGE = -5 };
 
 }  // namespace
 
@@ -78,6 +100,12 @@ typedef struct {
   double z_flat, rim_radius, depth;  // crater: flat ground height, bowl radius, depth
   int32_t repr;      // 0 FP64, 1 FP32 absolute, 2 FP32 cell-relative
   int32_t deposit;   // 0 fixed-point int64, 1 FP32 sum, 2 FP64 sum
+  int32_t reflect;   // bit f: box face f (x-, x+, y-, y+, z-, z+) reflects
+  int32_t inj_faces; // bit f: box face f injects ambient particles
+  uint64_t inj_seed;
+  double inj_density[kMaxSpecies];  // particles per unit volume
+  double inj_vth[kMaxSpecies];      // thermal speed per component
+  double inj_drift[kMaxSpecies][3];
 } orc_config;
 
 typedef struct {
@@ -89,6 +117,11 @@ typedef struct {
   int64_t *rho_fixed;                // nodes: fixed-point rho (fixed mode), may be null
   int64_t *tally;                    // nbins * n_species: absorbed counts [bin][s]
   int64_t *escaped;                  // 6 * n_species: escaped counts [face][s]
+  int64_t cap;                       // capacity of the per-particle arrays (>= n)
+  int64_t n_out;                     // particles written: the n loaded, then the
+                                     // injected ones in injection order
+  int32_t *species;                  // cap: species of every written particle
+  int64_t *injected;                 // n_species: particles injected (incl. collected)
 } orc_out;
 
 }  // extern "C"
@@ -288,6 +321,179 @@ int box_face_cell(const Mesh& m, const int32_t i[3], bool crater) {
   return -1;
 }
 
+// ---- global boundaries: random numbers -------------------------------------------
+
+constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ULL;
+
+// SplitMix64 output function (the generator's state increment is kGolden).
+uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// Key of one ghost particle (j >= 1) or of a face cell's count draw (j = 0).
+uint64_t inj_key(uint64_t seed, int32_t step, int s, int f, int64_t cell, int64_t j) {
+  uint64_t k = sm_mix(seed + kGolden);
+  k = sm_mix(k ^ (uint64_t)(uint32_t)step);
+  k = sm_mix(k ^ (uint64_t)(s * 8 + f));
+  k = sm_mix(k ^ (uint64_t)cell);
+  return sm_mix(k ^ (uint64_t)j);
+}
+
+// Draw d (0, 1, ...) of a key: uniform in [0, 1) on the 2^-53 grid.
+double inj_uniform(uint64_t key, uint64_t d) {
+  return (double)(sm_mix(key + (d + 1) * kGolden) >> 11) * 0x1.0p-53;
+}
+
+// Natural logarithm of x > 0 (finite): x = m 2^e with m in [sqrt(1/2), sqrt(2)),
+// ln x = e ln 2 + 2 atanh(s), s = (m - 1)/(m + 1), |s| < 0.1716, atanh by its
+// Taylor series s (1 + s^2/3 + s^4/5 + ... + s^22/23) in Horner form.
+double ln_series(double x) {
+  int e = 0;
+  double m = std::frexp(x, &e);  // m in [0.5, 1)
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double t = s * s;
+  double p = 1.0 / 23.0;
+  for (int k = 21; k >= 1; k -= 2) p = p * t + 1.0 / (double)k;
+  return (double)e * 0.69314718055994530942 + 2.0 * s * p;
+}
+
+// Three standard normals by Marsaglia's polar method; *d counts the draws used.
+void normals3(uint64_t key, uint64_t* d, double z[3]) {
+  int got = 0;
+  for (int attempt = 0; attempt < 64 && got < 3; ++attempt) {
+    const double a = 2.0 * inj_uniform(key, (*d)++) - 1.0;
+    const double b = 2.0 * inj_uniform(key, (*d)++) - 1.0;
+    const double r = a * a + b * b;
+    if (!(r > 0.0 && r < 1.0)) continue;
+    const double f = std::sqrt(-2.0 * ln_series(r) / r);
+    z[got++] = a * f;
+    if (got < 3) z[got++] = b * f;
+  }
+  while (got < 3) z[got++] = 0.0;  // 64 rejected pairs: probability 0.2146^64
+}
+
+// Injection geometry of one face in cell units.
+struct InjFace {
+  int f, axis, t1, t2;  // face, its normal axis, the two tangential axes
+  bool max_side;        // face at n[axis] (else at 0)
+  int64_t cells;        // n[t1] * n[t2]
+};
+
+InjFace inj_face(const int32_t n[3], int f) {
+  InjFace F;
+  F.f = f;
+  F.axis = f / 2;
+  F.max_side = (f & 1) != 0;
+  F.t1 = F.axis == 0 ? 1 : 0;
+  F.t2 = F.axis == 2 ? 1 : 2;
+  F.cells = (int64_t)n[F.t1] * n[F.t2];
+  return F;
+}
+
+// Per-species injection constants in cell units (from physical inputs).
+struct InjSpecies {
+  double ncell;   // particles per cell volume
+  double vth;     // cell units per unit time
+  double u[3];
+};
+
+InjSpecies inj_species(const orc_config& c, int s) {
+  InjSpecies I;
+  const double h3 = c.h * c.h * c.h;
+  I.ncell = c.inj_density[s] * h3;
+  I.vth = c.inj_vth[s] / c.h;
+  for (int d = 0; d < 3; ++d) I.u[d] = c.inj_drift[s][d] / c.h;
+  return I;
+}
+
+// Ghost-slab thickness of a face for a species.
+double inj_thickness(const InjSpecies& I, const InjFace& F, double dt) {
+  const double un = F.max_side ? -I.u[F.axis] : I.u[F.axis];
+  double L = dt * ((un > 0.0 ? un : 0.0) + 6.0 * I.vth);
+  if (L > 1.0) L = 1.0;
+  return L;
+}
+
+// Visits every ghost particle of one step that ends inside the box, in the
+// order species, face, face cell, ghost: emit(s, g[3], v[3]) in cell units.
+template <class Emit>
+void inject_ghosts(const orc_config& cfg, const int32_t n[3], int32_t step, Emit emit) {
+  for (int s = 0; s < cfg.n_species; ++s) {
+    const InjSpecies I = inj_species(cfg, s);
+    if (!(I.ncell > 0.0)) continue;
+    for (int f = 0; f < 6; ++f) {
+      if (!((cfg.inj_faces >> f) & 1)) continue;
+      const InjFace F = inj_face(n, f);
+      const double L = inj_thickness(I, F, cfg.dt);
+      const double mean = I.ncell * L;
+      for (int64_t cell = 0; cell < F.cells; ++cell) {
+        const int64_t a = cell % n[F.t1], b = cell / n[F.t1];
+        const int64_t k = (int64_t)std::floor(mean + inj_uniform(inj_key(cfg.inj_seed, step, s, f, cell, 0), 0));
+        for (int64_t j = 1; j <= k; ++j) {
+          const uint64_t key = inj_key(cfg.inj_seed, step, s, f, cell, j);
+          double g[3], v[3], z[3];
+          g[F.t1] = (double)a + inj_uniform(key, 0);
+          g[F.t2] = (double)b + inj_uniform(key, 1);
+          const double depth = L * (1.0 - inj_uniform(key, 2));
+          g[F.axis] = F.max_side ? (double)n[F.axis] + depth : -depth;
+          uint64_t d = 3;
+          normals3(key, &d, z);
+          for (int q = 0; q < 3; ++q) v[q] = I.u[q] + I.vth * z[q];
+          for (int q = 0; q < 3; ++q) g[q] = std::fma(v[q], cfg.dt, g[q]);
+          emit(s, g, v);
+        }
+      }
+    }
+  }
+}
+
+// Mirror about a reflecting face; absolute positions (cell units).
+template <class T>
+void reflect_abs(const orc_config& cfg, const int32_t n[3], T g[3], T u[3]) {
+  for (int d = 0; d < 3; ++d) {
+    if (((cfg.reflect >> (2 * d)) & 1) && g[d] < T(0)) {
+      g[d] = -g[d];
+      u[d] = -u[d];
+    }
+    if (((cfg.reflect >> (2 * d + 1)) & 1) && g[d] >= (T)n[d]) {
+      g[d] = (T)(2 * n[d]) - g[d];
+      if (g[d] >= (T)n[d]) g[d] = std::nextafter((T)n[d], T(0));
+      u[d] = -u[d];
+    }
+  }
+}
+
+// Mirror about a reflecting face; cell-relative form (cell i, offset o).
+void reflect_cell(const orc_config& cfg, const int32_t n[3], int32_t i[3], float o[3], float u[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const bool lo = ((cfg.reflect >> (2 * d)) & 1) && i[d] < 0;
+    const bool hi = ((cfg.reflect >> (2 * d + 1)) & 1) && i[d] >= n[d];
+    if (!lo && !hi) continue;
+    const int32_t m = lo ? 0 : 2 * n[d];  // position -> m - position
+    if (o[d] == 0.0f) {
+      i[d] = m - i[d];
+    } else {
+      i[d] = m - i[d] - 1;
+      o[d] = 1.0f - o[d];
+      if (o[d] == 1.0f) {
+        o[d] = 0.0f;
+        i[d] += 1;
+      }
+    }
+    if (hi && i[d] >= n[d]) {  // exactly on the face: just inside
+      i[d] = n[d] - 1;
+      o[d] = std::nextafter(1.0f, 0.0f);
+    }
+    u[d] = -u[d];
+  }
+}
+
 // ---- deposit -----------------------------------------------------------------
 
 struct RhoAcc {
@@ -368,18 +574,39 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
       P.u[d][p] = (T)(vin[d][p] / cfg.h);
     }
   }
+  std::vector<int32_t> spv(sp, sp + n);
   Book B;
   B.fate.assign(n, 0);
   B.where.assign(n, -1);
   B.when.assign(n, -1);
   B.tally.assign(nbins * ns, 0);
   B.escaped.assign(6 * ns, 0);
+  std::vector<int64_t> injected(ns, 0);
   RhoAcc rho;
   rho.mode = cfg.deposit;
 
+  // an injected particle (cell units, FP64) in this form's arithmetic
+  auto inject = [&](int32_t step) {
+    inject_ghosts(cfg, M.n, step, [&](int s, const double gd[3], const double vd[3]) {
+      const T g[3] = {(T)gd[0], (T)gd[1], (T)gd[2]};
+      if (box_face_abs(M, g, crater) >= 0) return;  // did not enter the box
+      injected[s] += 1;
+      for (int d = 0; d < 3; ++d) {
+        P.g[d].push_back(g[d]);
+        P.u[d].push_back((T)vd[d]);
+      }
+      spv.push_back(s);
+      const int32_t bin = object_hit_abs(G, M, g);
+      B.fate.push_back(bin >= 0 ? 2 : 0);
+      B.where.push_back(bin);
+      B.when.push_back(bin >= 0 ? step : -1);
+      if (bin >= 0) B.tally[(int64_t)bin * ns + s] += 1;
+    });
+  };
+
   auto deposit_all = [&]() {
     rho.reset(nodes);
-    for (int64_t p = 0; p < n; ++p) {
+    for (int64_t p = 0; p < (int64_t)spv.size(); ++p) {
       if (B.fate[p] != 0) continue;
       T g[3] = {P.g[0][p], P.g[1][p], P.g[2][p]};
       int32_t i[3];
@@ -392,14 +619,15 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
       weights(f, W);
       int64_t idx[8];
       corners(M, i, idx);
-      rho.add(idx, W, S[sp[p]].chg);
+      rho.add(idx, W, S[spv[p]].chg);
     }
   };
 
   for (int32_t step = 0; step < nsteps; ++step) {
-    for (int64_t p = 0; p < n; ++p) {
+    const int64_t np = (int64_t)spv.size();
+    for (int64_t p = 0; p < np; ++p) {
       if (B.fate[p] != 0) continue;
-      const int s = sp[p];
+      const int s = spv[p];
       T g[3] = {P.g[0][p], P.g[1][p], P.g[2][p]};
       T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
       int32_t i[3];
@@ -418,6 +646,7 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
       for (int d = 0; d < 3; ++d) g[d] = fma_t(u[d], dt, g[d]);
       const double gd[3] = {(double)g[0], (double)g[1], (double)g[2]};
       if (!finite3(gd)) return ORC_E_RANGE;
+      if (cfg.reflect) reflect_abs(cfg, M.n, g, u);
       for (int d = 0; d < 3; ++d) {
         P.g[d][p] = g[d];
         P.u[d][p] = u[d];
@@ -438,12 +667,19 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
         B.tally[(int64_t)bin * ns + s] += 1;
       }
     }
+    if (cfg.inj_faces) inject(step);
     deposit_all();
   }
   if (nsteps == 0) deposit_all();
 
   // outputs
-  for (int64_t p = 0; p < n; ++p) {
+  const int64_t nout = (int64_t)spv.size();
+  if (nout > out->cap) return ORC_E_CAPACITY;
+  out->n_out = nout;
+  for (int s = 0; s < ns; ++s)
+    if (out->injected) out->injected[s] = injected[s];
+  for (int64_t p = 0; p < nout; ++p) {
+    if (out->species) out->species[p] = spv[p];
     out->x[p] = cfg.origin[0] + (double)P.g[0][p] * cfg.h;
     out->y[p] = cfg.origin[1] + (double)P.g[1][p] * cfg.h;
     out->z[p] = cfg.origin[2] + (double)P.g[2][p] * cfg.h;
@@ -511,18 +747,49 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
       P.u[d][p] = (T)(vin[d][p] / cfg.h);
     }
   }
+  std::vector<int32_t> spv(sp, sp + n);
   Book B;
   B.fate.assign(n, 0);
   B.where.assign(n, -1);
   B.when.assign(n, -1);
   B.tally.assign(nbins * ns, 0);
   B.escaped.assign(6 * ns, 0);
+  std::vector<int64_t> injected(ns, 0);
   RhoAcc rho;
   rho.mode = cfg.deposit;
 
+  // an injected particle (cell units, FP64) in the cell-relative form
+  auto inject = [&](int32_t step) {
+    inject_ghosts(cfg, M.n, step, [&](int s, const double gd[3], const double vd[3]) {
+      int32_t i[3];
+      T o[3];
+      for (int d = 0; d < 3; ++d) {
+        i[d] = (int32_t)std::floor(gd[d]);
+        o[d] = (T)(gd[d] - (double)i[d]);
+        if (o[d] == 1.0f) {
+          o[d] = 0.0f;
+          i[d] += 1;
+        }
+      }
+      if (box_face_cell(M, i, crater) >= 0) return;  // did not enter the box
+      injected[s] += 1;
+      for (int d = 0; d < 3; ++d) {
+        P.i[d].push_back(i[d]);
+        P.o[d].push_back(o[d]);
+        P.u[d].push_back((T)vd[d]);
+      }
+      spv.push_back(s);
+      const int32_t bin = object_hit_cell(G, M, i, o);
+      B.fate.push_back(bin >= 0 ? 2 : 0);
+      B.where.push_back(bin);
+      B.when.push_back(bin >= 0 ? step : -1);
+      if (bin >= 0) B.tally[(int64_t)bin * ns + s] += 1;
+    });
+  };
+
   auto deposit_all = [&]() {
     rho.reset(nodes);
-    for (int64_t p = 0; p < n; ++p) {
+    for (int64_t p = 0; p < (int64_t)spv.size(); ++p) {
       if (B.fate[p] != 0) continue;
       const int32_t i[3] = {P.i[0][p], P.i[1][p], P.i[2][p]};
       const T f[3] = {P.o[0][p], P.o[1][p], P.o[2][p]};
@@ -530,14 +797,15 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
       weights(f, W);
       int64_t idx[8];
       corners(M, i, idx);
-      rho.add(idx, W, S[sp[p]].chg);
+      rho.add(idx, W, S[spv[p]].chg);
     }
   };
 
   for (int32_t step = 0; step < nsteps; ++step) {
-    for (int64_t p = 0; p < n; ++p) {
+    const int64_t np = (int64_t)spv.size();
+    for (int64_t p = 0; p < np; ++p) {
       if (B.fate[p] != 0) continue;
-      const int s = sp[p];
+      const int s = spv[p];
       int32_t i[3] = {P.i[0][p], P.i[1][p], P.i[2][p]};
       T o[3] = {P.o[0][p], P.o[1][p], P.o[2][p]};
       T u[3] = {P.u[0][p], P.u[1][p], P.u[2][p]};
@@ -561,6 +829,7 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
         o[d] = op;
         i[d] += (int32_t)sh;
       }
+      if (cfg.reflect) reflect_cell(cfg, M.n, i, o, u);
       for (int d = 0; d < 3; ++d) {
         P.i[d][p] = i[d];
         P.o[d][p] = o[d];
@@ -582,11 +851,18 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
         B.tally[(int64_t)bin * ns + s] += 1;
       }
     }
+    if (cfg.inj_faces) inject(step);
     deposit_all();
   }
   if (nsteps == 0) deposit_all();
 
-  for (int64_t p = 0; p < n; ++p) {
+  const int64_t nout = (int64_t)spv.size();
+  if (nout > out->cap) return ORC_E_CAPACITY;
+  out->n_out = nout;
+  for (int s = 0; s < ns; ++s)
+    if (out->injected) out->injected[s] = injected[s];
+  for (int64_t p = 0; p < nout; ++p) {
+    if (out->species) out->species[p] = spv[p];
     out->x[p] = cfg.origin[0] + ((double)P.i[0][p] + (double)P.o[0][p]) * cfg.h;
     out->y[p] = cfg.origin[1] + ((double)P.i[1][p] + (double)P.o[1][p]) * cfg.h;
     out->z[p] = cfg.origin[2] + ((double)P.i[2][p] + (double)P.o[2][p]) * cfg.h;
@@ -621,6 +897,13 @@ bool valid(const orc_config& c, int64_t n, const int32_t* sp, const double* cons
   if (c.obj_kind == OBJ_CRATER && !(c.depth > 0)) return false;
   for (int s = 0; s < c.n_species; ++s)
     if (!(c.m[s] > 0)) return false;
+  if ((c.reflect | c.inj_faces) & ~63) return false;
+  if (c.reflect & c.inj_faces) return false;             // a face reflects or injects
+  if (c.obj_kind == OBJ_CRATER && ((c.reflect | c.inj_faces) & 16)) return false;  // terrain
+  for (int s = 0; s < c.n_species && c.inj_faces; ++s)
+    if (!(c.inj_density[s] >= 0) || !(c.inj_vth[s] >= 0) || !std::isfinite(c.inj_drift[s][0]) ||
+        !std::isfinite(c.inj_drift[s][1]) || !std::isfinite(c.inj_drift[s][2]))
+      return false;
   const int32_t nn[3] = {c.nx, c.ny, c.nz};
   for (int64_t p = 0; p < n; ++p) {
     if (sp[p] < 0 || sp[p] >= c.n_species) return false;
@@ -638,8 +921,9 @@ extern "C" {
 
 // Runs nsteps PIC steps on n particles (species index sp[p]); nsteps == 0 only
 // deposits the loaded positions. Velocities are those at t - dt/2. Node fields
-// are (nx+1)(ny+1)(nz+1) values, x fastest. Returns 0, -1 (invalid input) or
-// -5 (a non-finite or runaway position).
+// are (nx+1)(ny+1)(nz+1) values, x fastest. Returns 0, -1 (invalid input), -2
+// (more particles than out->cap after injection) or -5 (a non-finite or
+// runaway position).
 int orc_run(const orc_config* cfg, int64_t n, const int32_t* sp, const double* x,
             const double* y, const double* z, const double* vx, const double* vy,
             const double* vz, const double* Ex, const double* Ey, const double* Ez,
@@ -647,7 +931,8 @@ int orc_run(const orc_config* cfg, int64_t n, const int32_t* sp, const double* x
   const double* xin[3] = {x, y, z};
   const double* vin[3] = {vx, vy, vz};
   const double* Ein[3] = {Ex, Ey, Ez};
-  if (!cfg || !out || nsteps < 0 || n < 0 || !valid(*cfg, n, sp, xin)) return ORC_E_INVALID;
+  if (!cfg || !out || nsteps < 0 || n < 0 || out->cap < n || !valid(*cfg, n, sp, xin))
+    return ORC_E_INVALID;
   if (cfg->repr == REPR_FP64) return run_abs<double>(*cfg, n, sp, xin, vin, Ein, nsteps, out);
   if (cfg->repr == REPR_FP32_ABS) return run_abs<float>(*cfg, n, sp, xin, vin, Ein, nsteps, out);
   return run_cell(*cfg, n, sp, xin, vin, Ein, nsteps, out);
@@ -672,6 +957,18 @@ void orc_gather_f64(int32_t nx, int32_t ny, int32_t nz, const double* Ex, const 
 
 void orc_fixed_contrib_f64(double chg, const double W[8], int64_t C[8]) { fixed_contrib(chg, W, C); }
 void orc_fixed_contrib_f32(float chg, const float W[8], int64_t C[8]) { fixed_contrib(chg, W, C); }
+
+// Pieces of the boundary source, exposed for the pins.
+uint64_t orc_splitmix_draw(uint64_t key, uint64_t d) { return sm_mix(key + (d + 1) * kGolden); }
+double orc_inj_uniform(uint64_t seed, int32_t step, int32_t s, int32_t f, int64_t cell, int64_t j,
+                       uint64_t d) {
+  return inj_uniform(inj_key(seed, step, s, f, cell, j), d);
+}
+double orc_ln(double x) { return ln_series(x); }
+void orc_normals3(uint64_t key, double z[3]) {
+  uint64_t d = 0;
+  normals3(key, &d, z);
+}
 
 // Object predicate at one point (physical units), in the arithmetic of `repr`.
 // Returns the bin when the point is absorbed, else -1.

@@ -101,6 +101,9 @@ const char *validate_config(const pic_config *c) {
   if (c->repr < 0 || c->repr > 2) return "repr must be a pic_repr";
   if (c->deposit < 0 || c->deposit > 2) return "deposit must be a pic_deposit";
   if (c->sort_interval < 0 || c->sort_interval > 1000000) return "sort_interval must be 0..1e6";
+  if (c->reflect & ~63) return "reflect: only bits 0..5 (the six box faces)";
+  if (c->object.kind == PIC_OBJ_CRATER && (c->reflect & 16))
+    return "reflect: the crater's z- face is the terrain";
   const pic_object &o = c->object;
   if (o.kind < 0 || o.kind > 2) return "object.kind must be a pic_object_kind";
   if (o.kind == PIC_OBJ_SPHERE) {
@@ -203,6 +206,10 @@ struct pic_ctx {
   std::vector<hipEvent_t> event_pool;
   pic_profile acc{};
   pic_batch *batch = nullptr;  // attached to a batch
+  bool inj_on = false;          // ambient particles are injected each step
+  pic_injection inj{};
+  int64_t step_index = 0;       // pic_step steps since creation (injection key)
+  int64_t *injected = nullptr;  // device [ns]: particles injected
 };
 
 namespace {
@@ -371,6 +378,7 @@ StepParams step_params(pic_ctx *c) {
   P.ntz = L.ntz;
   P.ntiles = L.ntiles;
   P.has_ids = ids_mask(c);
+  P.reflect = c->cfg.reflect;
   const bool f64 = c->cfg.repr == PIC_REPR_FP64;
   for (int s = 0; s < L.ns; ++s) {
     const pic_species &sp = c->cfg.species[s];
@@ -388,6 +396,60 @@ StepParams step_params(pic_ctx *c) {
   P.stats = c->stats;
   P.err = c->err;
   return P;
+}
+
+// Injection of one step into the output buffer `out` of that step. The slab
+// thickness and the mean ghost count per face cell are evaluated in FP64 from
+// the physical inputs exactly as stated with pic_injection.
+InjParams inj_params(pic_ctx *c, int out) {
+  InjParams I{};
+  const Dims &L = c->L;
+  const pic_config &cfg = c->cfg;
+  for (int s = 0; s < L.ns; ++s) I.out[s] = c->sp[s].buf[out];
+  I.bins = bins_of(c);
+  I.out_idx = out;
+  I.ns = L.ns;
+  I.nx = L.nx;
+  I.ny = L.ny;
+  I.nz = L.nz;
+  I.ntx = L.ntx;
+  I.nty = L.nty;
+  I.ntiles = L.ntiles;
+  I.has_ids = ids_mask(c);
+  I.step = (int32_t)c->step_index;
+  I.seed = c->inj.seed;
+  I.dt = cfg.dt;
+  const int n[3] = {L.nx, L.ny, L.nz};
+  const double h3 = cfg.h * cfg.h * cfg.h;
+  const bool f64 = cfg.repr == PIC_REPR_FP64;
+  int64_t total = 0;
+  for (int s = 0; s < L.ns; ++s) {
+    const double ncell = c->inj.density[s] * h3;
+    I.vth[s] = c->inj.vth[s] / cfg.h;
+    for (int d = 0; d < 3; ++d) I.u[s][d] = c->inj.drift[s][d] / cfg.h;
+    for (int f = 0; f < 6; ++f) {
+      I.first[s * 6 + f] = total;
+      const int axis = f / 2;
+      const double un = (f & 1) ? -I.u[s][axis] : I.u[s][axis];
+      double th = cfg.dt * ((un > 0.0 ? un : 0.0) + 6.0 * I.vth[s]);
+      if (th > 1.0) th = 1.0;
+      I.L[s][f] = th;
+      I.mean[s][f] = ncell * th;
+      if (((c->inj.faces >> f) & 1) && ncell > 0.0)
+        total += (int64_t)n[axis == 0 ? 1 : 0] * n[axis == 2 ? 1 : 2];
+    }
+    const pic_species &sp = cfg.species[s];
+    I.chg[s] = sp.q * sp.weight;
+    const double chgT = f64 ? I.chg[s] : (double)(float)I.chg[s];
+    I.chg_fixed[s] = std::llrint(chgT * kTwo32);
+  }
+  I.first[L.ns * 6] = total;
+  I.geom = c->geom;
+  I.rho = c->rho;
+  I.tally = c->tally;
+  I.injected = c->injected;
+  I.err = c->err;
+  return I;
 }
 
 // Re-bucketing with fresh tile capacities: from the current buffer (tile
@@ -607,6 +669,7 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
       {(void **)&c->ovf[0], 64},
       {(void **)&c->ovf[1], 64},
       {(void **)&c->flags, 64},
+      {(void **)&c->injected, 64},
       {(void **)&c->count, (int64_t)L.ns * L.ntiles * 4},
       {(void **)&c->cursor, (int64_t)L.ns * L.ntiles * 4},
       {(void **)&c->hist, (int64_t)L.ns * L.ntiles * kNeighbours * 4},
@@ -821,10 +884,15 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
     const int pe = prof_begin(c, 0);
     PIC_HIP(c, launch_step(c->cfg.repr, c->cfg.deposit, true, P, c->stream));
     prof_end(c, pe);
+    if (c->inj_on) {
+      const InjParams I = inj_params(c, 1 - c->cur);
+      PIC_HIP(c, launch_inject(c->cfg.repr, c->cfg.deposit, I, c->stream));
+    }
     PIC_HIP(c, hipMemcpyAsync((void *)c->flag_host, c->flags, sizeof(int32_t),
                               hipMemcpyDeviceToHost, c->stream));
     c->cur = 1 - c->cur;
     c->since_sort++;
+    c->step_index++;
   }
   return PIC_OK;
 }
@@ -891,14 +959,54 @@ pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64
   std::vector<int64_t> t(L.nbins * L.ns), e(6 * L.ns);
   if (L.nbins) PIC_HIP(c, hipMemcpy(t.data(), c->tally, t.size() * 8, hipMemcpyDeviceToHost));
   PIC_HIP(c, hipMemcpy(e.data(), c->escaped, e.size() * 8, hipMemcpyDeviceToHost));
+  int64_t inj[PIC_MAX_SPECIES] = {0, 0, 0, 0};
+  PIC_HIP(c, hipMemcpy(inj, c->injected, sizeof(int64_t) * L.ns, hipMemcpyDeviceToHost));
   for (int s = 0; s < L.ns; ++s) {
     int64_t a = 0, es = 0;
     for (int64_t b = 0; b < L.nbins; ++b) a += t[b * L.ns + s];
     for (int f = 0; f < 6; ++f) es += e[f * L.ns + s];
     if (absorbed) absorbed[s] = a;
-    if (alive) alive[s] = c->sp[s].loaded - a - es;
+    if (alive) alive[s] = c->sp[s].loaded + inj[s] - a - es;
   }
   if (escaped) std::memcpy(escaped, e.data(), e.size() * 8);
+  return PIC_OK;
+}
+
+pic_status pic_set_injection(pic_ctx *c, const pic_injection *inj) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (!inj || inj->faces == 0) {
+    c->inj_on = false;
+    return PIC_OK;
+  }
+  if (inj->faces & ~63) return fail(c, PIC_E_INVALID, "faces: only bits 0..5");
+  if (inj->faces & c->cfg.reflect) return fail(c, PIC_E_INVALID, "a face cannot reflect and inject");
+  if (c->cfg.object.kind == PIC_OBJ_CRATER && (inj->faces & 16))
+    return fail(c, PIC_E_INVALID, "the crater's z- face is the terrain");
+  for (int s = 0; s < c->L.ns; ++s) {
+    if (!(inj->density[s] >= 0) || !is_finite(inj->density[s]) || !(inj->vth[s] >= 0) ||
+        !is_finite(inj->vth[s]))
+      return fail(c, PIC_E_INVALID, "density and vth must be finite and >= 0");
+    double sp = 13.0 * inj->vth[s];
+    for (int d = 0; d < 3; ++d) {
+      if (!is_finite(inj->drift[s][d])) return fail(c, PIC_E_INVALID, "drift must be finite");
+      sp += std::fabs(inj->drift[s][d]);
+    }
+    if (!(c->cfg.dt * sp / c->cfg.h <= 1048576.0))
+      return fail(c, PIC_E_INVALID, "ambient speeds move more than 2^20 cells per step");
+    if (!(inj->density[s] * c->cfg.h * c->cfg.h * c->cfg.h <= 1048576.0))
+      return fail(c, PIC_E_INVALID, "density above 2^20 particles per cell");
+  }
+  c->inj = *inj;
+  c->inj_on = true;
+  return PIC_OK;
+}
+
+pic_status pic_get_injected(pic_ctx *c, int64_t *injected) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (!injected) return fail(c, PIC_E_INVALID, "injected must not be NULL");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  PIC_HIP(c, hipMemcpy(injected, c->injected, sizeof(int64_t) * c->L.ns, hipMemcpyDeviceToHost));
   return PIC_OK;
 }
 
@@ -1280,6 +1388,7 @@ pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *s
   if (c->cfg.repr != b->cfg.repr || c->cfg.deposit != b->cfg.deposit)
     return bfail(b, PIC_E_INVALID, "repr / deposit differ from the batch's");
   if (!c->E_set) return bfail(b, PIC_E_STATE, "the context has no node field");
+  if (c->inj_on) return bfail(b, PIC_E_INVALID, "contexts that inject particles run alone (pic_step)");
   int free_slot = -1;
   for (int k = 0; k < b->cfg.max_slots && free_slot < 0; ++k)
     if (!b->ctx[k]) free_slot = k;

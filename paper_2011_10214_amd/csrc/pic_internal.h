@@ -93,6 +93,7 @@ struct StepParams {
   int32_t nx, ny, nz;
   int32_t ntx, nty, ntz, ntiles;
   int32_t has_ids;            // bit s: species s carries ids
+  int32_t reflect;            // bit f: box face f reflects
   double qmdt[PIC_MAX_SPECIES];  // q/m*dt/h
   double chg[PIC_MAX_SPECIES];   // q*w
   int64_t chg_fixed[PIC_MAX_SPECIES];  // llrint(chg_T * 2^32), chg_T in the path's type
@@ -140,6 +141,32 @@ struct LoadParams {
   int32_t *bad;             // count of positions outside the box
 };
 
+// Injection of ambient particles through box faces (one thread per species,
+// face and face cell), after the step kernel: appended to the arrival zones of
+// the output buffer and deposited with global atomics.
+struct InjParams {
+  PBuf out[PIC_MAX_SPECIES];  // the buffer the step wrote
+  Bins bins;
+  int32_t out_idx;            // its index (arrival / overflow counters)
+  int32_t ns, nx, ny, nz, ntx, nty, ntiles;
+  int32_t has_ids;
+  int32_t step;
+  uint64_t seed;
+  double dt;
+  double vth[PIC_MAX_SPECIES];     // cell units
+  double u[PIC_MAX_SPECIES][3];    // cell units
+  double L[PIC_MAX_SPECIES][6];    // ghost slab thickness
+  double mean[PIC_MAX_SPECIES][6]; // ghosts per face cell
+  int64_t first[PIC_MAX_SPECIES * 6 + 1];  // thread prefix over (species, face)
+  double chg[PIC_MAX_SPECIES];
+  int64_t chg_fixed[PIC_MAX_SPECIES];
+  Geom geom;
+  void *rho;
+  int64_t *tally;
+  int64_t *injected;          // [ns]
+  int32_t *err;
+};
+
 // Batched runs: many contexts (slots) advanced by one launch per step. Work
 // item b belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles + 1
 // items per slot); persistent workgroups take items from a counter. The slot
@@ -165,6 +192,7 @@ hipError_t launch_sort_count(int repr, const SortParams &p, int64_t max_src, hip
 hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s);
+hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
                            int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,

@@ -231,6 +231,113 @@ __device__ __forceinline__ int box_face_abs(const T g[3], int nx, int ny, int nz
   return -1;
 }
 
+// Mirror about the reflecting faces (bit f of mask), axes x, y, z in turn, with
+// the normal velocity negated; a particle mirrored exactly onto a max face is
+// put just inside (the largest value below n).
+__device__ __forceinline__ float below(float x) { return __int_as_float(__float_as_int(x) - 1); }
+__device__ __forceinline__ double below(double x) {
+  return __longlong_as_double(__double_as_longlong(x) - 1);
+}
+
+template <class T>
+__device__ __forceinline__ void reflect_abs(int mask, const int n[3], T g[3], T u[3]) {
+  for (int d = 0; d < 3; ++d) {
+    if (((mask >> (2 * d)) & 1) && g[d] < T(0)) {
+      g[d] = -g[d];
+      u[d] = -u[d];
+    }
+    if (((mask >> (2 * d + 1)) & 1) && g[d] >= (T)n[d]) {
+      g[d] = (T)(2 * n[d]) - g[d];
+      if (g[d] >= (T)n[d]) g[d] = below((T)n[d]);
+      u[d] = -u[d];
+    }
+  }
+}
+
+// The same on a cell + offset position: m - (i + o) = (m - i - 1) + (1 - o).
+__device__ __forceinline__ void reflect_cell(int mask, const int n[3], int i[3], float o[3],
+                                             float u[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const bool lo = ((mask >> (2 * d)) & 1) && i[d] < 0;
+    const bool hi = ((mask >> (2 * d + 1)) & 1) && i[d] >= n[d];
+    if (!lo && !hi) continue;
+    const int m = lo ? 0 : 2 * n[d];
+    if (o[d] == 0.0f) {
+      i[d] = m - i[d];
+    } else {
+      i[d] = m - i[d] - 1;
+      o[d] = 1.0f - o[d];
+      if (o[d] == 1.0f) {
+        o[d] = 0.0f;
+        i[d] += 1;
+      }
+    }
+    if (hi && i[d] >= n[d]) {
+      i[d] = n[d] - 1;
+      o[d] = below(1.0f);
+    }
+    u[d] = -u[d];
+  }
+}
+
+// ------------------------------------------------------------------ injection random numbers
+
+// SplitMix64 (Steele, Lea and Flood, 2014) used as a counter-based generator:
+// draw d of a key is the output function applied to key + (d + 1) * gamma.
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+
+__device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t inj_key(uint64_t seed, int32_t step, int s, int f,
+                                            int64_t cell, int64_t j) {
+  uint64_t k = sm_mix(seed + kGamma);
+  k = sm_mix(k ^ (uint64_t)(uint32_t)step);
+  k = sm_mix(k ^ (uint64_t)(s * 8 + f));
+  k = sm_mix(k ^ (uint64_t)cell);
+  return sm_mix(k ^ (uint64_t)j);
+}
+
+// uniform in [0, 1) on the 2^-53 grid
+__device__ __forceinline__ double inj_uniform(uint64_t key, uint64_t d) {
+  return (double)(sm_mix(key + (d + 1) * kGamma) >> 11) * 0x1.0p-53;
+}
+
+// ln x = e ln 2 + 2 atanh((m - 1)/(m + 1)), x = m 2^e, m in [sqrt(1/2), sqrt(2));
+// atanh by its Taylor series to s^23 (correctly rounded operations only).
+__device__ double ln_series(double x) {
+  int e = 0;
+  double m = frexp(x, &e);
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    e = e - 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double t = s * s;
+  double p = 1.0 / 23.0;
+#pragma unroll
+  for (int k = 21; k >= 1; k -= 2) p = p * t + 1.0 / (double)k;
+  return (double)e * 0.69314718055994530942 + 2.0 * s * p;
+}
+
+// Three standard normals (Marsaglia's polar method); *d counts the draws.
+__device__ void normals3(uint64_t key, uint64_t *d, double z[3]) {
+  int got = 0;
+  for (int attempt = 0; attempt < 64 && got < 3; ++attempt) {
+    const double a = 2.0 * inj_uniform(key, (*d)++) - 1.0;
+    const double b = 2.0 * inj_uniform(key, (*d)++) - 1.0;
+    const double r = a * a + b * b;
+    if (!(r > 0.0 && r < 1.0)) continue;
+    const double f = __builtin_sqrt(-2.0 * ln_series(r) / r);
+    z[got++] = a * f;
+    if (got < 3) z[got++] = b * f;
+  }
+  while (got < 3) z[got++] = 0.0;
+}
+
 // ------------------------------------------------------------------ tile regions
 
 // Source range of a workgroup: a tile's stayed + arrived particles, or (t ==
@@ -557,10 +664,18 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
             f[d] = op;
             ci[d] += bad ? 0 : (int)sh;
           }
+          if (P.reflect && !bad) {
+            const int dims[3] = {nx, ny, nz};
+            reflect_cell(P.reflect, dims, ci, f, u);
+          }
         } else {
           for (int d = 0; d < 3; ++d) {
             q.x[d] = fmaT(u[d], dt, q.x[d]);
             bad |= !finiteT(q.x[d]);
+          }
+          if (P.reflect && !bad) {
+            const int dims[3] = {nx, ny, nz};
+            reflect_abs(P.reflect, dims, q.x, u);
           }
         }
         int face = -1, bin = -1;
@@ -1106,6 +1221,119 @@ __global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32
 
 // ------------------------------------------------------------------ utility
 
+// Injection: one thread per (species, face, face cell). Every ghost of the
+// face cell's slab is drawn, moved dt and, if it ends inside the box, rounded
+// to the representation, tested against the object (collected at once) or
+// appended to its tile's arrival zone in the output buffer and deposited.
+template <int R, int D>
+__global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
+  using T = typename RealOf<R>::T;
+  using A = typename AccOf<D>::type;
+  constexpr bool kCell = R == PIC_REPR_FP32_CELL;
+  constexpr bool kFixed = D == PIC_DEP_FIXED64;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nsf = P.ns * 6;
+  if (tid >= P.first[nsf]) return;
+  int sf = 0;
+  while (P.first[sf + 1] <= tid) ++sf;
+  const int s = sf / 6, f = sf % 6;
+  const int64_t cell = tid - P.first[sf];
+  const int n[3] = {P.nx, P.ny, P.nz};
+  const int axis = f / 2;
+  const bool max_side = (f & 1) != 0;
+  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+  const int64_t a = cell % n[t1], b = cell / n[t1];
+  const double L = P.L[s][f];
+  const int64_t k =
+      (int64_t)floor(P.mean[s][f] + inj_uniform(inj_key(P.seed, P.step, s, f, cell, 0), 0));
+  const bool crater = P.geom.kind == PIC_OBJ_CRATER;
+  const GeomT<T> G = geom_of<T>(P.geom);
+  const bool ids = (P.has_ids >> s) & 1;
+  const T chg = (T)P.chg[s];
+  const bool neg = chg < T(0);
+  const T amag = absT(chg) * two32<T>();
+  const unsigned long long fmag =
+      (unsigned long long)(P.chg_fixed[s] < 0 ? -P.chg_fixed[s] : P.chg_fixed[s]);
+  const int sx = P.nx + 1, sy = (P.nx + 1) * (P.ny + 1);
+  A *__restrict__ gRho = (A *)P.rho;
+  for (int64_t j = 1; j <= k; ++j) {
+    const uint64_t key = inj_key(P.seed, P.step, s, f, cell, j);
+    double g[3], v[3], z[3];
+    g[t1] = (double)a + inj_uniform(key, 0);
+    g[t2] = (double)b + inj_uniform(key, 1);
+    const double depth = L * (1.0 - inj_uniform(key, 2));
+    g[axis] = max_side ? (double)n[axis] + depth : -depth;
+    uint64_t d = 3;
+    normals3(key, &d, z);
+    for (int q = 0; q < 3; ++q) v[q] = P.u[s][q] + P.vth[s] * z[q];
+    for (int q = 0; q < 3; ++q) g[q] = fma(v[q], P.dt, g[q]);
+    // the representation of the injected particle, then the same tests as a
+    // pushed particle
+    Particle<T> pt;
+    int ci[3];
+    T fo[3];
+    if constexpr (kCell) {
+      for (int q = 0; q < 3; ++q) {
+        ci[q] = (int)floor(g[q]);
+        fo[q] = (T)(g[q] - (double)ci[q]);
+        if (fo[q] == T(1)) {
+          fo[q] = T(0);
+          ci[q] += 1;
+        }
+      }
+      if (box_face(ci, P.nx, P.ny, P.nz, crater) >= 0) continue;
+      pt.cell = pack_cell(ci[0], ci[1], ci[2]);
+      for (int q = 0; q < 3; ++q) pt.x[q] = fo[q];
+    } else {
+      for (int q = 0; q < 3; ++q) pt.x[q] = (T)g[q];
+      if (box_face_abs(pt.x, P.nx, P.ny, P.nz, crater) >= 0) continue;
+      for (int q = 0; q < 3; ++q) {
+        ci[q] = (int)floorT(pt.x[q]);
+        fo[q] = pt.x[q] - (T)ci[q];
+      }
+      pt.cell = 0;
+    }
+    for (int q = 0; q < 3; ++q) pt.u[q] = (T)v[q];
+    pt.id = -1;
+    atomicAdd((unsigned long long *)&P.injected[s], 1ull);
+    int bin;
+    if constexpr (kCell) bin = hit_cell(G, P.nx, P.ny, ci, fo);
+    else bin = hit_abs(G, P.nx, P.ny, pt.x);
+    if (bin >= 0) {
+      atomicAdd((unsigned long long *)&P.tally[(int64_t)bin * P.ns + s], 1ull);
+      continue;
+    }
+    const int tn = tile_of_cell(ci, P.ntx, P.nty);
+    const int64_t slot = arrival_slot(P.bins, P.out_idx, s, tn, P.ntiles, P.err);
+    if (slot >= 0) store_particle<R>(P.out[s], slot, pt, ids);
+    // deposit (global atomics)
+    T W[8];
+    weights(fo, W);
+    int idx[8];
+    const int b0 = ci[0] + sx * ci[1] + sy * ci[2];
+    idx[0] = b0;
+    idx[1] = b0 + 1;
+    idx[2] = b0 + sx;
+    idx[3] = b0 + sx + 1;
+    idx[4] = b0 + sy;
+    idx[5] = b0 + sy + 1;
+    idx[6] = b0 + sy + sx;
+    idx[7] = b0 + sy + sx + 1;
+    if constexpr (kFixed) {
+      unsigned long long C[8];
+      unsigned long long sum = 0;
+      for (int q = 0; q < 7; ++q) {
+        C[q] = fix_mag<T>(amag * W[q]);
+        sum += C[q];
+      }
+      C[7] = fmag - sum;
+      for (int q = 0; q < 8; ++q) atomicAdd(&gRho[idx[q]], neg ? 0ull - C[q] : C[q]);
+    } else {
+      for (int q = 0; q < 8; ++q) unsafeAtomicAdd(&gRho[idx[q]], (A)(chg * W[q]));
+    }
+  }
+}
+
 __global__ void fill_kernel(uint32_t *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1300,6 +1528,36 @@ hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, (uint32_t *)ptr, n);
   return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_inject_r(int deposit, const InjParams &p, dim3 grid, hipStream_t s) {
+  switch (deposit) {
+    case PIC_DEP_FIXED64:
+      hipLaunchKernelGGL((inject_kernel<R, PIC_DEP_FIXED64>), grid, dim3(256), 0, s, p);
+      break;
+    case PIC_DEP_ATOMIC_FP32:
+      hipLaunchKernelGGL((inject_kernel<R, PIC_DEP_ATOMIC_FP32>), grid, dim3(256), 0, s, p);
+      break;
+    case PIC_DEP_ATOMIC_FP64:
+      hipLaunchKernelGGL((inject_kernel<R, PIC_DEP_ATOMIC_FP64>), grid, dim3(256), 0, s, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t s) {
+  const int64_t total = p.first[p.ns * 6];
+  if (total <= 0) return hipSuccess;
+  const dim3 grid(grid_for(total, 256));
+  switch (repr) {
+    case PIC_REPR_FP64: return launch_inject_r<PIC_REPR_FP64>(deposit, p, grid, s);
+    case PIC_REPR_FP32_ABS: return launch_inject_r<PIC_REPR_FP32_ABS>(deposit, p, grid, s);
+    case PIC_REPR_FP32_CELL: return launch_inject_r<PIC_REPR_FP32_CELL>(deposit, p, grid, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s) {

@@ -39,8 +39,14 @@ class _Config(ctypes.Structure):
                 ("h", ctypes.c_double), ("origin", ctypes.c_double * 3), ("dt", ctypes.c_double),
                 ("n_species", ctypes.c_int32), ("species", _Species * MAX_SPECIES),
                 ("object", _Object), ("repr", ctypes.c_int32), ("deposit", ctypes.c_int32),
-                ("sort_interval", ctypes.c_int32), ("capacity", ctypes.c_int64 * MAX_SPECIES),
-                ("stream", ctypes.c_void_p)]
+                ("sort_interval", ctypes.c_int32), ("reflect", ctypes.c_int32),
+                ("capacity", ctypes.c_int64 * MAX_SPECIES), ("stream", ctypes.c_void_p)]
+
+
+class _Injection(ctypes.Structure):
+    _fields_ = [("faces", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("density", ctypes.c_double * MAX_SPECIES), ("vth", ctypes.c_double * MAX_SPECIES),
+                ("drift", ctypes.c_double * (3 * MAX_SPECIES))]
 
 
 class _BatchConfig(ctypes.Structure):
@@ -71,6 +77,8 @@ SIGNATURES = {
     "pic_set_node_E": (_st, [_vp, _vp, _vp, _vp]),
     "pic_set_node_E_f32_dev": (_st, [_vp, _vp, _vp, _vp]),
     "pic_step": (_st, [_vp, _i32]),
+    "pic_set_injection": (_st, [_vp, ctypes.POINTER(_Injection)]),
+    "pic_get_injected": (_st, [_vp, _vp]),
     "pic_synchronize": (_st, [_vp]),
     "pic_get_rho": (_st, [_vp, _vp, _vp]),
     "pic_num_bins": (_i64, [_vp]),
@@ -149,6 +157,7 @@ class Config:
     repr: str = "fp32_cell"
     deposit: str = "fixed64"
     sort_interval: int = 0
+    reflect: int = 0                    # bit f: box face f (x-, x+, y-, y+, z-, z+) reflects
     stream: int = 0                     # hipStream_t handle (e.g. torch stream.cuda_stream)
 
     @property
@@ -171,6 +180,7 @@ class Config:
                                                                 self.depth)
         c.repr = REPR[self.repr]
         c.deposit = DEPOSIT[self.deposit]
+        c.reflect = int(self.reflect)
         c.sort_interval = self.sort_interval
         for s in range(len(self.species)):
             c.capacity[s] = int(self.capacity[s])
@@ -293,6 +303,28 @@ class Context:
 
     def step(self, nsteps: int):
         self._check(lib().pic_step(self._h, int(nsteps)))
+
+    def set_injection(self, faces: int, seed: int = 0, density=None, vth=None, drift=None):
+        """Ambient particles injected through the faces in the bit mask each
+        step (``faces`` = 0 turns it off); per species density, thermal speed
+        and drift (3 components), physical units."""
+        if not faces:
+            self._check(lib().pic_set_injection(self._h, None))
+            return
+        c = _Injection()
+        c.faces = int(faces)
+        c.seed = int(seed) & (2 ** 64 - 1)
+        for s in range(self.ns):
+            c.density[s] = float(density[s]) if density is not None else 0.0
+            c.vth[s] = float(vth[s]) if vth is not None else 0.0
+            for d in range(3):
+                c.drift[3 * s + d] = float(drift[s][d]) if drift is not None else 0.0
+        self._check(lib().pic_set_injection(self._h, ctypes.byref(c)))
+
+    def get_injected(self) -> np.ndarray:
+        out = np.zeros(self.ns, np.int64)
+        self._check(lib().pic_get_injected(self._h, _ptr(out)))
+        return out
 
     def synchronize(self):
         self._check(lib().pic_synchronize(self._h))
