@@ -330,6 +330,9 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=0,
                     help="re-plan the tile regions every K steps (0: on demand)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--boundaries", default="open", choices=["open", "lunar"],
+                    help="open: all faces remove; lunar: y- reflects and ambient plasma is "
+                         "injected at x-, x+, y+, z+ every step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy kernel (counter calibration)")
@@ -380,11 +383,25 @@ def main():
     # a stream of torch's own (default priority) that the library enqueues on,
     # so that the events below bracket exactly the library's work
     stream = torch.cuda.Stream()
+    cap = None
+    if args.boundaries == "lunar":
+        cap = [int(sp.count * 1.05) + 4096 for sp in w.species]
     cfg = pam.config_from_workload(w, repr=args.repr, deposit=args.deposit,
-                                   sort_interval=args.sort_interval, stream=stream.cuda_stream)
+                                   sort_interval=args.sort_interval, stream=stream.cuda_stream,
+                                   capacity=cap)
+    inj = None
+    if args.boundaries == "lunar":
+        # the lunar setup of §5.2.2: symmetry plane y-, ambient plasma injected
+        # at x-, x+, y+ and z+ with the loaded density above the flat ground
+        cfg.reflect = 4
+        above = w.nx * w.ny * (w.nz - w.z_flat) * w.h ** 3
+        inj = dict(faces=1 | 2 | 8 | 32, seed=17, density=[sp.count / above for sp in w.species],
+                   vth=[sp.vth for sp in w.species], drift=[tuple(sp.drift) for sp in w.species])
     log(f"workload {w.name}: {w.nx}x{w.ny}x{w.nz} cells, {w.n_particles} particles, "
-        f"{args.repr}/{args.deposit}, K={args.sort_interval}")
+        f"{args.repr}/{args.deposit}, K={args.sort_interval}, boundaries {args.boundaries}")
     ctx = pam.Context(cfg)
+    if inj:
+        ctx.set_injection(**inj)
     t0 = time.perf_counter()
     for s in range(len(w.species)):
         cols = synth.particles(w, s)
@@ -403,6 +420,7 @@ def main():
     ctx.step(args.warmup)
     ctx.synchronize()
     alive0, _, _ = ctx.get_counters()
+    injected0 = ctx.get_injected()
 
     ctx.profile_enable(True)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -418,6 +436,7 @@ def main():
     ms = e0.elapsed_time(e1)
     prof = ctx.profile_read()
     alive1, absorbed, escaped = ctx.get_counters()
+    injected = ctx.get_injected()
     log(f"timed {args.steps} steps: {ms:.2f} ms (host wall {wall_ms:.2f} ms); step kernel {prof.step_ms / max(1, prof.step_launches):.3f} ms avg, "
         f"sort {prof.sort_ms / max(1, prof.sort_launches):.3f} ms avg x{prof.sort_launches}")
     ctx.close()
@@ -471,8 +490,17 @@ def main():
             "step_kernel": prof.step_ms / args.steps,
             "sort": prof.sort_ms / args.steps,
             "rho_clear": prof.clear_ms / args.steps,
+            "injection": prof.inject_ms / args.steps,
         },
     }
+    if inj:
+        out["config"]["boundaries"] = ("lunar: y- reflects; ambient plasma injected at x-, x+, y+, "
+                                       "z+ (ghost slabs, drifting Maxwellian)")
+        out["injection"] = {
+            "kernel_ms_avg": prof.inject_ms / max(1, prof.inject_launches),
+            "injected_per_step": int((injected - injected0).sum()) / args.steps,
+            "share_of_step": prof.inject_ms / ms if ms > 0 else None,
+        }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -270,6 +270,8 @@ typedef struct {
   int64_t clear_launches; /* rho clears */
   double clear_ms;
   int64_t particle_steps; /* particles alive at the start of each step, summed */
+  int64_t inject_launches; /* injection launches (pic_set_injection) */
+  double inject_ms;
 } pic_profile;
 
 /* Enables (on != 0) or disables event timing and resets the totals. */

@@ -51,7 +51,8 @@
 //     gives no method; this oracle uses a ghost layer: per face cell, a slab of
 //     thickness L = min(1, dt (max(0, u.n_in) + 6 vth)) outside the face holds
 //     floor(n L + U) ghost particles uniform in the slab with velocities drawn
-//     from the drifting Maxwellian; each moves dt (g' = fma(v, dt, g)) and is
+//     from the drifting Maxwellian (the first normal drawn is the component
+//     along the face normal); each moves dt (g' = fma(v, dt, g)) and is
 //     injected if it ends inside the box (the terrain's z < 0 counts as inside
 //     and is then collected), rounded to the form's representation and tested
 //     against the object like a pushed particle; it carries v as its half-step
@@ -444,7 +445,10 @@ void inject_ghosts(const orc_config& cfg, const int32_t n[3], int32_t step, Emit
           g[F.axis] = F.max_side ? (double)n[F.axis] + depth : -depth;
           uint64_t d = 3;
           normals3(key, &d, z);
-          for (int q = 0; q < 3; ++q) v[q] = I.u[q] + I.vth * z[q];
+          // the first normal goes to the face's normal axis, then t1, t2
+          v[F.axis] = I.u[F.axis] + I.vth * z[0];
+          v[F.t1] = I.u[F.t1] + I.vth * z[1];
+          v[F.t2] = I.u[F.t2] + I.vth * z[2];
           for (int q = 0; q < 3; ++q) g[q] = std::fma(v[q], cfg.dt, g[q]);
           emit(s, g, v);
         }

@@ -159,7 +159,7 @@ int64_t footprint(const pic_config &c) {
 }
 
 struct Ev {
-  int kind;  // 0 step, 1 sort, 2 clear
+  int kind;  // 0 step, 1 sort, 2 clear, 3 injection
   hipEvent_t a, b;
 };
 
@@ -303,6 +303,9 @@ void prof_collect(pic_ctx *c) {
       } else if (e.kind == 1) {
         c->acc.sort_launches++;
         c->acc.sort_ms += ms;
+      } else if (e.kind == 3) {
+        c->acc.inject_launches++;
+        c->acc.inject_ms += ms;
       } else {
         c->acc.clear_launches++;
         c->acc.clear_ms += ms;
@@ -435,8 +438,9 @@ InjParams inj_params(pic_ctx *c, int out) {
       if (th > 1.0) th = 1.0;
       I.L[s][f] = th;
       I.mean[s][f] = ncell * th;
+      I.gmax[s][f] = (int64_t)std::floor(I.mean[s][f]) + 1;
       if (((c->inj.faces >> f) & 1) && ncell > 0.0)
-        total += (int64_t)n[axis == 0 ? 1 : 0] * n[axis == 2 ? 1 : 2];
+        total += (int64_t)n[axis == 0 ? 1 : 0] * n[axis == 2 ? 1 : 2] * I.gmax[s][f];
     }
     const pic_species &sp = cfg.species[s];
     I.chg[s] = sp.q * sp.weight;
@@ -886,7 +890,11 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
     prof_end(c, pe);
     if (c->inj_on) {
       const InjParams I = inj_params(c, 1 - c->cur);
+      if (I.first[c->L.ns * 6] > (int64_t(1) << 36))
+        return fail(c, PIC_E_INVALID, "injection: more than 2^36 ghost slots per step");
+      const int pi = prof_begin(c, 3);
       PIC_HIP(c, launch_inject(c->cfg.repr, c->cfg.deposit, I, c->stream));
+      prof_end(c, pi);
     }
     PIC_HIP(c, hipMemcpyAsync((void *)c->flag_host, c->flags, sizeof(int32_t),
                               hipMemcpyDeviceToHost, c->stream));

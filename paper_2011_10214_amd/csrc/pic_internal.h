@@ -142,8 +142,8 @@ struct LoadParams {
 };
 
 // Injection of ambient particles through box faces (one thread per species,
-// face and face cell), after the step kernel: appended to the arrival zones of
-// the output buffer and deposited with global atomics.
+// face, face cell and ghost slot), after the step kernel: appended to the
+// arrival zones of the output buffer and deposited with global atomics.
 struct InjParams {
   PBuf out[PIC_MAX_SPECIES];  // the buffer the step wrote
   Bins bins;
@@ -157,6 +157,7 @@ struct InjParams {
   double u[PIC_MAX_SPECIES][3];    // cell units
   double L[PIC_MAX_SPECIES][6];    // ghost slab thickness
   double mean[PIC_MAX_SPECIES][6]; // ghosts per face cell
+  int64_t gmax[PIC_MAX_SPECIES][6];  // ghost slots per face cell: floor(mean) + 1
   int64_t first[PIC_MAX_SPECIES * 6 + 1];  // thread prefix over (species, face)
   double chg[PIC_MAX_SPECIES];
   int64_t chg_fixed[PIC_MAX_SPECIES];

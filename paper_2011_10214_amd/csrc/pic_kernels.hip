@@ -292,13 +292,14 @@ __device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ uint64_t inj_key(uint64_t seed, int32_t step, int s, int f,
-                                            int64_t cell, int64_t j) {
+// key of a face cell; its ghost j (j >= 1) or count draw (j = 0) has key
+// sm_mix(cell key ^ j)
+__device__ __forceinline__ uint64_t inj_cell_key(uint64_t seed, int32_t step, int s, int f,
+                                                 int64_t cell) {
   uint64_t k = sm_mix(seed + kGamma);
   k = sm_mix(k ^ (uint64_t)(uint32_t)step);
   k = sm_mix(k ^ (uint64_t)(s * 8 + f));
-  k = sm_mix(k ^ (uint64_t)cell);
-  return sm_mix(k ^ (uint64_t)j);
+  return sm_mix(k ^ (uint64_t)cell);
 }
 
 // uniform in [0, 1) on the 2^-53 grid
@@ -323,19 +324,23 @@ __device__ double ln_series(double x) {
   return (double)e * 0.69314718055994530942 + 2.0 * s * p;
 }
 
-// Three standard normals (Marsaglia's polar method); *d counts the draws.
-__device__ void normals3(uint64_t key, uint64_t *d, double z[3]) {
-  int got = 0;
-  for (int attempt = 0; attempt < 64 && got < 3; ++attempt) {
+// One pair of standard normals by Marsaglia's polar method; *d counts the
+// draws and *attempts the pairs tried (at most 64 over the three normals of a
+// ghost; none left gives zeros).
+__device__ void normal_pair(uint64_t key, uint64_t *d, int *attempts, double *z0, double *z1) {
+  *z0 = 0.0;
+  *z1 = 0.0;
+  for (; *attempts < 64;) {
+    ++*attempts;
     const double a = 2.0 * inj_uniform(key, (*d)++) - 1.0;
     const double b = 2.0 * inj_uniform(key, (*d)++) - 1.0;
     const double r = a * a + b * b;
     if (!(r > 0.0 && r < 1.0)) continue;
     const double f = __builtin_sqrt(-2.0 * ln_series(r) / r);
-    z[got++] = a * f;
-    if (got < 3) z[got++] = b * f;
+    *z0 = a * f;
+    *z1 = b * f;
+    return;
   }
-  while (got < 3) z[got++] = 0.0;
 }
 
 // ------------------------------------------------------------------ tile regions
@@ -1221,9 +1226,10 @@ __global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32
 
 // ------------------------------------------------------------------ utility
 
-// Injection: one thread per (species, face, face cell). Every ghost of the
-// face cell's slab is drawn, moved dt and, if it ends inside the box, rounded
-// to the representation, tested against the object (collected at once) or
+// Injection: one thread per (species, face, face cell, ghost slot); a face
+// cell has floor(mean) + 1 slots, of which the first floor(mean + U) hold a
+// ghost. A ghost is drawn, moved dt and, if it ends inside the box, rounded to
+// the representation, tested against the object (collected at once) or
 // appended to its tile's arrival zone in the output buffer and deposited.
 template <int R, int D>
 __global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
@@ -1233,45 +1239,65 @@ __global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
   constexpr bool kFixed = D == PIC_DEP_FIXED64;
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int nsf = P.ns * 6;
-  if (tid >= P.first[nsf]) return;
+  const bool active = tid < P.first[nsf];
   int sf = 0;
-  while (P.first[sf + 1] <= tid) ++sf;
+  while (active && P.first[sf + 1] <= tid) ++sf;
   const int s = sf / 6, f = sf % 6;
-  const int64_t cell = tid - P.first[sf];
+  const int64_t slot_id = tid - P.first[sf];
+  const int64_t gmax = P.gmax[s][f];
+  const int64_t cell = active ? slot_id / gmax : 0;
+  const int64_t j = active ? slot_id - cell * gmax + 1 : 0;  // ghost 1..gmax of the face cell
   const int n[3] = {P.nx, P.ny, P.nz};
   const int axis = f / 2;
   const bool max_side = (f & 1) != 0;
   const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
   const int64_t a = cell % n[t1], b = cell / n[t1];
-  const double L = P.L[s][f];
-  const int64_t k =
-      (int64_t)floor(P.mean[s][f] + inj_uniform(inj_key(P.seed, P.step, s, f, cell, 0), 0));
+  const uint64_t ckey = inj_cell_key(P.seed, P.step, s, f, cell);
+  const int64_t k = active ? (int64_t)floor(P.mean[s][f] + inj_uniform(sm_mix(ckey ^ 0ull), 0)) : 0;
   const bool crater = P.geom.kind == PIC_OBJ_CRATER;
-  const GeomT<T> G = geom_of<T>(P.geom);
   const bool ids = (P.has_ids >> s) & 1;
-  const T chg = (T)P.chg[s];
-  const bool neg = chg < T(0);
-  const T amag = absT(chg) * two32<T>();
-  const unsigned long long fmag =
-      (unsigned long long)(P.chg_fixed[s] < 0 ? -P.chg_fixed[s] : P.chg_fixed[s]);
   const int sx = P.nx + 1, sy = (P.nx + 1) * (P.ny + 1);
-  A *__restrict__ gRho = (A *)P.rho;
-  for (int64_t j = 1; j <= k; ++j) {
-    const uint64_t key = inj_key(P.seed, P.step, s, f, cell, j);
-    double g[3], v[3], z[3];
-    g[t1] = (double)a + inj_uniform(key, 0);
-    g[t2] = (double)b + inj_uniform(key, 1);
-    const double depth = L * (1.0 - inj_uniform(key, 2));
-    g[axis] = max_side ? (double)n[axis] + depth : -depth;
-    uint64_t d = 3;
-    normals3(key, &d, z);
-    for (int q = 0; q < 3; ++q) v[q] = P.u[s][q] + P.vth[s] * z[q];
-    for (int q = 0; q < 3; ++q) g[q] = fma(v[q], P.dt, g[q]);
-    // the representation of the injected particle, then the same tests as a
-    // pushed particle
-    Particle<T> pt;
-    int ci[3];
-    T fo[3];
+  const int lane = __lane_id();
+
+  // the ghost of this slot, if the face cell has one there
+  bool inside = false, keep = false;
+  Particle<T> pt;
+  int ci[3] = {0, 0, 0};
+  T fo[3] = {T(0), T(0), T(0)};
+  bool enters = false;
+  double g[3], v[3];
+  uint64_t key = 0, d = 3;
+  int attempts = 0;
+  double z1 = 0.0;
+  if (active && j <= k) {
+    // the normal component first: most ghosts do not reach the face, and
+    // the test of the normal axis alone (in the representation, as the box
+    // test makes it) rejects them before the tangential draws
+    key = sm_mix(ckey ^ (uint64_t)j);
+    const double depth = P.L[s][f] * (1.0 - inj_uniform(key, 2));
+    double z0;
+    normal_pair(key, &d, &attempts, &z0, &z1);
+    v[axis] = P.u[s][axis] + P.vth[s] * z0;
+    g[axis] = fma(v[axis], P.dt, max_side ? (double)n[axis] + depth : -depth);
+    if constexpr (kCell) {
+      int i = (int)floor(g[axis]);
+      const T o = (T)(g[axis] - (double)i);
+      if (o == T(1)) i += 1;
+      enters = i < n[axis] && (i >= 0 || (crater && axis == 2));
+    } else {
+      const T x = (T)g[axis];
+      enters = x < (T)n[axis] && (x >= T(0) || (crater && axis == 2));
+    }
+  }
+  if (enters) {
+    double z2, z3;
+    normal_pair(key, &d, &attempts, &z2, &z3);
+    (void)z3;
+    v[t1] = P.u[s][t1] + P.vth[s] * z1;
+    v[t2] = P.u[s][t2] + P.vth[s] * z2;
+    g[t1] = fma(v[t1], P.dt, (double)a + inj_uniform(key, 0));
+    g[t2] = fma(v[t2], P.dt, (double)b + inj_uniform(key, 1));
+    // the representation of the injected particle, then the tests of a pushed one
     if constexpr (kCell) {
       for (int q = 0; q < 3; ++q) {
         ci[q] = (int)floor(g[q]);
@@ -1281,56 +1307,98 @@ __global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
           ci[q] += 1;
         }
       }
-      if (box_face(ci, P.nx, P.ny, P.nz, crater) >= 0) continue;
+      inside = box_face(ci, P.nx, P.ny, P.nz, crater) < 0;
       pt.cell = pack_cell(ci[0], ci[1], ci[2]);
       for (int q = 0; q < 3; ++q) pt.x[q] = fo[q];
     } else {
       for (int q = 0; q < 3; ++q) pt.x[q] = (T)g[q];
-      if (box_face_abs(pt.x, P.nx, P.ny, P.nz, crater) >= 0) continue;
-      for (int q = 0; q < 3; ++q) {
-        ci[q] = (int)floorT(pt.x[q]);
-        fo[q] = pt.x[q] - (T)ci[q];
+      inside = box_face_abs(pt.x, P.nx, P.ny, P.nz, crater) < 0;
+      if (inside) {
+        for (int q = 0; q < 3; ++q) {
+          ci[q] = (int)floorT(pt.x[q]);
+          fo[q] = pt.x[q] - (T)ci[q];
+        }
       }
       pt.cell = 0;
     }
     for (int q = 0; q < 3; ++q) pt.u[q] = (T)v[q];
     pt.id = -1;
-    atomicAdd((unsigned long long *)&P.injected[s], 1ull);
-    int bin;
-    if constexpr (kCell) bin = hit_cell(G, P.nx, P.ny, ci, fo);
-    else bin = hit_abs(G, P.nx, P.ny, pt.x);
-    if (bin >= 0) {
-      atomicAdd((unsigned long long *)&P.tally[(int64_t)bin * P.ns + s], 1ull);
-      continue;
+    if (inside) {
+      const GeomT<T> G = geom_of<T>(P.geom);
+      int bin;
+      if constexpr (kCell) bin = hit_cell(G, P.nx, P.ny, ci, fo);
+      else bin = hit_abs(G, P.nx, P.ny, pt.x);
+      if (bin >= 0) atomicAdd((unsigned long long *)&P.tally[(int64_t)bin * P.ns + s], 1ull);
+      keep = bin < 0;
     }
-    const int tn = tile_of_cell(ci, P.ntx, P.nty);
-    const int64_t slot = arrival_slot(P.bins, P.out_idx, s, tn, P.ntiles, P.err);
+  }
+
+  // append to the arrival zone of the particle's tile (one reservation per
+  // tile and species in the wave)
+  if (keep) {
+    const int key = s * P.ntiles + tile_of_cell(ci, P.ntx, P.nty);
+    const int32_t kk = agg_add(P.bins.arr[P.out_idx], key);
+    const int32_t cap = P.bins.lay.cap[key], room = cap - P.bins.lay.sz[key];
+    int64_t slot = -1;
+    if (kk < room) {
+      slot = P.bins.lay.base[key] + cap - 1 - kk;
+    } else {
+      atomicOr(&P.bins.flags[0], 1);
+      const int32_t o = atomicAdd(&P.bins.ovf[P.out_idx][s], 1);
+      if (o < P.bins.ovf_cap[s]) slot = P.bins.ovf_base[s] + o;
+      else atomicOr(P.err, kErrCapacity);
+    }
     if (slot >= 0) store_particle<R>(P.out[s], slot, pt, ids);
-    // deposit (global atomics)
+  }
+
+  // deposit: the contributions of the lanes that landed in the same cell are
+  // summed across the wave first (integer sums: exact), one atomic per corner
+  A C[8];
+  {
     T W[8];
     weights(fo, W);
-    int idx[8];
-    const int b0 = ci[0] + sx * ci[1] + sy * ci[2];
-    idx[0] = b0;
-    idx[1] = b0 + 1;
-    idx[2] = b0 + sx;
-    idx[3] = b0 + sx + 1;
-    idx[4] = b0 + sy;
-    idx[5] = b0 + sy + 1;
-    idx[6] = b0 + sy + sx;
-    idx[7] = b0 + sy + sx + 1;
+    const T chg = (T)P.chg[s];
     if constexpr (kFixed) {
-      unsigned long long C[8];
+      const bool neg = chg < T(0);
+      const T amag = absT(chg) * two32<T>();
+      const unsigned long long fmag =
+          (unsigned long long)(P.chg_fixed[s] < 0 ? -P.chg_fixed[s] : P.chg_fixed[s]);
       unsigned long long sum = 0;
       for (int q = 0; q < 7; ++q) {
-        C[q] = fix_mag<T>(amag * W[q]);
-        sum += C[q];
+        const unsigned long long m = fix_mag<T>(amag * W[q]);
+        sum += m;
+        C[q] = neg ? 0ull - m : m;
       }
-      C[7] = fmag - sum;
-      for (int q = 0; q < 8; ++q) atomicAdd(&gRho[idx[q]], neg ? 0ull - C[q] : C[q]);
+      C[7] = neg ? 0ull - (fmag - sum) : fmag - sum;
     } else {
-      for (int q = 0; q < 8; ++q) unsafeAtomicAdd(&gRho[idx[q]], (A)(chg * W[q]));
+      for (int q = 0; q < 8; ++q) C[q] = (A)(chg * W[q]);
     }
+  }
+  const int b0 = keep ? ci[0] + sx * ci[1] + sy * ci[2] : -1;
+  A *__restrict__ gRho = (A *)P.rho;
+  const int off[8] = {0, 1, sx, sx + 1, sy, sy + 1, sy + sx, sy + sx + 1};
+  unsigned long long pending = __ballot(keep);
+  while (pending) {  // wave-uniform
+    const int leader = __ffsll(pending) - 1;
+    const int bl = __shfl(b0, leader);
+    const unsigned long long m = __ballot(keep && b0 == bl) & pending;
+    const bool mine = (m >> lane) & 1ull;
+    for (int q = 0; q < 8; ++q) {
+      A vsum = mine ? C[q] : A(0);
+      for (int o = 32; o >= 1; o >>= 1) vsum += __shfl_xor(vsum, o);
+      if (lane == leader) {
+        if constexpr (kFixed) atomicAdd(&gRho[bl + off[q]], vsum);
+        else unsafeAtomicAdd(&gRho[bl + off[q]], vsum);
+      }
+    }
+    pending &= ~m;
+  }
+
+  // the injected counts: one atomic per wave and species
+  for (int sp = 0; sp < P.ns; ++sp) {
+    unsigned long long c = (inside && s == sp) ? 1ull : 0ull;
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+    if (c && lane == 0) atomicAdd((unsigned long long *)&P.injected[sp], c);
   }
 }
 

@@ -60,7 +60,8 @@ class _Profile(ctypes.Structure):
     _fields_ = [("step_launches", ctypes.c_int64), ("step_ms", ctypes.c_double),
                 ("sort_launches", ctypes.c_int64), ("sort_ms", ctypes.c_double),
                 ("clear_launches", ctypes.c_int64), ("clear_ms", ctypes.c_double),
-                ("particle_steps", ctypes.c_int64)]
+                ("particle_steps", ctypes.c_int64), ("inject_launches", ctypes.c_int64),
+                ("inject_ms", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -223,6 +224,8 @@ class Profile:
     clear_launches: int
     clear_ms: float
     particle_steps: int
+    inject_launches: int = 0
+    inject_ms: float = 0.0
 
 
 class Context:
@@ -397,7 +400,7 @@ class Context:
         p = _Profile()
         self._check(lib().pic_profile_read(self._h, ctypes.byref(p)))
         return Profile(p.step_launches, p.step_ms, p.sort_launches, p.sort_ms, p.clear_launches,
-                       p.clear_ms, p.particle_steps)
+                       p.clear_ms, p.particle_steps, p.inject_launches, p.inject_ms)
 
 
 def footprint_bytes(cfg: Config) -> int:
