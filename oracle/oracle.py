@@ -93,6 +93,13 @@ def lib():
         L.orc_ln.restype = ctypes.c_double
         L.orc_ln.argtypes = [ctypes.c_double]
         L.orc_normals3.argtypes = [ctypes.c_uint64, _dp]
+        L.orc_field_solve.restype = ctypes.c_int
+        L.orc_field_solve.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_double,
+                                                             ctypes.c_int32, _dp, _dp, _dp,
+                                                             ctypes.c_double, ctypes.c_int32,
+                                                             _i32p, _dp]
+        L.orc_field_E.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_int32, _dp,
+                                                         _dp, _dp, _dp]
         L.orc_object_hit.restype = ctypes.c_int32
         L.orc_object_hit.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double]
@@ -324,3 +331,33 @@ def normals3(key: int) -> np.ndarray:
     z = np.empty(3)
     lib().orc_normals3(key & (2 ** 64 - 1), z.ctypes.data_as(_dp))
     return z
+
+
+def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=None, tol=1e-10,
+                max_iter=10000):
+    """Solves the field problem on the nodes (see the oracle source); returns
+    (phi, iterations, relative residual)."""
+    nodes = (nx + 1) * (ny + 1) * (nz + 1)
+    rho = _c(rho, np.float64).ravel()
+    if rho.size != nodes:
+        raise ValueError("rho has the wrong size")
+    phi = np.zeros(nodes) if phi0 is None else _c(phi0, np.float64).ravel().copy()
+    g = _c(values if values is not None else np.zeros(6), np.float64)
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    rc = lib().orc_field_solve(nx, ny, nz, float(h), float(eps), int(dirichlet),
+                               g.ctypes.data_as(_dp), rho.ctypes.data_as(_dp),
+                               phi.ctypes.data_as(_dp), float(tol), int(max_iter),
+                               ctypes.byref(it), ctypes.byref(rr))
+    if rc != 0:
+        raise OracleError(f"oracle returned {rc}")
+    return phi, it.value, rr.value
+
+
+def field_E(nx, ny, nz, phi, dirichlet, h=1.0) -> np.ndarray:
+    """E = -grad phi at the nodes, (3, nodes)."""
+    phi = _c(phi, np.float64).ravel()
+    E = [np.empty(phi.size) for _ in range(3)]
+    lib().orc_field_E(nx, ny, nz, float(h), int(dirichlet), phi.ctypes.data_as(_dp),
+                      *[e.ctypes.data_as(_dp) for e in E])
+    return np.stack(E)

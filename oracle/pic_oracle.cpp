@@ -962,6 +962,186 @@ void orc_gather_f64(int32_t nx, int32_t ny, int32_t nz, const double* Ex, const 
 void orc_fixed_contrib_f64(double chg, const double W[8], int64_t C[8]) { fixed_contrib(chg, W, C); }
 void orc_fixed_contrib_f32(float chg, const float W[8], int64_t C[8]) { fixed_contrib(chg, W, C); }
 
+}  // extern "C"
+
+namespace {
+
+// ---- field solve on the PIC mesh ------------------------------------------------
+//
+// The boundary value problem of §2.1, -div(eps grad phi) = rho in the box,
+// phi = g on the Dirichlet faces, d phi / dn = 0 on the others (the
+// zero-Neumann symmetry planes of §3.1.3 and the open faces of §5.2.2), with a
+// uniform eps (no interface: the immersed-finite-element treatment of the
+// object is not in this operator). Node-centred finite volumes on the PIC
+// nodes: a node's control volume is its dual cell clipped to the box, so on a
+// Neumann face the zero flux is natural; the flux through the dual face of
+// the link p-q is eps w (phi_p - phi_q) h, w = product of the two tangential
+// half-width factors c = 1/2 at a boundary index, else 1; the charge in the
+// control volume is rho_p h^3 with rho_p the deposited nodal density (which
+// at a boundary node already counts only the inside part of the cloud). So
+//   (A phi)_p = eps / h^2 sum_links w (phi_p - phi_q) = rho_p,
+// symmetric positive definite once one face is Dirichlet. Solved by conjugate
+// gradients with the Jacobi preconditioner (the PCG of §2.4) from the initial
+// guess in phi, until ||r||_2 <= tol ||b||_2 (b: rho plus the Dirichlet
+// terms) or max_iter iterations. E = -grad phi at the nodes: central
+// differences inside; on a Neumann face the normal component is 0; on a
+// Dirichlet face the second-order one-sided difference.
+
+struct FieldGrid {
+  int32_t n[3];
+  int64_t sx, sy, nodes;
+  double h, eps;
+  int32_t mask;
+  double g[6];
+  bool dir(int i, int j, int k) const {
+    return ((mask & 1) && i == 0) || ((mask & 2) && i == n[0]) || ((mask & 4) && j == 0) ||
+           ((mask & 8) && j == n[1]) || ((mask & 16) && k == 0) || ((mask & 32) && k == n[2]);
+  }
+  // Dirichlet value of a node (the first Dirichlet face it lies on, faces in order)
+  double gval(int i, int j, int k) const {
+    if ((mask & 1) && i == 0) return g[0];
+    if ((mask & 2) && i == n[0]) return g[1];
+    if ((mask & 4) && j == 0) return g[2];
+    if ((mask & 8) && j == n[1]) return g[3];
+    if ((mask & 16) && k == 0) return g[4];
+    return g[5];
+  }
+  double c(int d, int i) const { return (i == 0 || i == n[d]) ? 0.5 : 1.0; }
+  int64_t id(int i, int j, int k) const { return i + sx * j + sy * k; }
+};
+
+// Visits the links of node (i, j, k): f(q, w) for each neighbour q in the box.
+template <class F>
+void field_links(const FieldGrid& G, int i, int j, int k, F f) {
+  const int64_t p = G.id(i, j, k);
+  if (i > 0) f(p - 1, G.c(1, j) * G.c(2, k));
+  if (i < G.n[0]) f(p + 1, G.c(1, j) * G.c(2, k));
+  if (j > 0) f(p - G.sx, G.c(0, i) * G.c(2, k));
+  if (j < G.n[1]) f(p + G.sx, G.c(0, i) * G.c(2, k));
+  if (k > 0) f(p - G.sy, G.c(0, i) * G.c(1, j));
+  if (k < G.n[2]) f(p + G.sy, G.c(0, i) * G.c(1, j));
+}
+
+int field_solve(const FieldGrid& G, const double* rho, double* x, double tol, int32_t max_iter,
+                int32_t* iters, double* relres) {
+  const int64_t N = G.nodes;
+  const double s = G.eps / (G.h * G.h);
+  std::vector<double> r(N, 0.0), z(N, 0.0), p(N, 0.0), Ap(N, 0.0), D(N, 0.0);
+  std::vector<char> unk(N, 0);
+  double bb = 0.0, rz = 0.0, rr = 0.0;
+  for (int k = 0; k <= G.n[2]; ++k)
+    for (int j = 0; j <= G.n[1]; ++j)
+      for (int i = 0; i <= G.n[0]; ++i) {
+        const int64_t q0 = G.id(i, j, k);
+        if (G.dir(i, j, k)) {
+          x[q0] = G.gval(i, j, k);
+          continue;
+        }
+        unk[q0] = 1;
+      }
+  for (int k = 0; k <= G.n[2]; ++k)
+    for (int j = 0; j <= G.n[1]; ++j)
+      for (int i = 0; i <= G.n[0]; ++i) {
+        const int64_t q0 = G.id(i, j, k);
+        if (!unk[q0]) continue;
+        double ax = 0.0, b = rho[q0], d = 0.0;
+        field_links(G, i, j, k, [&](int64_t q, double w) {
+          ax += w * (x[q0] - x[q]);
+          d += w;
+          if (!unk[q]) b += s * w * x[q];
+        });
+        r[q0] = rho[q0] - s * ax;
+        D[q0] = s * d;
+        z[q0] = r[q0] / D[q0];
+        p[q0] = z[q0];
+        bb += b * b;
+        rz += r[q0] * z[q0];
+        rr += r[q0] * r[q0];
+      }
+  const double bn = std::sqrt(bb);
+  int32_t it = 0;
+  if (!(std::sqrt(rr) <= tol * bn)) {
+    for (it = 1; it <= max_iter; ++it) {
+      double pap = 0.0;
+      for (int k = 0; k <= G.n[2]; ++k)
+        for (int j = 0; j <= G.n[1]; ++j)
+          for (int i = 0; i <= G.n[0]; ++i) {
+            const int64_t q0 = G.id(i, j, k);
+            if (!unk[q0]) continue;
+            double a = 0.0;
+            field_links(G, i, j, k, [&](int64_t q, double w) { a += w * (p[q0] - p[q]); });
+            Ap[q0] = s * a;
+            pap += p[q0] * Ap[q0];
+          }
+      const double alpha = rz / pap;
+      double rz1 = 0.0;
+      rr = 0.0;
+      for (int64_t q = 0; q < N; ++q) {
+        if (!unk[q]) continue;
+        x[q] = x[q] + alpha * p[q];
+        r[q] = r[q] - alpha * Ap[q];
+        z[q] = r[q] / D[q];
+        rz1 += r[q] * z[q];
+        rr += r[q] * r[q];
+      }
+      if (std::sqrt(rr) <= tol * bn) break;
+      const double beta = rz1 / rz;
+      rz = rz1;
+      for (int64_t q = 0; q < N; ++q)
+        if (unk[q]) p[q] = z[q] + beta * p[q];
+    }
+    if (it > max_iter) it = max_iter;
+  }
+  if (iters) *iters = it;
+  if (relres) *relres = bn > 0.0 ? std::sqrt(rr) / bn : 0.0;
+  return ORC_OK;
+}
+
+// E = -grad phi at the nodes.
+void field_E(const FieldGrid& G, const double* phi, double* E[3]) {
+  for (int k = 0; k <= G.n[2]; ++k)
+    for (int j = 0; j <= G.n[1]; ++j)
+      for (int i = 0; i <= G.n[0]; ++i) {
+        const int idx[3] = {i, j, k};
+        const int64_t q0 = G.id(i, j, k);
+        const int64_t st[3] = {1, G.sx, G.sy};
+        for (int d = 0; d < 3; ++d) {
+          const int a = idx[d], n = G.n[d];
+          double e;
+          if (a > 0 && a < n) {
+            e = -(phi[q0 + st[d]] - phi[q0 - st[d]]) / (2.0 * G.h);
+          } else if (!((G.mask >> (2 * d + (a == 0 ? 0 : 1))) & 1)) {
+            e = 0.0;  // zero-Neumann face
+          } else if (n == 1) {
+            e = a == 0 ? -(phi[q0 + st[d]] - phi[q0]) / G.h : -(phi[q0] - phi[q0 - st[d]]) / G.h;
+          } else if (a == 0) {
+            e = -(-3.0 * phi[q0] + 4.0 * phi[q0 + st[d]] - phi[q0 + 2 * st[d]]) / (2.0 * G.h);
+          } else {
+            e = -(3.0 * phi[q0] - 4.0 * phi[q0 - st[d]] + phi[q0 - 2 * st[d]]) / (2.0 * G.h);
+          }
+          E[d][q0] = e;
+        }
+      }
+}
+
+FieldGrid field_grid(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t mask,
+                     const double g[6]) {
+  FieldGrid G;
+  G.n[0] = nx; G.n[1] = ny; G.n[2] = nz;
+  G.sx = nx + 1;
+  G.sy = (int64_t)(nx + 1) * (ny + 1);
+  G.nodes = G.sy * (nz + 1);
+  G.h = h;
+  G.eps = eps;
+  G.mask = mask;
+  for (int f = 0; f < 6; ++f) G.g[f] = g ? g[f] : 0.0;
+  return G;
+}
+
+}  // namespace
+
+extern "C" {
+
 // Pieces of the boundary source, exposed for the pins.
 uint64_t orc_splitmix_draw(uint64_t key, uint64_t d) { return sm_mix(key + (d + 1) * kGolden); }
 double orc_inj_uniform(uint64_t seed, int32_t step, int32_t s, int32_t f, int64_t cell, int64_t j,
@@ -972,6 +1152,25 @@ double orc_ln(double x) { return ln_series(x); }
 void orc_normals3(uint64_t key, double z[3]) {
   uint64_t d = 0;
   normals3(key, &d, z);
+}
+
+// Field solve (see above). phi: in the initial guess, out the solution (nodes
+// values). Returns 0, or -1 for invalid arguments (no Dirichlet face, h or eps
+// not > 0, tol not > 0, max_iter < 0).
+int orc_field_solve(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t dirichlet,
+                    const double* g, const double* rho, double* phi, double tol, int32_t max_iter,
+                    int32_t* iters, double* relres) {
+  if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || !(tol > 0) || max_iter < 0 ||
+      (dirichlet & 63) == 0 || (dirichlet & ~63) || !rho || !phi)
+    return ORC_E_INVALID;
+  return field_solve(field_grid(nx, ny, nz, h, eps, dirichlet, g), rho, phi, tol, max_iter, iters,
+                     relres);
+}
+
+void orc_field_E(int32_t nx, int32_t ny, int32_t nz, double h, int32_t dirichlet, const double* phi,
+                 double* Ex, double* Ey, double* Ez) {
+  double* E[3] = {Ex, Ey, Ez};
+  field_E(field_grid(nx, ny, nz, h, 1.0, dirichlet, nullptr), phi, E);
 }
 
 // Object predicate at one point (physical units), in the arithmetic of `repr`.
