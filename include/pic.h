@@ -228,6 +228,43 @@ pic_status pic_get_surface_charge(pic_ctx *ctx, int64_t nbins, double *charge, i
  * through face f (escaped[f*n_species + s]). Synchronises. */
 pic_status pic_get_counters(pic_ctx *ctx, int64_t *alive, int64_t *absorbed, int64_t *escaped);
 
+/* The field solve on the PIC mesh (the boundary value problem of §2.1 with a
+ * uniform permittivity; no immersed-interface treatment of the object):
+ * -eps lap(phi) = rho on the nodes, phi = value[f] on the Dirichlet faces f,
+ * zero normal derivative on the others (the symmetry / open faces of §3.1.3
+ * and §5.2.2). Node-centred finite volumes: each node's control volume is its
+ * dual cell clipped to the box and the right-hand side is the deposited
+ * nodal density of pic_get_rho, so a zero-Neumann face needs no extra term.
+ * Solved by Jacobi-preconditioned conjugate gradients (the PCG of §2.4) until
+ * ||r||_2 <= tol ||b||_2 or max_iter iterations, from the previous solution
+ * (zero before the first). Then E = -grad phi at the nodes (central
+ * differences; 0 normal to a zero-Neumann face; second-order one-sided on a
+ * Dirichlet face) becomes the context's node field, as pic_set_node_E would. */
+typedef struct {
+  int32_t dirichlet; /* bit f: face f (0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+) holds
+                        phi = value[f]; at least one face */
+  double value[6];
+  double eps;        /* permittivity (> 0) */
+  double tol;        /* relative residual (> 0); the paper uses 1e-6 */
+  int32_t max_iter;  /* >= 0; the paper uses 60-150 per PIC step */
+} pic_field;
+
+/* Solves for the deposit of the last pic_step (PIC_E_STATE before any) and
+ * synchronises; *iterations and *rel_residual (nullable) receive the CG
+ * iterations and ||r|| / ||b||. PIC_E_INVALID: bad field settings. Deterministic
+ * (fixed-order reductions). */
+pic_status pic_solve_field(pic_ctx *ctx, const pic_field *field, int32_t *iterations,
+                           double *rel_residual);
+
+/* Copies the context's node field (set, or from the last field solve) to host
+ * arrays of (nx+1)(ny+1)(nz+1) values, x fastest, in FP64 (FP32 forms hold it
+ * in FP32). PIC_E_STATE before any. Synchronises. */
+pic_status pic_get_node_E(pic_ctx *ctx, double *Ex, double *Ey, double *Ez);
+
+/* Copies the potential of the last pic_solve_field to phi (host, one value per
+ * node, x fastest); PIC_E_STATE before any solve. Synchronises. */
+pic_status pic_get_phi(pic_ctx *ctx, double *phi);
+
 /* Sets (inj non-NULL with faces != 0) or clears (NULL or faces == 0) the
  * injection of ambient particles, from the next pic_step on (copied; the
  * caller keeps inj). PIC_E_INVALID: a face bit beyond 5, an injecting face

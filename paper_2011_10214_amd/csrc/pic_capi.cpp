@@ -210,6 +210,12 @@ struct pic_ctx {
   pic_injection inj{};
   int64_t step_index = 0;       // pic_step steps since creation (injection key)
   int64_t *injected = nullptr;  // device [ns]: particles injected
+  bool deposited = false;       // rho holds a deposit
+  // field solve (allocated at the first solve)
+  double *fx = nullptr, *fr = nullptr, *fz = nullptr, *fp = nullptr, *fAp = nullptr,
+         *fpart = nullptr;
+  FieldCtrl *fctrl = nullptr, *fctrl_host = nullptr;
+  bool solved = false;
 };
 
 namespace {
@@ -257,6 +263,8 @@ void free_all(pic_ctx *c) {
   c->events.clear();
   if (c->flag_host) (void)hipHostFree((void *)c->flag_host);
   c->flag_host = nullptr;
+  if (c->fctrl_host) (void)hipHostFree(c->fctrl_host);
+  c->fctrl_host = nullptr;
 }
 
 hipError_t dmalloc(pic_ctx *c, void **p, int64_t bytes) {
@@ -846,6 +854,32 @@ pic_status pic_set_node_E(pic_ctx *c, const double *Ex, const double *Ey, const 
   return PIC_OK;
 }
 
+pic_status pic_get_node_E(pic_ctx *c, double *Ex, double *Ey, double *Ez) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (!Ex || !Ey || !Ez) return fail(c, PIC_E_INVALID, "field arrays must not be NULL");
+  if (!c->E_set) return fail(c, PIC_E_STATE, "no node field yet");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  const int64_t nodes = c->L.nodes;
+  const bool f64 = c->cfg.repr == PIC_REPR_FP64;
+  std::vector<char> buf(nodes * (f64 ? 32 : 16));
+  PIC_HIP(c, hipMemcpy(buf.data(), c->E, buf.size(), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < nodes; ++i) {
+    if (f64) {
+      const double *d = (const double *)buf.data() + 4 * i;
+      Ex[i] = d[0];
+      Ey[i] = d[1];
+      Ez[i] = d[2];
+    } else {
+      const float *f = (const float *)buf.data() + 4 * i;
+      Ex[i] = f[0];
+      Ey[i] = f[1];
+      Ez[i] = f[2];
+    }
+  }
+  return PIC_OK;
+}
+
 pic_status pic_set_node_E_f32_dev(pic_ctx *c, const float *Ex, const float *Ey, const float *Ez) {
   if (const pic_status s0 = check_ctx(c)) return s0;
   if (!Ex || !Ey || !Ez) return fail(c, PIC_E_INVALID, "field arrays must not be NULL");
@@ -873,6 +907,7 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
     const int pe = prof_begin(c, 0);
     PIC_HIP(c, launch_step(c->cfg.repr, c->cfg.deposit, false, P, c->stream));
     prof_end(c, pe);
+    c->deposited = true;
     return PIC_OK;
   }
   for (int k = 0; k < nsteps; ++k) {
@@ -901,6 +936,7 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
     c->cur = 1 - c->cur;
     c->since_sort++;
     c->step_index++;
+    c->deposited = true;
   }
   return PIC_OK;
 }
@@ -977,6 +1013,96 @@ pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64
     if (alive) alive[s] = c->sp[s].loaded + inj[s] - a - es;
   }
   if (escaped) std::memcpy(escaped, e.data(), e.size() * 8);
+  return PIC_OK;
+}
+
+pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
+                           double *rel_residual) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (!fs) return fail(c, PIC_E_INVALID, "field settings must not be NULL");
+  if ((fs->dirichlet & 63) == 0 || (fs->dirichlet & ~63))
+    return fail(c, PIC_E_INVALID, "dirichlet: bits 0..5, at least one face");
+  if (!(fs->eps > 0) || !is_finite(fs->eps)) return fail(c, PIC_E_INVALID, "eps must be > 0");
+  if (!(fs->tol > 0) || !is_finite(fs->tol)) return fail(c, PIC_E_INVALID, "tol must be > 0");
+  if (fs->max_iter < 0) return fail(c, PIC_E_INVALID, "max_iter must be >= 0");
+  for (int f = 0; f < 6; ++f)
+    if (!is_finite(fs->value[f])) return fail(c, PIC_E_INVALID, "face values must be finite");
+  if (!c->deposited) return fail(c, PIC_E_STATE, "no deposit yet (call pic_step first)");
+  const Dims &L = c->L;
+  const int64_t nodes = L.nodes;
+  const int32_t G = (int32_t)std::min<int64_t>(1024, (nodes + kBlock - 1) / kBlock);
+  if (!c->fx) {
+    void *q = nullptr;
+    double **vecs[5] = {&c->fx, &c->fr, &c->fz, &c->fp, &c->fAp};
+    for (double **v : vecs) {
+      if (dmalloc(c, &q, nodes * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+      *v = (double *)q;
+    }
+    if (dmalloc(c, &q, 6 * 1024 * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+    c->fpart = (double *)q;
+    if (dmalloc(c, &q, sizeof(FieldCtrl)) != hipSuccess)
+      return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+    c->fctrl = (FieldCtrl *)q;
+    if (hipHostMalloc(&q, sizeof(FieldCtrl), hipHostMallocDefault) != hipSuccess)
+      return fail(c, PIC_E_NOMEM, "hipHostMalloc failed");
+    c->fctrl_host = (FieldCtrl *)q;
+    PIC_HIP(c, launch_fill(c->fx, nodes * 8, c->stream));
+  }
+  FieldParams P{};
+  P.rho = c->rho;
+  P.x = c->fx;
+  P.r = c->fr;
+  P.z = c->fz;
+  P.p = c->fp;
+  P.Ap = c->fAp;
+  P.part = c->fpart;
+  P.ctrl = c->fctrl;
+  P.E = c->E;
+  P.n[0] = L.nx;
+  P.n[1] = L.ny;
+  P.n[2] = L.nz;
+  P.sx = L.nx + 1;
+  P.sy = (int64_t)(L.nx + 1) * (L.ny + 1);
+  P.nodes = nodes;
+  P.h = c->cfg.h;
+  P.eps = fs->eps;
+  P.s = fs->eps / (c->cfg.h * c->cfg.h);
+  P.mask = fs->dirichlet;
+  for (int f = 0; f < 6; ++f) P.g[f] = fs->value[f];
+  P.tol = fs->tol;
+  P.max_iter = fs->max_iter;
+  P.G = G;
+  PIC_HIP(c, launch_field_init(c->cfg.deposit, P, c->stream));
+  // iterations in chunks; the kernels themselves stop at convergence or
+  // max_iter, the host only stops enqueueing
+  constexpr int kChunkIters = 16;
+  for (int it = 1; it <= fs->max_iter; it += kChunkIters) {
+    for (int k = it; k < it + kChunkIters && k <= fs->max_iter; ++k)
+      PIC_HIP(c, launch_field_iter(P, (k - 1) & 1, c->stream));
+    PIC_HIP(c, hipMemcpyAsync(c->fctrl_host, c->fctrl, sizeof(FieldCtrl), hipMemcpyDeviceToHost,
+                              c->stream));
+    PIC_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->fctrl_host->converged) break;
+  }
+  PIC_HIP(c, launch_field_E(c->cfg.repr, P, c->stream));
+  PIC_HIP(c, hipMemcpyAsync(c->fctrl_host, c->fctrl, sizeof(FieldCtrl), hipMemcpyDeviceToHost,
+                            c->stream));
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  const FieldCtrl f = *c->fctrl_host;
+  if (iterations) *iterations = f.iters;
+  if (rel_residual) *rel_residual = f.bb > 0 ? std::sqrt(f.rr) / std::sqrt(f.bb) : 0.0;
+  c->E_set = true;
+  c->solved = true;
+  return PIC_OK;
+}
+
+pic_status pic_get_phi(pic_ctx *c, double *phi) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (!phi) return fail(c, PIC_E_INVALID, "phi must not be NULL");
+  if (!c->solved) return fail(c, PIC_E_STATE, "no field solve yet");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK) return st;
+  PIC_HIP(c, hipMemcpy(phi, c->fx, c->L.nodes * 8, hipMemcpyDeviceToHost));
   return PIC_OK;
 }
 

@@ -168,6 +168,32 @@ struct InjParams {
   int32_t *err;
 };
 
+// Field solve on the nodes: Jacobi-preconditioned CG for the node-centred
+// finite-volume Poisson operator (Dirichlet / zero-Neumann faces), then
+// E = -grad phi into the context's node field.
+struct FieldCtrl {
+  int32_t converged;
+  int32_t iters;
+  double rr, bb;  // last squared residual norm, squared right-hand-side norm
+};
+
+struct FieldParams {
+  const void *rho;          // the deposit (raw: fixed int64 at 2^32, or float / double)
+  double *x, *r, *z, *p, *Ap;
+  double *part;             // [6][G]: pAp, rz0, rz1, rr0, rr1, bb
+  FieldCtrl *ctrl;
+  void *E;                  // float4 / double4 per node
+  int32_t n[3];
+  int64_t sx, sy, nodes;
+  double h, eps, s;         // s = eps / h^2
+  double rho_scale;         // raw deposit -> density (2^-32 / h^3 or 1 / h^3)
+  int32_t mask;             // Dirichlet faces
+  double g[6];
+  double tol;
+  int32_t max_iter;
+  int32_t G;                // workgroups of every field kernel (partials per sum)
+};
+
 // Batched runs: many contexts (slots) advanced by one launch per step. Work
 // item b belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles + 1
 // items per slot); persistent workgroups take items from a counter. The slot
@@ -194,6 +220,11 @@ hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s);
 hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t s);
+// field solve: init (+ initial convergence check), one CG iteration (parity o:
+// the partials of the previous iteration), and E
+hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s);
+hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s);
+hipError_t launch_field_E(int repr, const FieldParams &p, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
                            int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,

@@ -1402,6 +1402,275 @@ __global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
   }
 }
 
+// ------------------------------------------------------------------ field solve
+//
+// -div(eps grad phi) = rho on the nodes (node-centred finite volumes: the flux
+// through the dual face of a link is eps w (phi_p - phi_q) h with w the
+// product of the two tangential half-width factors, 1/2 at a boundary index),
+// Dirichlet faces in a mask, zero-Neumann elsewhere; Jacobi-preconditioned
+// conjugate gradients. Every kernel runs G workgroups over the nodes; sums
+// are per-workgroup partials that every consumer adds in the same fixed
+// order, so the solve is deterministic.
+
+__device__ __forceinline__ bool f_dir(const FieldParams &P, int i, int j, int k) {
+  const int m = P.mask;
+  return ((m & 1) && i == 0) || ((m & 2) && i == P.n[0]) || ((m & 4) && j == 0) ||
+         ((m & 8) && j == P.n[1]) || ((m & 16) && k == 0) || ((m & 32) && k == P.n[2]);
+}
+
+// Dirichlet value of a node: the first Dirichlet face (in face order) it lies on
+__device__ __forceinline__ double f_gval(const FieldParams &P, int i, int j, int k) {
+  const int m = P.mask;
+  if ((m & 1) && i == 0) return P.g[0];
+  if ((m & 2) && i == P.n[0]) return P.g[1];
+  if ((m & 4) && j == 0) return P.g[2];
+  if ((m & 8) && j == P.n[1]) return P.g[3];
+  if ((m & 16) && k == 0) return P.g[4];
+  return P.g[5];
+}
+
+__device__ __forceinline__ double f_c(int a, int n) { return (a == 0 || a == n) ? 0.5 : 1.0; }
+
+// node index -> (i, j, k); node counts stay below 2^31 (1024^3 cells at most)
+__device__ __forceinline__ void f_ijk(const FieldParams &P, int64_t q, int &i, int &j, int &k) {
+  const uint32_t u = (uint32_t)q, sy = (uint32_t)P.sy, sx = (uint32_t)P.sx;
+  const uint32_t kk = u / sy, rem = u - kk * sy, jj = rem / sx;
+  k = (int)kk;
+  j = (int)jj;
+  i = (int)(rem - jj * sx);
+}
+
+// Visits the links of node (i, j, k) in the order -x, +x, -y, +y, -z, +z:
+// f(q, w) with q the neighbour's node index.
+template <class F>
+__device__ __forceinline__ void f_links(const FieldParams &P, int i, int j, int k, int64_t q0, F f) {
+  const double cx = f_c(i, P.n[0]), cy = f_c(j, P.n[1]), cz = f_c(k, P.n[2]);
+  if (i > 0) f(q0 - 1, cy * cz);
+  if (i < P.n[0]) f(q0 + 1, cy * cz);
+  if (j > 0) f(q0 - P.sx, cx * cz);
+  if (j < P.n[1]) f(q0 + P.sx, cx * cz);
+  if (k > 0) f(q0 - P.sy, cx * cy);
+  if (k < P.n[2]) f(q0 + P.sy, cx * cy);
+}
+
+// Sum over the workgroup (fixed tree order); the result in every thread.
+__device__ double block_sum(double v) {
+  __shared__ double sRed[kBlock];
+  sRed[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kBlock / 2; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) sRed[threadIdx.x] = sRed[threadIdx.x] + sRed[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double t = sRed[0];
+  __syncthreads();
+  return t;
+}
+
+// Sum of G partials, the same value in every workgroup.
+__device__ double sum_partials(const double *part, int G) {
+  double v = 0.0;
+  for (int t = threadIdx.x; t < G; t += kBlock) v = v + part[t];
+  return block_sum(v);
+}
+
+template <int D>
+__device__ __forceinline__ double f_rho(const FieldParams &P, int64_t q) {
+  if constexpr (D == PIC_DEP_FIXED64) {
+    return ((double)((const int64_t *)P.rho)[q] * 2.3283064365386963e-10) / (P.h * P.h * P.h);
+  } else if constexpr (D == PIC_DEP_ATOMIC_FP32) {
+    return (double)((const float *)P.rho)[q] / (P.h * P.h * P.h);
+  } else {
+    return ((const double *)P.rho)[q] / (P.h * P.h * P.h);
+  }
+}
+
+// r = b - A x, z = r / diag, p = z; Dirichlet nodes get x = g (and r = z = p = 0).
+template <int D>
+__global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) {
+      P.x[q] = f_gval(P, i, j, k);
+      P.r[q] = 0.0;
+      P.z[q] = 0.0;
+      P.p[q] = 0.0;
+      P.Ap[q] = 0.0;
+      continue;
+    }
+    const double xq = P.x[q];
+    const double rho = f_rho<D>(P, q);
+    double ax = 0.0, dsum = 0.0, b = rho;
+    f_links(P, i, j, k, q, [&](int64_t nb, double w) {
+      int a, c, e;
+      f_ijk(P, nb, a, c, e);
+      const bool nd = f_dir(P, a, c, e);
+      const double xn = nd ? f_gval(P, a, c, e) : P.x[nb];
+      ax = ax + w * (xq - xn);
+      dsum = dsum + w;
+      if (nd) b = b + P.s * w * xn;
+    });
+    const double r = rho - P.s * ax;
+    const double z = r / (P.s * dsum);
+    P.r[q] = r;
+    P.z[q] = z;
+    P.p[q] = z;
+    P.Ap[q] = 0.0;
+    rz = rz + r * z;
+    rr = rr + r * r;
+    bb = bb + b * b;
+  }
+  rz = block_sum(rz);
+  rr = block_sum(rr);
+  bb = block_sum(bb);
+  if (threadIdx.x == 0) {
+    P.part[1 * P.G + blockIdx.x] = rz;
+    P.part[3 * P.G + blockIdx.x] = rr;
+    P.part[5 * P.G + blockIdx.x] = bb;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void field_check0_kernel(FieldParams P) {
+  const double rr = sum_partials(P.part + 3 * P.G, P.G);
+  const double bb = sum_partials(P.part + 5 * P.G, P.G);
+  if (threadIdx.x == 0) {
+    P.ctrl->rr = rr;
+    P.ctrl->bb = bb;
+    P.ctrl->iters = 0;
+    P.ctrl->converged = __builtin_sqrt(rr) <= P.tol * __builtin_sqrt(bb) ? 1 : 0;
+  }
+}
+
+// The control block, read once per workgroup (thread 0, then shared), so that
+// every thread takes the same early exit even while workgroup 0 of the same
+// launch updates it.
+__device__ __forceinline__ FieldCtrl f_ctrl(const FieldParams &P) {
+  __shared__ FieldCtrl sCtrl;
+  if (threadIdx.x == 0) sCtrl = *P.ctrl;
+  __syncthreads();
+  const FieldCtrl c = sCtrl;
+  __syncthreads();
+  return c;
+}
+
+__device__ __forceinline__ bool f_done(const FieldCtrl &c, const FieldParams &P) {
+  return c.converged != 0 || c.iters >= P.max_iter;
+}
+
+// Ap = A p; partial p.Ap
+__global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  double pap = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) continue;
+    const double pq = P.p[q];
+    double a = 0.0;
+    f_links(P, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (pq - P.p[nb]); });
+    const double ap = P.s * a;
+    P.Ap[q] = ap;
+    pap = pap + pq * ap;
+  }
+  pap = block_sum(pap);
+  if (threadIdx.x == 0) P.part[blockIdx.x] = pap;
+}
+
+// x += alpha p, r -= alpha Ap, z = r / diag; partials r.z, r.r (parity n)
+__global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int o) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const int n = 1 - o;
+  const double alpha = sum_partials(P.part + (1 + o) * P.G, P.G) / sum_partials(P.part, P.G);
+  double rz = 0.0, rr = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) continue;
+    double dsum = 0.0;
+    f_links(P, i, j, k, q, [&](int64_t, double w) { dsum = dsum + w; });
+    const double x = P.x[q] + alpha * P.p[q];
+    const double r = P.r[q] - alpha * P.Ap[q];
+    const double z = r / (P.s * dsum);
+    P.x[q] = x;
+    P.r[q] = r;
+    P.z[q] = z;
+    rz = rz + r * z;
+    rr = rr + r * r;
+  }
+  rz = block_sum(rz);
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) {
+    P.part[(1 + n) * P.G + blockIdx.x] = rz;
+    P.part[(3 + n) * P.G + blockIdx.x] = rr;
+  }
+}
+
+// convergence test; p = z + beta p
+__global__ __launch_bounds__(kBlock) void field_dir_kernel(FieldParams P, int o) {
+  const FieldCtrl c = f_ctrl(P);
+  if (f_done(c, P)) return;  // uniform
+  const int n = 1 - o;
+  const double rr = sum_partials(P.part + (3 + n) * P.G, P.G);
+  const bool conv = __builtin_sqrt(rr) <= P.tol * __builtin_sqrt(c.bb);
+  const int it = c.iters;
+  const double beta = sum_partials(P.part + (1 + n) * P.G, P.G) /
+                      sum_partials(P.part + (1 + o) * P.G, P.G);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    P.ctrl->rr = rr;
+    P.ctrl->iters = it + 1;
+    if (conv) P.ctrl->converged = 1;
+  }
+  if (conv) return;  // uniform
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) continue;
+    P.p[q] = P.z[q] + beta * P.p[q];
+  }
+}
+
+// E = -grad phi at the nodes: central differences inside, 0 normal to a
+// zero-Neumann face, second-order one-sided differences on a Dirichlet face.
+template <int R>
+__global__ __launch_bounds__(kBlock) void field_E_kernel(FieldParams P) {
+  using T = typename RealOf<R>::T;
+  using V4 = typename Vec4Of<T>::type;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int ijk[3];
+    f_ijk(P, q, ijk[0], ijk[1], ijk[2]);
+    const int64_t st[3] = {1, P.sx, P.sy};
+    double e[3];
+    for (int d = 0; d < 3; ++d) {
+      const int a = ijk[d], n = P.n[d];
+      const double *x = P.x;
+      if (a > 0 && a < n) {
+        e[d] = -(x[q + st[d]] - x[q - st[d]]) / (2.0 * P.h);
+      } else if (!((P.mask >> (2 * d + (a == 0 ? 0 : 1))) & 1)) {
+        e[d] = 0.0;
+      } else if (n == 1) {
+        e[d] = a == 0 ? -(x[q + st[d]] - x[q]) / P.h : -(x[q] - x[q - st[d]]) / P.h;
+      } else if (a == 0) {
+        e[d] = -(-3.0 * x[q] + 4.0 * x[q + st[d]] - x[q + 2 * st[d]]) / (2.0 * P.h);
+      } else {
+        e[d] = -(3.0 * x[q] - 4.0 * x[q - st[d]] + x[q - 2 * st[d]]) / (2.0 * P.h);
+      }
+    }
+    V4 v;
+    v.x = (T)e[0];
+    v.y = (T)e[1];
+    v.z = (T)e[2];
+    v.w = T(0);
+    ((V4 *)P.E)[q] = v;
+  }
+}
+
 __global__ void fill_kernel(uint32_t *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -1626,6 +1895,45 @@ hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t 
     case PIC_REPR_FP32_CELL: return launch_inject_r<PIC_REPR_FP32_CELL>(deposit, p, grid, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s) {
+  switch (deposit) {
+    case PIC_DEP_FIXED64:
+      hipLaunchKernelGGL(field_init_kernel<PIC_DEP_FIXED64>, dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    case PIC_DEP_ATOMIC_FP32:
+      hipLaunchKernelGGL(field_init_kernel<PIC_DEP_ATOMIC_FP32>, dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    case PIC_DEP_ATOMIC_FP64:
+      hipLaunchKernelGGL(field_init_kernel<PIC_DEP_ATOMIC_FP64>, dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(field_check0_kernel, dim3(1), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s) {
+  hipLaunchKernelGGL(field_apply_kernel, dim3(p.G), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(field_update_kernel, dim3(p.G), dim3(kBlock), 0, s, p, o);
+  hipLaunchKernelGGL(field_dir_kernel, dim3(p.G), dim3(kBlock), 0, s, p, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_E(int repr, const FieldParams &p, hipStream_t s) {
+  switch (repr) {
+    case PIC_REPR_FP64:
+      hipLaunchKernelGGL(field_E_kernel<PIC_REPR_FP64>, dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    case PIC_REPR_FP32_ABS:
+      hipLaunchKernelGGL(field_E_kernel<PIC_REPR_FP32_ABS>, dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    default:
+      hipLaunchKernelGGL(field_E_kernel<PIC_REPR_FP32_CELL>, dim3(p.G), dim3(kBlock), 0, s, p);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s) {

@@ -43,6 +43,11 @@ class _Config(ctypes.Structure):
                 ("capacity", ctypes.c_int64 * MAX_SPECIES), ("stream", ctypes.c_void_p)]
 
 
+class _Field(ctypes.Structure):
+    _fields_ = [("dirichlet", ctypes.c_int32), ("value", ctypes.c_double * 6),
+                ("eps", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
 class _Injection(ctypes.Structure):
     _fields_ = [("faces", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("density", ctypes.c_double * MAX_SPECIES), ("vth", ctypes.c_double * MAX_SPECIES),
@@ -79,6 +84,10 @@ SIGNATURES = {
     "pic_set_node_E_f32_dev": (_st, [_vp, _vp, _vp, _vp]),
     "pic_step": (_st, [_vp, _i32]),
     "pic_set_injection": (_st, [_vp, ctypes.POINTER(_Injection)]),
+    "pic_solve_field": (_st, [_vp, ctypes.POINTER(_Field), ctypes.POINTER(_i32),
+                              ctypes.POINTER(ctypes.c_double)]),
+    "pic_get_phi": (_st, [_vp, _vp]),
+    "pic_get_node_E": (_st, [_vp, _vp, _vp, _vp]),
     "pic_get_injected": (_st, [_vp, _vp]),
     "pic_synchronize": (_st, [_vp]),
     "pic_get_rho": (_st, [_vp, _vp, _vp]),
@@ -323,6 +332,31 @@ class Context:
             for d in range(3):
                 c.drift[3 * s + d] = float(drift[s][d]) if drift is not None else 0.0
         self._check(lib().pic_set_injection(self._h, ctypes.byref(c)))
+
+    def solve_field(self, dirichlet: int, values=None, eps: float = 1.0, tol: float = 1e-6,
+                    max_iter: int = 150):
+        """Field solve for the last deposit (pic_solve_field); the node field
+        becomes -grad phi. Returns (iterations, relative residual)."""
+        f = _Field()
+        f.dirichlet = int(dirichlet)
+        for k in range(6):
+            f.value[k] = float(values[k]) if values is not None else 0.0
+        f.eps, f.tol, f.max_iter = float(eps), float(tol), int(max_iter)
+        it = ctypes.c_int32(0)
+        rr = ctypes.c_double(0.0)
+        self._check(lib().pic_solve_field(self._h, ctypes.byref(f), ctypes.byref(it),
+                                          ctypes.byref(rr)))
+        return it.value, rr.value
+
+    def get_node_E(self) -> np.ndarray:
+        E = [np.empty(self.cfg.nodes) for _ in range(3)]
+        self._check(lib().pic_get_node_E(self._h, *[_ptr(e) for e in E]))
+        return np.stack(E)
+
+    def get_phi(self) -> np.ndarray:
+        phi = np.empty(self.cfg.nodes)
+        self._check(lib().pic_get_phi(self._h, _ptr(phi)))
+        return phi
 
     def get_injected(self) -> np.ndarray:
         out = np.zeros(self.ns, np.int64)
