@@ -330,6 +330,10 @@ def main():
     ap.add_argument("--sort-interval", type=int, default=0,
                     help="re-plan the tile regions every K steps (0: on demand)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--field", default="off", choices=["off", "lunar", "oml"],
+                    help="close the PIC loop: a field solve after every step (lunar: phi = 0 "
+                         "at z+, zero-Neumann elsewhere; oml: phi = 0 at the max faces); "
+                         "PCG tolerance 1e-6 and at most 150 iterations as in the paper")
     ap.add_argument("--boundaries", default="open", choices=["open", "lunar"],
                     help="open: all faces remove; lunar: y- reflects and ambient plasma is "
                          "injected at x-, x+, y+, z+ every step")
@@ -416,8 +420,22 @@ def main():
     ctx.set_node_E(E)
     del E
 
+    field_mask = {"off": 0, "lunar": 32, "oml": 2 | 8 | 32}[args.field]
+
+    def advance(k):
+        if not field_mask:
+            ctx.step(k)
+            return
+        for _ in range(k):  # deposit -> field solve -> gather / push
+            ctx.step(1)
+            ctx.solve_field(field_mask, tol=1e-6, max_iter=150)
+
     log(f"warmup {args.warmup} steps")
-    ctx.step(args.warmup)
+    if field_mask:
+        ctx.step(0)
+        it, rr = ctx.solve_field(field_mask, tol=1e-6, max_iter=2000)
+        log(f"initial field: {it} iterations, relative residual {rr:.2e}")
+    advance(args.warmup)
     ctx.synchronize()
     alive0, _, _ = ctx.get_counters()
     injected0 = ctx.get_injected()
@@ -428,7 +446,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    ctx.step(args.steps)
+    advance(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
@@ -491,8 +509,19 @@ def main():
             "sort": prof.sort_ms / args.steps,
             "rho_clear": prof.clear_ms / args.steps,
             "injection": prof.inject_ms / args.steps,
+            "field_solve": prof.field_ms / args.steps,
         },
     }
+    if field_mask:
+        nodes = (w.nx + 1) * (w.ny + 1) * (w.nz + 1)
+        iters = prof.field_iterations / max(1, prof.field_solves)
+        out["config"]["field"] = (f"{args.field}: Dirichlet faces mask {field_mask}, PCG tol 1e-6, "
+                                  "max 150 iterations, warm start")
+        out["field_solve"] = {
+            "ms_per_solve": prof.field_ms / max(1, prof.field_solves),
+            "iterations_per_solve": iters,
+            "nodes": nodes,
+        }
     if inj:
         out["config"]["boundaries"] = ("lunar: y- reflects; ambient plasma injected at x-, x+, y+, "
                                        "z+ (ghost slabs, drifting Maxwellian)")

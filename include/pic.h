@@ -309,6 +309,9 @@ typedef struct {
   int64_t particle_steps; /* particles alive at the start of each step, summed */
   int64_t inject_launches; /* injection launches (pic_set_injection) */
   double inject_ms;
+  int64_t field_solves;    /* pic_solve_field calls */
+  double field_ms;         /* device time from the solve's first to last kernel */
+  int64_t field_iterations; /* CG iterations, summed */
 } pic_profile;
 
 /* Enables (on != 0) or disables event timing and resets the totals. */

@@ -159,7 +159,7 @@ int64_t footprint(const pic_config &c) {
 }
 
 struct Ev {
-  int kind;  // 0 step, 1 sort, 2 clear, 3 injection
+  int kind;  // 0 step, 1 sort, 2 clear, 3 injection, 4 field solve
   hipEvent_t a, b;
 };
 
@@ -314,6 +314,9 @@ void prof_collect(pic_ctx *c) {
       } else if (e.kind == 3) {
         c->acc.inject_launches++;
         c->acc.inject_ms += ms;
+      } else if (e.kind == 4) {
+        c->acc.field_solves++;
+        c->acc.field_ms += ms;
       } else {
         c->acc.clear_launches++;
         c->acc.clear_ms += ms;
@@ -1072,6 +1075,7 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   P.tol = fs->tol;
   P.max_iter = fs->max_iter;
   P.G = G;
+  const int pe = prof_begin(c, 4);
   PIC_HIP(c, launch_field_init(c->cfg.deposit, P, c->stream));
   // iterations in chunks; the kernels themselves stop at convergence or
   // max_iter, the host only stops enqueueing
@@ -1085,10 +1089,12 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
     if (c->fctrl_host->converged) break;
   }
   PIC_HIP(c, launch_field_E(c->cfg.repr, P, c->stream));
+  prof_end(c, pe);
   PIC_HIP(c, hipMemcpyAsync(c->fctrl_host, c->fctrl, sizeof(FieldCtrl), hipMemcpyDeviceToHost,
                             c->stream));
   PIC_HIP(c, hipStreamSynchronize(c->stream));
   const FieldCtrl f = *c->fctrl_host;
+  if (c->prof) c->acc.field_iterations += f.iters;
   if (iterations) *iterations = f.iters;
   if (rel_residual) *rel_residual = f.bb > 0 ? std::sqrt(f.rr) / std::sqrt(f.bb) : 0.0;
   c->E_set = true;

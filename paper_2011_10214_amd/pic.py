@@ -66,7 +66,8 @@ class _Profile(ctypes.Structure):
                 ("sort_launches", ctypes.c_int64), ("sort_ms", ctypes.c_double),
                 ("clear_launches", ctypes.c_int64), ("clear_ms", ctypes.c_double),
                 ("particle_steps", ctypes.c_int64), ("inject_launches", ctypes.c_int64),
-                ("inject_ms", ctypes.c_double)]
+                ("inject_ms", ctypes.c_double), ("field_solves", ctypes.c_int64),
+                ("field_ms", ctypes.c_double), ("field_iterations", ctypes.c_int64)]
 
 
 _vp = ctypes.c_void_p
@@ -235,6 +236,9 @@ class Profile:
     particle_steps: int
     inject_launches: int = 0
     inject_ms: float = 0.0
+    field_solves: int = 0
+    field_ms: float = 0.0
+    field_iterations: int = 0
 
 
 class Context:
@@ -434,7 +438,8 @@ class Context:
         p = _Profile()
         self._check(lib().pic_profile_read(self._h, ctypes.byref(p)))
         return Profile(p.step_launches, p.step_ms, p.sort_launches, p.sort_ms, p.clear_launches,
-                       p.clear_ms, p.particle_steps, p.inject_launches, p.inject_ms)
+                       p.clear_ms, p.particle_steps, p.inject_launches, p.inject_ms,
+                       p.field_solves, p.field_ms, p.field_iterations)
 
 
 def footprint_bytes(cfg: Config) -> int:
