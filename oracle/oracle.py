@@ -97,7 +97,10 @@ def lib():
         L.orc_field_solve.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_double,
                                                              ctypes.c_int32, _dp, _dp, _dp,
                                                              ctypes.c_double, ctypes.c_int32,
-                                                             _i32p, _dp]
+                                                             ctypes.c_int32, _i32p, _dp, _i32p]
+        L.orc_field_vcycle.restype = ctypes.c_int
+        L.orc_field_vcycle.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_double,
+                                                              ctypes.c_int32, _dp, _dp]
         L.orc_field_E.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_int32, _dp,
                                                          _dp, _dp, _dp]
         L.orc_object_hit.restype = ctypes.c_int32
@@ -333,10 +336,15 @@ def normals3(key: int) -> np.ndarray:
     return z
 
 
+PRECONDITIONERS = {"multigrid": 0, "jacobi": 1}
+
+
 def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=None, tol=1e-10,
-                max_iter=10000):
+                max_iter=10000, precond="multigrid", info=None):
     """Solves the field problem on the nodes (see the oracle source); returns
-    (phi, iterations, relative residual)."""
+    (phi, iterations, relative residual). precond "multigrid" uses the V-cycle
+    where the grid coarsens (else Jacobi); a dict passed as info gets the
+    multigrid level count used ("levels", 0 for Jacobi)."""
     nodes = (nx + 1) * (ny + 1) * (nz + 1)
     rho = _c(rho, np.float64).ravel()
     if rho.size != nodes:
@@ -345,13 +353,31 @@ def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=No
     g = _c(values if values is not None else np.zeros(6), np.float64)
     it = ctypes.c_int32(0)
     rr = ctypes.c_double(0.0)
+    lv = ctypes.c_int32(0)
     rc = lib().orc_field_solve(nx, ny, nz, float(h), float(eps), int(dirichlet),
                                g.ctypes.data_as(_dp), rho.ctypes.data_as(_dp),
                                phi.ctypes.data_as(_dp), float(tol), int(max_iter),
-                               ctypes.byref(it), ctypes.byref(rr))
+                               PRECONDITIONERS[precond], ctypes.byref(it), ctypes.byref(rr),
+                               ctypes.byref(lv))
     if rc != 0:
         raise OracleError(f"oracle returned {rc}")
+    if info is not None:
+        info["levels"] = lv.value
     return phi, it.value, rr.value
+
+
+def field_vcycle(nx, ny, nz, r, dirichlet, h=1.0, eps=1.0):
+    """One multigrid V-cycle z = B r (homogeneous Dirichlet faces); returns
+    (z, levels), z None when the grid does not coarsen."""
+    r = _c(r, np.float64).ravel()
+    if r.size != (nx + 1) * (ny + 1) * (nz + 1):
+        raise ValueError("r has the wrong size")
+    z = np.zeros(r.size)
+    rc = lib().orc_field_vcycle(nx, ny, nz, float(h), float(eps), int(dirichlet),
+                                r.ctypes.data_as(_dp), z.ctypes.data_as(_dp))
+    if rc < 0:
+        raise OracleError(f"oracle returned {rc}")
+    return (z if rc > 0 else None), rc
 
 
 def field_E(nx, ny, nz, phi, dirichlet, h=1.0) -> np.ndarray:

@@ -980,12 +980,14 @@ namespace {
 // control volume is rho_p h^3 with rho_p the deposited nodal density (which
 // at a boundary node already counts only the inside part of the cloud). So
 //   (A phi)_p = eps / h^2 sum_links w (phi_p - phi_q) = rho_p,
-// symmetric positive definite once one face is Dirichlet. Solved by conjugate
-// gradients with the Jacobi preconditioner (the PCG of §2.4) from the initial
-// guess in phi, until ||r||_2 <= tol ||b||_2 (b: rho plus the Dirichlet
-// terms) or max_iter iterations. E = -grad phi at the nodes: central
-// differences inside; on a Neumann face the normal component is 0; on a
-// Dirichlet face the second-order one-sided difference.
+// symmetric positive definite once one face is Dirichlet. Solved by
+// preconditioned conjugate gradients (the PCG of §2.4) from the initial guess
+// in phi, until ||r||_2 <= tol ||b||_2 (b: rho plus the Dirichlet terms) or
+// max_iter iterations. The paper leaves the preconditioner open; two are
+// here: Jacobi (z = r / diag A), and one geometric multigrid V-cycle (below).
+// E = -grad phi at the nodes: central differences inside; on a Neumann face
+// the normal component is 0; on a Dirichlet face the second-order one-sided
+// difference.
 
 struct FieldGrid {
   int32_t n[3];
@@ -1022,8 +1024,187 @@ void field_links(const FieldGrid& G, int i, int j, int k, F f) {
   if (k < G.n[2]) f(p + G.sy, G.c(0, i) * G.c(1, j));
 }
 
+FieldGrid field_grid(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t mask,
+                     const double g[6]);
+
+// ---- multigrid V-cycle preconditioner ----------------------------------------
+//
+// Textbook geometric multigrid on nested node grids. Level l + 1 takes every
+// other node of level l (all cell counts even), spacing 2h, the same faces and
+// the same finite-volume operator (rediscretised, homogeneous Dirichlet values:
+// the V-cycle acts on corrections). Grids are coarsened while a level has more
+// than kMgCoarseNodes nodes, at most kMgLevels levels; the coarsest level is
+// solved exactly (Cholesky). A grid that cannot reach kMgCoarseNodes so, or is
+// already that small, keeps the Jacobi preconditioner.
+//   prolongation P: trilinear interpolation of the coarse corrections;
+//   restriction R = P^T / 8 (the coarse density of the fine residual charge:
+//     a residual is a density, charge over h^3, and h_c^3 = 8 h^3);
+//   smoother: kMgSweeps damped-Jacobi sweeps e += w (b - A e) / diag A before
+//     the coarse correction and as many after it.
+// With the same smoother before and after, R proportional to P^T and an exact
+// (symmetric) coarsest solve, one V-cycle from a zero guess is a symmetric
+// positive definite linear map of the residual (w * eigenvalues of
+// diag^-1 A < 2), so CG stays CG.
+
+constexpr int kMgLevels = 8;
+constexpr int64_t kMgCoarseNodes = 1024;
+constexpr int kMgSweeps = 2;
+constexpr double kMgOmega = 6.0 / 7.0;
+
+struct Multigrid {
+  std::vector<FieldGrid> lv;        // level 0: the PIC mesh
+  std::vector<int64_t> unk;         // coarsest level: node of each unknown
+  std::vector<double> chol;         // coarsest level: Cholesky factor (row-major, lower)
+};
+
+bool dirichlet_node(const FieldGrid& G, int64_t q) {
+  const int i = (int)(q % G.sx), j = (int)((q / G.sx) % (G.n[1] + 1)), k = (int)(q / G.sy);
+  return G.dir(i, j, k);
+}
+
+// Levels and the coarsest factor; false when the grid does not coarsen so.
+bool mg_setup(const FieldGrid& G0, Multigrid& M) {
+  M.lv.assign(1, G0);
+  while (M.lv.back().nodes > kMgCoarseNodes && (int)M.lv.size() < kMgLevels) {
+    const FieldGrid& f = M.lv.back();
+    if (f.n[0] % 2 || f.n[1] % 2 || f.n[2] % 2) break;
+    M.lv.push_back(field_grid(f.n[0] / 2, f.n[1] / 2, f.n[2] / 2, 2.0 * f.h, f.eps, f.mask, f.g));
+  }
+  if (M.lv.size() < 2 || M.lv.back().nodes > kMgCoarseNodes) return false;
+  const FieldGrid& C = M.lv.back();
+  const double s = C.eps / (C.h * C.h);
+  std::vector<int64_t> pos(C.nodes, -1);
+  for (int64_t q = 0; q < C.nodes; ++q)
+    if (!dirichlet_node(C, q)) {
+      pos[q] = (int64_t)M.unk.size();
+      M.unk.push_back(q);
+    }
+  const int64_t m = (int64_t)M.unk.size();
+  std::vector<double> A(m * m, 0.0);
+  for (int64_t u = 0; u < m; ++u) {
+    const int64_t q0 = M.unk[u];
+    const int i = (int)(q0 % C.sx), j = (int)((q0 / C.sx) % (C.n[1] + 1)), k = (int)(q0 / C.sy);
+    field_links(C, i, j, k, [&](int64_t q, double w) {
+      A[u * m + u] += s * w;
+      if (pos[q] >= 0) A[u * m + pos[q]] -= s * w;
+    });
+  }
+  // A = L L^T
+  M.chol.assign(m * m, 0.0);
+  for (int64_t r = 0; r < m; ++r)
+    for (int64_t c = 0; c <= r; ++c) {
+      double v = A[r * m + c];
+      for (int64_t t = 0; t < c; ++t) v -= M.chol[r * m + t] * M.chol[c * m + t];
+      M.chol[r * m + c] = r == c ? std::sqrt(v) : v / M.chol[c * m + c];
+    }
+  return true;
+}
+
+// (A e)_p at an unknown node of a level, e = 0 on the Dirichlet nodes.
+double mg_apply(const FieldGrid& G, const std::vector<double>& e, int i, int j, int k) {
+  const int64_t p = G.id(i, j, k);
+  double a = 0.0;
+  field_links(G, i, j, k, [&](int64_t q, double w) { a += w * (e[p] - e[q]); });
+  return G.eps / (G.h * G.h) * a;
+}
+
+double mg_diag(const FieldGrid& G, int i, int j, int k) {
+  double d = 0.0;
+  field_links(G, i, j, k, [&](int64_t, double w) { d += w; });
+  return G.eps / (G.h * G.h) * d;
+}
+
+void mg_jacobi(const FieldGrid& G, const std::vector<double>& b, std::vector<double>& e) {
+  std::vector<double> out(G.nodes, 0.0);
+  for (int k = 0; k <= G.n[2]; ++k)
+    for (int j = 0; j <= G.n[1]; ++j)
+      for (int i = 0; i <= G.n[0]; ++i) {
+        if (G.dir(i, j, k)) continue;
+        const int64_t p = G.id(i, j, k);
+        out[p] = e[p] + kMgOmega * (b[p] - mg_apply(G, e, i, j, k)) / mg_diag(G, i, j, k);
+      }
+  e.swap(out);
+}
+
+// coarse index and weight of the 1 or 2 coarse nodes a fine index interpolates from
+int mg_parents(int a, int c[2], double w[2]) {
+  if (a % 2 == 0) {
+    c[0] = a / 2; w[0] = 1.0;
+    return 1;
+  }
+  c[0] = (a - 1) / 2; c[1] = (a + 1) / 2; w[0] = w[1] = 0.5;
+  return 2;
+}
+
+// Visits the coarse parents of fine node (i, j, k): f(coarse node, weight).
+template <class F>
+void mg_each_parent(const FieldGrid& C, int i, int j, int k, F f) {
+  int ci[2], cj[2], ck[2];
+  double wi[2], wj[2], wk[2];
+  const int ni = mg_parents(i, ci, wi), nj = mg_parents(j, cj, wj), nk = mg_parents(k, ck, wk);
+  for (int c = 0; c < nk; ++c)
+    for (int b = 0; b < nj; ++b)
+      for (int a = 0; a < ni; ++a) f(C.id(ci[a], cj[b], ck[c]), wi[a] * wj[b] * wk[c]);
+}
+
+void mg_vcycle(const Multigrid& M, size_t l, const std::vector<double>& b, std::vector<double>& e) {
+  const FieldGrid& G = M.lv[l];
+  e.assign(G.nodes, 0.0);
+  if (l + 1 == M.lv.size()) {  // exact solve: L y = b, L^T e = y
+    const int64_t m = (int64_t)M.unk.size();
+    std::vector<double> y(m);
+    for (int64_t r = 0; r < m; ++r) {
+      double v = b[M.unk[r]];
+      for (int64_t t = 0; t < r; ++t) v -= M.chol[r * m + t] * y[t];
+      y[r] = v / M.chol[r * m + r];
+    }
+    for (int64_t r = m - 1; r >= 0; --r) {
+      double v = y[r];
+      for (int64_t t = r + 1; t < m; ++t) v -= M.chol[t * m + r] * e[M.unk[t]];
+      e[M.unk[r]] = v / M.chol[r * m + r];
+    }
+    return;
+  }
+  for (int t = 0; t < kMgSweeps; ++t) mg_jacobi(G, b, e);
+  const FieldGrid& C = M.lv[l + 1];
+  std::vector<double> bc(C.nodes, 0.0), ec;
+  for (int k = 0; k <= G.n[2]; ++k)  // bc = P^T (b - A e) / 8
+    for (int j = 0; j <= G.n[1]; ++j)
+      for (int i = 0; i <= G.n[0]; ++i) {
+        if (G.dir(i, j, k)) continue;
+        const double res = b[G.id(i, j, k)] - mg_apply(G, e, i, j, k);
+        mg_each_parent(C, i, j, k, [&](int64_t Q, double w) { bc[Q] += w * res / 8.0; });
+      }
+  for (int64_t Q = 0; Q < C.nodes; ++Q)
+    if (dirichlet_node(C, Q)) bc[Q] = 0.0;
+  mg_vcycle(M, l + 1, bc, ec);
+  for (int k = 0; k <= G.n[2]; ++k)  // e += P ec
+    for (int j = 0; j <= G.n[1]; ++j)
+      for (int i = 0; i <= G.n[0]; ++i) {
+        if (G.dir(i, j, k)) continue;
+        double v = 0.0;
+        mg_each_parent(C, i, j, k, [&](int64_t Q, double w) { v += w * ec[Q]; });
+        e[G.id(i, j, k)] += v;
+      }
+  for (int t = 0; t < kMgSweeps; ++t) mg_jacobi(G, b, e);
+}
+
 int field_solve(const FieldGrid& G, const double* rho, double* x, double tol, int32_t max_iter,
-                int32_t* iters, double* relres) {
+                int32_t precond, int32_t* iters, double* relres, int32_t* levels) {
+  Multigrid M;
+  const bool mg = precond == 0 && mg_setup(G, M);
+  if (levels) *levels = mg ? (int32_t)M.lv.size() : 0;
+  std::vector<double> rv, zv;
+  // z = B r
+  auto precondition = [&](const std::vector<double>& r, std::vector<double>& z,
+                          const std::vector<double>& D, const std::vector<char>& unk) {
+    if (mg) {
+      mg_vcycle(M, 0, r, zv);
+      for (int64_t q = 0; q < G.nodes; ++q) z[q] = unk[q] ? zv[q] : 0.0;
+    } else {
+      for (int64_t q = 0; q < G.nodes; ++q) z[q] = unk[q] ? r[q] / D[q] : 0.0;
+    }
+  };
   const int64_t N = G.nodes;
   const double s = G.eps / (G.h * G.h);
   std::vector<double> r(N, 0.0), z(N, 0.0), p(N, 0.0), Ap(N, 0.0), D(N, 0.0);
@@ -1052,15 +1233,17 @@ int field_solve(const FieldGrid& G, const double* rho, double* x, double tol, in
         });
         r[q0] = rho[q0] - s * ax;
         D[q0] = s * d;
-        z[q0] = r[q0] / D[q0];
-        p[q0] = z[q0];
         bb += b * b;
-        rz += r[q0] * z[q0];
         rr += r[q0] * r[q0];
       }
   const double bn = std::sqrt(bb);
   int32_t it = 0;
   if (!(std::sqrt(rr) <= tol * bn)) {
+    precondition(r, z, D, unk);
+    for (int64_t q = 0; q < N; ++q) {
+      p[q] = z[q];
+      rz += r[q] * z[q];
+    }
     for (it = 1; it <= max_iter; ++it) {
       double pap = 0.0;
       for (int k = 0; k <= G.n[2]; ++k)
@@ -1074,17 +1257,17 @@ int field_solve(const FieldGrid& G, const double* rho, double* x, double tol, in
             pap += p[q0] * Ap[q0];
           }
       const double alpha = rz / pap;
-      double rz1 = 0.0;
       rr = 0.0;
       for (int64_t q = 0; q < N; ++q) {
         if (!unk[q]) continue;
         x[q] = x[q] + alpha * p[q];
         r[q] = r[q] - alpha * Ap[q];
-        z[q] = r[q] / D[q];
-        rz1 += r[q] * z[q];
         rr += r[q] * r[q];
       }
       if (std::sqrt(rr) <= tol * bn) break;
+      precondition(r, z, D, unk);
+      double rz1 = 0.0;
+      for (int64_t q = 0; q < N; ++q) rz1 += r[q] * z[q];
       const double beta = rz1 / rz;
       rz = rz1;
       for (int64_t q = 0; q < N; ++q)
@@ -1126,7 +1309,7 @@ void field_E(const FieldGrid& G, const double* phi, double* E[3]) {
 
 FieldGrid field_grid(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t mask,
                      const double g[6]) {
-  FieldGrid G;
+  FieldGrid G{};
   G.n[0] = nx; G.n[1] = ny; G.n[2] = nz;
   G.sx = nx + 1;
   G.sy = (int64_t)(nx + 1) * (ny + 1);
@@ -1155,16 +1338,37 @@ void orc_normals3(uint64_t key, double z[3]) {
 }
 
 // Field solve (see above). phi: in the initial guess, out the solution (nodes
-// values). Returns 0, or -1 for invalid arguments (no Dirichlet face, h or eps
-// not > 0, tol not > 0, max_iter < 0).
+// values). precond: 0 multigrid V-cycle where the grid coarsens (else Jacobi),
+// 1 Jacobi; *levels gets the multigrid level count used (0: Jacobi). Returns
+// 0, or -1 for invalid arguments (no Dirichlet face, h or eps not > 0, tol not
+// > 0, max_iter < 0, precond not 0 or 1).
 int orc_field_solve(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t dirichlet,
                     const double* g, const double* rho, double* phi, double tol, int32_t max_iter,
-                    int32_t* iters, double* relres) {
+                    int32_t precond, int32_t* iters, double* relres, int32_t* levels) {
   if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || !(tol > 0) || max_iter < 0 ||
-      (dirichlet & 63) == 0 || (dirichlet & ~63) || !rho || !phi)
+      (dirichlet & 63) == 0 || (dirichlet & ~63) || !rho || !phi || precond < 0 || precond > 1)
     return ORC_E_INVALID;
-  return field_solve(field_grid(nx, ny, nz, h, eps, dirichlet, g), rho, phi, tol, max_iter, iters,
-                     relres);
+  return field_solve(field_grid(nx, ny, nz, h, eps, dirichlet, g), rho, phi, tol, max_iter, precond,
+                     iters, relres, levels);
+}
+
+// One multigrid V-cycle z = B r on the grid (homogeneous Dirichlet faces in
+// the mask), for the pins of the preconditioner. Returns the level count, or
+// 0 when the grid does not coarsen (z untouched), -1 for invalid arguments.
+int orc_field_vcycle(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t dirichlet,
+                     const double* r, double* z) {
+  if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || (dirichlet & 63) == 0 ||
+      (dirichlet & ~63) || !r || !z)
+    return ORC_E_INVALID;
+  const FieldGrid G = field_grid(nx, ny, nz, h, eps, dirichlet, nullptr);
+  Multigrid M;
+  if (!mg_setup(G, M)) return 0;
+  std::vector<double> b(r, r + G.nodes), e;
+  for (int64_t q = 0; q < G.nodes; ++q)
+    if (dirichlet_node(G, q)) b[q] = 0.0;
+  mg_vcycle(M, 0, b, e);
+  for (int64_t q = 0; q < G.nodes; ++q) z[q] = e[q];
+  return (int)M.lv.size();
 }
 
 void orc_field_E(int32_t nx, int32_t ny, int32_t nz, double h, int32_t dirichlet, const double* phi,
