@@ -235,11 +235,24 @@ pic_status pic_get_counters(pic_ctx *ctx, int64_t *alive, int64_t *absorbed, int
  * and §5.2.2). Node-centred finite volumes: each node's control volume is its
  * dual cell clipped to the box and the right-hand side is the deposited
  * nodal density of pic_get_rho, so a zero-Neumann face needs no extra term.
- * Solved by Jacobi-preconditioned conjugate gradients (the PCG of §2.4) until
+ * Solved by preconditioned conjugate gradients (the PCG of §2.4) until
  * ||r||_2 <= tol ||b||_2 or max_iter iterations, from the previous solution
  * (zero before the first). Then E = -grad phi at the nodes (central
  * differences; 0 normal to a zero-Neumann face; second-order one-sided on a
- * Dirichlet face) becomes the context's node field, as pic_set_node_E would. */
+ * Dirichlet face) becomes the context's node field, as pic_set_node_E would.
+ *
+ * Preconditioners (the paper does not fix one):
+ *   PIC_PRECOND_MULTIGRID: one geometric multigrid V-cycle on nested node
+ *     grids (every other node, spacing doubled, while the grid has more than
+ *     1024 nodes and all three cell counts are even, at most 8 levels; two
+ *     damped-Jacobi sweeps before and after the coarse correction, full-
+ *     weighting restriction, trilinear prolongation, exact solve on the
+ *     coarsest grid, whose inverse is computed on the host once per set of
+ *     Dirichlet faces and eps). A grid that does not coarsen to at most 1024
+ *     nodes, or has at most 1024, uses Jacobi; pic_get_field_levels tells.
+ *     The iteration count does not grow with the grid.
+ *   PIC_PRECOND_JACOBI: z = r / diag(A). */
+enum { PIC_PRECOND_MULTIGRID = 0, PIC_PRECOND_JACOBI = 1 };
 typedef struct {
   int32_t dirichlet; /* bit f: face f (0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+) holds
                         phi = value[f]; at least one face */
@@ -247,6 +260,7 @@ typedef struct {
   double eps;        /* permittivity (> 0) */
   double tol;        /* relative residual (> 0); the paper uses 1e-6 */
   int32_t max_iter;  /* >= 0; the paper uses 60-150 per PIC step */
+  int32_t preconditioner; /* PIC_PRECOND_* */
 } pic_field;
 
 /* Solves for the deposit of the last pic_step (PIC_E_STATE before any) and
@@ -264,6 +278,10 @@ pic_status pic_get_node_E(pic_ctx *ctx, double *Ex, double *Ey, double *Ez);
 /* Copies the potential of the last pic_solve_field to phi (host, one value per
  * node, x fastest); PIC_E_STATE before any solve. Synchronises. */
 pic_status pic_get_phi(pic_ctx *ctx, double *phi);
+
+/* *levels = the multigrid level count of the last pic_solve_field (0: the
+ * Jacobi preconditioner ran); PIC_E_STATE before any solve. */
+pic_status pic_get_field_levels(pic_ctx *ctx, int32_t *levels);
 
 /* Sets (inj non-NULL with faces != 0) or clears (NULL or faces == 0) the
  * injection of ambient particles, from the next pic_step on (copied; the

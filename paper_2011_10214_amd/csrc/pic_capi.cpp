@@ -216,6 +216,15 @@ struct pic_ctx {
          *fpart = nullptr;
   FieldCtrl *fctrl = nullptr, *fctrl_host = nullptr;
   bool solved = false;
+  // multigrid preconditioner (planned and allocated at the first multigrid solve)
+  int32_t mg_levels = -1;       // -1 not planned; 0 the grid does not coarsen
+  MgLevel mg[kMaxLevels] = {};
+  double *mg_ainv = nullptr;    // coarsest inverse (m x m)
+  int32_t *mg_umap = nullptr;   // coarsest unknowns' nodes
+  int32_t mg_m = 0;
+  int32_t mg_mask = -1;         // faces and eps the inverse was computed for
+  double mg_eps = 0.0;
+  int32_t field_levels = 0;     // of the last solve
 };
 
 namespace {
@@ -1019,6 +1028,114 @@ pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64
   return PIC_OK;
 }
 
+namespace {
+
+int64_t level_nodes(const MgLevel &L) { return L.nodes; }
+
+MgLevel make_level(int nx, int ny, int nz) {
+  MgLevel L{};
+  L.n[0] = nx;
+  L.n[1] = ny;
+  L.n[2] = nz;
+  L.sx = nx + 1;
+  L.sy = (int64_t)(nx + 1) * (ny + 1);
+  L.nodes = L.sy * (nz + 1);
+  L.G = (int32_t)std::min<int64_t>(1024, (L.nodes + kBlock - 1) / kBlock);
+  return L;
+}
+
+// Levels of the V-cycle: halve all three cell counts while the level has
+// more than kCoarseNodes nodes and all are even; 0 unless that ends at two
+// or more levels with at most kCoarseNodes nodes on the coarsest.
+int32_t mg_plan(const Dims &D, MgLevel *lv) {
+  lv[0] = make_level(D.nx, D.ny, D.nz);
+  int32_t n = 1;
+  while (level_nodes(lv[n - 1]) > kCoarseNodes && n < kMaxLevels) {
+    const MgLevel &f = lv[n - 1];
+    if ((f.n[0] | f.n[1] | f.n[2]) & 1) break;
+    lv[n] = make_level(f.n[0] / 2, f.n[1] / 2, f.n[2] / 2);
+    ++n;
+  }
+  return (n >= 2 && level_nodes(lv[n - 1]) <= kCoarseNodes) ? n : 0;
+}
+
+bool level_dir(const MgLevel &L, int mask, int i, int j, int k) {
+  return ((mask & 1) && i == 0) || ((mask & 2) && i == L.n[0]) || ((mask & 4) && j == 0) ||
+         ((mask & 8) && j == L.n[1]) || ((mask & 16) && k == 0) || ((mask & 32) && k == L.n[2]);
+}
+
+// The coarsest level's operator on its unknowns (non-Dirichlet nodes, in node
+// order), inverted on the host: A = L L^T, W = L^-1, A^-1 = W^T W. Returns
+// false if A is not positive definite (it always is with a Dirichlet face).
+bool coarse_inverse(const MgLevel &C, int mask, double s, std::vector<double> &inv,
+                    std::vector<int32_t> &umap) {
+  std::vector<int64_t> pos(C.nodes, -1);
+  umap.clear();
+  for (int k = 0; k <= C.n[2]; ++k)
+    for (int j = 0; j <= C.n[1]; ++j)
+      for (int i = 0; i <= C.n[0]; ++i)
+        if (!level_dir(C, mask, i, j, k)) {
+          const int64_t q = i + C.sx * j + C.sy * k;
+          pos[q] = (int64_t)umap.size();
+          umap.push_back((int32_t)q);
+        }
+  const int64_t m = (int64_t)umap.size();
+  std::vector<double> A(m * m, 0.0), W(m * m, 0.0);
+  auto cw = [&](int a, int n) { return (a == 0 || a == n) ? 0.5 : 1.0; };
+  for (int64_t u = 0; u < m; ++u) {
+    const int64_t q = umap[u];
+    const int i = (int)(q % C.sx), j = (int)((q / C.sx) % (C.n[1] + 1)), k = (int)(q / C.sy);
+    const double wx = cw(j, C.n[1]) * cw(k, C.n[2]), wy = cw(i, C.n[0]) * cw(k, C.n[2]),
+                 wz = cw(i, C.n[0]) * cw(j, C.n[1]);
+    const struct { bool ok; int64_t nb; double w; } links[6] = {
+        {i > 0, q - 1, wx},         {i < C.n[0], q + 1, wx},    {j > 0, q - C.sx, wy},
+        {j < C.n[1], q + C.sx, wy}, {k > 0, q - C.sy, wz},      {k < C.n[2], q + C.sy, wz}};
+    for (const auto &L : links) {
+      if (!L.ok) continue;
+      A[u * m + u] += s * L.w;
+      if (pos[L.nb] >= 0) A[u * m + pos[L.nb]] -= s * L.w;
+    }
+  }
+  for (int64_t r = 0; r < m; ++r)  // Cholesky, lower factor in place
+    for (int64_t c = 0; c <= r; ++c) {
+      double v = A[r * m + c];
+      for (int64_t t = 0; t < c; ++t) v -= A[r * m + t] * A[c * m + t];
+      if (r == c) {
+        if (!(v > 0.0)) return false;
+        A[r * m + r] = std::sqrt(v);
+      } else {
+        A[r * m + c] = v / A[c * m + c];
+      }
+    }
+  for (int64_t c = 0; c < m; ++c) {  // W = L^-1 (lower)
+    W[c * m + c] = 1.0 / A[c * m + c];
+    for (int64_t r = c + 1; r < m; ++r) {
+      double v = 0.0;
+      for (int64_t t = c; t < r; ++t) v += A[r * m + t] * W[t * m + c];
+      W[r * m + c] = -v / A[r * m + r];
+    }
+  }
+  inv.assign(m * m, 0.0);  // A^-1 = W^T W, by rows of W
+  for (int64_t t = 0; t < m; ++t)
+    for (int64_t a = 0; a <= t; ++a) {
+      const double wa = W[t * m + a];
+      for (int64_t b = a; b <= t; ++b) inv[a * m + b] += wa * W[t * m + b];
+    }
+  for (int64_t a = 0; a < m; ++a)
+    for (int64_t b = 0; b < a; ++b) inv[a * m + b] = inv[b * m + a];
+  return true;
+}
+
+}  // namespace
+
+pic_status pic_get_field_levels(pic_ctx *c, int32_t *levels) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (!levels) return fail(c, PIC_E_INVALID, "levels must not be NULL");
+  if (!c->solved) return fail(c, PIC_E_STATE, "no field solve yet");
+  *levels = c->field_levels;
+  return PIC_OK;
+}
+
 pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
                            double *rel_residual) {
   if (const pic_status s0 = check_ctx(c)) return s0;
@@ -1028,6 +1145,8 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   if (!(fs->eps > 0) || !is_finite(fs->eps)) return fail(c, PIC_E_INVALID, "eps must be > 0");
   if (!(fs->tol > 0) || !is_finite(fs->tol)) return fail(c, PIC_E_INVALID, "tol must be > 0");
   if (fs->max_iter < 0) return fail(c, PIC_E_INVALID, "max_iter must be >= 0");
+  if (fs->preconditioner != PIC_PRECOND_MULTIGRID && fs->preconditioner != PIC_PRECOND_JACOBI)
+    return fail(c, PIC_E_INVALID, "preconditioner: PIC_PRECOND_MULTIGRID or PIC_PRECOND_JACOBI");
   for (int f = 0; f < 6; ++f)
     if (!is_finite(fs->value[f])) return fail(c, PIC_E_INVALID, "face values must be finite");
   if (!c->deposited) return fail(c, PIC_E_STATE, "no deposit yet (call pic_step first)");
@@ -1050,6 +1169,53 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
       return fail(c, PIC_E_NOMEM, "hipHostMalloc failed");
     c->fctrl_host = (FieldCtrl *)q;
     PIC_HIP(c, launch_fill(c->fx, nodes * 8, c->stream));
+  }
+  int32_t levels = 0;
+  if (fs->preconditioner == PIC_PRECOND_MULTIGRID) {
+    if (c->mg_levels < 0) {
+      MgLevel lv[kMaxLevels];
+      const int32_t n = mg_plan(L, lv);
+      for (int l = 0; l < n; ++l) {
+        void *q = nullptr;
+        const int64_t b = lv[l].nodes * 8;
+        double **bufs[4] = {&lv[l].e, &lv[l].e2, &lv[l].res, &lv[l].rhs};
+        for (int t = 0; t < 4; ++t) {
+          if (l == 0 && (t == 0 || t == 3)) continue;  // level 0: e = z, rhs = r
+          if (dmalloc(c, &q, b) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+          *bufs[t] = (double *)q;
+        }
+      }
+      if (n > 0) {
+        void *q = nullptr;
+        const int64_t cn = lv[n - 1].nodes;
+        if (dmalloc(c, &q, cn * cn * 8) != hipSuccess)
+          return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+        c->mg_ainv = (double *)q;
+        if (dmalloc(c, &q, cn * 4) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+        c->mg_umap = (int32_t *)q;
+      }
+      for (int l = 0; l < n; ++l) c->mg[l] = lv[l];
+      c->mg_levels = n;
+    }
+    levels = c->mg_levels;
+    if (levels >= 2 && (c->mg_mask != fs->dirichlet || c->mg_eps != fs->eps)) {
+      const MgLevel &C = c->mg[levels - 1];
+      const double hc = c->cfg.h * (double)(1 << (levels - 1));
+      std::vector<double> inv;
+      std::vector<int32_t> umap;
+      if (!coarse_inverse(C, fs->dirichlet, fs->eps / (hc * hc), inv, umap))
+        return fail(c, PIC_E_DEVICE, "coarsest multigrid operator is not positive definite");
+      c->mg_m = (int32_t)umap.size();
+      if (c->mg_m > 0) {
+        PIC_HIP(c, hipMemcpyAsync(c->mg_ainv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice,
+                                  c->stream));
+        PIC_HIP(c, hipMemcpyAsync(c->mg_umap, umap.data(), umap.size() * 4,
+                                  hipMemcpyHostToDevice, c->stream));
+        PIC_HIP(c, hipStreamSynchronize(c->stream));
+      }
+      c->mg_mask = fs->dirichlet;
+      c->mg_eps = fs->eps;
+    }
   }
   FieldParams P{};
   P.rho = c->rho;
@@ -1075,11 +1241,27 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   P.tol = fs->tol;
   P.max_iter = fs->max_iter;
   P.G = G;
+  P.levels = levels;
+  if (levels >= 2) {
+    for (int l = 0; l < levels; ++l) {
+      P.lv[l] = c->mg[l];
+      P.lv[l].mask = fs->dirichlet;
+      const double hl = c->cfg.h * (double)(1 << l);
+      P.lv[l].s = fs->eps / (hl * hl);
+    }
+    P.lv[0].e = c->fz;
+    P.lv[0].rhs = c->fr;
+    P.ainv = c->mg_ainv;
+    P.umap = c->mg_umap;
+    P.m = c->mg_m;
+  }
   const int pe = prof_begin(c, 4);
   PIC_HIP(c, launch_field_init(c->cfg.deposit, P, c->stream));
+  if (levels >= 2) PIC_HIP(c, launch_field_mg_start(P, c->stream));
   // iterations in chunks; the kernels themselves stop at convergence or
-  // max_iter, the host only stops enqueueing
-  constexpr int kChunkIters = 16;
+  // max_iter, the host only stops enqueueing (a multigrid iteration is some
+  // 6 launches per level, so it checks more often)
+  const int kChunkIters = levels >= 2 ? 2 : 16;
   for (int it = 1; it <= fs->max_iter; it += kChunkIters) {
     for (int k = it; k < it + kChunkIters && k <= fs->max_iter; ++k)
       PIC_HIP(c, launch_field_iter(P, (k - 1) & 1, c->stream));
@@ -1099,6 +1281,7 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   if (rel_residual) *rel_residual = f.bb > 0 ? std::sqrt(f.rr) / std::sqrt(f.bb) : 0.0;
   c->E_set = true;
   c->solved = true;
+  c->field_levels = levels;
   return PIC_OK;
 }
 

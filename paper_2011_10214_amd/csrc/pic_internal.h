@@ -177,6 +177,19 @@ struct FieldCtrl {
   double rr, bb;  // last squared residual norm, squared right-hand-side norm
 };
 
+// One level of the multigrid preconditioner (level 0: the PIC nodes; level
+// l + 1 keeps every other node of level l, spacing doubled).
+constexpr int kMaxLevels = 8;
+constexpr int64_t kCoarseNodes = 1024;  // the coarsest level is solved exactly
+struct MgLevel {
+  int32_t n[3];
+  int64_t sx, sy, nodes;
+  int32_t mask;                // Dirichlet faces (homogeneous for corrections)
+  double s;                    // eps / h_l^2
+  double *e, *e2, *res, *rhs;  // correction (ping-pong), residual, right-hand side
+  int32_t G;                   // workgroups of the level's kernels
+};
+
 struct FieldParams {
   const void *rho;          // the deposit (raw: fixed int64 at 2^32, or float / double)
   double *x, *r, *z, *p, *Ap;
@@ -192,6 +205,12 @@ struct FieldParams {
   double tol;
   int32_t max_iter;
   int32_t G;                // workgroups of every field kernel (partials per sum)
+  // multigrid preconditioner (levels >= 2: z = V-cycle(r)); 0 levels: Jacobi
+  int32_t levels;
+  MgLevel lv[kMaxLevels];
+  const double *ainv;       // coarsest level: inverse operator on its m unknowns (m x m)
+  const int32_t *umap;      // coarsest level: node of each unknown
+  int32_t m;
 };
 
 // Batched runs: many contexts (slots) advanced by one launch per step. Work
@@ -223,7 +242,11 @@ hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t 
 // field solve: init (+ initial convergence check), one CG iteration (parity o:
 // the partials of the previous iteration), and E
 hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s);
+// (with levels >= 2 the multigrid form: z = V-cycle(r) between the update and
+// the new direction)
 hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s);
+// multigrid form, after init: z = V-cycle(r), p = z
+hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s);
 hipError_t launch_field_E(int repr, const FieldParams &p, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,

@@ -1412,7 +1412,10 @@ __global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
 // are per-workgroup partials that every consumer adds in the same fixed
 // order, so the solve is deterministic.
 
-__device__ __forceinline__ bool f_dir(const FieldParams &P, int i, int j, int k) {
+// The grid helpers take the fine grid (FieldParams) or a multigrid level
+// (MgLevel): both carry n, sx, sy and mask.
+template <class Gd>
+__device__ __forceinline__ bool f_dir(const Gd &P, int i, int j, int k) {
   const int m = P.mask;
   return ((m & 1) && i == 0) || ((m & 2) && i == P.n[0]) || ((m & 4) && j == 0) ||
          ((m & 8) && j == P.n[1]) || ((m & 16) && k == 0) || ((m & 32) && k == P.n[2]);
@@ -1432,7 +1435,8 @@ __device__ __forceinline__ double f_gval(const FieldParams &P, int i, int j, int
 __device__ __forceinline__ double f_c(int a, int n) { return (a == 0 || a == n) ? 0.5 : 1.0; }
 
 // node index -> (i, j, k); node counts stay below 2^31 (1024^3 cells at most)
-__device__ __forceinline__ void f_ijk(const FieldParams &P, int64_t q, int &i, int &j, int &k) {
+template <class Gd>
+__device__ __forceinline__ void f_ijk(const Gd &P, int64_t q, int &i, int &j, int &k) {
   const uint32_t u = (uint32_t)q, sy = (uint32_t)P.sy, sx = (uint32_t)P.sx;
   const uint32_t kk = u / sy, rem = u - kk * sy, jj = rem / sx;
   k = (int)kk;
@@ -1442,8 +1446,8 @@ __device__ __forceinline__ void f_ijk(const FieldParams &P, int64_t q, int &i, i
 
 // Visits the links of node (i, j, k) in the order -x, +x, -y, +y, -z, +z:
 // f(q, w) with q the neighbour's node index.
-template <class F>
-__device__ __forceinline__ void f_links(const FieldParams &P, int i, int j, int k, int64_t q0, F f) {
+template <class Gd, class F>
+__device__ __forceinline__ void f_links(const Gd &P, int i, int j, int k, int64_t q0, F f) {
   const double cx = f_c(i, P.n[0]), cy = f_c(j, P.n[1]), cz = f_c(k, P.n[2]);
   if (i > 0) f(q0 - 1, cy * cz);
   if (i < P.n[0]) f(q0 + 1, cy * cz);
@@ -1580,7 +1584,9 @@ __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
   if (threadIdx.x == 0) P.part[blockIdx.x] = pap;
 }
 
-// x += alpha p, r -= alpha Ap, z = r / diag; partials r.z, r.r (parity n)
+// x += alpha p, r -= alpha Ap; partial r.r (parity n); Jacobi form: also
+// z = r / diag and partial r.z
+template <bool J>
 __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int o) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const int n = 1 - o;
@@ -1591,41 +1597,62 @@ __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int
     int i, j, k;
     f_ijk(P, q, i, j, k);
     if (f_dir(P, i, j, k)) continue;
-    double dsum = 0.0;
-    f_links(P, i, j, k, q, [&](int64_t, double w) { dsum = dsum + w; });
     const double x = P.x[q] + alpha * P.p[q];
     const double r = P.r[q] - alpha * P.Ap[q];
-    const double z = r / (P.s * dsum);
     P.x[q] = x;
     P.r[q] = r;
-    P.z[q] = z;
-    rz = rz + r * z;
+    if constexpr (J) {
+      double dsum = 0.0;
+      f_links(P, i, j, k, q, [&](int64_t, double w) { dsum = dsum + w; });
+      const double z = r / (P.s * dsum);
+      P.z[q] = z;
+      rz = rz + r * z;
+    }
     rr = rr + r * r;
   }
-  rz = block_sum(rz);
+  if constexpr (J) rz = block_sum(rz);
   rr = block_sum(rr);
   if (threadIdx.x == 0) {
-    P.part[(1 + n) * P.G + blockIdx.x] = rz;
+    if constexpr (J) P.part[(1 + n) * P.G + blockIdx.x] = rz;
     P.part[(3 + n) * P.G + blockIdx.x] = rr;
   }
 }
 
-// convergence test; p = z + beta p
+// The convergence test of an iteration (parity o): ||r|| <= tol ||b||; the
+// iteration count, ||r||^2 and the flag go to the control block.
+__device__ __forceinline__ bool f_check(const FieldParams &P, const FieldCtrl &c, int o,
+                                        bool write) {
+  const int n = 1 - o;
+  const double rr = sum_partials(P.part + (3 + n) * P.G, P.G);
+  const bool conv = __builtin_sqrt(rr) <= P.tol * __builtin_sqrt(c.bb);
+  if (write && threadIdx.x == 0) {
+    P.ctrl->rr = rr;
+    P.ctrl->iters = c.iters + 1;
+    if (conv) P.ctrl->converged = 1;
+  }
+  return conv;
+}
+
+// multigrid form: the test alone, one workgroup, before the V-cycle (whose
+// kernels then stop at f_done)
+__global__ __launch_bounds__(kBlock) void field_check_kernel(FieldParams P, int o) {
+  const FieldCtrl c = f_ctrl(P);
+  if (f_done(c, P)) return;  // uniform
+  f_check(P, c, o, true);
+}
+
+// Jacobi form: convergence test, then p = z + beta p; multigrid form: p = z +
+// beta p (the test ran before the V-cycle)
+template <bool J>
 __global__ __launch_bounds__(kBlock) void field_dir_kernel(FieldParams P, int o) {
   const FieldCtrl c = f_ctrl(P);
   if (f_done(c, P)) return;  // uniform
   const int n = 1 - o;
-  const double rr = sum_partials(P.part + (3 + n) * P.G, P.G);
-  const bool conv = __builtin_sqrt(rr) <= P.tol * __builtin_sqrt(c.bb);
-  const int it = c.iters;
+  if constexpr (J) {
+    if (f_check(P, c, o, blockIdx.x == 0)) return;  // uniform
+  }
   const double beta = sum_partials(P.part + (1 + n) * P.G, P.G) /
                       sum_partials(P.part + (1 + o) * P.G, P.G);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    P.ctrl->rr = rr;
-    P.ctrl->iters = it + 1;
-    if (conv) P.ctrl->converged = 1;
-  }
-  if (conv) return;  // uniform
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
        q += (int64_t)P.G * kBlock) {
     int i, j, k;
@@ -1633,6 +1660,194 @@ __global__ __launch_bounds__(kBlock) void field_dir_kernel(FieldParams P, int o)
     if (f_dir(P, i, j, k)) continue;
     P.p[q] = P.z[q] + beta * P.p[q];
   }
+}
+
+// ---- multigrid V-cycle preconditioner
+//
+// z = B r by one V-cycle over nested node grids (level l + 1: every other node
+// of level l, spacing 2h, the same faces, the finite-volume operator
+// rediscretised, homogeneous Dirichlet values): two damped-Jacobi sweeps from
+// zero, residual, restriction R = P^T / 8 (full weighting of the residual
+// density), the coarser cycle, trilinear prolongation P, two more sweeps; the
+// coarsest level (at most kCoarseNodes nodes) is solved exactly with its
+// inverse. With the same sweeps before and after and R proportional to P^T,
+// B is symmetric positive definite, so CG with it is still CG. Each level's
+// kernels run its own G workgroups over its nodes; all of them stop at
+// f_done.
+
+constexpr double kOmega = 6.0 / 7.0;  // Jacobi damping (3-D 7-point smoothing optimum)
+
+template <class Gd>
+__device__ __forceinline__ double f_dsum(const Gd &L, int i, int j, int k) {
+  return ((i > 0) + (i < L.n[0])) * (f_c(j, L.n[1]) * f_c(k, L.n[2])) +
+         ((j > 0) + (j < L.n[1])) * (f_c(i, L.n[0]) * f_c(k, L.n[2])) +
+         ((k > 0) + (k < L.n[2])) * (f_c(i, L.n[0]) * f_c(j, L.n[1]));
+}
+
+// A e at an unknown node of level L (e = 0 on its Dirichlet nodes)
+__device__ __forceinline__ double mg_Ae(const MgLevel &L, const double *e, int i, int j, int k,
+                                        int64_t q) {
+  const double eq = e[q];
+  double a = 0.0;
+  f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (eq - e[nb]); });
+  return L.s * a;
+}
+
+// e = two sweeps from zero: e1 = w b / d is pointwise, so the second sweep
+// computes e1 at the neighbours itself.
+__global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &L = P.lv[l];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    if (f_dir(L, i, j, k)) {
+      L.e[q] = 0.0;
+      continue;
+    }
+    const double d = L.s * f_dsum(L, i, j, k);
+    const double bq = L.rhs[q];
+    const double e1 = kOmega * bq / d;
+    double a = 0.0;
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) {
+      int a2, b2, c2;
+      f_ijk(L, nb, a2, b2, c2);
+      const double en =
+          f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / (L.s * f_dsum(L, a2, b2, c2));
+      a = a + w * (e1 - en);
+    });
+    L.e[q] = e1 + kOmega * (bq - L.s * a) / d;
+  }
+}
+
+// res = b - A e
+__global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &L = P.lv[l];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - mg_Ae(L, L.e, i, j, k, q);
+  }
+}
+
+// rhs of level l + 1 = P^T res / 8: a coarse node gathers the fine residuals
+// of its 3x3x3 fine neighbourhood (in the box) with weights 1 or 1/2 per axis.
+__global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
+  for (int64_t Q = (int64_t)blockIdx.x * kBlock + threadIdx.x; Q < C.nodes;
+       Q += (int64_t)C.G * kBlock) {
+    int I, J, K;
+    f_ijk(C, Q, I, J, K);
+    if (f_dir(C, I, J, K)) {
+      C.rhs[Q] = 0.0;
+      continue;
+    }
+    const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
+    double v = 0.0;
+    for (int dk = -1; dk <= 1; ++dk) {
+      const int k = k0 + dk;
+      if (k < 0 || k > F.n[2]) continue;
+      const double wk = dk == 0 ? 1.0 : 0.5;
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int j = j0 + dj;
+        if (j < 0 || j > F.n[1]) continue;
+        const double wjk = wk * (dj == 0 ? 1.0 : 0.5);
+        const double *row = F.res + (int64_t)k * F.sy + (int64_t)j * F.sx;
+        for (int di = -1; di <= 1; ++di) {
+          const int i = i0 + di;
+          if (i < 0 || i > F.n[0]) continue;
+          v = v + wjk * (di == 0 ? 1.0 : 0.5) * row[i];
+        }
+      }
+    }
+    C.rhs[Q] = v * 0.125;
+  }
+}
+
+// e of the coarsest level = A^-1 rhs on its m unknowns: one wave per row,
+// the right-hand side gathered into LDS.
+__global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &C = P.lv[P.levels - 1];
+  __shared__ double sb[kCoarseNodes];
+  const int m = P.m;
+  for (int v = threadIdx.x; v < m; v += kBlock) sb[v] = C.rhs[P.umap[v]];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < C.nodes;
+       q += (int64_t)gridDim.x * kBlock) {
+    int i, j, k;
+    f_ijk(C, q, i, j, k);
+    if (f_dir(C, i, j, k)) C.e[q] = 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int u = blockIdx.x * (kBlock / 64) + wave; u < m; u += gridDim.x * (kBlock / 64)) {
+    const double *row = P.ainv + (int64_t)u * m;
+    double a = 0.0;
+    for (int v = lane; v < m; v += 64) a = a + row[v] * sb[v];
+    for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) C.e[P.umap[u]] = a;
+  }
+}
+
+// e += P e_c (trilinear: per axis the coarse node itself, or the mean of two)
+__global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < F.nodes;
+       q += (int64_t)F.G * kBlock) {
+    int i, j, k;
+    f_ijk(F, q, i, j, k);
+    if (f_dir(F, i, j, k)) continue;
+    const int ni = 1 + (i & 1), nj = 1 + (j & 1), nk = 1 + (k & 1);
+    const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
+    double v = 0.0;
+    for (int c = 0; c < nk; ++c)
+      for (int b = 0; b < nj; ++b) {
+        const double *row = C.e + (int64_t)(k / 2 + c) * C.sy + (int64_t)(j / 2 + b) * C.sx;
+        for (int a = 0; a < ni; ++a) v = v + (wi * wj * wk) * row[i / 2 + a];
+      }
+    F.e[q] += v;
+  }
+}
+
+// One damped-Jacobi sweep out = in + w (b - A in) / d. On level 0 the second
+// post-sweep writes z itself and the partial r.z to part[prz].
+template <bool Dot>
+__global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, int to_e2, int prz) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &L = P.lv[l];
+  const double *in = to_e2 ? L.e : L.e2;
+  double *out = to_e2 ? L.e2 : L.e;
+  double rz = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    if (f_dir(L, i, j, k)) {
+      out[q] = 0.0;
+      continue;
+    }
+    const double bq = L.rhs[q];
+    const double v = in[q] + kOmega * (bq - mg_Ae(L, in, i, j, k, q)) / (L.s * f_dsum(L, i, j, k));
+    out[q] = v;
+    if constexpr (Dot) rz = rz + bq * v;
+  }
+  if constexpr (Dot) {
+    rz = block_sum(rz);
+    if (threadIdx.x == 0) P.part[prz * P.G + blockIdx.x] = rz;
+  }
+}
+
+// multigrid start: p = z
+__global__ __launch_bounds__(kBlock) void field_pstart_kernel(FieldParams P) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock)
+    P.p[q] = P.z[q];
 }
 
 // E = -grad phi at the nodes: central differences inside, 0 normal to a
@@ -1915,10 +2130,43 @@ hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
+// z = V-cycle(r); the partial r.z to part[prz]
+static void field_vcycle(const FieldParams &p, int prz, hipStream_t s) {
+  const int L = p.levels;
+  for (int l = 0; l + 1 < L; ++l) {
+    hipLaunchKernelGGL(mg_pre_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL(mg_res_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL(mg_restrict_kernel, dim3(p.lv[l + 1].G), dim3(kBlock), 0, s, p, l);
+  }
+  const int gc = p.m > 0 ? (p.m + kBlock / 64 - 1) / (kBlock / 64) : 1;
+  hipLaunchKernelGGL(mg_coarse_kernel, dim3(gc), dim3(kBlock), 0, s, p);
+  for (int l = L - 2; l >= 0; --l) {
+    hipLaunchKernelGGL(mg_prolong_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL(mg_sweep_kernel<false>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 1, 0);
+    if (l == 0)
+      hipLaunchKernelGGL(mg_sweep_kernel<true>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0, prz);
+    else
+      hipLaunchKernelGGL(mg_sweep_kernel<false>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0, 0);
+  }
+}
+
+hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s) {
+  field_vcycle(p, 1, s);
+  hipLaunchKernelGGL(field_pstart_kernel, dim3(p.G), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s) {
   hipLaunchKernelGGL(field_apply_kernel, dim3(p.G), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(field_update_kernel, dim3(p.G), dim3(kBlock), 0, s, p, o);
-  hipLaunchKernelGGL(field_dir_kernel, dim3(p.G), dim3(kBlock), 0, s, p, o);
+  if (p.levels >= 2) {
+    hipLaunchKernelGGL(field_update_kernel<false>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+    hipLaunchKernelGGL(field_check_kernel, dim3(1), dim3(kBlock), 0, s, p, o);
+    field_vcycle(p, 2 - o, s);  // parity n = 1 - o
+    hipLaunchKernelGGL(field_dir_kernel<false>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(field_update_kernel<true>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+  hipLaunchKernelGGL(field_dir_kernel<true>, dim3(p.G), dim3(kBlock), 0, s, p, o);
   return hipGetLastError();
 }
 

@@ -45,7 +45,11 @@ class _Config(ctypes.Structure):
 
 class _Field(ctypes.Structure):
     _fields_ = [("dirichlet", ctypes.c_int32), ("value", ctypes.c_double * 6),
-                ("eps", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+                ("eps", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("preconditioner", ctypes.c_int32)]
+
+
+PRECONDITIONERS = {"multigrid": 0, "jacobi": 1}
 
 
 class _Injection(ctypes.Structure):
@@ -88,6 +92,7 @@ SIGNATURES = {
     "pic_solve_field": (_st, [_vp, ctypes.POINTER(_Field), ctypes.POINTER(_i32),
                               ctypes.POINTER(ctypes.c_double)]),
     "pic_get_phi": (_st, [_vp, _vp]),
+    "pic_get_field_levels": (_st, [_vp, ctypes.POINTER(_i32)]),
     "pic_get_node_E": (_st, [_vp, _vp, _vp, _vp]),
     "pic_get_injected": (_st, [_vp, _vp]),
     "pic_synchronize": (_st, [_vp]),
@@ -338,11 +343,12 @@ class Context:
         self._check(lib().pic_set_injection(self._h, ctypes.byref(c)))
 
     def solve_field(self, dirichlet: int, values=None, eps: float = 1.0, tol: float = 1e-6,
-                    max_iter: int = 150):
+                    max_iter: int = 150, precond: str = "multigrid"):
         """Field solve for the last deposit (pic_solve_field); the node field
         becomes -grad phi. Returns (iterations, relative residual)."""
         f = _Field()
         f.dirichlet = int(dirichlet)
+        f.preconditioner = PRECONDITIONERS[precond]
         for k in range(6):
             f.value[k] = float(values[k]) if values is not None else 0.0
         f.eps, f.tol, f.max_iter = float(eps), float(tol), int(max_iter)
@@ -356,6 +362,12 @@ class Context:
         E = [np.empty(self.cfg.nodes) for _ in range(3)]
         self._check(lib().pic_get_node_E(self._h, *[_ptr(e) for e in E]))
         return np.stack(E)
+
+    def get_field_levels(self) -> int:
+        """Multigrid levels of the last field solve (0: Jacobi ran)."""
+        n = _i32(0)
+        self._check(lib().pic_get_field_levels(self._h, ctypes.byref(n)))
+        return n.value
 
     def get_phi(self) -> np.ndarray:
         phi = np.empty(self.cfg.nodes)
