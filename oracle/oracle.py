@@ -48,6 +48,7 @@ class _Cfg(ctypes.Structure):
         ("reflect", ctypes.c_int32), ("inj_faces", ctypes.c_int32), ("inj_seed", ctypes.c_uint64),
         ("inj_density", ctypes.c_double * 4), ("inj_vth", ctypes.c_double * 4),
         ("inj_drift", ctypes.c_double * 12),
+        ("sphere_patches", ctypes.c_int32),
     ]
 
 
@@ -137,6 +138,7 @@ class Problem:
     inj_density: list = None   # per species, particles per unit volume
     inj_vth: list = None
     inj_drift: list = None     # per species, 3 components
+    sphere_patches: int = 0    # sphere: 0 one bin, m > 0 6 m^2 surface patches
 
     @property
     def n_species(self):
@@ -148,7 +150,9 @@ class Problem:
 
     @property
     def nbins(self):
-        return self.nx * self.ny if self.obj == "crater" else 1
+        if self.obj == "crater":
+            return self.nx * self.ny
+        return 6 * self.sphere_patches ** 2 if self.sphere_patches else 1
 
     def cstruct(self) -> _Cfg:
         c = _Cfg()
@@ -169,6 +173,7 @@ class Problem:
         c.reflect = int(self.reflect)
         c.inj_faces = int(self.inj_faces)
         c.inj_seed = int(self.inj_seed) & (2 ** 64 - 1)
+        c.sphere_patches = int(self.sphere_patches)
         for s in range(self.n_species):
             c.inj_density[s] = self.inj_density[s] if self.inj_density else 0.0
             c.inj_vth[s] = self.inj_vth[s] if self.inj_vth else 0.0

@@ -34,7 +34,9 @@
 //   6. box:    first axis (x, y, z) with g < 0 (face 2d) or g >= n (face 2d+1)
 //              -> escaped. For the crater terrain, z < 0 is not an escape.
 //   7. object: sphere |g - c|^2 <= R^2, or crater (z < 0) or (z <= z_flat and
-//              |g - zc|^2 >= Rc^2) -> absorbed, counted in its bin.
+//              |g - zc|^2 >= Rc^2) -> absorbed, counted in its bin: the
+//              crater's surface column (i, j); the sphere's one bin, or with
+//              m patches its surface patch (sphere_patch below).
 //   8. deposit (after all particles moved): rho is zeroed, then every alive
 //      particle adds its charge chg = q*w times W[n] at its new position.
 //      Fixed-point mode: C[n] = llrint(chg*W[n] * 2^32) for n < 7 and
@@ -107,6 +109,7 @@ typedef struct {
   double inj_density[kMaxSpecies];  // particles per unit volume
   double inj_vth[kMaxSpecies];      // thermal speed per component
   double inj_drift[kMaxSpecies][3];
+  int32_t sphere_patches;  // sphere: 0 one bin; m > 0: 6 m^2 surface patches
 } orc_config;
 
 typedef struct {
@@ -202,6 +205,7 @@ struct SpeciesConst {
 template <class T>
 struct Geometry {
   int kind;
+  int patches;  // sphere surface patches per cube-face edge (0: one bin)
   T c[3];    // sphere centre / crater axis (x, y); c[2] = bowl sphere centre height
   T r2;      // sphere R^2 / crater bowl-sphere Rc^2
   T z_flat;  // crater flat ground
@@ -216,6 +220,7 @@ template <class T>
 Geometry<T> make_geometry(const orc_config& cfg) {
   Geometry<T> g{};
   g.kind = cfg.obj_kind;
+  g.patches = cfg.obj_kind == OBJ_SPHERE ? cfg.sphere_patches : 0;
   double c[3] = {0, 0, 0}, r2 = 0, zf = 0;
   if (cfg.obj_kind == OBJ_SPHERE) {
     for (int d = 0; d < 3; ++d) c[d] = (cfg.center[d] - cfg.origin[d]) / cfg.h;
@@ -252,12 +257,43 @@ T dist2(const T d[3]) {
   return fma_t(d[2], d[2], fma_t(d[1], d[1], d[0] * d[0]));
 }
 
+// Surface patch of a collected particle on a sphere with m patches per
+// cube-face edge (6 m^2 patches; the per-patch collected charge is the
+// surface charge distribution behind the flux jump of eq. (2.5)). d is the
+// particle's offset from the centre; its direction is projected on the cube
+// around the sphere (gnomonic cube map): the face is that of the largest |d_a|
+// (ties to the lower axis; face 2a for d_a < 0, 2a + 1 otherwise), and the
+// two other components, in axis order and divided by |d_a|, lie in [-1, 1]
+// and are cut into m equal intervals each. Only correctly rounded operations,
+// in the form's type.
+template <class T>
+int32_t sphere_patch(const T d[3], int m) {
+  const T a[3] = {std::fabs(d[0]), std::fabs(d[1]), std::fabs(d[2])};
+  int ax = 0;
+  if (a[1] > a[ax]) ax = 1;
+  if (a[2] > a[ax]) ax = 2;
+  const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+  const int face = 2 * ax + (d[ax] < T(0) ? 0 : 1);
+  T su = T(0), sv = T(0);
+  if (a[ax] > T(0)) {
+    su = d[u] / a[ax];
+    sv = d[v] / a[ax];
+  }
+  const T half = (T)(0.5 * m);
+  auto cell = [&](T t) {
+    const int k = (int)floor_t((t + T(1)) * half);
+    return k < 0 ? 0 : (k > m - 1 ? m - 1 : k);
+  };
+  return (int32_t)((face * m + cell(sv)) * m + cell(su));
+}
+
 // Absolute-position forms. Returns the bin (>= 0) when absorbed, else -1.
 template <class T>
 int32_t object_hit_abs(const Geometry<T>& G, const Mesh& m, const T g[3]) {
   if (G.kind == OBJ_SPHERE) {
     const T d[3] = {g[0] - G.c[0], g[1] - G.c[1], g[2] - G.c[2]};
-    return dist2(d) <= G.r2 ? 0 : -1;
+    if (!(dist2(d) <= G.r2)) return -1;
+    return G.patches ? sphere_patch(d, G.patches) : 0;
   }
   if (G.kind == OBJ_CRATER) {
     bool hit = g[2] < T(0);
@@ -281,7 +317,8 @@ int32_t object_hit_cell(const Geometry<float>& G, const Mesh& m, const int32_t i
   if (G.kind == OBJ_SPHERE) {
     float d[3];
     for (int k = 0; k < 3; ++k) d[k] = (float)(i[k] - G.ci[k]) + (o[k] - G.cf[k]);
-    return dist2(d) <= G.r2 ? 0 : -1;
+    if (!(dist2(d) <= G.r2)) return -1;
+    return G.patches ? sphere_patch(d, G.patches) : 0;
   }
   if (G.kind == OBJ_CRATER) {
     bool hit = i[2] < 0;
@@ -555,7 +592,10 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
   const int ns = cfg.n_species;
   const bool crater = cfg.obj_kind == OBJ_CRATER;
   const Geometry<T> G = make_geometry<T>(cfg);
-  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny : 1;
+  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny
+                                : (cfg.sphere_patches > 0 ? 6 * (int64_t)cfg.sphere_patches *
+                                                                cfg.sphere_patches
+                                                          : 1);
   std::vector<T> E[3];
   for (int d = 0; d < 3; ++d) {
     E[d].resize(nodes);
@@ -719,7 +759,10 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
   const int ns = cfg.n_species;
   const bool crater = cfg.obj_kind == OBJ_CRATER;
   const Geometry<T> G = make_geometry<T>(cfg);
-  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny : 1;
+  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny
+                                : (cfg.sphere_patches > 0 ? 6 * (int64_t)cfg.sphere_patches *
+                                                                cfg.sphere_patches
+                                                          : 1);
   std::vector<T> E[3];
   for (int d = 0; d < 3; ++d) {
     E[d].resize(nodes);
@@ -904,6 +947,8 @@ bool valid(const orc_config& c, int64_t n, const int32_t* sp, const double* cons
   if ((c.reflect | c.inj_faces) & ~63) return false;
   if (c.reflect & c.inj_faces) return false;             // a face reflects or injects
   if (c.obj_kind == OBJ_CRATER && ((c.reflect | c.inj_faces) & 16)) return false;  // terrain
+  if (c.sphere_patches < 0 || c.sphere_patches > 64) return false;
+  if (c.sphere_patches && c.obj_kind != OBJ_SPHERE) return false;
   for (int s = 0; s < c.n_species && c.inj_faces; ++s)
     if (!(c.inj_density[s] >= 0) || !(c.inj_vth[s] >= 0) || !std::isfinite(c.inj_drift[s][0]) ||
         !std::isfinite(c.inj_drift[s][1]) || !std::isfinite(c.inj_drift[s][2]))
