@@ -100,6 +100,15 @@ typedef struct {
   double z_flat;     /* crater: height of the flat ground */
   double rim_radius; /* crater: bowl radius at the flat level (a) */
   double depth;      /* crater: bowl depth below the flat level (d > 0) */
+  int32_t patches;   /* sphere only, 0..64: 0 = one tally bin for the whole
+                        sphere; m >= 1 = 6 m^2 surface patches, the bin of a
+                        collected particle being the patch its offset d from
+                        the centre points through (gnomonic cube map): face
+                        2a + (d_a >= 0) of the largest |d_a| (ties to the lower
+                        axis), the two other components in axis order divided
+                        by |d_a| and cut into m equal intervals of [-1, 1]:
+                        bin = (face m + iv) m + iu. Where on the sphere the
+                        collected charge sits (the flux jump q(X) of eq. (2.5)). */
 } pic_object;
 
 typedef struct {

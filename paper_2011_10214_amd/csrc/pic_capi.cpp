@@ -46,8 +46,12 @@ Dims dims_of(const pic_config &c) {
   L.ntz = (c.nz + kTile - 1) / kTile;
   L.ntiles = L.ntx * L.nty * L.ntz;
   L.nodes = (int64_t)(c.nx + 1) * (c.ny + 1) * (c.nz + 1);
-  L.nbins = c.object.kind == PIC_OBJ_CRATER ? (int64_t)c.nx * c.ny
-                                             : (c.object.kind == PIC_OBJ_SPHERE ? 1 : 0);
+  L.nbins = c.object.kind == PIC_OBJ_CRATER
+                ? (int64_t)c.nx * c.ny
+                : (c.object.kind == PIC_OBJ_SPHERE
+                       ? (c.object.patches > 0 ? 6 * (int64_t)c.object.patches * c.object.patches
+                                               : 1)
+                       : 0);
   return L;
 }
 
@@ -106,6 +110,8 @@ const char *validate_config(const pic_config *c) {
     return "reflect: the crater's z- face is the terrain";
   const pic_object &o = c->object;
   if (o.kind < 0 || o.kind > 2) return "object.kind must be a pic_object_kind";
+  if (o.patches < 0 || o.patches > 64) return "object.patches must be 0..64";
+  if (o.patches && o.kind != PIC_OBJ_SPHERE) return "object.patches: spheres only";
   if (o.kind == PIC_OBJ_SPHERE) {
     for (int d = 0; d < 3; ++d)
       if (!is_finite(o.center[d])) return "sphere centre must be finite";
@@ -123,6 +129,7 @@ const char *validate_config(const pic_config *c) {
 Geom geometry_of(const pic_config &c) {
   Geom g{};
   g.kind = c.object.kind;
+  g.patches = c.object.kind == PIC_OBJ_SPHERE ? c.object.patches : 0;
   double cc[3] = {0, 0, 0}, r2 = 0, zf = 0;
   if (c.object.kind == PIC_OBJ_SPHERE) {
     for (int d = 0; d < 3; ++d) cc[d] = (c.object.center[d] - c.origin[d]) / c.h;

@@ -75,6 +75,7 @@ __host__ inline int32_t overflow_slots(int64_t n) {
 
 struct Geom {
   int32_t kind;
+  int32_t patches;  // sphere surface patches per cube-face edge (0: one bin)
   int32_t ci[3];    // floor of c (cell form)
   int32_t zfi;      // floor of z_flat (cell form)
   double c[3];      // sphere centre / crater (xc, yc, zc), cell units

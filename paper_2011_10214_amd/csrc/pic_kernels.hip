@@ -139,13 +139,14 @@ __device__ __forceinline__ int agg_add(int32_t *ctr, int key) {
 template <class T>
 struct GeomT {
   T c[3], r2, z_flat, cf[3], zff;
-  int ci[3], zfi, kind;
+  int ci[3], zfi, kind, patches;
 };
 
 template <class T>
 __device__ __forceinline__ GeomT<T> geom_of(const Geom &g) {
   GeomT<T> o;
   o.kind = g.kind;
+  o.patches = g.patches;
   for (int d = 0; d < 3; ++d) {
     o.c[d] = (T)g.c[d];
     o.cf[d] = (T)g.cf[d];
@@ -165,11 +166,48 @@ __device__ __forceinline__ T dist2(T dx, T dy, T dz) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Surface patch of a collected particle at offset d from the sphere's centre,
+// m patches per cube-face edge: the face of the largest |d_a| (ties to the
+// lower axis; 2a for d_a < 0, else 2a + 1), the two other components in axis
+// order divided by |d_a|, each cut into m equal intervals of [-1, 1].
+template <class T>
+__device__ __forceinline__ int sphere_patch(T dx, T dy, T dz, int m) {
+  const T ax = dx < T(0) ? -dx : dx, ay = dy < T(0) ? -dy : dy, az = dz < T(0) ? -dz : dz;
+  int a = 0;
+  T big = ax, du = dy, dv = dz, dn = dx;
+  if (ay > big) {
+    a = 1;
+    big = ay;
+    du = dx;
+    dv = dz;
+    dn = dy;
+  }
+  if (az > big) {
+    a = 2;
+    big = az;
+    du = dx;
+    dv = dy;
+    dn = dz;
+  }
+  const int face = 2 * a + (dn < T(0) ? 0 : 1);
+  T su = T(0), sv = T(0);
+  if (big > T(0)) {
+    su = du / big;
+    sv = dv / big;
+  }
+  const T half = (T)(0.5 * m);
+  const int iu = clampi((int)floorT((su + T(1)) * half), 0, m - 1);
+  const int iv = clampi((int)floorT((sv + T(1)) * half), 0, m - 1);
+  return (face * m + iv) * m + iu;
+}
+
 // Object test on an absolute position (cell units); bin or -1.
 template <class T>
 __device__ __forceinline__ int hit_abs(const GeomT<T> &G, int nx, int ny, const T g[3]) {
   if (G.kind == PIC_OBJ_SPHERE) {
-    return dist2(g[0] - G.c[0], g[1] - G.c[1], g[2] - G.c[2]) <= G.r2 ? 0 : -1;
+    const T dx = g[0] - G.c[0], dy = g[1] - G.c[1], dz = g[2] - G.c[2];
+    if (!(dist2(dx, dy, dz) <= G.r2)) return -1;
+    return G.patches ? sphere_patch(dx, dy, dz, G.patches) : 0;
   }
   if (G.kind == PIC_OBJ_CRATER) {
     bool hit = g[2] < T(0);
@@ -189,7 +227,8 @@ __device__ __forceinline__ int hit_cell(const GeomT<float> &G, int nx, int ny, c
     const float dx = (float)(i[0] - G.ci[0]) + (o[0] - G.cf[0]);
     const float dy = (float)(i[1] - G.ci[1]) + (o[1] - G.cf[1]);
     const float dz = (float)(i[2] - G.ci[2]) + (o[2] - G.cf[2]);
-    return dist2(dx, dy, dz) <= G.r2 ? 0 : -1;
+    if (!(dist2(dx, dy, dz) <= G.r2)) return -1;
+    return G.patches ? sphere_patch(dx, dy, dz, G.patches) : 0;
   }
   if (G.kind == PIC_OBJ_CRATER) {
     bool hit = i[2] < 0;
@@ -542,7 +581,8 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
 
   const GeomT<T> G = geom_of<T>(P.geom);
   const bool crater = P.geom.kind == PIC_OBJ_CRATER;
-  const bool sphere = P.geom.kind == PIC_OBJ_SPHERE;
+  // one sphere bin: counted per wave into LDS; patches: per particle
+  const bool sphere = P.geom.kind == PIC_OBJ_SPHERE && P.geom.patches == 0;
   const T dt = (T)P.dt;
   const int lane = __lane_id();
   const unsigned long long below = (1ull << lane) - 1ull;

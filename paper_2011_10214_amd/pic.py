@@ -31,7 +31,8 @@ class _Species(ctypes.Structure):
 class _Object(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("center", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("z_flat", ctypes.c_double),
-                ("rim_radius", ctypes.c_double), ("depth", ctypes.c_double)]
+                ("rim_radius", ctypes.c_double), ("depth", ctypes.c_double),
+                ("patches", ctypes.c_int32)]
 
 
 class _Config(ctypes.Structure):
@@ -170,6 +171,7 @@ class Config:
     z_flat: float = 0.0
     rim_radius: float = 0.0
     depth: float = 0.0
+    patches: int = 0                    # sphere: 0 one tally bin, m > 0 6 m^2 surface patches
     repr: str = "fp32_cell"
     deposit: str = "fixed64"
     sort_interval: int = 0
@@ -194,6 +196,7 @@ class Config:
         c.object.radius = self.radius
         c.object.z_flat, c.object.rim_radius, c.object.depth = (self.z_flat, self.rim_radius,
                                                                 self.depth)
+        c.object.patches = int(self.patches)
         c.repr = REPR[self.repr]
         c.deposit = DEPOSIT[self.deposit]
         c.reflect = int(self.reflect)

@@ -15,7 +15,7 @@ class GpuRun:
 
 
 def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interval=0,
-            order=None, device_load=False, split_steps=None):
+            order=None, device_load=False, split_steps=None, patches=0):
     """Runs nsteps on the GPU; particle ids are the indices into (sp, x, v).
     Returns state of alive particles ordered by id."""
     import torch
@@ -26,6 +26,7 @@ def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interva
         sp, x, v, ids = sp[order], x[order], v[order], ids[order]
     cfg = pam.config_from_workload(w, repr=repr, deposit=deposit, sort_interval=sort_interval,
                                    capacity=[max(1, int((sp == s).sum())) for s in range(len(w.species))])
+    cfg.patches = patches
     with pam.Context(cfg) as ctx:
         for s in range(len(w.species)):
             m = sp == s

@@ -60,6 +60,8 @@ def _create(cfg):
     dict(species=[(4e6, 1.0, 1.0)], capacity=[1]), dict(capacity=[-1, 5]),
     dict(capacity=[2 ** 31, 5]), dict(repr="fp32_cell", radius=0.0),
     dict(obj="crater", rim_radius=10.0, depth=0.0), dict(sort_interval=-1),
+    dict(patches=-1), dict(patches=65),
+    dict(obj="crater", rim_radius=2.0, depth=1.0, z_flat=3.0, patches=2),
 ])
 def test_invalid_config_is_rejected_before_any_device_call(bad):
     st, h = _create(_cfg(**bad))

@@ -29,11 +29,12 @@ def ambient(w):
             [tuple(s.drift) for s in w.species])
 
 
-def run_pair(w, form, reflect, faces, nsteps, seed=11, split=None):
+def run_pair(w, form, reflect, faces, nsteps, seed=11, split=None, patches=0):
     sp, x, v, E = inputs(w)
     dens, vth, drift = ambient(w)
     prob = problem_of(w, form)
     prob.reflect, prob.inj_faces, prob.inj_seed = reflect, faces, seed
+    prob.sphere_patches = patches
     prob.inj_density, prob.inj_vth, prob.inj_drift = dens, vth, drift
     r = oracle.run(prob, sp, x, v, E, nsteps)
 
@@ -42,6 +43,7 @@ def run_pair(w, form, reflect, faces, nsteps, seed=11, split=None):
     cfg = pam.config_from_workload(w, repr=form, deposit="fixed64",
                                    capacity=[int((sp == s).sum()) + extra for s in range(ns)])
     cfg.reflect = reflect
+    cfg.patches = patches
     n = len(sp)
     ids = np.arange(n, dtype=np.int64)
     with pam.Context(cfg) as ctx:
@@ -93,6 +95,14 @@ def test_oml_setup_reflect_and_inject_bit_exact(form):
     w = synth.sphere_16()
     sp, r, g = run_pair(w, form, OML["reflect"], OML["faces"], 12)
     assert r.injected.sum() > 1000
+    assert_same(w, sp, r, g)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_oml_setup_with_surface_patches_bit_exact(form):
+    w = synth.sphere_16()
+    sp, r, g = run_pair(w, form, OML["reflect"], OML["faces"], 12, patches=3)
+    assert r.tally.shape[0] == 54 and r.injected.sum() > 1000
     assert_same(w, sp, r, g)
 
 

@@ -50,6 +50,21 @@ def test_sphere16_bit_exact(form):
 
 
 @pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("m", [1, 4])
+def test_sphere_surface_patches_bit_exact(form, m):
+    # 6 m^2 tally bins on the sphere: per-patch counts and charges as the oracle's
+    w = synth.sphere_16()
+    sp, x, v, E = inputs(w)
+    prob = problem_of(w, form)
+    prob.sphere_patches = m
+    r = oracle.run(prob, sp, x, v, E, w.steps)
+    g = run_gpu(w, sp, x, v, E, w.steps, repr=form, patches=m)
+    assert r.tally.shape[0] == 6 * m * m and (r.tally.sum(1) > 0).sum() > min(6 * m * m // 2, 6)
+    assert_bit_exact(w, sp, r, g)
+    assert np.array_equal(g.charge, r.charge(prob))
+
+
+@pytest.mark.parametrize("form", FORMS)
 def test_deposit_only_bit_exact(form):
     w = synth.sphere_16()
     sp, x, v, E = inputs(w)
