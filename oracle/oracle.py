@@ -52,6 +52,13 @@ class _Cfg(ctypes.Structure):
     ]
 
 
+class _FieldObj(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("center", ctypes.c_double * 3),
+                ("radius", ctypes.c_double), ("z_flat", ctypes.c_double),
+                ("rim_radius", ctypes.c_double), ("depth", ctypes.c_double),
+                ("eps_in", ctypes.c_double)]
+
+
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -98,10 +105,18 @@ def lib():
         L.orc_field_solve.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_double,
                                                              ctypes.c_int32, _dp, _dp, _dp,
                                                              ctypes.c_double, ctypes.c_int32,
-                                                             ctypes.c_int32, _i32p, _dp, _i32p]
+                                                             ctypes.c_int32,
+                                                             ctypes.POINTER(_FieldObj), _i32p,
+                                                             _dp, _i32p]
         L.orc_field_vcycle.restype = ctypes.c_int
         L.orc_field_vcycle.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_double,
-                                                              ctypes.c_int32, _dp, _dp]
+                                                              ctypes.c_int32,
+                                                              ctypes.POINTER(_FieldObj), _dp, _dp]
+        L.orc_object_psi.restype = ctypes.c_double
+        L.orc_object_psi.argtypes = [ctypes.POINTER(_FieldObj), ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double]
+        L.orc_surface_rho.restype = ctypes.c_int
+        L.orc_surface_rho.argtypes = [ctypes.POINTER(_Cfg), _i64p, _i64p]
         L.orc_field_E.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_int32, _dp,
                                                          _dp, _dp, _dp]
         L.orc_object_hit.restype = ctypes.c_int32
@@ -344,12 +359,61 @@ def normals3(key: int) -> np.ndarray:
 PRECONDITIONERS = {"multigrid": 0, "jacobi": 1}
 
 
+@dataclass
+class FieldObject:
+    """The object as an interface of the field problem, in the field mesh's
+    cell units with node 0 at the origin; eps_in inside it."""
+    kind: str                   # "sphere" or "crater"
+    eps_in: float
+    center: tuple = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    z_flat: float = 0.0
+    rim_radius: float = 0.0
+    depth: float = 0.0
+
+    def cstruct(self) -> _FieldObj:
+        o = _FieldObj()
+        o.kind = OBJECT[self.kind]
+        o.center[:] = list(self.center)
+        o.radius, o.z_flat, o.rim_radius, o.depth = self.radius, self.z_flat, self.rim_radius, self.depth
+        o.eps_in = self.eps_in
+        return o
+
+
+def field_object_of(prob: "Problem", eps_in: float) -> FieldObject:
+    """The run's object in cell units."""
+    c = tuple((prob.center[d] - prob.origin[d]) / prob.h for d in range(3))
+    return FieldObject(kind=prob.obj, eps_in=eps_in, center=c, radius=prob.radius / prob.h,
+                       z_flat=(prob.z_flat - prob.origin[2]) / prob.h,
+                       rim_radius=prob.rim_radius / prob.h, depth=prob.depth / prob.h)
+
+
+def object_psi(obj: FieldObject, x, y, z) -> float:
+    o = obj.cstruct()
+    return float(lib().orc_object_psi(ctypes.byref(o), float(x), float(y), float(z)))
+
+
+def surface_rho(prob: "Problem", tally) -> np.ndarray:
+    """Fixed-point nodal charge (int64 at 2^32) of the collected surface
+    charge placed at the bins' surface points (see the oracle source)."""
+    t = _c(tally, np.int64)
+    if t.shape != (prob.nbins, prob.n_species):
+        raise ValueError("tally has the wrong shape")
+    out = np.zeros(prob.nodes, np.int64)
+    cfg = prob.cstruct()
+    rc = lib().orc_surface_rho(ctypes.byref(cfg), t.ctypes.data_as(_i64p), out.ctypes.data_as(_i64p))
+    if rc != 0:
+        raise OracleError(f"oracle returned {rc}")
+    return out
+
+
 def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=None, tol=1e-10,
-                max_iter=10000, precond="multigrid", info=None):
+                max_iter=10000, precond="multigrid", info=None, obj: FieldObject = None):
     """Solves the field problem on the nodes (see the oracle source); returns
     (phi, iterations, relative residual). precond "multigrid" uses the V-cycle
     where the grid coarsens (else Jacobi); a dict passed as info gets the
-    multigrid level count used ("levels", 0 for Jacobi)."""
+    multigrid level count used ("levels", 0 for Jacobi); obj makes the object
+    an interface with permittivity obj.eps_in inside."""
     nodes = (nx + 1) * (ny + 1) * (nz + 1)
     rho = _c(rho, np.float64).ravel()
     if rho.size != nodes:
@@ -359,10 +423,11 @@ def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=No
     it = ctypes.c_int32(0)
     rr = ctypes.c_double(0.0)
     lv = ctypes.c_int32(0)
+    o = ctypes.byref(obj.cstruct()) if obj is not None else None
     rc = lib().orc_field_solve(nx, ny, nz, float(h), float(eps), int(dirichlet),
                                g.ctypes.data_as(_dp), rho.ctypes.data_as(_dp),
                                phi.ctypes.data_as(_dp), float(tol), int(max_iter),
-                               PRECONDITIONERS[precond], ctypes.byref(it), ctypes.byref(rr),
+                               PRECONDITIONERS[precond], o, ctypes.byref(it), ctypes.byref(rr),
                                ctypes.byref(lv))
     if rc != 0:
         raise OracleError(f"oracle returned {rc}")
@@ -371,14 +436,15 @@ def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=No
     return phi, it.value, rr.value
 
 
-def field_vcycle(nx, ny, nz, r, dirichlet, h=1.0, eps=1.0):
+def field_vcycle(nx, ny, nz, r, dirichlet, h=1.0, eps=1.0, obj: FieldObject = None):
     """One multigrid V-cycle z = B r (homogeneous Dirichlet faces); returns
     (z, levels), z None when the grid does not coarsen."""
     r = _c(r, np.float64).ravel()
     if r.size != (nx + 1) * (ny + 1) * (nz + 1):
         raise ValueError("r has the wrong size")
     z = np.zeros(r.size)
-    rc = lib().orc_field_vcycle(nx, ny, nz, float(h), float(eps), int(dirichlet),
+    o = ctypes.byref(obj.cstruct()) if obj is not None else None
+    rc = lib().orc_field_vcycle(nx, ny, nz, float(h), float(eps), int(dirichlet), o,
                                 r.ctypes.data_as(_dp), z.ctypes.data_as(_dp))
     if rc < 0:
         raise OracleError(f"oracle returned {rc}")

@@ -128,6 +128,16 @@ typedef struct {
   int64_t *injected;                 // n_species: particles injected (incl. collected)
 } orc_out;
 
+// The object as an interface of the field problem (orc_field_solve), in the
+// field mesh's cell units with node 0 at the origin.
+typedef struct {
+  int32_t kind;                      // 0 none, 1 sphere, 2 crater terrain
+  double center[3];                  // sphere centre; crater axis at (center[0], center[1])
+  double radius;                     // sphere
+  double z_flat, rim_radius, depth;  // crater
+  double eps_in;                     // permittivity inside the object (> 0)
+} orc_field_object;
+
 }  // extern "C"
 
 namespace {
@@ -1015,17 +1025,29 @@ namespace {
 //
 // The boundary value problem of §2.1, -div(eps grad phi) = rho in the box,
 // phi = g on the Dirichlet faces, d phi / dn = 0 on the others (the
-// zero-Neumann symmetry planes of §3.1.3 and the open faces of §5.2.2), with a
-// uniform eps (no interface: the immersed-finite-element treatment of the
-// object is not in this operator). Node-centred finite volumes on the PIC
-// nodes: a node's control volume is its dual cell clipped to the box, so on a
-// Neumann face the zero flux is natural; the flux through the dual face of
-// the link p-q is eps w (phi_p - phi_q) h, w = product of the two tangential
-// half-width factors c = 1/2 at a boundary index, else 1; the charge in the
-// control volume is rho_p h^3 with rho_p the deposited nodal density (which
-// at a boundary node already counts only the inside part of the cloud). So
-//   (A phi)_p = eps / h^2 sum_links w (phi_p - phi_q) = rho_p,
-// symmetric positive definite once one face is Dirichlet. Solved by
+// zero-Neumann symmetry planes of §3.1.3 and the open faces of §5.2.2).
+// Node-centred finite volumes on the PIC nodes: a node's control volume is
+// its dual cell clipped to the box, so on a Neumann face the zero flux is
+// natural; the flux through the dual face of the link p-q is
+// eps_pq w (phi_p - phi_q) h, w = product of the two tangential half-width
+// factors c = 1/2 at a boundary index, else 1; the charge in the control
+// volume is rho_p h^3 with rho_p the deposited nodal density (which at a
+// boundary node already counts only the inside part of the cloud). So
+//   (A phi)_p = 1 / h^2 sum_links eps_pq w (phi_p - phi_q) = rho_p,
+// symmetric positive definite once one face is Dirichlet.
+//
+// The object as an interface (eq. (2.2)-(2.5); the paper discretises it with
+// immersed finite elements on the same Cartesian mesh): the object region
+// (sphere interior, or below the terrain) has eps_in, the plasma eps. A level
+// set psi (< 0 inside: |x - c| - R for the sphere, z - h(x, y) for the
+// terrain) is evaluated at the nodes; a link whose ends have psi of the same
+// sign has that side's eps; a link that crosses has the inside fraction f from
+// linear interpolation of psi (crossing at t = psi_a / (psi_a - psi_b) from
+// the lower-index end a) and the series (harmonic) permittivity
+// 1 / (f / eps_in + (1 - f) / eps), exact for a layered medium. The flux-jump
+// source q(X) of eq. (2.5) is the collected surface charge, which enters the
+// right-hand side as charge at the surface points of its tally bins (see
+// orc_surface_rho). With no object, eps_pq = eps everywhere. Solved by
 // preconditioned conjugate gradients (the PCG of §2.4) from the initial guess
 // in phi, until ||r||_2 <= tol ||b||_2 (b: rho plus the Dirichlet terms) or
 // max_iter iterations. The paper leaves the preconditioner open; two are
@@ -1034,12 +1056,78 @@ namespace {
 // the normal component is 0; on a Dirichlet face the second-order one-sided
 // difference.
 
+// The object in the field problem (fine-mesh cell units, origin at node 0).
+struct FieldObject {
+  int kind;          // 1 sphere, 2 crater terrain
+  double c[3], r;    // sphere centre, radius; crater: axis (c[0], c[1])
+  double z_flat, a2, zc, rc2;  // crater: flat ground, rim radius^2, bowl sphere centre, radius^2
+  double eps_in;
+};
+
+// Level set at a point (fine cells): < 0 inside the object.
+double object_psi(const FieldObject& o, double x, double y, double z) {
+  if (o.kind == OBJ_SPHERE) {
+    const double dx = x - o.c[0], dy = y - o.c[1], dz = z - o.c[2];
+    return std::sqrt(dx * dx + dy * dy + dz * dz) - o.r;
+  }
+  const double dx = x - o.c[0], dy = y - o.c[1];
+  const double r2 = dx * dx + dy * dy;
+  const double ground = r2 < o.a2 ? o.zc - std::sqrt(o.rc2 - r2) : o.z_flat;
+  return z - ground;
+}
+
+bool field_object(const orc_field_object& in, FieldObject& o) {
+  if (!(in.eps_in > 0) || !std::isfinite(in.eps_in)) return false;
+  o = FieldObject{};
+  o.kind = in.kind;
+  o.eps_in = in.eps_in;
+  for (int d = 0; d < 3; ++d) o.c[d] = in.center[d];
+  if (in.kind == OBJ_SPHERE) {
+    if (!(in.radius > 0)) return false;
+    o.r = in.radius;
+    return true;
+  }
+  if (in.kind == OBJ_CRATER) {
+    if (!(in.depth > 0) || !(in.rim_radius > 0)) return false;
+    const double a = in.rim_radius, dep = in.depth;
+    const double Rc = (a * a + dep * dep) / (2.0 * dep);
+    o.z_flat = in.z_flat;
+    o.a2 = a * a;
+    o.zc = in.z_flat - dep + Rc;
+    o.rc2 = Rc * Rc;
+    return true;
+  }
+  return false;
+}
+
+// Series permittivity of a link whose lower-index end has psi a, the other b.
+double link_eps(double a, double b, double ein, double eout) {
+  const bool ia = a < 0.0, ib = b < 0.0;
+  if (ia == ib) return ia ? ein : eout;
+  const double t = a / (a - b);
+  const double f = ia ? t : 1.0 - t;
+  return (ein * eout) / (f * eout + (1.0 - f) * ein);
+}
+
 struct FieldGrid {
   int32_t n[3];
   int64_t sx, sy, nodes;
   double h, eps;
   int32_t mask;
   double g[6];
+  double scale = 1.0;               // fine cells per cell of this grid
+  const FieldObject* obj = nullptr;  // null: uniform eps
+  double psi(int i, int j, int k) const {
+    return object_psi(*obj, scale * i, scale * j, scale * k);
+  }
+  // coefficient of the link (i, j, k) - (i2, j2, k2) with tangential weight w
+  double coef(int i, int j, int k, int i2, int j2, int k2, double w) const {
+    if (!obj) return eps / (h * h) * w;
+    const bool lower = id(i, j, k) < id(i2, j2, k2);
+    const double a = lower ? psi(i, j, k) : psi(i2, j2, k2);
+    const double b = lower ? psi(i2, j2, k2) : psi(i, j, k);
+    return link_eps(a, b, obj->eps_in, eps) * w / (h * h);
+  }
   bool dir(int i, int j, int k) const {
     return ((mask & 1) && i == 0) || ((mask & 2) && i == n[0]) || ((mask & 4) && j == 0) ||
            ((mask & 8) && j == n[1]) || ((mask & 16) && k == 0) || ((mask & 32) && k == n[2]);
@@ -1057,16 +1145,18 @@ struct FieldGrid {
   int64_t id(int i, int j, int k) const { return i + sx * j + sy * k; }
 };
 
-// Visits the links of node (i, j, k): f(q, w) for each neighbour q in the box.
+// Visits the links of node (i, j, k): f(q, c) for each neighbour q in the box,
+// c the link's coefficient in A (eps_pq w / h^2).
 template <class F>
 void field_links(const FieldGrid& G, int i, int j, int k, F f) {
   const int64_t p = G.id(i, j, k);
-  if (i > 0) f(p - 1, G.c(1, j) * G.c(2, k));
-  if (i < G.n[0]) f(p + 1, G.c(1, j) * G.c(2, k));
-  if (j > 0) f(p - G.sx, G.c(0, i) * G.c(2, k));
-  if (j < G.n[1]) f(p + G.sx, G.c(0, i) * G.c(2, k));
-  if (k > 0) f(p - G.sy, G.c(0, i) * G.c(1, j));
-  if (k < G.n[2]) f(p + G.sy, G.c(0, i) * G.c(1, j));
+  const double wx = G.c(1, j) * G.c(2, k), wy = G.c(0, i) * G.c(2, k), wz = G.c(0, i) * G.c(1, j);
+  if (i > 0) f(p - 1, G.coef(i, j, k, i - 1, j, k, wx));
+  if (i < G.n[0]) f(p + 1, G.coef(i, j, k, i + 1, j, k, wx));
+  if (j > 0) f(p - G.sx, G.coef(i, j, k, i, j - 1, k, wy));
+  if (j < G.n[1]) f(p + G.sx, G.coef(i, j, k, i, j + 1, k, wy));
+  if (k > 0) f(p - G.sy, G.coef(i, j, k, i, j, k - 1, wz));
+  if (k < G.n[2]) f(p + G.sy, G.coef(i, j, k, i, j, k + 1, wz));
 }
 
 FieldGrid field_grid(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t mask,
@@ -1113,11 +1203,13 @@ bool mg_setup(const FieldGrid& G0, Multigrid& M) {
   while (M.lv.back().nodes > kMgCoarseNodes && (int)M.lv.size() < kMgLevels) {
     const FieldGrid& f = M.lv.back();
     if (f.n[0] % 2 || f.n[1] % 2 || f.n[2] % 2) break;
-    M.lv.push_back(field_grid(f.n[0] / 2, f.n[1] / 2, f.n[2] / 2, 2.0 * f.h, f.eps, f.mask, f.g));
+    FieldGrid c = field_grid(f.n[0] / 2, f.n[1] / 2, f.n[2] / 2, 2.0 * f.h, f.eps, f.mask, f.g);
+    c.scale = 2.0 * f.scale;
+    c.obj = f.obj;
+    M.lv.push_back(c);
   }
   if (M.lv.size() < 2 || M.lv.back().nodes > kMgCoarseNodes) return false;
   const FieldGrid& C = M.lv.back();
-  const double s = C.eps / (C.h * C.h);
   std::vector<int64_t> pos(C.nodes, -1);
   for (int64_t q = 0; q < C.nodes; ++q)
     if (!dirichlet_node(C, q)) {
@@ -1129,9 +1221,9 @@ bool mg_setup(const FieldGrid& G0, Multigrid& M) {
   for (int64_t u = 0; u < m; ++u) {
     const int64_t q0 = M.unk[u];
     const int i = (int)(q0 % C.sx), j = (int)((q0 / C.sx) % (C.n[1] + 1)), k = (int)(q0 / C.sy);
-    field_links(C, i, j, k, [&](int64_t q, double w) {
-      A[u * m + u] += s * w;
-      if (pos[q] >= 0) A[u * m + pos[q]] -= s * w;
+    field_links(C, i, j, k, [&](int64_t q, double c) {
+      A[u * m + u] += c;
+      if (pos[q] >= 0) A[u * m + pos[q]] -= c;
     });
   }
   // A = L L^T
@@ -1149,14 +1241,14 @@ bool mg_setup(const FieldGrid& G0, Multigrid& M) {
 double mg_apply(const FieldGrid& G, const std::vector<double>& e, int i, int j, int k) {
   const int64_t p = G.id(i, j, k);
   double a = 0.0;
-  field_links(G, i, j, k, [&](int64_t q, double w) { a += w * (e[p] - e[q]); });
-  return G.eps / (G.h * G.h) * a;
+  field_links(G, i, j, k, [&](int64_t q, double c) { a += c * (e[p] - e[q]); });
+  return a;
 }
 
 double mg_diag(const FieldGrid& G, int i, int j, int k) {
   double d = 0.0;
-  field_links(G, i, j, k, [&](int64_t, double w) { d += w; });
-  return G.eps / (G.h * G.h) * d;
+  field_links(G, i, j, k, [&](int64_t, double c) { d += c; });
+  return d;
 }
 
 void mg_jacobi(const FieldGrid& G, const std::vector<double>& b, std::vector<double>& e) {
@@ -1251,7 +1343,6 @@ int field_solve(const FieldGrid& G, const double* rho, double* x, double tol, in
     }
   };
   const int64_t N = G.nodes;
-  const double s = G.eps / (G.h * G.h);
   std::vector<double> r(N, 0.0), z(N, 0.0), p(N, 0.0), Ap(N, 0.0), D(N, 0.0);
   std::vector<char> unk(N, 0);
   double bb = 0.0, rz = 0.0, rr = 0.0;
@@ -1271,13 +1362,13 @@ int field_solve(const FieldGrid& G, const double* rho, double* x, double tol, in
         const int64_t q0 = G.id(i, j, k);
         if (!unk[q0]) continue;
         double ax = 0.0, b = rho[q0], d = 0.0;
-        field_links(G, i, j, k, [&](int64_t q, double w) {
-          ax += w * (x[q0] - x[q]);
-          d += w;
-          if (!unk[q]) b += s * w * x[q];
+        field_links(G, i, j, k, [&](int64_t q, double c) {
+          ax += c * (x[q0] - x[q]);
+          d += c;
+          if (!unk[q]) b += c * x[q];
         });
-        r[q0] = rho[q0] - s * ax;
-        D[q0] = s * d;
+        r[q0] = rho[q0] - ax;
+        D[q0] = d;
         bb += b * b;
         rr += r[q0] * r[q0];
       }
@@ -1297,8 +1388,8 @@ int field_solve(const FieldGrid& G, const double* rho, double* x, double tol, in
             const int64_t q0 = G.id(i, j, k);
             if (!unk[q0]) continue;
             double a = 0.0;
-            field_links(G, i, j, k, [&](int64_t q, double w) { a += w * (p[q0] - p[q]); });
-            Ap[q0] = s * a;
+            field_links(G, i, j, k, [&](int64_t q, double c) { a += c * (p[q0] - p[q]); });
+            Ap[q0] = a;
             pap += p[q0] * Ap[q0];
           }
       const double alpha = rz / pap;
@@ -1387,25 +1478,38 @@ void orc_normals3(uint64_t key, double z[3]) {
 // 1 Jacobi; *levels gets the multigrid level count used (0: Jacobi). Returns
 // 0, or -1 for invalid arguments (no Dirichlet face, h or eps not > 0, tol not
 // > 0, max_iter < 0, precond not 0 or 1).
+// obj (nullable, or kind 0): the object as an interface with permittivity
+// eps_in inside (see above).
 int orc_field_solve(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t dirichlet,
                     const double* g, const double* rho, double* phi, double tol, int32_t max_iter,
-                    int32_t precond, int32_t* iters, double* relres, int32_t* levels) {
+                    int32_t precond, const orc_field_object* obj, int32_t* iters, double* relres,
+                    int32_t* levels) {
   if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || !(tol > 0) || max_iter < 0 ||
       (dirichlet & 63) == 0 || (dirichlet & ~63) || !rho || !phi || precond < 0 || precond > 1)
     return ORC_E_INVALID;
-  return field_solve(field_grid(nx, ny, nz, h, eps, dirichlet, g), rho, phi, tol, max_iter, precond,
-                     iters, relres, levels);
+  FieldObject fo{};
+  FieldGrid G = field_grid(nx, ny, nz, h, eps, dirichlet, g);
+  if (obj && obj->kind != 0) {
+    if (!field_object(*obj, fo)) return ORC_E_INVALID;
+    G.obj = &fo;
+  }
+  return field_solve(G, rho, phi, tol, max_iter, precond, iters, relres, levels);
 }
 
 // One multigrid V-cycle z = B r on the grid (homogeneous Dirichlet faces in
 // the mask), for the pins of the preconditioner. Returns the level count, or
 // 0 when the grid does not coarsen (z untouched), -1 for invalid arguments.
 int orc_field_vcycle(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t dirichlet,
-                     const double* r, double* z) {
+                     const orc_field_object* obj, const double* r, double* z) {
   if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || (dirichlet & 63) == 0 ||
       (dirichlet & ~63) || !r || !z)
     return ORC_E_INVALID;
-  const FieldGrid G = field_grid(nx, ny, nz, h, eps, dirichlet, nullptr);
+  FieldObject fo{};
+  FieldGrid G = field_grid(nx, ny, nz, h, eps, dirichlet, nullptr);
+  if (obj && obj->kind != 0) {
+    if (!field_object(*obj, fo)) return ORC_E_INVALID;
+    G.obj = &fo;
+  }
   Multigrid M;
   if (!mg_setup(G, M)) return 0;
   std::vector<double> b(r, r + G.nodes), e;
@@ -1420,6 +1524,79 @@ void orc_field_E(int32_t nx, int32_t ny, int32_t nz, double h, int32_t dirichlet
                  double* Ex, double* Ey, double* Ez) {
   double* E[3] = {Ex, Ey, Ez};
   field_E(field_grid(nx, ny, nz, h, 1.0, dirichlet, nullptr), phi, E);
+}
+
+// Level set of the object at points (cell units), for the pins.
+double orc_object_psi(const orc_field_object* obj, double x, double y, double z) {
+  FieldObject fo{};
+  if (!obj || !field_object(*obj, fo)) return 0.0;
+  return object_psi(fo, x, y, z);
+}
+
+// The collected surface charge as a source of the field problem (the flux
+// jump q(X) of eq. (2.5)): the charge of each tally bin, sum over species of
+// (q_s w_s) count[bin][s] in FP64, is placed at the bin's surface point and
+// deposited to the mesh nodes like a particle's charge (trilinear weights,
+// int64 fixed point at 2^32 with the remainder rule of the deposit), added to
+// rho_fixed (nodes). The surface point of a crater column (i, j) is the
+// terrain above its centre, (i + 1/2, j + 1/2, ground height); of a sphere
+// patch the sphere point in the direction of the patch centre (the centre of
+// its (iu, iv) square on its cube face). A sphere without patches has one bin
+// for the whole sphere and no surface point: returns -1 then, and for invalid
+// arguments; 0 otherwise.
+int orc_surface_rho(const orc_config* cfg, const int64_t* tally, int64_t* rho_fixed) {
+  if (!cfg || !tally || !rho_fixed) return ORC_E_INVALID;
+  if (cfg->obj_kind == OBJ_NONE) return ORC_OK;
+  if (cfg->obj_kind == OBJ_SPHERE && cfg->sphere_patches < 1) return ORC_E_INVALID;
+  const Mesh M = make_mesh(*cfg);
+  const Geometry<double> G = make_geometry<double>(*cfg);
+  const int ns = cfg->n_species;
+  const int m = cfg->sphere_patches;
+  const int64_t nbins =
+      cfg->obj_kind == OBJ_CRATER ? (int64_t)cfg->nx * cfg->ny : 6 * (int64_t)m * m;
+  for (int64_t b = 0; b < nbins; ++b) {
+    double Q = 0.0;
+    for (int s = 0; s < ns; ++s) Q += (cfg->q[s] * cfg->w[s]) * (double)tally[b * ns + s];
+    if (Q == 0.0) continue;
+    double g[3];
+    if (cfg->obj_kind == OBJ_CRATER) {
+      g[0] = (double)(b % cfg->nx) + 0.5;
+      g[1] = (double)(b / cfg->nx) + 0.5;
+      const double dx = g[0] - G.c[0], dy = g[1] - G.c[1];
+      const double a = cfg->rim_radius / cfg->h;
+      const double r2 = dx * dx + dy * dy;
+      g[2] = r2 < a * a ? G.c[2] - std::sqrt(G.r2 - r2) : G.z_flat;
+    } else {
+      const int face = (int)(b / ((int64_t)m * m)), iv = (int)((b / m) % m), iu = (int)(b % m);
+      const int ax = face / 2;
+      const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+      double d[3];
+      d[ax] = face % 2 ? 1.0 : -1.0;
+      d[u] = -1.0 + (2.0 * iu + 1.0) / m;
+      d[v] = -1.0 + (2.0 * iv + 1.0) / m;
+      const double len = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double R = std::sqrt(G.r2);
+      for (int k = 0; k < 3; ++k) g[k] = G.c[k] + R * (d[k] / len);
+    }
+    int32_t i[3];
+    double f[3];
+    for (int k = 0; k < 3; ++k) {
+      double fl = std::floor(g[k]);
+      if (fl < 0.0) fl = 0.0;
+      if (fl > (double)(M.n[k] - 1)) fl = (double)(M.n[k] - 1);
+      i[k] = (int32_t)fl;
+      double o = g[k] - fl;
+      o = o < 0.0 ? 0.0 : (o > 1.0 ? 1.0 : o);
+      f[k] = o;
+    }
+    double W[8];
+    weights(f, W);
+    int64_t C[8], idx[8];
+    fixed_contrib(Q, W, C);
+    corners(M, i, idx);
+    for (int n = 0; n < 8; ++n) rho_fixed[idx[n]] += C[n];
+  }
+  return ORC_OK;
 }
 
 // Object predicate at one point (physical units), in the arithmetic of `repr`.
