@@ -250,6 +250,12 @@ pic_status pic_get_counters(pic_ctx *ctx, int64_t *alive, int64_t *absorbed, int
  * differences; 0 normal to a zero-Neumann face; second-order one-sided on a
  * Dirichlet face) becomes the context's node field, as pic_set_node_E would.
  *
+ * With eps_object > 0 each link's permittivity is the series (harmonic)
+ * combination of eps_object and eps by the fraction of the link inside the
+ * object, from linear interpolation of a level set at its two nodes
+ * (|x - c| - R for the sphere, z - ground(x, y) for the terrain); the same
+ * rule on every multigrid level. Exact for a layered medium.
+ *
  * Preconditioners (the paper does not fix one):
  *   PIC_PRECOND_MULTIGRID: one geometric multigrid V-cycle on nested node
  *     grids (every other node, spacing doubled, while the grid has more than
@@ -270,6 +276,20 @@ typedef struct {
   double tol;        /* relative residual (> 0); the paper uses 1e-6 */
   int32_t max_iter;  /* >= 0; the paper uses 60-150 per PIC step */
   int32_t preconditioner; /* PIC_PRECOND_* */
+  double eps_object;      /* > 0: the object is an interface of the problem (eq.
+                             (2.2)-(2.5)) with this permittivity inside it (the
+                             sphere's interior, or below the terrain) and eps
+                             outside; 0: uniform eps (the object is not part of
+                             the field problem) */
+  int32_t surface_charge; /* 1: the collected charge of pic_get_surface_charge is
+                             the flux-jump source q(X) of eq. (2.5), placed at
+                             each tally bin's surface point (crater column:
+                             the terrain above its centre; sphere patch: the
+                             sphere point towards the patch centre; a sphere
+                             needs patches >= 1) and deposited to the nodes in
+                             int64 fixed point like a particle's charge; a
+                             bin's charge must stay below 2^30 in magnitude
+                             (PIC_E_RANGE at the solve). 0: volume charge only */
 } pic_field;
 
 /* Solves for the deposit of the last pic_step (PIC_E_STATE before any) and

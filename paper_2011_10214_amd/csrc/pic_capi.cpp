@@ -229,9 +229,15 @@ struct pic_ctx {
   double *mg_ainv = nullptr;    // coarsest inverse (m x m)
   int32_t *mg_umap = nullptr;   // coarsest unknowns' nodes
   int32_t mg_m = 0;
-  int32_t mg_mask = -1;         // faces and eps the inverse was computed for
-  double mg_eps = 0.0;
+  int32_t mg_mask = -1;         // faces and permittivities the inverse was computed for
+  double mg_eps = 0.0, mg_eps_obj = 0.0;
+  bool mg_bufs = false;         // multigrid level buffers allocated
   int32_t field_levels = 0;     // of the last solve
+  // object as an interface: level sets (once) and diagonals (per permittivities)
+  int32_t if_psi_levels = 0;    // levels whose psi is computed
+  int32_t if_diag_levels = 0;   // levels whose diag matches if_eps_*
+  double if_eps_in = 0.0, if_eps_out = 0.0;
+  int64_t *rho_surf = nullptr;  // surface source (fixed point)
 };
 
 namespace {
@@ -361,6 +367,8 @@ pic_status sync_and_check(pic_ctx *c) {
     PIC_HIP(c, hipMemcpy(c->err, &zero, sizeof(zero), hipMemcpyHostToDevice));
     if (err & kErrCapacity)
       return fail(c, PIC_E_NOMEM, "particles were lost: the tile regions and overflow list are full");
+    if (err == kErrSurface)
+      return fail(c, PIC_E_RANGE, "a tally bin's collected charge reached 2^30 (surface source)");
     return fail(c, PIC_E_RANGE, "a particle position became non-finite or moved > 2^20 cells");
   }
   return PIC_OK;
@@ -1074,8 +1082,49 @@ bool level_dir(const MgLevel &L, int mask, int i, int j, int k) {
 // The coarsest level's operator on its unknowns (non-Dirichlet nodes, in node
 // order), inverted on the host: A = L L^T, W = L^-1, A^-1 = W^T W. Returns
 // false if A is not positive definite (it always is with a Dirichlet face).
-bool coarse_inverse(const MgLevel &C, int mask, double s, std::vector<double> &inv,
-                    std::vector<int32_t> &umap) {
+// Level set of the object (cell units of the PIC mesh); the kernels'
+// field_psi_kernel evaluates the same expression.
+double geo_psi(const FieldGeom &o, double x, double y, double z) {
+  if (o.kind == PIC_OBJ_SPHERE) {
+    const double dx = x - o.c[0], dy = y - o.c[1], dz = z - o.c[2];
+    return std::sqrt(dx * dx + dy * dy + dz * dz) - o.r;
+  }
+  const double dx = x - o.c[0], dy = y - o.c[1];
+  const double r2 = dx * dx + dy * dy;
+  const double ground = r2 < o.a2 ? o.zc - std::sqrt(o.rc2 - r2) : o.z_flat;
+  return z - ground;
+}
+
+double link_eps(double a, double b, double ein, double eout) {
+  const bool ia = a < 0.0, ib = b < 0.0;
+  if (ia == ib) return ia ? ein : eout;
+  const double t = a / (a - b);
+  const double f = ia ? t : 1.0 - t;
+  return (ein * eout) / (f * eout + (1.0 - f) * ein);
+}
+
+// Field geometry of the context's object in cell units.
+FieldGeom field_geom(const pic_ctx *c) {
+  const Geom g = geometry_of(c->cfg);
+  FieldGeom o{};
+  o.kind = c->cfg.object.kind;
+  for (int d = 0; d < 3; ++d) o.c[d] = g.c[d];
+  o.patches = c->cfg.object.patches;
+  if (o.kind == PIC_OBJ_SPHERE) {
+    o.r = c->cfg.object.radius / c->cfg.h;
+    o.rs = std::sqrt(g.r2);
+  } else if (o.kind == PIC_OBJ_CRATER) {
+    const double a = c->cfg.object.rim_radius / c->cfg.h;
+    o.z_flat = g.z_flat;
+    o.a2 = a * a;
+    o.zc = g.c[2];
+    o.rc2 = g.r2;
+  }
+  return o;
+}
+
+bool coarse_inverse(const MgLevel &C, int mask, double s, const FieldGeom *obj, double ein,
+                    double eout, std::vector<double> &inv, std::vector<int32_t> &umap) {
   std::vector<int64_t> pos(C.nodes, -1);
   umap.clear();
   for (int k = 0; k <= C.n[2]; ++k)
@@ -1099,8 +1148,18 @@ bool coarse_inverse(const MgLevel &C, int mask, double s, std::vector<double> &i
         {j < C.n[1], q + C.sx, wy}, {k > 0, q - C.sy, wz},      {k < C.n[2], q + C.sy, wz}};
     for (const auto &L : links) {
       if (!L.ok) continue;
-      A[u * m + u] += s * L.w;
-      if (pos[L.nb] >= 0) A[u * m + pos[L.nb]] -= s * L.w;
+      double cf = s * L.w;
+      if (obj) {  // series permittivity of the link, lower-index end first
+        const int64_t lo = std::min(q, L.nb), hi = std::max(q, L.nb);
+        auto psi = [&](int64_t n) {
+          const int a = (int)(n % C.sx), b = (int)((n / C.sx) % (C.n[1] + 1)),
+                    cc = (int)(n / C.sy);
+          return geo_psi(*obj, C.scale * a, C.scale * b, C.scale * cc);
+        };
+        cf = link_eps(psi(lo), psi(hi), ein, eout) * L.w * C.ih2;
+      }
+      A[u * m + u] += cf;
+      if (pos[L.nb] >= 0) A[u * m + pos[L.nb]] -= cf;
     }
   }
   for (int64_t r = 0; r < m; ++r)  // Cholesky, lower factor in place
@@ -1156,6 +1215,14 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
     return fail(c, PIC_E_INVALID, "preconditioner: PIC_PRECOND_MULTIGRID or PIC_PRECOND_JACOBI");
   for (int f = 0; f < 6; ++f)
     if (!is_finite(fs->value[f])) return fail(c, PIC_E_INVALID, "face values must be finite");
+  if (!(fs->eps_object >= 0) || !is_finite(fs->eps_object))
+    return fail(c, PIC_E_INVALID, "eps_object must be >= 0 (0: no interface)");
+  if (fs->surface_charge != 0 && fs->surface_charge != 1)
+    return fail(c, PIC_E_INVALID, "surface_charge must be 0 or 1");
+  if ((fs->eps_object > 0 || fs->surface_charge) && c->cfg.object.kind == PIC_OBJ_NONE)
+    return fail(c, PIC_E_INVALID, "eps_object and surface_charge need an object");
+  if (fs->surface_charge && c->cfg.object.kind == PIC_OBJ_SPHERE && c->cfg.object.patches < 1)
+    return fail(c, PIC_E_INVALID, "surface_charge on a sphere needs surface patches");
   if (!c->deposited) return fail(c, PIC_E_STATE, "no deposit yet (call pic_step first)");
   const Dims &L = c->L;
   const int64_t nodes = L.nodes;
@@ -1177,40 +1244,64 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
     c->fctrl_host = (FieldCtrl *)q;
     PIC_HIP(c, launch_fill(c->fx, nodes * 8, c->stream));
   }
-  int32_t levels = 0;
-  if (fs->preconditioner == PIC_PRECOND_MULTIGRID) {
-    if (c->mg_levels < 0) {
-      MgLevel lv[kMaxLevels];
-      const int32_t n = mg_plan(L, lv);
-      for (int l = 0; l < n; ++l) {
-        void *q = nullptr;
-        const int64_t b = lv[l].nodes * 8;
-        double **bufs[4] = {&lv[l].e, &lv[l].e2, &lv[l].res, &lv[l].rhs};
-        for (int t = 0; t < 4; ++t) {
-          if (l == 0 && (t == 0 || t == 3)) continue;  // level 0: e = z, rhs = r
-          if (dmalloc(c, &q, b) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-          *bufs[t] = (double *)q;
-        }
-      }
-      if (n > 0) {
-        void *q = nullptr;
-        const int64_t cn = lv[n - 1].nodes;
-        if (dmalloc(c, &q, cn * cn * 8) != hipSuccess)
-          return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-        c->mg_ainv = (double *)q;
-        if (dmalloc(c, &q, cn * 4) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-        c->mg_umap = (int32_t *)q;
-      }
-      for (int l = 0; l < n; ++l) c->mg[l] = lv[l];
-      c->mg_levels = n;
+  // multigrid plan (once): level 0 is the PIC mesh; levels >= 2 when it coarsens
+  if (c->mg_levels < 0) {
+    MgLevel lv[kMaxLevels];
+    const int32_t n = mg_plan(L, lv);
+    for (int l = 0; l < std::max(n, 1); ++l) {
+      lv[l].scale = (double)(1 << l);
+      const double hl = c->cfg.h * lv[l].scale;
+      lv[l].ih2 = 1.0 / (hl * hl);
+      c->mg[l] = lv[l];
     }
-    levels = c->mg_levels;
-    if (levels >= 2 && (c->mg_mask != fs->dirichlet || c->mg_eps != fs->eps)) {
+    c->mg_levels = n;
+  }
+  const bool use_mg = fs->preconditioner == PIC_PRECOND_MULTIGRID && c->mg_levels >= 2;
+  const int32_t levels = use_mg ? c->mg_levels : 0;
+  const int32_t nl = std::max(levels, 1);  // grids the solve uses
+  if (use_mg && !c->mg_bufs) {
+    for (int l = 0; l < levels; ++l) {
+      void *q = nullptr;
+      MgLevel &lv = c->mg[l];
+      const int64_t b = lv.nodes * 8;
+      double **bufs[4] = {&lv.e, &lv.e2, &lv.res, &lv.rhs};
+      for (int t = 0; t < 4; ++t) {
+        if (l == 0 && (t == 0 || t == 3)) continue;  // level 0: e = z, rhs = r
+        if (dmalloc(c, &q, b) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+        *bufs[t] = (double *)q;
+      }
+    }
+    void *q = nullptr;
+    const int64_t cn = c->mg[levels - 1].nodes;
+    if (dmalloc(c, &q, cn * cn * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+    c->mg_ainv = (double *)q;
+    if (dmalloc(c, &q, cn * 4) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+    c->mg_umap = (int32_t *)q;
+    c->mg_bufs = true;
+  }
+  const bool iface = fs->eps_object > 0;
+  const FieldGeom geo = field_geom(c);
+  if (iface) {
+    for (int l = 0; l < nl; ++l) {
+      if (c->mg[l].psi) continue;
+      void *q = nullptr;
+      if (dmalloc(c, &q, c->mg[l].nodes * 8) != hipSuccess)
+        return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+      c->mg[l].psi = (double *)q;
+      if (dmalloc(c, &q, c->mg[l].nodes * 8) != hipSuccess)
+        return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+      c->mg[l].diag = (double *)q;
+    }
+  }
+  if (levels >= 2) {
+    const double eobj = iface ? fs->eps_object : 0.0;
+    if (c->mg_mask != fs->dirichlet || c->mg_eps != fs->eps || c->mg_eps_obj != eobj) {
       const MgLevel &C = c->mg[levels - 1];
-      const double hc = c->cfg.h * (double)(1 << (levels - 1));
+      const double hc = c->cfg.h * C.scale;
       std::vector<double> inv;
       std::vector<int32_t> umap;
-      if (!coarse_inverse(C, fs->dirichlet, fs->eps / (hc * hc), inv, umap))
+      if (!coarse_inverse(C, fs->dirichlet, fs->eps / (hc * hc), iface ? &geo : nullptr,
+                          fs->eps_object, fs->eps, inv, umap))
         return fail(c, PIC_E_DEVICE, "coarsest multigrid operator is not positive definite");
       c->mg_m = (int32_t)umap.size();
       if (c->mg_m > 0) {
@@ -1222,6 +1313,7 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
       }
       c->mg_mask = fs->dirichlet;
       c->mg_eps = fs->eps;
+      c->mg_eps_obj = eobj;
     }
   }
   FieldParams P{};
@@ -1249,20 +1341,59 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   P.max_iter = fs->max_iter;
   P.G = G;
   P.levels = levels;
+  for (int l = 0; l < nl; ++l) {
+    P.lv[l] = c->mg[l];
+    P.lv[l].mask = fs->dirichlet;
+    const double hl = c->cfg.h * c->mg[l].scale;
+    P.lv[l].s = fs->eps / (hl * hl);
+  }
+  P.lv[0].e = c->fz;
+  P.lv[0].rhs = c->fr;
   if (levels >= 2) {
-    for (int l = 0; l < levels; ++l) {
-      P.lv[l] = c->mg[l];
-      P.lv[l].mask = fs->dirichlet;
-      const double hl = c->cfg.h * (double)(1 << l);
-      P.lv[l].s = fs->eps / (hl * hl);
-    }
-    P.lv[0].e = c->fz;
-    P.lv[0].rhs = c->fr;
     P.ainv = c->mg_ainv;
     P.umap = c->mg_umap;
     P.m = c->mg_m;
   }
+  P.iface = iface ? 1 : 0;
+  P.e_in = fs->eps_object;
+  P.e_out = fs->eps;
+  P.geo = geo;
+  P.psi = c->mg[0].psi;
+  P.diag = c->mg[0].diag;
+  P.ih2 = c->mg[0].ih2;
   const int pe = prof_begin(c, 4);
+  if (iface) {  // level sets once, diagonals when the permittivities change
+    for (int l = c->if_psi_levels; l < nl; ++l) PIC_HIP(c, launch_field_psi(P, l, c->stream));
+    c->if_psi_levels = std::max(c->if_psi_levels, nl);
+    if (c->if_eps_in != fs->eps_object || c->if_eps_out != fs->eps) c->if_diag_levels = 0;
+    for (int l = c->if_diag_levels; l < nl; ++l) PIC_HIP(c, launch_field_diag(P, l, c->stream));
+    c->if_diag_levels = std::max(c->if_diag_levels, nl);
+    c->if_eps_in = fs->eps_object;
+    c->if_eps_out = fs->eps;
+  }
+  if (fs->surface_charge) {
+    if (!c->rho_surf) {
+      void *q = nullptr;
+      if (dmalloc(c, &q, nodes * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+      c->rho_surf = (int64_t *)q;
+    }
+    PIC_HIP(c, launch_fill(c->rho_surf, nodes * 8, c->stream));
+    SurfParams S{};
+    S.tally = c->tally;
+    for (int sp = 0; sp < L.ns; ++sp) S.chg[sp] = c->cfg.species[sp].q * c->cfg.species[sp].weight;
+    S.ns = L.ns;
+    S.nbins = L.nbins;
+    S.n[0] = L.nx;
+    S.n[1] = L.ny;
+    S.n[2] = L.nz;
+    S.sx = P.sx;
+    S.sy = P.sy;
+    S.geo = geo;
+    S.rho_surf = c->rho_surf;
+    S.err = c->err;
+    PIC_HIP(c, launch_surface_rho(S, c->stream));
+    P.rho_surf = c->rho_surf;
+  }
   PIC_HIP(c, launch_field_init(c->cfg.deposit, P, c->stream));
   if (levels >= 2) PIC_HIP(c, launch_field_mg_start(P, c->stream));
   // iterations in chunks; the kernels themselves stop at convergence or
@@ -1283,6 +1414,10 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
                             c->stream));
   PIC_HIP(c, hipStreamSynchronize(c->stream));
   const FieldCtrl f = *c->fctrl_host;
+  if (fs->surface_charge) {
+    const pic_status st = sync_and_check(c);
+    if (st != PIC_OK) return st;
+  }
   if (c->prof) c->acc.field_iterations += f.iters;
   if (iterations) *iterations = f.iters;
   if (rel_residual) *rel_residual = f.bb > 0 ? std::sqrt(f.rr) / std::sqrt(f.bb) : 0.0;

@@ -26,6 +26,7 @@ constexpr int kMaxDim = (1 << kCellBits) - 1;
 enum : int32_t {
   kErrRange = 1,     // a particle position became non-finite / ran away
   kErrCapacity = 2,  // the overflow list itself overflowed (particles lost)
+  kErrSurface = 4,   // a tally bin's collected charge reached 2^30 (surface source)
 };
 
 // Per-species particle arrays of one buffer. Positions: x/y/z (FP64, FP32
@@ -189,6 +190,19 @@ struct MgLevel {
   double s;                    // eps / h_l^2
   double *e, *e2, *res, *rhs;  // correction (ping-pong), residual, right-hand side
   int32_t G;                   // workgroups of the level's kernels
+  // object as an interface: level set and diagonal of A at the level's nodes
+  double *psi, *diag;
+  double ih2;                  // 1 / h_l^2
+  double scale;                // fine cells per cell of the level
+};
+
+// The object in the field problem (cell units of the PIC mesh).
+struct FieldGeom {
+  int32_t kind;                 // PIC_OBJ_SPHERE or PIC_OBJ_CRATER
+  double c[3], r;               // sphere centre and radius; crater axis (c[0], c[1])
+  double z_flat, a2, zc, rc2;   // crater: flat ground, rim radius^2, bowl centre, radius^2
+  double rs;                    // sphere: radius of the surface points (sqrt of R^2)
+  int32_t patches;
 };
 
 struct FieldParams {
@@ -212,6 +226,27 @@ struct FieldParams {
   const double *ainv;       // coarsest level: inverse operator on its m unknowns (m x m)
   const int32_t *umap;      // coarsest level: node of each unknown
   int32_t m;
+  // object as an interface (iface): permittivities, level set and diagonal of
+  // the fine level (= lv[0].psi / lv[0].diag), geometry; surface source
+  int32_t iface;
+  double e_in, e_out;
+  const double *psi, *diag;
+  double ih2;
+  FieldGeom geo;
+  const int64_t *rho_surf;  // fixed-point surface charge (nullable)
+};
+
+// The collected charge as a surface source: one thread per tally bin.
+struct SurfParams {
+  const int64_t *tally;     // [nbins][ns]
+  double chg[PIC_MAX_SPECIES];  // q_s w_s
+  int32_t ns;
+  int64_t nbins;
+  int32_t n[3];
+  int64_t sx, sy;
+  FieldGeom geo;
+  int64_t *rho_surf;        // [nodes], cleared before
+  int32_t *err;
 };
 
 // Batched runs: many contexts (slots) advanced by one launch per step. Work
@@ -248,6 +283,10 @@ hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s);
 hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s);
 // multigrid form, after init: z = V-cycle(r), p = z
 hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s);
+// object as an interface: level set of level l (once), diagonal of level l
+hipError_t launch_field_psi(const FieldParams &p, int l, hipStream_t s);
+hipError_t launch_field_diag(const FieldParams &p, int l, hipStream_t s);
+hipError_t launch_surface_rho(const SurfParams &p, hipStream_t s);
 hipError_t launch_field_E(int repr, const FieldParams &p, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,

@@ -1518,19 +1518,58 @@ __device__ double sum_partials(const double *part, int G) {
   return block_sum(v);
 }
 
+// Density at a node: the deposit, plus the surface source when there is one
+// (fixed point; with the fixed-point deposit the two are added as integers).
 template <int D>
 __device__ __forceinline__ double f_rho(const FieldParams &P, int64_t q) {
+  const double h3 = P.h * P.h * P.h;
+  const int64_t surf = P.rho_surf ? P.rho_surf[q] : 0;
   if constexpr (D == PIC_DEP_FIXED64) {
-    return ((double)((const int64_t *)P.rho)[q] * 2.3283064365386963e-10) / (P.h * P.h * P.h);
-  } else if constexpr (D == PIC_DEP_ATOMIC_FP32) {
-    return (double)((const float *)P.rho)[q] / (P.h * P.h * P.h);
+    return ((double)(((const int64_t *)P.rho)[q] + surf) * 2.3283064365386963e-10) / h3;
   } else {
-    return ((const double *)P.rho)[q] / (P.h * P.h * P.h);
+    const double v = D == PIC_DEP_ATOMIC_FP32 ? (double)((const float *)P.rho)[q]
+                                              : ((const double *)P.rho)[q];
+    if (!P.rho_surf) return v / h3;
+    return v / h3 + ((double)surf * 2.3283064365386963e-10) / h3;
+  }
+}
+
+// Series permittivity of a link: a the level set at its lower-index node, b at
+// the other; the inside fraction by linear interpolation of the level set.
+__device__ __forceinline__ double f_eps(double a, double b, double ein, double eout) {
+  const bool ia = a < 0.0, ib = b < 0.0;
+  if (ia == ib) return ia ? ein : eout;
+  const double t = a / (a - b);
+  const double f = ia ? t : 1.0 - t;
+  return (ein * eout) / (f * eout + (1.0 - f) * ein);
+}
+
+template <class Gd>
+__device__ __forceinline__ double f_link_eps(const Gd &L, const FieldParams &P, int64_t q,
+                                             int64_t nb) {
+  return nb < q ? f_eps(L.psi[nb], L.psi[q], P.e_in, P.e_out)
+                : f_eps(L.psi[q], L.psi[nb], P.e_in, P.e_out);
+}
+
+// (A x) at an unknown node q of a grid (the fine grid or a level)
+template <bool IF, class Gd>
+__device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const double *x, int i,
+                                       int j, int k, int64_t q) {
+  const double xq = x[q];
+  double a = 0.0;
+  if constexpr (IF) {
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) {
+      a = a + (f_link_eps(L, P, q, nb) * w) * (xq - x[nb]);
+    });
+    return a * L.ih2;
+  } else {
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (xq - x[nb]); });
+    return L.s * a;
   }
 }
 
 // r = b - A x, z = r / diag, p = z; Dirichlet nodes get x = g (and r = z = p = 0).
-template <int D>
+template <int D, bool IF>
 __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
   double rz = 0.0, rr = 0.0, bb = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
@@ -1553,12 +1592,19 @@ __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
       f_ijk(P, nb, a, c, e);
       const bool nd = f_dir(P, a, c, e);
       const double xn = nd ? f_gval(P, a, c, e) : P.x[nb];
-      ax = ax + w * (xq - xn);
-      dsum = dsum + w;
-      if (nd) b = b + P.s * w * xn;
+      if constexpr (IF) {
+        const double cw = (f_link_eps(P, P, q, nb) * w) * P.ih2;
+        ax = ax + cw * (xq - xn);
+        dsum = dsum + cw;
+        if (nd) b = b + cw * xn;
+      } else {
+        ax = ax + w * (xq - xn);
+        dsum = dsum + w;
+        if (nd) b = b + P.s * w * xn;
+      }
     });
-    const double r = rho - P.s * ax;
-    const double z = r / (P.s * dsum);
+    const double r = IF ? rho - ax : rho - P.s * ax;
+    const double z = IF ? r / dsum : r / (P.s * dsum);
     P.r[q] = r;
     P.z[q] = z;
     P.p[q] = z;
@@ -1605,6 +1651,7 @@ __device__ __forceinline__ bool f_done(const FieldCtrl &c, const FieldParams &P)
 }
 
 // Ap = A p; partial p.Ap
+template <bool IF>
 __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   double pap = 0.0;
@@ -1614,9 +1661,7 @@ __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
     f_ijk(P, q, i, j, k);
     if (f_dir(P, i, j, k)) continue;
     const double pq = P.p[q];
-    double a = 0.0;
-    f_links(P, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (pq - P.p[nb]); });
-    const double ap = P.s * a;
+    const double ap = f_Ax<IF>(P, P, P.p, i, j, k, q);
     P.Ap[q] = ap;
     pap = pap + pq * ap;
   }
@@ -1626,7 +1671,7 @@ __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
 
 // x += alpha p, r -= alpha Ap; partial r.r (parity n); Jacobi form: also
 // z = r / diag and partial r.z
-template <bool J>
+template <bool J, bool IF>
 __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int o) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const int n = 1 - o;
@@ -1642,9 +1687,15 @@ __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int
     P.x[q] = x;
     P.r[q] = r;
     if constexpr (J) {
-      double dsum = 0.0;
-      f_links(P, i, j, k, q, [&](int64_t, double w) { dsum = dsum + w; });
-      const double z = r / (P.s * dsum);
+      double d;
+      if constexpr (IF) {
+        d = P.diag[q];
+      } else {
+        double dsum = 0.0;
+        f_links(P, i, j, k, q, [&](int64_t, double w) { dsum = dsum + w; });
+        d = P.s * dsum;
+      }
+      const double z = r / d;
       P.z[q] = z;
       rz = rz + r * z;
     }
@@ -1724,17 +1775,16 @@ __device__ __forceinline__ double f_dsum(const Gd &L, int i, int j, int k) {
          ((k > 0) + (k < L.n[2])) * (f_c(i, L.n[0]) * f_c(j, L.n[1]));
 }
 
-// A e at an unknown node of level L (e = 0 on its Dirichlet nodes)
-__device__ __forceinline__ double mg_Ae(const MgLevel &L, const double *e, int i, int j, int k,
-                                        int64_t q) {
-  const double eq = e[q];
-  double a = 0.0;
-  f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (eq - e[nb]); });
-  return L.s * a;
+// diagonal of A at an unknown node of a level
+template <bool IF>
+__device__ __forceinline__ double mg_D(const MgLevel &L, int i, int j, int k, int64_t q) {
+  if constexpr (IF) return L.diag[q];
+  else return L.s * f_dsum(L, i, j, k);
 }
 
 // e = two sweeps from zero: e1 = w b / d is pointwise, so the second sweep
 // computes e1 at the neighbours itself.
+template <bool IF>
 __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
@@ -1746,22 +1796,24 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
       L.e[q] = 0.0;
       continue;
     }
-    const double d = L.s * f_dsum(L, i, j, k);
+    const double d = mg_D<IF>(L, i, j, k, q);
     const double bq = L.rhs[q];
     const double e1 = kOmega * bq / d;
     double a = 0.0;
     f_links(L, i, j, k, q, [&](int64_t nb, double w) {
       int a2, b2, c2;
       f_ijk(L, nb, a2, b2, c2);
-      const double en =
-          f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / (L.s * f_dsum(L, a2, b2, c2));
-      a = a + w * (e1 - en);
+      const double en = f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<IF>(L, a2, b2, c2, nb);
+      if constexpr (IF) a = a + (f_link_eps(L, P, q, nb) * w) * (e1 - en);
+      else a = a + w * (e1 - en);
     });
-    L.e[q] = e1 + kOmega * (bq - L.s * a) / d;
+    const double Ae1 = IF ? a * L.ih2 : L.s * a;
+    L.e[q] = e1 + kOmega * (bq - Ae1) / d;
   }
 }
 
 // res = b - A e
+template <bool IF>
 __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
@@ -1769,7 +1821,7 @@ __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
        q += (int64_t)L.G * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
-    L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - mg_Ae(L, L.e, i, j, k, q);
+    L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - f_Ax<IF>(P, L, L.e, i, j, k, q);
   }
 }
 
@@ -1856,7 +1908,7 @@ __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l
 
 // One damped-Jacobi sweep out = in + w (b - A in) / d. On level 0 the second
 // post-sweep writes z itself and the partial r.z to part[prz].
-template <bool Dot>
+template <bool Dot, bool IF>
 __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, int to_e2, int prz) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
@@ -1872,7 +1924,7 @@ __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, 
       continue;
     }
     const double bq = L.rhs[q];
-    const double v = in[q] + kOmega * (bq - mg_Ae(L, in, i, j, k, q)) / (L.s * f_dsum(L, i, j, k));
+    const double v = in[q] + kOmega * (bq - f_Ax<IF>(P, L, in, i, j, k, q)) / mg_D<IF>(L, i, j, k, q);
     out[q] = v;
     if constexpr (Dot) rz = rz + bq * v;
   }
@@ -1880,6 +1932,98 @@ __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, 
     rz = block_sum(rz);
     if (threadIdx.x == 0) P.part[prz * P.G + blockIdx.x] = rz;
   }
+}
+
+// Level set of the object at the nodes of level l (< 0 inside; fine cell units).
+__global__ __launch_bounds__(kBlock) void field_psi_kernel(FieldParams P, int l) {
+  const MgLevel &L = P.lv[l];
+  const FieldGeom &o = P.geo;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    const double x = L.scale * i, y = L.scale * j, z = L.scale * k;
+    double v;
+    if (o.kind == PIC_OBJ_SPHERE) {
+      const double dx = x - o.c[0], dy = y - o.c[1], dz = z - o.c[2];
+      v = __builtin_sqrt(dx * dx + dy * dy + dz * dz) - o.r;
+    } else {
+      const double dx = x - o.c[0], dy = y - o.c[1];
+      const double r2 = dx * dx + dy * dy;
+      const double ground = r2 < o.a2 ? o.zc - __builtin_sqrt(o.rc2 - r2) : o.z_flat;
+      v = z - ground;
+    }
+    L.psi[q] = v;
+  }
+}
+
+// Diagonal of A at the nodes of level l: sum of the link coefficients.
+__global__ __launch_bounds__(kBlock) void field_diag_kernel(FieldParams P, int l) {
+  const MgLevel &L = P.lv[l];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    double d = 0.0;
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) { d = d + f_link_eps(L, P, q, nb) * w; });
+    L.diag[q] = d * L.ih2;
+  }
+}
+
+// The collected charge of each tally bin at the bin's surface point,
+// deposited to the nodes in int64 fixed point (trilinear weights, the
+// remainder on the last corner so that the bin's charge is kept exactly).
+__global__ __launch_bounds__(kBlock) void surface_rho_kernel(SurfParams S) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= S.nbins) return;
+  double Q = 0.0;
+  for (int s = 0; s < S.ns; ++s) Q = Q + S.chg[s] * (double)S.tally[b * S.ns + s];
+  if (Q == 0.0) return;
+  if (!(__builtin_fabs(Q) < 1073741824.0)) {
+    atomicOr(S.err, kErrSurface);
+    return;
+  }
+  const FieldGeom &o = S.geo;
+  double g[3];
+  if (o.kind == PIC_OBJ_CRATER) {
+    g[0] = (double)(b % S.n[0]) + 0.5;
+    g[1] = (double)(b / S.n[0]) + 0.5;
+    const double dx = g[0] - o.c[0], dy = g[1] - o.c[1];
+    const double r2 = dx * dx + dy * dy;
+    g[2] = r2 < o.a2 ? o.zc - __builtin_sqrt(o.rc2 - r2) : o.z_flat;
+  } else {
+    const int m = o.patches;
+    const int face = (int)(b / ((int64_t)m * m)), iv = (int)((b / m) % m), iu = (int)(b % m);
+    const int ax = face / 2;
+    const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+    double d[3];
+    d[ax] = (face & 1) ? 1.0 : -1.0;
+    d[u] = -1.0 + (2.0 * iu + 1.0) / m;
+    d[v] = -1.0 + (2.0 * iv + 1.0) / m;
+    const double len = __builtin_sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int k = 0; k < 3; ++k) g[k] = o.c[k] + o.rs * (d[k] / len);
+  }
+  int ci[3];
+  double f[3];
+  for (int k = 0; k < 3; ++k) {
+    double fl = __builtin_floor(g[k]);
+    fl = fl < 0.0 ? 0.0 : (fl > (double)(S.n[k] - 1) ? (double)(S.n[k] - 1) : fl);
+    ci[k] = (int)fl;
+    double of = g[k] - fl;
+    f[k] = of < 0.0 ? 0.0 : (of > 1.0 ? 1.0 : of);
+  }
+  double W[8];
+  weights(f, W);
+  long long C[8], sum = 0;
+  for (int n = 0; n < 7; ++n) {
+    C[n] = fixq(Q * W[n]);
+    sum += C[n];
+  }
+  C[7] = fixq(Q) - sum;
+  const int64_t base = ci[0] + S.sx * ci[1] + S.sy * ci[2];
+  const int64_t off[8] = {0, 1, S.sx, S.sx + 1, S.sy, S.sy + 1, S.sy + S.sx, S.sy + S.sx + 1};
+  for (int n = 0; n < 8; ++n)
+    atomicAdd((unsigned long long *)&S.rho_surf[base + off[n]], (unsigned long long)C[n]);
 }
 
 // multigrid start: p = z
@@ -2152,16 +2296,19 @@ hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s) {
+template <bool IF>
+static hipError_t field_init(int deposit, const FieldParams &p, hipStream_t s) {
   switch (deposit) {
     case PIC_DEP_FIXED64:
-      hipLaunchKernelGGL(field_init_kernel<PIC_DEP_FIXED64>, dim3(p.G), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_FIXED64, IF>), dim3(p.G), dim3(kBlock), 0, s, p);
       break;
     case PIC_DEP_ATOMIC_FP32:
-      hipLaunchKernelGGL(field_init_kernel<PIC_DEP_ATOMIC_FP32>, dim3(p.G), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP32, IF>), dim3(p.G), dim3(kBlock), 0, s,
+                         p);
       break;
     case PIC_DEP_ATOMIC_FP64:
-      hipLaunchKernelGGL(field_init_kernel<PIC_DEP_ATOMIC_FP64>, dim3(p.G), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP64, IF>), dim3(p.G), dim3(kBlock), 0, s,
+                         p);
       break;
     default:
       return hipErrorInvalidValue;
@@ -2170,43 +2317,74 @@ hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s) {
+  return p.iface ? field_init<true>(deposit, p, s) : field_init<false>(deposit, p, s);
+}
+
 // z = V-cycle(r); the partial r.z to part[prz]
+template <bool IF>
 static void field_vcycle(const FieldParams &p, int prz, hipStream_t s) {
   const int L = p.levels;
   for (int l = 0; l + 1 < L; ++l) {
-    hipLaunchKernelGGL(mg_pre_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
-    hipLaunchKernelGGL(mg_res_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL(mg_pre_kernel<IF>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL(mg_res_kernel<IF>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
     hipLaunchKernelGGL(mg_restrict_kernel, dim3(p.lv[l + 1].G), dim3(kBlock), 0, s, p, l);
   }
   const int gc = p.m > 0 ? (p.m + kBlock / 64 - 1) / (kBlock / 64) : 1;
   hipLaunchKernelGGL(mg_coarse_kernel, dim3(gc), dim3(kBlock), 0, s, p);
   for (int l = L - 2; l >= 0; --l) {
     hipLaunchKernelGGL(mg_prolong_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
-    hipLaunchKernelGGL(mg_sweep_kernel<false>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 1, 0);
+    hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 1,
+                       0);
     if (l == 0)
-      hipLaunchKernelGGL(mg_sweep_kernel<true>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0, prz);
+      hipLaunchKernelGGL((mg_sweep_kernel<true, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0,
+                         prz);
     else
-      hipLaunchKernelGGL(mg_sweep_kernel<false>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0, 0);
+      hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0,
+                         0);
   }
 }
 
 hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s) {
-  field_vcycle(p, 1, s);
+  if (p.iface) field_vcycle<true>(p, 1, s);
+  else field_vcycle<false>(p, 1, s);
   hipLaunchKernelGGL(field_pstart_kernel, dim3(p.G), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
-hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s) {
-  hipLaunchKernelGGL(field_apply_kernel, dim3(p.G), dim3(kBlock), 0, s, p);
+template <bool IF>
+static hipError_t field_iter(const FieldParams &p, int o, hipStream_t s) {
+  hipLaunchKernelGGL(field_apply_kernel<IF>, dim3(p.G), dim3(kBlock), 0, s, p);
   if (p.levels >= 2) {
-    hipLaunchKernelGGL(field_update_kernel<false>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+    hipLaunchKernelGGL((field_update_kernel<false, IF>), dim3(p.G), dim3(kBlock), 0, s, p, o);
     hipLaunchKernelGGL(field_check_kernel, dim3(1), dim3(kBlock), 0, s, p, o);
-    field_vcycle(p, 2 - o, s);  // parity n = 1 - o
+    field_vcycle<IF>(p, 2 - o, s);  // parity n = 1 - o
     hipLaunchKernelGGL(field_dir_kernel<false>, dim3(p.G), dim3(kBlock), 0, s, p, o);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(field_update_kernel<true>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+  hipLaunchKernelGGL((field_update_kernel<true, IF>), dim3(p.G), dim3(kBlock), 0, s, p, o);
   hipLaunchKernelGGL(field_dir_kernel<true>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s) {
+  return p.iface ? field_iter<true>(p, o, s) : field_iter<false>(p, o, s);
+}
+
+hipError_t launch_field_psi(const FieldParams &p, int l, hipStream_t s) {
+  hipLaunchKernelGGL(field_psi_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_diag(const FieldParams &p, int l, hipStream_t s) {
+  hipLaunchKernelGGL(field_diag_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_surface_rho(const SurfParams &p, hipStream_t s) {
+  if (p.nbins <= 0) return hipSuccess;
+  hipLaunchKernelGGL(surface_rho_kernel, dim3((unsigned)((p.nbins + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 

@@ -47,7 +47,8 @@ class _Config(ctypes.Structure):
 class _Field(ctypes.Structure):
     _fields_ = [("dirichlet", ctypes.c_int32), ("value", ctypes.c_double * 6),
                 ("eps", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("preconditioner", ctypes.c_int32)]
+                ("preconditioner", ctypes.c_int32), ("eps_object", ctypes.c_double),
+                ("surface_charge", ctypes.c_int32)]
 
 
 PRECONDITIONERS = {"multigrid": 0, "jacobi": 1}
@@ -346,12 +347,17 @@ class Context:
         self._check(lib().pic_set_injection(self._h, ctypes.byref(c)))
 
     def solve_field(self, dirichlet: int, values=None, eps: float = 1.0, tol: float = 1e-6,
-                    max_iter: int = 150, precond: str = "multigrid"):
+                    max_iter: int = 150, precond: str = "multigrid", eps_object: float = 0.0,
+                    surface_charge: bool = False):
         """Field solve for the last deposit (pic_solve_field); the node field
-        becomes -grad phi. Returns (iterations, relative residual)."""
+        becomes -grad phi. eps_object > 0 makes the object an interface with
+        that permittivity inside; surface_charge adds the collected charge as
+        its surface source. Returns (iterations, relative residual)."""
         f = _Field()
         f.dirichlet = int(dirichlet)
         f.preconditioner = PRECONDITIONERS[precond]
+        f.eps_object = float(eps_object)
+        f.surface_charge = 1 if surface_charge else 0
         for k in range(6):
             f.value[k] = float(values[k]) if values is not None else 0.0
         f.eps, f.tol, f.max_iter = float(eps), float(tol), int(max_iter)
