@@ -334,9 +334,17 @@ def main():
                     help="close the PIC loop: a field solve after every step (lunar: phi = 0 "
                          "at z+, zero-Neumann elsewhere; oml: phi = 0 at the max faces); "
                          "PCG tolerance 1e-6 and at most 150 iterations as in the paper")
-    ap.add_argument("--boundaries", default="open", choices=["open", "lunar"],
+    ap.add_argument("--eps-object", type=float, default=4.0,
+                    help="field modes: permittivity inside the object relative to the plasma "
+                         "(the paper's regolith and OML sphere: 4; 0: no interface)")
+    ap.add_argument("--no-surface-charge", action="store_true",
+                    help="field modes: leave the collected charge out of the field source")
+    ap.add_argument("--patches", type=int, default=8,
+                    help="sphere workloads: surface patches per cube-face edge (tally bins)")
+    ap.add_argument("--boundaries", default="open", choices=["open", "lunar", "oml"],
                     help="open: all faces remove; lunar: y- reflects and ambient plasma is "
-                         "injected at x-, x+, y+, z+ every step")
+                         "injected at x-, x+, y+, z+ every step; oml: the min faces reflect "
+                         "and the max faces inject")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy kernel (counter calibration)")
@@ -388,11 +396,13 @@ def main():
     # so that the events below bracket exactly the library's work
     stream = torch.cuda.Stream()
     cap = None
-    if args.boundaries == "lunar":
-        cap = [int(sp.count * 1.05) + 4096 for sp in w.species]
+    if args.boundaries != "open":  # injection: room for the population to fluctuate
+        cap = [int(sp.count * 1.1) + 4096 for sp in w.species]
     cfg = pam.config_from_workload(w, repr=args.repr, deposit=args.deposit,
                                    sort_interval=args.sort_interval, stream=stream.cuda_stream,
                                    capacity=cap)
+    if w.obj == "sphere" and args.field != "off":
+        cfg.patches = args.patches  # where the collected charge sits
     inj = None
     if args.boundaries == "lunar":
         # the lunar setup of §5.2.2: symmetry plane y-, ambient plasma injected
@@ -400,6 +410,13 @@ def main():
         cfg.reflect = 4
         above = w.nx * w.ny * (w.nz - w.z_flat) * w.h ** 3
         inj = dict(faces=1 | 2 | 8 | 32, seed=17, density=[sp.count / above for sp in w.species],
+                   vth=[sp.vth for sp in w.species], drift=[tuple(sp.drift) for sp in w.species])
+    elif args.boundaries == "oml":
+        # the OML setup of §3.1.3: the min faces are symmetry planes, the max
+        # faces inject the ambient plasma at the loaded density
+        cfg.reflect = 1 | 4 | 16
+        vol = w.nx * w.ny * w.nz * w.h ** 3
+        inj = dict(faces=2 | 8 | 32, seed=17, density=[sp.count / vol for sp in w.species],
                    vth=[sp.vth for sp in w.species], drift=[tuple(sp.drift) for sp in w.species])
     log(f"workload {w.name}: {w.nx}x{w.ny}x{w.nz} cells, {w.n_particles} particles, "
         f"{args.repr}/{args.deposit}, K={args.sort_interval}, boundaries {args.boundaries}")
@@ -421,6 +438,8 @@ def main():
     del E
 
     field_mask = {"off": 0, "lunar": 32, "oml": 2 | 8 | 32}[args.field]
+    surface = field_mask != 0 and not args.no_surface_charge and w.obj != "none"
+    field_kw = dict(eps_object=args.eps_object if w.obj != "none" else 0.0, surface_charge=surface)
 
     def advance(k):
         if not field_mask:
@@ -428,12 +447,12 @@ def main():
             return
         for _ in range(k):  # deposit -> field solve -> gather / push
             ctx.step(1)
-            ctx.solve_field(field_mask, tol=1e-6, max_iter=150)
+            ctx.solve_field(field_mask, tol=1e-6, max_iter=150, **field_kw)
 
     log(f"warmup {args.warmup} steps")
     if field_mask:
         ctx.step(0)
-        it, rr = ctx.solve_field(field_mask, tol=1e-6, max_iter=2000)
+        it, rr = ctx.solve_field(field_mask, tol=1e-6, max_iter=2000, **field_kw)
         log(f"initial field: {it} iterations, relative residual {rr:.2e}")
     advance(args.warmup)
     ctx.synchronize()
@@ -482,7 +501,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{w.name}: {w.nx}x{w.ny}x{w.nz} cells, {w.n_particles} particles "
-                        f"({len(w.species)} species), crater terrain, dt {w.dt}",
+                        f"({len(w.species)} species), "
+                        + ("crater terrain" if w.obj == "crater" else
+                           f"absorbing sphere radius {w.radius}" if w.obj == "sphere" else
+                           "no object") + f", dt {w.dt}",
             "repr": args.repr,
             "deposit": args.deposit + (" (int64 at 2^-32)" if args.deposit == "fixed64" else ""),
             "sort_interval": args.sort_interval,
@@ -516,15 +538,20 @@ def main():
         nodes = (w.nx + 1) * (w.ny + 1) * (w.nz + 1)
         iters = prof.field_iterations / max(1, prof.field_solves)
         out["config"]["field"] = (f"{args.field}: Dirichlet faces mask {field_mask}, PCG tol 1e-6, "
-                                  "max 150 iterations, warm start")
+                                  "max 150 iterations, warm start, multigrid preconditioner; "
+                                  f"object permittivity {field_kw['eps_object']} (0: none), "
+                                  f"surface charge {'on' if surface else 'off'}")
         out["field_solve"] = {
             "ms_per_solve": prof.field_ms / max(1, prof.field_solves),
             "iterations_per_solve": iters,
             "nodes": nodes,
         }
     if inj:
-        out["config"]["boundaries"] = ("lunar: y- reflects; ambient plasma injected at x-, x+, y+, "
-                                       "z+ (ghost slabs, drifting Maxwellian)")
+        out["config"]["boundaries"] = (
+            "lunar: y- reflects; ambient plasma injected at x-, x+, y+, z+ (ghost slabs, "
+            "drifting Maxwellian)" if args.boundaries == "lunar" else
+            "oml: x-, y-, z- reflect; ambient plasma injected at x+, y+, z+ (ghost slabs, "
+            "drifting Maxwellian)")
         out["injection"] = {
             "kernel_ms_avg": prof.inject_ms / max(1, prof.inject_launches),
             "injected_per_step": int((injected - injected0).sum()) / args.steps,
