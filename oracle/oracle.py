@@ -49,6 +49,8 @@ class _Cfg(ctypes.Structure):
         ("inj_density", ctypes.c_double * 4), ("inj_vth", ctypes.c_double * 4),
         ("inj_drift", ctypes.c_double * 12),
         ("sphere_patches", ctypes.c_int32),
+        ("pe_species", ctypes.c_int32), ("pe_seed", ctypes.c_uint64),
+        ("pe_sun", ctypes.c_double * 3), ("pe_flux", ctypes.c_double), ("pe_vth", ctypes.c_double),
     ]
 
 
@@ -115,6 +117,10 @@ def lib():
         L.orc_object_psi.restype = ctypes.c_double
         L.orc_object_psi.argtypes = [ctypes.POINTER(_FieldObj), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double]
+        L.orc_photo_column.restype = ctypes.c_int
+        L.orc_photo_column.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int64, ctypes.c_int64, _dp]
+        L.orc_photo_max_per_step.restype = ctypes.c_int64
+        L.orc_photo_max_per_step.argtypes = [ctypes.POINTER(_Cfg)]
         L.orc_surface_rho.restype = ctypes.c_int
         L.orc_surface_rho.argtypes = [ctypes.POINTER(_Cfg), _i64p, _i64p]
         L.orc_field_E.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_int32, _dp,
@@ -154,6 +160,12 @@ class Problem:
     inj_vth: list = None
     inj_drift: list = None     # per species, 3 components
     sphere_patches: int = 0    # sphere: 0 one bin, m > 0 6 m^2 surface patches
+    # photoemission from the crater terrain (pe_species -1: none)
+    pe_species: int = -1
+    pe_seed: int = 0
+    pe_sun: tuple = (1.0, 0.0, 1.0)
+    pe_flux: float = 0.0
+    pe_vth: float = 0.0
 
     @property
     def n_species(self):
@@ -189,6 +201,11 @@ class Problem:
         c.inj_faces = int(self.inj_faces)
         c.inj_seed = int(self.inj_seed) & (2 ** 64 - 1)
         c.sphere_patches = int(self.sphere_patches)
+        c.pe_species = int(self.pe_species)
+        c.pe_seed = int(self.pe_seed) & (2 ** 64 - 1)
+        c.pe_sun[:] = [float(a) for a in self.pe_sun]
+        c.pe_flux = float(self.pe_flux)
+        c.pe_vth = float(self.pe_vth)
         for s in range(self.n_species):
             c.inj_density[s] = self.inj_density[s] if self.inj_density else 0.0
             c.inj_vth[s] = self.inj_vth[s] if self.inj_vth else 0.0
@@ -197,10 +214,12 @@ class Problem:
         return c
 
     def injection_bound(self, nsteps: int) -> int:
-        """Most particles that nsteps of injection can add (each face cell gets
-        at most floor(n L) + 1 ghosts per step and species)."""
+        """Most particles that nsteps of injection and photoemission can add
+        (each face cell gets at most floor(n L) + 1 ghosts per step and
+        species, each lit column floor(mean) + 1 photoelectrons)."""
+        photo = int(lib().orc_photo_max_per_step(ctypes.byref(self.cstruct()))) * int(nsteps)
         if not self.inj_faces:
-            return 0
+            return photo
         n = (self.nx, self.ny, self.nz)
         tot = 0
         for s in range(self.n_species):
@@ -217,7 +236,7 @@ class Problem:
                 L = min(1.0, self.dt * (max(0.0, un) + 6.0 * vth))
                 cells = n[0] * n[1] * n[2] // n[ax]
                 tot += cells * (int(ncell * L) + 1)
-        return tot * int(nsteps)
+        return tot * int(nsteps) + photo
 
 
 class OracleError(RuntimeError):
@@ -391,6 +410,15 @@ def field_object_of(prob: "Problem", eps_in: float) -> FieldObject:
 def object_psi(obj: FieldObject, x, y, z) -> float:
     o = obj.cstruct()
     return float(lib().orc_object_psi(ctypes.byref(o), float(x), float(y), float(z)))
+
+
+def photo_column(prob: "Problem", i: int, j: int) -> dict:
+    """The terrain of column (i, j) as the photoemission sees it."""
+    out = np.zeros(7)
+    cfg = prob.cstruct()
+    if lib().orc_photo_column(ctypes.byref(cfg), int(i), int(j), out.ctypes.data_as(_dp)) != 0:
+        raise OracleError("no photoemission in this problem")
+    return dict(n=out[:3].copy(), ground=out[3], index=out[4], lit=bool(out[5]), mean=out[6])
 
 
 def surface_rho(prob: "Problem", tally) -> np.ndarray:

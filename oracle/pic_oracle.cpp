@@ -110,6 +110,11 @@ typedef struct {
   double inj_vth[kMaxSpecies];      // thermal speed per component
   double inj_drift[kMaxSpecies][3];
   int32_t sphere_patches;  // sphere: 0 one bin; m > 0: 6 m^2 surface patches
+  int32_t pe_species;      // crater: photoelectron species, -1 none
+  uint64_t pe_seed;
+  double pe_sun[3];        // direction towards the Sun (any length, z > 0)
+  double pe_flux;          // emitted particles per unit area and time at normal incidence
+  double pe_vth;           // thermal speed of the emitted half-Maxwellian
 } orc_config;
 
 typedef struct {
@@ -504,7 +509,125 @@ void inject_ghosts(const orc_config& cfg, const int32_t n[3], int32_t step, Emit
   }
 }
 
-// Mirror about a reflecting face; absolute positions (cell units).
+// ---- photoemission (the lunar setup of §5.2.2) -------------------------------
+//
+// Photoelectrons are generated at the sunlit terrain according to the local
+// sunlight index, the inner product of the unit direction to the Sun s and
+// the terrain's outward unit normal n, and not in shadow. The paper fixes no
+// more; this oracle takes: per surface column (i, j) and step, the terrain at
+// the column centre gives n, the ground height and I = s.n; the column is
+// lit if I > 0 and, in the bowl, the ray from that ground point towards the
+// Sun leaves the bowl sphere at or above the flat ground (a chord of length
+// 2 Rc I; outside the bowl nothing rises above the ground, so it is lit).
+// A lit column emits floor(mean + U) photoelectrons with
+// mean = (flux / w) h^2 dt I / n_z (the flux at normal incidence times the
+// cosine of incidence over the column's terrain area h^2 / n_z). Each starts
+// at a uniform point of the column's footprint on the ground, with a
+// half-Maxwellian velocity about n (vth (|z0| n + z1 t1 + z2 t2), t1 =
+// (n_z, 0, -n_x) normalised, t2 = n x t1), and moves a uniform fraction of dt
+// (g = fma(v, dt U, ground point)); then it is handled like an injected
+// particle (the box and terrain tests, appended after the ambient injection).
+// Random numbers: the injection's keys with face index 6 for the column:
+// draw 0 of ghost 0 for the count; draws 0, 1 (footprint), 2 (fraction) and
+// normals from draw 3 for ghost q >= 1.
+
+struct PhotoSetup {
+  bool on = false;
+  int s = 0;
+  uint64_t seed = 0;
+  double sun[3] = {0, 0, 0};
+  double rate = 0.0, vth = 0.0;  // rate = (flux / w) h^2 dt; vth in cell units
+  double cx = 0, cy = 0, zc = 0, rc = 0, rc2 = 0, a2 = 0, z_flat = 0;  // terrain, cell units
+};
+
+PhotoSetup photo_setup(const orc_config& c) {
+  PhotoSetup P;
+  if (c.obj_kind != OBJ_CRATER || c.pe_species < 0) return P;
+  P.on = true;
+  P.s = c.pe_species;
+  P.seed = c.pe_seed;
+  const double len =
+      std::sqrt(c.pe_sun[0] * c.pe_sun[0] + c.pe_sun[1] * c.pe_sun[1] + c.pe_sun[2] * c.pe_sun[2]);
+  for (int d = 0; d < 3; ++d) P.sun[d] = c.pe_sun[d] / len;
+  P.rate = (c.pe_flux / c.w[P.s]) * (c.h * c.h) * c.dt;
+  P.vth = c.pe_vth / c.h;
+  const double a = c.rim_radius / c.h, dep = c.depth / c.h;
+  P.rc = (a * a + dep * dep) / (2.0 * dep);
+  P.rc2 = P.rc * P.rc;
+  P.a2 = a * a;
+  P.z_flat = (c.z_flat - c.origin[2]) / c.h;
+  P.zc = P.z_flat - dep + P.rc;
+  P.cx = (c.center[0] - c.origin[0]) / c.h;
+  P.cy = (c.center[1] - c.origin[1]) / c.h;
+  return P;
+}
+
+double photo_ground(const PhotoSetup& P, double x, double y) {
+  const double dx = x - P.cx, dy = y - P.cy;
+  const double r2 = dx * dx + dy * dy;
+  return r2 < P.a2 ? P.zc - std::sqrt(P.rc2 - r2) : P.z_flat;
+}
+
+// Terrain at the centre of column (i, j): outward normal, ground height,
+// sunlight index and whether the column is lit.
+void photo_column(const PhotoSetup& P, int64_t i, int64_t j, double n[3], double* zg, double* I,
+                  bool* lit) {
+  const double dx = ((double)i + 0.5) - P.cx, dy = ((double)j + 0.5) - P.cy;
+  const double r2 = dx * dx + dy * dy;
+  const bool bowl = r2 < P.a2;
+  if (bowl) {
+    *zg = P.zc - std::sqrt(P.rc2 - r2);
+    n[0] = -dx / P.rc;
+    n[1] = -dy / P.rc;
+    n[2] = (P.zc - *zg) / P.rc;
+  } else {
+    *zg = P.z_flat;
+    n[0] = 0.0;
+    n[1] = 0.0;
+    n[2] = 1.0;
+  }
+  *I = (P.sun[0] * n[0] + P.sun[1] * n[1]) + P.sun[2] * n[2];
+  *lit = *I > 0.0 && (!bowl || *zg + (2.0 * P.rc * *I) * P.sun[2] >= P.z_flat);
+}
+
+// Visits every photoelectron of one step in column order: emit(s, g, v).
+template <class Emit>
+void photo_emit(const orc_config& cfg, const int32_t n[3], int32_t step, Emit emit) {
+  const PhotoSetup P = photo_setup(cfg);
+  if (!P.on) return;
+  for (int64_t col = 0; col < (int64_t)n[0] * n[1]; ++col) {
+    const int64_t i = col % n[0], j = col / n[0];
+    double nr[3], zg, I;
+    bool lit;
+    photo_column(P, i, j, nr, &zg, &I, &lit);
+    if (!lit) continue;
+    const double mean = (P.rate * I) / nr[2];
+    const int64_t k =
+        (int64_t)std::floor(mean + inj_uniform(inj_key(P.seed, step, P.s, 6, col, 0), 0));
+    const double l1 = std::sqrt(nr[2] * nr[2] + nr[0] * nr[0]);
+    const double t1[3] = {nr[2] / l1, 0.0, -nr[0] / l1};
+    const double t2[3] = {nr[1] * t1[2] - nr[2] * t1[1], nr[2] * t1[0] - nr[0] * t1[2],
+                          nr[0] * t1[1] - nr[1] * t1[0]};
+    for (int64_t q = 1; q <= k; ++q) {
+      const uint64_t key = inj_key(P.seed, step, P.s, 6, col, q);
+      const double x = (double)i + inj_uniform(key, 0), y = (double)j + inj_uniform(key, 1);
+      const double z0 = photo_ground(P, x, y);
+      const double tau = cfg.dt * inj_uniform(key, 2);
+      uint64_t d = 3;
+      double z[3];
+      normals3(key, &d, z);
+      const double a0 = std::fabs(z[0]);
+      double v[3], g[3];
+      for (int c = 0; c < 3; ++c) v[c] = P.vth * ((a0 * nr[c] + z[1] * t1[c]) + z[2] * t2[c]);
+      g[0] = std::fma(v[0], tau, x);
+      g[1] = std::fma(v[1], tau, y);
+      g[2] = std::fma(v[2], tau, z0);
+      emit(P.s, g, v);
+    }
+  }
+}
+
+// Mirror about a reflecting face; absolute positions (cell units).// Mirror about a reflecting face; absolute positions (cell units).
 template <class T>
 void reflect_abs(const orc_config& cfg, const int32_t n[3], T g[3], T u[3]) {
   for (int d = 0; d < 3; ++d) {
@@ -641,7 +764,7 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
 
   // an injected particle (cell units, FP64) in this form's arithmetic
   auto inject = [&](int32_t step) {
-    inject_ghosts(cfg, M.n, step, [&](int s, const double gd[3], const double vd[3]) {
+    const auto add = [&](int s, const double gd[3], const double vd[3]) {
       const T g[3] = {(T)gd[0], (T)gd[1], (T)gd[2]};
       if (box_face_abs(M, g, crater) >= 0) return;  // did not enter the box
       injected[s] += 1;
@@ -655,7 +778,9 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
       B.where.push_back(bin);
       B.when.push_back(bin >= 0 ? step : -1);
       if (bin >= 0) B.tally[(int64_t)bin * ns + s] += 1;
-    });
+    };
+    inject_ghosts(cfg, M.n, step, add);
+    photo_emit(cfg, M.n, step, add);
   };
 
   auto deposit_all = [&]() {
@@ -721,7 +846,7 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
         B.tally[(int64_t)bin * ns + s] += 1;
       }
     }
-    if (cfg.inj_faces) inject(step);
+    if (cfg.inj_faces || (crater && cfg.pe_species >= 0)) inject(step);
     deposit_all();
   }
   if (nsteps == 0) deposit_all();
@@ -817,7 +942,7 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
 
   // an injected particle (cell units, FP64) in the cell-relative form
   auto inject = [&](int32_t step) {
-    inject_ghosts(cfg, M.n, step, [&](int s, const double gd[3], const double vd[3]) {
+    const auto add = [&](int s, const double gd[3], const double vd[3]) {
       int32_t i[3];
       T o[3];
       for (int d = 0; d < 3; ++d) {
@@ -841,7 +966,9 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
       B.where.push_back(bin);
       B.when.push_back(bin >= 0 ? step : -1);
       if (bin >= 0) B.tally[(int64_t)bin * ns + s] += 1;
-    });
+    };
+    inject_ghosts(cfg, M.n, step, add);
+    photo_emit(cfg, M.n, step, add);
   };
 
   auto deposit_all = [&]() {
@@ -908,7 +1035,7 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
         B.tally[(int64_t)bin * ns + s] += 1;
       }
     }
-    if (cfg.inj_faces) inject(step);
+    if (cfg.inj_faces || (crater && cfg.pe_species >= 0)) inject(step);
     deposit_all();
   }
   if (nsteps == 0) deposit_all();
@@ -958,6 +1085,16 @@ bool valid(const orc_config& c, int64_t n, const int32_t* sp, const double* cons
   if (c.reflect & c.inj_faces) return false;             // a face reflects or injects
   if (c.obj_kind == OBJ_CRATER && ((c.reflect | c.inj_faces) & 16)) return false;  // terrain
   if (c.sphere_patches < 0 || c.sphere_patches > 64) return false;
+  if (c.pe_species < -1 || c.pe_species >= c.n_species) return false;
+  if (c.pe_species >= 0) {
+    if (c.obj_kind != OBJ_CRATER) return false;  // photoemission from the terrain
+    if (!(c.pe_flux >= 0) || !std::isfinite(c.pe_flux) || !(c.pe_vth >= 0) ||
+        !std::isfinite(c.pe_vth) || !(c.w[c.pe_species] > 0))
+      return false;
+    if (!std::isfinite(c.pe_sun[0]) || !std::isfinite(c.pe_sun[1]) || !(c.pe_sun[2] > 0) ||
+        !std::isfinite(c.pe_sun[2]))
+      return false;
+  }
   if (c.sphere_patches && c.obj_kind != OBJ_SPHERE) return false;
   for (int s = 0; s < c.n_species && c.inj_faces; ++s)
     if (!(c.inj_density[s] >= 0) || !(c.inj_vth[s] >= 0) || !std::isfinite(c.inj_drift[s][0]) ||
@@ -1597,6 +1734,39 @@ int orc_surface_rho(const orc_config* cfg, const int64_t* tally, int64_t* rho_fi
     for (int n = 0; n < 8; ++n) rho_fixed[idx[n]] += C[n];
   }
   return ORC_OK;
+}
+
+// Photoemission pieces for the pins: the terrain of column (i, j) as the
+// emission sees it: out = {n_x, n_y, n_z, ground, sunlight index, lit (1/0),
+// mean count per step}. Returns -1 without photoemission.
+int orc_photo_column(const orc_config* cfg, int64_t i, int64_t j, double out[7]) {
+  if (!cfg || !out) return ORC_E_INVALID;
+  const PhotoSetup P = photo_setup(*cfg);
+  if (!P.on) return ORC_E_INVALID;
+  double n[3], zg, I;
+  bool lit;
+  photo_column(P, i, j, n, &zg, &I, &lit);
+  for (int d = 0; d < 3; ++d) out[d] = n[d];
+  out[3] = zg;
+  out[4] = I;
+  out[5] = lit ? 1.0 : 0.0;
+  out[6] = lit ? (P.rate * I) / n[2] : 0.0;
+  return ORC_OK;
+}
+
+// Most photoelectrons one step can emit (each lit column: floor(mean) + 1).
+int64_t orc_photo_max_per_step(const orc_config* cfg) {
+  if (!cfg) return 0;
+  const PhotoSetup P = photo_setup(*cfg);
+  if (!P.on) return 0;
+  int64_t t = 0;
+  for (int64_t col = 0; col < (int64_t)cfg->nx * cfg->ny; ++col) {
+    double n[3], zg, I;
+    bool lit;
+    photo_column(P, col % cfg->nx, col / cfg->nx, n, &zg, &I, &lit);
+    if (lit) t += (int64_t)std::floor((P.rate * I) / n[2]) + 1;
+  }
+  return t;
 }
 
 // Object predicate at one point (physical units), in the arithmetic of `repr`.
