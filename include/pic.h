@@ -321,8 +321,46 @@ pic_status pic_get_field_levels(pic_ctx *ctx, int32_t *levels);
 pic_status pic_set_injection(pic_ctx *ctx, const pic_injection *inj);
 
 /* Synchronises; injected[s] (n_species values) receives the particles
- * injected into species s since pic_create (collected at once included). */
+ * injected into species s since pic_create (collected at once included;
+ * photoelectrons count as injected into their species). */
 pic_status pic_get_injected(pic_ctx *ctx, int64_t *injected);
+
+/* Photoemission from the sunlit terrain (the lunar setup of §5.2.2, where
+ * photoelectrons are generated according to the local sunlight index, the
+ * inner product of the direction to the Sun and the surface normal, and none
+ * in shadow). Each step, after the ambient injection and before the
+ * deposit, every surface column (i, j) of the crater terrain takes the
+ * terrain at its centre: outward unit normal n, ground height, index
+ * I = s.n (s = sun normalised). The column is lit if I > 0 and, inside the
+ * bowl, the ray from that ground point towards the Sun leaves the bowl sphere
+ * (a chord of length 2 Rc I) at or above the flat ground. A lit column emits
+ * floor(mean + U) photoelectrons of the given species, mean =
+ * (flux / weight) h^2 dt I / n_z (the emitted flux at normal incidence times
+ * the cosine of incidence over the column's terrain area h^2 / n_z). Each
+ * starts at a uniform point of the column's footprint on the ground with a
+ * half-Maxwellian velocity about n, vth (|z0| n + z1 t1 + z2 t2) with
+ * t1 = (n_z, 0, -n_x) normalised and t2 = n x t1, moves a uniform fraction of
+ * dt, and is then tested and appended like an injected particle. Random
+ * numbers: the counter-based SplitMix64 keys of the injection (seed, step,
+ * species, face index 6, column, photoelectron), so the emission is the same
+ * in any step split and on any device. */
+typedef struct {
+  int32_t species;  /* the photoelectron species (its q, m, weight from the config) */
+  uint64_t seed;
+  double sun[3];    /* direction towards the Sun, any length, sun[2] > 0 */
+  double flux;      /* emitted physical particles per unit area and time at normal
+                       incidence (>= 0) */
+  double vth;       /* thermal speed of the emitted half-Maxwellian (>= 0) */
+} pic_photoemission;
+
+/* Sets (pe non-NULL) or clears (NULL) the photoemission, from the next
+ * pic_step on (copied). PIC_E_INVALID: no crater terrain, species out of
+ * range or with weight <= 0, sun not finite or sun[2] <= 0, negative or
+ * non-finite flux or vth, more than 2^20 photoelectrons per column per step
+ * or speeds beyond 2^20 cells per step; nothing changes on error. The
+ * particles must fit the species' capacity (PIC_E_NOMEM at the next sync
+ * otherwise). Contexts with photoemission are not attached to a batch. */
+pic_status pic_set_photoemission(pic_ctx *ctx, const pic_photoemission *pe);
 
 /* Copies the alive particles of one species to host arrays of capacity cap
  * (physical positions and half-step velocities as doubles; ids nullable, and
@@ -359,6 +397,8 @@ typedef struct {
   int64_t field_solves;    /* pic_solve_field calls */
   double field_ms;         /* device time from the solve's first to last kernel */
   int64_t field_iterations; /* CG iterations, summed */
+  int64_t photo_launches;  /* photoemission launches (pic_set_photoemission) */
+  double photo_ms;
 } pic_profile;
 
 /* Enables (on != 0) or disables event timing and resets the totals. */

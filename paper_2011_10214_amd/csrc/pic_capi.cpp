@@ -214,6 +214,8 @@ struct pic_ctx {
   pic_profile acc{};
   pic_batch *batch = nullptr;  // attached to a batch
   bool inj_on = false;          // ambient particles are injected each step
+  bool pe_on = false;           // photoemission from the terrain each step
+  PhotoParams pe{};
   pic_injection inj{};
   int64_t step_index = 0;       // pic_step steps since creation (injection key)
   int64_t *injected = nullptr;  // device [ns]: particles injected
@@ -339,6 +341,9 @@ void prof_collect(pic_ctx *c) {
       } else if (e.kind == 4) {
         c->acc.field_solves++;
         c->acc.field_ms += ms;
+      } else if (e.kind == 5) {
+        c->acc.photo_launches++;
+        c->acc.photo_ms += ms;
       } else {
         c->acc.clear_launches++;
         c->acc.clear_ms += ms;
@@ -958,6 +963,13 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
       PIC_HIP(c, launch_inject(c->cfg.repr, c->cfg.deposit, I, c->stream));
       prof_end(c, pi);
     }
+    if (c->pe_on) {
+      InjParams I = inj_params(c, 1 - c->cur);
+      I.pe = c->pe;
+      const int pp = prof_begin(c, 5);
+      PIC_HIP(c, launch_photo(c->cfg.repr, c->cfg.deposit, I, c->stream));
+      prof_end(c, pp);
+    }
     PIC_HIP(c, hipMemcpyAsync((void *)c->flag_host, c->flags, sizeof(int32_t),
                               hipMemcpyDeviceToHost, c->stream));
     c->cur = 1 - c->cur;
@@ -1466,6 +1478,70 @@ pic_status pic_set_injection(pic_ctx *c, const pic_injection *inj) {
   return PIC_OK;
 }
 
+pic_status pic_set_photoemission(pic_ctx *c, const pic_photoemission *pe) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (!pe) {
+    c->pe_on = false;
+    return PIC_OK;
+  }
+  const pic_config &cfg = c->cfg;
+  if (cfg.object.kind != PIC_OBJ_CRATER)
+    return fail(c, PIC_E_INVALID, "photoemission needs the crater terrain");
+  if (pe->species < 0 || pe->species >= c->L.ns)
+    return fail(c, PIC_E_INVALID, "photoemission species out of range");
+  if (!(cfg.species[pe->species].weight > 0))
+    return fail(c, PIC_E_INVALID, "the photoelectron species needs a weight > 0");
+  if (!(pe->flux >= 0) || !is_finite(pe->flux) || !(pe->vth >= 0) || !is_finite(pe->vth))
+    return fail(c, PIC_E_INVALID, "flux and vth must be finite and >= 0");
+  for (int d = 0; d < 3; ++d)
+    if (!is_finite(pe->sun[d])) return fail(c, PIC_E_INVALID, "sun must be finite");
+  if (!(pe->sun[2] > 0)) return fail(c, PIC_E_INVALID, "the Sun must be above the ground (sun[2] > 0)");
+  if (!(cfg.dt * 13.0 * pe->vth / cfg.h <= 1048576.0))
+    return fail(c, PIC_E_INVALID, "photoelectron speeds move more than 2^20 cells per step");
+  PhotoParams P{};
+  P.s = pe->species;
+  P.seed = pe->seed;
+  const double len =
+      std::sqrt(pe->sun[0] * pe->sun[0] + pe->sun[1] * pe->sun[1] + pe->sun[2] * pe->sun[2]);
+  for (int d = 0; d < 3; ++d) P.sun[d] = pe->sun[d] / len;
+  P.rate = (pe->flux / cfg.species[pe->species].weight) * (cfg.h * cfg.h) * cfg.dt;
+  P.vth = pe->vth / cfg.h;
+  const double a = cfg.object.rim_radius / cfg.h, dep = cfg.object.depth / cfg.h;
+  P.rc = (a * a + dep * dep) / (2.0 * dep);
+  P.rc2 = P.rc * P.rc;
+  P.a2 = a * a;
+  P.z_flat = (cfg.object.z_flat - cfg.origin[2]) / cfg.h;
+  P.zc = P.z_flat - dep + P.rc;
+  P.cx = (cfg.object.center[0] - cfg.origin[0]) / cfg.h;
+  P.cy = (cfg.object.center[1] - cfg.origin[1]) / cfg.h;
+  // slots per column: floor of the largest mean + 1 (the kernel's formulas)
+  double most = 0.0;
+  for (int64_t j = 0; j < c->L.ny; ++j)
+    for (int64_t i = 0; i < c->L.nx; ++i) {
+      const double dx = ((double)i + 0.5) - P.cx, dy = ((double)j + 0.5) - P.cy;
+      const double r2 = dx * dx + dy * dy;
+      const bool bowl = r2 < P.a2;
+      double n[3] = {0.0, 0.0, 1.0}, zg = P.z_flat;
+      if (bowl) {
+        zg = P.zc - std::sqrt(P.rc2 - r2);
+        n[0] = -dx / P.rc;
+        n[1] = -dy / P.rc;
+        n[2] = (P.zc - zg) / P.rc;
+      }
+      const double I = (P.sun[0] * n[0] + P.sun[1] * n[1]) + P.sun[2] * n[2];
+      const bool lit = I > 0.0 && (!bowl || zg + (2.0 * P.rc * I) * P.sun[2] >= P.z_flat);
+      if (lit) most = std::max(most, (P.rate * I) / n[2]);
+    }
+  if (!(most <= 1048576.0))
+    return fail(c, PIC_E_INVALID, "more than 2^20 photoelectrons per column per step");
+  P.gmax = (int64_t)std::floor(most) + 1;
+  if ((int64_t)c->L.nx * c->L.ny * P.gmax > (int64_t(1) << 36))
+    return fail(c, PIC_E_INVALID, "photoemission: more than 2^36 slots per step");
+  c->pe = P;
+  c->pe_on = true;
+  return PIC_OK;
+}
+
 pic_status pic_get_injected(pic_ctx *c, int64_t *injected) {
   if (const pic_status s0 = check_ctx(c)) return s0;
   if (!injected) return fail(c, PIC_E_INVALID, "injected must not be NULL");
@@ -1853,7 +1929,8 @@ pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *s
   if (c->cfg.repr != b->cfg.repr || c->cfg.deposit != b->cfg.deposit)
     return bfail(b, PIC_E_INVALID, "repr / deposit differ from the batch's");
   if (!c->E_set) return bfail(b, PIC_E_STATE, "the context has no node field");
-  if (c->inj_on) return bfail(b, PIC_E_INVALID, "contexts that inject particles run alone (pic_step)");
+  if (c->inj_on || c->pe_on)
+    return bfail(b, PIC_E_INVALID, "contexts that inject particles run alone (pic_step)");
   int free_slot = -1;
   for (int k = 0; k < b->cfg.max_slots && free_slot < 0; ++k)
     if (!b->ctx[k]) free_slot = k;

@@ -146,6 +146,17 @@ struct LoadParams {
 // Injection of ambient particles through box faces (one thread per species,
 // face, face cell and ghost slot), after the step kernel: appended to the
 // arrival zones of the output buffer and deposited with global atomics.
+// Photoemission from the crater terrain (cell units).
+struct PhotoParams {
+  int32_t s;                    // photoelectron species
+  uint64_t seed;
+  double sun[3];                // unit vector towards the Sun
+  double rate;                  // (flux / w) h^2 dt: mean per column = rate I / n_z
+  double vth;
+  int64_t gmax;                 // slots per column: floor(largest mean) + 1
+  double cx, cy, zc, rc, rc2, a2, z_flat;  // terrain
+};
+
 struct InjParams {
   PBuf out[PIC_MAX_SPECIES];  // the buffer the step wrote
   Bins bins;
@@ -168,6 +179,7 @@ struct InjParams {
   int64_t *tally;
   int64_t *injected;          // [ns]
   int32_t *err;
+  PhotoParams pe;             // photoemission (photo_kernel)
 };
 
 // Field solve on the nodes: Jacobi-preconditioned CG for the node-centred
@@ -275,6 +287,7 @@ hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s);
 hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t s);
+hipError_t launch_photo(int repr, int deposit, const InjParams &p, hipStream_t s);
 // field solve: init (+ initial convergence check), one CG iteration (parity o:
 // the partials of the previous iteration), and E
 hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s);

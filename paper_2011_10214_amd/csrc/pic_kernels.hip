@@ -1266,77 +1266,27 @@ __global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32
 
 // ------------------------------------------------------------------ utility
 
-// Injection: one thread per (species, face, face cell, ghost slot); a face
-// cell has floor(mean) + 1 slots, of which the first floor(mean + U) hold a
-// ghost. A ghost is drawn, moved dt and, if it ends inside the box, rounded to
-// the representation, tested against the object (collected at once) or
-// appended to its tile's arrival zone in the output buffer and deposited.
+// The common end of injection and photoemission for one lane's particle
+// (has: the lane holds one; g, v in cell units, FP64): rounded to the
+// representation, the box and object tests of a pushed particle (collected at
+// once, or dropped if outside the box), appended to its tile's arrival zone
+// in the output buffer, deposited, counted. Every lane of the wave calls it.
 template <int R, int D>
-__global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
+__device__ __forceinline__ void emit_particle(const InjParams &P, bool has, int s, const double g[3],
+                                              const double v[3]) {
   using T = typename RealOf<R>::T;
   using A = typename AccOf<D>::type;
   constexpr bool kCell = R == PIC_REPR_FP32_CELL;
   constexpr bool kFixed = D == PIC_DEP_FIXED64;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nsf = P.ns * 6;
-  const bool active = tid < P.first[nsf];
-  int sf = 0;
-  while (active && P.first[sf + 1] <= tid) ++sf;
-  const int s = sf / 6, f = sf % 6;
-  const int64_t slot_id = tid - P.first[sf];
-  const int64_t gmax = P.gmax[s][f];
-  const int64_t cell = active ? slot_id / gmax : 0;
-  const int64_t j = active ? slot_id - cell * gmax + 1 : 0;  // ghost 1..gmax of the face cell
-  const int n[3] = {P.nx, P.ny, P.nz};
-  const int axis = f / 2;
-  const bool max_side = (f & 1) != 0;
-  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
-  const int64_t a = cell % n[t1], b = cell / n[t1];
-  const uint64_t ckey = inj_cell_key(P.seed, P.step, s, f, cell);
-  const int64_t k = active ? (int64_t)floor(P.mean[s][f] + inj_uniform(sm_mix(ckey ^ 0ull), 0)) : 0;
   const bool crater = P.geom.kind == PIC_OBJ_CRATER;
   const bool ids = (P.has_ids >> s) & 1;
   const int sx = P.nx + 1, sy = (P.nx + 1) * (P.ny + 1);
   const int lane = __lane_id();
-
-  // the ghost of this slot, if the face cell has one there
   bool inside = false, keep = false;
   Particle<T> pt;
   int ci[3] = {0, 0, 0};
   T fo[3] = {T(0), T(0), T(0)};
-  bool enters = false;
-  double g[3], v[3];
-  uint64_t key = 0, d = 3;
-  int attempts = 0;
-  double z1 = 0.0;
-  if (active && j <= k) {
-    // the normal component first: most ghosts do not reach the face, and
-    // the test of the normal axis alone (in the representation, as the box
-    // test makes it) rejects them before the tangential draws
-    key = sm_mix(ckey ^ (uint64_t)j);
-    const double depth = P.L[s][f] * (1.0 - inj_uniform(key, 2));
-    double z0;
-    normal_pair(key, &d, &attempts, &z0, &z1);
-    v[axis] = P.u[s][axis] + P.vth[s] * z0;
-    g[axis] = fma(v[axis], P.dt, max_side ? (double)n[axis] + depth : -depth);
-    if constexpr (kCell) {
-      int i = (int)floor(g[axis]);
-      const T o = (T)(g[axis] - (double)i);
-      if (o == T(1)) i += 1;
-      enters = i < n[axis] && (i >= 0 || (crater && axis == 2));
-    } else {
-      const T x = (T)g[axis];
-      enters = x < (T)n[axis] && (x >= T(0) || (crater && axis == 2));
-    }
-  }
-  if (enters) {
-    double z2, z3;
-    normal_pair(key, &d, &attempts, &z2, &z3);
-    (void)z3;
-    v[t1] = P.u[s][t1] + P.vth[s] * z1;
-    v[t2] = P.u[s][t2] + P.vth[s] * z2;
-    g[t1] = fma(v[t1], P.dt, (double)a + inj_uniform(key, 0));
-    g[t2] = fma(v[t2], P.dt, (double)b + inj_uniform(key, 1));
+  if (has) {
     // the representation of the injected particle, then the tests of a pushed one
     if constexpr (kCell) {
       for (int q = 0; q < 3; ++q) {
@@ -1440,6 +1390,142 @@ __global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
     for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
     if (c && lane == 0) atomicAdd((unsigned long long *)&P.injected[sp], c);
   }
+}
+
+
+// Injection: one thread per (species, face, face cell, ghost slot); a face
+// cell has floor(mean) + 1 slots, of which the first floor(mean + U) hold a
+// ghost. A ghost is drawn, moved dt and, if it ends inside the box, rounded to
+// the representation, tested against the object (collected at once) or
+// appended to its tile's arrival zone in the output buffer and deposited.
+template <int R, int D>
+__global__ __launch_bounds__(256) void inject_kernel(InjParams P) {
+  using T = typename RealOf<R>::T;
+  constexpr bool kCell = R == PIC_REPR_FP32_CELL;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nsf = P.ns * 6;
+  const bool active = tid < P.first[nsf];
+  int sf = 0;
+  while (active && P.first[sf + 1] <= tid) ++sf;
+  const int s = sf / 6, f = sf % 6;
+  const int64_t slot_id = tid - P.first[sf];
+  const int64_t gmax = P.gmax[s][f];
+  const int64_t cell = active ? slot_id / gmax : 0;
+  const int64_t j = active ? slot_id - cell * gmax + 1 : 0;  // ghost 1..gmax of the face cell
+  const int n[3] = {P.nx, P.ny, P.nz};
+  const int axis = f / 2;
+  const bool max_side = (f & 1) != 0;
+  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+  const int64_t a = cell % n[t1], b = cell / n[t1];
+  const uint64_t ckey = inj_cell_key(P.seed, P.step, s, f, cell);
+  const int64_t k = active ? (int64_t)floor(P.mean[s][f] + inj_uniform(sm_mix(ckey ^ 0ull), 0)) : 0;
+  const bool crater = P.geom.kind == PIC_OBJ_CRATER;
+
+  // the ghost of this slot, if the face cell has one there
+  bool enters = false;
+  double g[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+  uint64_t key = 0, d = 3;
+  int attempts = 0;
+  double z1 = 0.0;
+  if (active && j <= k) {
+    // the normal component first: most ghosts do not reach the face, and
+    // the test of the normal axis alone (in the representation, as the box
+    // test makes it) rejects them before the tangential draws
+    key = sm_mix(ckey ^ (uint64_t)j);
+    const double depth = P.L[s][f] * (1.0 - inj_uniform(key, 2));
+    double z0;
+    normal_pair(key, &d, &attempts, &z0, &z1);
+    v[axis] = P.u[s][axis] + P.vth[s] * z0;
+    g[axis] = fma(v[axis], P.dt, max_side ? (double)n[axis] + depth : -depth);
+    if constexpr (kCell) {
+      int i = (int)floor(g[axis]);
+      const T o = (T)(g[axis] - (double)i);
+      if (o == T(1)) i += 1;
+      enters = i < n[axis] && (i >= 0 || (crater && axis == 2));
+    } else {
+      const T x = (T)g[axis];
+      enters = x < (T)n[axis] && (x >= T(0) || (crater && axis == 2));
+    }
+  }
+  if (enters) {
+    double z2, z3;
+    normal_pair(key, &d, &attempts, &z2, &z3);
+    (void)z3;
+    v[t1] = P.u[s][t1] + P.vth[s] * z1;
+    v[t2] = P.u[s][t2] + P.vth[s] * z2;
+    g[t1] = fma(v[t1], P.dt, (double)a + inj_uniform(key, 0));
+    g[t2] = fma(v[t2], P.dt, (double)b + inj_uniform(key, 1));
+  }
+  emit_particle<R, D>(P, enters, s, g, v);
+}
+
+// Photoemission from the sunlit terrain: one thread per (surface column,
+// slot); a lit column has floor(mean) + 1 slots (the largest over the columns),
+// of which the first floor(mean + U) hold a photoelectron. The terrain at the
+// column centre gives the normal n, the sunlight index I = s.n and the
+// shadow (a bowl column is lit if the ray to the Sun leaves the bowl sphere,
+// a chord of 2 Rc I, at or above the flat ground); mean = rate I / n_z. A
+// photoelectron starts at a uniform point of the column's footprint on the
+// ground with vth (|z0| n + z1 t1 + z2 t2), t1 = (n_z, 0, -n_x) normalised,
+// t2 = n x t1, and moves a uniform fraction of dt; then it is handled like an
+// injected particle.
+template <int R, int D>
+__global__ __launch_bounds__(256) void photo_kernel(InjParams P) {
+  const PhotoParams &E = P.pe;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ncol = (int64_t)P.nx * P.ny;
+  const bool active = tid < ncol * E.gmax;
+  const int64_t col = active ? tid / E.gmax : 0;
+  const int64_t j = active ? tid - col * E.gmax + 1 : 0;  // photoelectron 1..gmax of the column
+  const int64_t ci = col % P.nx, cj = col / P.nx;
+  const int s = E.s;
+  // the terrain at the column centre
+  const double dx = ((double)ci + 0.5) - E.cx, dy = ((double)cj + 0.5) - E.cy;
+  const double r2 = dx * dx + dy * dy;
+  const bool bowl = r2 < E.a2;
+  double n[3], zg;
+  if (bowl) {
+    zg = E.zc - __builtin_sqrt(E.rc2 - r2);
+    n[0] = -dx / E.rc;
+    n[1] = -dy / E.rc;
+    n[2] = (E.zc - zg) / E.rc;
+  } else {
+    zg = E.z_flat;
+    n[0] = 0.0;
+    n[1] = 0.0;
+    n[2] = 1.0;
+  }
+  const double I = (E.sun[0] * n[0] + E.sun[1] * n[1]) + E.sun[2] * n[2];
+  const bool lit = I > 0.0 && (!bowl || zg + (2.0 * E.rc * I) * E.sun[2] >= E.z_flat);
+  const uint64_t ckey = inj_cell_key(E.seed, P.step, s, 6, col);
+  int64_t k = 0;
+  if (active && lit) k = (int64_t)floor((E.rate * I) / n[2] + inj_uniform(sm_mix(ckey ^ 0ull), 0));
+  const bool has = active && j <= k;
+  double g[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+  if (has) {
+    const uint64_t key = sm_mix(ckey ^ (uint64_t)j);
+    const double x = (double)ci + inj_uniform(key, 0), y = (double)cj + inj_uniform(key, 1);
+    const double ex = x - E.cx, ey = y - E.cy;
+    const double q2 = ex * ex + ey * ey;
+    const double z0g = q2 < E.a2 ? E.zc - __builtin_sqrt(E.rc2 - q2) : E.z_flat;
+    const double tau = P.dt * inj_uniform(key, 2);
+    uint64_t d = 3;
+    int attempts = 0;
+    double z0, z1, z2, z3;
+    normal_pair(key, &d, &attempts, &z0, &z1);
+    normal_pair(key, &d, &attempts, &z2, &z3);
+    (void)z3;
+    const double l1 = __builtin_sqrt(n[2] * n[2] + n[0] * n[0]);
+    const double t1[3] = {n[2] / l1, 0.0, -n[0] / l1};
+    const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2],
+                          n[0] * t1[1] - n[1] * t1[0]};
+    const double a0 = __builtin_fabs(z0);
+    for (int c = 0; c < 3; ++c) v[c] = E.vth * ((a0 * n[c] + z1 * t1[c]) + z2 * t2[c]);
+    g[0] = fma(v[0], tau, x);
+    g[1] = fma(v[1], tau, y);
+    g[2] = fma(v[2], tau, z0g);
+  }
+  emit_particle<R, D>(P, has, s, g, v);
 }
 
 // ------------------------------------------------------------------ field solve
@@ -2282,6 +2368,36 @@ hipError_t launch_inject_r(int deposit, const InjParams &p, dim3 grid, hipStream
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_photo_r(int deposit, const InjParams &p, dim3 grid, hipStream_t s) {
+  switch (deposit) {
+    case PIC_DEP_FIXED64:
+      hipLaunchKernelGGL((photo_kernel<R, PIC_DEP_FIXED64>), grid, dim3(256), 0, s, p);
+      break;
+    case PIC_DEP_ATOMIC_FP32:
+      hipLaunchKernelGGL((photo_kernel<R, PIC_DEP_ATOMIC_FP32>), grid, dim3(256), 0, s, p);
+      break;
+    case PIC_DEP_ATOMIC_FP64:
+      hipLaunchKernelGGL((photo_kernel<R, PIC_DEP_ATOMIC_FP64>), grid, dim3(256), 0, s, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_photo(int repr, int deposit, const InjParams &p, hipStream_t s) {
+  const int64_t total = (int64_t)p.nx * p.ny * p.pe.gmax;
+  if (total <= 0) return hipSuccess;
+  const dim3 grid(grid_for(total, 256));
+  switch (repr) {
+    case PIC_REPR_FP64: return launch_photo_r<PIC_REPR_FP64>(deposit, p, grid, s);
+    case PIC_REPR_FP32_ABS: return launch_photo_r<PIC_REPR_FP32_ABS>(deposit, p, grid, s);
+    case PIC_REPR_FP32_CELL: return launch_photo_r<PIC_REPR_FP32_CELL>(deposit, p, grid, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t s) {

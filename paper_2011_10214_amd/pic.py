@@ -60,6 +60,11 @@ class _Injection(ctypes.Structure):
                 ("drift", ctypes.c_double * (3 * MAX_SPECIES))]
 
 
+class _Photo(ctypes.Structure):
+    _fields_ = [("species", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("sun", ctypes.c_double * 3), ("flux", ctypes.c_double), ("vth", ctypes.c_double)]
+
+
 class _BatchConfig(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("repr", ctypes.c_int32),
                 ("deposit", ctypes.c_int32), ("steps_per_run", ctypes.c_int32),
@@ -73,7 +78,8 @@ class _Profile(ctypes.Structure):
                 ("clear_launches", ctypes.c_int64), ("clear_ms", ctypes.c_double),
                 ("particle_steps", ctypes.c_int64), ("inject_launches", ctypes.c_int64),
                 ("inject_ms", ctypes.c_double), ("field_solves", ctypes.c_int64),
-                ("field_ms", ctypes.c_double), ("field_iterations", ctypes.c_int64)]
+                ("field_ms", ctypes.c_double), ("field_iterations", ctypes.c_int64),
+                ("photo_launches", ctypes.c_int64), ("photo_ms", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p
@@ -97,6 +103,7 @@ SIGNATURES = {
     "pic_get_field_levels": (_st, [_vp, ctypes.POINTER(_i32)]),
     "pic_get_node_E": (_st, [_vp, _vp, _vp, _vp]),
     "pic_get_injected": (_st, [_vp, _vp]),
+    "pic_set_photoemission": (_st, [_vp, ctypes.POINTER(_Photo)]),
     "pic_synchronize": (_st, [_vp]),
     "pic_get_rho": (_st, [_vp, _vp, _vp]),
     "pic_num_bins": (_i64, [_vp]),
@@ -248,6 +255,8 @@ class Profile:
     field_solves: int = 0
     field_ms: float = 0.0
     field_iterations: int = 0
+    photo_launches: int = 0
+    photo_ms: float = 0.0
 
 
 class Context:
@@ -345,6 +354,23 @@ class Context:
             for d in range(3):
                 c.drift[3 * s + d] = float(drift[s][d]) if drift is not None else 0.0
         self._check(lib().pic_set_injection(self._h, ctypes.byref(c)))
+
+    def set_photoemission(self, species: int = None, seed: int = 0, sun=(1.0, 0.0, 1.0),
+                          flux: float = 0.0, vth: float = 0.0):
+        """Photoemission of the species from the sunlit crater terrain each step
+        (``species`` None turns it off); sun: direction towards the Sun; flux:
+        emitted physical particles per unit area and time at normal incidence;
+        vth: thermal speed of the emitted half-Maxwellian."""
+        if species is None:
+            self._check(lib().pic_set_photoemission(self._h, None))
+            return
+        c = _Photo()
+        c.species = int(species)
+        c.seed = int(seed) & (2 ** 64 - 1)
+        c.sun[:] = [float(a) for a in sun]
+        c.flux = float(flux)
+        c.vth = float(vth)
+        self._check(lib().pic_set_photoemission(self._h, ctypes.byref(c)))
 
     def solve_field(self, dirichlet: int, values=None, eps: float = 1.0, tol: float = 1e-6,
                     max_iter: int = 150, precond: str = "multigrid", eps_object: float = 0.0,
@@ -460,7 +486,8 @@ class Context:
         self._check(lib().pic_profile_read(self._h, ctypes.byref(p)))
         return Profile(p.step_launches, p.step_ms, p.sort_launches, p.sort_ms, p.clear_launches,
                        p.clear_ms, p.particle_steps, p.inject_launches, p.inject_ms,
-                       p.field_solves, p.field_ms, p.field_iterations)
+                       p.field_solves, p.field_ms, p.field_iterations, p.photo_launches,
+                       p.photo_ms)
 
 
 def footprint_bytes(cfg: Config) -> int:
