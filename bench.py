@@ -16,10 +16,12 @@ Prints one JSON line (the last line of stdout). Progress goes to stderr.
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
 import sys
 import time
+from dataclasses import replace
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -114,6 +116,8 @@ def cpu_baseline(w, target_s):
     per = 1 << 19
     sp, xs, vs = [], [], []
     for s in range(len(w.species)):
+        if w.species[s].count == 0:
+            continue
         a = synth.particles(w, s, 0, per)
         sp.append(np.full(per, s, np.int32))
         xs.append(np.stack(a[:3], 1).astype(np.float64))
@@ -345,6 +349,11 @@ def main():
                     help="open: all faces remove; lunar: y- reflects and ambient plasma is "
                          "injected at x-, x+, y+, z+ every step; oml: the min faces reflect "
                          "and the max faces inject")
+    ap.add_argument("--photoemission", action="store_true",
+                    help="with --boundaries lunar: a photoelectron species emitted from the "
+                         "sunlit terrain (Sun 10 degrees above the ground in the X-Z plane; "
+                         "density and thermal speed relative to the solar-wind electrons as "
+                         "in the paper's table of plasma parameters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy kernel (counter calibration)")
@@ -392,12 +401,33 @@ def main():
         return
     torch.cuda.set_device(0)
     w = synth.WORKLOADS[args.workload]()
+    photo = None
+    if args.photoemission:
+        if args.boundaries != "lunar" or w.obj != "crater":
+            log("--photoemission needs --boundaries lunar on a crater workload")
+            sys.exit(2)
+        # photoelectrons at 90 degrees Sun: n_pe / n_sw = 64 / 8.7 and
+        # vth_pe / vth_e = 622 / 1453 (the paper's plasma parameters); the
+        # emitted half-Maxwellian of surface density n_pe carries the flux
+        # n_pe vth_pe sqrt(2 / pi) at normal incidence
+        e = w.species[0]
+        above = w.nx * w.ny * (w.nz - w.z_flat) * w.h ** 3
+        vth_pe = e.vth * 622.0 / 1453.0
+        flux = (64.0 / 8.7) * (e.count / above) * vth_pe * math.sqrt(2.0 / math.pi)
+        elev = math.radians(10.0)
+        photo = dict(seed=23, sun=(math.cos(elev), 0.0, math.sin(elev)), flux=flux, vth=vth_pe)
+        w = replace(w, species=list(w.species) + [synth.SpeciesSpec(
+            "photoelectron", q=-1.0, m=e.m, vth=vth_pe, count=0, w=e.w)])
     # a stream of torch's own (default priority) that the library enqueues on,
     # so that the events below bracket exactly the library's work
     stream = torch.cuda.Stream()
     cap = None
     if args.boundaries != "open":  # injection: room for the population to fluctuate
         cap = [int(sp.count * 1.1) + 4096 for sp in w.species]
+    if photo:  # the photoelectrons of every step stay near the ground; the tile
+        # regions keep room for some 20 more steps of them between re-plannings
+        per_step = photo["flux"] * math.sin(math.radians(10.0)) * w.nx * w.ny * w.dt
+        cap[-1] = int(per_step * (args.warmup + args.steps + 2 + 24) * 1.2) + 65536
     cfg = pam.config_from_workload(w, repr=args.repr, deposit=args.deposit,
                                    sort_interval=args.sort_interval, stream=stream.cuda_stream,
                                    capacity=cap)
@@ -421,8 +451,10 @@ def main():
     log(f"workload {w.name}: {w.nx}x{w.ny}x{w.nz} cells, {w.n_particles} particles, "
         f"{args.repr}/{args.deposit}, K={args.sort_interval}, boundaries {args.boundaries}")
     ctx = pam.Context(cfg)
-    if inj:
+    if inj:  # (a photoelectron species has no loaded particles: density 0, not injected)
         ctx.set_injection(**inj)
+    if photo:
+        ctx.set_photoemission(len(w.species) - 1, **photo)
     t0 = time.perf_counter()
     for s in range(len(w.species)):
         cols = synth.particles(w, s)
@@ -531,6 +563,7 @@ def main():
             "sort": prof.sort_ms / args.steps,
             "rho_clear": prof.clear_ms / args.steps,
             "injection": prof.inject_ms / args.steps,
+            "photoemission": prof.photo_ms / args.steps,
             "field_solve": prof.field_ms / args.steps,
         },
     }
@@ -552,10 +585,21 @@ def main():
             "drifting Maxwellian)" if args.boundaries == "lunar" else
             "oml: x-, y-, z- reflect; ambient plasma injected at x+, y+, z+ (ghost slabs, "
             "drifting Maxwellian)")
+        ambient = slice(0, len(w.species) - 1) if photo else slice(None)
         out["injection"] = {
             "kernel_ms_avg": prof.inject_ms / max(1, prof.inject_launches),
-            "injected_per_step": int((injected - injected0).sum()) / args.steps,
+            "injected_per_step": int((injected - injected0)[ambient].sum()) / args.steps,
             "share_of_step": prof.inject_ms / ms if ms > 0 else None,
+        }
+    if photo:
+        out["config"]["photoemission"] = (
+            "photoelectrons from the sunlit terrain: Sun 10 degrees above the ground in the X-Z "
+            f"plane, flux {photo['flux']:.4g} per unit area and time at normal incidence, "
+            f"vth {photo['vth']:.4g}")
+        out["photoemission"] = {
+            "kernel_ms_avg": prof.photo_ms / max(1, prof.photo_launches),
+            "emitted_per_step": int((injected - injected0)[-1]) / args.steps,
+            "share_of_step": prof.photo_ms / ms if ms > 0 else None,
         }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -359,7 +359,11 @@ typedef struct {
  * non-finite flux or vth, more than 2^20 photoelectrons per column per step
  * or speeds beyond 2^20 cells per step; nothing changes on error. The
  * particles must fit the species' capacity (PIC_E_NOMEM at the next sync
- * otherwise). Contexts with photoemission are not attached to a batch. */
+ * otherwise); when the capacity also leaves room for some 20 steps of
+ * emission, the tile regions keep room for 16 steps of it in the tiles the
+ * photoelectrons start in, so that a growing population does not re-plan
+ * the regions every step. Contexts with photoemission are not attached to a
+ * batch. */
 pic_status pic_set_photoemission(pic_ctx *ctx, const pic_photoemission *pe);
 
 /* Copies the alive particles of one species to host arrays of capacity cap

@@ -216,6 +216,7 @@ struct pic_ctx {
   bool inj_on = false;          // ambient particles are injected each step
   bool pe_on = false;           // photoemission from the terrain each step
   PhotoParams pe{};
+  int32_t *inflow = nullptr;    // device [ns][ntiles]: photoemission room per re-bucketing
   pic_injection inj{};
   int64_t step_index = 0;       // pic_step steps since creation (injection key)
   int64_t *injected = nullptr;  // device [ns]: particles injected
@@ -515,6 +516,7 @@ pic_status do_sort(pic_ctx *c) {
     S.region_cap[s] = sp.ovf_base;
   }
   S.bins = bins_of(c);
+  S.inflow = c->pe_on ? c->inflow : nullptr;
   S.dst_lay = c->lay[1 - c->li];
   S.cur = c->cur;
   S.count = c->count;
@@ -1514,7 +1516,10 @@ pic_status pic_set_photoemission(pic_ctx *c, const pic_photoemission *pe) {
   P.zc = P.z_flat - dep + P.rc;
   P.cx = (cfg.object.center[0] - cfg.origin[0]) / cfg.h;
   P.cy = (cfg.object.center[1] - cfg.origin[1]) / cfg.h;
-  // slots per column: floor of the largest mean + 1 (the kernel's formulas)
+  // slots per column: floor of the largest mean + 1 (the kernel's formulas);
+  // the tiles the photoelectrons start in get room for several steps of them
+  const Dims &D = c->L;
+  std::vector<int32_t> inflow((size_t)D.ns * D.ntiles, 0);
   double most = 0.0;
   for (int64_t j = 0; j < c->L.ny; ++j)
     for (int64_t i = 0; i < c->L.nx; ++i) {
@@ -1530,13 +1535,28 @@ pic_status pic_set_photoemission(pic_ctx *c, const pic_photoemission *pe) {
       }
       const double I = (P.sun[0] * n[0] + P.sun[1] * n[1]) + P.sun[2] * n[2];
       const bool lit = I > 0.0 && (!bowl || zg + (2.0 * P.rc * I) * P.sun[2] >= P.z_flat);
-      if (lit) most = std::max(most, (P.rate * I) / n[2]);
+      if (!lit) continue;
+      const double mean = (P.rate * I) / n[2];
+      most = std::max(most, mean);
+      if (!(mean <= 1048576.0)) continue;
+      const int64_t kz = std::min<int64_t>(std::max<int64_t>((int64_t)std::floor(zg), 0), D.nz - 1);
+      const int64_t t = (i / kTile) + D.ntx * ((j / kTile) + D.nty * (kz / kTile));
+      int32_t &v = inflow[(size_t)pe->species * D.ntiles + t];
+      v = (int32_t)std::min<int64_t>((int64_t)v + (int64_t)std::floor(mean) + 1, 1 << 20);
     }
   if (!(most <= 1048576.0))
     return fail(c, PIC_E_INVALID, "more than 2^20 photoelectrons per column per step");
   P.gmax = (int64_t)std::floor(most) + 1;
   if ((int64_t)c->L.nx * c->L.ny * P.gmax > (int64_t(1) << 36))
     return fail(c, PIC_E_INVALID, "photoemission: more than 2^36 slots per step");
+  if (!c->inflow) {
+    void *q = nullptr;
+    if (dmalloc(c, &q, (int64_t)inflow.size() * 4) != hipSuccess)
+      return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+    c->inflow = (int32_t *)q;
+  }
+  PIC_HIP(c, hipStreamSynchronize(c->stream));  // no re-bucketing reads the old map
+  PIC_HIP(c, hipMemcpy(c->inflow, inflow.data(), inflow.size() * 4, hipMemcpyHostToDevice));
   c->pe = P;
   c->pe_on = true;
   return PIC_OK;

@@ -62,7 +62,8 @@ struct Bins {
 };
 
 // Tile capacities after a re-bucketing of cnt particles: a stay zone with
-// 1/16 spare and an arrival zone of 1/8 (+ constants for sparse tiles).
+// 1/16 spare and an arrival zone of 1/8 (+ constants for sparse tiles); the
+// re-bucketing adds room for growth (sort_scan_kernel) when it fits.
 __host__ __device__ inline int32_t stay_zone(int32_t cnt) { return cnt + cnt / 16 + 32; }
 __host__ __device__ inline int32_t arrival_zone(int32_t cnt) { return cnt / 8 + 64; }
 // Slots of one buffer for n particles over nt tiles (tile regions + overflow).
@@ -129,7 +130,25 @@ struct SortParams {
   int32_t ntx, nty, ntz, ntiles;
   int32_t has_ids;          // bit s: species s carries ids
   int32_t *err;
+  // [ns][ntiles] or null: particles that a source (photoemission) may add to
+  // a tile in one step; the plan gives the tile's stay zone kInflowSteps
+  // steps of it (the added particles stay) and its arrival zone two, when
+  // that fits the buffer
+  const int32_t *inflow;
 };
+
+// Steps of a source's inflow that a re-bucketing leaves room for.
+constexpr int32_t kInflowSteps = 16;
+__host__ __device__ inline int64_t inflow_room(int32_t per_step) {
+  return (int64_t)per_step * (kInflowSteps + 2);
+}
+// Room for a tile that wanted a arrivals in the last step (a count of all
+// attempts, overflowed ones included): its stay zone one more step of them
+// (they stay), its arrival zone twice as many, beyond the zones of its count.
+__host__ __device__ inline int64_t demand_room(int32_t cnt, int32_t a) {
+  const int64_t az = arrival_zone(cnt);
+  return (int64_t)a + (2 * (int64_t)a > az ? 2 * (int64_t)a - az : 0);
+}
 
 struct LoadParams {
   const float *x[3];

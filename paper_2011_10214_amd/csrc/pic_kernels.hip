@@ -1127,11 +1127,25 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
   const int per = (nt + 1023) / 1024;
   const int b = threadIdx.x * per;
   const int e = b + per < nt ? b + per : nt;
-  long long local = 0;
+  const bool flat = (P.unsorted >> s) & 1;
+  long long local = 0, extra = 0;
   for (int i = b; i < e; ++i) {
-    const int32_t c = P.count[s * nt + i];
+    const int64_t j = (int64_t)s * nt + i;
+    const int32_t c = P.count[j];
     local += stay_zone(c) + arrival_zone(c);
+    if (P.inflow) extra += inflow_room(P.inflow[j]);
+    if (!flat) extra += demand_room(c, P.bins.arr[P.cur][j]);
   }
+  // the allowances for growth only if the regions with them fit the buffer
+  sS[threadIdx.x] = local + extra;
+  __syncthreads();
+  for (int o = 512; o >= 1; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) sS[threadIdx.x] += sS[threadIdx.x + o];
+    __syncthreads();
+  }
+  const bool use = sS[0] <= P.region_cap[s];
+  __syncthreads();
+  if (use) local += extra;
   sS[threadIdx.x] = local;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -1141,14 +1155,18 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
     __syncthreads();
   }
   long long run = sS[threadIdx.x] - local;
-  const bool flat = (P.unsorted >> s) & 1;
   for (int i = b; i < e; ++i) {
     const int64_t j = (int64_t)s * nt + i;
     // a freshly loaded species has no valid counters in the source buffer
     // either (the scatter clears them for binned species after reading)
+    const int32_t a = flat ? 0 : P.bins.arr[P.cur][j];  // arrivals wanted in the last step
     if (flat) P.bins.arr[P.cur][j] = 0;
     const int32_t c = P.count[j];
-    const int32_t sz = stay_zone(c), cap = sz + arrival_zone(c);
+    const int32_t in = use && P.inflow ? P.inflow[j] : 0;
+    const int32_t ga = use ? a : 0;
+    const int32_t sz = stay_zone(c) + kInflowSteps * in + ga;
+    const int32_t az = arrival_zone(c) > 2 * ga ? arrival_zone(c) : 2 * ga;
+    const int32_t cap = sz + az + 2 * in;
     P.dst_lay.base[j] = run;
     P.dst_lay.cap[j] = cap;
     P.dst_lay.sz[j] = sz;
