@@ -1,0 +1,747 @@
+// HIP kernels of the field solve on the PIC mesh for gfx950 (the boundary
+// value problem of §2.1 by node-centred finite volumes, preconditioned
+// conjugate gradients with a geometric multigrid V-cycle or Jacobi, the object
+// as an interface with the collected charge as its surface source, eq.
+// (2.2)-(2.5)), and E = -grad phi into the node field.
+#include "pic_device.h"
+
+namespace pic {
+namespace {
+
+// ------------------------------------------------------------------ field solve
+//
+// -div(eps grad phi) = rho on the nodes (node-centred finite volumes: the flux
+// through the dual face of a link is eps w (phi_p - phi_q) h with w the
+// product of the two tangential half-width factors, 1/2 at a boundary index),
+// Dirichlet faces in a mask, zero-Neumann elsewhere; Jacobi-preconditioned
+// conjugate gradients. Every kernel runs G workgroups over the nodes; sums
+// are per-workgroup partials that every consumer adds in the same fixed
+// order, so the solve is deterministic.
+
+// The grid helpers take the fine grid (FieldParams) or a multigrid level
+// (MgLevel): both carry n, sx, sy and mask.
+template <class Gd>
+__device__ __forceinline__ bool f_dir(const Gd &P, int i, int j, int k) {
+  const int m = P.mask;
+  return ((m & 1) && i == 0) || ((m & 2) && i == P.n[0]) || ((m & 4) && j == 0) ||
+         ((m & 8) && j == P.n[1]) || ((m & 16) && k == 0) || ((m & 32) && k == P.n[2]);
+}
+
+// Dirichlet value of a node: the first Dirichlet face (in face order) it lies on
+__device__ __forceinline__ double f_gval(const FieldParams &P, int i, int j, int k) {
+  const int m = P.mask;
+  if ((m & 1) && i == 0) return P.g[0];
+  if ((m & 2) && i == P.n[0]) return P.g[1];
+  if ((m & 4) && j == 0) return P.g[2];
+  if ((m & 8) && j == P.n[1]) return P.g[3];
+  if ((m & 16) && k == 0) return P.g[4];
+  return P.g[5];
+}
+
+__device__ __forceinline__ double f_c(int a, int n) { return (a == 0 || a == n) ? 0.5 : 1.0; }
+
+// node index -> (i, j, k); node counts stay below 2^31 (1024^3 cells at most)
+template <class Gd>
+__device__ __forceinline__ void f_ijk(const Gd &P, int64_t q, int &i, int &j, int &k) {
+  const uint32_t u = (uint32_t)q, sy = (uint32_t)P.sy, sx = (uint32_t)P.sx;
+  const uint32_t kk = u / sy, rem = u - kk * sy, jj = rem / sx;
+  k = (int)kk;
+  j = (int)jj;
+  i = (int)(rem - jj * sx);
+}
+
+// Visits the links of node (i, j, k) in the order -x, +x, -y, +y, -z, +z:
+// f(q, w) with q the neighbour's node index.
+template <class Gd, class F>
+__device__ __forceinline__ void f_links(const Gd &P, int i, int j, int k, int64_t q0, F f) {
+  const double cx = f_c(i, P.n[0]), cy = f_c(j, P.n[1]), cz = f_c(k, P.n[2]);
+  if (i > 0) f(q0 - 1, cy * cz);
+  if (i < P.n[0]) f(q0 + 1, cy * cz);
+  if (j > 0) f(q0 - P.sx, cx * cz);
+  if (j < P.n[1]) f(q0 + P.sx, cx * cz);
+  if (k > 0) f(q0 - P.sy, cx * cy);
+  if (k < P.n[2]) f(q0 + P.sy, cx * cy);
+}
+
+// Sum over the workgroup (fixed tree order); the result in every thread.
+__device__ double block_sum(double v) {
+  __shared__ double sRed[kBlock];
+  sRed[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kBlock / 2; o >= 1; o >>= 1) {
+    if ((int)threadIdx.x < o) sRed[threadIdx.x] = sRed[threadIdx.x] + sRed[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double t = sRed[0];
+  __syncthreads();
+  return t;
+}
+
+// Sum of G partials, the same value in every workgroup.
+__device__ double sum_partials(const double *part, int G) {
+  double v = 0.0;
+  for (int t = threadIdx.x; t < G; t += kBlock) v = v + part[t];
+  return block_sum(v);
+}
+
+// Density at a node: the deposit, plus the surface source when there is one
+// (fixed point; with the fixed-point deposit the two are added as integers).
+template <int D>
+__device__ __forceinline__ double f_rho(const FieldParams &P, int64_t q) {
+  const double h3 = P.h * P.h * P.h;
+  const int64_t surf = P.rho_surf ? P.rho_surf[q] : 0;
+  if constexpr (D == PIC_DEP_FIXED64) {
+    return ((double)(((const int64_t *)P.rho)[q] + surf) * 2.3283064365386963e-10) / h3;
+  } else {
+    const double v = D == PIC_DEP_ATOMIC_FP32 ? (double)((const float *)P.rho)[q]
+                                              : ((const double *)P.rho)[q];
+    if (!P.rho_surf) return v / h3;
+    return v / h3 + ((double)surf * 2.3283064365386963e-10) / h3;
+  }
+}
+
+// Series permittivity of a link: a the level set at its lower-index node, b at
+// the other; the inside fraction by linear interpolation of the level set.
+__device__ __forceinline__ double f_eps(double a, double b, double ein, double eout) {
+  const bool ia = a < 0.0, ib = b < 0.0;
+  if (ia == ib) return ia ? ein : eout;
+  const double t = a / (a - b);
+  const double f = ia ? t : 1.0 - t;
+  return (ein * eout) / (f * eout + (1.0 - f) * ein);
+}
+
+template <class Gd>
+__device__ __forceinline__ double f_link_eps(const Gd &L, const FieldParams &P, int64_t q,
+                                             int64_t nb) {
+  return nb < q ? f_eps(L.psi[nb], L.psi[q], P.e_in, P.e_out)
+                : f_eps(L.psi[q], L.psi[nb], P.e_in, P.e_out);
+}
+
+// (A x) at an unknown node q of a grid (the fine grid or a level)
+template <bool IF, class Gd>
+__device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const double *x, int i,
+                                       int j, int k, int64_t q) {
+  const double xq = x[q];
+  double a = 0.0;
+  if constexpr (IF) {
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) {
+      a = a + (f_link_eps(L, P, q, nb) * w) * (xq - x[nb]);
+    });
+    return a * L.ih2;
+  } else {
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (xq - x[nb]); });
+    return L.s * a;
+  }
+}
+
+// r = b - A x, z = r / diag, p = z; Dirichlet nodes get x = g (and r = z = p = 0).
+template <int D, bool IF>
+__global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) {
+      P.x[q] = f_gval(P, i, j, k);
+      P.r[q] = 0.0;
+      P.z[q] = 0.0;
+      P.p[q] = 0.0;
+      P.Ap[q] = 0.0;
+      continue;
+    }
+    const double xq = P.x[q];
+    const double rho = f_rho<D>(P, q);
+    double ax = 0.0, dsum = 0.0, b = rho;
+    f_links(P, i, j, k, q, [&](int64_t nb, double w) {
+      int a, c, e;
+      f_ijk(P, nb, a, c, e);
+      const bool nd = f_dir(P, a, c, e);
+      const double xn = nd ? f_gval(P, a, c, e) : P.x[nb];
+      if constexpr (IF) {
+        const double cw = (f_link_eps(P, P, q, nb) * w) * P.ih2;
+        ax = ax + cw * (xq - xn);
+        dsum = dsum + cw;
+        if (nd) b = b + cw * xn;
+      } else {
+        ax = ax + w * (xq - xn);
+        dsum = dsum + w;
+        if (nd) b = b + P.s * w * xn;
+      }
+    });
+    const double r = IF ? rho - ax : rho - P.s * ax;
+    const double z = IF ? r / dsum : r / (P.s * dsum);
+    P.r[q] = r;
+    P.z[q] = z;
+    P.p[q] = z;
+    P.Ap[q] = 0.0;
+    rz = rz + r * z;
+    rr = rr + r * r;
+    bb = bb + b * b;
+  }
+  rz = block_sum(rz);
+  rr = block_sum(rr);
+  bb = block_sum(bb);
+  if (threadIdx.x == 0) {
+    P.part[1 * P.G + blockIdx.x] = rz;
+    P.part[3 * P.G + blockIdx.x] = rr;
+    P.part[5 * P.G + blockIdx.x] = bb;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void field_check0_kernel(FieldParams P) {
+  const double rr = sum_partials(P.part + 3 * P.G, P.G);
+  const double bb = sum_partials(P.part + 5 * P.G, P.G);
+  if (threadIdx.x == 0) {
+    P.ctrl->rr = rr;
+    P.ctrl->bb = bb;
+    P.ctrl->iters = 0;
+    P.ctrl->converged = __builtin_sqrt(rr) <= P.tol * __builtin_sqrt(bb) ? 1 : 0;
+  }
+}
+
+// The control block, read once per workgroup (thread 0, then shared), so that
+// every thread takes the same early exit even while workgroup 0 of the same
+// launch updates it.
+__device__ __forceinline__ FieldCtrl f_ctrl(const FieldParams &P) {
+  __shared__ FieldCtrl sCtrl;
+  if (threadIdx.x == 0) sCtrl = *P.ctrl;
+  __syncthreads();
+  const FieldCtrl c = sCtrl;
+  __syncthreads();
+  return c;
+}
+
+__device__ __forceinline__ bool f_done(const FieldCtrl &c, const FieldParams &P) {
+  return c.converged != 0 || c.iters >= P.max_iter;
+}
+
+// Ap = A p; partial p.Ap
+template <bool IF>
+__global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  double pap = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) continue;
+    const double pq = P.p[q];
+    const double ap = f_Ax<IF>(P, P, P.p, i, j, k, q);
+    P.Ap[q] = ap;
+    pap = pap + pq * ap;
+  }
+  pap = block_sum(pap);
+  if (threadIdx.x == 0) P.part[blockIdx.x] = pap;
+}
+
+// x += alpha p, r -= alpha Ap; partial r.r (parity n); Jacobi form: also
+// z = r / diag and partial r.z
+template <bool J, bool IF>
+__global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int o) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const int n = 1 - o;
+  const double alpha = sum_partials(P.part + (1 + o) * P.G, P.G) / sum_partials(P.part, P.G);
+  double rz = 0.0, rr = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) continue;
+    const double x = P.x[q] + alpha * P.p[q];
+    const double r = P.r[q] - alpha * P.Ap[q];
+    P.x[q] = x;
+    P.r[q] = r;
+    if constexpr (J) {
+      double d;
+      if constexpr (IF) {
+        d = P.diag[q];
+      } else {
+        double dsum = 0.0;
+        f_links(P, i, j, k, q, [&](int64_t, double w) { dsum = dsum + w; });
+        d = P.s * dsum;
+      }
+      const double z = r / d;
+      P.z[q] = z;
+      rz = rz + r * z;
+    }
+    rr = rr + r * r;
+  }
+  if constexpr (J) rz = block_sum(rz);
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) {
+    if constexpr (J) P.part[(1 + n) * P.G + blockIdx.x] = rz;
+    P.part[(3 + n) * P.G + blockIdx.x] = rr;
+  }
+}
+
+// The convergence test of an iteration (parity o): ||r|| <= tol ||b||; the
+// iteration count, ||r||^2 and the flag go to the control block.
+__device__ __forceinline__ bool f_check(const FieldParams &P, const FieldCtrl &c, int o,
+                                        bool write) {
+  const int n = 1 - o;
+  const double rr = sum_partials(P.part + (3 + n) * P.G, P.G);
+  const bool conv = __builtin_sqrt(rr) <= P.tol * __builtin_sqrt(c.bb);
+  if (write && threadIdx.x == 0) {
+    P.ctrl->rr = rr;
+    P.ctrl->iters = c.iters + 1;
+    if (conv) P.ctrl->converged = 1;
+  }
+  return conv;
+}
+
+// multigrid form: the test alone, one workgroup, before the V-cycle (whose
+// kernels then stop at f_done)
+__global__ __launch_bounds__(kBlock) void field_check_kernel(FieldParams P, int o) {
+  const FieldCtrl c = f_ctrl(P);
+  if (f_done(c, P)) return;  // uniform
+  f_check(P, c, o, true);
+}
+
+// Jacobi form: convergence test, then p = z + beta p; multigrid form: p = z +
+// beta p (the test ran before the V-cycle)
+template <bool J>
+__global__ __launch_bounds__(kBlock) void field_dir_kernel(FieldParams P, int o) {
+  const FieldCtrl c = f_ctrl(P);
+  if (f_done(c, P)) return;  // uniform
+  const int n = 1 - o;
+  if constexpr (J) {
+    if (f_check(P, c, o, blockIdx.x == 0)) return;  // uniform
+  }
+  const double beta = sum_partials(P.part + (1 + n) * P.G, P.G) /
+                      sum_partials(P.part + (1 + o) * P.G, P.G);
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (f_dir(P, i, j, k)) continue;
+    P.p[q] = P.z[q] + beta * P.p[q];
+  }
+}
+
+// ---- multigrid V-cycle preconditioner
+//
+// z = B r by one V-cycle over nested node grids (level l + 1: every other node
+// of level l, spacing 2h, the same faces, the finite-volume operator
+// rediscretised, homogeneous Dirichlet values): two damped-Jacobi sweeps from
+// zero, residual, restriction R = P^T / 8 (full weighting of the residual
+// density), the coarser cycle, trilinear prolongation P, two more sweeps; the
+// coarsest level (at most kCoarseNodes nodes) is solved exactly with its
+// inverse. With the same sweeps before and after and R proportional to P^T,
+// B is symmetric positive definite, so CG with it is still CG. Each level's
+// kernels run its own G workgroups over its nodes; all of them stop at
+// f_done.
+
+constexpr double kOmega = 6.0 / 7.0;  // Jacobi damping (3-D 7-point smoothing optimum)
+
+template <class Gd>
+__device__ __forceinline__ double f_dsum(const Gd &L, int i, int j, int k) {
+  return ((i > 0) + (i < L.n[0])) * (f_c(j, L.n[1]) * f_c(k, L.n[2])) +
+         ((j > 0) + (j < L.n[1])) * (f_c(i, L.n[0]) * f_c(k, L.n[2])) +
+         ((k > 0) + (k < L.n[2])) * (f_c(i, L.n[0]) * f_c(j, L.n[1]));
+}
+
+// diagonal of A at an unknown node of a level
+template <bool IF>
+__device__ __forceinline__ double mg_D(const MgLevel &L, int i, int j, int k, int64_t q) {
+  if constexpr (IF) return L.diag[q];
+  else return L.s * f_dsum(L, i, j, k);
+}
+
+// e = two sweeps from zero: e1 = w b / d is pointwise, so the second sweep
+// computes e1 at the neighbours itself.
+template <bool IF>
+__global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &L = P.lv[l];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    if (f_dir(L, i, j, k)) {
+      L.e[q] = 0.0;
+      continue;
+    }
+    const double d = mg_D<IF>(L, i, j, k, q);
+    const double bq = L.rhs[q];
+    const double e1 = kOmega * bq / d;
+    double a = 0.0;
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) {
+      int a2, b2, c2;
+      f_ijk(L, nb, a2, b2, c2);
+      const double en = f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<IF>(L, a2, b2, c2, nb);
+      if constexpr (IF) a = a + (f_link_eps(L, P, q, nb) * w) * (e1 - en);
+      else a = a + w * (e1 - en);
+    });
+    const double Ae1 = IF ? a * L.ih2 : L.s * a;
+    L.e[q] = e1 + kOmega * (bq - Ae1) / d;
+  }
+}
+
+// res = b - A e
+template <bool IF>
+__global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &L = P.lv[l];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - f_Ax<IF>(P, L, L.e, i, j, k, q);
+  }
+}
+
+// rhs of level l + 1 = P^T res / 8: a coarse node gathers the fine residuals
+// of its 3x3x3 fine neighbourhood (in the box) with weights 1 or 1/2 per axis.
+__global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
+  for (int64_t Q = (int64_t)blockIdx.x * kBlock + threadIdx.x; Q < C.nodes;
+       Q += (int64_t)C.G * kBlock) {
+    int I, J, K;
+    f_ijk(C, Q, I, J, K);
+    if (f_dir(C, I, J, K)) {
+      C.rhs[Q] = 0.0;
+      continue;
+    }
+    const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
+    double v = 0.0;
+    for (int dk = -1; dk <= 1; ++dk) {
+      const int k = k0 + dk;
+      if (k < 0 || k > F.n[2]) continue;
+      const double wk = dk == 0 ? 1.0 : 0.5;
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int j = j0 + dj;
+        if (j < 0 || j > F.n[1]) continue;
+        const double wjk = wk * (dj == 0 ? 1.0 : 0.5);
+        const double *row = F.res + (int64_t)k * F.sy + (int64_t)j * F.sx;
+        for (int di = -1; di <= 1; ++di) {
+          const int i = i0 + di;
+          if (i < 0 || i > F.n[0]) continue;
+          v = v + wjk * (di == 0 ? 1.0 : 0.5) * row[i];
+        }
+      }
+    }
+    C.rhs[Q] = v * 0.125;
+  }
+}
+
+// e of the coarsest level = A^-1 rhs on its m unknowns: one wave per row,
+// the right-hand side gathered into LDS.
+__global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &C = P.lv[P.levels - 1];
+  __shared__ double sb[kCoarseNodes];
+  const int m = P.m;
+  for (int v = threadIdx.x; v < m; v += kBlock) sb[v] = C.rhs[P.umap[v]];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < C.nodes;
+       q += (int64_t)gridDim.x * kBlock) {
+    int i, j, k;
+    f_ijk(C, q, i, j, k);
+    if (f_dir(C, i, j, k)) C.e[q] = 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int u = blockIdx.x * (kBlock / 64) + wave; u < m; u += gridDim.x * (kBlock / 64)) {
+    const double *row = P.ainv + (int64_t)u * m;
+    double a = 0.0;
+    for (int v = lane; v < m; v += 64) a = a + row[v] * sb[v];
+    for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+    if (lane == 0) C.e[P.umap[u]] = a;
+  }
+}
+
+// e += P e_c (trilinear: per axis the coarse node itself, or the mean of two)
+__global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < F.nodes;
+       q += (int64_t)F.G * kBlock) {
+    int i, j, k;
+    f_ijk(F, q, i, j, k);
+    if (f_dir(F, i, j, k)) continue;
+    const int ni = 1 + (i & 1), nj = 1 + (j & 1), nk = 1 + (k & 1);
+    const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
+    double v = 0.0;
+    for (int c = 0; c < nk; ++c)
+      for (int b = 0; b < nj; ++b) {
+        const double *row = C.e + (int64_t)(k / 2 + c) * C.sy + (int64_t)(j / 2 + b) * C.sx;
+        for (int a = 0; a < ni; ++a) v = v + (wi * wj * wk) * row[i / 2 + a];
+      }
+    F.e[q] += v;
+  }
+}
+
+// One damped-Jacobi sweep out = in + w (b - A in) / d. On level 0 the second
+// post-sweep writes z itself and the partial r.z to part[prz].
+template <bool Dot, bool IF>
+__global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, int to_e2, int prz) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &L = P.lv[l];
+  const double *in = to_e2 ? L.e : L.e2;
+  double *out = to_e2 ? L.e2 : L.e;
+  double rz = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    if (f_dir(L, i, j, k)) {
+      out[q] = 0.0;
+      continue;
+    }
+    const double bq = L.rhs[q];
+    const double v = in[q] + kOmega * (bq - f_Ax<IF>(P, L, in, i, j, k, q)) / mg_D<IF>(L, i, j, k, q);
+    out[q] = v;
+    if constexpr (Dot) rz = rz + bq * v;
+  }
+  if constexpr (Dot) {
+    rz = block_sum(rz);
+    if (threadIdx.x == 0) P.part[prz * P.G + blockIdx.x] = rz;
+  }
+}
+
+// Level set of the object at the nodes of level l (< 0 inside; fine cell units).
+__global__ __launch_bounds__(kBlock) void field_psi_kernel(FieldParams P, int l) {
+  const MgLevel &L = P.lv[l];
+  const FieldGeom &o = P.geo;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    const double x = L.scale * i, y = L.scale * j, z = L.scale * k;
+    double v;
+    if (o.kind == PIC_OBJ_SPHERE) {
+      const double dx = x - o.c[0], dy = y - o.c[1], dz = z - o.c[2];
+      v = __builtin_sqrt(dx * dx + dy * dy + dz * dz) - o.r;
+    } else {
+      const double dx = x - o.c[0], dy = y - o.c[1];
+      const double r2 = dx * dx + dy * dy;
+      const double ground = r2 < o.a2 ? o.zc - __builtin_sqrt(o.rc2 - r2) : o.z_flat;
+      v = z - ground;
+    }
+    L.psi[q] = v;
+  }
+}
+
+// Diagonal of A at the nodes of level l: sum of the link coefficients.
+__global__ __launch_bounds__(kBlock) void field_diag_kernel(FieldParams P, int l) {
+  const MgLevel &L = P.lv[l];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)L.G * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    double d = 0.0;
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) { d = d + f_link_eps(L, P, q, nb) * w; });
+    L.diag[q] = d * L.ih2;
+  }
+}
+
+// The collected charge of each tally bin at the bin's surface point,
+// deposited to the nodes in int64 fixed point (trilinear weights, the
+// remainder on the last corner so that the bin's charge is kept exactly).
+__global__ __launch_bounds__(kBlock) void surface_rho_kernel(SurfParams S) {
+  const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (b >= S.nbins) return;
+  double Q = 0.0;
+  for (int s = 0; s < S.ns; ++s) Q = Q + S.chg[s] * (double)S.tally[b * S.ns + s];
+  if (Q == 0.0) return;
+  if (!(__builtin_fabs(Q) < 1073741824.0)) {
+    atomicOr(S.err, kErrSurface);
+    return;
+  }
+  const FieldGeom &o = S.geo;
+  double g[3];
+  if (o.kind == PIC_OBJ_CRATER) {
+    g[0] = (double)(b % S.n[0]) + 0.5;
+    g[1] = (double)(b / S.n[0]) + 0.5;
+    const double dx = g[0] - o.c[0], dy = g[1] - o.c[1];
+    const double r2 = dx * dx + dy * dy;
+    g[2] = r2 < o.a2 ? o.zc - __builtin_sqrt(o.rc2 - r2) : o.z_flat;
+  } else {
+    const int m = o.patches;
+    const int face = (int)(b / ((int64_t)m * m)), iv = (int)((b / m) % m), iu = (int)(b % m);
+    const int ax = face / 2;
+    const int u = ax == 0 ? 1 : 0, v = ax == 2 ? 1 : 2;
+    double d[3];
+    d[ax] = (face & 1) ? 1.0 : -1.0;
+    d[u] = -1.0 + (2.0 * iu + 1.0) / m;
+    d[v] = -1.0 + (2.0 * iv + 1.0) / m;
+    const double len = __builtin_sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int k = 0; k < 3; ++k) g[k] = o.c[k] + o.rs * (d[k] / len);
+  }
+  int ci[3];
+  double f[3];
+  for (int k = 0; k < 3; ++k) {
+    double fl = __builtin_floor(g[k]);
+    fl = fl < 0.0 ? 0.0 : (fl > (double)(S.n[k] - 1) ? (double)(S.n[k] - 1) : fl);
+    ci[k] = (int)fl;
+    double of = g[k] - fl;
+    f[k] = of < 0.0 ? 0.0 : (of > 1.0 ? 1.0 : of);
+  }
+  double W[8];
+  weights(f, W);
+  long long C[8], sum = 0;
+  for (int n = 0; n < 7; ++n) {
+    C[n] = fixq(Q * W[n]);
+    sum += C[n];
+  }
+  C[7] = fixq(Q) - sum;
+  const int64_t base = ci[0] + S.sx * ci[1] + S.sy * ci[2];
+  const int64_t off[8] = {0, 1, S.sx, S.sx + 1, S.sy, S.sy + 1, S.sy + S.sx, S.sy + S.sx + 1};
+  for (int n = 0; n < 8; ++n)
+    atomicAdd((unsigned long long *)&S.rho_surf[base + off[n]], (unsigned long long)C[n]);
+}
+
+// multigrid start: p = z
+__global__ __launch_bounds__(kBlock) void field_pstart_kernel(FieldParams P) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock)
+    P.p[q] = P.z[q];
+}
+
+// E = -grad phi at the nodes: central differences inside, 0 normal to a
+// zero-Neumann face, second-order one-sided differences on a Dirichlet face.
+template <int R>
+__global__ __launch_bounds__(kBlock) void field_E_kernel(FieldParams P) {
+  using T = typename RealOf<R>::T;
+  using V4 = typename Vec4Of<T>::type;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)P.G * kBlock) {
+    int ijk[3];
+    f_ijk(P, q, ijk[0], ijk[1], ijk[2]);
+    const int64_t st[3] = {1, P.sx, P.sy};
+    double e[3];
+    for (int d = 0; d < 3; ++d) {
+      const int a = ijk[d], n = P.n[d];
+      const double *x = P.x;
+      if (a > 0 && a < n) {
+        e[d] = -(x[q + st[d]] - x[q - st[d]]) / (2.0 * P.h);
+      } else if (!((P.mask >> (2 * d + (a == 0 ? 0 : 1))) & 1)) {
+        e[d] = 0.0;
+      } else if (n == 1) {
+        e[d] = a == 0 ? -(x[q + st[d]] - x[q]) / P.h : -(x[q] - x[q - st[d]]) / P.h;
+      } else if (a == 0) {
+        e[d] = -(-3.0 * x[q] + 4.0 * x[q + st[d]] - x[q + 2 * st[d]]) / (2.0 * P.h);
+      } else {
+        e[d] = -(3.0 * x[q] - 4.0 * x[q - st[d]] + x[q - 2 * st[d]]) / (2.0 * P.h);
+      }
+    }
+    V4 v;
+    v.x = (T)e[0];
+    v.y = (T)e[1];
+    v.z = (T)e[2];
+    v.w = T(0);
+    ((V4 *)P.E)[q] = v;
+  }
+}
+
+}  // namespace
+
+template <bool IF>
+static hipError_t field_init(int deposit, const FieldParams &p, hipStream_t s) {
+  switch (deposit) {
+    case PIC_DEP_FIXED64:
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_FIXED64, IF>), dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    case PIC_DEP_ATOMIC_FP32:
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP32, IF>), dim3(p.G), dim3(kBlock), 0, s,
+                         p);
+      break;
+    case PIC_DEP_ATOMIC_FP64:
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP64, IF>), dim3(p.G), dim3(kBlock), 0, s,
+                         p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(field_check0_kernel, dim3(1), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s) {
+  return p.iface ? field_init<true>(deposit, p, s) : field_init<false>(deposit, p, s);
+}
+
+// z = V-cycle(r); the partial r.z to part[prz]
+template <bool IF>
+static void field_vcycle(const FieldParams &p, int prz, hipStream_t s) {
+  const int L = p.levels;
+  for (int l = 0; l + 1 < L; ++l) {
+    hipLaunchKernelGGL(mg_pre_kernel<IF>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL(mg_res_kernel<IF>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL(mg_restrict_kernel, dim3(p.lv[l + 1].G), dim3(kBlock), 0, s, p, l);
+  }
+  const int gc = p.m > 0 ? (p.m + kBlock / 64 - 1) / (kBlock / 64) : 1;
+  hipLaunchKernelGGL(mg_coarse_kernel, dim3(gc), dim3(kBlock), 0, s, p);
+  for (int l = L - 2; l >= 0; --l) {
+    hipLaunchKernelGGL(mg_prolong_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 1,
+                       0);
+    if (l == 0)
+      hipLaunchKernelGGL((mg_sweep_kernel<true, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0,
+                         prz);
+    else
+      hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0,
+                         0);
+  }
+}
+
+hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s) {
+  if (p.iface) field_vcycle<true>(p, 1, s);
+  else field_vcycle<false>(p, 1, s);
+  hipLaunchKernelGGL(field_pstart_kernel, dim3(p.G), dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+template <bool IF>
+static hipError_t field_iter(const FieldParams &p, int o, hipStream_t s) {
+  hipLaunchKernelGGL(field_apply_kernel<IF>, dim3(p.G), dim3(kBlock), 0, s, p);
+  if (p.levels >= 2) {
+    hipLaunchKernelGGL((field_update_kernel<false, IF>), dim3(p.G), dim3(kBlock), 0, s, p, o);
+    hipLaunchKernelGGL(field_check_kernel, dim3(1), dim3(kBlock), 0, s, p, o);
+    field_vcycle<IF>(p, 2 - o, s);  // parity n = 1 - o
+    hipLaunchKernelGGL(field_dir_kernel<false>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((field_update_kernel<true, IF>), dim3(p.G), dim3(kBlock), 0, s, p, o);
+  hipLaunchKernelGGL(field_dir_kernel<true>, dim3(p.G), dim3(kBlock), 0, s, p, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s) {
+  return p.iface ? field_iter<true>(p, o, s) : field_iter<false>(p, o, s);
+}
+
+hipError_t launch_field_psi(const FieldParams &p, int l, hipStream_t s) {
+  hipLaunchKernelGGL(field_psi_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_diag(const FieldParams &p, int l, hipStream_t s) {
+  hipLaunchKernelGGL(field_diag_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_surface_rho(const SurfParams &p, hipStream_t s) {
+  if (p.nbins <= 0) return hipSuccess;
+  hipLaunchKernelGGL(surface_rho_kernel, dim3((unsigned)((p.nbins + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_E(int repr, const FieldParams &p, hipStream_t s) {
+  switch (repr) {
+    case PIC_REPR_FP64:
+      hipLaunchKernelGGL(field_E_kernel<PIC_REPR_FP64>, dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    case PIC_REPR_FP32_ABS:
+      hipLaunchKernelGGL(field_E_kernel<PIC_REPR_FP32_ABS>, dim3(p.G), dim3(kBlock), 0, s, p);
+      break;
+    default:
+      hipLaunchKernelGGL(field_E_kernel<PIC_REPR_FP32_CELL>, dim3(p.G), dim3(kBlock), 0, s, p);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pic
