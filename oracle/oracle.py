@@ -179,6 +179,8 @@ class Problem:
     def nbins(self):
         if self.obj == "crater":
             return self.nx * self.ny
+        if self.obj != "sphere":
+            return 0  # nothing collects particles
         return 6 * self.sphere_patches ** 2 if self.sphere_patches else 1
 
     def cstruct(self) -> _Cfg:

@@ -725,10 +725,12 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
   const int ns = cfg.n_species;
   const bool crater = cfg.obj_kind == OBJ_CRATER;
   const Geometry<T> G = make_geometry<T>(cfg);
-  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny
-                                : (cfg.sphere_patches > 0 ? 6 * (int64_t)cfg.sphere_patches *
-                                                                cfg.sphere_patches
-                                                          : 1);
+  const int64_t nbins =
+      crater ? (int64_t)cfg.nx * cfg.ny
+             : (cfg.obj_kind != OBJ_SPHERE
+                    ? 0
+                    : (cfg.sphere_patches > 0 ? 6 * (int64_t)cfg.sphere_patches * cfg.sphere_patches
+                                              : 1));
   std::vector<T> E[3];
   for (int d = 0; d < 3; ++d) {
     E[d].resize(nodes);
@@ -880,7 +882,7 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
       out->rho[k] = rho.f64[k] / h3;
     }
   }
-  std::memcpy(out->tally, B.tally.data(), sizeof(int64_t) * B.tally.size());
+  if (!B.tally.empty()) std::memcpy(out->tally, B.tally.data(), sizeof(int64_t) * B.tally.size());
   std::memcpy(out->escaped, B.escaped.data(), sizeof(int64_t) * B.escaped.size());
   return ORC_OK;
 }
@@ -894,10 +896,12 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
   const int ns = cfg.n_species;
   const bool crater = cfg.obj_kind == OBJ_CRATER;
   const Geometry<T> G = make_geometry<T>(cfg);
-  const int64_t nbins = crater ? (int64_t)cfg.nx * cfg.ny
-                                : (cfg.sphere_patches > 0 ? 6 * (int64_t)cfg.sphere_patches *
-                                                                cfg.sphere_patches
-                                                          : 1);
+  const int64_t nbins =
+      crater ? (int64_t)cfg.nx * cfg.ny
+             : (cfg.obj_kind != OBJ_SPHERE
+                    ? 0
+                    : (cfg.sphere_patches > 0 ? 6 * (int64_t)cfg.sphere_patches * cfg.sphere_patches
+                                              : 1));
   std::vector<T> E[3];
   for (int d = 0; d < 3; ++d) {
     E[d].resize(nodes);
@@ -1068,7 +1072,7 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
       out->rho[k] = rho.f64[k] / h3;
     }
   }
-  std::memcpy(out->tally, B.tally.data(), sizeof(int64_t) * B.tally.size());
+  if (!B.tally.empty()) std::memcpy(out->tally, B.tally.data(), sizeof(int64_t) * B.tally.size());
   std::memcpy(out->escaped, B.escaped.data(), sizeof(int64_t) * B.escaped.size());
   return ORC_OK;
 }
