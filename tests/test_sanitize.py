@@ -1,0 +1,25 @@
+"""The oracle under AddressSanitizer and UndefinedBehaviorSanitizer: a driver
+that calls every entry on small inputs (all representations, objects,
+boundaries, injection, photoemission, field solves) is built with g++ and
+the sanitizer runtimes linked statically, and must run clean."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_oracle_is_clean_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    exe = tmp_path / "oracle_driver"
+    src = os.path.join(HERE, "sanitize", "oracle_driver.cpp")
+    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-ffp-contract=off",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-static-libasan", "-static-libubsan", src, "-o", str(exe)])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert r.stdout.strip().endswith("ok")
