@@ -1305,6 +1305,9 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
       if (dmalloc(c, &q, c->mg[l].nodes * 8) != hipSuccess)
         return fail(c, PIC_E_NOMEM, "hipMalloc failed");
       c->mg[l].diag = (double *)q;
+      if (dmalloc(c, &q, c->mg[l].nodes * 8) != hipSuccess)
+        return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+      c->mg[l].cq = (double *)q;
     }
   }
   if (levels >= 2) {
@@ -1374,6 +1377,7 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   P.geo = geo;
   P.psi = c->mg[0].psi;
   P.diag = c->mg[0].diag;
+  P.cq = c->mg[0].cq;
   P.ih2 = c->mg[0].ih2;
   const int pe = prof_begin(c, 4);
   if (iface) {  // level sets once, diagonals when the permittivities change

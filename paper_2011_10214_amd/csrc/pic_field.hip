@@ -124,6 +124,11 @@ __device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const 
   const double xq = x[q];
   double a = 0.0;
   if constexpr (IF) {
+    const double cq = L.cq[q];
+    if (cq > 0.0) {  // all six links of one permittivity (nearly every node)
+      f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (xq - x[nb]); });
+      return cq * a;
+    }
     f_links(L, i, j, k, q, [&](int64_t nb, double w) {
       a = a + (f_link_eps(L, P, q, nb) * w) * (xq - x[nb]);
     });
@@ -159,7 +164,8 @@ __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
       const bool nd = f_dir(P, a, c, e);
       const double xn = nd ? f_gval(P, a, c, e) : P.x[nb];
       if constexpr (IF) {
-        const double cw = (f_link_eps(P, P, q, nb) * w) * P.ih2;
+        const double cq = P.cq[q];
+        const double cw = cq > 0.0 ? cq * w : (f_link_eps(P, P, q, nb) * w) * P.ih2;
         ax = ax + cw * (xq - xn);
         dsum = dsum + cw;
         if (nd) b = b + cw * xn;
@@ -366,14 +372,21 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
     const double bq = L.rhs[q];
     const double e1 = kOmega * bq / d;
     double a = 0.0;
-    f_links(L, i, j, k, q, [&](int64_t nb, double w) {
+    const double cq = IF ? L.cq[q] : 0.0;
+    const bool uni = !IF || cq > 0.0;  // one permittivity on all six links
+    auto e1n = [&](int64_t nb) {
       int a2, b2, c2;
       f_ijk(L, nb, a2, b2, c2);
-      const double en = f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<IF>(L, a2, b2, c2, nb);
-      if constexpr (IF) a = a + (f_link_eps(L, P, q, nb) * w) * (e1 - en);
-      else a = a + w * (e1 - en);
-    });
-    const double Ae1 = IF ? a * L.ih2 : L.s * a;
+      return f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<IF>(L, a2, b2, c2, nb);
+    };
+    if (uni) {
+      f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (e1 - e1n(nb)); });
+    } else {
+      f_links(L, i, j, k, q, [&](int64_t nb, double w) {
+        a = a + (f_link_eps(L, P, q, nb) * w) * (e1 - e1n(nb));
+      });
+    }
+    const double Ae1 = IF ? (uni ? cq * a : a * L.ih2) : L.s * a;
     L.e[q] = e1 + kOmega * (bq - Ae1) / d;
   }
 }
@@ -531,8 +544,14 @@ __global__ __launch_bounds__(kBlock) void field_diag_kernel(FieldParams P, int l
     int i, j, k;
     f_ijk(L, q, i, j, k);
     double d = 0.0;
-    f_links(L, i, j, k, q, [&](int64_t nb, double w) { d = d + f_link_eps(L, P, q, nb) * w; });
+    const bool in = L.psi[q] < 0.0;
+    bool uni = true;
+    f_links(L, i, j, k, q, [&](int64_t nb, double w) {
+      d = d + f_link_eps(L, P, q, nb) * w;
+      uni = uni && ((L.psi[nb] < 0.0) == in);
+    });
     L.diag[q] = d * L.ih2;
+    L.cq[q] = uni ? (in ? P.e_in : P.e_out) * L.ih2 : -1.0;
   }
 }
 

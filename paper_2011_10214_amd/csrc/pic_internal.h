@@ -221,8 +221,10 @@ struct MgLevel {
   double s;                    // eps / h_l^2
   double *e, *e2, *res, *rhs;  // correction (ping-pong), residual, right-hand side
   int32_t G;                   // workgroups of the level's kernels
-  // object as an interface: level set and diagonal of A at the level's nodes
-  double *psi, *diag;
+  // object as an interface: level set and diagonal of A at the level's nodes;
+  // cq: eps / h_l^2 of a node whose six links lie on its side of the
+  // interface (all one permittivity), -1 for a node with a crossing link
+  double *psi, *diag, *cq;
   double ih2;                  // 1 / h_l^2
   double scale;                // fine cells per cell of the level
 };
@@ -261,7 +263,7 @@ struct FieldParams {
   // the fine level (= lv[0].psi / lv[0].diag), geometry; surface source
   int32_t iface;
   double e_in, e_out;
-  const double *psi, *diag;
+  const double *psi, *diag, *cq;
   double ih2;
   FieldGeom geo;
   const int64_t *rho_surf;  // fixed-point surface charge (nullable)
