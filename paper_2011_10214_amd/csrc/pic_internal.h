@@ -143,11 +143,13 @@ __host__ __device__ inline int64_t inflow_room(int32_t per_step) {
   return (int64_t)per_step * (kInflowSteps + 2);
 }
 // Room for a tile that wanted a arrivals in the last step (a count of all
-// attempts, overflowed ones included): its stay zone one more step of them
-// (they stay), its arrival zone twice as many, beyond the zones of its count.
+// attempts, overflowed ones included): its stay zone kDemandSteps more steps
+// of them (they stay), its arrival zone twice as many, beyond the zones of
+// its count.
+constexpr int32_t kDemandSteps = 4;
 __host__ __device__ inline int64_t demand_room(int32_t cnt, int32_t a) {
   const int64_t az = arrival_zone(cnt);
-  return (int64_t)a + (2 * (int64_t)a > az ? 2 * (int64_t)a - az : 0);
+  return kDemandSteps * (int64_t)a + (2 * (int64_t)a > az ? 2 * (int64_t)a - az : 0);
 }
 
 struct LoadParams {

@@ -1081,7 +1081,7 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
     const int32_t c = P.count[j];
     const int32_t in = use && P.inflow ? P.inflow[j] : 0;
     const int32_t ga = use ? a : 0;
-    const int32_t sz = stay_zone(c) + kInflowSteps * in + ga;
+    const int32_t sz = stay_zone(c) + kInflowSteps * in + kDemandSteps * ga;
     const int32_t az = arrival_zone(c) > 2 * ga ? arrival_zone(c) : 2 * ga;
     const int32_t cap = sz + az + 2 * in;
     P.dst_lay.base[j] = run;
