@@ -129,9 +129,10 @@ typedef struct {
   int32_t deposit;       /* pic_deposit */
   int32_t sort_interval; /* particles are kept grouped by tile of 4^3 cells; every
                             step moves each particle to its new tile's region.
-                            K >= 1 also re-plans the tile regions every K steps;
-                            0 (default) only after a load or when a tile's spare
-                            room runs out. Results do not depend on it. */
+                            K >= 1 also re-plans the tile regions of all species
+                            every K steps; 0 (default) re-plans a species' regions
+                            only after its load or when one of its tiles runs
+                            out of spare room. Results do not depend on it. */
   int32_t reflect;       /* bit f: box face f (0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+)
                             reflects instead of removing (the symmetry planes of
                             the particle setups in §3.1.3 and §5.2.2): right after
@@ -391,7 +392,7 @@ pic_status pic_get_particles_by_id(pic_ctx *ctx, int32_t species, int64_t n,
 typedef struct {
   int64_t step_launches;  /* fused gather/push/collect/deposit kernel */
   double step_ms;         /* summed event time of those launches */
-  int64_t sort_launches;  /* re-bucketing passes (each: count, scan, scatter) */
+  int64_t sort_launches;  /* re-bucketing passes (each: count, scan, scatter, commit) */
   double sort_ms;
   int64_t clear_launches; /* rho clears */
   double clear_ms;

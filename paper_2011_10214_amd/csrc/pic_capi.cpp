@@ -78,7 +78,7 @@ int64_t mesh_bytes(const pic_config &c, const Dims &L) {
   b += 6 * align256((int64_t)L.ns * L.ntiles * 4);              // stayed / arrived counts
   b += 2 * align256((int64_t)L.ns * L.ntiles * 4);              // counts, cursors
   b += align256((int64_t)L.ns * L.ntiles * kNeighbours * 4);    // per-tile histograms
-  b += 4096;                                                    // stats, flags
+  b += 4096;                                                    // stats, counters
   return b;
 }
 
@@ -185,8 +185,9 @@ struct pic_ctx {
   int32_t *err = nullptr, *bad = nullptr;
   pic::Layout lay[2] = {};  // tile layouts (the one in use: lay[li])
   int32_t *nst[2] = {nullptr, nullptr}, *arr[2] = {nullptr, nullptr}, *ovf[2] = {nullptr, nullptr};
-  int32_t *flags = nullptr;          // device: re-bucketing wanted
-  volatile int32_t *flag_host = nullptr;  // pinned copy, refreshed after each step
+  // pinned copy of the overflow counts of the current buffer, refreshed after
+  // each step: species with a nonzero count want their regions re-planned
+  volatile int32_t *ovf_host = nullptr;
   int32_t *count = nullptr, *cursor = nullptr, *hist = nullptr;
   struct Species {
     int64_t cap = 0;
@@ -219,7 +220,7 @@ struct pic_ctx {
   int32_t *inflow = nullptr;    // device [ns][ntiles]: photoemission room per re-bucketing
   pic_injection inj{};
   int64_t step_index = 0;       // pic_step steps since creation (injection key)
-  int64_t *injected = nullptr;  // device [ns]: particles injected
+  int64_t *injected = nullptr;  // device [ns][kCountSlots]: particles injected
   bool deposited = false;       // rho holds a deposit
   // field solve (allocated at the first solve)
   double *fx = nullptr, *fr = nullptr, *fz = nullptr, *fp = nullptr, *fAp = nullptr,
@@ -286,8 +287,8 @@ void free_all(pic_ctx *c) {
     (void)hipEventDestroy(e.b);
   }
   c->events.clear();
-  if (c->flag_host) (void)hipHostFree((void *)c->flag_host);
-  c->flag_host = nullptr;
+  if (c->ovf_host) (void)hipHostFree((void *)c->ovf_host);
+  c->ovf_host = nullptr;
   if (c->fctrl_host) (void)hipHostFree(c->fctrl_host);
   c->fctrl_host = nullptr;
 }
@@ -392,7 +393,6 @@ Bins bins_of(pic_ctx *c) {
     B.ovf_base[s] = c->sp[s].ovf_base;
     B.ovf_cap[s] = c->sp[s].ovf_cap;
   }
-  B.flags = c->flags;
   return B;
 }
 
@@ -497,12 +497,17 @@ InjParams inj_params(pic_ctx *c, int out) {
   return I;
 }
 
-// Re-bucketing with fresh tile capacities: from the current buffer (tile
-// regions + overflow list, or the flat range of a freshly loaded species) into
-// the other buffer under a new layout.
-pic_status do_sort(pic_ctx *c) {
+// Re-bucketing with fresh tile capacities of the species in want and of every
+// freshly loaded species: from the current buffer (tile regions + overflow
+// list, or the flat range of a freshly loaded species) into the spare buffer
+// under a new layout, which then becomes the species' current buffer (the
+// buffer index stays; the two buffers of the species swap). The other species
+// keep their particles and layout as they are.
+pic_status do_sort(pic_ctx *c, int32_t want) {
   const Dims &L = c->L;
+  const int32_t all = (1 << L.ns) - 1;
   SortParams S{};
+  S.sel = want & all;
   int64_t max_src = 0;
   for (int s = 0; s < L.ns; ++s) {
     const pic_ctx::Species &sp = c->sp[s];
@@ -514,6 +519,11 @@ pic_status do_sort(pic_ctx *c) {
       if (sp.n_buf > max_src) max_src = sp.n_buf;
     }
     S.region_cap[s] = sp.ovf_base;
+  }
+  S.sel |= S.unsorted;
+  if (S.sel == 0) {
+    c->sorted = true;
+    return PIC_OK;
   }
   S.bins = bins_of(c);
   S.inflow = c->pe_on ? c->inflow : nullptr;
@@ -536,13 +546,21 @@ pic_status do_sort(pic_ctx *c) {
   PIC_HIP(c, launch_sort_count(c->cfg.repr, S, max_src, c->stream));
   PIC_HIP(c, launch_sort_scan(S, c->stream));
   PIC_HIP(c, launch_sort_scatter(c->cfg.repr, S, max_src, c->stream));
+  PIC_HIP(c, launch_sort_commit(S, c->stream));
   prof_end(c, pe);
-  c->cur = 1 - c->cur;
-  c->li = 1 - c->li;
-  for (int s = 0; s < L.ns; ++s) c->sp[s].unsorted = false;
+  for (int s = 0; s < L.ns; ++s) {
+    if (!((S.sel >> s) & 1)) continue;
+    pic_ctx::Species &sp = c->sp[s];
+    std::swap(sp.mem[0], sp.mem[1]);
+    std::swap(sp.ids_mem[0], sp.ids_mem[1]);
+    std::swap(sp.buf[0], sp.buf[1]);
+    sp.unsorted = false;
+  }
   c->sorted = true;
-  c->since_sort = 0;
-  if (c->flag_host) *c->flag_host = 0;
+  if (S.sel == all) c->since_sort = 0;
+  if (c->ovf_host)
+    for (int s = 0; s < L.ns; ++s)
+      if ((S.sel >> s) & 1) c->ovf_host[s] = 0;
   return PIC_OK;
 }
 
@@ -553,7 +571,21 @@ pic_status clear_rho(pic_ctx *c) {
   return PIC_OK;
 }
 
-// Resets the collected counts and escape counters of one species.
+// Particles injected per species: the sum of the species' count slots.
+pic_status read_injected(pic_ctx *c, int64_t *out) {
+  const int ns = c->L.ns;
+  std::vector<int64_t> v((size_t)ns * kCountSlots);
+  PIC_HIP(c, hipMemcpy(v.data(), c->injected, v.size() * 8, hipMemcpyDeviceToHost));
+  for (int s = 0; s < ns; ++s) {
+    int64_t a = 0;
+    for (int k = 0; k < kCountSlots; ++k) a += v[(size_t)s * kCountSlots + k];
+    out[s] = a;
+  }
+  return PIC_OK;
+}
+
+// Resets the collected counts, escape counters and injected count of one
+// species.
 pic_status reset_species_counters(pic_ctx *c, int s) {
   const Dims &L = c->L;
   std::vector<int64_t> t(L.nbins * L.ns), e(6 * L.ns);
@@ -563,6 +595,9 @@ pic_status reset_species_counters(pic_ctx *c, int s) {
   for (int f = 0; f < 6; ++f) e[f * L.ns + s] = 0;
   if (L.nbins) PIC_HIP(c, hipMemcpy(c->tally, t.data(), t.size() * 8, hipMemcpyHostToDevice));
   PIC_HIP(c, hipMemcpy(c->escaped, e.data(), e.size() * 8, hipMemcpyHostToDevice));
+  const std::vector<int64_t> z(kCountSlots, 0);
+  PIC_HIP(c, hipMemcpy(c->injected + (size_t)s * kCountSlots, z.data(), kCountSlots * 8,
+                       hipMemcpyHostToDevice));
   return PIC_OK;
 }
 
@@ -586,7 +621,7 @@ pic_status commit_species(pic_ctx *c, int s, int64_t n, bool ids) {
 // re-bucketing does not change any result). Synchronises.
 pic_status species_ranges(pic_ctx *c, int s, std::vector<std::pair<int64_t, int64_t>> &out) {
   pic_status st;
-  if (!c->sorted && (st = do_sort(c)) != PIC_OK) return st;
+  if (!c->sorted && (st = do_sort(c, 0)) != PIC_OK) return st;
   PIC_HIP(c, hipStreamSynchronize(c->stream));
   const int nt = c->L.ntiles;
   std::vector<int64_t> base(nt);
@@ -714,8 +749,7 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
       {(void **)&c->arr[1], (int64_t)L.ns * L.ntiles * 4},
       {(void **)&c->ovf[0], 64},
       {(void **)&c->ovf[1], 64},
-      {(void **)&c->flags, 64},
-      {(void **)&c->injected, 64},
+      {(void **)&c->injected, 8 * PIC_MAX_SPECIES * kCountSlots},
       {(void **)&c->count, (int64_t)L.ns * L.ntiles * 4},
       {(void **)&c->cursor, (int64_t)L.ns * L.ntiles * 4},
       {(void **)&c->hist, (int64_t)L.ns * L.ntiles * kNeighbours * 4},
@@ -729,8 +763,8 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
   void *fh = nullptr;
   if (hipHostMalloc(&fh, 64, hipHostMallocDefault) != hipSuccess)
     return bail(PIC_E_NOMEM, "hipHostMalloc failed");
-  c->flag_host = (volatile int32_t *)fh;
-  *c->flag_host = 0;
+  c->ovf_host = (volatile int32_t *)fh;
+  for (int s = 0; s < PIC_MAX_SPECIES; ++s) c->ovf_host[s] = 0;
   for (int s = 0; s < L.ns; ++s) {
     pic_ctx::Species &S = c->sp[s];
     S.cap = cfg->capacity[s];
@@ -935,7 +969,7 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
   if (nsteps > 0 && !c->E_set) return fail(c, PIC_E_STATE, "pic_set_node_E has not been called");
   pic_status st;
   if (nsteps == 0) {
-    if (!c->sorted && (st = do_sort(c)) != PIC_OK) return st;
+    if (!c->sorted && (st = do_sort(c, 0)) != PIC_OK) return st;
     if ((st = clear_rho(c)) != PIC_OK) return st;
     StepParams P = step_params(c);
     const int pe = prof_begin(c, 0);
@@ -946,12 +980,16 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
   }
   for (int k = 0; k < nsteps; ++k) {
     // particles are re-bucketed by the step itself; a re-bucketing with fresh
-    // tile capacities runs after a load, every K steps if K > 0, and when a
-    // tile ran out of spare room (seen through the pinned flag, which may lag
-    // by a step: the overflow list keeps every particle in the meantime)
-    const bool want = !c->sorted || (c->K > 0 && c->since_sort >= c->K) ||
-                      (c->flag_host && *c->flag_host != 0);
-    if (want && (st = do_sort(c)) != PIC_OK) return st;
+    // tile capacities runs for a species after its load and when one of its
+    // tiles ran out of spare room (its overflow list is not empty; seen through
+    // the pinned counts, which may lag by a step: the overflow list keeps every
+    // particle in the meantime), and for all species every K steps if K > 0
+    int32_t want = 0;
+    if (c->ovf_host)
+      for (int s = 0; s < c->L.ns; ++s)
+        if (c->ovf_host[s] > 0) want |= 1 << s;
+    if (c->K > 0 && c->since_sort >= c->K) want = (1 << c->L.ns) - 1;
+    if ((want || !c->sorted) && (st = do_sort(c, want)) != PIC_OK) return st;
     if ((st = clear_rho(c)) != PIC_OK) return st;
     StepParams P = step_params(c);
     const int pe = prof_begin(c, 0);
@@ -972,8 +1010,8 @@ pic_status pic_step(pic_ctx *c, int32_t nsteps) {
       PIC_HIP(c, launch_photo(c->cfg.repr, c->cfg.deposit, I, c->stream));
       prof_end(c, pp);
     }
-    PIC_HIP(c, hipMemcpyAsync((void *)c->flag_host, c->flags, sizeof(int32_t),
-                              hipMemcpyDeviceToHost, c->stream));
+    PIC_HIP(c, hipMemcpyAsync((void *)c->ovf_host, c->ovf[1 - c->cur],
+                              sizeof(int32_t) * c->L.ns, hipMemcpyDeviceToHost, c->stream));
     c->cur = 1 - c->cur;
     c->since_sort++;
     c->step_index++;
@@ -1045,7 +1083,7 @@ pic_status pic_get_counters(pic_ctx *c, int64_t *alive, int64_t *absorbed, int64
   if (L.nbins) PIC_HIP(c, hipMemcpy(t.data(), c->tally, t.size() * 8, hipMemcpyDeviceToHost));
   PIC_HIP(c, hipMemcpy(e.data(), c->escaped, e.size() * 8, hipMemcpyDeviceToHost));
   int64_t inj[PIC_MAX_SPECIES] = {0, 0, 0, 0};
-  PIC_HIP(c, hipMemcpy(inj, c->injected, sizeof(int64_t) * L.ns, hipMemcpyDeviceToHost));
+  if ((st = read_injected(c, inj)) != PIC_OK) return st;
   for (int s = 0; s < L.ns; ++s) {
     int64_t a = 0, es = 0;
     for (int64_t b = 0; b < L.nbins; ++b) a += t[b * L.ns + s];
@@ -1571,8 +1609,7 @@ pic_status pic_get_injected(pic_ctx *c, int64_t *injected) {
   if (!injected) return fail(c, PIC_E_INVALID, "injected must not be NULL");
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
-  PIC_HIP(c, hipMemcpy(injected, c->injected, sizeof(int64_t) * c->L.ns, hipMemcpyDeviceToHost));
-  return PIC_OK;
+  return read_injected(c, injected);
 }
 
 pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *n_out, double *x,
@@ -1666,7 +1703,7 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
   if (n == 0) return PIC_OK;
-  if (!c->sorted && (st = do_sort(c)) != PIC_OK) return st;
+  if (!c->sorted && (st = do_sort(c, 0)) != PIC_OK) return st;
   void *d_ids = nullptr, *d_found = nullptr, *d_out = nullptr;
   auto cleanup = [&]() {
     if (d_ids) (void)hipFree(d_ids);
@@ -1756,7 +1793,7 @@ struct pic_batch {
   std::vector<int64_t> bytes;       // per slot footprint
   std::vector<int64_t> work;        // per slot: particles at attach (the cost of one step)
   std::vector<double> weight;       // per slot: share of a run's particle-steps (default 1)
-  std::vector<int32_t> want_sort;   // per slot: spare room ran out in the last run
+  std::vector<int32_t> want_sort;   // per slot: bit s: species s ran out of spare room
   std::vector<int32_t> order;       // table entry -> slot of the run in flight
   std::vector<int32_t> quota;       // per slot: steps of the run in flight
   bool inflight = false;            // launched, not yet waited for
@@ -1801,7 +1838,7 @@ BatchTable table_of(const pic_batch *b) {
 }
 
 // The graph of a run of run_length(j) batched steps followed by the read-back
-// of the slots' re-bucketing flags (captured on first use).
+// of the slots' re-bucketing requests (captured on first use).
 pic_status ensure_graph(pic_batch *b, int j) {
   if (b->exec[j]) return PIC_OK;
   const BatchTable T = table_of(b);
@@ -1965,7 +2002,7 @@ pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *s
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return bfail(b, PIC_E_DEVICE, "context stream failed");
   if (!c->sorted) {
-    if (do_sort(c) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
+    if (do_sort(c, 0) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
     if (hipStreamSynchronize(c->stream) != hipSuccess)
       return bfail(b, PIC_E_DEVICE, "context stream failed");
   }
@@ -1995,7 +2032,7 @@ pic_status pic_batch_launch(pic_batch *b) {
     pic_ctx *c = b->ctx[k];
     if (!c || b->remaining[k] <= 0) continue;
     if (b->want_sort[k] || !c->sorted) {
-      if (do_sort(c) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
+      if (do_sort(c, b->want_sort[k]) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
       PIC_BHIP(b, hipStreamSynchronize(c->stream));
       b->want_sort[k] = 0;
     }
@@ -2070,7 +2107,7 @@ pic_status pic_batch_wait(pic_batch *b, int32_t *n_done, int32_t *done_slots) {
     if (did & 1) c->cur = 1 - c->cur;
     c->since_sort += did;
     b->remaining[k] -= did;
-    b->want_sort[k] = b->h_ctrl[2 + M + i] != 0;
+    b->want_sort[k] = b->h_ctrl[2 + M + i];
     if (b->remaining[k] == 0) {
       if (done_slots) done_slots[nd] = k;
       ++nd;

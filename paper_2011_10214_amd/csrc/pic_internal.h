@@ -55,10 +55,11 @@ struct Bins {
   Layout lay;               // the layout in use
   int32_t *nst[2];          // stayed counts, by buffer
   int32_t *arr[2];          // arrival counts, by buffer
-  int32_t *ovf[2];          // [ns] overflow counts, by buffer
+  int32_t *ovf[2];          // [ns] overflow counts, by buffer; a species with a
+                            // nonzero count ran out of spare room and wants
+                            // its tile regions re-planned
   int64_t ovf_base[PIC_MAX_SPECIES];
   int32_t ovf_cap[PIC_MAX_SPECIES];
-  int32_t *flags;           // [0]: re-bucketing wanted (spare room ran out)
 };
 
 // Tile capacities after a re-bucketing of cnt particles: a stay zone with
@@ -110,12 +111,16 @@ struct StepParams {
   int32_t *err;
 };
 
-// Re-bucketing: every particle of the source (tile regions and overflow list,
-// or an unsorted range [0, n_src) after a load) is written to the stay zone of
-// its tile in the destination buffer, and the tile regions are re-planned.
+// Re-bucketing of the species in sel: every particle of the source (tile
+// regions and overflow list, or an unsorted range [0, n_src) after a load) is
+// written to the stay zone of its tile in the destination buffer, and the tile
+// regions are re-planned; the commit pass then makes the new layout and stay
+// counts those of the source buffer index (the host swaps the species' two
+// buffers), so species outside sel are not touched at all.
 struct SortParams {
   PBuf src[PIC_MAX_SPECIES];
   PBuf dst[PIC_MAX_SPECIES];
+  int32_t sel;              // bit s: species s is re-bucketed
   int64_t n_src[PIC_MAX_SPECIES];  // unsorted source: entries
   int32_t unsorted;         // bit s: species s is an unsorted range [0, n_src)
   Bins bins;                // bins.lay: the source layout
@@ -136,6 +141,10 @@ struct SortParams {
   // that fits the buffer
   const int32_t *inflow;
 };
+
+// Counters that many waves of one short launch add to are spread over this
+// many slots (by workgroup), so that the atomics do not queue on one address.
+constexpr int kCountSlots = 64;
 
 // Steps of a source's inflow that a re-bucketing leaves room for.
 constexpr int32_t kInflowSteps = 16;
@@ -198,7 +207,7 @@ struct InjParams {
   Geom geom;
   void *rho;
   int64_t *tally;
-  int64_t *injected;          // [ns]
+  int64_t *injected;          // [ns][kCountSlots]: the host adds the slots
   int32_t *err;
   PhotoParams pe;             // photoemission (photo_kernel)
 };
@@ -308,6 +317,7 @@ hipError_t launch_batch_flags(const BatchTable &t, int32_t *out, hipStream_t s);
 hipError_t launch_sort_count(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
+hipError_t launch_sort_commit(const SortParams &p, hipStream_t s);
 hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s);
 hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t s);
 hipError_t launch_photo(int repr, int deposit, const InjParams &p, hipStream_t s);

@@ -358,15 +358,14 @@ __device__ __forceinline__ void store_particle(const PBuf &B, int64_t q, const P
 }
 
 // Slot for a particle entering tile tn of the output buffer: its arrival zone,
-// else the overflow list (and re-bucketing is requested). -1 if even the
-// overflow list is full (the particle is lost; reported as an error).
+// else the overflow list (whose nonzero count requests a re-bucketing). -1 if
+// even the overflow list is full (the particle is lost; reported as an error).
 __device__ __forceinline__ int64_t arrival_slot(const Bins &B, int out, int s, int tn, int nt,
                                                 int32_t *err) {
   const int64_t i = (int64_t)s * nt + tn;
   const int32_t k = atomicAdd(&B.arr[out][i], 1);
   const int32_t cap = B.lay.cap[i], room = cap - B.lay.sz[i];
   if (k < room) return B.lay.base[i] + cap - 1 - k;
-  atomicOr(&B.flags[0], 1);
   const int32_t o = atomicAdd(&B.ovf[out][s], 1);
   if (o < B.ovf_cap[s]) return B.ovf_base[s] + o;
   atomicOr(err, kErrCapacity);
@@ -705,7 +704,6 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
         }
         if (!removed && slot == -1) {
           if (stay) {  // the stay zone is full
-            atomicOr(&P.bins.flags[0], 1);
             const int32_t o = atomicAdd(&P.bins.ovf[out][s], 1);
             if (o < P.bins.ovf_cap[s]) slot = P.bins.ovf_base[s] + o;
             else atomicOr(P.err, kErrCapacity);
@@ -813,7 +811,6 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
           if (k < room) {
             slot = P.bins.lay.base[j] + cap - 1 - k;
           } else {
-            atomicOr(&P.bins.flags[0], 1);
             const int32_t o = atomicAdd(&P.bins.ovf[out][s], 1);
             slot = o < P.bins.ovf_cap[s] ? P.bins.ovf_base[s] + o : -1;
             if (slot < 0) atomicOr(P.err, kErrCapacity);
@@ -911,12 +908,16 @@ __global__ void batch_clear_kernel(BatchTable B, int64_t elem_bytes) {
     r[i] = 0u;
 }
 
-// After a batched run: the re-bucketing flag of every slot of the table, for
-// one read-back by the host.
+// After a batched run: for every slot of the table, the species whose
+// overflow list in the current buffer is not empty (bit s), for one read-back
+// by the host.
 __global__ void batch_flags_kernel(BatchTable B, int32_t *out) {
   for (int k = threadIdx.x; k < B.nslots; k += blockDim.x) {
-    const int32_t *f = B.slots[k].bins.flags;
-    out[k] = f ? f[0] : 0;
+    const StepParams &P = B.slots[k];
+    int32_t m = 0;
+    for (int s = 0; s < P.ns; ++s)
+      if (P.bins.ovf[P.cur][s] > 0) m |= 1 << s;
+    out[k] = m;
   }
 }
 
@@ -1003,6 +1004,7 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void sort_count_kernel(SortParams P, int64_t chunk) {
   __shared__ int32_t sH[kNeighbours];
   const int s = blockIdx.y;
+  if (!((P.sel >> s) & 1)) return;  // uniform
   const int nt = P.ntiles;
   const SortSrc so = sort_src(P, s, blockIdx.x, chunk);
   if (!so.any) return;  // uniform
@@ -1039,6 +1041,7 @@ __global__ __launch_bounds__(kBlock) void sort_count_kernel(SortParams P, int64_
 __global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
   __shared__ long long sS[1024];
   const int s = blockIdx.x;
+  if (!((P.sel >> s) & 1)) return;  // uniform
   const int nt = P.ntiles;
   const int out = 1 - P.cur;
   const int per = (nt + 1023) / 1024;
@@ -1097,7 +1100,6 @@ __global__ __launch_bounds__(1024) void sort_scan_kernel(SortParams P) {
     if (sS[1023] > P.region_cap[s]) atomicOr(P.err, kErrCapacity);
     P.bins.ovf[out][s] = 0;
     if (flat) P.bins.ovf[P.cur][s] = 0;
-    if (s == 0) P.bins.flags[0] = 0;
   }
 }
 
@@ -1106,6 +1108,7 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int6
   __shared__ long long sBase[kNeighbours];
   __shared__ int32_t sCur[kNeighbours];
   const int s = blockIdx.y;
+  if (!((P.sel >> s) & 1)) return;  // uniform
   const int nt = P.ntiles;
   const SortSrc so = sort_src(P, s, blockIdx.x, chunk);
   if (!so.any) return;  // uniform
@@ -1161,6 +1164,21 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int6
   }
 }
 
+// After the scatter: the new layout and stay counts of every re-bucketed
+// species become those of the source buffer index, whose particle storage the
+// host swaps with the destination's. One thread per tile.
+__global__ void sort_commit_kernel(SortParams P) {
+  const int s = blockIdx.y;
+  if (!((P.sel >> s) & 1)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.ntiles) return;
+  const int64_t j = (int64_t)s * P.ntiles + i;
+  P.bins.lay.base[j] = P.dst_lay.base[j];
+  P.bins.lay.cap[j] = P.dst_lay.cap[j];
+  P.bins.lay.sz[j] = P.dst_lay.sz[j];
+  P.bins.nst[P.cur][j] = P.bins.nst[1 - P.cur][j];
+}
+
 // Sampled read-back: for every particle whose id is in the sorted list, write
 // its state (cell units, FP64) to the list slot. One workgroup per tile region
 // (and one for the overflow list).
@@ -1206,6 +1224,8 @@ __global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32
 // representation, the box and object tests of a pushed particle (collected at
 // once, or dropped if outside the box), appended to its tile's arrival zone
 // in the output buffer, deposited, counted. Every lane of the wave calls it.
+__device__ __forceinline__ int sp_slot() { return (int)(blockIdx.x & (kCountSlots - 1)); }
+
 template <int R, int D>
 __device__ __forceinline__ void emit_particle(const InjParams &P, bool has, int s, const double g[3],
                                               const double v[3]) {
@@ -1268,7 +1288,6 @@ __device__ __forceinline__ void emit_particle(const InjParams &P, bool has, int 
     if (kk < room) {
       slot = P.bins.lay.base[key] + cap - 1 - kk;
     } else {
-      atomicOr(&P.bins.flags[0], 1);
       const int32_t o = atomicAdd(&P.bins.ovf[P.out_idx][s], 1);
       if (o < P.bins.ovf_cap[s]) slot = P.bins.ovf_base[s] + o;
       else atomicOr(P.err, kErrCapacity);
@@ -1319,11 +1338,14 @@ __device__ __forceinline__ void emit_particle(const InjParams &P, bool has, int 
     pending &= ~m;
   }
 
-  // the injected counts: one atomic per wave and species
+  // the injected counts: one atomic per wave and species, on the workgroup's
+  // count slot
+  const int slot = sp_slot();
   for (int sp = 0; sp < P.ns; ++sp) {
     unsigned long long c = (inside && s == sp) ? 1ull : 0ull;
     for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
-    if (c && lane == 0) atomicAdd((unsigned long long *)&P.injected[sp], c);
+    if (c && lane == 0)
+      atomicAdd((unsigned long long *)&P.injected[sp * kCountSlots + slot], c);
   }
 }
 
@@ -1563,7 +1585,7 @@ constexpr int64_t kChunk = 4096;
 // unsorted ones (max_src: the largest unsorted range).
 int64_t sort_blocks(const SortParams &p, int64_t max_src) {
   const int64_t chunks = (max_src + kChunk - 1) / kChunk;
-  const int64_t binned = (p.unsorted != (1 << p.ns) - 1) ? (int64_t)p.ntiles + 1 : 0;
+  const int64_t binned = (p.sel & ~p.unsorted) ? (int64_t)p.ntiles + 1 : 0;
   return chunks > binned ? chunks : binned;
 }
 
@@ -1632,6 +1654,12 @@ hipError_t launch_sort_count(int repr, const SortParams &p, int64_t max_src, hip
 
 hipError_t launch_sort_scan(const SortParams &p, hipStream_t s) {
   hipLaunchKernelGGL(sort_scan_kernel, dim3(p.ns), dim3(1024), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_commit(const SortParams &p, hipStream_t s) {
+  if (p.ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sort_commit_kernel, dim3((p.ntiles + 255) / 256, p.ns), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

@@ -7,27 +7,35 @@ import synth
 
 
 class GpuRun:
-    def __init__(self, x, v, alive_ids, rho, rho_fixed, charge, counts, alive, absorbed, escaped):
+    def __init__(self, x, v, alive_ids, rho, rho_fixed, charge, counts, alive, absorbed, escaped,
+                 profile=None):
         self.x, self.v, self.alive_ids = x, v, alive_ids
         self.rho, self.rho_fixed = rho, rho_fixed
         self.charge, self.counts = charge, counts
         self.alive, self.absorbed, self.escaped = alive, absorbed, escaped
+        self.profile = profile
 
 
 def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interval=0,
-            order=None, device_load=False, split_steps=None, patches=0):
+            order=None, device_load=False, split_steps=None, patches=0, spare=1.0,
+            profile=False, sync_steps=False):
     """Runs nsteps on the GPU; particle ids are the indices into (sp, x, v).
-    Returns state of alive particles ordered by id."""
+    Returns state of alive particles ordered by id (and the launch profile if
+    profile). spare scales every species' capacity; sync_steps waits for each
+    step before the next, so the host sees each step's re-planning request."""
     import torch
 
     n = len(sp)
     ids = np.arange(n, dtype=np.int64)
     if order is not None:
         sp, x, v, ids = sp[order], x[order], v[order], ids[order]
+    cap = [max(1, int(spare * (sp == s).sum())) for s in range(len(w.species))]
     cfg = pam.config_from_workload(w, repr=repr, deposit=deposit, sort_interval=sort_interval,
-                                   capacity=[max(1, int((sp == s).sum())) for s in range(len(w.species))])
+                                   capacity=cap)
     cfg.patches = patches
     with pam.Context(cfg) as ctx:
+        if profile:
+            ctx.profile_enable(True)
         for s in range(len(w.species)):
             m = sp == s
             if device_load:
@@ -41,7 +49,11 @@ def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interva
             ctx.set_node_E([torch.tensor(e, dtype=torch.float32, device="cuda") for e in E])
         else:
             ctx.set_node_E([np.asarray(e, np.float64) for e in E])
-        if split_steps:
+        if sync_steps:
+            for _ in range(nsteps):
+                ctx.step(1)
+                ctx.synchronize()
+        elif split_steps:
             for k in split_steps:
                 ctx.step(k)
         else:
@@ -49,6 +61,7 @@ def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interva
         rho, rho_fixed = ctx.get_rho()
         charge, counts = ctx.get_surface_charge()
         alive, absorbed, escaped = ctx.get_counters()
+        prof = ctx.profile_read() if profile else None
         xs, vs, is_ = [], [], []
         for s in range(len(w.species)):
             px, pv, pid = ctx.get_particles(s)
@@ -58,7 +71,7 @@ def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interva
     pid = np.concatenate(is_)
     o = np.argsort(pid)
     return GpuRun(np.concatenate(xs)[o], np.concatenate(vs)[o], pid[o], rho, rho_fixed, charge,
-                  counts, alive, absorbed, escaped)
+                  counts, alive, absorbed, escaped, prof)
 
 
 def inputs(w):

@@ -1,0 +1,134 @@
+"""Tile re-planning per species, bit for bit against the oracle: a species
+whose tiles run out of spare room is re-bucketed alone while the others keep
+their buffers and layout, and so is a species loaded again in mid-run. The
+re-bucketing only changes where particles are stored, so every result equals
+the oracle's whatever is re-planned when."""
+import numpy as np
+import pytest
+
+import paper_2011_10214_amd as pam
+import synth
+from oracle import oracle
+
+from gpu_util import run_gpu
+from helpers import problem_of
+from test_parity_gpu import assert_bit_exact
+
+pytestmark = pytest.mark.gpu
+
+FORMS = ["fp64", "fp32_abs", "fp32_cell"]
+
+
+def workload():
+    sp = [synth.SpeciesSpec("electron", q=-1.0, m=1.0, vth=1.0, count=0),
+          synth.SpeciesSpec("ion", q=1.0, m=100.0, vth=0.1, count=0)]
+    return synth.Workload(name="replan_32x16x16", nx=32, ny=16, nz=16, species=sp, dt=0.05)
+
+
+def field(w, seed):
+    return np.random.default_rng(seed).uniform(-0.1, 0.1, size=(3, w.nodes))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_a_drifting_cluster_is_re_planned_alone(form):
+    # 4000 electrons packed in one tile drift +x at about half a cell per step:
+    # each step sends hundreds of them into a tile planned for 64 arrivals, so
+    # the electrons' tiles keep running out of room; 2000 slow ions spread over
+    # the box never do
+    w = workload()
+    rng = np.random.default_rng(11)
+    ne, ni = 4000, 2000
+    xe = rng.uniform(4.0, 8.0, size=(ne, 3))
+    ve = np.column_stack([10.0 + rng.normal(0, 0.5, ne), rng.normal(0, 0.5, ne),
+                          rng.normal(0, 0.5, ne)])
+    xi = rng.uniform(0.0, 1.0, size=(ni, 3)) * [w.nx, w.ny, w.nz]
+    vi = rng.normal(0, 0.1, size=(ni, 3))
+    sp = np.concatenate([np.zeros(ne, np.int32), np.ones(ni, np.int32)])
+    x, v = np.vstack([xe, xi]), np.vstack([ve, vi])
+    E = field(w, 12)
+    nsteps = 20
+    r = oracle.run(problem_of(w, form), sp, x, v, E, nsteps)
+    g = run_gpu(w, sp, x, v, E, nsteps, repr=form, spare=2.0, profile=True, sync_steps=True)
+    assert_bit_exact(w, sp, r, g)
+    # the load's re-plan, then one each time the cluster enters new tiles
+    assert g.profile.sort_launches >= 3
+    # queued without waiting, the steps see the requests late (the overflow
+    # list holds the particles meanwhile): the same results
+    g2 = run_gpu(w, sp, x, v, E, nsteps, repr=form, spare=2.0)
+    assert_bit_exact(w, sp, r, g2)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_a_species_loaded_again_is_re_planned_alone(form):
+    # electrons run 10 steps; the ions are replaced by a new set after 5. The
+    # electrons equal an electron-only oracle run of 10 steps, the new ions an
+    # ion-only run of 5, and the fixed-point rho (exact integer sums) the sum
+    # of the two runs' rho
+    w = workload()
+    rng = np.random.default_rng(21)
+    ne, ni = 3000, 1000
+    box = np.array([w.nx, w.ny, w.nz], np.float64)
+    xe = rng.uniform(0.0, 1.0, size=(ne, 3)) * box
+    ve = rng.normal(0, 1.0, size=(ne, 3))
+    xi0 = rng.uniform(0.0, 1.0, size=(ni, 3)) * box
+    vi0 = rng.normal(0, 0.1, size=(ni, 3))
+    xi1 = rng.uniform(0.0, 1.0, size=(ni, 3)) * box
+    vi1 = rng.normal(0, 0.1, size=(ni, 3))
+    E = field(w, 22)
+    ids_e = np.arange(ne, dtype=np.int64)
+    ids_i1 = np.arange(ni, dtype=np.int64) + 100000
+    cfg = pam.config_from_workload(w, repr=form, deposit="fixed64", capacity=[ne, ni])
+    with pam.Context(cfg) as ctx:
+        ctx.profile_enable(True)
+        ctx.load_particles(0, xe, ve, ids_e)
+        ctx.load_particles(1, xi0, vi0, np.arange(ni, dtype=np.int64) + 50000)
+        ctx.set_node_E([np.asarray(e, np.float64) for e in E])
+        ctx.step(5)
+        ctx.load_particles(1, xi1, vi1, ids_i1)
+        ctx.step(5)
+        _, rho_fixed = ctx.get_rho()
+        alive, _, escaped = ctx.get_counters()
+        ge = ctx.get_particles(0)
+        gi = ctx.get_particles(1)
+        prof = ctx.profile_read()
+    assert prof.sort_launches == 2  # the first loads', then the new ions'
+    prob = problem_of(w, form)
+    ra = oracle.run(prob, np.zeros(ne, np.int32), xe, ve, E, 10)
+    rb = oracle.run(prob, np.ones(ni, np.int32), xi1, vi1, E, 5)
+    for (px, pv, pid), r, base in ((ge, ra, 0), (gi, rb, 100000)):
+        o = np.argsort(pid)
+        keep = np.nonzero(r.fate == 0)[0]
+        assert np.array_equal(pid[o] - base, keep)
+        assert np.array_equal(px[o], r.x[keep])
+        assert np.array_equal(pv[o], r.v[keep])
+    assert np.array_equal(alive, [(ra.fate == 0).sum(), (rb.fate == 0).sum()])
+    assert np.array_equal(escaped[:, 0], ra.escaped[:, 0])
+    assert np.array_equal(escaped[:, 1], rb.escaped[:, 1])
+    assert np.array_equal(rho_fixed, ra.rho_fixed + rb.rho_fixed)
+
+
+def test_reloading_an_injected_species_restarts_its_counts():
+    # with injection on, a species loaded again counts from its new particles:
+    # its alive count equals the particles it holds, and so do the other's
+    w = workload()
+    rng = np.random.default_rng(31)
+    box = np.array([w.nx, w.ny, w.nz], np.float64)
+    n = 2000
+    xs = [rng.uniform(0.0, 1.0, size=(n, 3)) * box for _ in range(3)]
+    vs = [rng.normal(0, 1.0, size=(n, 3)) for _ in range(3)]
+    cfg = pam.config_from_workload(w, repr="fp32_cell", deposit="fixed64", capacity=[40000, 40000])
+    with pam.Context(cfg) as ctx:
+        ctx.load_particles(0, xs[0], vs[0], np.arange(n, dtype=np.int64))
+        ctx.load_particles(1, xs[1], 0.1 * vs[1], np.arange(n, dtype=np.int64))
+        ctx.set_node_E([np.zeros(w.nodes)] * 3)
+        ctx.set_injection(1 | 2 | 8 | 32, 5, [8.0, 8.0], [1.0, 0.1], [(0, 0, 0)] * 2)
+        ctx.step(6)
+        inj0 = ctx.get_injected()
+        assert inj0[0] > 0
+        ctx.load_particles(0, xs[2], vs[2], np.arange(n, dtype=np.int64) + 10 ** 6)
+        assert ctx.get_injected()[0] == 0
+        ctx.step(6)
+        alive, _, _ = ctx.get_counters()
+        for s in range(2):
+            assert alive[s] == len(ctx.get_particles(s)[2])
+        assert ctx.get_injected()[0] > 0
