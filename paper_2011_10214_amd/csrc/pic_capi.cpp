@@ -1107,7 +1107,7 @@ MgLevel make_level(int nx, int ny, int nz) {
   L.sx = nx + 1;
   L.sy = (int64_t)(nx + 1) * (ny + 1);
   L.nodes = L.sy * (nz + 1);
-  L.G = (int32_t)std::min<int64_t>(1024, (L.nodes + kBlock - 1) / kBlock);
+  L.G = field_groups(L.nodes);
   return L;
 }
 
@@ -1278,7 +1278,7 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   if (!c->deposited) return fail(c, PIC_E_STATE, "no deposit yet (call pic_step first)");
   const Dims &L = c->L;
   const int64_t nodes = L.nodes;
-  const int32_t G = (int32_t)std::min<int64_t>(1024, (nodes + kBlock - 1) / kBlock);
+  const int32_t G = field_groups(nodes);
   if (!c->fx) {
     void *q = nullptr;
     double **vecs[5] = {&c->fx, &c->fr, &c->fz, &c->fp, &c->fAp};
@@ -1286,7 +1286,7 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
       if (dmalloc(c, &q, nodes * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
       *v = (double *)q;
     }
-    if (dmalloc(c, &q, 6 * 1024 * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+    if (dmalloc(c, &q, 6 * kFieldGroups * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
     c->fpart = (double *)q;
     if (dmalloc(c, &q, sizeof(FieldCtrl)) != hipSuccess)
       return fail(c, PIC_E_NOMEM, "hipMalloc failed");

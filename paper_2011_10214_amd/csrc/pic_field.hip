@@ -52,6 +52,18 @@ __device__ __forceinline__ void f_ijk(const Gd &P, int64_t q, int &i, int &j, in
 
 // Visits the links of node (i, j, k) in the order -x, +x, -y, +y, -z, +z:
 // f(q, w) with q the neighbour's node index.
+// The same, f(q, w, i', j', k') with the neighbour's indices as well.
+template <class Gd, class F>
+__device__ __forceinline__ void f_links_n(const Gd &P, int i, int j, int k, int64_t q0, F f) {
+  const double cx = f_c(i, P.n[0]), cy = f_c(j, P.n[1]), cz = f_c(k, P.n[2]);
+  if (i > 0) f(q0 - 1, cy * cz, i - 1, j, k);
+  if (i < P.n[0]) f(q0 + 1, cy * cz, i + 1, j, k);
+  if (j > 0) f(q0 - P.sx, cx * cz, i, j - 1, k);
+  if (j < P.n[1]) f(q0 + P.sx, cx * cz, i, j + 1, k);
+  if (k > 0) f(q0 - P.sy, cx * cy, i, j, k - 1);
+  if (k < P.n[2]) f(q0 + P.sy, cx * cy, i, j, k + 1);
+}
+
 template <class Gd, class F>
 __device__ __forceinline__ void f_links(const Gd &P, int i, int j, int k, int64_t q0, F f) {
   const double cx = f_c(i, P.n[0]), cy = f_c(j, P.n[1]), cz = f_c(k, P.n[2]);
@@ -374,16 +386,16 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
     double a = 0.0;
     const double cq = IF ? L.cq[q] : 0.0;
     const bool uni = !IF || cq > 0.0;  // one permittivity on all six links
-    auto e1n = [&](int64_t nb) {
-      int a2, b2, c2;
-      f_ijk(L, nb, a2, b2, c2);
+    auto e1n = [&](int64_t nb, int a2, int b2, int c2) {
       return f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<IF>(L, a2, b2, c2, nb);
     };
     if (uni) {
-      f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (e1 - e1n(nb)); });
+      f_links_n(L, i, j, k, q, [&](int64_t nb, double w, int a2, int b2, int c2) {
+        a = a + w * (e1 - e1n(nb, a2, b2, c2));
+      });
     } else {
-      f_links(L, i, j, k, q, [&](int64_t nb, double w) {
-        a = a + (f_link_eps(L, P, q, nb) * w) * (e1 - e1n(nb));
+      f_links_n(L, i, j, k, q, [&](int64_t nb, double w, int a2, int b2, int c2) {
+        a = a + (f_link_eps(L, P, q, nb) * w) * (e1 - e1n(nb, a2, b2, c2));
       });
     }
     const double Ae1 = IF ? (uni ? cq * a : a * L.ih2) : L.s * a;

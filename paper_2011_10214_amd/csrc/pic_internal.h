@@ -17,6 +17,16 @@ constexpr int kReg = kTile + 2;
 constexpr int kRegN = kTile + 3;
 constexpr int kRegNodes = kRegN * kRegN * kRegN;
 constexpr int kBlock = 256;
+// Largest workgroup count of a field-solve kernel (each strides over its
+// grid's nodes; every consumer of a dot product adds this many partials)
+constexpr int kFieldGroups = 2048;
+
+// Workgroups of a field kernel over a grid of this many nodes: one node per
+// thread up to kFieldGroups.
+inline int32_t field_groups(int64_t nodes) {
+  const int64_t g = (nodes + kBlock - 1) / kBlock;
+  return (int32_t)(g < kFieldGroups ? g : kFieldGroups);
+}
 constexpr int kNeighbours = 27;
 constexpr int kCellBits = 10;  // packed cell: i | j << 10 | k << 20
 constexpr int32_t kDeadCell = -1;
