@@ -181,10 +181,15 @@ def serving_run(args):
     seq0 = serve(requests([0.0] * len(stream_w)), SequentialExecutor(budget))
     mu = seq0["throughput_req_per_s"]
     log(f"one at a time, all queued: {seq0['wall_s']:.1f} s, {mu:.2f} req/s")
+    # the same exponential draws for every load, scaled by 1 / rate
+    gaps = np.random.default_rng(4).exponential(1.0, len(stream_w))
+
+    def arrivals_at(rate):
+        a = np.cumsum(gaps / rate)
+        return a - a[0]
+
     rate = args.load * mu
-    rng = np.random.default_rng(4)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, len(stream_w)))
-    arrivals -= arrivals[0]
+    arrivals = arrivals_at(rate)
     seq = serve(requests(arrivals), SequentialExecutor(budget))
     log(f"one at a time, Poisson {rate:.2f} req/s: p50 {seq['latency_p50_s']:.2f} s, "
         f"p99 {seq['latency_p99_s']:.2f} s, mean {seq['latency_mean_s']:.2f} s")
@@ -206,9 +211,28 @@ def serving_run(args):
         batched[name] = st
         log(f"batched ({name}), Poisson {rate:.2f} req/s: p50 {st['latency_p50_s']:.2f} s, "
             f"p99 {st['latency_p99_s']:.2f} s, mean {st['latency_mean_s']:.2f} s")
+    # other loads: one at a time and the default batched policy
+    sweep = {}
+    for load in [float(x) for x in args.sweep.split(",") if x.strip()]:
+        r = load * mu
+        a = arrivals_at(r)
+        sq = serve(requests(a), SequentialExecutor(budget))
+        ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
+                           steps_per_run=args.steps_per_run, hbm_budget_bytes=budget,
+                           particle_steps_per_run=int(args.ps_per_run), policy="head")
+        try:
+            bt = serve(requests(a), ex)
+        finally:
+            ex.close()
+        sweep[str(load)] = {"arrival_rate_req_per_s": r, "one_at_a_time": sq, "batched_head_half": bt}
+        for name, st in (("one at a time", sq), ("batched (head_half)", bt)):
+            log(f"load {load}: {name}, Poisson {r:.2f} req/s: p50 {st['latency_p50_s']:.2f} s, "
+                f"p99 {st['latency_p99_s']:.2f} s, mean {st['latency_mean_s']:.2f} s, "
+                f"wall {st['wall_s']:.1f} s")
     return {"requests": len(stream_w), "arrival_rate_req_per_s": rate, "load": args.load,
             "service_rate_one_at_a_time_req_per_s": mu, "slots": args.slots,
-            "hbm_budget_bytes": budget, "batched": batched, "one_at_a_time": seq}
+            "hbm_budget_bytes": budget, "batched": batched, "one_at_a_time": seq,
+            "load_sweep": sweep}
 
 
 PRECISION_FORMS = [("fp64", "fixed64"), ("fp64", "fp64"), ("fp32_abs", "fixed64"),
@@ -371,6 +395,9 @@ def main():
                     help="serving: particle-steps shared equally by the running requests "
                          "per batched run (0: every request gets --steps-per-run steps)")
     ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--sweep", default="0.5,1.0",
+                    help="--serve: further loads (comma-separated) run one at a time and "
+                         "with the default batched policy")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     args = ap.parse_args()
 
