@@ -1107,7 +1107,7 @@ MgLevel make_level(int nx, int ny, int nz) {
   L.sx = nx + 1;
   L.sy = (int64_t)(nx + 1) * (ny + 1);
   L.nodes = L.sy * (nz + 1);
-  L.G = field_groups(L.nodes);
+  L.G = (int32_t)((L.nodes + kBlock - 1) / kBlock);  // one node per thread (no dot products)
   return L;
 }
 

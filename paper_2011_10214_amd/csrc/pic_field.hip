@@ -14,8 +14,9 @@ namespace {
 // through the dual face of a link is eps w (phi_p - phi_q) h with w the
 // product of the two tangential half-width factors, 1/2 at a boundary index),
 // Dirichlet faces in a mask, zero-Neumann elsewhere; Jacobi-preconditioned
-// conjugate gradients. Every kernel runs G workgroups over the nodes; sums
-// are per-workgroup partials that every consumer adds in the same fixed
+// conjugate gradients. Every kernel strides over the nodes with its grid; a
+// kernel that forms a dot product runs the fine grid's G workgroups and
+// leaves per-workgroup partials that every consumer adds in the same fixed
 // order, so the solve is deterministic.
 
 // The grid helpers take the fine grid (FieldParams) or a multigrid level
@@ -156,7 +157,7 @@ template <int D, bool IF>
 __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
   double rz = 0.0, rr = 0.0, bb = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
-       q += (int64_t)P.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(P, q, i, j, k);
     if (f_dir(P, i, j, k)) {
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   double pap = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
-       q += (int64_t)P.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(P, q, i, j, k);
     if (f_dir(P, i, j, k)) continue;
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int
   const double alpha = sum_partials(P.part + (1 + o) * P.G, P.G) / sum_partials(P.part, P.G);
   double rz = 0.0, rr = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
-       q += (int64_t)P.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(P, q, i, j, k);
     if (f_dir(P, i, j, k)) continue;
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void field_dir_kernel(FieldParams P, int o)
   const double beta = sum_partials(P.part + (1 + n) * P.G, P.G) /
                       sum_partials(P.part + (1 + o) * P.G, P.G);
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
-       q += (int64_t)P.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(P, q, i, j, k);
     if (f_dir(P, i, j, k)) continue;
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)L.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
     if (f_dir(L, i, j, k)) {
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)L.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
     L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - f_Ax<IF>(P, L, L.e, i, j, k, q);
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int 
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
   for (int64_t Q = (int64_t)blockIdx.x * kBlock + threadIdx.x; Q < C.nodes;
-       Q += (int64_t)C.G * kBlock) {
+       Q += (int64_t)gridDim.x * kBlock) {
     int I, J, K;
     f_ijk(C, Q, I, J, K);
     if (f_dir(C, I, J, K)) {
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < F.nodes;
-       q += (int64_t)F.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(F, q, i, j, k);
     if (f_dir(F, i, j, k)) continue;
@@ -507,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, 
   double *out = to_e2 ? L.e2 : L.e;
   double rz = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)L.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
     if (f_dir(L, i, j, k)) {
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void field_psi_kernel(FieldParams P, int l)
   const MgLevel &L = P.lv[l];
   const FieldGeom &o = P.geo;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)L.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
     const double x = L.scale * i, y = L.scale * j, z = L.scale * k;
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void field_psi_kernel(FieldParams P, int l)
 __global__ __launch_bounds__(kBlock) void field_diag_kernel(FieldParams P, int l) {
   const MgLevel &L = P.lv[l];
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)L.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
     double d = 0.0;
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void surface_rho_kernel(SurfParams S) {
 __global__ __launch_bounds__(kBlock) void field_pstart_kernel(FieldParams P) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
-       q += (int64_t)P.G * kBlock)
+       q += (int64_t)gridDim.x * kBlock)
     P.p[q] = P.z[q];
 }
 
@@ -638,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void field_E_kernel(FieldParams P) {
   using T = typename RealOf<R>::T;
   using V4 = typename Vec4Of<T>::type;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
-       q += (int64_t)P.G * kBlock) {
+       q += (int64_t)gridDim.x * kBlock) {
     int ijk[3];
     f_ijk(P, q, ijk[0], ijk[1], ijk[2]);
     const int64_t st[3] = {1, P.sx, P.sy};
@@ -709,8 +710,8 @@ static void field_vcycle(const FieldParams &p, int prz, hipStream_t s) {
     hipLaunchKernelGGL(mg_prolong_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
     hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 1,
                        0);
-    if (l == 0)
-      hipLaunchKernelGGL((mg_sweep_kernel<true, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0,
+    if (l == 0)  // the r.z partials: the fine grid's workgroups
+      hipLaunchKernelGGL((mg_sweep_kernel<true, IF>), dim3(p.G), dim3(kBlock), 0, s, p, l, 0,
                          prz);
     else
       hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0,

@@ -241,7 +241,7 @@ struct MgLevel {
   int32_t mask;                // Dirichlet faces (homogeneous for corrections)
   double s;                    // eps / h_l^2
   double *e, *e2, *res, *rhs;  // correction (ping-pong), residual, right-hand side
-  int32_t G;                   // workgroups of the level's kernels
+  int32_t G;                   // workgroups of the level's kernels: one node per thread
   // object as an interface: level set and diagonal of A at the level's nodes;
   // cq: eps / h_l^2 of a node whose six links lie on its side of the
   // interface (all one permittivity), -1 for a node with a crossing link
@@ -273,7 +273,7 @@ struct FieldParams {
   double g[6];
   double tol;
   int32_t max_iter;
-  int32_t G;                // workgroups of every field kernel (partials per sum)
+  int32_t G;                // workgroups of the fine-grid kernels that form or use dot products (partials per sum)
   // multigrid preconditioner (levels >= 2: z = V-cycle(r)); 0 levels: Jacobi
   int32_t levels;
   MgLevel lv[kMaxLevels];
