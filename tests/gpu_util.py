@@ -18,11 +18,13 @@ class GpuRun:
 
 def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interval=0,
             order=None, device_load=False, split_steps=None, patches=0, spare=1.0,
-            profile=False, sync_steps=False):
+            profile=False, sync_steps=False, batch_steps_per_run=None):
     """Runs nsteps on the GPU; particle ids are the indices into (sp, x, v).
     Returns state of alive particles ordered by id (and the launch profile if
     profile). spare scales every species' capacity; sync_steps waits for each
-    step before the next, so the host sees each step's re-planning request."""
+    step before the next, so the host sees each step's re-planning request;
+    batch_steps_per_run runs the steps through a one-slot batch instead, in
+    runs of that many steps."""
     import torch
 
     n = len(sp)
@@ -49,7 +51,21 @@ def run_gpu(w, sp, x, v, E, nsteps, repr="fp64", deposit="fixed64", sort_interva
             ctx.set_node_E([torch.tensor(e, dtype=torch.float32, device="cuda") for e in E])
         else:
             ctx.set_node_E([np.asarray(e, np.float64) for e in E])
-        if sync_steps:
+        if batch_steps_per_run:
+            b = pam.Batch(1, repr, deposit, batch_steps_per_run, 64 << 30)
+            try:
+                slot = b.attach(ctx, nsteps)
+                done = []
+                for _ in range(nsteps + 1):
+                    b.launch()
+                    done += b.wait()
+                    if slot in done:
+                        break
+                assert slot in done
+                b.detach(slot)
+            finally:
+                b.close()
+        elif sync_steps:
             for _ in range(nsteps):
                 ctx.step(1)
                 ctx.synchronize()

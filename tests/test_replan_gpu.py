@@ -59,6 +59,30 @@ def test_a_drifting_cluster_is_re_planned_alone(form):
 
 
 @pytest.mark.parametrize("form", FORMS)
+def test_a_batched_run_re_plans_the_species_that_ask(form):
+    # the drifting cluster through the batched path in runs of 2 steps: the
+    # slot's requests are read back after each run and only the electrons
+    # re-planned before the next
+    w = workload()
+    rng = np.random.default_rng(13)
+    ne, ni = 4000, 2000
+    xe = rng.uniform(4.0, 8.0, size=(ne, 3))
+    ve = np.column_stack([10.0 + rng.normal(0, 0.5, ne), rng.normal(0, 0.5, ne),
+                          rng.normal(0, 0.5, ne)])
+    xi = rng.uniform(0.0, 1.0, size=(ni, 3)) * [w.nx, w.ny, w.nz]
+    vi = rng.normal(0, 0.1, size=(ni, 3))
+    sp = np.concatenate([np.zeros(ne, np.int32), np.ones(ni, np.int32)])
+    x, v = np.vstack([xe, xi]), np.vstack([ve, vi])
+    E = field(w, 14)
+    nsteps = 20
+    r = oracle.run(problem_of(w, form), sp, x, v, E, nsteps)
+    g = run_gpu(w, sp, x, v, E, nsteps, repr=form, spare=2.0, profile=True,
+                batch_steps_per_run=2)
+    assert_bit_exact(w, sp, r, g)
+    assert g.profile.sort_launches >= 3
+
+
+@pytest.mark.parametrize("form", FORMS)
 def test_a_species_loaded_again_is_re_planned_alone(form):
     # electrons run 10 steps; the ions are replaced by a new set after 5. The
     # electrons equal an electron-only oracle run of 10 steps, the new ions an
