@@ -186,7 +186,8 @@ void pic_destroy(pic_ctx *ctx);
  * through sorting and returned by pic_get_particles; without ids the particle
  * order is unspecified after a step. Every position must lie inside the box
  * (PIC_E_INVALID otherwise); n must not exceed the species capacity. Loading a
- * species resets its collected counts (tally column) and escape counters.
+ * species resets its collected counts (tally column), escape counters and
+ * injected count.
  * Values are rounded to the representation (round to nearest). Synchronous. */
 pic_status pic_load_particles(pic_ctx *ctx, int32_t species, int64_t n, const double *x,
                               const double *y, const double *z, const double *vx,
@@ -322,8 +323,8 @@ pic_status pic_get_field_levels(pic_ctx *ctx, int32_t *levels);
 pic_status pic_set_injection(pic_ctx *ctx, const pic_injection *inj);
 
 /* Synchronises; injected[s] (n_species values) receives the particles
- * injected into species s since pic_create (collected at once included;
- * photoelectrons count as injected into their species). */
+ * injected into species s since pic_create or its last load (collected at
+ * once included; photoelectrons count as injected into their species). */
 pic_status pic_get_injected(pic_ctx *ctx, int64_t *injected);
 
 /* Photoemission from the sunlit terrain (the lunar setup of §5.2.2, where
