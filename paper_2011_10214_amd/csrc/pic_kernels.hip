@@ -971,8 +971,10 @@ __device__ __forceinline__ int neighbour_tile(int rel, int tx, int ty, int tz, i
 }
 
 // The source entries of workgroup wg for species s: a chunk of an unsorted
-// range, or a tile's region (wg < ntiles; home tile wg) / the overflow list
-// (wg == ntiles). Returns false if the workgroup has no source.
+// range, or a tile's region (wg < ntiles; home tile wg) / a chunk of the
+// overflow list (wg >= ntiles: chunk wg - ntiles, so that a long list is
+// spread over many workgroups). o.any is false if the workgroup has no
+// source.
 struct SortSrc {
   Src r;
   int home;  // home tile, or -1
@@ -991,10 +993,17 @@ __device__ __forceinline__ SortSrc sort_src(const SortParams &P, int s, int wg, 
     o.r.n1 = (int32_t)(b - a);
     o.r.na = 0;
     o.r.gap = 0;
-  } else {
-    if (wg > P.ntiles) return o;
+  } else if (wg < P.ntiles) {
     o.r = src_of(P.bins, P.cur, s, wg, P.ntiles);
-    o.home = wg < P.ntiles ? wg : -1;
+    o.home = wg;
+  } else {
+    const Src all = src_of(P.bins, P.cur, s, P.ntiles, P.ntiles);
+    const int64_t a = (int64_t)(wg - P.ntiles) * chunk;
+    if (a >= all.n1) return o;
+    o.r.base = all.base + a;
+    o.r.n1 = (int32_t)(all.n1 - a < chunk ? all.n1 - a : chunk);
+    o.r.na = 0;
+    o.r.gap = 0;
   }
   o.any = true;
   return o;
@@ -1154,24 +1163,24 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int6
     if constexpr (R == PIC_REPR_FP32_CELL) Dd.cell[q] = S.cell[p];
     if (ids) Dd.ids[q] = S.ids[p];
   }
-  // the source counters are consumed (the source buffer is the next output)
-  if (!((P.unsorted >> s) & 1)) {
+  // the source counters are consumed (the source buffer is the next output;
+  // the overflow count, which every overflow chunk reads, in the commit pass)
+  if (t >= 0 && !((P.unsorted >> s) & 1)) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-      if (t >= 0) P.bins.arr[P.cur][(int64_t)s * nt + t] = 0;
-      else P.bins.ovf[P.cur][s] = 0;
-    }
+    if (threadIdx.x == 0) P.bins.arr[P.cur][(int64_t)s * nt + t] = 0;
   }
 }
 
 // After the scatter: the new layout and stay counts of every re-bucketed
 // species become those of the source buffer index, whose particle storage the
-// host swaps with the destination's. One thread per tile.
+// host swaps with the destination's, and its overflow list is empty. One
+// thread per tile.
 __global__ void sort_commit_kernel(SortParams P) {
   const int s = blockIdx.y;
   if (!((P.sel >> s) & 1)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P.ntiles) return;
+  if (i == 0) P.bins.ovf[P.cur][s] = 0;
   const int64_t j = (int64_t)s * P.ntiles + i;
   P.bins.lay.base[j] = P.dst_lay.base[j];
   P.bins.lay.cap[j] = P.dst_lay.cap[j];
@@ -1581,12 +1590,17 @@ hipError_t launch_step_r(int deposit, bool push, const StepParams &p, hipStream_
 
 constexpr int64_t kChunk = 4096;
 
-// Workgroups per species: tiles + overflow list for binned species, chunks for
-// unsorted ones (max_src: the largest unsorted range).
+// Workgroups per species: tiles + chunks of the overflow list (as many as its
+// capacity takes) for binned species, chunks for unsorted ones (max_src: the
+// largest unsorted range).
 int64_t sort_blocks(const SortParams &p, int64_t max_src) {
-  const int64_t chunks = (max_src + kChunk - 1) / kChunk;
-  const int64_t binned = (p.sel & ~p.unsorted) ? (int64_t)p.ntiles + 1 : 0;
-  return chunks > binned ? chunks : binned;
+  int64_t n = (max_src + kChunk - 1) / kChunk;
+  for (int s = 0; s < p.ns; ++s) {
+    if (!(((p.sel & ~p.unsorted) >> s) & 1)) continue;
+    const int64_t b = (int64_t)p.ntiles + (p.bins.ovf_cap[s] + kChunk - 1) / kChunk;
+    if (b > n) n = b;
+  }
+  return n;
 }
 
 }  // namespace

@@ -29,15 +29,16 @@ def field(w, seed):
     return np.random.default_rng(seed).uniform(-0.1, 0.1, size=(3, w.nodes))
 
 
-@pytest.mark.parametrize("form", FORMS)
-def test_a_drifting_cluster_is_re_planned_alone(form):
-    # 4000 electrons packed in one tile drift +x at about half a cell per step:
-    # each step sends hundreds of them into a tile planned for 64 arrivals, so
-    # the electrons' tiles keep running out of room; 2000 slow ions spread over
-    # the box never do
+@pytest.mark.parametrize("form,ne", [(f, 4000) for f in FORMS] + [("fp32_cell", 40000)])
+def test_a_drifting_cluster_is_re_planned_alone(form, ne):
+    # ne electrons packed in one tile drift +x at about half a cell per step:
+    # each step sends an eighth of them into a tile planned for 64 arrivals, so
+    # the electrons' tiles keep running out of room (with 40000, over 4096 a
+    # step: an overflow list of several re-bucketing chunks); 2000 slow ions
+    # spread over the box never do
     w = workload()
     rng = np.random.default_rng(11)
-    ne, ni = 4000, 2000
+    ni = 2000
     xe = rng.uniform(4.0, 8.0, size=(ne, 3))
     ve = np.column_stack([10.0 + rng.normal(0, 0.5, ne), rng.normal(0, 0.5, ne),
                           rng.normal(0, 0.5, ne)])
@@ -48,13 +49,16 @@ def test_a_drifting_cluster_is_re_planned_alone(form):
     E = field(w, 12)
     nsteps = 20
     r = oracle.run(problem_of(w, form), sp, x, v, E, nsteps)
-    g = run_gpu(w, sp, x, v, E, nsteps, repr=form, spare=2.0, profile=True, sync_steps=True)
+    # queued without waiting (below), the overflow list may hold a cluster's
+    # arrivals of many steps: room for them with the large cluster
+    spare = 2.0 if ne <= 4000 else 100.0
+    g = run_gpu(w, sp, x, v, E, nsteps, repr=form, spare=spare, profile=True, sync_steps=True)
     assert_bit_exact(w, sp, r, g)
     # the load's re-plan, then one each time the cluster enters new tiles
     assert g.profile.sort_launches >= 3
     # queued without waiting, the steps see the requests late (the overflow
     # list holds the particles meanwhile): the same results
-    g2 = run_gpu(w, sp, x, v, E, nsteps, repr=form, spare=2.0)
+    g2 = run_gpu(w, sp, x, v, E, nsteps, repr=form, spare=spare)
     assert_bit_exact(w, sp, r, g2)
 
 
