@@ -564,9 +564,11 @@ pic_status do_sort(pic_ctx *c, int32_t want) {
   return PIC_OK;
 }
 
+// Before a step: rho, and the overflow counts of the buffer the step writes.
 pic_status clear_rho(pic_ctx *c) {
   const int pe = prof_begin(c, 2);
-  PIC_HIP(c, launch_fill(c->rho, c->L.nodes * rho_elem(c->cfg.deposit), c->stream));
+  PIC_HIP(c, launch_step_clear(c->rho, c->L.nodes * rho_elem(c->cfg.deposit), c->ovf[1 - c->cur],
+                               c->L.ns, c->stream));
   prof_end(c, pe);
   return PIC_OK;
 }
@@ -2062,7 +2064,7 @@ pic_status pic_batch_launch(pic_batch *b) {
       pic_ctx *c = b->ctx[order[i]];
       b->h_slots[i] = step_params(c);
       b->h_slots[i].remaining = b->quota[order[i]];
-      total += c->L.ntiles + 1;
+      total += c->L.ntiles + kOvfGroups;
     } else {
       b->h_slots[i] = StepParams{};
     }

@@ -152,6 +152,10 @@ struct SortParams {
   const int32_t *inflow;
 };
 
+// Step-kernel workgroups that share the overflow list (after the tiles'),
+// each a contiguous part of it
+constexpr int kOvfGroups = 32;
+
 // Counters that many waves of one short launch add to are spread over this
 // many slots (by workgroup), so that the atomics do not queue on one address.
 constexpr int kCountSlots = 64;
@@ -304,8 +308,8 @@ struct SurfParams {
 };
 
 // Batched runs: many contexts (slots) advanced by one launch per step. Work
-// item b belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles + 1
-// items per slot); persistent workgroups take items from a counter. The slot
+// item b belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles +
+// kOvfGroups items per slot); persistent workgroups take items from a counter. The slot
 // descriptors live in device memory so that a captured graph can replay steps
 // while the host changes the batch between replays.
 struct BatchTable {
@@ -329,6 +333,9 @@ hipError_t launch_sort_scan(const SortParams &p, hipStream_t s);
 hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, hipStream_t s);
 hipError_t launch_sort_commit(const SortParams &p, hipStream_t s);
 hipError_t launch_fill(void *ptr, int64_t bytes, hipStream_t s);
+// Zeroes rho (bytes) before a step and the overflow counts of the step's
+// output buffer (ns of them), which the step's overflow workgroups add to.
+hipError_t launch_step_clear(void *rho, int64_t bytes, int32_t *ovf_out, int32_t ns, hipStream_t s);
 hipError_t launch_inject(int repr, int deposit, const InjParams &p, hipStream_t s);
 hipError_t launch_photo(int repr, int deposit, const InjParams &p, hipStream_t s);
 // field solve: init (+ initial convergence check), one CG iteration (parity o:

@@ -423,7 +423,7 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
   __shared__ int32_t sRelRes[kNeighbours];
 
   const int nt = P.ntiles;
-  const bool ovf_block = block == nt;
+  const bool ovf_block = block >= nt;  // one of the kOvfGroups overflow workgroups
   // workgroups take tiles in the order of their regions in memory, so the
   // workgroups resident at any time stream one contiguous window of HBM
   const int t = block;
@@ -431,8 +431,16 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
   if (threadIdx.x == 0) {
     int total = 0;
     for (int s = 0; s < P.ns; ++s) {
-      sSrc[s] = src_of(P.bins, cur, s, t, nt);
-      total += sSrc[s].n1 + sSrc[s].na;
+      Src r = src_of(P.bins, cur, s, ovf_block ? nt : t, nt);
+      if (ovf_block) {  // part c of the list: [n c / K, n (c + 1) / K)
+        const int64_t c = block - nt;
+        const int32_t lo = (int32_t)((int64_t)r.n1 * c / kOvfGroups);
+        const int32_t hi = (int32_t)((int64_t)r.n1 * (c + 1) / kOvfGroups);
+        r.base += lo;
+        r.n1 = hi - lo;
+      }
+      sSrc[s] = r;
+      total += r.n1 + r.na;
     }
     sTotal = total;
   }
@@ -442,12 +450,11 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
     if (PUSH && !ovf_block && threadIdx.x < P.ns) P.bins.nst[out][(int64_t)threadIdx.x * nt + t] = 0;
     return;
   }
-  if (PUSH && threadIdx.x == 0) {
+  if (PUSH && !ovf_block && threadIdx.x == 0) {
     // the input counters are consumed: they count the next step's arrivals
-    for (int s = 0; s < P.ns; ++s) {
-      if (ovf_block) P.bins.ovf[cur][s] = 0;
-      else P.bins.arr[cur][(int64_t)s * nt + t] = 0;
-    }
+    // (the overflow count, which every overflow workgroup reads, is cleared
+    // before the next step instead)
+    for (int s = 0; s < P.ns; ++s) P.bins.arr[cur][(int64_t)s * nt + t] = 0;
   }
 
   const int nx = P.nx, ny = P.ny, nz = P.nz;
@@ -893,14 +900,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == PIC
   }
 }
 
-// Clears rho of every slot that will step (blockIdx.y = slot) and resets the
-// work counter of the step.
+// Clears rho and the output overflow counts of every slot that will step
+// (blockIdx.y = slot) and resets the work counter of the step.
 __global__ void batch_clear_kernel(BatchTable B, int64_t elem_bytes) {
   const int k = blockIdx.y;
   if (k == 0 && blockIdx.x == 0 && threadIdx.x == 0) *B.work = 0;
   if (k >= B.nslots) return;
   const StepParams &P = B.slots[k];
   if (P.remaining <= 0) return;
+  if (blockIdx.x == 0 && threadIdx.x < (unsigned)P.ns) P.bins.ovf[1 - P.cur][threadIdx.x] = 0;
   const int64_t n = (int64_t)(P.nx + 1) * (P.ny + 1) * (P.nz + 1) * elem_bytes / 4;
   uint32_t *r = (uint32_t *)P.rho;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -1570,11 +1578,11 @@ int grid_for(int64_t n, int block) {
 template <int R, int D>
 hipError_t launch_step_rd(bool push, const StepParams &p, hipStream_t s) {
   if (p.ntiles <= 0) return hipSuccess;
-  // one workgroup per tile plus one for the overflow list
+  // one workgroup per tile plus kOvfGroups for the overflow list
   if (push)
-    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles + 1), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles + kOvfGroups), dim3(kBlock), 0, s, p);
   else
-    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles + 1), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles + kOvfGroups), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
@@ -1691,6 +1699,22 @@ hipError_t launch_sort_scatter(int repr, const SortParams &p, int64_t max_src, h
     default:
       hipLaunchKernelGGL(sort_scatter_kernel<PIC_REPR_FP32_CELL>, grid, dim3(kBlock), 0, s, p, kChunk);
   }
+  return hipGetLastError();
+}
+
+// rho and the output overflow counts of a step cleared in one launch
+__global__ void step_clear_kernel(uint32_t *r, int64_t n, int32_t *ovf, int32_t ns) {
+  if (blockIdx.x == 0 && threadIdx.x < (unsigned)ns) ovf[threadIdx.x] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = 0u;
+}
+
+hipError_t launch_step_clear(void *rho, int64_t bytes, int32_t *ovf_out, int32_t ns,
+                             hipStream_t s) {
+  const int64_t n = bytes / 4;
+  hipLaunchKernelGGL(step_clear_kernel, dim3(grid_for(n > 0 ? n : 1, 256)), dim3(256), 0, s,
+                     (uint32_t *)rho, n, ovf_out, ns);
   return hipGetLastError();
 }
 
