@@ -406,6 +406,7 @@ int32_t ids_mask(pic_ctx *c) {
 StepParams step_params(pic_ctx *c) {
   StepParams P{};
   const Dims &L = c->L;
+  P.ovf_groups = ovf_groups_for(L.ntiles);
   for (int s = 0; s < L.ns; ++s) {
     P.buf[0][s] = c->sp[s].buf[0];
     P.buf[1][s] = c->sp[s].buf[1];
@@ -2064,7 +2065,7 @@ pic_status pic_batch_launch(pic_batch *b) {
       pic_ctx *c = b->ctx[order[i]];
       b->h_slots[i] = step_params(c);
       b->h_slots[i].remaining = b->quota[order[i]];
-      total += c->L.ntiles + kOvfGroups;
+      total += c->L.ntiles + b->h_slots[i].ovf_groups;
     } else {
       b->h_slots[i] = StepParams{};
     }

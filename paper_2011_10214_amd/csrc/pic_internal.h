@@ -103,6 +103,7 @@ struct StepParams {
   Bins bins;
   int32_t cur;                // buffer holding the state at the start of the step
   int32_t remaining;          // batched runs: steps left (the step is skipped at 0)
+  int32_t ovf_groups;         // workgroups that share the overflow list (ovf_groups_for)
   int32_t ns;
   int32_t nx, ny, nz;
   int32_t ntx, nty, ntz, ntiles;
@@ -153,8 +154,12 @@ struct SortParams {
 };
 
 // Step-kernel workgroups that share the overflow list (after the tiles'),
-// each a contiguous part of it
-constexpr int kOvfGroups = 32;
+// each a contiguous part of it: one per 1000 tiles, 1 to 32 (small grids,
+// which a batch runs by the dozen, keep a single one)
+inline int32_t ovf_groups_for(int32_t ntiles) {
+  const int32_t g = ntiles / 1000;
+  return g < 1 ? 1 : (g > 32 ? 32 : g);
+}
 
 // Counters that many waves of one short launch add to are spread over this
 // many slots (by workgroup), so that the atomics do not queue on one address.
@@ -309,7 +314,7 @@ struct SurfParams {
 
 // Batched runs: many contexts (slots) advanced by one launch per step. Work
 // item b belongs to slot k with prefix[k] <= b < prefix[k + 1] (ntiles +
-// kOvfGroups items per slot); persistent workgroups take items from a counter. The slot
+// ovf_groups items per slot); persistent workgroups take items from a counter. The slot
 // descriptors live in device memory so that a captured graph can replay steps
 // while the host changes the batch between replays.
 struct BatchTable {

@@ -423,7 +423,7 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
   __shared__ int32_t sRelRes[kNeighbours];
 
   const int nt = P.ntiles;
-  const bool ovf_block = block >= nt;  // one of the kOvfGroups overflow workgroups
+  const bool ovf_block = block >= nt;  // one of the P.ovf_groups overflow workgroups
   // workgroups take tiles in the order of their regions in memory, so the
   // workgroups resident at any time stream one contiguous window of HBM
   const int t = block;
@@ -434,8 +434,8 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
       Src r = src_of(P.bins, cur, s, ovf_block ? nt : t, nt);
       if (ovf_block) {  // part c of the list: [n c / K, n (c + 1) / K)
         const int64_t c = block - nt;
-        const int32_t lo = (int32_t)((int64_t)r.n1 * c / kOvfGroups);
-        const int32_t hi = (int32_t)((int64_t)r.n1 * (c + 1) / kOvfGroups);
+        const int32_t lo = (int32_t)((int64_t)r.n1 * c / P.ovf_groups);
+        const int32_t hi = (int32_t)((int64_t)r.n1 * (c + 1) / P.ovf_groups);
         r.base += lo;
         r.n1 = hi - lo;
       }
@@ -1578,11 +1578,11 @@ int grid_for(int64_t n, int block) {
 template <int R, int D>
 hipError_t launch_step_rd(bool push, const StepParams &p, hipStream_t s) {
   if (p.ntiles <= 0) return hipSuccess;
-  // one workgroup per tile plus kOvfGroups for the overflow list
+  // one workgroup per tile plus ovf_groups for the overflow list
   if (push)
-    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles + kOvfGroups), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles + p.ovf_groups), dim3(kBlock), 0, s, p);
   else
-    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles + kOvfGroups), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles + p.ovf_groups), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
