@@ -51,6 +51,7 @@ class _Cfg(ctypes.Structure):
         ("sphere_patches", ctypes.c_int32),
         ("pe_species", ctypes.c_int32), ("pe_seed", ctypes.c_uint64),
         ("pe_sun", ctypes.c_double * 3), ("pe_flux", ctypes.c_double), ("pe_vth", ctypes.c_double),
+        ("first_step", ctypes.c_int32),
     ]
 
 
@@ -166,6 +167,9 @@ class Problem:
     pe_sun: tuple = (1.0, 0.0, 1.0)
     pe_flux: float = 0.0
     pe_vth: float = 0.0
+    # index of the run's first step (the injection and photoemission draws are
+    # keyed by the step index): a run continued from step k
+    first_step: int = 0
 
     @property
     def n_species(self):
@@ -208,6 +212,7 @@ class Problem:
         c.pe_sun[:] = [float(a) for a in self.pe_sun]
         c.pe_flux = float(self.pe_flux)
         c.pe_vth = float(self.pe_vth)
+        c.first_step = int(self.first_step)
         for s in range(self.n_species):
             c.inj_density[s] = self.inj_density[s] if self.inj_density else 0.0
             c.inj_vth[s] = self.inj_vth[s] if self.inj_vth else 0.0

@@ -115,6 +115,9 @@ typedef struct {
   double pe_sun[3];        // direction towards the Sun (any length, z > 0)
   double pe_flux;          // emitted particles per unit area and time at normal incidence
   double pe_vth;           // thermal speed of the emitted half-Maxwellian
+  int32_t first_step;      // index of the run's first step: the random draws of injection
+                           // and photoemission are keyed by the step index, so a run
+                           // continued from step k draws what one long run draws there
 } orc_config;
 
 typedef struct {
@@ -781,8 +784,8 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
       B.when.push_back(bin >= 0 ? step : -1);
       if (bin >= 0) B.tally[(int64_t)bin * ns + s] += 1;
     };
-    inject_ghosts(cfg, M.n, step, add);
-    photo_emit(cfg, M.n, step, add);
+    inject_ghosts(cfg, M.n, cfg.first_step + step, add);
+    photo_emit(cfg, M.n, cfg.first_step + step, add);
   };
 
   auto deposit_all = [&]() {
@@ -971,8 +974,8 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
       B.when.push_back(bin >= 0 ? step : -1);
       if (bin >= 0) B.tally[(int64_t)bin * ns + s] += 1;
     };
-    inject_ghosts(cfg, M.n, step, add);
-    photo_emit(cfg, M.n, step, add);
+    inject_ghosts(cfg, M.n, cfg.first_step + step, add);
+    photo_emit(cfg, M.n, cfg.first_step + step, add);
   };
 
   auto deposit_all = [&]() {

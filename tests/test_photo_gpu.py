@@ -87,3 +87,79 @@ def test_photoemission_settings_are_checked():
     with pam.Context(pam.config_from_workload(s, capacity=[10, 10])) as ctx:
         with pytest.raises(pam.PicError):
             ctx.set_photoemission(0, 0, SUN, 1.0, 1.0)  # no terrain
+
+
+def test_closed_lunar_loop_follows_the_oracle():
+    # the benchmarked loop at a small size: ambient injection, the symmetry
+    # plane and photoemission, then after every step a field solve with the
+    # terrain as an interface and the collected charge as its surface source.
+    # The oracle runs step by step (each run continued from its step index)
+    # with its own field solve; the two solves agree to rounding, so positions
+    # are compared within 1e-9 and the counts exactly
+    w = lunar_with_photoelectrons()
+    nsteps, mask, tol, eps_in = 4, 32, 1e-12, 4.0
+    sp, x, v, _ = inputs(w)
+    dens, vth, drift = ambient(w)
+    dens[2] = 0.0
+    prob = problem_of(w, "fp64")
+    prob.reflect, prob.inj_faces, prob.inj_seed = LUNAR["reflect"], LUNAR["faces"], 11
+    prob.inj_density, prob.inj_vth, prob.inj_drift = dens, vth, drift
+    prob.pe_species, prob.pe_seed, prob.pe_sun, prob.pe_flux, prob.pe_vth = 2, 21, SUN, 30.0, PHOTO.vth
+    obj = oracle.field_object_of(prob, eps_in)
+    E = np.zeros((3, w.nodes))
+    ox, ov, osp, oid = x.copy(), v.copy(), sp.copy(), np.arange(len(sp))
+    tally = np.zeros((prob.nbins, 3), np.int64)
+    injected = np.zeros(3, np.int64)
+    for k in range(nsteps):
+        prob.first_step = k
+        r = oracle.run(prob, osp, ox, ov, E, 1)
+        tally += r.tally
+        injected += r.injected
+        ids = np.concatenate([oid, np.full(len(r.x) - len(oid), -1)])
+        alive = r.fate == 0
+        ox, ov, osp, oid = r.x[alive], r.v[alive], r.species[alive], ids[alive]
+        rho = (r.rho_fixed + oracle.surface_rho(prob, tally)) * 2.0 ** -32
+        phi, _, _ = oracle.field_solve(w.nx, w.ny, w.nz, rho, mask, tol=tol, max_iter=5000, obj=obj)
+        E = oracle.field_E(w.nx, w.ny, w.nz, phi, mask)
+    assert injected[2] > 100 and tally.sum() > 0
+
+    prob.first_step = 0
+    cfg = pam.config_from_workload(w, repr="fp64", deposit="fixed64",
+                                   capacity=[int((sp == s).sum()) + prob.injection_bound(nsteps)
+                                             for s in range(3)])
+    cfg.reflect = LUNAR["reflect"]
+    with pam.Context(cfg) as ctx:
+        for s in range(3):
+            m = sp == s
+            ctx.load_particles(s, x[m], v[m], np.arange(len(sp), dtype=np.int64)[m])
+        ctx.set_node_E([np.zeros(w.nodes)] * 3)
+        ctx.set_injection(LUNAR["faces"], 11, dens, vth, drift)
+        ctx.set_photoemission(2, 21, SUN, 30.0, PHOTO.vth)
+        for _ in range(nsteps):
+            ctx.step(1)
+            ctx.solve_field(mask, tol=tol, max_iter=5000, eps_object=eps_in, surface_charge=True)
+        gphi = ctx.get_phi()
+        counts = ctx.get_surface_charge()[1]
+        g_injected = ctx.get_injected()
+        parts = [ctx.get_particles(s) for s in range(3)]
+    assert np.array_equal(counts, tally)
+    assert np.array_equal(g_injected, injected)
+    for s in range(3):
+        gx, gv, gid = parts[s]
+        m = osp == s
+        assert len(gid) == int(m.sum())
+        # loaded particles by id
+        keep = gid >= 0
+        o = np.argsort(gid[keep])
+        want = np.nonzero(m & (oid >= 0))[0]
+        want = want[np.argsort(oid[want])]
+        assert np.array_equal(gid[keep][o], oid[want])
+        assert np.abs(gx[keep][o] - ox[want]).max(initial=0.0) < 1e-9
+        assert np.abs(gv[keep][o] - ov[want]).max(initial=0.0) < 1e-9
+        # injected and emitted particles as a set
+        gi = np.concatenate([gx[~keep], gv[~keep]], 1)
+        ri = np.concatenate([ox[m & (oid < 0)], ov[m & (oid < 0)]], 1)
+        assert len(gi) == len(ri)
+        gi, ri = gi[np.lexsort(gi.T[::-1])], ri[np.lexsort(ri.T[::-1])]
+        assert np.abs(gi - ri).max(initial=0.0) < 1e-9
+    assert np.abs(gphi - phi).max() < 1e-8 * np.abs(phi).max()
