@@ -114,38 +114,56 @@ def copy_ceiling(nbytes=4 << 30, reps=5):
 
 
 def cpu_baseline(w, target_s):
-    """The FP64 oracle, single-threaded, on a bounded sample of the workload."""
+    """The FP64 oracle on a bounded sample of the workload, timed twice: on one
+    thread, and on every host core (OpenMP: the particle updates in parallel,
+    the fixed-point rho per thread, summed in thread order; the same bits as
+    one thread). `value` and `cores` are the all-cores run's."""
     import numpy as np
 
     import synth
     from oracle import oracle
 
-    per = 1 << 19
-    sp, xs, vs = [], [], []
-    for s in range(len(w.species)):
-        if w.species[s].count == 0:
-            continue
-        a = synth.particles(w, s, 0, per)
-        sp.append(np.full(per, s, np.int32))
-        xs.append(np.stack(a[:3], 1).astype(np.float64))
-        vs.append(np.stack(a[3:], 1).astype(np.float64))
-    sp, x, v = np.concatenate(sp), np.concatenate(xs), np.concatenate(vs)
     E = synth.node_E(w)
     prob = oracle.Problem(nx=w.nx, ny=w.ny, nz=w.nz, dt=w.dt, q=[s.q for s in w.species],
                           m=[s.m for s in w.species], w=[s.w for s in w.species], obj=w.obj,
                           center=w.center, radius=w.radius, z_flat=w.z_flat,
                           rim_radius=w.rim_radius, depth=w.depth, repr="fp64", deposit="fixed64")
-    t0 = time.perf_counter()
-    oracle.run(prob, sp, x, v, E, 1)
-    one = time.perf_counter() - t0
-    steps = int(max(1, min(w.steps, target_s / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    r = oracle.run(prob, sp, x, v, E, steps)
-    dt = time.perf_counter() - t0
-    ps = int(np.where(r.fate == 0, steps, r.when + 1).sum())
-    return {"value": ps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first {per} particles of each species of {w.name}, {steps} steps, "
-                       f"FP64 oracle with fixed-point deposit, single thread, {dt:.1f} s"),
+
+    def sample(per):
+        sp, xs, vs = [], [], []
+        for s in range(len(w.species)):
+            if w.species[s].count == 0:
+                continue
+            a = synth.particles(w, s, 0, per)
+            sp.append(np.full(per, s, np.int32))
+            xs.append(np.stack(a[:3], 1).astype(np.float64))
+            vs.append(np.stack(a[3:], 1).astype(np.float64))
+        return np.concatenate(sp), np.concatenate(xs), np.concatenate(vs)
+
+    def timed(per, threads):
+        sp, x, v = sample(per)
+        pr = replace(prob, threads=threads)
+        t0 = time.perf_counter()
+        oracle.run(pr, sp, x, v, E, 1)
+        one = time.perf_counter() - t0
+        steps = int(max(1, min(w.steps, target_s / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        r = oracle.run(pr, sp, x, v, E, steps)
+        dt = time.perf_counter() - t0
+        ps = int(np.where(r.fate == 0, steps, r.when + 1).sum())
+        return ps / dt, steps, dt
+
+    cores = host_info()["logical_cpus"] or 1
+    v1, st1, t1 = timed(1 << 19, 1)
+    log(f"cpu baseline, one thread: {v1:.3e} particle-steps/s ({st1} steps, {t1:.1f} s)")
+    per_n = 1 << 19 if cores <= 1 else 1 << 21
+    vn, stn, tn = timed(per_n, cores)
+    log(f"cpu baseline, {cores} threads: {vn:.3e} particle-steps/s ({stn} steps, {tn:.1f} s)")
+    return {"value": vn, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"first {per_n} particles of each species of {w.name}, {stn} steps, FP64 "
+                       f"oracle with fixed-point deposit on {cores} threads, {tn:.1f} s; one "
+                       f"thread: first {1 << 19} per species, {st1} steps, {t1:.1f} s"),
+            "single_thread": {"value": v1, "cores": 1},
             "host": host_info()}
 
 
@@ -526,19 +544,37 @@ def main():
     alive0, _, _ = ctx.get_counters()
     injected0 = ctx.get_injected()
 
-    ctx.profile_enable(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # the K timed steps in 5 blocks (as equal as K allows), each bracketed by
+    # events on the library's stream and synchronised; value = all particle-
+    # steps / the summed block times, beside the median of the block rates
+    nblocks = min(5, args.steps)
+    sizes = [args.steps // nblocks + (1 if b < args.steps % nblocks else 0)
+             for b in range(nblocks)]
+    ms = 0.0
+    block_rates = []
+    tot = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    advance(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    for k in sizes:
+        ctx.profile_enable(True)  # (resets the totals)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        advance(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1)
+        p = ctx.profile_read()
+        ms += bms
+        block_rates.append(p.particle_steps / (bms / 1e3))
+        if tot is None:
+            tot = p
+        else:
+            for f in p.__dataclass_fields__:
+                setattr(tot, f, getattr(tot, f) + getattr(p, f))
     wall_ms = (time.perf_counter() - t0) * 1e3
     ctx.synchronize()
-    ms = e0.elapsed_time(e1)
-    prof = ctx.profile_read()
+    prof = tot
     alive1, absorbed, escaped = ctx.get_counters()
     injected = ctx.get_injected()
     log(f"timed {args.steps} steps: {ms:.2f} ms (host wall {wall_ms:.2f} ms); step kernel {prof.step_ms / max(1, prof.step_launches):.3f} ms avg, "
@@ -578,6 +614,12 @@ def main():
             "particles_alive_start": int(alive0.sum()),
             "particles_alive_end": int(alive1.sum()),
             "timed_wall_ms": wall_ms,
+            "timed_blocks": sizes,
+        },
+        "median_of_blocks": {
+            "value": float(np.median(block_rates)),
+            "unit": "particle-steps/s",
+            "block_values": block_rates,
         },
         "roofline": {
             "bound": "hbm",

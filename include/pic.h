@@ -49,8 +49,11 @@
  *     pic_get_* calls synchronise the stream and report device-side errors
  *     (PIC_E_RANGE: a non-finite or runaway particle position) raised since
  *     the last synchronising call.
- *   - The library owns all device memory it allocates (hipMalloc) and frees it
- *     in pic_destroy.
+ *   - The library owns all device memory of a context and frees it in
+ *     pic_destroy. It takes that memory from pic_config.alloc when the caller
+ *     gives an allocator (for instance a framework's caching allocator, so
+ *     that the context's tens of GB are not held beside the framework's pool),
+ *     else from hipMalloc.
  */
 #ifndef PIC_H_
 #define PIC_H_
@@ -144,6 +147,19 @@ typedef struct {
                                         reserved for this many plus per-tile spare
                                         room and an overflow list, double-buffered) */
   void *stream;          /* hipStream_t to enqueue on, or NULL for a library stream */
+  /* Device memory allocator (optional; all three NULL: hipMalloc / hipFree).
+   * alloc(bytes, alloc_user) returns device memory of the context's GPU with
+   * at least 256-byte alignment, or NULL when it cannot (the calling
+   * pic_* function then fails with PIC_E_NOMEM and nothing changes);
+   * dealloc(ptr, alloc_user) takes back a pointer that alloc returned. The
+   * library calls them from the calling thread, only inside pic_create,
+   * pic_load_particles* (id arrays), pic_set_photoemission, pic_solve_field,
+   * pic_get_particles_by_id and pic_destroy, and gives back every
+   * allocation by the end of pic_destroy (after synchronising the context's
+   * stream). alloc and dealloc are given together or not at all. */
+  void *(*alloc)(size_t bytes, void *user);
+  void (*dealloc)(void *ptr, void *user);
+  void *alloc_user;
 } pic_config;
 
 /* Ambient particles injected through box faces every step (the particle
@@ -158,7 +174,7 @@ typedef struct {
  * the object test like a pushed particle (collected at once, or kept and
  * deposited). Random numbers: SplitMix64 as a counter-based generator keyed by
  * (seed, step index, species, face, face cell, ghost); the step index counts
- * pic_step steps from pic_create. Only correctly rounded operations are used
+ * pic_step steps from pic_create, or from the value pic_set_step_index set. Only correctly rounded operations are used
  * (ln by an atanh series), so the injected particles are fully determined by
  * the inputs. Ghosts faster than u.n_in + 6 vth toward the face are not
  * generated (a relative flux deficit below 1e-9). Injected particles take the
@@ -184,7 +200,9 @@ void pic_destroy(pic_ctx *ctx);
  * (x, y, z) with velocities (vx, vy, vz) taken at t - dt/2 (the leapfrog
  * stagger). Host arrays of n doubles. ids (nullable) are n int64 labels carried
  * through sorting and returned by pic_get_particles; without ids the particle
- * order is unspecified after a step. Every position must lie inside the box
+ * order is unspecified after a step. Every position must lie inside the box,
+ * also after rounding to the representation (an FP32 coordinate that rounds
+ * up to the upper face is outside)
  * (PIC_E_INVALID otherwise); n must not exceed the species capacity. Loading a
  * species resets its collected counts (tally column), escape counters and
  * injected count.
@@ -326,6 +344,14 @@ pic_status pic_set_injection(pic_ctx *ctx, const pic_injection *inj);
  * injected into species s since pic_create or its last load (collected at
  * once included; photoelectrons count as injected into their species). */
 pic_status pic_get_injected(pic_ctx *ctx, int64_t *injected);
+
+/* Sets the step index of the next pic_step (0 <= step < 2^31; it counts on by
+ * one per step). The random draws of the injection and of the photoemission
+ * are keyed by it, so a run exported after k steps (pic_get_particles, tallies)
+ * and loaded into a fresh context continues the draws of one long run when
+ * the new context is set to k; a fresh context starts at 0. Takes effect for
+ * steps enqueued after the call. PIC_E_INVALID: out of range. */
+pic_status pic_set_step_index(pic_ctx *ctx, int64_t step);
 
 /* Photoemission from the sunlit terrain (the lunar setup of §5.2.2, where
  * photoelectrons are generated according to the local sunlight index, the

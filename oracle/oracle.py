@@ -25,7 +25,10 @@ DEPOSIT = {"fixed64": 0, "fp32": 1, "fp64": 2}
 OBJECT = {"none": 0, "sphere": 1, "crater": 2}
 
 # -ffp-contract=off: no multiply-add is fused unless written as fma.
-CFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+# -fopenmp: the particle updates and the fixed-point deposit on several
+# threads when Problem.threads > 1 (bit-identical to one thread).
+CFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+          "-shared"]
 
 
 def build() -> str:
@@ -52,6 +55,7 @@ class _Cfg(ctypes.Structure):
         ("pe_species", ctypes.c_int32), ("pe_seed", ctypes.c_uint64),
         ("pe_sun", ctypes.c_double * 3), ("pe_flux", ctypes.c_double), ("pe_vth", ctypes.c_double),
         ("first_step", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
     ]
 
 
@@ -170,6 +174,9 @@ class Problem:
     # index of the run's first step (the injection and photoemission draws are
     # keyed by the step index): a run continued from step k
     first_step: int = 0
+    # OpenMP threads of the particle updates and the fixed-point deposit (the
+    # results are bit-identical to one thread's)
+    threads: int = 1
 
     @property
     def n_species(self):
@@ -213,6 +220,7 @@ class Problem:
         c.pe_flux = float(self.pe_flux)
         c.pe_vth = float(self.pe_vth)
         c.first_step = int(self.first_step)
+        c.threads = int(self.threads)
         for s in range(self.n_species):
             c.inj_density[s] = self.inj_density[s] if self.inj_density else 0.0
             c.inj_vth[s] = self.inj_vth[s] if self.inj_vth else 0.0

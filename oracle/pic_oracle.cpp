@@ -1,5 +1,6 @@
-// PIC particle-mesh oracle: a plain, slow, single-threaded CPU implementation
-// of one explicit PIC step (gather -> push -> boundary/object -> deposit).
+// PIC particle-mesh oracle: a plain, slow CPU implementation of one explicit
+// PIC step (gather -> push -> boundary/object -> deposit). It runs on one
+// thread unless orc_config.threads asks for more (below).
 //
 // THIS FILE IS TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the
 // CPU-baseline leg of the benchmark load it. The GPU library never links,
@@ -70,6 +71,17 @@
 // mirrors (absolute positions; int32 cell + float offset). The same expression
 // order is used in every form. Build with -ffp-contract=off so that no
 // multiply-add is fused unless written as fma.
+//
+// Threads (orc_config.threads > 1, OpenMP): the particles' updates of one
+// step are independent of each other (each reads the fixed node field and its
+// own state), so steps 1-7 run for the particles in parallel, the removal
+// counters being integer sums; the fixed-point deposit sums each thread's
+// particles into its own int64 rho, and the threads' arrays are added in
+// thread order. Integer addition is associative, so every result is the same
+// bit for bit as on one thread. The injection and the FP32 / FP64 summing
+// deposits (whose rounding depends on the order) stay on one thread.
+
+#include <omp.h>
 
 #include <cmath>
 #include <cstdint>
@@ -118,6 +130,8 @@ typedef struct {
   int32_t first_step;      // index of the run's first step: the random draws of injection
                            // and photoemission are keyed by the step index, so a run
                            // continued from step k draws what one long run draws there
+  int32_t threads;         // OpenMP threads for the particle updates and the
+                           // fixed-point deposit (0 or 1: one thread)
 } orc_config;
 
 typedef struct {
@@ -630,7 +644,7 @@ void photo_emit(const orc_config& cfg, const int32_t n[3], int32_t step, Emit em
   }
 }
 
-// Mirror about a reflecting face; absolute positions (cell units).// Mirror about a reflecting face; absolute positions (cell units).
+// Mirror about a reflecting face; absolute positions (cell units).
 template <class T>
 void reflect_abs(const orc_config& cfg, const int32_t n[3], T g[3], T u[3]) {
   for (int d = 0; d < 3; ++d) {
@@ -686,16 +700,63 @@ struct RhoAcc {
   template <class T>
   void add(const int64_t idx[8], const T W[8], T chg) {
     if (mode == DEP_FIXED64) {
-      int64_t C[8];
-      fixed_contrib(chg, W, C);
-      for (int n = 0; n < 8; ++n) fixed[idx[n]] += C[n];
+      add_fixed(fixed.data(), idx, W, chg);
     } else if (mode == DEP_FP32) {
       for (int n = 0; n < 8; ++n) f32[idx[n]] += (float)(chg * W[n]);
     } else {
       for (int n = 0; n < 8; ++n) f64[idx[n]] += (double)(chg * W[n]);
     }
   }
+  template <class T>
+  static void add_fixed(int64_t* r, const int64_t idx[8], const T W[8], T chg) {
+    int64_t C[8];
+    fixed_contrib(chg, W, C);
+    for (int n = 0; n < 8; ++n) r[idx[n]] += C[n];
+  }
 };
+
+// Number of threads a run uses.
+int run_threads(const orc_config& cfg) { return cfg.threads > 1 ? cfg.threads : 1; }
+
+// The deposit of every alive particle (alive(p), contribution by
+// at(p, idx, W, chg)): in index order on one thread; with several threads
+// and the fixed-point mode, each thread's particles into its own int64 array
+// (part), the arrays added in thread order.
+template <class T, class Alive, class At>
+void deposit_particles(RhoAcc& rho, std::vector<std::vector<int64_t>>& part, int nthr,
+                       int64_t np, int64_t nodes, Alive alive, At at) {
+  rho.reset(nodes);
+  if (nthr <= 1 || rho.mode != DEP_FIXED64) {
+    for (int64_t p = 0; p < np; ++p) {
+      if (!alive(p)) continue;
+      int64_t idx[8];
+      T W[8], chg;
+      at(p, idx, W, &chg);
+      rho.add(idx, W, chg);
+    }
+    return;
+  }
+  part.resize(nthr);
+#pragma omp parallel num_threads(nthr)
+  {
+    std::vector<int64_t>& r = part[omp_get_thread_num()];
+    r.assign(nodes, 0);
+#pragma omp for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+      if (!alive(p)) continue;
+      int64_t idx[8];
+      T W[8], chg;
+      at(p, idx, W, &chg);
+      RhoAcc::add_fixed(r.data(), idx, W, chg);
+    }
+  }
+#pragma omp parallel for schedule(static) num_threads(nthr)
+  for (int64_t k = 0; k < nodes; ++k) {
+    int64_t a = 0;
+    for (int t = 0; t < nthr; ++t) a += part[t][k];
+    rho.fixed[k] = a;
+  }
+}
 
 // ---- particle state of each form -----------------------------------------------
 
@@ -788,27 +849,29 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
     photo_emit(cfg, M.n, cfg.first_step + step, add);
   };
 
+  const int nthr = run_threads(cfg);
+  std::vector<std::vector<int64_t>> part;
   auto deposit_all = [&]() {
-    rho.reset(nodes);
-    for (int64_t p = 0; p < (int64_t)spv.size(); ++p) {
-      if (B.fate[p] != 0) continue;
-      T g[3] = {P.g[0][p], P.g[1][p], P.g[2][p]};
-      int32_t i[3];
-      T f[3];
-      for (int d = 0; d < 3; ++d) {
-        i[d] = (int32_t)floor_t(g[d]);
-        f[d] = g[d] - (T)i[d];
-      }
-      T W[8];
-      weights(f, W);
-      int64_t idx[8];
-      corners(M, i, idx);
-      rho.add(idx, W, S[spv[p]].chg);
-    }
+    deposit_particles<T>(
+        rho, part, nthr, (int64_t)spv.size(), nodes, [&](int64_t p) { return B.fate[p] == 0; },
+        [&](int64_t p, int64_t* idx, T* W, T* chg) {
+          T g[3] = {P.g[0][p], P.g[1][p], P.g[2][p]};
+          int32_t i[3];
+          T f[3];
+          for (int d = 0; d < 3; ++d) {
+            i[d] = (int32_t)floor_t(g[d]);
+            f[d] = g[d] - (T)i[d];
+          }
+          weights(f, W);
+          corners(M, i, idx);
+          *chg = S[spv[p]].chg;
+        });
   };
 
   for (int32_t step = 0; step < nsteps; ++step) {
     const int64_t np = (int64_t)spv.size();
+    int bad = 0;
+#pragma omp parallel for schedule(static) num_threads(nthr) if (nthr > 1)
     for (int64_t p = 0; p < np; ++p) {
       if (B.fate[p] != 0) continue;
       const int s = spv[p];
@@ -829,7 +892,11 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
       for (int d = 0; d < 3; ++d) u[d] = fma_t(S[s].qmdt, Epart[d], u[d]);
       for (int d = 0; d < 3; ++d) g[d] = fma_t(u[d], dt, g[d]);
       const double gd[3] = {(double)g[0], (double)g[1], (double)g[2]};
-      if (!finite3(gd)) return ORC_E_RANGE;
+      if (!finite3(gd)) {
+#pragma omp atomic write
+        bad = 1;
+        continue;
+      }
       if (cfg.reflect) reflect_abs(cfg, M.n, g, u);
       for (int d = 0; d < 3; ++d) {
         P.g[d][p] = g[d];
@@ -840,6 +907,7 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
         B.fate[p] = 1;
         B.where[p] = face;
         B.when[p] = step;
+#pragma omp atomic
         B.escaped[face * ns + s] += 1;
         continue;
       }
@@ -848,9 +916,11 @@ int run_abs(const orc_config& cfg, int64_t n, const int32_t* sp, const double* c
         B.fate[p] = 2;
         B.where[p] = bin;
         B.when[p] = step;
+#pragma omp atomic
         B.tally[(int64_t)bin * ns + s] += 1;
       }
     }
+    if (bad) return ORC_E_RANGE;
     if (cfg.inj_faces || (crater && cfg.pe_species >= 0)) inject(step);
     deposit_all();
   }
@@ -978,22 +1048,24 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
     photo_emit(cfg, M.n, cfg.first_step + step, add);
   };
 
+  const int nthr = run_threads(cfg);
+  std::vector<std::vector<int64_t>> part;
   auto deposit_all = [&]() {
-    rho.reset(nodes);
-    for (int64_t p = 0; p < (int64_t)spv.size(); ++p) {
-      if (B.fate[p] != 0) continue;
-      const int32_t i[3] = {P.i[0][p], P.i[1][p], P.i[2][p]};
-      const T f[3] = {P.o[0][p], P.o[1][p], P.o[2][p]};
-      T W[8];
-      weights(f, W);
-      int64_t idx[8];
-      corners(M, i, idx);
-      rho.add(idx, W, S[spv[p]].chg);
-    }
+    deposit_particles<T>(
+        rho, part, nthr, (int64_t)spv.size(), nodes, [&](int64_t p) { return B.fate[p] == 0; },
+        [&](int64_t p, int64_t* idx, T* W, T* chg) {
+          const int32_t i[3] = {P.i[0][p], P.i[1][p], P.i[2][p]};
+          const T f[3] = {P.o[0][p], P.o[1][p], P.o[2][p]};
+          weights(f, W);
+          corners(M, i, idx);
+          *chg = S[spv[p]].chg;
+        });
   };
 
   for (int32_t step = 0; step < nsteps; ++step) {
     const int64_t np = (int64_t)spv.size();
+    int bad = 0;
+#pragma omp parallel for schedule(static) num_threads(nthr) if (nthr > 1)
     for (int64_t p = 0; p < np; ++p) {
       if (B.fate[p] != 0) continue;
       const int s = spv[p];
@@ -1007,18 +1079,24 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
       T Epart[3];
       gather(Ep, idx, W, Epart);
       for (int d = 0; d < 3; ++d) u[d] = fma_t(S[s].qmdt, Epart[d], u[d]);
-      for (int d = 0; d < 3; ++d) {
+      bool runaway = false;
+      for (int d = 0; d < 3 && !runaway; ++d) {
         T op = fma_t(u[d], dt, o[d]);
-        if (!std::isfinite(op)) return ORC_E_RANGE;
         T sh = floor_t(op);
         op = op - sh;
         if (op == 1.0f) {  // a tiny negative offset rounded up to 1 after the shift
           op = 0.0f;
           sh = sh + 1.0f;
         }
-        if (!(std::fabs(sh) <= 1048576.0f)) return ORC_E_RANGE;
+        // non-finite, or more than 2^20 cells in one step
+        runaway = !std::isfinite(op) || !(std::fabs(sh) <= 1048576.0f);
         o[d] = op;
-        i[d] += (int32_t)sh;
+        i[d] += runaway ? 0 : (int32_t)sh;
+      }
+      if (runaway) {
+#pragma omp atomic write
+        bad = 1;
+        continue;
       }
       if (cfg.reflect) reflect_cell(cfg, M.n, i, o, u);
       for (int d = 0; d < 3; ++d) {
@@ -1031,6 +1109,7 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
         B.fate[p] = 1;
         B.where[p] = face;
         B.when[p] = step;
+#pragma omp atomic
         B.escaped[face * ns + s] += 1;
         continue;
       }
@@ -1039,9 +1118,11 @@ int run_cell(const orc_config& cfg, int64_t n, const int32_t* sp, const double* 
         B.fate[p] = 2;
         B.where[p] = bin;
         B.when[p] = step;
+#pragma omp atomic
         B.tally[(int64_t)bin * ns + s] += 1;
       }
     }
+    if (bad) return ORC_E_RANGE;
     if (cfg.inj_faces || (crater && cfg.pe_species >= 0)) inject(step);
     deposit_all();
   }

@@ -102,6 +102,7 @@ const char *validate_config(const pic_config *c) {
     if (c->capacity[s] < 0 || c->capacity[s] > kMaxCapacity)
       return "capacity must be in 0..2^31-1025";
   }
+  if (!c->alloc != !c->dealloc) return "alloc and dealloc must be given together";
   if (c->repr < 0 || c->repr > 2) return "repr must be a pic_repr";
   if (c->deposit < 0 || c->deposit > 2) return "deposit must be a pic_deposit";
   if (c->sort_interval < 0 || c->sort_interval > 1000000) return "sort_interval must be 0..1e6";
@@ -277,8 +278,22 @@ void carve(PBuf &b, void *mem, int repr, int64_t cap) {
   b.ids = nullptr;
 }
 
+// Device memory of a context: from the caller's allocator when pic_config
+// gives one, else hipMalloc; returned the same way.
+void *dev_alloc(const pic_config &cf, int64_t bytes) {
+  if (cf.alloc) return cf.alloc((size_t)bytes, cf.alloc_user);
+  void *p = nullptr;
+  return hipMalloc(&p, (size_t)bytes) == hipSuccess ? p : nullptr;
+}
+
+void dev_free(const pic_config &cf, void *p) {
+  if (!p) return;
+  if (cf.dealloc) cf.dealloc(p, cf.alloc_user);
+  else (void)hipFree(p);
+}
+
 void free_all(pic_ctx *c) {
-  for (void *p : c->allocs) (void)hipFree(p);
+  for (void *p : c->allocs) dev_free(c->cfg, p);
   c->allocs.clear();
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   c->event_pool.clear();
@@ -293,12 +308,31 @@ void free_all(pic_ctx *c) {
   c->fctrl_host = nullptr;
 }
 
+// Allocation owned by the context until pic_destroy.
 hipError_t dmalloc(pic_ctx *c, void **p, int64_t bytes) {
-  *p = nullptr;
   if (bytes <= 0) bytes = 256;
-  hipError_t e = hipMalloc(p, (size_t)bytes);
-  if (e == hipSuccess) c->allocs.push_back(*p);
-  return e;
+  *p = dev_alloc(c->cfg, bytes);
+  if (!*p) return hipErrorOutOfMemory;
+  c->allocs.push_back(*p);
+  return hipSuccess;
+}
+
+// Allocates n buffers (owned by the context) or none: if one fails, those
+// made are given back and no *out is set.
+bool dmalloc_all(pic_ctx *c, int n, void **const *out, const int64_t *bytes) {
+  const size_t mark = c->allocs.size();
+  std::vector<void *> got((size_t)n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    if (dmalloc(c, &got[(size_t)i], bytes[i]) != hipSuccess) {
+      while (c->allocs.size() > mark) {
+        dev_free(c->cfg, c->allocs.back());
+        c->allocs.pop_back();
+      }
+      return false;
+    }
+  }
+  for (int i = 0; i < n; ++i) *out[i] = got[(size_t)i];
+  return true;
 }
 
 hipEvent_t take_event(pic_ctx *c) {
@@ -652,12 +686,10 @@ pic_status species_ranges(pic_ctx *c, int s, std::vector<std::pair<int64_t, int6
 pic_status ensure_ids(pic_ctx *c, int s) {
   pic_ctx::Species &S = c->sp[s];
   if (S.ids_mem[0]) return PIC_OK;
-  void *a = nullptr, *b = nullptr;
-  const int64_t bytes = align256(S.slots * 8);
-  if (dmalloc(c, &a, bytes) != hipSuccess) return fail(c, PIC_E_NOMEM, "no device memory for ids");
-  if (dmalloc(c, &b, bytes) != hipSuccess) return fail(c, PIC_E_NOMEM, "no device memory for ids");
-  S.ids_mem[0] = (int64_t *)a;
-  S.ids_mem[1] = (int64_t *)b;
+  const int64_t b = align256(S.slots * 8);
+  void **const outs[2] = {(void **)&S.ids_mem[0], (void **)&S.ids_mem[1]};
+  const int64_t bytes[2] = {b, b};
+  if (!dmalloc_all(c, 2, outs, bytes)) return fail(c, PIC_E_NOMEM, "no device memory for ids");
   S.buf[0].ids = S.ids_mem[0];
   S.buf[1].ids = S.ids_mem[1];
   return PIC_OK;
@@ -707,7 +739,9 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
     return fail(nullptr, PIC_E_DEVICE, "hipGetDevice failed");
   }
   size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)need > free_b) {
+  // (a caller's allocator may hold cached memory that hipMemGetInfo counts as
+  // used: it decides by itself)
+  if (!cfg->alloc && hipMemGetInfo(&free_b, &total_b) == hipSuccess && (size_t)need > free_b) {
     delete c;
     return fail(nullptr, PIC_E_NOMEM,
                 "footprint " + std::to_string(need) + " B exceeds free device memory");
@@ -758,7 +792,8 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
       {(void **)&c->hist, (int64_t)L.ns * L.ntiles * kNeighbours * 4},
   };
   for (Req &r : reqs) {
-    if (dmalloc(c, &p, r.bytes) != hipSuccess) return bail(PIC_E_NOMEM, "hipMalloc failed");
+    if (dmalloc(c, &p, r.bytes) != hipSuccess)
+      return bail(PIC_E_NOMEM, "device memory allocation failed");
     *r.dst = p;
     if (launch_fill(p, r.bytes > 0 ? r.bytes : 256, c->stream) != hipSuccess)
       return bail(PIC_E_DEVICE, "clearing a new buffer failed");
@@ -776,7 +811,7 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
     S.ovf_cap = overflow_slots(S.cap);
     for (int b = 0; b < 2; ++b) {
       if (dmalloc(c, &S.mem[b], species_buffer_bytes(cfg->repr, S.slots)) != hipSuccess)
-        return bail(PIC_E_NOMEM, "hipMalloc of particle buffers failed");
+        return bail(PIC_E_NOMEM, "allocation of the particle buffers failed");
       carve(S.buf[b], S.mem[b], cfg->repr, S.slots);
     }
   }
@@ -823,6 +858,8 @@ pic_status pic_load_particles(pic_ctx *c, int32_t species, int64_t n, const doub
         ((double *)pos.data())[d * n + p] = g;
         ((double *)vel.data())[d * n + p] = u;
       } else if (repr == PIC_REPR_FP32_ABS) {
+        if (!((float)g < (float)n3[d]))  // rounded up onto the upper face
+          return fail(c, PIC_E_INVALID, "particle " + std::to_string(p) + " is outside the box");
         ((float *)pos.data())[d * n + p] = (float)g;
         ((float *)vel.data())[d * n + p] = (float)u;
       } else {
@@ -1284,19 +1321,18 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   const int32_t G = field_groups(nodes);
   if (!c->fx) {
     void *q = nullptr;
-    double **vecs[5] = {&c->fx, &c->fr, &c->fz, &c->fp, &c->fAp};
-    for (double **v : vecs) {
-      if (dmalloc(c, &q, nodes * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-      *v = (double *)q;
+    if (!c->fctrl_host) {
+      if (hipHostMalloc(&q, sizeof(FieldCtrl), hipHostMallocDefault) != hipSuccess)
+        return fail(c, PIC_E_NOMEM, "hipHostMalloc failed");
+      c->fctrl_host = (FieldCtrl *)q;
     }
-    if (dmalloc(c, &q, 6 * kFieldGroups * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-    c->fpart = (double *)q;
-    if (dmalloc(c, &q, sizeof(FieldCtrl)) != hipSuccess)
-      return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-    c->fctrl = (FieldCtrl *)q;
-    if (hipHostMalloc(&q, sizeof(FieldCtrl), hipHostMallocDefault) != hipSuccess)
-      return fail(c, PIC_E_NOMEM, "hipHostMalloc failed");
-    c->fctrl_host = (FieldCtrl *)q;
+    void **const outs[7] = {(void **)&c->fx,    (void **)&c->fr, (void **)&c->fz,
+                            (void **)&c->fp,    (void **)&c->fAp, (void **)&c->fpart,
+                            (void **)&c->fctrl};
+    const int64_t bytes[7] = {nodes * 8, nodes * 8, nodes * 8, nodes * 8, nodes * 8,
+                              6 * kFieldGroups * 8, (int64_t)sizeof(FieldCtrl)};
+    if (!dmalloc_all(c, 7, outs, bytes))
+      return fail(c, PIC_E_NOMEM, "device memory allocation failed");
     PIC_HIP(c, launch_fill(c->fx, nodes * 8, c->stream));
   }
   // multigrid plan (once): level 0 is the PIC mesh; levels >= 2 when it coarsens
@@ -1315,23 +1351,24 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   const int32_t levels = use_mg ? c->mg_levels : 0;
   const int32_t nl = std::max(levels, 1);  // grids the solve uses
   if (use_mg && !c->mg_bufs) {
+    std::vector<void **> outs;
+    std::vector<int64_t> bytes;
     for (int l = 0; l < levels; ++l) {
-      void *q = nullptr;
       MgLevel &lv = c->mg[l];
-      const int64_t b = lv.nodes * 8;
       double **bufs[4] = {&lv.e, &lv.e2, &lv.res, &lv.rhs};
       for (int t = 0; t < 4; ++t) {
         if (l == 0 && (t == 0 || t == 3)) continue;  // level 0: e = z, rhs = r
-        if (dmalloc(c, &q, b) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-        *bufs[t] = (double *)q;
+        outs.push_back((void **)bufs[t]);
+        bytes.push_back(lv.nodes * 8);
       }
     }
-    void *q = nullptr;
     const int64_t cn = c->mg[levels - 1].nodes;
-    if (dmalloc(c, &q, cn * cn * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-    c->mg_ainv = (double *)q;
-    if (dmalloc(c, &q, cn * 4) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-    c->mg_umap = (int32_t *)q;
+    outs.push_back((void **)&c->mg_ainv);
+    bytes.push_back(cn * cn * 8);
+    outs.push_back((void **)&c->mg_umap);
+    bytes.push_back(cn * 4);
+    if (!dmalloc_all(c, (int)outs.size(), outs.data(), bytes.data()))
+      return fail(c, PIC_E_NOMEM, "device memory allocation failed");
     c->mg_bufs = true;
   }
   const bool iface = fs->eps_object > 0;
@@ -1339,16 +1376,12 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   if (iface) {
     for (int l = 0; l < nl; ++l) {
       if (c->mg[l].psi) continue;
-      void *q = nullptr;
-      if (dmalloc(c, &q, c->mg[l].nodes * 8) != hipSuccess)
-        return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-      c->mg[l].psi = (double *)q;
-      if (dmalloc(c, &q, c->mg[l].nodes * 8) != hipSuccess)
-        return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-      c->mg[l].diag = (double *)q;
-      if (dmalloc(c, &q, c->mg[l].nodes * 8) != hipSuccess)
-        return fail(c, PIC_E_NOMEM, "hipMalloc failed");
-      c->mg[l].cq = (double *)q;
+      void **const outs[3] = {(void **)&c->mg[l].psi, (void **)&c->mg[l].diag,
+                              (void **)&c->mg[l].cq};
+      const int64_t b = c->mg[l].nodes * 8;
+      const int64_t bytes[3] = {b, b, b};
+      if (!dmalloc_all(c, 3, outs, bytes))
+        return fail(c, PIC_E_NOMEM, "device memory allocation failed");
     }
   }
   if (levels >= 2) {
@@ -1433,7 +1466,8 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   if (fs->surface_charge) {
     if (!c->rho_surf) {
       void *q = nullptr;
-      if (dmalloc(c, &q, nodes * 8) != hipSuccess) return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+      if (dmalloc(c, &q, nodes * 8) != hipSuccess)
+        return fail(c, PIC_E_NOMEM, "device memory allocation failed");
       c->rho_surf = (int64_t *)q;
     }
     PIC_HIP(c, launch_fill(c->rho_surf, nodes * 8, c->stream));
@@ -1597,7 +1631,7 @@ pic_status pic_set_photoemission(pic_ctx *c, const pic_photoemission *pe) {
   if (!c->inflow) {
     void *q = nullptr;
     if (dmalloc(c, &q, (int64_t)inflow.size() * 4) != hipSuccess)
-      return fail(c, PIC_E_NOMEM, "hipMalloc failed");
+      return fail(c, PIC_E_NOMEM, "device memory allocation failed");
     c->inflow = (int32_t *)q;
   }
   PIC_HIP(c, hipStreamSynchronize(c->stream));  // no re-bucketing reads the old map
@@ -1613,6 +1647,13 @@ pic_status pic_get_injected(pic_ctx *c, int64_t *injected) {
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
   return read_injected(c, injected);
+}
+
+pic_status pic_set_step_index(pic_ctx *c, int64_t step) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (step < 0 || step > 0x7fffffffLL) return fail(c, PIC_E_INVALID, "step must be in 0..2^31-1");
+  c->step_index = step;
+  return PIC_OK;
 }
 
 pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *n_out, double *x,
@@ -1707,19 +1748,20 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
   if (st != PIC_OK) return st;
   if (n == 0) return PIC_OK;
   if (!c->sorted && (st = do_sort(c, 0)) != PIC_OK) return st;
-  void *d_ids = nullptr, *d_found = nullptr, *d_out = nullptr;
+  // staging of the id list and of the results, for this call only
+  void *d_ids = dev_alloc(c->cfg, n * 8), *d_found = dev_alloc(c->cfg, n * 4),
+       *d_out = dev_alloc(c->cfg, n * 6 * 8);
   auto cleanup = [&]() {
-    if (d_ids) (void)hipFree(d_ids);
-    if (d_found) (void)hipFree(d_found);
-    if (d_out) (void)hipFree(d_out);
+    dev_free(c->cfg, d_ids);
+    dev_free(c->cfg, d_found);
+    dev_free(c->cfg, d_out);
   };
-  if (hipMalloc(&d_ids, n * 8) != hipSuccess || hipMalloc(&d_found, n * 4) != hipSuccess ||
-      hipMalloc(&d_out, n * 6 * 8) != hipSuccess) {
+  if (!d_ids || !d_found || !d_out) {
     cleanup();
     return fail(c, PIC_E_NOMEM, "no device memory for the id search");
   }
   hipError_t e = hipMemcpy(d_ids, ids_sorted, n * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(d_found, 0, n * 4);
+  if (e == hipSuccess) e = launch_fill(d_found, n * 4, c->stream);
   if (e == hipSuccess)
     e = launch_find_ids(c->cfg.repr, S.buf[c->cur], bins_of(c), c->cur, species, c->L.ntiles,
                         (const int64_t *)d_ids, n, (int32_t *)d_found, (double *)d_out, c->stream);
@@ -1924,7 +1966,7 @@ pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
   if (hipMalloc(&b->d_slots, sizeof(StepParams) * n) != hipSuccess ||
       hipMalloc(&b->d_prefix, sizeof(int32_t) * (n + 1)) != hipSuccess ||
       hipMalloc(&b->d_ctrl, ctrl) != hipSuccess)
-    return bail(PIC_E_NOMEM, "hipMalloc failed");
+    return bail(PIC_E_NOMEM, "device memory allocation failed");
   if (hipHostMalloc((void **)&b->h_slots, sizeof(StepParams) * n, hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void **)&b->h_prefix, sizeof(int32_t) * (n + 1), hipHostMallocDefault) !=

@@ -1521,6 +1521,8 @@ __global__ void load_f32_kernel(LoadParams L) {
     for (int d = 0; d < 3; ++d) {
       g[d] = ((double)L.x[d][p] - L.origin[d]) / L.h;
       bad |= !(g[d] >= 0.0 && g[d] < (double)n3[d]);
+      // an FP32 coordinate just below the upper face may round up onto it
+      if constexpr (R == PIC_REPR_FP32_ABS) bad |= !((float)g[d] < (float)n3[d]);
       if constexpr (R == PIC_REPR_FP32_CELL) {
         int i = bad ? 0 : (int)__builtin_floor(g[d]);
         float oo = (float)(g[d] - (double)i);

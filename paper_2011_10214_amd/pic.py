@@ -35,13 +35,19 @@ class _Object(ctypes.Structure):
                 ("patches", ctypes.c_int32)]
 
 
+# pic_config.alloc / dealloc
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class _Config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("h", ctypes.c_double), ("origin", ctypes.c_double * 3), ("dt", ctypes.c_double),
                 ("n_species", ctypes.c_int32), ("species", _Species * MAX_SPECIES),
                 ("object", _Object), ("repr", ctypes.c_int32), ("deposit", ctypes.c_int32),
                 ("sort_interval", ctypes.c_int32), ("reflect", ctypes.c_int32),
-                ("capacity", ctypes.c_int64 * MAX_SPECIES), ("stream", ctypes.c_void_p)]
+                ("capacity", ctypes.c_int64 * MAX_SPECIES), ("stream", ctypes.c_void_p),
+                ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_user", ctypes.c_void_p)]
 
 
 class _Field(ctypes.Structure):
@@ -103,6 +109,7 @@ SIGNATURES = {
     "pic_get_field_levels": (_st, [_vp, ctypes.POINTER(_i32)]),
     "pic_get_node_E": (_st, [_vp, _vp, _vp, _vp]),
     "pic_get_injected": (_st, [_vp, _vp]),
+    "pic_set_step_index": (_st, [_vp, _i64]),
     "pic_set_photoemission": (_st, [_vp, ctypes.POINTER(_Photo)]),
     "pic_synchronize": (_st, [_vp]),
     "pic_get_rho": (_st, [_vp, _vp, _vp]),
@@ -185,6 +192,10 @@ class Config:
     sort_interval: int = 0
     reflect: int = 0                    # bit f: box face f (x-, x+, y-, y+, z-, z+) reflects
     stream: int = 0                     # hipStream_t handle (e.g. torch stream.cuda_stream)
+    # device memory of the context: None -> hipMalloc; "torch" -> torch's caching
+    # allocator; or an object with alloc(nbytes) -> int pointer (0 if it cannot)
+    # and free(ptr)
+    allocator: object = None
 
     @property
     def nodes(self) -> int:
@@ -215,6 +226,46 @@ class Config:
         return c
 
 
+class TorchAllocator:
+    """Device memory from torch's caching allocator, on the context's stream
+    (or torch's current stream), so that a context's buffers come out of the
+    same pool as the framework's tensors."""
+
+    def __init__(self, stream: int = 0):
+        self.stream = stream or None
+
+    def alloc(self, nbytes: int) -> int:
+        import torch
+
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=self.stream))
+        except (RuntimeError, MemoryError):  # torch raises when it is out of memory
+            return 0
+
+    def free(self, ptr: int):
+        import torch
+
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+
+def _hooks(allocator):
+    """ctypes callbacks for pic_config.alloc / dealloc around an allocator
+    object (kept alive by the caller for the context's lifetime)."""
+    def alloc(nbytes, _user):
+        try:
+            p = int(allocator.alloc(int(nbytes)))
+        except Exception:  # an exception must not cross into the library
+            return None
+        return p or None
+
+    def dealloc(ptr, _user):
+        try:
+            allocator.free(int(ptr))
+        except Exception:
+            pass
+    return ALLOC_FN(alloc), DEALLOC_FN(dealloc)
+
+
 def _ptr(a):
     """Data pointer of a numpy array or a torch tensor (None passes NULL)."""
     if a is None:
@@ -230,6 +281,32 @@ def _host(a, dtype):
 
 def _is_device(a) -> bool:
     return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _check_dev(tensors, dtype, n, what):
+    """Device tensors handed to the library as raw pointers: each must be a
+    contiguous tensor of the expected dtype and length on the current GPU
+    (the library reads exactly n elements from its data pointer)."""
+    import torch
+
+    for k, t in enumerate(tensors):
+        _check_shape(t, dtype, n, f"{what} {k}")
+    dev = torch.cuda.current_device()
+    for k, t in enumerate(tensors):
+        if t.device.index != dev:
+            raise ValueError(f"{what} {k}: the tensor is on device {t.device.index}, "
+                             f"not the current device {dev}")
+
+
+def _check_shape(t, dtype, n, what):
+    if not (hasattr(t, "is_cuda") and t.is_cuda):
+        raise ValueError(f"{what}: a CUDA tensor is required")
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: the tensor must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {n}")
 
 
 def _device_sync():
@@ -265,6 +342,14 @@ class Context:
     def __init__(self, cfg: Config):
         self.cfg = cfg
         self._c = cfg.cstruct()
+        self._hooks = None
+        if cfg.allocator is not None:
+            a = TorchAllocator(cfg.stream) if cfg.allocator == "torch" else cfg.allocator
+            # the callbacks live as long as the context: the library calls
+            # dealloc from pic_destroy
+            self._allocator = a
+            self._hooks = _hooks(a)
+            self._c.alloc, self._c.dealloc = self._hooks
         h = _vp()
         st = lib().pic_create(ctypes.byref(self._c), ctypes.byref(h))
         if st != OK:
@@ -299,12 +384,11 @@ class Context:
         """x, v: (n, 3) positions and half-step velocities. numpy (host, FP64)
         or float32 CUDA tensors (device) -- see pic_load_particles(_f32_dev)."""
         if _is_device(x):
-            _device_sync()
+            if x.dim() != 2 or x.shape[1] != 3 or tuple(v.shape) != tuple(x.shape):
+                raise ValueError("x and v must be (n, 3) tensors of the same shape")
             cols = [x[:, d].contiguous() for d in range(3)] + [v[:, d].contiguous() for d in range(3)]
             idt = ids.contiguous() if ids is not None else None
-            n = x.shape[0]
-            self._check(lib().pic_load_particles_f32_dev(self._h, species, n,
-                                                         *[_ptr(c) for c in cols], _ptr(idt)))
+            self.load_particles_cols(species, cols, idt)
             return
         x = _host(x, np.float64).reshape(-1, 3)
         v = _host(v, np.float64).reshape(-1, 3)
@@ -315,8 +399,18 @@ class Context:
                                              *[_ptr(c) for c in cols], _ptr(idh)))
 
     def load_particles_cols(self, species: int, cols, ids=None):
-        """cols: six float32 device tensors (x, y, z, vx, vy, vz) of equal length."""
-        n = int(cols[0].shape[0])
+        """cols: six float32 device tensors (x, y, z, vx, vy, vz) of equal length;
+        ids: None or an int64 device tensor of that length."""
+        import torch
+
+        if len(cols) != 6:
+            raise ValueError(f"{len(cols)} columns given, expected 6 (x, y, z, vx, vy, vz)")
+        n = int(cols[0].numel())
+        if ids is not None:
+            _check_shape(ids, torch.int64, n, "ids")
+        _check_dev(cols, torch.float32, n, "column")
+        if ids is not None:
+            _check_dev([ids], torch.int64, n, "ids")
         _device_sync()
         self._check(lib().pic_load_particles_f32_dev(self._h, species, n,
                                                      *[_ptr(c) for c in cols], _ptr(ids)))
@@ -324,8 +418,13 @@ class Context:
     def set_node_E(self, E):
         """E: three arrays of (nx+1)(ny+1)(nz+1) values, x fastest: numpy (host,
         FP64) or float32 CUDA tensors."""
+        if len(E) != 3:
+            raise ValueError("three field components are required")
         if _is_device(E[0]):
+            import torch
+
             Es = [e.contiguous() for e in E]
+            _check_dev(Es, torch.float32, self.cfg.nodes, "E component")
             _device_sync()
             self._check(lib().pic_set_node_E_f32_dev(self._h, *[_ptr(e) for e in Es]))
             return
@@ -337,6 +436,11 @@ class Context:
 
     def step(self, nsteps: int):
         self._check(lib().pic_step(self._h, int(nsteps)))
+
+    def set_step_index(self, step: int):
+        """Index of the next step (keys the injection and photoemission draws):
+        a run resumed from an export after k steps continues at k."""
+        self._check(lib().pic_set_step_index(self._h, int(step)))
 
     def set_injection(self, faces: int, seed: int = 0, density=None, vth=None, drift=None):
         """Ambient particles injected through the faces in the bit mask each

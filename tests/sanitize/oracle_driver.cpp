@@ -2,7 +2,8 @@
 // AddressSanitizer and UndefinedBehaviorSanitizer: the three representations
 // with a sphere (one bin and surface patches) and a crater, reflection,
 // injection and photoemission, the field solve with both preconditioners,
-// with and without the object as an interface, and the surface source.
+// with and without the object as an interface, and the surface source; runs on
+// one and on three threads.
 #include "../../oracle/pic_oracle.cpp"
 
 #include <cstdio>
@@ -94,6 +95,7 @@ int main() {
         c.pe_species = 2; c.pe_seed = 3; c.pe_flux = 30.0; c.pe_vth = 0.4;
         c.pe_sun[0] = 0.98; c.pe_sun[2] = 0.17;
       }
+      c.threads = (repr + obj) % 2 ? 3 : 1;  // the threaded updates and deposit too
       const int rc = run(c, 3000, 6, 11 + repr * 3 + obj);
       if (rc != 0) {
         std::printf("orc_run repr %d obj %d: %d\n", repr, obj, rc);

@@ -127,3 +127,90 @@ def test_binding_shares_one_hip_runtime_with_torch():
     out = subprocess.run([os.sys.executable, "-c", code], capture_output=True, text=True,
                          check=True, timeout=300).stdout.strip().splitlines()[-1]
     assert out == "1"
+
+
+def test_allocator_hooks_must_come_together():
+    c = _cfg().cstruct()
+    c.alloc = pic.ALLOC_FN(lambda n, u: None)
+    h = ctypes.c_void_p()
+    assert pam.lib().pic_create(ctypes.byref(c), ctypes.byref(h)) == pic.E_INVALID
+    assert b"together" in pam.lib().pic_last_error(None)
+
+
+class _FakeDev:
+    """Stands in for a CUDA tensor on a host without a GPU: the binding's
+    checks of device arguments run before anything reads the pointer."""
+
+    def __init__(self, n, dtype, contiguous=True):
+        import torch
+
+        self.is_cuda = True
+        self.dtype = dtype
+        self._n = n
+        self._contig = contiguous
+        self.device = torch.device("cuda", 0)
+        self.shape = (n,)
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._contig
+
+    def contiguous(self):
+        return self
+
+    def data_ptr(self):
+        raise AssertionError("the pointer must not be taken")
+
+
+class _NoCtx(pam.Context):
+    """A Context shell without a library context (argument checks only)."""
+
+    def __init__(self, cfg):
+        self.cfg = cfg
+        self.ns = len(cfg.species)
+        self._h = None
+
+
+@pytest.mark.parametrize("case", ["five_columns", "float64", "short", "non_contiguous",
+                                  "ids_int32", "ids_short", "host_tensor"])
+def test_device_columns_are_checked_before_the_call(case):
+    import torch
+
+    f32 = torch.float32
+    cols = [_FakeDev(10, f32) for _ in range(6)]
+    ids = None
+    if case == "five_columns":
+        cols = cols[:5]
+    elif case == "float64":
+        cols[3] = _FakeDev(10, torch.float64)
+    elif case == "short":
+        cols[5] = _FakeDev(9, f32)
+    elif case == "non_contiguous":
+        cols[1] = _FakeDev(10, f32, contiguous=False)
+    elif case == "ids_int32":
+        ids = _FakeDev(10, torch.int32)
+    elif case == "ids_short":
+        ids = _FakeDev(11, torch.int64)
+    elif case == "host_tensor":
+        cols[0] = torch.zeros(10, dtype=f32)
+    ctx = _NoCtx(_cfg())
+    with pytest.raises(ValueError):
+        ctx.load_particles_cols(0, cols, ids)
+
+
+@pytest.mark.parametrize("case", ["two_components", "short", "float64"])
+def test_device_field_is_checked_before_the_call(case):
+    import torch
+
+    cfg = _cfg()
+    E = [_FakeDev(cfg.nodes, torch.float32) for _ in range(3)]
+    if case == "two_components":
+        E = E[:2]
+    elif case == "short":
+        E[2] = _FakeDev(cfg.nodes - 1, torch.float32)
+    else:
+        E[0] = _FakeDev(cfg.nodes, torch.float64)
+    with pytest.raises(ValueError):
+        _NoCtx(cfg).set_node_E(E)

@@ -120,3 +120,36 @@ def test_sphere_touching_the_box(form):
     v = rng.normal(0, 1.0, (len(x), 3))
     r = check(w, sp, x, v, field(w, 11), 10, form)
     assert r.tally.sum() > 0 and r.escaped[0].sum() > 0
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_position_that_rounds_up_onto_the_upper_face_is_refused(device):
+    # x = 8 with the origin 1e-8 lies 1e-8 below the upper face of an 8-cell
+    # box: inside in FP64, but its FP32 coordinate rounds up to 8 (the face);
+    # the FP32 forms refuse it (absolute: rounded onto the face; cell-relative:
+    # the offset rounds up to 1 and the particle into cell 8), the FP64 form
+    # takes it
+    import torch
+
+    import paper_2011_10214_amd as pam
+
+    w = workload(8, 8, 8)
+    x = np.array([[8.0, 3.5, 3.5], [2.0, 8.0, 3.5], [2.0, 2.0, 8.0]])
+    v = np.zeros_like(x)
+    for form in FORMS:
+        cfg = pam.config_from_workload(w, repr=form, capacity=[4, 4])
+        cfg.origin = (1e-8, 1e-8, 1e-8)
+        with pam.Context(cfg) as ctx:
+            for k in range(3):
+                xs = x[k:k + 1]
+                if device:
+                    xs = torch.tensor(xs, dtype=torch.float32, device="cuda")
+                    vs = torch.zeros_like(xs)
+                else:
+                    vs = v[k:k + 1]
+                if form == "fp64":
+                    ctx.load_particles(0, xs, vs)
+                    continue
+                with pytest.raises(pam.PicError) as ei:
+                    ctx.load_particles(0, xs, vs)
+                assert ei.value.status == pam.pic.E_INVALID

@@ -124,3 +124,90 @@ def test_export_and_resume_is_bit_exact(form):
     assert np.array_equal(rho_got, rho_want)
     assert np.array_equal(counts_a + counts_b, counts_want) and counts_want.sum() > 0
     assert np.array_equal(esc_a + esc_b, esc_want)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_abs", "fp32_cell"])
+def test_resume_continues_the_injection_and_photoemission_draws(form):
+    # the lunar loop (symmetry plane, ambient injection, photoemission): a run
+    # exported after 5 steps and loaded into a fresh context set to step
+    # index 5 ends where one 10-step run of the oracle ends, bit for bit
+    from oracle import oracle
+
+    from helpers import problem_of
+    from test_boundaries_gpu import LUNAR, ambient
+    from test_photo_gpu import PHOTO, SUN, lunar_with_photoelectrons
+
+    w = lunar_with_photoelectrons()
+    half, ns = 5, 3
+    sp, x, v, E = inputs(w)
+    dens, vth, drift = ambient(w)
+    dens[2] = 0.0
+    prob = problem_of(w, form)
+    prob.reflect, prob.inj_faces, prob.inj_seed = LUNAR["reflect"], LUNAR["faces"], 11
+    prob.inj_density, prob.inj_vth, prob.inj_drift = dens, vth, drift
+    prob.pe_species, prob.pe_seed, prob.pe_sun, prob.pe_flux, prob.pe_vth = 2, 21, SUN, 30.0, PHOTO.vth
+    r = oracle.run(prob, sp, x, v, E, 2 * half)
+    extra = prob.injection_bound(2 * half)
+    cap = [int((sp == s).sum()) + extra for s in range(ns)]
+
+    def boundaries(ctx):
+        ctx.set_node_E([np.asarray(e, np.float64) for e in E])
+        ctx.set_injection(LUNAR["faces"], 11, dens, vth, drift)
+        ctx.set_photoemission(2, 21, SUN, 30.0, PHOTO.vth)
+
+    cfg = pam.config_from_workload(w, repr=form, deposit="fixed64", capacity=cap)
+    cfg.reflect = LUNAR["reflect"]
+    ids = np.arange(len(sp), dtype=np.int64)
+    with pam.Context(cfg) as first:
+        for s in range(ns):
+            m = sp == s
+            first.load_particles(s, x[m], v[m], ids[m])
+        boundaries(first)
+        first.step(half)
+        parts = [first.get_particles(s) for s in range(ns)]
+        counts_a = first.get_surface_charge()[1]
+        esc_a = first.get_counters()[2]
+        inj_a = first.get_injected()
+    with pam.Context(cfg) as second:
+        for s, (px, pv, pid) in enumerate(parts):
+            second.load_particles(s, px, pv, pid)
+        boundaries(second)
+        second.set_step_index(half)
+        second.step(half)
+        rho_fixed = second.get_rho()[1]
+        counts_b = second.get_surface_charge()[1]
+        esc_b = second.get_counters()[2]
+        inj_b = second.get_injected()
+        got = [second.get_particles(s) for s in range(ns)]
+    assert r.injected[2] > 100
+    assert np.array_equal(rho_fixed, r.rho_fixed)
+    assert np.array_equal(counts_a + counts_b, r.tally)
+    assert np.array_equal(esc_a + esc_b, r.escaped)
+    # the second context counts as injected only its own steps' particles
+    assert np.array_equal(inj_a + inj_b, r.injected)
+    n = len(sp)
+    for s in range(ns):
+        gx, gv, gid = got[s]
+        keep = gid >= 0
+        o = np.argsort(gid[keep])
+        want = np.nonzero((r.fate[:n] == 0) & (sp == s))[0]
+        assert np.array_equal(gid[keep][o], want)
+        assert np.array_equal(gx[keep][o], r.x[want]) and np.array_equal(gv[keep][o], r.v[want])
+        # injected and emitted particles (id -1) as a set
+        m = (r.fate == 0) & (r.species == s)
+        m[:n] = False
+        gi = np.concatenate([gx[~keep], gv[~keep]], 1)
+        ri = np.concatenate([r.x[m], r.v[m]], 1)
+        assert len(gi) == len(ri)
+        assert np.array_equal(gi[np.lexsort(gi.T[::-1])], ri[np.lexsort(ri.T[::-1])])
+
+
+def test_step_index_is_checked():
+    w = synth.sphere_16()
+    ctx, _ = loaded(w)
+    with ctx:
+        for bad in (-1, 2 ** 31):
+            with pytest.raises(pam.PicError) as ei:
+                ctx.set_step_index(bad)
+            assert ei.value.status == pam.pic.E_INVALID
+        ctx.set_step_index(7)

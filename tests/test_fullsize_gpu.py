@@ -1,8 +1,13 @@
 """Full-size runs in the launch configuration the benchmark times (FP32 cell
-form, int64 fixed-point deposit, re-bucketing every 4 steps), checked against
-the oracle on sampled particles (particles are independent under a fixed node
-field, so the oracle can run the sample alone) and against properties that hold
-at any size."""
+form, int64 fixed-point deposit), checked against the oracle on sampled
+particles (particles are independent under a fixed node field, so the oracle
+can run the sample alone): bit for bit against its FP32 cell-form mirror, and
+within the cross-precision bounds against its FP64 form (positions and
+velocities within 1e-5 relative; fates differ only within 1e-4 cells of a
+deciding surface, their number printed); and against properties that hold at
+any size."""
+import os
+
 import numpy as np
 import pytest
 
@@ -10,7 +15,7 @@ import paper_2011_10214_amd as pam
 import synth
 from oracle import oracle
 
-from helpers import problem_of
+from helpers import check_mismatches_near_surface, fate_mismatches, problem_of
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +35,20 @@ def _load_full(ctx, w):
         torch.cuda.empty_cache()
 
 
+def _threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+# sampled particles per species: 1/64 of sphere_64 (SURVEY's subsample for the
+# FP32 vs FP64 comparison at 64^3 over 100 steps), 2^18 of crater_160
+SAMPLED = {"sphere_64": lambda count: np.arange(0, count, 64),
+           "crater_160": None}
+
+
 @pytest.mark.parametrize("name", ["sphere_64", "crater_160"])
 def test_full_size_sampled_parity(name):
     import torch
@@ -37,9 +56,12 @@ def test_full_size_sampled_parity(name):
     w = synth.WORKLOADS[name]()
     print(f"[{name}] {w.n_particles} particles, {w.steps} steps", flush=True)
     E = synth.node_E(w)
-    cfg = pam.config_from_workload(w, repr="fp32_cell", deposit="fixed64", sort_interval=4)
+    cfg = pam.config_from_workload(w, repr="fp32_cell", deposit="fixed64")
     rng = np.random.default_rng(2011)
-    samples = [np.sort(rng.choice(s.count, SAMPLE, replace=False)) for s in w.species]
+    if SAMPLED[name] is not None:
+        samples = [SAMPLED[name](s.count) for s in w.species]
+    else:
+        samples = [np.sort(rng.choice(s.count, 1 << 18, replace=False)) for s in w.species]
     with pam.Context(cfg) as ctx:
         _load_full(ctx, w)
         ctx.set_node_E([torch.from_numpy(e).to("cuda") for e in E])
@@ -56,23 +78,63 @@ def test_full_size_sampled_parity(name):
     assert np.allclose(charge, counts @ chg, rtol=0, atol=0)
     assert np.all(alive > 0) and absorbed.sum() > 0
 
-    # the sample through the FP32 cell-form mirror of the oracle
-    sp = np.concatenate([np.full(SAMPLE, s, np.int32) for s in range(len(w.species))])
+    # the sample through the FP32 cell-form mirror of the oracle: bit for bit
+    sp = np.concatenate([np.full(len(samples[s]), s, np.int32) for s in range(len(w.species))])
     parts = [synth.particles(w, s, idx=samples[s]) for s in range(len(w.species))]
     x = np.concatenate([np.stack(p[:3], 1) for p in parts]).astype(np.float64)
     v = np.concatenate([np.stack(p[3:], 1) for p in parts]).astype(np.float64)
-    r = oracle.run(problem_of(w, "fp32_cell"), sp, x, v, E, w.steps)
+    thr = _threads()
+    mirror = problem_of(w, "fp32_cell")
+    mirror.threads = thr
+    r = oracle.run(mirror, sp, x, v, E, w.steps)
+    gx_all, gv_all, found_all = [], [], []
     for s in range(len(w.species)):
         found, gx, gv = got[s]
         sel = sp == s
         assert np.array_equal(found, r.fate[sel] == 0)
         assert np.array_equal(gx[found], r.x[sel][found])
         assert np.array_equal(gv[found], r.v[sel][found])
-    print(f"[{name}] sampled {len(sp)} particles bit-exact; alive {alive.tolist()}", flush=True)
+        gx_all.append(gx)
+        gv_all.append(gv)
+        found_all.append(found)
+    print(f"[{name}] sampled {len(sp)} particles bit-exact against the FP32 mirror; "
+          f"alive {alive.tolist()}", flush=True)
 
-    # rho of the sample alone, same launch configuration
-    cfg_s = pam.config_from_workload(w, repr="fp32_cell", deposit="fixed64", sort_interval=4,
-                                     capacity=[SAMPLE] * len(w.species))
+    # across precisions (R19): the FP32 GPU path against the FP64 oracle on the
+    # same sample. Positions within 1e-5 max(|x|, 1), velocities within
+    # 1e-5 max(|v|, vth) over particles alive in both; a particle whose fate
+    # differs must lie within 1e-4 cells of the deciding surface in the FP64
+    # run (the GPU's fates are the mirror's, equal by the check above)
+    ref = problem_of(w, "fp64")
+    ref.threads = thr
+    r64 = oracle.run(ref, sp, x, v, E, w.steps)
+    gx, gv, found = np.concatenate(gx_all), np.concatenate(gv_all), np.concatenate(found_all)
+    both = found & (r64.fate == 0)
+    vth = np.array([w.species[s].vth for s in sp])
+    dx = np.abs(gx[both] - r64.x[both])
+    dv = np.abs(gv[both] - r64.v[both])
+    xrel = (dx / np.maximum(np.abs(r64.x[both]), 1.0)).max()
+    vrel = (dv / np.maximum(np.abs(r64.v[both]), vth[both][:, None])).max()
+    mism = fate_mismatches(r.fate, r.where, r.when, r64.fate, r64.where, r64.when)
+    dist = check_mismatches_near_surface(w, sp, x, v, E, mism, r.when, r.fate, r64.when,
+                                         r64.fate)
+    print(f"[{name}] FP32 GPU vs FP64 oracle on {len(sp)} sampled particles, {w.steps} steps: "
+          f"max rel. error x {xrel:.2e}, v {vrel:.2e}; {len(mism)} fate differences "
+          f"(FP64 distance to the deciding surface at most "
+          f"{dist.max() if len(dist) else 0.0:.2e} cells)", flush=True)
+    assert xrel <= 1e-5 and vrel <= 1e-5
+    assert np.all(dist <= 1e-4)
+
+    # rho of a small sample alone, same launch configuration
+    small = [samples[s][:: max(1, len(samples[s]) // SAMPLE)][:SAMPLE]
+             for s in range(len(w.species))]
+    sp = np.concatenate([np.full(len(small[s]), s, np.int32) for s in range(len(w.species))])
+    parts = [synth.particles(w, s, idx=small[s]) for s in range(len(w.species))]
+    x = np.concatenate([np.stack(p[:3], 1) for p in parts]).astype(np.float64)
+    v = np.concatenate([np.stack(p[3:], 1) for p in parts]).astype(np.float64)
+    r = oracle.run(mirror, sp, x, v, E, w.steps)
+    cfg_s = pam.config_from_workload(w, repr="fp32_cell", deposit="fixed64",
+                                     capacity=[len(a) for a in small])
     with pam.Context(cfg_s) as ctx:
         for s in range(len(w.species)):
             ctx.load_particles(s, x[sp == s], v[sp == s])

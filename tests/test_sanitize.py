@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 def test_oracle_is_clean_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     exe = tmp_path / "oracle_driver"
     src = os.path.join(HERE, "sanitize", "oracle_driver.cpp")
-    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-ffp-contract=off",
+    subprocess.check_call(["g++", "-O1", "-g", "-std=c++17", "-ffp-contract=off", "-fopenmp",
                            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
                            "-static-libasan", "-static-libubsan", src, "-o", str(exe)])
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
