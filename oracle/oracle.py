@@ -113,12 +113,19 @@ def lib():
                                                              ctypes.c_int32, _dp, _dp, _dp,
                                                              ctypes.c_double, ctypes.c_int32,
                                                              ctypes.c_int32,
-                                                             ctypes.POINTER(_FieldObj), _i32p,
-                                                             _dp, _i32p]
+                                                             ctypes.POINTER(_FieldObj),
+                                                             ctypes.c_int32, _i32p, _dp, _i32p]
         L.orc_field_vcycle.restype = ctypes.c_int
         L.orc_field_vcycle.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_double,
                                                               ctypes.c_int32,
-                                                              ctypes.POINTER(_FieldObj), _dp, _dp]
+                                                              ctypes.POINTER(_FieldObj),
+                                                              ctypes.c_int32, _dp, _dp]
+        L.orc_ife_basis.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_ife_element.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.orc_cube_tets.argtypes = [ctypes.c_int32] * 3 + [_i32p]
+        L.orc_ife_links.restype = ctypes.c_int
+        L.orc_ife_links.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_double, ctypes.c_double,
+                                                           ctypes.POINTER(_FieldObj), _dp]
         L.orc_object_psi.restype = ctypes.c_double
         L.orc_object_psi.argtypes = [ctypes.POINTER(_FieldObj), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double]
@@ -450,13 +457,19 @@ def surface_rho(prob: "Problem", tally) -> np.ndarray:
     return out
 
 
+OPERATORS = {"fv": 0, "ife": 1}
+
+
 def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=None, tol=1e-10,
-                max_iter=10000, precond="multigrid", info=None, obj: FieldObject = None):
+                max_iter=10000, precond="multigrid", info=None, obj: FieldObject = None,
+                op="fv"):
     """Solves the field problem on the nodes (see the oracle source); returns
     (phi, iterations, relative residual). precond "multigrid" uses the V-cycle
     where the grid coarsens (else Jacobi); a dict passed as info gets the
     multigrid level count used ("levels", 0 for Jacobi); obj makes the object
-    an interface with permittivity obj.eps_in inside."""
+    an interface with permittivity obj.eps_in inside; op: "fv" node-centred
+    finite volumes, "ife" immersed finite elements on five tetrahedra per
+    cell."""
     nodes = (nx + 1) * (ny + 1) * (nz + 1)
     rho = _c(rho, np.float64).ravel()
     if rho.size != nodes:
@@ -470,8 +483,8 @@ def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=No
     rc = lib().orc_field_solve(nx, ny, nz, float(h), float(eps), int(dirichlet),
                                g.ctypes.data_as(_dp), rho.ctypes.data_as(_dp),
                                phi.ctypes.data_as(_dp), float(tol), int(max_iter),
-                               PRECONDITIONERS[precond], o, ctypes.byref(it), ctypes.byref(rr),
-                               ctypes.byref(lv))
+                               PRECONDITIONERS[precond], o, OPERATORS[op], ctypes.byref(it),
+                               ctypes.byref(rr), ctypes.byref(lv))
     if rc != 0:
         raise OracleError(f"oracle returned {rc}")
     if info is not None:
@@ -479,7 +492,7 @@ def field_solve(nx, ny, nz, rho, dirichlet, values=None, h=1.0, eps=1.0, phi0=No
     return phi, it.value, rr.value
 
 
-def field_vcycle(nx, ny, nz, r, dirichlet, h=1.0, eps=1.0, obj: FieldObject = None):
+def field_vcycle(nx, ny, nz, r, dirichlet, h=1.0, eps=1.0, obj: FieldObject = None, op="fv"):
     """One multigrid V-cycle z = B r (homogeneous Dirichlet faces); returns
     (z, levels), z None when the grid does not coarsen."""
     r = _c(r, np.float64).ravel()
@@ -488,10 +501,56 @@ def field_vcycle(nx, ny, nz, r, dirichlet, h=1.0, eps=1.0, obj: FieldObject = No
     z = np.zeros(r.size)
     o = ctypes.byref(obj.cstruct()) if obj is not None else None
     rc = lib().orc_field_vcycle(nx, ny, nz, float(h), float(eps), int(dirichlet), o,
-                                r.ctypes.data_as(_dp), z.ctypes.data_as(_dp))
+                                OPERATORS[op], r.ctypes.data_as(_dp), z.ctypes.data_as(_dp))
     if rc < 0:
         raise OracleError(f"oracle returned {rc}")
     return (z if rc > 0 else None), rc
+
+
+def ife_basis(X, psi, eps_in, eps) -> dict:
+    """The IFE basis of one tetrahedron (vertices X (4, 3), level set psi (4,)):
+    a (4, 3) grad phi- per basis function, t (4,), c (4, 4) with
+    phi- = sum_j c[i, j] lambda_j, g = grad psi_h, vol, vin (inside volume), cut."""
+    X = _c(X, np.float64).ravel()
+    p = _c(psi, np.float64)
+    out = np.zeros(38)
+    lib().orc_ife_basis(X.ctypes.data_as(_dp), p.ctypes.data_as(_dp), float(eps_in), float(eps),
+                        out.ctypes.data_as(_dp))
+    return dict(a=out[:12].reshape(4, 3), t=out[12:16].copy(), c=out[16:32].reshape(4, 4),
+                g=out[32:35].copy(), vol=out[35], vin=out[36],
+                cut=bool(out[37]))
+
+
+def ife_element(X, psi, eps_in, eps) -> np.ndarray:
+    X = _c(X, np.float64).ravel()
+    p = _c(psi, np.float64)
+    K = np.zeros(16)
+    lib().orc_ife_element(X.ctypes.data_as(_dp), p.ctypes.data_as(_dp), float(eps_in), float(eps),
+                          K.ctypes.data_as(_dp))
+    return K.reshape(4, 4)
+
+
+def cube_tets(i, j, k) -> np.ndarray:
+    """The five tetrahedra of cube (i, j, k): (5, 4, 3) corner offsets."""
+    out = np.zeros(60, np.int32)
+    lib().orc_cube_tets(int(i), int(j), int(k), out.ctypes.data_as(_i32p))
+    return out.reshape(5, 4, 3)
+
+
+# neighbour offsets of the IFE link table, in the oracle's order
+IFE_LINKS = [(-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1),
+             (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 1, 0), (-1, 0, -1), (1, 0, -1),
+             (-1, 0, 1), (1, 0, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1), (0, 1, 1)]
+
+
+def ife_links(nx, ny, nz, h=1.0, eps=1.0, obj: FieldObject = None) -> np.ndarray:
+    """The assembled IFE link coefficients (nodes, 18), c_pq = -A_pq."""
+    nodes = (nx + 1) * (ny + 1) * (nz + 1)
+    c = np.zeros(nodes * 18)
+    o = ctypes.byref(obj.cstruct()) if obj is not None else None
+    if lib().orc_ife_links(nx, ny, nz, float(h), float(eps), o, c.ctypes.data_as(_dp)) != 0:
+        raise OracleError("invalid arguments")
+    return c.reshape(nodes, 18)
 
 
 def field_E(nx, ny, nz, phi, dirichlet, h=1.0) -> np.ndarray:

@@ -1342,6 +1342,9 @@ struct FieldGrid {
   double g[6];
   double scale = 1.0;               // fine cells per cell of this grid
   const FieldObject* obj = nullptr;  // null: uniform eps
+  // immersed finite elements (level 0 only): link coefficients c_pq of the
+  // assembled operator, kIfeLinks per node (null: finite volumes)
+  const std::vector<double>* ife = nullptr;
   double psi(int i, int j, int k) const {
     return object_psi(*obj, scale * i, scale * j, scale * k);
   }
@@ -1372,9 +1375,26 @@ struct FieldGrid {
 
 // Visits the links of node (i, j, k): f(q, c) for each neighbour q in the box,
 // c the link's coefficient in A (eps_pq w / h^2).
+// Neighbours of a node in the five-tetrahedra mesh: the 6 axis neighbours,
+// then the 12 face diagonals (every edge of the mesh is one of these).
+constexpr int kIfeLinks = 18;
+constexpr int kIfeOff[kIfeLinks][3] = {
+    {-1, 0, 0},  {1, 0, 0},  {0, -1, 0}, {0, 1, 0},  {0, 0, -1}, {0, 0, 1},
+    {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 1, 0},  {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1},  {1, 0, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}, {0, 1, 1}};
+
 template <class F>
 void field_links(const FieldGrid& G, int i, int j, int k, F f) {
   const int64_t p = G.id(i, j, k);
+  if (G.ife) {
+    for (int l = 0; l < kIfeLinks; ++l) {
+      const int a = i + kIfeOff[l][0], b = j + kIfeOff[l][1], c = k + kIfeOff[l][2];
+      if (a < 0 || b < 0 || c < 0 || a > G.n[0] || b > G.n[1] || c > G.n[2]) continue;
+      const double cl = (*G.ife)[p * kIfeLinks + l];
+      if (cl != 0.0) f(G.id(a, b, c), cl);
+    }
+    return;
+  }
   const double wx = G.c(1, j) * G.c(2, k), wy = G.c(0, i) * G.c(2, k), wz = G.c(0, i) * G.c(1, j);
   if (i > 0) f(p - 1, G.coef(i, j, k, i - 1, j, k, wx));
   if (i < G.n[0]) f(p + 1, G.coef(i, j, k, i + 1, j, k, wx));
@@ -1386,6 +1406,241 @@ void field_links(const FieldGrid& G, int i, int j, int k, F f) {
 
 FieldGrid field_grid(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t mask,
                      const double g[6]);
+
+// ---- immersed finite elements ------------------------------------------------
+//
+// The paper's discretisation of the interface (§2.3; §3.1.1: each cubic PIC
+// cell is cut into five tetrahedra, and the IFE mesh is the PIC mesh). Away
+// from the interface the IFE space is the standard linear finite element
+// space on the tetrahedra; in a tetrahedron that the interface cuts, the basis
+// functions are linear on each side, continuous across the interface (eq.
+// (2.4)) and have a continuous flux eps d phi / dn across it (eq. (2.5) with
+// q = 0: the charge on the surface enters the right-hand side). The paper
+// gives the construction by reference only; this oracle takes:
+//   * tetrahedra: cube (i, j, k) of parity p = (i + j + k) mod 2 has the
+//     central tetrahedron on its four corners (a, b, c) with a + b + c = p
+//     mod 2 and one corner tetrahedron per other corner (that corner and its
+//     three axis neighbours), so that the face diagonals of neighbouring cubes
+//     coincide;
+//   * the interface in a tetrahedron: the zero set of the linear interpolant
+//     psi_h of the level set's values at its vertices (a plane); T- = {psi_h
+//     < 0} lies in the object (eps_in), T+ (psi_h >= 0) in the plasma (eps); a
+//     tetrahedron is cut when its vertices have psi < 0 and psi >= 0;
+//   * in a cut tetrahedron the basis function with vertex values v is
+//     phi- = sum_j c_j lambda_j (lambda: barycentric coordinates) on T- and
+//     phi+ = phi- + t psi_h on T+ (so phi+ = phi- on the interface), with t
+//     such that eps_in grad phi- . g = eps grad phi+ . g, g = grad psi_h:
+//     t = kappa (a . g), a = grad phi-, kappa = (eps_in - eps) / (eps |g|^2).
+//     The vertex values are v = c + d t, d_i = psi_i at the vertices outside
+//     and 0 inside; with w_j = grad lambda_j . g this is v = (I + kappa d w^T) c,
+//     so c = v - kappa d (w . v) / (1 + kappa w . d);
+//   * element matrix K_ij = eps_in |T-| a_i . a_j + eps |T+| b_i . b_j,
+//     b = a + t g, computed for i <= j and mirrored;
+//   * the operator is the assembled matrix over h^3 (the right-hand side is
+//     the nodal charge density, the deposit's charge per node over h^3, as
+//     for the finite volumes), applied in link form
+//     (A phi)_p = sum_q c_pq (phi_p - phi_q), c_pq = -A_pq, over the 18
+//     neighbours of the five-tetrahedra mesh (its rows sum to zero: the
+//     constant function is in every element's space).
+
+// Gradients of the barycentric coordinates of a tetrahedron and its volume.
+void tet_gradients(const double X[4][3], double G[4][3], double* vol) {
+  double e[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int d = 0; d < 3; ++d) e[r][d] = X[r + 1][d] - X[0][d];
+  const auto cross = [](const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+  };
+  double c23[3], c31[3], c12[3];
+  cross(e[1], e[2], c23);
+  cross(e[2], e[0], c31);
+  cross(e[0], e[1], c12);
+  const double det = e[0][0] * c23[0] + e[0][1] * c23[1] + e[0][2] * c23[2];
+  for (int d = 0; d < 3; ++d) {
+    G[1][d] = c23[d] / det;
+    G[2][d] = c31[d] / det;
+    G[3][d] = c12[d] / det;
+    G[0][d] = -(G[1][d] + G[2][d] + G[3][d]);
+  }
+  *vol = std::fabs(det) / 6.0;
+}
+
+double tet_volume(const double* A, const double* B, const double* C, const double* D) {
+  double e[3][3];
+  for (int d = 0; d < 3; ++d) {
+    e[0][d] = B[d] - A[d];
+    e[1][d] = C[d] - A[d];
+    e[2][d] = D[d] - A[d];
+  }
+  const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                     e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                     e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+  return std::fabs(det) / 6.0;
+}
+
+// Volume of {psi_h < 0} in the tetrahedron (vertex values psi).
+double tet_inside_volume(const double X[4][3], const double psi[4], double vol) {
+  int neg[4], pos[4], nn = 0, np = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (psi[i] < 0.0) neg[nn++] = i;
+    else pos[np++] = i;
+  }
+  if (np == 0) return vol;
+  if (nn == 0) return 0.0;
+  // crossing point on the edge from vertex a to vertex b
+  const auto at = [&](int a, int b, double* P) {
+    const double t = psi[a] / (psi[a] - psi[b]);
+    for (int d = 0; d < 3; ++d) P[d] = X[a][d] + t * (X[b][d] - X[a][d]);
+  };
+  if (nn == 1 || np == 1) {  // a small tetrahedron at the lone vertex
+    const int lone = nn == 1 ? neg[0] : pos[0];
+    const int* other = nn == 1 ? pos : neg;
+    double P[3][3];
+    for (int r = 0; r < 3; ++r) at(lone, other[r], P[r]);
+    const double small = tet_volume(X[lone], P[0], P[1], P[2]);
+    return nn == 1 ? small : vol - small;
+  }
+  // two and two: the inside part is a prism with ends (a, Pac, Pad) and
+  // (b, Pbc, Pbd) and lateral edges a-b, Pac-Pbc, Pad-Pbd; three tetrahedra
+  const int a = neg[0], b = neg[1], c = pos[0], d = pos[1];
+  double Pac[3], Pad[3], Pbc[3], Pbd[3];
+  at(a, c, Pac);
+  at(a, d, Pad);
+  at(b, c, Pbc);
+  at(b, d, Pbd);
+  return tet_volume(X[a], Pac, Pad, X[b]) + tet_volume(Pac, Pad, X[b], Pbd) +
+         tet_volume(Pac, X[b], Pbc, Pbd);
+}
+
+// The IFE basis of one tetrahedron: grad phi- of basis function i (a[i]),
+// its interface coefficient t[i], the vertex coefficients c[i][j] of phi-,
+// g = grad psi_h and the volume of T-. For an uncut tetrahedron a = grad
+// lambda, t = 0, c = identity, and the inside volume is all or nothing.
+struct IfeBasis {
+  double a[4][3], t[4], c[4][4], g[3], vol, vin;
+  bool cut;
+};
+
+IfeBasis ife_basis(const double X[4][3], const double psi[4], double ein, double eout) {
+  IfeBasis B{};
+  double G[4][3];
+  tet_gradients(X, G, &B.vol);
+  bool any_in = false, any_out = false;
+  for (int i = 0; i < 4; ++i) (psi[i] < 0.0 ? any_in : any_out) = true;
+  B.cut = any_in && any_out;
+  B.vin = tet_inside_volume(X, psi, B.vol);
+  for (int d = 0; d < 3; ++d) {
+    B.g[d] = 0.0;
+    for (int i = 0; i < 4; ++i) B.g[d] += psi[i] * G[i][d];
+  }
+  double kappa = 0.0, w[4] = {0, 0, 0, 0}, dv[4] = {0, 0, 0, 0}, wd = 0.0;
+  if (B.cut) {
+    const double g2 = B.g[0] * B.g[0] + B.g[1] * B.g[1] + B.g[2] * B.g[2];
+    kappa = (ein - eout) / (eout * g2);
+    for (int j = 0; j < 4; ++j) {
+      w[j] = G[j][0] * B.g[0] + G[j][1] * B.g[1] + G[j][2] * B.g[2];
+      dv[j] = psi[j] < 0.0 ? 0.0 : psi[j];
+      wd += w[j] * dv[j];
+    }
+  }
+  const double den = 1.0 + kappa * wd;
+  for (int i = 0; i < 4; ++i) {
+    for (int j = 0; j < 4; ++j) B.c[i][j] = (i == j ? 1.0 : 0.0) - kappa * dv[j] * w[i] / den;
+    for (int d = 0; d < 3; ++d) {
+      B.a[i][d] = 0.0;
+      for (int j = 0; j < 4; ++j) B.a[i][d] += B.c[i][j] * G[j][d];
+    }
+    B.t[i] = kappa * (B.a[i][0] * B.g[0] + B.a[i][1] * B.g[1] + B.a[i][2] * B.g[2]);
+  }
+  return B;
+}
+
+// Element matrix of the IFE basis (uncut: eps of its side times the linear
+// finite element matrix).
+void ife_element(const double X[4][3], const double psi[4], double ein, double eout,
+                 double K[4][4]) {
+  const IfeBasis B = ife_basis(X, psi, ein, eout);
+  const double vout = B.vol - B.vin;
+  for (int i = 0; i < 4; ++i)
+    for (int j = i; j < 4; ++j) {
+      double aa = 0.0, bb = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        aa += B.a[i][d] * B.a[j][d];
+        bb += (B.a[i][d] + B.t[i] * B.g[d]) * (B.a[j][d] + B.t[j] * B.g[d]);
+      }
+      K[i][j] = ein * B.vin * aa + eout * vout * bb;
+      K[j][i] = K[i][j];
+    }
+}
+
+// The five tetrahedra of cube (i, j, k) as corner offsets (a, b, c).
+void cube_tets(int i, int j, int k, int T[5][4][3]) {
+  const int p = (i + j + k) & 1;
+  int even[4][3], odd[4][3], ne = 0, no = 0;
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        int* dst = ((a + b + c) & 1) == p ? even[ne++] : odd[no++];
+        dst[0] = a;
+        dst[1] = b;
+        dst[2] = c;
+      }
+  for (int v = 0; v < 4; ++v)
+    for (int d = 0; d < 3; ++d) T[0][v][d] = even[v][d];
+  for (int o = 0; o < 4; ++o) {  // the odd corner and its three axis neighbours
+    for (int d = 0; d < 3; ++d) T[1 + o][0][d] = odd[o][d];
+    int m = 1;
+    for (int e = 0; e < 4; ++e) {
+      const int dist = std::abs(even[e][0] - odd[o][0]) + std::abs(even[e][1] - odd[o][1]) +
+                       std::abs(even[e][2] - odd[o][2]);
+      if (dist != 1) continue;
+      for (int d = 0; d < 3; ++d) T[1 + o][m][d] = even[e][d];
+      ++m;
+    }
+  }
+}
+
+int ife_link(int di, int dj, int dk) {
+  for (int l = 0; l < kIfeLinks; ++l)
+    if (kIfeOff[l][0] == di && kIfeOff[l][1] == dj && kIfeOff[l][2] == dk) return l;
+  return -1;
+}
+
+// Assembles the link coefficients of the IFE operator on grid G (the object
+// in G.obj with eps_in inside, G.eps outside; no object: uniform G.eps).
+void ife_assemble(const FieldGrid& G, std::vector<double>& c) {
+  c.assign(G.nodes * kIfeLinks, 0.0);
+  const double ein = G.obj ? G.obj->eps_in : G.eps;
+  const double h3 = G.h * G.h * G.h;
+  for (int k = 0; k < G.n[2]; ++k)
+    for (int j = 0; j < G.n[1]; ++j)
+      for (int i = 0; i < G.n[0]; ++i) {
+        int T[5][4][3];
+        cube_tets(i, j, k, T);
+        for (int t = 0; t < 5; ++t) {
+          double X[4][3], psi[4];
+          int idx[4][3];
+          for (int v = 0; v < 4; ++v) {
+            idx[v][0] = i + T[t][v][0];
+            idx[v][1] = j + T[t][v][1];
+            idx[v][2] = k + T[t][v][2];
+            for (int d = 0; d < 3; ++d) X[v][d] = G.h * idx[v][d];
+            psi[v] = G.obj ? G.psi(idx[v][0], idx[v][1], idx[v][2]) : 1.0;
+          }
+          double K[4][4];
+          ife_element(X, psi, ein, G.eps, K);
+          for (int r = 0; r < 4; ++r)
+            for (int q = 0; q < 4; ++q) {
+              if (r == q) continue;
+              const int l = ife_link(idx[q][0] - idx[r][0], idx[q][1] - idx[r][1],
+                                     idx[q][2] - idx[r][2]);
+              c[G.id(idx[r][0], idx[r][1], idx[r][2]) * kIfeLinks + l] -= K[r][q] / h3;
+            }
+        }
+      }
+}
 
 // ---- multigrid V-cycle preconditioner ----------------------------------------
 //
@@ -1705,18 +1960,28 @@ void orc_normals3(uint64_t key, double z[3]) {
 // > 0, max_iter < 0, precond not 0 or 1).
 // obj (nullable, or kind 0): the object as an interface with permittivity
 // eps_in inside (see above).
+// op: 0 node-centred finite volumes, 1 immersed finite elements (the
+// multigrid preconditioner then smooths its finest level with the IFE
+// operator and corrects with the finite-volume operators of the coarser
+// levels).
 int orc_field_solve(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t dirichlet,
                     const double* g, const double* rho, double* phi, double tol, int32_t max_iter,
-                    int32_t precond, const orc_field_object* obj, int32_t* iters, double* relres,
-                    int32_t* levels) {
+                    int32_t precond, const orc_field_object* obj, int32_t op, int32_t* iters,
+                    double* relres, int32_t* levels) {
   if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || !(tol > 0) || max_iter < 0 ||
-      (dirichlet & 63) == 0 || (dirichlet & ~63) || !rho || !phi || precond < 0 || precond > 1)
+      (dirichlet & 63) == 0 || (dirichlet & ~63) || !rho || !phi || precond < 0 || precond > 1 ||
+      op < 0 || op > 1)
     return ORC_E_INVALID;
   FieldObject fo{};
   FieldGrid G = field_grid(nx, ny, nz, h, eps, dirichlet, g);
   if (obj && obj->kind != 0) {
     if (!field_object(*obj, fo)) return ORC_E_INVALID;
     G.obj = &fo;
+  }
+  std::vector<double> links;
+  if (op == 1) {
+    ife_assemble(G, links);
+    G.ife = &links;
   }
   return field_solve(G, rho, phi, tol, max_iter, precond, iters, relres, levels);
 }
@@ -1725,15 +1990,20 @@ int orc_field_solve(int32_t nx, int32_t ny, int32_t nz, double h, double eps, in
 // the mask), for the pins of the preconditioner. Returns the level count, or
 // 0 when the grid does not coarsen (z untouched), -1 for invalid arguments.
 int orc_field_vcycle(int32_t nx, int32_t ny, int32_t nz, double h, double eps, int32_t dirichlet,
-                     const orc_field_object* obj, const double* r, double* z) {
+                     const orc_field_object* obj, int32_t op, const double* r, double* z) {
   if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || (dirichlet & 63) == 0 ||
-      (dirichlet & ~63) || !r || !z)
+      (dirichlet & ~63) || !r || !z || op < 0 || op > 1)
     return ORC_E_INVALID;
   FieldObject fo{};
   FieldGrid G = field_grid(nx, ny, nz, h, eps, dirichlet, nullptr);
   if (obj && obj->kind != 0) {
     if (!field_object(*obj, fo)) return ORC_E_INVALID;
     G.obj = &fo;
+  }
+  std::vector<double> links;
+  if (op == 1) {
+    ife_assemble(G, links);
+    G.ife = &links;
   }
   Multigrid M;
   if (!mg_setup(G, M)) return 0;
@@ -1749,6 +2019,63 @@ void orc_field_E(int32_t nx, int32_t ny, int32_t nz, double h, int32_t dirichlet
                  double* Ex, double* Ey, double* Ez) {
   double* E[3] = {Ex, Ey, Ez};
   field_E(field_grid(nx, ny, nz, h, 1.0, dirichlet, nullptr), phi, E);
+}
+
+// Pieces of the immersed finite elements, for the pins. X: the 4 vertices
+// (x, y, z each), psi: the level set there.
+// out (38 values): a[4][3] (grad phi- of each basis function), t[4], c[4][4]
+// (phi- = sum_j c[i][j] lambda_j), g[3] (grad psi_h), volume, inside volume,
+// cut (1 or 0).
+void orc_ife_basis(const double* X, const double* psi, double ein, double eout, double* out) {
+  double Xv[4][3];
+  for (int v = 0; v < 4; ++v)
+    for (int d = 0; d < 3; ++d) Xv[v][d] = X[3 * v + d];
+  const IfeBasis B = ife_basis(Xv, psi, ein, eout);
+  int o = 0;
+  for (int i = 0; i < 4; ++i)
+    for (int d = 0; d < 3; ++d) out[o++] = B.a[i][d];
+  for (int i = 0; i < 4; ++i) out[o++] = B.t[i];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) out[o++] = B.c[i][j];
+  for (int d = 0; d < 3; ++d) out[o++] = B.g[d];
+  out[o++] = B.vol;
+  out[o++] = B.vin;
+  out[o++] = B.cut ? 1.0 : 0.0;
+}
+
+void orc_ife_element(const double* X, const double* psi, double ein, double eout, double* K) {
+  double Xv[4][3], Kv[4][4];
+  for (int v = 0; v < 4; ++v)
+    for (int d = 0; d < 3; ++d) Xv[v][d] = X[3 * v + d];
+  ife_element(Xv, psi, ein, eout, Kv);
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) K[4 * i + j] = Kv[i][j];
+}
+
+// The five tetrahedra of cube (i, j, k): T[t][v] = corner offsets (60 ints).
+void orc_cube_tets(int32_t i, int32_t j, int32_t k, int32_t* out) {
+  int T[5][4][3];
+  cube_tets(i, j, k, T);
+  for (int t = 0; t < 5; ++t)
+    for (int v = 0; v < 4; ++v)
+      for (int d = 0; d < 3; ++d) out[12 * t + 3 * v + d] = T[t][v][d];
+}
+
+// The assembled IFE link coefficients c[node][18] (neighbour order of the
+// oracle source) on a grid; obj nullable (uniform eps).
+int orc_ife_links(int32_t nx, int32_t ny, int32_t nz, double h, double eps,
+                  const orc_field_object* obj, double* c) {
+  if (nx < 1 || ny < 1 || nz < 1 || !(h > 0) || !(eps > 0) || !c) return ORC_E_INVALID;
+  FieldObject fo{};
+  FieldGrid G = field_grid(nx, ny, nz, h, eps, 1, nullptr);
+  if (obj && obj->kind != 0) {
+    if (!field_object(*obj, fo)) return ORC_E_INVALID;
+    G.obj = &fo;
+  }
+  std::vector<double> links;
+  ife_assemble(G, links);
+  std::memcpy(c, links.data(), sizeof(double) * links.size());
+  return ORC_OK;
 }
 
 // Level set of the object at points (cell units), for the pins.

@@ -116,6 +116,7 @@ int main() {
   objs[1].radius = 3; objs[1].eps_in = 4;
   objs[2].kind = 2; objs[2].center[0] = 8; objs[2].center[1] = 6; objs[2].z_flat = 3;
   objs[2].rim_radius = 4; objs[2].depth = 2; objs[2].eps_in = 10;
+  for (int op = 0; op < 2; ++op)
   for (int k = 0; k < 3; ++k)
     for (int pc = 0; pc < 2; ++pc)
       for (int mask : {32, 63, 1 | 2}) {
@@ -123,15 +124,26 @@ int main() {
         int32_t it = 0, lv = 0;
         double rr = 0;
         if (orc_field_solve(nx, ny, nz, 1.0, 1.0, mask, vals, rho.data(), phi.data(), 1e-10, 500, pc,
-                            k ? &objs[k] : nullptr, &it, &rr, &lv) != 0) {
-          std::printf("field solve obj %d precond %d mask %d failed\n", k, pc, mask);
+                            k ? &objs[k] : nullptr, op, &it, &rr, &lv) != 0) {
+          std::printf("field solve op %d obj %d precond %d mask %d failed\n", op, k, pc, mask);
           ++bad;
         }
         orc_field_E(nx, ny, nz, 1.0, mask, phi.data(), Ex.data(), Ey.data(), Ez.data());
-        if (orc_field_vcycle(nx, ny, nz, 1.0, 1.0, mask, k ? &objs[k] : nullptr, r.data(),
+        if (orc_field_vcycle(nx, ny, nz, 1.0, 1.0, mask, k ? &objs[k] : nullptr, op, r.data(),
                              zz.data()) < 0)
           ++bad;
       }
+  {  // the IFE pieces on their own
+    std::vector<double> links(nodes * 18), out(38), K(16);
+    for (int k = 0; k < 3; ++k)
+      if (orc_ife_links(nx, ny, nz, 1.0, 1.0, k ? &objs[k] : nullptr, links.data()) != 0) ++bad;
+    const double X[12] = {0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1};
+    const double ps[4] = {-0.3, 0.2, 0.0, 0.7};
+    orc_ife_basis(X, ps, 4.0, 1.0, out.data());
+    orc_ife_element(X, ps, 4.0, 1.0, K.data());
+    int32_t T[60];
+    orc_cube_tets(1, 2, 3, T);
+  }
   std::printf(bad ? "FAILED %d\n" : "ok\n", bad);
   return bad ? 1 : 0;
 }
