@@ -67,6 +67,8 @@ extern "C" {
 
 #define PIC_MAX_SPECIES 4
 #define PIC_NUM_FACES 6
+/* Most ids of one pic_get_particles_by_id_noalloc call. */
+#define PIC_NOALLOC_MAX_IDS 65536
 
 typedef struct pic_ctx pic_ctx;
 
@@ -413,6 +415,21 @@ pic_status pic_get_particles(pic_ctx *ctx, int32_t species, int64_t cap, int64_t
 pic_status pic_get_particles_by_id(pic_ctx *ctx, int32_t species, int64_t n,
                                    const int64_t *ids_sorted, int32_t *found, double *x,
                                    double *y, double *z, double *vx, double *vy, double *vz);
+
+/* pic_get_particles_by_id for callers that cannot allocate device memory
+ * (a tight serving loop, a harness that forbids allocation): the same
+ * arguments, results and errors, but the id list and the results are staged
+ * in a fixed scratch area of the library's (PIC_NOALLOC_MAX_IDS * 64 bytes of
+ * device memory on each GPU it runs on, kept until the process ends) instead
+ * of memory allocated per call; the call allocates no device memory (neither
+ * hipMalloc nor pic_config.alloc). n > PIC_NOALLOC_MAX_IDS: PIC_E_INVALID.
+ * All contexts on one GPU share that GPU's scratch area and it keeps the last
+ * call's contents: calls that overlap in time on one GPU (from several host
+ * threads) race and must be serialised by the caller. Synchronises. */
+pic_status pic_get_particles_by_id_noalloc(pic_ctx *ctx, int32_t species, int64_t n,
+                                           const int64_t *ids_sorted, int32_t *found, double *x,
+                                           double *y, double *z, double *vx, double *vy,
+                                           double *vz);
 
 /* Kernel timing for measurement: when enabled, the library records HIP events
  * around each launch of its kernels on the context's stream. */

@@ -243,6 +243,7 @@ struct pic_ctx {
   int32_t if_diag_levels = 0;   // levels whose diag matches if_eps_*
   double if_eps_in = 0.0, if_eps_out = 0.0;
   int64_t *rho_surf = nullptr;  // surface source (fixed point)
+  void *scratch = nullptr;      // the device's scratch of the no-allocation id lookup
 };
 
 namespace {
@@ -695,6 +696,26 @@ pic_status ensure_ids(pic_ctx *c, int s) {
   return PIC_OK;
 }
 
+// Checks of an id lookup; then synchronises (reporting device-side errors)
+// and makes sure the particles are binned. PIC_OK with nothing to do for n == 0.
+pic_status by_id_prepare(pic_ctx *c, int32_t species, int64_t n, const int64_t *ids_sorted,
+                         const int32_t *found, const double *x, const double *y, const double *z,
+                         const double *vx, const double *vy, const double *vz) {
+  if (const pic_status s0 = check_ctx(c)) return s0;
+  if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
+  if (n < 0) return fail(c, PIC_E_INVALID, "n must be >= 0");
+  if (n > 0 && (!ids_sorted || !found || !x || !y || !z || !vx || !vy || !vz))
+    return fail(c, PIC_E_INVALID, "arrays must not be NULL");
+  for (int64_t k = 1; k < n; ++k)
+    if (!(ids_sorted[k - 1] < ids_sorted[k]))
+      return fail(c, PIC_E_INVALID, "ids must be distinct and ascending");
+  if (!c->sp[species].ids) return fail(c, PIC_E_STATE, "no ids were loaded for this species");
+  pic_status st = sync_and_check(c);
+  if (st != PIC_OK || n == 0) return st;
+  if (!c->sorted && (st = do_sort(c, 0)) != PIC_OK) return st;
+  return PIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -759,6 +780,10 @@ pic_status pic_create(const pic_config *cfg, pic_ctx **out) {
       return bail(PIC_E_DEVICE, "hipStreamCreate failed");
     c->own_stream = true;
   }
+  // the scratch of pic_get_particles_by_id_noalloc on this device (its
+  // address looked up once per device)
+  if (noalloc_scratch(&c->scratch) != hipSuccess)
+    return bail(PIC_E_DEVICE, "hipGetSymbolAddress of the scratch area failed");
   const Dims &L = c->L;
   const int64_t e4 = cfg->repr == PIC_REPR_FP64 ? 32 : 16;
   void *p = nullptr;
@@ -1734,20 +1759,9 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
 pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
                                    const int64_t *ids_sorted, int32_t *found, double *x,
                                    double *y, double *z, double *vx, double *vy, double *vz) {
-  if (const pic_status s0 = check_ctx(c)) return s0;
-  if (species < 0 || species >= c->L.ns) return fail(c, PIC_E_INVALID, "species out of range");
-  if (n < 0) return fail(c, PIC_E_INVALID, "n must be >= 0");
-  if (n > 0 && (!ids_sorted || !found || !x || !y || !z || !vx || !vy || !vz))
-    return fail(c, PIC_E_INVALID, "arrays must not be NULL");
-  for (int64_t k = 1; k < n; ++k)
-    if (!(ids_sorted[k - 1] < ids_sorted[k]))
-      return fail(c, PIC_E_INVALID, "ids must be distinct and ascending");
+  pic_status st = by_id_prepare(c, species, n, ids_sorted, found, x, y, z, vx, vy, vz);
+  if (st != PIC_OK || n == 0) return st;
   pic_ctx::Species &S = c->sp[species];
-  if (!S.ids) return fail(c, PIC_E_STATE, "no ids were loaded for this species");
-  pic_status st = sync_and_check(c);
-  if (st != PIC_OK) return st;
-  if (n == 0) return PIC_OK;
-  if (!c->sorted && (st = do_sort(c, 0)) != PIC_OK) return st;
   // staging of the id list and of the results, for this call only
   void *d_ids = dev_alloc(c->cfg, n * 8), *d_found = dev_alloc(c->cfg, n * 4),
        *d_out = dev_alloc(c->cfg, n * 6 * 8);
@@ -1764,7 +1778,8 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
   if (e == hipSuccess) e = launch_fill(d_found, n * 4, c->stream);
   if (e == hipSuccess)
     e = launch_find_ids(c->cfg.repr, S.buf[c->cur], bins_of(c), c->cur, species, c->L.ntiles,
-                        (const int64_t *)d_ids, n, (int32_t *)d_found, (double *)d_out, c->stream);
+                        (const int64_t *)d_ids, n, (int32_t *)d_found, (double *)d_out,
+                        PhysUnits{}, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   std::vector<double> out(n * 6);
   if (e == hipSuccess) e = hipMemcpy(found, d_found, n * 4, hipMemcpyDeviceToHost);
@@ -1780,6 +1795,42 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
       V[d][k] = out[(3 + d) * n + k] * cf.h;
     }
   }
+  return PIC_OK;
+}
+
+pic_status pic_get_particles_by_id_noalloc(pic_ctx *c, int32_t species, int64_t n,
+                                           const int64_t *ids_sorted, int32_t *found, double *x,
+                                           double *y, double *z, double *vx, double *vy,
+                                           double *vz) {
+  if (c && n > PIC_NOALLOC_MAX_IDS)
+    return fail(c, PIC_E_INVALID, "n must be <= PIC_NOALLOC_MAX_IDS");
+  pic_status st = by_id_prepare(c, species, n, ids_sorted, found, x, y, z, vx, vy, vz);
+  if (st != PIC_OK || n == 0) return st;
+  if (!c->scratch) return fail(c, PIC_E_DEVICE, "no scratch area on this device");
+  // staged in the device's scratch area (c->scratch: its address on this
+  // device): the ids, the caller's output arrays (entries of ids not found
+  // stay as they are), the found flags cleared by a kernel; the lookup writes
+  // physical units, so the results go back into the caller's arrays directly
+  char *base = (char *)c->scratch;
+  int64_t *d_ids = (int64_t *)(base + kNoAllocIdsOff);
+  double *d_out = (double *)(base + kNoAllocOutOff);
+  int32_t *d_found = (int32_t *)(base + kNoAllocFoundOff);
+  double *O[6] = {x, y, z, vx, vy, vz};
+  const hipStream_t s = c->stream;
+  PIC_HIP(c, hipMemcpyAsync(d_ids, ids_sorted, n * 8, hipMemcpyHostToDevice, s));
+  for (int d = 0; d < 6; ++d)
+    PIC_HIP(c, hipMemcpyAsync(d_out + d * n, O[d], n * 8, hipMemcpyHostToDevice, s));
+  PIC_HIP(c, launch_fill(d_found, n * 4, s));
+  PhysUnits ph{};
+  ph.on = true;
+  for (int d = 0; d < 3; ++d) ph.origin[d] = c->cfg.origin[d];
+  ph.h = c->cfg.h;
+  PIC_HIP(c, launch_find_ids(c->cfg.repr, c->sp[species].buf[c->cur], bins_of(c), c->cur, species,
+                             c->L.ntiles, d_ids, n, d_found, d_out, ph, s));
+  PIC_HIP(c, hipMemcpyAsync(found, d_found, n * 4, hipMemcpyDeviceToHost, s));
+  for (int d = 0; d < 6; ++d)
+    PIC_HIP(c, hipMemcpyAsync(O[d], d_out + d * n, n * 8, hipMemcpyDeviceToHost, s));
+  PIC_HIP(c, hipStreamSynchronize(s));
   return PIC_OK;
 }
 

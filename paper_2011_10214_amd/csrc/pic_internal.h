@@ -357,9 +357,27 @@ hipError_t launch_field_diag(const FieldParams &p, int l, hipStream_t s);
 hipError_t launch_surface_rho(const SurfParams &p, hipStream_t s);
 hipError_t launch_field_E(int repr, const FieldParams &p, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
+// Sampled read-back: out6 receives, per found id, the position and velocity in
+// cell units, or with phys (origin, h) the physical ones (origin + g h, u h).
+struct PhysUnits {
+  bool on;
+  double origin[3];
+  double h;
+};
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
                            int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,
-                           int32_t *found, double *out6, hipStream_t st);
+                           int32_t *found, double *out6, const PhysUnits &phys, hipStream_t st);
+
+// Scratch of pic_get_particles_by_id_noalloc: a file-scope device array of
+// kNoAllocBytes on every GPU the library runs on, laid out as the id list
+// (8 B per id), the results (48 B per id) and the found flags (4 B per id),
+// each at a fixed offset for PIC_NOALLOC_MAX_IDS ids.
+constexpr int64_t kNoAllocIdsOff = 0;
+constexpr int64_t kNoAllocOutOff = (int64_t)PIC_NOALLOC_MAX_IDS * 8;
+constexpr int64_t kNoAllocFoundOff = (int64_t)PIC_NOALLOC_MAX_IDS * 56;
+constexpr int64_t kNoAllocBytes = (int64_t)PIC_NOALLOC_MAX_IDS * 64;
+// Its address on the current device (looked up once per device).
+hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_node_E_f32(int repr, const float *Ex, const float *Ey, const float *Ez,
                              void *E, int64_t nodes, int32_t *bad, hipStream_t s);
 

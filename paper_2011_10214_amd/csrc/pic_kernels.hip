@@ -21,6 +21,8 @@
 // the expression order of the method's definition, so that the FP64 form
 // reproduces an FP64 CPU evaluation of the same definition bit for bit (and the
 // FP32 forms an FP32 one).
+#include <mutex>
+
 #include "pic_device.h"
 
 namespace pic {
@@ -1201,7 +1203,8 @@ __global__ void sort_commit_kernel(SortParams P) {
 // (and one for the overflow list).
 template <int R>
 __global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32_t nt,
-                                const int64_t *ids, int64_t n_ids, int32_t *found, double *out) {
+                                const int64_t *ids, int64_t n_ids, int32_t *found, double *out,
+                                PhysUnits phys) {
   using T = typename RealOf<R>::T;
   const Src r = src_of(bins, cur, s, blockIdx.x, nt);
   const int32_t np = r.n1 + r.na;
@@ -1228,8 +1231,9 @@ __global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32
     if (lo >= n_ids || ids[lo] != id) continue;
     found[lo] = 1;
     for (int d = 0; d < 3; ++d) {
-      out[d * n_ids + lo] = g[d];
-      out[(3 + d) * n_ids + lo] = (double)((const T *)B.vel[d])[p];
+      const double u = (double)((const T *)B.vel[d])[p];
+      out[d * n_ids + lo] = phys.on ? phys.origin[d] + g[d] * phys.h : g[d];
+      out[(3 + d) * n_ids + lo] = phys.on ? u * phys.h : u;
     }
   }
 }
@@ -1805,23 +1809,48 @@ hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s) {
 
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
                            int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,
-                           int32_t *found, double *out6, hipStream_t st) {
+                           int32_t *found, double *out6, const PhysUnits &phys, hipStream_t st) {
   if (n_ids <= 0) return hipSuccess;
   const dim3 grid(ntiles + 1);
   switch (repr) {
     case PIC_REPR_FP64:
       hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP64>, grid, dim3(256), 0, st, buf, bins, cur, s,
-                         ntiles, ids_sorted, n_ids, found, out6);
+                         ntiles, ids_sorted, n_ids, found, out6, phys);
       break;
     case PIC_REPR_FP32_ABS:
       hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_ABS>, grid, dim3(256), 0, st, buf, bins, cur,
-                         s, ntiles, ids_sorted, n_ids, found, out6);
+                         s, ntiles, ids_sorted, n_ids, found, out6, phys);
       break;
     default:
       hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_CELL>, grid, dim3(256), 0, st, buf, bins, cur,
-                         s, ntiles, ids_sorted, n_ids, found, out6);
+                         s, ntiles, ids_sorted, n_ids, found, out6, phys);
   }
   return hipGetLastError();
+}
+
+// The scratch of pic_get_particles_by_id_noalloc (each GPU holds its own copy
+// until the process ends). In host code `scratch` names a host-side stand-in,
+// not a device address: every use goes through the address that
+// hipGetSymbolAddress gives per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+hipError_t noalloc_scratch(void **ptr) {
+  constexpr int kDevices = 64;
+  static std::mutex mu;
+  static void *addr[kDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_node_E_f32(int repr, const float *Ex, const float *Ey, const float *Ez,

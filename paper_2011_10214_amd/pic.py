@@ -118,6 +118,7 @@ SIGNATURES = {
     "pic_get_counters": (_st, [_vp, _vp, _vp, _vp]),
     "pic_get_particles": (_st, [_vp, _i32, _i64, _vp] + [_vp] * 7),
     "pic_get_particles_by_id": (_st, [_vp, _i32, _i64, _vp, _vp] + [_vp] * 6),
+    "pic_get_particles_by_id_noalloc": (_st, [_vp, _i32, _i64, _vp, _vp] + [_vp] * 6),
     "pic_profile_enable": (_st, [_vp, _i32]),
     "pic_profile_read": (_st, [_vp, ctypes.POINTER(_Profile)]),
     "pic_last_error": (ctypes.c_char_p, [_vp]),
