@@ -390,6 +390,9 @@ def main():
     ap.add_argument("--eps-object", type=float, default=4.0,
                     help="field modes: permittivity inside the object relative to the plasma "
                          "(the paper's regolith and OML sphere: 4; 0: no interface)")
+    ap.add_argument("--field-op", default="fv", choices=["fv", "ife"],
+                    help="field modes: node-centred finite volumes, or immersed finite elements "
+                         "on five tetrahedra per cell (the paper's discretisation)")
     ap.add_argument("--no-surface-charge", action="store_true",
                     help="field modes: leave the collected charge out of the field source")
     ap.add_argument("--patches", type=int, default=8,
@@ -524,7 +527,8 @@ def main():
 
     field_mask = {"off": 0, "lunar": 32, "oml": 2 | 8 | 32}[args.field]
     surface = field_mask != 0 and not args.no_surface_charge and w.obj != "none"
-    field_kw = dict(eps_object=args.eps_object if w.obj != "none" else 0.0, surface_charge=surface)
+    field_kw = dict(eps_object=args.eps_object if w.obj != "none" else 0.0, surface_charge=surface,
+                    op=args.field_op)
 
     def advance(k):
         if not field_mask:
@@ -650,6 +654,7 @@ def main():
         iters = prof.field_iterations / max(1, prof.field_solves)
         out["config"]["field"] = (f"{args.field}: Dirichlet faces mask {field_mask}, PCG tol 1e-6, "
                                   "max 150 iterations, warm start, multigrid preconditioner; "
+                                  f"operator {'immersed finite elements' if args.field_op == 'ife' else 'finite volumes'}; "
                                   f"object permittivity {field_kw['eps_object']} (0: none), "
                                   f"surface charge {'on' if surface else 'off'}")
         out["field_solve"] = {

@@ -259,8 +259,9 @@ pic_status pic_get_surface_charge(pic_ctx *ctx, int64_t nbins, double *charge, i
  * through face f (escaped[f*n_species + s]). Synchronises. */
 pic_status pic_get_counters(pic_ctx *ctx, int64_t *alive, int64_t *absorbed, int64_t *escaped);
 
-/* The field solve on the PIC mesh (the boundary value problem of §2.1 with a
- * uniform permittivity; no immersed-interface treatment of the object):
+/* The field solve on the PIC mesh (the boundary value problem of §2.1),
+ * by node-centred finite volumes (below) or by immersed finite elements
+ * (PIC_FIELD_IFE):
  * -eps lap(phi) = rho on the nodes, phi = value[f] on the Dirichlet faces f,
  * zero normal derivative on the others (the symmetry / open faces of §3.1.3
  * and §5.2.2). Node-centred finite volumes: each node's control volume is its
@@ -290,6 +291,23 @@ pic_status pic_get_counters(pic_ctx *ctx, int64_t *alive, int64_t *absorbed, int
  *     The iteration count does not grow with the grid.
  *   PIC_PRECOND_JACOBI: z = r / diag(A). */
 enum { PIC_PRECOND_MULTIGRID = 0, PIC_PRECOND_JACOBI = 1 };
+/* Discretisation of the field problem (pic_field.op):
+ *   PIC_FIELD_FV: the node-centred finite volumes above.
+ *   PIC_FIELD_IFE: immersed finite elements, the paper's method (§2.3), on
+ *     the PIC mesh with every cell cut into five tetrahedra (§3.1.1): in a
+ *     cube of parity (i + j + k) mod 2 = p the central tetrahedron on the four
+ *     corners (a, b, c) with a + b + c = p mod 2 and one tetrahedron per other
+ *     corner (that corner and its three axis neighbours). Linear elements
+ *     away from the object; in a tetrahedron that the object's surface cuts
+ *     (the plane where the linear interpolant of the level set vanishes) the
+ *     basis functions are linear on each side, continuous across the plane
+ *     and with eps grad phi . n continuous across it (eq. (2.4), (2.5) with
+ *     the collected charge in the right-hand side). The right-hand side is the
+ *     nodal density of the deposit, as for the finite volumes. The multigrid
+ *     preconditioner smooths the finest level with this operator and keeps
+ *     the finite volumes on the coarser ones. Without an object
+ *     (eps_object = 0) the plain linear elements on the same tetrahedra. */
+enum { PIC_FIELD_FV = 0, PIC_FIELD_IFE = 1 };
 typedef struct {
   int32_t dirichlet; /* bit f: face f (0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+) holds
                         phi = value[f]; at least one face */
@@ -312,6 +330,7 @@ typedef struct {
                              int64 fixed point like a particle's charge; a
                              bin's charge must stay below 2^30 in magnitude
                              (PIC_E_RANGE at the solve). 0: volume charge only */
+  int32_t op;             /* PIC_FIELD_FV or PIC_FIELD_IFE */
 } pic_field;
 
 /* Solves for the deposit of the last pic_step (PIC_E_STATE before any) and

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "pic_internal.h"
+#include "pic_ife.h"
 
 using namespace pic;
 
@@ -243,6 +244,15 @@ struct pic_ctx {
   int32_t if_diag_levels = 0;   // levels whose diag matches if_eps_*
   double if_eps_in = 0.0, if_eps_out = 0.0;
   int64_t *rho_surf = nullptr;  // surface source (fixed point)
+  // immersed finite elements: row index per node, the rows (capacity in
+  // rows), the fine level's diagonal, a counter; the rows hold for
+  // ife_key_* (object as an interface, eps inside, eps outside)
+  int32_t *ife_srow = nullptr, *ife_count = nullptr;
+  double *ife_rows = nullptr, *ife_diag = nullptr;
+  int64_t ife_rows_cap = 0;
+  bool ife_ready = false;
+  int32_t ife_key_iface = -1;
+  double ife_key_in = 0.0, ife_key_out = 0.0;
   void *scratch = nullptr;      // the device's scratch of the no-allocation id lookup
 };
 
@@ -1311,6 +1321,61 @@ bool coarse_inverse(const MgLevel &C, int mask, double s, const FieldGeom *obj, 
 
 }  // namespace
 
+namespace {
+
+// The immersed finite elements of the fine grid for the object as an
+// interface (iface, eps inside ein) or not, eps outside eout: the reference
+// links of interior nodes in P, and, when not yet made for these settings,
+// the rows of the nodes that need one (box faces, vertices of cut
+// tetrahedra) and the fine level's diagonal. P must carry the level set.
+pic_status ife_setup(pic_ctx *c, FieldParams &P, bool iface, double ein, double eout) {
+  const int64_t nodes = c->L.nodes;
+  for (int par = 0; par < 2; ++par) {
+    double rl[kIfeLinks];
+    ife_reference_links(par, rl);
+    double d = 0.0;
+    for (int l = 0; l < kIfeLinks; ++l) {
+      P.rl[par][l] = rl[l] * P.ih2;
+      d = d + P.rl[par][l];
+    }
+    P.rld[par] = d;
+  }
+  if (c->ife_ready && c->ife_key_iface == (int32_t)iface && c->ife_key_in == ein &&
+      c->ife_key_out == eout)
+    return PIC_OK;
+  if (!c->ife_srow) {
+    void **const outs[3] = {(void **)&c->ife_srow, (void **)&c->ife_count,
+                            (void **)&c->ife_diag};
+    const int64_t bytes[3] = {nodes * 4, 256, nodes * 8};
+    if (!dmalloc_all(c, 3, outs, bytes))
+      return fail(c, PIC_E_NOMEM, "device memory allocation failed");
+  }
+  P.ife = 1;
+  PIC_HIP(c, launch_fill(c->ife_count, 8, c->stream));
+  PIC_HIP(c, launch_ife_mark(P, c->ife_srow, c->ife_count, c->stream));
+  int32_t count = 0;
+  PIC_HIP(c, hipMemcpyAsync(&count, c->ife_count, 4, hipMemcpyDeviceToHost, c->stream));
+  PIC_HIP(c, hipStreamSynchronize(c->stream));
+  if (count > c->ife_rows_cap) {
+    void *q = nullptr;
+    const int64_t cap = (int64_t)count + count / 8 + 64;
+    if (dmalloc(c, &q, cap * (kIfeLinks + 1) * 8) != hipSuccess)
+      return fail(c, PIC_E_NOMEM, "device memory allocation failed");
+    c->ife_rows = (double *)q;  // (a smaller earlier one stays with the context)
+    c->ife_rows_cap = cap;
+  }
+  PIC_HIP(c, launch_fill(c->ife_count + 1, 4, c->stream));
+  PIC_HIP(c, launch_ife_rows(P, c->ife_srow, c->ife_rows, c->ife_count + 1, c->ife_diag,
+                             c->stream));
+  c->ife_ready = true;
+  c->ife_key_iface = iface;
+  c->ife_key_in = ein;
+  c->ife_key_out = eout;
+  return PIC_OK;
+}
+
+}  // namespace
+
 pic_status pic_get_field_levels(pic_ctx *c, int32_t *levels) {
   if (const pic_status s0 = check_ctx(c)) return s0;
   if (!levels) return fail(c, PIC_E_INVALID, "levels must not be NULL");
@@ -1336,6 +1401,8 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
     return fail(c, PIC_E_INVALID, "eps_object must be >= 0 (0: no interface)");
   if (fs->surface_charge != 0 && fs->surface_charge != 1)
     return fail(c, PIC_E_INVALID, "surface_charge must be 0 or 1");
+  if (fs->op != PIC_FIELD_FV && fs->op != PIC_FIELD_IFE)
+    return fail(c, PIC_E_INVALID, "op: PIC_FIELD_FV or PIC_FIELD_IFE");
   if ((fs->eps_object > 0 || fs->surface_charge) && c->cfg.object.kind == PIC_OBJ_NONE)
     return fail(c, PIC_E_INVALID, "eps_object and surface_charge need an object");
   if (fs->surface_charge && c->cfg.object.kind == PIC_OBJ_SPHERE && c->cfg.object.patches < 1)
@@ -1487,6 +1554,15 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
     c->if_diag_levels = std::max(c->if_diag_levels, nl);
     c->if_eps_in = fs->eps_object;
     c->if_eps_out = fs->eps;
+  }
+  if (fs->op == PIC_FIELD_IFE) {
+    pic_status st = ife_setup(c, P, iface, fs->eps_object, fs->eps);
+    if (st != PIC_OK) return st;
+    P.ife = 1;
+    P.srow = c->ife_srow;
+    P.rows = c->ife_rows;
+    P.diag = c->ife_diag;
+    P.lv[0].diag = c->ife_diag;
   }
   if (fs->surface_charge) {
     if (!c->rho_surf) {

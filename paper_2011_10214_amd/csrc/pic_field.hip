@@ -1,9 +1,11 @@
 // HIP kernels of the field solve on the PIC mesh for gfx950 (the boundary
-// value problem of §2.1 by node-centred finite volumes, preconditioned
-// conjugate gradients with a geometric multigrid V-cycle or Jacobi, the object
-// as an interface with the collected charge as its surface source, eq.
-// (2.2)-(2.5)), and E = -grad phi into the node field.
+// value problem of §2.1 by node-centred finite volumes or by immersed finite
+// elements on five tetrahedra per cell, preconditioned conjugate gradients
+// with a geometric multigrid V-cycle or Jacobi, the object as an interface
+// with the collected charge as its surface source, eq. (2.2)-(2.5)), and
+// E = -grad phi into the node field.
 #include "pic_device.h"
+#include "pic_ife.h"
 
 namespace pic {
 namespace {
@@ -130,13 +132,52 @@ __device__ __forceinline__ double f_link_eps(const Gd &L, const FieldParams &P, 
                 : f_eps(L.psi[q], L.psi[nb], P.e_in, P.e_out);
 }
 
+// The operator of a grid: node-centred finite volumes with one permittivity
+// (kOpFV) or with the object as an interface (kOpIF, link permittivities), or
+// immersed finite elements (kOpIFE, the fine grid only; the multigrid's
+// coarser levels keep the finite volumes).
+enum { kOpFV = 0, kOpIF = 1, kOpIFE = 2 };
+
+// Visits the links of fine-grid node q = (i, j, k) of the IFE operator:
+// f(nb, c, i', j', k') with c = -A_q,nb. A node away from the box faces whose
+// tetrahedra the interface does not cut (srow < 0) has eps of its side times
+// the reference links of its parity (a node of odd parity has no face
+// diagonals); the others have their assembled row.
+template <class F>
+__device__ __forceinline__ void ife_links(const FieldParams &P, int i, int j, int k, int64_t q,
+                                          F f) {
+  const int32_t r = P.srow[q];
+  if (r < 0) {
+    const int par = (i + j + k) & 1;
+    const double e = (P.iface && P.psi[q] < 0.0) ? P.e_in : P.e_out;
+    const int nl = par ? 6 : kIfeLinks;
+    for (int l = 0; l < nl; ++l) {
+      int o[3];
+      ife_link_offset(l, o);
+      f(q + o[0] + P.sx * o[1] + P.sy * o[2], e * P.rl[par][l], i + o[0], j + o[1], k + o[2]);
+    }
+    return;
+  }
+  const double *row = P.rows + (int64_t)r * (kIfeLinks + 1);
+  for (int l = 0; l < kIfeLinks; ++l) {
+    const double c = row[l];
+    if (c == 0.0) continue;  // no link (outside the box)
+    int o[3];
+    ife_link_offset(l, o);
+    f(q + o[0] + P.sx * o[1] + P.sy * o[2], c, i + o[0], j + o[1], k + o[2]);
+  }
+}
+
 // (A x) at an unknown node q of a grid (the fine grid or a level)
-template <bool IF, class Gd>
+template <int OP, class Gd>
 __device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const double *x, int i,
                                        int j, int k, int64_t q) {
   const double xq = x[q];
   double a = 0.0;
-  if constexpr (IF) {
+  if constexpr (OP == kOpIFE) {
+    ife_links(P, i, j, k, q, [&](int64_t nb, double c, int, int, int) { a = a + c * (xq - x[nb]); });
+    return a;
+  } else if constexpr (OP == kOpIF) {
     const double cq = L.cq[q];
     if (cq > 0.0) {  // all six links of one permittivity (nearly every node)
       f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (xq - x[nb]); });
@@ -153,8 +194,9 @@ __device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const 
 }
 
 // r = b - A x, z = r / diag, p = z; Dirichlet nodes get x = g (and r = z = p = 0).
-template <int D, bool IF>
+template <int D, int OP>
 __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
+  constexpr bool IF = OP == kOpIF;
   double rz = 0.0, rr = 0.0, bb = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
        q += (int64_t)gridDim.x * kBlock) {
@@ -171,6 +213,15 @@ __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
     const double xq = P.x[q];
     const double rho = f_rho<D>(P, q);
     double ax = 0.0, dsum = 0.0, b = rho;
+    if constexpr (OP == kOpIFE) {
+      ife_links(P, i, j, k, q, [&](int64_t nb, double c, int a, int cc, int e) {
+        const bool nd = f_dir(P, a, cc, e);
+        const double xn = nd ? f_gval(P, a, cc, e) : P.x[nb];
+        ax = ax + c * (xq - xn);
+        dsum = dsum + c;
+        if (nd) b = b + c * xn;
+      });
+    } else
     f_links(P, i, j, k, q, [&](int64_t nb, double w) {
       int a, c, e;
       f_ijk(P, nb, a, c, e);
@@ -188,8 +239,8 @@ __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
         if (nd) b = b + P.s * w * xn;
       }
     });
-    const double r = IF ? rho - ax : rho - P.s * ax;
-    const double z = IF ? r / dsum : r / (P.s * dsum);
+    const double r = OP != kOpFV ? rho - ax : rho - P.s * ax;
+    const double z = OP != kOpFV ? r / dsum : r / (P.s * dsum);
     P.r[q] = r;
     P.z[q] = z;
     P.p[q] = z;
@@ -236,7 +287,7 @@ __device__ __forceinline__ bool f_done(const FieldCtrl &c, const FieldParams &P)
 }
 
 // Ap = A p; partial p.Ap
-template <bool IF>
+template <int OP>
 __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   double pap = 0.0;
@@ -246,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
     f_ijk(P, q, i, j, k);
     if (f_dir(P, i, j, k)) continue;
     const double pq = P.p[q];
-    const double ap = f_Ax<IF>(P, P, P.p, i, j, k, q);
+    const double ap = f_Ax<OP>(P, P, P.p, i, j, k, q);
     P.Ap[q] = ap;
     pap = pap + pq * ap;
   }
@@ -256,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void field_apply_kernel(FieldParams P) {
 
 // x += alpha p, r -= alpha Ap; partial r.r (parity n); Jacobi form: also
 // z = r / diag and partial r.z
-template <bool J, bool IF>
+template <bool J, int OP>
 __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int o) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const int n = 1 - o;
@@ -273,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int
     P.r[q] = r;
     if constexpr (J) {
       double d;
-      if constexpr (IF) {
+      if constexpr (OP != kOpFV) {
         d = P.diag[q];
       } else {
         double dsum = 0.0;
@@ -361,16 +412,17 @@ __device__ __forceinline__ double f_dsum(const Gd &L, int i, int j, int k) {
 }
 
 // diagonal of A at an unknown node of a level
-template <bool IF>
+template <int OP>
 __device__ __forceinline__ double mg_D(const MgLevel &L, int i, int j, int k, int64_t q) {
-  if constexpr (IF) return L.diag[q];
+  if constexpr (OP != kOpFV) return L.diag[q];
   else return L.s * f_dsum(L, i, j, k);
 }
 
 // e = two sweeps from zero: e1 = w b / d is pointwise, so the second sweep
 // computes e1 at the neighbours itself.
-template <bool IF>
+template <int OP>
 __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
+  constexpr bool IF = OP == kOpIF;
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
@@ -381,15 +433,22 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
       L.e[q] = 0.0;
       continue;
     }
-    const double d = mg_D<IF>(L, i, j, k, q);
+    const double d = mg_D<OP>(L, i, j, k, q);
     const double bq = L.rhs[q];
     const double e1 = kOmega * bq / d;
     double a = 0.0;
     const double cq = IF ? L.cq[q] : 0.0;
     const bool uni = !IF || cq > 0.0;  // one permittivity on all six links
     auto e1n = [&](int64_t nb, int a2, int b2, int c2) {
-      return f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<IF>(L, a2, b2, c2, nb);
+      return f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<OP>(L, a2, b2, c2, nb);
     };
+    if constexpr (OP == kOpIFE) {
+      ife_links(P, i, j, k, q, [&](int64_t nb, double c, int a2, int b2, int c2) {
+        a = a + c * (e1 - e1n(nb, a2, b2, c2));
+      });
+      L.e[q] = e1 + kOmega * (bq - a) / d;
+      continue;
+    }
     if (uni) {
       f_links_n(L, i, j, k, q, [&](int64_t nb, double w, int a2, int b2, int c2) {
         a = a + w * (e1 - e1n(nb, a2, b2, c2));
@@ -405,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
 }
 
 // res = b - A e
-template <bool IF>
+template <int OP>
 __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
@@ -413,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
-    L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - f_Ax<IF>(P, L, L.e, i, j, k, q);
+    L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - f_Ax<OP>(P, L, L.e, i, j, k, q);
   }
 }
 
@@ -500,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l
 
 // One damped-Jacobi sweep out = in + w (b - A in) / d. On level 0 the second
 // post-sweep writes z itself and the partial r.z to part[prz].
-template <bool Dot, bool IF>
+template <bool Dot, int OP>
 __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, int to_e2, int prz) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel &L = P.lv[l];
@@ -516,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, 
       continue;
     }
     const double bq = L.rhs[q];
-    const double v = in[q] + kOmega * (bq - f_Ax<IF>(P, L, in, i, j, k, q)) / mg_D<IF>(L, i, j, k, q);
+    const double v = in[q] + kOmega * (bq - f_Ax<OP>(P, L, in, i, j, k, q)) / mg_D<OP>(L, i, j, k, q);
     out[q] = v;
     if constexpr (Dot) rz = rz + bq * v;
   }
@@ -565,6 +624,142 @@ __global__ __launch_bounds__(kBlock) void field_diag_kernel(FieldParams P, int l
     });
     L.diag[q] = d * L.ih2;
     L.cq[q] = uni ? (in ? P.e_in : P.e_out) * L.ih2 : -1.0;
+  }
+}
+
+// ---- immersed finite elements: the rows of the operator
+//
+// A fine-grid node on a box face, or a vertex of a tetrahedron that the
+// interface cuts, gets an explicit row; every other node applies eps of its
+// side times the reference links of its parity (FieldParams.rl, evaluated on
+// the host with the same element functions). A row is gathered by its node
+// over the cubes around it in increasing global order and their tetrahedra in
+// order: per link, a tetrahedron adds its element matrix entry; a link whose
+// tetrahedra are all uncut and of one side takes that side's eps times the sum
+// of the reference entries instead, exactly as a neighbour without a row
+// computes it, so the operator stays exactly symmetric.
+
+// Level set of a fine-grid node as the elements see it (+1 without an object).
+__device__ __forceinline__ double ife_psi(const FieldParams &P, int64_t q) {
+  return P.iface ? P.psi[q] : 1.0;
+}
+
+// The level set at the 8 corners of cube (ci, cj, ck).
+__device__ __forceinline__ void ife_cube_psi(const FieldParams &P, int ci, int cj, int ck,
+                                             double cp[8]) {
+  const int64_t base = ci + P.sx * cj + P.sy * ck;
+  for (int c = 0; c < 8; ++c)
+    cp[c] = ife_psi(P, base + (c & 1) + P.sx * ((c >> 1) & 1) + P.sy * ((c >> 2) & 1));
+}
+
+// Whether node (i, j, k) needs an explicit row.
+__device__ bool ife_special(const FieldParams &P, int i, int j, int k) {
+  if (i == 0 || j == 0 || k == 0 || i == P.n[0] || j == P.n[1] || k == P.n[2]) return true;
+  if (!P.iface) return false;
+  for (int dc = -1; dc <= 0; ++dc)
+    for (int db = -1; db <= 0; ++db)
+      for (int da = -1; da <= 0; ++da) {
+        const int ci = i + da, cj = j + db, ck = k + dc;
+        double cp[8];
+        ife_cube_psi(P, ci, cj, ck, cp);
+        const int p = (ci + cj + ck) & 1, lp = -da - 2 * db - 4 * dc;
+        for (int t = 0; t < 5; ++t) {
+          int v[4];
+          ife_tet(p, t, v);
+          bool has = false, in = false, out = false;
+          for (int r = 0; r < 4; ++r) {
+            has |= v[r] == lp;
+            (cp[v[r]] < 0.0 ? in : out) = true;
+          }
+          if (has && in && out) return true;
+        }
+      }
+  return false;
+}
+
+// srow = -2 for the nodes that need a row, else -1; count[0] += their number.
+__global__ __launch_bounds__(kBlock) void ife_mark_kernel(FieldParams P, int32_t *srow,
+                                                          int32_t *count) {
+  int32_t c = 0;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)gridDim.x * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    const bool sp = ife_special(P, i, j, k);
+    srow[q] = sp ? -2 : -1;
+    c += sp;
+  }
+  for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o);
+  if (__lane_id() == 0 && c) atomicAdd(count, c);
+}
+
+// The rows of the marked nodes (each takes the next free row index), and the
+// diagonal of the fine level at every node.
+__global__ __launch_bounds__(kBlock) void ife_rows_kernel(FieldParams P, int32_t *srow,
+                                                          double *rows, int32_t *next,
+                                                          double *diag) {
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
+       q += (int64_t)gridDim.x * kBlock) {
+    int i, j, k;
+    f_ijk(P, q, i, j, k);
+    if (srow[q] != -2) {
+      const int par = (i + j + k) & 1;
+      const double e = (P.iface && P.psi[q] < 0.0) ? P.e_in : P.e_out;
+      diag[q] = e * P.rld[par];
+      continue;
+    }
+    double act[kIfeLinks], ref[kIfeLinks];
+    int8_t side[kIfeLinks];  // -1 no tetrahedron yet, 0 outside, 1 inside, 2 cut or both
+    for (int l = 0; l < kIfeLinks; ++l) {
+      act[l] = 0.0;
+      ref[l] = 0.0;
+      side[l] = -1;
+    }
+    const double ones[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    for (int dc = -1; dc <= 0; ++dc)
+      for (int db = -1; db <= 0; ++db)
+        for (int da = -1; da <= 0; ++da) {
+          const int ci = i + da, cj = j + db, ck = k + dc;
+          if (ci < 0 || cj < 0 || ck < 0 || ci >= P.n[0] || cj >= P.n[1] || ck >= P.n[2]) continue;
+          double cp[8];
+          ife_cube_psi(P, ci, cj, ck, cp);
+          const int p = (ci + cj + ck) & 1, lp = -da - 2 * db - 4 * dc;
+          for (int t = 0; t < 5; ++t) {
+            int v[4];
+            double K[4][4], R[4][4];
+            ife_cube_element(p, t, cp, P.e_in, P.e_out, v, K);
+            ife_cube_element(p, t, ones, 1.0, 1.0, v, R);
+            int rp = -1;
+            bool in = false, out = false;
+            for (int r = 0; r < 4; ++r) {
+              if (v[r] == lp) rp = r;
+              (cp[v[r]] < 0.0 ? in : out) = true;
+            }
+            if (rp < 0) continue;
+            const int8_t sd = (in && out) ? 2 : (in ? 1 : 0);
+            for (int r = 0; r < 4; ++r) {
+              if (r == rp) continue;
+              const int l = ife_link_of((v[r] & 1) - (lp & 1), ((v[r] >> 1) & 1) - ((lp >> 1) & 1),
+                                        ((v[r] >> 2) & 1) - ((lp >> 2) & 1));
+              act[l] -= K[rp][r];
+              ref[l] -= R[rp][r];
+              side[l] = side[l] < 0 ? sd : (side[l] == sd ? sd : 2);
+            }
+          }
+        }
+    const int32_t r = atomicAdd(next, 1);
+    srow[q] = r;
+    double *row = rows + (int64_t)r * (kIfeLinks + 1);
+    double d = 0.0;
+    for (int l = 0; l < kIfeLinks; ++l) {
+      double c = 0.0;
+      if (side[l] == 2) c = act[l] * P.ih2;
+      else if (side[l] >= 0) c = (side[l] == 1 ? P.e_in : P.e_out) * (ref[l] * P.ih2);
+      row[l] = c;
+      d = d + c;
+    }
+    row[kIfeLinks] = d;
+    diag[q] = d;
   }
 }
 
@@ -670,18 +865,18 @@ __global__ __launch_bounds__(kBlock) void field_E_kernel(FieldParams P) {
 
 }  // namespace
 
-template <bool IF>
+template <int OP>
 static hipError_t field_init(int deposit, const FieldParams &p, hipStream_t s) {
   switch (deposit) {
     case PIC_DEP_FIXED64:
-      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_FIXED64, IF>), dim3(p.G), dim3(kBlock), 0, s, p);
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_FIXED64, OP>), dim3(p.G), dim3(kBlock), 0, s, p);
       break;
     case PIC_DEP_ATOMIC_FP32:
-      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP32, IF>), dim3(p.G), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP32, OP>), dim3(p.G), dim3(kBlock), 0, s,
                          p);
       break;
     case PIC_DEP_ATOMIC_FP64:
-      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP64, IF>), dim3(p.G), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL((field_init_kernel<PIC_DEP_ATOMIC_FP64, OP>), dim3(p.G), dim3(kBlock), 0, s,
                          p);
       break;
     default:
@@ -692,57 +887,73 @@ static hipError_t field_init(int deposit, const FieldParams &p, hipStream_t s) {
 }
 
 hipError_t launch_field_init(int deposit, const FieldParams &p, hipStream_t s) {
-  return p.iface ? field_init<true>(deposit, p, s) : field_init<false>(deposit, p, s);
+  if (p.ife) return field_init<kOpIFE>(deposit, p, s);
+  return p.iface ? field_init<kOpIF>(deposit, p, s) : field_init<kOpFV>(deposit, p, s);
 }
 
-// z = V-cycle(r); the partial r.z to part[prz]
-template <bool IF>
+// z = V-cycle(r); the partial r.z to part[prz]. O0: the operator of the fine
+// level, OC: of the coarser ones.
+template <int O0, int OC>
 static void field_vcycle(const FieldParams &p, int prz, hipStream_t s) {
   const int L = p.levels;
   for (int l = 0; l + 1 < L; ++l) {
-    hipLaunchKernelGGL(mg_pre_kernel<IF>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
-    hipLaunchKernelGGL(mg_res_kernel<IF>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    if (l == 0) {
+      hipLaunchKernelGGL(mg_pre_kernel<O0>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+      hipLaunchKernelGGL(mg_res_kernel<O0>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    } else {
+      hipLaunchKernelGGL(mg_pre_kernel<OC>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+      hipLaunchKernelGGL(mg_res_kernel<OC>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+    }
     hipLaunchKernelGGL(mg_restrict_kernel, dim3(p.lv[l + 1].G), dim3(kBlock), 0, s, p, l);
   }
   const int gc = p.m > 0 ? (p.m + kBlock / 64 - 1) / (kBlock / 64) : 1;
   hipLaunchKernelGGL(mg_coarse_kernel, dim3(gc), dim3(kBlock), 0, s, p);
   for (int l = L - 2; l >= 0; --l) {
     hipLaunchKernelGGL(mg_prolong_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
-    hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 1,
-                       0);
-    if (l == 0)  // the r.z partials: the fine grid's workgroups
-      hipLaunchKernelGGL((mg_sweep_kernel<true, IF>), dim3(p.G), dim3(kBlock), 0, s, p, l, 0,
+    if (l == 0) {  // the r.z partials: the fine grid's workgroups
+      hipLaunchKernelGGL((mg_sweep_kernel<false, O0>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l,
+                         1, 0);
+      hipLaunchKernelGGL((mg_sweep_kernel<true, O0>), dim3(p.G), dim3(kBlock), 0, s, p, l, 0,
                          prz);
-    else
-      hipLaunchKernelGGL((mg_sweep_kernel<false, IF>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l, 0,
-                         0);
+    } else {
+      hipLaunchKernelGGL((mg_sweep_kernel<false, OC>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l,
+                         1, 0);
+      hipLaunchKernelGGL((mg_sweep_kernel<false, OC>), dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l,
+                         0, 0);
+    }
   }
 }
 
-hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s) {
-  if (p.iface) field_vcycle<true>(p, 1, s);
-  else field_vcycle<false>(p, 1, s);
+template <int O0, int OC>
+static hipError_t field_start(const FieldParams &p, hipStream_t s) {
+  field_vcycle<O0, OC>(p, 1, s);
   hipLaunchKernelGGL(field_pstart_kernel, dim3(p.G), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
-template <bool IF>
+hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s) {
+  if (p.ife) return p.iface ? field_start<kOpIFE, kOpIF>(p, s) : field_start<kOpIFE, kOpFV>(p, s);
+  return p.iface ? field_start<kOpIF, kOpIF>(p, s) : field_start<kOpFV, kOpFV>(p, s);
+}
+
+template <int O0, int OC>
 static hipError_t field_iter(const FieldParams &p, int o, hipStream_t s) {
-  hipLaunchKernelGGL(field_apply_kernel<IF>, dim3(p.G), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(field_apply_kernel<O0>, dim3(p.G), dim3(kBlock), 0, s, p);
   if (p.levels >= 2) {
-    hipLaunchKernelGGL((field_update_kernel<false, IF>), dim3(p.G), dim3(kBlock), 0, s, p, o);
+    hipLaunchKernelGGL((field_update_kernel<false, O0>), dim3(p.G), dim3(kBlock), 0, s, p, o);
     hipLaunchKernelGGL(field_check_kernel, dim3(1), dim3(kBlock), 0, s, p, o);
-    field_vcycle<IF>(p, 2 - o, s);  // parity n = 1 - o
+    field_vcycle<O0, OC>(p, 2 - o, s);  // parity n = 1 - o
     hipLaunchKernelGGL(field_dir_kernel<false>, dim3(p.G), dim3(kBlock), 0, s, p, o);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((field_update_kernel<true, IF>), dim3(p.G), dim3(kBlock), 0, s, p, o);
+  hipLaunchKernelGGL((field_update_kernel<true, O0>), dim3(p.G), dim3(kBlock), 0, s, p, o);
   hipLaunchKernelGGL(field_dir_kernel<true>, dim3(p.G), dim3(kBlock), 0, s, p, o);
   return hipGetLastError();
 }
 
 hipError_t launch_field_iter(const FieldParams &p, int o, hipStream_t s) {
-  return p.iface ? field_iter<true>(p, o, s) : field_iter<false>(p, o, s);
+  if (p.ife) return p.iface ? field_iter<kOpIFE, kOpIF>(p, o, s) : field_iter<kOpIFE, kOpFV>(p, o, s);
+  return p.iface ? field_iter<kOpIF, kOpIF>(p, o, s) : field_iter<kOpFV, kOpFV>(p, o, s);
 }
 
 hipError_t launch_field_psi(const FieldParams &p, int l, hipStream_t s) {
@@ -752,6 +963,18 @@ hipError_t launch_field_psi(const FieldParams &p, int l, hipStream_t s) {
 
 hipError_t launch_field_diag(const FieldParams &p, int l, hipStream_t s) {
   hipLaunchKernelGGL(field_diag_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
+  return hipGetLastError();
+}
+
+hipError_t launch_ife_mark(const FieldParams &p, int32_t *srow, int32_t *count, hipStream_t s) {
+  hipLaunchKernelGGL(ife_mark_kernel, dim3(p.lv[0].G), dim3(kBlock), 0, s, p, srow, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_ife_rows(const FieldParams &p, int32_t *srow, double *rows, int32_t *next,
+                           double *diag, hipStream_t s) {
+  hipLaunchKernelGGL(ife_rows_kernel, dim3(p.lv[0].G), dim3(kBlock), 0, s, p, srow, rows, next,
+                     diag);
   return hipGetLastError();
 }
 

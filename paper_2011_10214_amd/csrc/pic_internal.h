@@ -297,6 +297,16 @@ struct FieldParams {
   double ih2;
   FieldGeom geo;
   const int64_t *rho_surf;  // fixed-point surface charge (nullable)
+  // immersed finite elements on the fine grid (ife): per node the index of
+  // its explicit row (-1: eps of its side times the reference links of its
+  // parity), rows of 18 link coefficients c_pq = -A_pq and their sum; the
+  // reference links of an interior node of parity 0 / 1 (eps = 1) and their
+  // sums, over h^2
+  int32_t ife;
+  const int32_t *srow;
+  const double *rows;
+  double rl[2][18];
+  double rld[2];
 };
 
 // The collected charge as a surface source: one thread per tally bin.
@@ -355,6 +365,11 @@ hipError_t launch_field_mg_start(const FieldParams &p, hipStream_t s);
 hipError_t launch_field_psi(const FieldParams &p, int l, hipStream_t s);
 hipError_t launch_field_diag(const FieldParams &p, int l, hipStream_t s);
 hipError_t launch_surface_rho(const SurfParams &p, hipStream_t s);
+// immersed finite elements: mark the nodes that need a row (count[0] += their
+// number), then assemble the rows and the fine level's diagonal
+hipError_t launch_ife_mark(const FieldParams &p, int32_t *srow, int32_t *count, hipStream_t s);
+hipError_t launch_ife_rows(const FieldParams &p, int32_t *srow, double *rows, int32_t *next,
+                           double *diag, hipStream_t s);
 hipError_t launch_field_E(int repr, const FieldParams &p, hipStream_t s);
 hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s);
 // Sampled read-back: out6 receives, per found id, the position and velocity in

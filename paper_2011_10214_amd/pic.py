@@ -54,10 +54,11 @@ class _Field(ctypes.Structure):
     _fields_ = [("dirichlet", ctypes.c_int32), ("value", ctypes.c_double * 6),
                 ("eps", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("preconditioner", ctypes.c_int32), ("eps_object", ctypes.c_double),
-                ("surface_charge", ctypes.c_int32)]
+                ("surface_charge", ctypes.c_int32), ("op", ctypes.c_int32)]
 
 
 PRECONDITIONERS = {"multigrid": 0, "jacobi": 1}
+FIELD_OPS = {"fv": 0, "ife": 1}
 
 
 class _Injection(ctypes.Structure):
@@ -479,12 +480,16 @@ class Context:
 
     def solve_field(self, dirichlet: int, values=None, eps: float = 1.0, tol: float = 1e-6,
                     max_iter: int = 150, precond: str = "multigrid", eps_object: float = 0.0,
-                    surface_charge: bool = False):
+                    surface_charge: bool = False, op: str = "fv"):
         """Field solve for the last deposit (pic_solve_field); the node field
         becomes -grad phi. eps_object > 0 makes the object an interface with
         that permittivity inside; surface_charge adds the collected charge as
-        its surface source. Returns (iterations, relative residual)."""
+        its surface source; op "fv" (node-centred finite volumes) or "ife"
+        (immersed finite elements). Returns (iterations, relative residual)."""
+        if op not in FIELD_OPS:
+            raise ValueError(f"op must be one of {sorted(FIELD_OPS)}")
         f = _Field()
+        f.op = FIELD_OPS[op]
         f.dirichlet = int(dirichlet)
         f.preconditioner = PRECONDITIONERS[precond]
         f.eps_object = float(eps_object)
