@@ -148,17 +148,29 @@ __device__ __forceinline__ void ife_links(const FieldParams &P, int i, int j, in
                                           F f) {
   const int32_t r = P.srow[q];
   if (r < 0) {
-    const int par = (i + j + k) & 1;
+    // (the loops are unrolled: offsets and coefficients are constants of
+    // the launch, the parity only selects between two of them)
+    const bool odd = ((i + j + k) & 1) != 0;
     const double e = (P.iface && P.psi[q] < 0.0) ? P.e_in : P.e_out;
-    const int nl = par ? 6 : kIfeLinks;
-    for (int l = 0; l < nl; ++l) {
+#pragma unroll
+    for (int l = 0; l < 6; ++l) {
       int o[3];
       ife_link_offset(l, o);
-      f(q + o[0] + P.sx * o[1] + P.sy * o[2], e * P.rl[par][l], i + o[0], j + o[1], k + o[2]);
+      const double c = e * (odd ? P.rl[1][l] : P.rl[0][l]);
+      f(q + o[0] + P.sx * o[1] + P.sy * o[2], c, i + o[0], j + o[1], k + o[2]);
+    }
+    if (!odd) {  // the face diagonals join nodes of even parity only
+#pragma unroll
+      for (int l = 6; l < kIfeLinks; ++l) {
+        int o[3];
+        ife_link_offset(l, o);
+        f(q + o[0] + P.sx * o[1] + P.sy * o[2], e * P.rl[0][l], i + o[0], j + o[1], k + o[2]);
+      }
     }
     return;
   }
   const double *row = P.rows + (int64_t)r * (kIfeLinks + 1);
+#pragma unroll
   for (int l = 0; l < kIfeLinks; ++l) {
     const double c = row[l];
     if (c == 0.0) continue;  // no link (outside the box)
