@@ -28,7 +28,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s (gather+push+deposit), % HBM roofline; p50/p99 req latency"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_PARTICLE_STEP = {"fp32_cell": 56, "fp32_abs": 48, "fp64": 96}
+# state read + written per particle-step: FP32 cell form 24 B (offsets that
+# carry the cell within the tile + velocities), FP32 absolute 24 B, FP64 48 B
+BYTES_PER_PARTICLE_STEP = {"fp32_cell": 48, "fp32_abs": 48, "fp64": 96}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_10214_amd", "csrc", "pic_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel_crater_160.json")
 
@@ -219,20 +221,26 @@ def serving_run(args):
     log(f"one at a time, Poisson {rate:.2f} req/s: p50 {seq['latency_p50_s']:.2f} s, "
         f"p99 {seq['latency_p99_s']:.2f} s, mean {seq['latency_mean_s']:.2f} s")
     batched = {}
-    # head half: the oldest running request gets half of a run's particle-
-    # steps, the others share the rest; fair share: equal shares; equal steps:
-    # every running request advances 16 steps per run
-    for name, M, P, policy in [("head_half", args.steps_per_run, int(args.ps_per_run), "head"),
-                               ("fair_share", args.steps_per_run, int(args.ps_per_run), "fair"),
-                               ("equal_steps", 16, 0, "fair")]:
+    # priority: the oldest request runs, younger ones beside it only in the
+    # room a small one leaves on the GPU; priority with backfill: and in a
+    # share of a large one's runs; head half: the oldest running request
+    # gets half of a run's particle-steps, the others share the rest; fair
+    # share: equal shares
+    M, P = args.steps_per_run, int(args.ps_per_run)
+    prio = dict(policy="priority", backfill=args.backfill, saturation=int(args.saturation))
+    for name, kw in [("priority", prio),
+                     ("priority_backfill_5pct", dict(prio, backfill=0.05)),
+                     ("head_half", dict(policy="head")),
+                     ("fair_share", dict(policy="fair"))]:
         ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
                            steps_per_run=M, hbm_budget_bytes=budget, particle_steps_per_run=P,
-                           policy=policy)
+                           **kw)
         try:
             st = serve(requests(arrivals), ex)
         finally:
             ex.close()
-        st.update(steps_per_run=M, particle_steps_per_run=P)
+        st.update(steps_per_run=M, particle_steps_per_run=P,
+                  **{k: v for k, v in kw.items() if k != "policy"})
         batched[name] = st
         log(f"batched ({name}), Poisson {rate:.2f} req/s: p50 {st['latency_p50_s']:.2f} s, "
             f"p99 {st['latency_p99_s']:.2f} s, mean {st['latency_mean_s']:.2f} s")
@@ -243,14 +251,14 @@ def serving_run(args):
         a = arrivals_at(r)
         sq = serve(requests(a), SequentialExecutor(budget))
         ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
-                           steps_per_run=args.steps_per_run, hbm_budget_bytes=budget,
-                           particle_steps_per_run=int(args.ps_per_run), policy="head")
+                           steps_per_run=M, hbm_budget_bytes=budget, particle_steps_per_run=P,
+                           **prio)
         try:
             bt = serve(requests(a), ex)
         finally:
             ex.close()
-        sweep[str(load)] = {"arrival_rate_req_per_s": r, "one_at_a_time": sq, "batched_head_half": bt}
-        for name, st in (("one at a time", sq), ("batched (head_half)", bt)):
+        sweep[str(load)] = {"arrival_rate_req_per_s": r, "one_at_a_time": sq, "batched_priority": bt}
+        for name, st in (("one at a time", sq), ("batched (priority)", bt)):
             log(f"load {load}: {name}, Poisson {r:.2f} req/s: p50 {st['latency_p50_s']:.2f} s, "
                 f"p99 {st['latency_p99_s']:.2f} s, mean {st['latency_mean_s']:.2f} s, "
                 f"wall {st['wall_s']:.1f} s")
@@ -422,6 +430,11 @@ def main():
     ap.add_argument("--ps-per-run", type=float, default=3e9,
                     help="serving: particle-steps shared equally by the running requests "
                          "per batched run (0: every request gets --steps-per-run steps)")
+    ap.add_argument("--backfill", type=float, default=0.0,
+                    help="serving, priority policy: share of a large head's runs that "
+                         "younger requests may take")
+    ap.add_argument("--saturation", type=float, default=2e7,
+                    help="serving, priority policy: particles that fill the GPU")
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--sweep", default="0.5,1.0",
                     help="--serve: further loads (comma-separated) run one at a time and "

@@ -86,7 +86,11 @@ typedef enum {
 typedef enum {
   PIC_REPR_FP64 = 0,      /* FP64 positions and velocities (48 B per particle) */
   PIC_REPR_FP32_ABS = 1,  /* FP32 positions (cell units) and velocities (24 B) */
-  PIC_REPR_FP32_CELL = 2  /* int32 cell + FP32 in-cell offsets + FP32 velocities (28 B) */
+  PIC_REPR_FP32_CELL = 2  /* cell + FP32 in-cell offsets + FP32 velocities: 24 B per
+                             particle streamed (the offsets' two top bits, always zero
+                             in [0, 1), hold the cell within its tile of 4^3 cells; the
+                             tile region holding a particle gives the tile) and a 4 B
+                             cell index kept only for particles outside a region */
 } pic_repr;
 
 /* Charge deposition arithmetic. */
@@ -520,9 +524,12 @@ void pic_batch_destroy(pic_batch *b);
 pic_status pic_batch_attach(pic_batch *b, pic_ctx *ctx, int64_t nsteps, int32_t *slot);
 
 /* Weight of an attached context in the share of P (default 1 at attach; used
- * from the next run on). PIC_E_INVALID: no context in the slot, weight not in
- * (0, 1e30). A scheduler sets weights to implement its policy (e.g. a larger
- * weight for the oldest request). */
+ * from the next run on). Weight 0 pauses the context: it takes no step in the
+ * runs that follow (its state stays on the device) until its weight is set
+ * again, unless every attached context with steps left is paused, in which
+ * case all of them run with equal weights. PIC_E_INVALID: no context in the
+ * slot, weight not in [0, 1e30). A scheduler sets weights to implement its
+ * policy (e.g. the oldest request first, small ones beside it). */
 pic_status pic_batch_set_weight(pic_batch *b, int32_t slot, double weight);
 
 /* Advances every attached context by min(its quota, its remaining steps)
@@ -546,6 +553,11 @@ pic_status pic_batch_detach(pic_batch *b, int32_t slot);
 
 /* Summed footprints of the attached contexts. */
 int64_t pic_batch_used_bytes(const pic_batch *b);
+
+/* Steps the context in `slot` still has to take (after the runs completed by
+ * pic_batch_run / pic_batch_wait; a run in flight is not counted yet); -1 if
+ * the slot is empty or out of range. For schedulers that size quotas. */
+int64_t pic_batch_remaining(const pic_batch *b, int32_t slot);
 
 /* Message of the last failed call on a batch. Never NULL. */
 const char *pic_batch_last_error(const pic_batch *b);

@@ -27,12 +27,14 @@ FLAGS = [
     "-munsafe-fp-atomics",
     "-Wno-unused-command-line-argument",
 ]
+# roctx ranges around the library's calls (for profilers)
+LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose: bool = False) -> str:
     """Compile every source into libpic.so (always recompiles)."""
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *SOURCES, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *SOURCES, *LIBS, "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

@@ -11,6 +11,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "pic_internal.h"
 #include "pic_ife.h"
 
@@ -23,6 +25,16 @@ constexpr int kDefaultSort = 0;  // re-bucket with fresh capacities only on dema
 constexpr int64_t kMaxCapacity = 0x7fffffffLL - 1024;
 
 thread_local std::string g_create_error = "no error";
+
+// A roctx range over a scope: the library's calls show up by name on the host
+// timeline of a profiler (rocprofv3 --marker-trace), around the kernels they
+// enqueue; without a profiler each range costs two library calls.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
 
 int64_t particle_bytes(int repr) {
   return repr == PIC_REPR_FP64 ? 48 : (repr == PIC_REPR_FP32_ABS ? 24 : 28);
@@ -550,6 +562,7 @@ InjParams inj_params(pic_ctx *c, int out) {
 // buffer index stays; the two buffers of the species swap). The other species
 // keep their particles and layout as they are.
 pic_status do_sort(pic_ctx *c, int32_t want) {
+  const Range range("pic_replan");
   const Dims &L = c->L;
   const int32_t all = (1 << L.ns) - 1;
   SortParams S{};
@@ -667,7 +680,11 @@ pic_status commit_species(pic_ctx *c, int s, int64_t n, bool ids) {
 // Ranges [offset, offset + count) of the current buffer that hold species s
 // (tile regions and the overflow list). Re-buckets first if needed (the
 // re-bucketing does not change any result). Synchronises.
-pic_status species_ranges(pic_ctx *c, int s, std::vector<std::pair<int64_t, int64_t>> &out) {
+// The live slot ranges (first, count) of species s in the current buffer
+// (binned first if needed); tiles (nullable) gets each range's tile, -1 for
+// the overflow list.
+pic_status species_ranges(pic_ctx *c, int s, std::vector<std::pair<int64_t, int64_t>> &out,
+                          std::vector<int32_t> *tiles = nullptr) {
   pic_status st;
   if (!c->sorted && (st = do_sort(c, 0)) != PIC_OK) return st;
   PIC_HIP(c, hipStreamSynchronize(c->stream));
@@ -684,13 +701,18 @@ pic_status species_ranges(pic_ctx *c, int s, std::vector<std::pair<int64_t, int6
   int32_t novf = 0;
   PIC_HIP(c, hipMemcpy(&novf, c->ovf[c->cur] + s, 4, hipMemcpyDeviceToHost));
   out.clear();
+  if (tiles) tiles->clear();
   for (int t = 0; t < nt; ++t) {
     const int64_t n1 = std::min(nst[t], sz[t]), na = std::min(arr[t], cap[t] - sz[t]);
     if (n1 > 0) out.emplace_back(base[t], n1);
     if (na > 0) out.emplace_back(base[t] + cap[t] - na, na);
+    if (tiles) tiles->insert(tiles->end(), (n1 > 0) + (na > 0), t);
   }
   const int64_t no = std::min(novf, c->sp[s].ovf_cap);
-  if (no > 0) out.emplace_back(c->sp[s].ovf_base, no);
+  if (no > 0) {
+    out.emplace_back(c->sp[s].ovf_base, no);
+    if (tiles) tiles->push_back(-1);
+  }
   return PIC_OK;
 }
 
@@ -907,7 +929,7 @@ pic_status pic_load_particles(pic_ctx *c, int32_t species, int64_t n, const doub
         if (i >= n3[d])
           return fail(c, PIC_E_INVALID, "particle " + std::to_string(p) + " is outside the box");
         ci[d] = i;
-        ((float *)pos.data())[d * n + p] = o;
+        ((float *)pos.data())[d * n + p] = off_pack(o, i);
         ((float *)vel.data())[d * n + p] = (float)u;
       }
     }
@@ -1039,6 +1061,7 @@ pic_status pic_set_node_E_f32_dev(pic_ctx *c, const float *Ex, const float *Ey, 
 }
 
 pic_status pic_step(pic_ctx *c, int32_t nsteps) {
+  const Range range("pic_step");
   if (const pic_status s0 = check_ctx(c)) return s0;
   if (nsteps < 0) return fail(c, PIC_E_INVALID, "nsteps must be >= 0");
   if (nsteps > 0 && !c->E_set) return fail(c, PIC_E_STATE, "pic_set_node_E has not been called");
@@ -1386,6 +1409,7 @@ pic_status pic_get_field_levels(pic_ctx *c, int32_t *levels) {
 
 pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
                            double *rel_residual) {
+  const Range range("pic_solve_field");
   if (const pic_status s0 = check_ctx(c)) return s0;
   if (!fs) return fail(c, PIC_E_INVALID, "field settings must not be NULL");
   if ((fs->dirichlet & 63) == 0 || (fs->dirichlet & ~63))
@@ -1768,7 +1792,8 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
   pic_status st = sync_and_check(c);
   if (st != PIC_OK) return st;
   std::vector<std::pair<int64_t, int64_t>> rg;
-  if ((st = species_ranges(c, species, rg)) != PIC_OK) return st;
+  std::vector<int32_t> rt;
+  if ((st = species_ranges(c, species, rg, &rt)) != PIC_OK) return st;
   int64_t total = 0;
   for (auto &r : rg) total += r.second;
   *n_out = total;
@@ -1784,8 +1809,9 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
   std::vector<int32_t> cell;
   std::vector<int64_t> id;
   int64_t k = 0;
-  for (auto &r : rg) {
-    const int64_t o = r.first, n = r.second;
+  for (size_t ri = 0; ri < rg.size(); ++ri) {
+    const int64_t o = rg[ri].first, n = rg[ri].second;
+    const int32_t t = rt[ri];
     pos.resize(3 * n * e);
     vel.resize(3 * n * e);
     for (int d = 0; d < 3; ++d) {
@@ -1794,7 +1820,7 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
       PIC_HIP(c, hipMemcpy(vel.data() + d * n * e, (char *)B.vel[d] + o * e, n * e,
                            hipMemcpyDeviceToHost));
     }
-    if (repr == PIC_REPR_FP32_CELL) {
+    if (repr == PIC_REPR_FP32_CELL && t < 0) {  // a region implies its tile
       cell.resize(n);
       PIC_HIP(c, hipMemcpy(cell.data(), B.cell + o, n * 4, hipMemcpyDeviceToHost));
     }
@@ -1805,10 +1831,18 @@ pic_status pic_get_particles(pic_ctx *c, int32_t species, int64_t cap, int64_t *
     for (int64_t p = 0; p < n; ++p, ++k) {
       double g[3], u[3];
       if (repr == PIC_REPR_FP32_CELL) {
-        const int ci[3] = {cell[p] & kMaxDim, (cell[p] >> kCellBits) & kMaxDim,
-                           cell[p] >> (2 * kCellBits)};
+        const float *po = (const float *)pos.data();
+        int ci[3];
+        if (t >= 0) {
+          const int tc[3] = {t % c->L.ntx, (t / c->L.ntx) % c->L.nty, t / (c->L.ntx * c->L.nty)};
+          for (int d = 0; d < 3; ++d) ci[d] = (tc[d] << kTileShift) + off_sub(po[d * n + p]);
+        } else {
+          ci[0] = cell[p] & kMaxDim;
+          ci[1] = (cell[p] >> kCellBits) & kMaxDim;
+          ci[2] = cell[p] >> (2 * kCellBits);
+        }
         for (int d = 0; d < 3; ++d) {
-          g[d] = (double)ci[d] + (double)((float *)pos.data())[d * n + p];
+          g[d] = (double)ci[d] + (double)off_value(po[d * n + p]);
           u[d] = (double)((float *)vel.data())[d * n + p];
         }
       } else if (repr == PIC_REPR_FP32_ABS) {
@@ -1854,7 +1888,7 @@ pic_status pic_get_particles_by_id(pic_ctx *c, int32_t species, int64_t n,
   if (e == hipSuccess) e = launch_fill(d_found, n * 4, c->stream);
   if (e == hipSuccess)
     e = launch_find_ids(c->cfg.repr, S.buf[c->cur], bins_of(c), c->cur, species, c->L.ntiles,
-                        (const int64_t *)d_ids, n, (int32_t *)d_found, (double *)d_out,
+                        c->L.ntx, c->L.nty, (const int64_t *)d_ids, n, (int32_t *)d_found, (double *)d_out,
                         PhysUnits{}, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   std::vector<double> out(n * 6);
@@ -1902,7 +1936,8 @@ pic_status pic_get_particles_by_id_noalloc(pic_ctx *c, int32_t species, int64_t 
   for (int d = 0; d < 3; ++d) ph.origin[d] = c->cfg.origin[d];
   ph.h = c->cfg.h;
   PIC_HIP(c, launch_find_ids(c->cfg.repr, c->sp[species].buf[c->cur], bins_of(c), c->cur, species,
-                             c->L.ntiles, d_ids, n, d_found, d_out, ph, s));
+                             c->L.ntiles, c->L.ntx, c->L.nty, d_ids, n, d_found, d_out, ph,
+                             s));
   PIC_HIP(c, hipMemcpyAsync(found, d_found, n * 4, hipMemcpyDeviceToHost, s));
   for (int d = 0; d < 6; ++d)
     PIC_HIP(c, hipMemcpyAsync(O[d], d_out + d * n, n * 8, hipMemcpyDeviceToHost, s));
@@ -2059,6 +2094,11 @@ const char *pic_batch_last_error(const pic_batch *b) {
 
 int64_t pic_batch_used_bytes(const pic_batch *b) { return b ? b->used : 0; }
 
+int64_t pic_batch_remaining(const pic_batch *b, int32_t slot) {
+  if (!b || slot < 0 || slot >= b->cfg.max_slots || !b->ctx[slot]) return -1;
+  return b->remaining[slot];
+}
+
 pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
   if (!out) return bfail(nullptr, PIC_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -2122,7 +2162,8 @@ pic_status pic_batch_set_weight(pic_batch *b, int32_t slot, double weight) {
   if (!b) return PIC_E_INVALID;
   if (slot < 0 || slot >= b->cfg.max_slots || !b->ctx[slot])
     return bfail(b, PIC_E_INVALID, "no context in this slot");
-  if (!(weight > 0.0) || !(weight < 1e30)) return bfail(b, PIC_E_INVALID, "weight must be in (0, 1e30)");
+  if (!(weight >= 0.0) || !(weight < 1e30))
+    return bfail(b, PIC_E_INVALID, "weight must be in [0, 1e30)");
   b->weight[slot] = weight;
   return PIC_OK;
 }
@@ -2193,16 +2234,22 @@ pic_status pic_batch_attach(pic_batch *b, pic_ctx *c, int64_t nsteps, int32_t *s
 }
 
 pic_status pic_batch_launch(pic_batch *b) {
+  const Range range("pic_batch_launch");
   if (!b) return PIC_E_INVALID;
   if (b->inflight) return bfail(b, PIC_E_STATE, "a run is in flight (pic_batch_wait first)");
   const int n = b->cfg.max_slots, M = b->cfg.steps_per_run;
   const int64_t P = b->cfg.particle_steps_per_run;
+  // contexts of weight 0 are paused for this run, unless all are
+  bool any_weight = false;
+  for (int k = 0; k < n; ++k)
+    if (b->ctx[k] && b->remaining[k] > 0 && b->weight[k] > 0.0) any_weight = true;
   // re-plan the tile regions of contexts whose spare room ran out
   std::vector<int32_t> &order = b->order;
   order.clear();
   for (int k = 0; k < n; ++k) {
     pic_ctx *c = b->ctx[k];
     if (!c || b->remaining[k] <= 0) continue;
+    if (any_weight && !(b->weight[k] > 0.0)) continue;
     if (b->want_sort[k] || !c->sorted) {
       if (do_sort(c, b->want_sort[k]) != PIC_OK) return bfail(b, PIC_E_DEVICE, c->msg);
       PIC_BHIP(b, hipStreamSynchronize(c->stream));
@@ -2214,11 +2261,12 @@ pic_status pic_batch_launch(pic_batch *b) {
   if (S == 0) return PIC_OK;
   // step quotas: M each, or a weighted share of P particle-steps
   double wsum = 0.0;
-  for (int k : order) wsum += b->weight[k];
+  for (int k : order) wsum += any_weight ? b->weight[k] : 1.0;
   for (int k : order) {
     int64_t qk = M;
     if (P > 0) {
-      const double share = (double)P * (b->weight[k] / wsum) / (double)b->work[k];
+      const double wk = any_weight ? b->weight[k] : 1.0;
+      const double share = (double)P * (wk / wsum) / (double)b->work[k];
       qk = share >= (double)M ? M : std::max<int64_t>(1, (int64_t)share);
     }
     b->quota[k] = (int32_t)std::min<int64_t>(qk, b->remaining[k]);
@@ -2265,6 +2313,7 @@ pic_status pic_batch_launch(pic_batch *b) {
 }
 
 pic_status pic_batch_wait(pic_batch *b, int32_t *n_done, int32_t *done_slots) {
+  const Range range("pic_batch_wait");
   if (!b) return PIC_E_INVALID;
   if (n_done) *n_done = 0;
   if (!b->inflight) return PIC_OK;

@@ -32,6 +32,25 @@ constexpr int kCellBits = 10;  // packed cell: i | j << 10 | k << 20
 constexpr int32_t kDeadCell = -1;
 constexpr int kMaxDim = (1 << kCellBits) - 1;
 
+// FP32 cell form, stored offsets: an in-cell offset lies in [0, 1), so the two
+// top bits of its FP32 pattern (the sign and the exponent's top bit) are
+// zero. They carry the cell's coordinate within its tile along the same axis
+// (0..kTile-1), so that a particle in a tile's region needs no stored cell
+// index: the region gives the tile. The cell array holds full cells only
+// where no region does: the overflow list and a freshly loaded buffer.
+static_assert(kTile == 4, "two bits per axis hold the coordinate within a tile");
+constexpr uint32_t kOffMask = 0x3fffffffu;
+__host__ __device__ inline float off_pack(float o, int ci) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, o) |
+                                       ((uint32_t)(ci & (kTile - 1)) << 30));
+}
+__host__ __device__ inline float off_value(float s) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, s) & kOffMask);
+}
+__host__ __device__ inline int off_sub(float s) {
+  return (int)(__builtin_bit_cast(uint32_t, s) >> 30);
+}
+
 // Device flags (bitwise or).
 enum : int32_t {
   kErrRange = 1,     // a particle position became non-finite / ran away
@@ -40,7 +59,8 @@ enum : int32_t {
 };
 
 // Per-species particle arrays of one buffer. Positions: x/y/z (FP64, FP32
-// absolute: cell units) or in-cell offsets (FP32 cell form, with `cell`).
+// absolute: cell units) or in-cell offsets (FP32 cell form: off_pack, with
+// `cell` where no tile region implies the tile).
 struct PBuf {
   void *pos[3];
   void *vel[3];
@@ -380,8 +400,9 @@ struct PhysUnits {
   double h;
 };
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
-                           int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,
-                           int32_t *found, double *out6, const PhysUnits &phys, hipStream_t st);
+                           int32_t ntiles, int32_t ntx, int32_t nty, const int64_t *ids_sorted,
+                           int64_t n_ids, int32_t *found, double *out6, const PhysUnits &phys,
+                           hipStream_t st);
 
 // Scratch of pic_get_particles_by_id_noalloc: a file-scope device array of
 // kNoAllocBytes on every GPU the library runs on, laid out as the id list

@@ -341,21 +341,27 @@ __device__ __forceinline__ int tile_of_cell(const int ci[3], int ntx, int nty) {
 template <class T>
 struct Particle {
   int32_t cell;  // packed cell (cell form)
-  T x[3];        // in-cell offsets (cell form) or positions in cell units
+  T x[3];        // stored offsets (cell form: off_pack) or positions in cell units
   T u[3];
   int64_t id;
 };
 
+// Writes particle v to slot q of B. In the FP32 cell form v.x holds the
+// stored offsets (off_pack: with the cell's coordinates within its tile), and
+// the full cell is written too for a slot at or past full_from (the start of
+// the overflow list, where no region implies the tile).
 template <int R>
 __device__ __forceinline__ void store_particle(const PBuf &B, int64_t q, const Particle<typename RealOf<R>::T> &v,
-                                               bool ids) {
+                                               bool ids, int64_t full_from) {
   using T = typename RealOf<R>::T;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     ((T *)B.pos[d])[q] = v.x[d];
     ((T *)B.vel[d])[q] = v.u[d];
   }
-  if constexpr (R == PIC_REPR_FP32_CELL) B.cell[q] = v.cell;
+  if constexpr (R == PIC_REPR_FP32_CELL) {
+    if (q >= full_from) B.cell[q] = v.cell;
+  }
   if (ids) B.ids[q] = v.id;
 }
 
@@ -534,7 +540,8 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
     const T *__restrict__ U0 = (const T *)In.vel[0] + src.base;
     const T *__restrict__ U1 = (const T *)In.vel[1] + src.base;
     const T *__restrict__ U2 = (const T *)In.vel[2] + src.base;
-    const int32_t *__restrict__ CELL = kCell ? In.cell + src.base : nullptr;
+    // full cells only in the overflow list; a region implies its tile
+    const int32_t *__restrict__ CELL = kCell && ovf_block ? In.cell + src.base : nullptr;
     const int64_t *__restrict__ ID = ids ? In.ids + src.base : nullptr;
     const int64_t sbase = ovf_block ? 0 : P.bins.lay.base[(int64_t)s * nt + t];
     const int32_t ssz = ovf_block ? 0 : P.bins.lay.sz[(int64_t)s * nt + t];
@@ -542,7 +549,7 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
     auto load = [&](int32_t k) {
       const int32_t o = src_off(src, k);
       Particle<T> q;
-      q.cell = kCell ? CELL[o] : 0;
+      q.cell = kCell && ovf_block ? CELL[o] : 0;
       q.x[0] = X0[o];
       q.x[1] = X1[o];
       q.x[2] = X2[o];
@@ -558,13 +565,19 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
       T f[3];  // in-cell offsets
       T *u = q.u;
       if constexpr (kCell) {
-        if (q.cell < 0) return;  // not a particle (defensive: never written)
-        ci[0] = q.cell & kMaxDim;
-        ci[1] = (q.cell >> kCellBits) & kMaxDim;
-        ci[2] = q.cell >> (2 * kCellBits);
-        f[0] = q.x[0];
-        f[1] = q.x[1];
-        f[2] = q.x[2];
+        if (ovf_block) {
+          if (q.cell < 0) return;  // not a particle (defensive: never written)
+          ci[0] = q.cell & kMaxDim;
+          ci[1] = (q.cell >> kCellBits) & kMaxDim;
+          ci[2] = q.cell >> (2 * kCellBits);
+        } else {
+          ci[0] = (tx << kTileShift) + off_sub(q.x[0]);
+          ci[1] = (ty << kTileShift) + off_sub(q.x[1]);
+          ci[2] = (tz << kTileShift) + off_sub(q.x[2]);
+        }
+        f[0] = off_value(q.x[0]);
+        f[1] = off_value(q.x[1]);
+        f[2] = off_value(q.x[2]);
       } else {
         if (q.x[0] < T(0)) return;
         for (int d = 0; d < 3; ++d) {
@@ -668,9 +681,9 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
         }
         const bool removed = bad || face >= 0 || bin >= 0;
         if constexpr (kCell) {
-          q.x[0] = f[0];
-          q.x[1] = f[1];
-          q.x[2] = f[2];
+          q.x[0] = off_pack(f[0], ci[0]);
+          q.x[1] = off_pack(f[1], ci[1]);
+          q.x[2] = off_pack(f[2], ci[2]);
           q.cell = pack_cell(ci[0], ci[1], ci[2]);
         } else if (!removed) {
           for (int d = 0; d < 3; ++d) {
@@ -720,11 +733,18 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
             slot = arrival_slot(P.bins, out, s, tn, nt, P.err);
           }
         }
-        if (slot >= 0) store_particle<R>(P.buf[out][s], slot, q, ids);
+        if (slot >= 0) store_particle<R>(P.buf[out][s], slot, q, ids, P.bins.ovf_base[s]);
         if (removed) return;
       }
 
-      // trilinear deposit at the (new) position
+      // trilinear deposit at the (new) position (the cell form takes the
+      // offsets back from the stored values, so that only those stay live
+      // across the write)
+      if constexpr (kCell && PUSH) {
+        f[0] = off_value(q.x[0]);
+        f[1] = off_value(q.x[1]);
+        f[2] = off_value(q.x[2]);
+      }
       T W[8];
       weights(f, W);
       const int li = ci[0] - rx0, lj = ci[1] - ry0, lk = ci[2] - rz0;
@@ -827,7 +847,7 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
         } else {
           slot = arrival_slot(P.bins, out, s, tn, nt, P.err);
         }
-        if (slot >= 0) store_particle<R>(P.buf[out][s], slot, sMv[i], ids);
+        if (slot >= 0) store_particle<R>(P.buf[out][s], slot, sMv[i], ids, P.bins.ovf_base[s]);
       }
       __syncthreads();
       if (threadIdx.x == 0) sMvN = 0;
@@ -864,8 +884,11 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
     atomicAdd((unsigned long long *)&P.stats[0], (unsigned long long)sAlive);
 }
 
+// The FP32 cell form runs at 5 waves per SIMD (96 VGPRs, no spills): the
+// step is bound by the latency of its particle stream, which more resident
+// waves hide.
 template <int R, int D, bool PUSH>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepParams P) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == PIC_REPR_FP32_CELL ? 5 : 1))) void step_kernel(StepParams P) {
   step_block<R, D, PUSH>(P, blockIdx.x);
 }
 
@@ -945,12 +968,21 @@ __global__ void batch_advance_kernel(BatchTable B) {
 
 // ------------------------------------------------------------------ re-bucketing
 
-// Tile of a particle's current cell, or -1 if it is not a particle.
+// Tile of a particle's current cell, or -1 if it is not a particle. home:
+// the tile whose region slot p belongs to, or -1 (the overflow list, a
+// freshly loaded buffer); a region holds its own tile's particles only.
 template <int R>
-__device__ __forceinline__ int tile_at(const PBuf &B, int64_t p, int ntx, int nty, int tc[3]) {
+__device__ __forceinline__ int tile_at(const PBuf &B, int64_t p, int ntx, int nty, int home,
+                                       int tc[3]) {
   using T = typename RealOf<R>::T;
   int i, j, k;
   if constexpr (R == PIC_REPR_FP32_CELL) {
+    if (home >= 0) {
+      tc[0] = home % ntx;
+      tc[1] = (home / ntx) % nty;
+      tc[2] = home / (ntx * nty);
+      return home;
+    }
     const int32_t cell = B.cell[p];
     if (cell < 0) return -1;
     i = cell & kMaxDim;
@@ -1040,7 +1072,7 @@ __global__ __launch_bounds__(kBlock) void sort_count_kernel(SortParams P, int64_
   const int32_t np = so.r.n1 + so.r.na;
   for (int32_t k = threadIdx.x; k < np; k += kBlock) {
     int tc[3];
-    const int ct = tile_at<R>(B, so.r.base + src_off(so.r, k), P.ntx, P.nty, tc);
+    const int ct = tile_at<R>(B, so.r.base + src_off(so.r, k), P.ntx, P.nty, t, tc);
     if (ct < 0) continue;
     const int rel = t >= 0 ? neighbour_rel(tc, tx, ty, tz) : -1;
     if (rel >= 0) agg_add(sH, rel);
@@ -1155,7 +1187,7 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int6
   for (int32_t k = threadIdx.x; k < np; k += kBlock) {
     const int64_t p = so.r.base + src_off(so.r, k);
     int tc[3];
-    const int ct = tile_at<R>(S, p, P.ntx, P.nty, tc);
+    const int ct = tile_at<R>(S, p, P.ntx, P.nty, t, tc);
     if (ct < 0) continue;
     const int rel = t >= 0 ? neighbour_rel(tc, tx, ty, tz) : -1;
     long long q;
@@ -1170,7 +1202,7 @@ __global__ __launch_bounds__(kBlock) void sort_scatter_kernel(SortParams P, int6
       ((T *)Dd.pos[d])[q] = ((const T *)S.pos[d])[p];
       ((T *)Dd.vel[d])[q] = ((const T *)S.vel[d])[p];
     }
-    if constexpr (R == PIC_REPR_FP32_CELL) Dd.cell[q] = S.cell[p];
+    // (the destination is a region: the stored offsets carry the cell)
     if (ids) Dd.ids[q] = S.ids[p];
   }
   // the source counters are consumed (the source buffer is the next output;
@@ -1202,7 +1234,8 @@ __global__ void sort_commit_kernel(SortParams P) {
 // its state (cell units, FP64) to the list slot. One workgroup per tile region
 // (and one for the overflow list).
 template <int R>
-__global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32_t nt,
+__global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32_t nt, int32_t ntx,
+                                int32_t nty,
                                 const int64_t *ids, int64_t n_ids, int32_t *found, double *out,
                                 PhysUnits phys) {
   using T = typename RealOf<R>::T;
@@ -1212,10 +1245,21 @@ __global__ void find_ids_kernel(PBuf B, Bins bins, int32_t cur, int32_t s, int32
     const int64_t p = r.base + src_off(r, k);
     double g[3];
     if constexpr (R == PIC_REPR_FP32_CELL) {
-      const int32_t cell = B.cell[p];
-      if (cell < 0) continue;
-      const int ci[3] = {cell & kMaxDim, (cell >> kCellBits) & kMaxDim, cell >> (2 * kCellBits)};
-      for (int d = 0; d < 3; ++d) g[d] = (double)ci[d] + (double)((const float *)B.pos[d])[p];
+      int ci[3];
+      const float *X[3] = {(const float *)B.pos[0], (const float *)B.pos[1], (const float *)B.pos[2]};
+      if ((int)blockIdx.x < nt) {  // a tile's region: the tile and the offsets' sub-cells
+        const int t = blockIdx.x;
+        ci[0] = ((t % ntx) << kTileShift) + off_sub(X[0][p]);
+        ci[1] = (((t / ntx) % nty) << kTileShift) + off_sub(X[1][p]);
+        ci[2] = ((t / (ntx * nty)) << kTileShift) + off_sub(X[2][p]);
+      } else {
+        const int32_t cell = B.cell[p];
+        if (cell < 0) continue;
+        ci[0] = cell & kMaxDim;
+        ci[1] = (cell >> kCellBits) & kMaxDim;
+        ci[2] = cell >> (2 * kCellBits);
+      }
+      for (int d = 0; d < 3; ++d) g[d] = (double)ci[d] + (double)off_value(X[d][p]);
     } else {
       const T x = ((const T *)B.pos[0])[p];
       if (x < T(0)) continue;
@@ -1275,7 +1319,7 @@ __device__ __forceinline__ void emit_particle(const InjParams &P, bool has, int 
       }
       inside = box_face(ci, P.nx, P.ny, P.nz, crater) < 0;
       pt.cell = pack_cell(ci[0], ci[1], ci[2]);
-      for (int q = 0; q < 3; ++q) pt.x[q] = fo[q];
+      for (int q = 0; q < 3; ++q) pt.x[q] = off_pack(fo[q], ci[q]);
     } else {
       for (int q = 0; q < 3; ++q) pt.x[q] = (T)g[q];
       inside = box_face_abs(pt.x, P.nx, P.ny, P.nz, crater) < 0;
@@ -1313,7 +1357,7 @@ __device__ __forceinline__ void emit_particle(const InjParams &P, bool has, int 
       if (o < P.bins.ovf_cap[s]) slot = P.bins.ovf_base[s] + o;
       else atomicOr(P.err, kErrCapacity);
     }
-    if (slot >= 0) store_particle<R>(P.out[s], slot, pt, ids);
+    if (slot >= 0) store_particle<R>(P.out[s], slot, pt, ids, P.bins.ovf_base[s]);
   }
 
   // deposit: the contributions of the lanes that landed in the same cell are
@@ -1549,7 +1593,7 @@ __global__ void load_f32_kernel(LoadParams L) {
         continue;
       }
       L.out.cell[p] = pack_cell(ci[0], ci[1], ci[2]);
-      for (int d = 0; d < 3; ++d) ((float *)L.out.pos[d])[p] = o[d];
+      for (int d = 0; d < 3; ++d) ((float *)L.out.pos[d])[p] = off_pack(o[d], ci[d]);
     } else {
       for (int d = 0; d < 3; ++d) ((T *)L.out.pos[d])[p] = (T)g[d];
     }
@@ -1808,22 +1852,23 @@ hipError_t launch_load_f32(int repr, const LoadParams &p, hipStream_t s) {
 }
 
 hipError_t launch_find_ids(int repr, const PBuf &buf, const Bins &bins, int32_t cur, int32_t s,
-                           int32_t ntiles, const int64_t *ids_sorted, int64_t n_ids,
-                           int32_t *found, double *out6, const PhysUnits &phys, hipStream_t st) {
+                           int32_t ntiles, int32_t ntx, int32_t nty, const int64_t *ids_sorted,
+                           int64_t n_ids, int32_t *found, double *out6, const PhysUnits &phys,
+                           hipStream_t st) {
   if (n_ids <= 0) return hipSuccess;
   const dim3 grid(ntiles + 1);
   switch (repr) {
     case PIC_REPR_FP64:
       hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP64>, grid, dim3(256), 0, st, buf, bins, cur, s,
-                         ntiles, ids_sorted, n_ids, found, out6, phys);
+                         ntiles, ntx, nty, ids_sorted, n_ids, found, out6, phys);
       break;
     case PIC_REPR_FP32_ABS:
       hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_ABS>, grid, dim3(256), 0, st, buf, bins, cur,
-                         s, ntiles, ids_sorted, n_ids, found, out6, phys);
+                         s, ntiles, ntx, nty, ids_sorted, n_ids, found, out6, phys);
       break;
     default:
       hipLaunchKernelGGL(find_ids_kernel<PIC_REPR_FP32_CELL>, grid, dim3(256), 0, st, buf, bins, cur,
-                         s, ntiles, ids_sorted, n_ids, found, out6, phys);
+                         s, ntiles, ntx, nty, ids_sorted, n_ids, found, out6, phys);
   }
   return hipGetLastError();
 }

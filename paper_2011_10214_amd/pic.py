@@ -134,6 +134,7 @@ SIGNATURES = {
     "pic_batch_wait": (_st, [_vp, ctypes.POINTER(_i32), _vp]),
     "pic_batch_detach": (_st, [_vp, _i32]),
     "pic_batch_used_bytes": (_i64, [_vp]),
+    "pic_batch_remaining": (_i64, [_vp, _i32]),
     "pic_batch_last_error": (ctypes.c_char_p, [_vp]),
 }
 
@@ -646,6 +647,10 @@ class Batch:
     @property
     def used_bytes(self) -> int:
         return int(lib().pic_batch_used_bytes(self._h))
+
+    def remaining(self, slot: int) -> int:
+        """Steps the context in `slot` has left (-1: empty slot)."""
+        return int(lib().pic_batch_remaining(self._h, slot))
 
     def attach(self, ctx: "Context", nsteps: int) -> int:
         slot = ctypes.c_int32(-1)

@@ -48,26 +48,94 @@ class Request:
         return self.t_done - self.arrival
 
 
+def priority_weights(running: dict, remaining: dict, steps_per_run: int,
+                     particle_steps_per_run: int, backfill: float = 0.0,
+                     saturation: int = 20_000_000) -> dict:
+    """Weights of the "priority" policy for the running requests (slot ->
+    Request; `remaining`: slot -> steps left), in the units of pic_batch's
+    share of a run (the particle-steps each request should take; 0 pauses it).
+
+    The oldest request (the head) always runs. Younger ones run beside it, in
+    age order, while their particles add up to at most
+    max(backfill * head particles, saturation - head particles): with the
+    default backfill 0 only in the room a head below `saturation` particles
+    leaves on the GPU, so no request waits for one that arrived after it
+    while it could use the whole GPU. The others are paused. A request beside
+    the head takes min(M, its remaining) steps per run, all of them together
+    at most that fraction of the run's P particle-steps and never more than
+    the head leaves of P at M steps (scaled down evenly beyond it); the head
+    takes the rest of P (at most M steps). With P = 0 every running request
+    takes M steps."""
+    if not running:
+        return {}
+    M, P = int(steps_per_run), int(particle_steps_per_run)
+    order = sorted(running, key=lambda k: (running[k].arrival, running[k].rid))
+    n = {k: max(int(running[k].particles), 1) for k in order}
+    left = {k: max(int(remaining.get(k, M)), 1) for k in order}
+    head = order[0]
+    nh = n[head]
+    room = max(backfill * nh, saturation - nh)
+    side = []
+    for k in order[1:]:
+        if n[k] <= room:
+            side.append(k)
+            room -= n[k]
+    w = {k: 0.0 for k in order}
+    if P <= 0:
+        for k in [head] + side:
+            w[k] = 1.0
+        return w
+    q = {k: min(M, left[k]) for k in side}
+    work = sum(q[k] * n[k] for k in side)
+    # the share of the run beside the head: the GPU room a small head leaves
+    # (or the backfill fraction), and never what the head itself can use
+    free = (saturation - nh) / saturation if saturation > 0 else 0.0
+    cap = P * min(1.0, max(backfill, free))
+    cap = min(cap, max(backfill * P, P - min(M, left[head]) * nh))
+    if work > cap:
+        scale = cap / work
+        q = {k: max(1, int(q[k] * scale)) for k in side}
+        work = sum(q[k] * n[k] for k in side)
+    q[head] = min(M, left[head], max(1, (P - work) // nh))
+    # pic_batch gives slot k the quota P * w_k / sum(w) / n_k steps (rounded
+    # down); a quarter step more in each weight keeps the rounding from
+    # losing a step when the run is exactly full
+    for k, qk in q.items():
+        w[k] = (qk + 0.25) * n[k]
+    return w
+
+
 class BatchExecutor:
     """Continuous batching on one GPU through pic_batch.
 
     With ``particle_steps_per_run`` > 0 every run shares that many particle-
     steps among the running requests by weight; ``policy`` sets the weights:
-      "fair" -- all equal (each request gets about the same GPU time)
-      "head" -- the oldest running request gets the fraction ``head_share``
-                of a run, the others share the rest equally (small requests
-                still pass big ones, and the oldest request keeps most of the
-                GPU, which bounds the tail latency)
+      "fair"     -- all equal (each request gets about the same GPU time)
+      "head"     -- the oldest running request gets the fraction ``head_share``
+                    of a run, the others share the rest equally
+      "priority" -- the oldest running request runs as if alone; younger
+                    ones run beside it only in the room a small head leaves
+                    on a GPU of ``saturation`` particles (plus ``backfill``
+                    times the head's particles, 0 by default), with up to M
+                    steps per run each; the others wait paused on the device
+                    (priority_weights).
     """
 
     def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
                  hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0,
-                 policy: str = "fair", head_share: float = 0.5):
-        if policy not in ("fair", "head"):
+                 policy: str = "fair", head_share: float = 0.5, backfill: float = 0.0,
+                 saturation: int = 20_000_000):
+        if policy not in ("fair", "head", "priority"):
             raise ValueError(f"unknown policy {policy!r}")
         if not 0.0 < head_share < 1.0:
             raise ValueError("head_share must be in (0, 1)")
+        if not backfill >= 0.0:
+            raise ValueError("backfill must be >= 0")
         self.head_share = head_share
+        self.steps_per_run = int(steps_per_run)
+        self.particle_steps_per_run = int(particle_steps_per_run)
+        self.backfill = backfill
+        self.saturation = int(saturation)
         self.batch = pic.Batch(max_slots, repr, deposit, steps_per_run, hbm_budget_bytes, stream,
                                particle_steps_per_run)
         self.stream = stream
@@ -103,7 +171,14 @@ class BatchExecutor:
 
     def launch(self) -> None:
         """Enqueues one run; admissions may proceed until wait()."""
-        if self.policy == "head" and len(self.slots) > 1:
+        if self.policy == "priority":
+            w = priority_weights({k: v[0] for k, v in self.slots.items()},
+                                 {k: self.batch.remaining(k) for k in self.slots},
+                                 self.steps_per_run, self.particle_steps_per_run,
+                                 self.backfill, self.saturation)
+            for k, wk in w.items():
+                self.batch.set_weight(k, wk)
+        elif self.policy == "head" and len(self.slots) > 1:
             head = min(self.slots, key=lambda k: (self.slots[k][0].arrival, self.slots[k][0].rid))
             others = len(self.slots) - 1
             wh = self.head_share / (1.0 - self.head_share) * others

@@ -4,7 +4,7 @@ request completes, latency accounting."""
 import numpy as np
 import pytest
 
-from paper_2011_10214_amd.serve import Request, serve
+from paper_2011_10214_amd.serve import Request, priority_weights, serve
 
 
 class VClock:
@@ -180,3 +180,105 @@ def test_overlapped_admission_keeps_fifo_and_budget():
     assert ex.admitted_in_flight > 0
     for r in reqs:
         assert r.arrival <= r.t_admit <= r.t_done
+
+
+def _req(rid, arrival, particles):
+    return Request(rid=rid, arrival=arrival, steps=10, cfg=None, particles=particles)
+
+
+def quotas(w, running, P, M):
+    """The step quotas pic_batch computes from the weights (share of P
+    particle-steps by weight over the particles, rounded down, 1..M)."""
+    tot = sum(w.values())
+    return {k: (0 if wk == 0 else min(M, max(1, int(P * (wk / tot) / running[k].particles))))
+            for k, wk in w.items()}
+
+
+def test_priority_weights_run_the_oldest_and_backfill_small_ones():
+    running = {3: _req(7, 0.5, 100_000_000), 0: _req(4, 0.1, 80_000_000),
+               1: _req(9, 0.7, 2_000_000), 2: _req(10, 0.8, 5_000_000),
+               5: _req(12, 0.9, 3_000_000)}
+    left = {3: 900, 0: 500, 1: 1000, 2: 50, 5: 300}
+    P, M = 10 ** 9, 256
+    w = priority_weights(running, left, M, P, backfill=0.1, saturation=20_000_000)
+    # slot 0 is the oldest; the room beside it is 8 M particles: slot 3
+    # (100 M) waits, slots 1 (2 M) and 2 (5 M) run, slot 5 (3 M) no longer fits
+    assert w[3] == w[5] == 0.0 and min(w[0], w[1], w[2]) > 0
+    q = quotas(w, running, P, M)
+    # beside the head at most a tenth of P: 256 and 50 steps scaled to 33 and 6
+    assert q[1] == 33 and q[2] == 6
+    assert q[1] * 2_000_000 + q[2] * 5_000_000 <= 0.1 * P
+    # the head takes the rest: (1e9 - 96e6) // 80e6 = 11 steps
+    assert q[0] == 11
+    # without backfill a head above saturation runs alone
+    w0 = priority_weights(running, left, M, P, saturation=20_000_000)
+    assert [k for k in w0 if w0[k] > 0] == [0]
+    assert quotas(w0, running, P, M)[0] == 12
+
+
+def test_priority_weights_leave_a_small_head_the_rest_of_the_gpu():
+    running = {0: _req(0, 0.0, 1_000_000), 1: _req(1, 0.1, 15_000_000),
+               2: _req(2, 0.2, 10_000_000)}
+    left = {0: 1000, 1: 1000, 2: 1000}
+    P, M = 3 * 10 ** 9, 256
+    w = priority_weights(running, left, M, P, saturation=20_000_000)
+    # room: 20 M - 1 M = 19 M: 15 M runs, then 10 M does not fit
+    assert w[2] == 0.0 and w[0] > 0 and w[1] > 0
+    q = quotas(w, running, P, M)
+    # the head keeps M steps; the other takes what is left of P
+    assert q[0] == M
+    assert q[1] == (P - M * 1_000_000) * M // (M * 15_000_000)
+    assert q[0] * 1_000_000 + q[1] * 15_000_000 <= P
+    # a request near its end asks for no more than its remaining steps
+    w = priority_weights(running, {0: 7, 1: 3, 2: 1000}, M, P, saturation=20_000_000)
+    q = quotas(w, running, P, M)
+    assert q[0] >= 7 and q[1] >= 3 and q[2] == 0
+    # P = 0: every running request takes M steps (equal weights)
+    assert priority_weights(running, left, M, 0, saturation=20_000_000) == {0: 1.0, 1: 1.0, 2: 0.0}
+    assert priority_weights({}, {}, M, P) == {}
+    w = priority_weights({4: _req(0, 0.0, 0)}, {4: 10}, M, P)
+    assert list(w) == [4] and w[4] > 0
+
+
+def test_priority_weights_without_saturation_room():
+    # saturation 0: only the backfill share runs beside the head
+    running = {0: _req(0, 0.0, 1000), 1: _req(1, 0.1, 50), 2: _req(2, 0.2, 200)}
+    left = {0: 40, 1: 40, 2: 40}
+    w = priority_weights(running, left, 8, 4000, backfill=0.1, saturation=0)
+    assert w[0] > 0 and w[1] > 0 and w[2] == 0.0
+    q = quotas(w, running, 4000, 8)
+    assert q[1] * 50 <= 0.1 * 4000 and q[0] * 1000 + q[1] * 50 <= 4000
+    w = priority_weights(running, left, 8, 4000, saturation=0)
+    assert [k for k in w if w[k] > 0] == [0]
+
+
+def test_priority_serving_keeps_every_request_moving_to_completion():
+    # a simulated executor with the priority weights: paused requests take no
+    # steps; every request completes and the oldest is never paused
+    vc = VClock()
+
+    class Prio(FakeBatch):
+        def run(self):
+            w = priority_weights({k: r for k, (r, _) in self.running.items()},
+                                 {k: left for k, (_, left) in self.running.items()},
+                                 self.M, 0, backfill=0.1, saturation=5)
+            oldest = min(self.running, key=lambda k: (self.running[k][0].arrival, k))
+            assert w[oldest] > 0
+            active = [k for k in self.running if w[k] > 0]
+            size = sum(self.running[k][0].cfg["size"] for k in active)
+            self.vc.t += self.dt * self.M * max(size, self.floor)
+            done = []
+            for rid in active:
+                r, left = self.running[rid]
+                left -= self.M
+                if left <= 0:
+                    del self.running[rid]
+                    self.used -= r.footprint
+                    done.append(r)
+                else:
+                    self.running[rid][1] = left
+            return done
+
+    reqs = _requests(150, 3, rate=30.0)
+    st = serve(reqs, Prio(vc, 8, 10 ** 9), clock=vc.clock, sleep=vc.sleep)
+    assert st["requests"] == len(reqs)

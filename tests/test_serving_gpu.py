@@ -55,15 +55,19 @@ def _same(a, b):
 @pytest.mark.parametrize("repr_,ps_per_run,policy", [("fp32_cell", 0, "fair"), ("fp64", 0, "fair"),
                                                      ("fp32_cell", 150_000, "fair"),
                                                      ("fp64", 150_000, "fair"),
-                                                     ("fp32_cell", 150_000, "head")])
+                                                     ("fp32_cell", 150_000, "head"),
+                                                     ("fp32_cell", 150_000, "priority"),
+                                                     ("fp64", 0, "priority")])
 def test_alone_and_in_the_mix_are_identical(repr_, ps_per_run, policy):
     # ps_per_run > 0: unequal step quotas per run (fair share), so contexts of
-    # one run leave the persistent launches at different steps
+    # one run leave the persistent launches at different steps; priority with
+    # no saturation room: requests above a tenth of the oldest's size wait
+    # paused between runs
     arrivals = [0.0, 0.0, 0.0, 0.05, 0.1, 0.1, 0.3]
     mix = _requests(repr_, arrivals)
     ex = BatchExecutor(max_slots=3, repr=repr_, deposit="fixed64", steps_per_run=4,
                        hbm_budget_bytes=64 << 30, particle_steps_per_run=ps_per_run,
-                       policy=policy)
+                       policy=policy, saturation=0, backfill=0.1)
     try:
         st = serve(mix, ex)
     finally:
@@ -115,7 +119,7 @@ def test_launch_wait_protocol():
             ctxs.append((c, b.attach(c, r.steps)))
         assert b.wait() == []                     # nothing in flight
         with pytest.raises(pam.PicError):
-            b.set_weight(ctxs[0][1], 0.0)         # weights must be positive
+            b.set_weight(ctxs[0][1], -1.0)        # weights must be >= 0
         with pytest.raises(pam.PicError):
             b.set_weight(3, 1.0)                  # no context in slot 3
         b.set_weight(ctxs[0][1], 4.0)
@@ -142,3 +146,51 @@ def test_launch_wait_protocol():
         for c, _ in ctxs:
             c.close()
         b.close()
+
+
+def test_a_paused_slot_takes_no_steps():
+    # weight 0 pauses a context: a run advances the others only; its state and
+    # remaining steps stay; with every context paused, all of them run
+    reqs = _requests("fp32_cell", [0.0] * 2)
+    b = pam.Batch(2, "fp32_cell", "fixed64", 3, 64 << 30)
+    ctxs = []
+    try:
+        for r in reqs:
+            c = pam.Context(r.cfg)
+            r.loader(c)
+            ctxs.append((c, b.attach(c, 6)))
+        (ca, sa), (cb, sb) = ctxs
+        b.set_weight(sb, 0.0)
+        assert b.remaining(sa) == b.remaining(sb) == 6
+        b.launch()
+        assert b.remaining(sa) == 6               # counted when the run is waited for
+        assert b.wait() == []
+        assert b.remaining(sa) == 3 and b.remaining(sb) == 6
+        b.detach(sb)
+        assert b.remaining(sb) == -1 and b.remaining(99) == -1
+        before = _collect(cb)
+        sb = b.attach(cb, 6)
+        b.set_weight(sb, 0.0)
+        b.launch()
+        assert b.wait() == [sa]                   # 3 + 3 steps of a
+        b.detach(sa)
+        b.detach(sb)
+        _same(_collect(cb), before)               # b did not move
+        sb = b.attach(cb, 6)
+        b.set_weight(sb, 0.0)                     # paused, but the only one
+        b.launch()
+        assert b.wait() == []
+        b.launch()
+        assert b.wait() == [sb]
+        b.detach(sb)
+        after = _collect(cb)
+    finally:
+        for c, _ in ctxs:
+            c.close()
+        b.close()
+    # b took 6 steps in all: the same as 6 steps alone
+    alone = _requests("fp32_cell", [0.0] * 2)
+    for r in alone:
+        r.steps = 6
+    serve(alone, SequentialExecutor(hbm_budget_bytes=64 << 30))
+    _same(after, alone[1].result)
