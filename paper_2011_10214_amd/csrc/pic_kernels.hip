@@ -399,8 +399,10 @@ __device__ __forceinline__ unsigned long long fix_mag(T a) {
 // tile's stay zone if it stayed in the tile, into the arrival zone of its new
 // tile if it moved, nowhere if it was removed -- so the particles are
 // re-bucketed by tile at every step, in the same pass. Without PUSH only the
-// deposit of the current positions is made.
-template <int R, int D, bool PUSH>
+// deposit of the current positions is made. REFL: the code of reflecting box
+// faces is compiled in (taken where P.reflect sets a face); a context without
+// them runs the kernel without it, which needs fewer registers.
+template <int R, int D, bool PUSH, bool REFL = true>
 __device__ __forceinline__ void step_block(const StepParams &P, const int block) {
   using T = typename RealOf<R>::T;
   using V4 = typename Vec4Of<T>::type;
@@ -647,7 +649,7 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
             f[d] = op;
             ci[d] += bad ? 0 : (int)sh;
           }
-          if (P.reflect && !bad) {
+          if (REFL && P.reflect && !bad) {
             const int dims[3] = {nx, ny, nz};
             reflect_cell(P.reflect, dims, ci, f, u);
           }
@@ -656,7 +658,7 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
             q.x[d] = fmaT(u[d], dt, q.x[d]);
             bad |= !finiteT(q.x[d]);
           }
-          if (P.reflect && !bad) {
+          if (REFL && P.reflect && !bad) {
             const int dims[3] = {nx, ny, nz};
             reflect_abs(P.reflect, dims, q.x, u);
           }
@@ -887,9 +889,9 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
 // The FP32 cell form runs at 5 waves per SIMD (96 VGPRs, no spills): the
 // step is bound by the latency of its particle stream, which more resident
 // waves hide.
-template <int R, int D, bool PUSH>
+template <int R, int D, bool PUSH, bool REFL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == PIC_REPR_FP32_CELL ? 5 : 1))) void step_kernel(StepParams P) {
-  step_block<R, D, PUSH>(P, blockIdx.x);
+  step_block<R, D, PUSH, REFL>(P, blockIdx.x);
 }
 
 // Batched step (persistent): workgroups take work items (slot, block) from a
@@ -1629,10 +1631,13 @@ template <int R, int D>
 hipError_t launch_step_rd(bool push, const StepParams &p, hipStream_t s) {
   if (p.ntiles <= 0) return hipSuccess;
   // one workgroup per tile plus ovf_groups for the overflow list
-  if (push)
-    hipLaunchKernelGGL((step_kernel<R, D, true>), dim3(p.ntiles + p.ovf_groups), dim3(kBlock), 0, s, p);
+  const dim3 grid(p.ntiles + p.ovf_groups);
+  if (push && p.reflect)
+    hipLaunchKernelGGL((step_kernel<R, D, true, true>), grid, dim3(kBlock), 0, s, p);
+  else if (push)
+    hipLaunchKernelGGL((step_kernel<R, D, true, false>), grid, dim3(kBlock), 0, s, p);
   else
-    hipLaunchKernelGGL((step_kernel<R, D, false>), dim3(p.ntiles + p.ovf_groups), dim3(kBlock), 0, s, p);
+    hipLaunchKernelGGL((step_kernel<R, D, false, false>), grid, dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 
