@@ -427,9 +427,10 @@ def main():
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--steps-per-run", type=int, default=256)
-    ap.add_argument("--ps-per-run", type=float, default=3e9,
-                    help="serving: particle-steps shared equally by the running requests "
-                         "per batched run (0: every request gets --steps-per-run steps)")
+    ap.add_argument("--ps-per-run", type=float, default=1e10,
+                    help="serving: particle-steps shared by the running requests per "
+                         "batched run, about 0.12 s of GPU time (0: every request gets "
+                         "--steps-per-run steps)")
     ap.add_argument("--backfill", type=float, default=0.0,
                     help="serving, priority policy: share of a large head's runs that "
                          "younger requests may take")

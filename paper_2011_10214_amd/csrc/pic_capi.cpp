@@ -2004,8 +2004,10 @@ struct pic_batch {
   std::vector<int32_t> order;       // table entry -> slot of the run in flight
   std::vector<int32_t> quota;       // per slot: steps of the run in flight
   bool inflight = false;            // launched, not yet waited for
+  bool single = false;              // the run in flight steps one context alone
   int64_t used = 0;
-  std::vector<hipGraphExec_t> exec; // [j]: a run of min(2^j, M) steps
+  std::vector<hipGraphExec_t> exec; // [2 j + r]: a run of min(2^j, M) steps; r: with the
+                                    // code of reflecting faces (some slot reflects)
   std::string msg = "no error";
 };
 
@@ -2045,16 +2047,18 @@ BatchTable table_of(const pic_batch *b) {
 }
 
 // The graph of a run of run_length(j) batched steps followed by the read-back
-// of the slots' re-bucketing requests (captured on first use).
-pic_status ensure_graph(pic_batch *b, int j) {
-  if (b->exec[j]) return PIC_OK;
+// of the slots' re-bucketing requests (captured on first use); refl: the step
+// kernel with the code of reflecting faces.
+pic_status ensure_graph(pic_batch *b, int j, bool refl) {
+  hipGraphExec_t &ex = b->exec[2 * j + (refl ? 1 : 0)];
+  if (ex) return PIC_OK;
   const BatchTable T = table_of(b);
   int32_t *flags_out = b->d_ctrl + 2 + b->cfg.steps_per_run;
   hipGraph_t graph = nullptr;
   PIC_BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < run_length(b, j) && le == hipSuccess; ++k)
-    le = launch_batch_step(b->cfg.repr, b->cfg.deposit, T, kBatchGrid, b->stream);
+    le = launch_batch_step(b->cfg.repr, b->cfg.deposit, refl, T, kBatchGrid, b->stream);
   if (le == hipSuccess) le = launch_batch_flags(T, flags_out, b->stream);
   hipError_t ce = hipStreamEndCapture(b->stream, &graph);
   if (le != hipSuccess) {
@@ -2062,10 +2066,10 @@ pic_status ensure_graph(pic_batch *b, int j) {
     return bhip(b, le, "batched step launch");
   }
   if (ce != hipSuccess) return bhip(b, ce, "hipStreamEndCapture");
-  hipError_t ie = hipGraphInstantiate(&b->exec[j], graph, nullptr, nullptr, 0);
+  hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) {
-    b->exec[j] = nullptr;
+    ex = nullptr;
     return bhip(b, ie, "hipGraphInstantiate");
   }
   return PIC_OK;
@@ -2153,7 +2157,7 @@ pic_status pic_batch_create(const pic_batch_config *cfg, pic_batch **out) {
   b->quota.assign(n, 0);
   int nj = 1;
   while (run_length(b, nj - 1) < M) ++nj;
-  b->exec.assign(nj, nullptr);
+  b->exec.assign(2 * nj, nullptr);
   *out = b;
   return PIC_OK;
 }
@@ -2271,6 +2275,25 @@ pic_status pic_batch_launch(pic_batch *b) {
     }
     b->quota[k] = (int32_t)std::min<int64_t>(qk, b->remaining[k]);
   }
+  if (S == 1) {
+    // one context runs: its steps go through the single-context kernels, as
+    // pic_step launches them (the same per-tile code, no persistent work
+    // queue), then its overflow counts come back for the re-planning request
+    const int k = order[0];
+    pic_ctx *c = b->ctx[k];
+    StepParams sp = step_params(c);
+    for (int t = 0; t < b->quota[k]; ++t) {
+      PIC_BHIP(b, launch_step_clear(c->rho, c->L.nodes * rho_elem(c->cfg.deposit),
+                                    sp.bins.ovf[1 - sp.cur], c->L.ns, b->stream));
+      PIC_BHIP(b, launch_step(c->cfg.repr, c->cfg.deposit, true, sp, b->stream));
+      sp.cur = 1 - sp.cur;
+    }
+    PIC_BHIP(b, hipMemcpyAsync((void *)c->ovf_host, sp.bins.ovf[sp.cur],
+                               sizeof(int32_t) * c->L.ns, hipMemcpyDeviceToHost, b->stream));
+    b->single = true;
+    b->inflight = true;
+    return PIC_OK;
+  }
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return b->quota[x] > b->quota[y]; });
   // the table: entry i holds slot order[i]; the work items of step t are
@@ -2298,16 +2321,19 @@ pic_status pic_batch_launch(pic_batch *b) {
   const int32_t len = b->quota[order[0]];
   int j = 0;
   while (run_length(b, j) < len) ++j;
-  if (pic_status st = ensure_graph(b, j)) return st;
+  bool refl = false;
+  for (int k : order) refl |= b->ctx[k]->cfg.reflect != 0;
+  if (pic_status st = ensure_graph(b, j, refl)) return st;
   PIC_BHIP(b, hipMemcpyAsync(b->d_slots, b->h_slots, sizeof(StepParams) * n,
                              hipMemcpyHostToDevice, b->stream));
   PIC_BHIP(b, hipMemcpyAsync(b->d_prefix, b->h_prefix, sizeof(int32_t) * (n + 1),
                              hipMemcpyHostToDevice, b->stream));
   PIC_BHIP(b, hipMemcpyAsync(b->d_ctrl, b->h_ctrl, sizeof(int32_t) * (2 + M),
                              hipMemcpyHostToDevice, b->stream));
-  PIC_BHIP(b, hipGraphLaunch(b->exec[j], b->stream));
+  PIC_BHIP(b, hipGraphLaunch(b->exec[2 * j + (refl ? 1 : 0)], b->stream));
   PIC_BHIP(b, hipMemcpyAsync(b->h_ctrl + 2 + M, b->d_ctrl + 2 + M, sizeof(int32_t) * S,
                              hipMemcpyDeviceToHost, b->stream));
+  b->single = false;
   b->inflight = true;
   return PIC_OK;
 }
@@ -2328,7 +2354,14 @@ pic_status pic_batch_wait(pic_batch *b, int32_t *n_done, int32_t *done_slots) {
     if (did & 1) c->cur = 1 - c->cur;
     c->since_sort += did;
     b->remaining[k] -= did;
-    b->want_sort[k] = b->h_ctrl[2 + M + i];
+    if (b->single) {
+      int32_t want = 0;
+      for (int s = 0; s < c->L.ns; ++s)
+        if (c->ovf_host[s] > 0) want |= 1 << s;
+      b->want_sort[k] = want;
+    } else {
+      b->want_sort[k] = b->h_ctrl[2 + M + i];
+    }
     if (b->remaining[k] == 0) {
       if (done_slots) done_slots[nd] = k;
       ++nd;

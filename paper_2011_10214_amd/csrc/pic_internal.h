@@ -359,7 +359,8 @@ struct BatchTable {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_step(int repr, int deposit, bool push, const StepParams &p, hipStream_t s);
 // one batched step: clear rho of every running slot, step them, advance them
-hipError_t launch_batch_step(int repr, int deposit, const BatchTable &t, int32_t grid,
+// (refl: some slot has reflecting faces; else the kernel without that code)
+hipError_t launch_batch_step(int repr, int deposit, bool refl, const BatchTable &t, int32_t grid,
                              hipStream_t s);
 // the re-bucketing flags of the table's slots into out[nslots]
 hipError_t launch_batch_flags(const BatchTable &t, int32_t *out, hipStream_t s);

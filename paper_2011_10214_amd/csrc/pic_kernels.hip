@@ -904,7 +904,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == PIC
 typedef const __attribute__((address_space(4))) StepParams ConstStep;
 typedef const __attribute__((address_space(4))) int32_t ConstI32;
 
-template <int R, int D>
+template <int R, int D, bool REFL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == PIC_REPR_FP32_CELL ? 5 : 1))) void batch_step_kernel(BatchTable B) {
   __shared__ int32_t sItem;
   ConstStep *slots = (ConstStep *)B.slots;
@@ -923,7 +923,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == PIC
       else hi = mid - 1;
     }
     const StepParams &P = *(const StepParams *)(slots + lo);
-    if (P.remaining > 0) step_block<R, D, true>(P, b - prefix[lo]);
+    if (P.remaining > 0) step_block<R, D, true, REFL>(P, b - prefix[lo]);
   }
 }
 
@@ -1678,20 +1678,24 @@ hipError_t launch_step(int repr, int deposit, bool push, const StepParams &p, hi
 }
 
 template <int R, int D>
-hipError_t launch_batch_rd(const BatchTable &t, int32_t grid, hipStream_t s) {
+hipError_t launch_batch_rd(bool refl, const BatchTable &t, int32_t grid, hipStream_t s) {
   const int64_t eb = D == PIC_DEP_ATOMIC_FP32 ? 4 : 8;
   hipLaunchKernelGGL(batch_clear_kernel, dim3(64, t.nslots), dim3(256), 0, s, t, eb);
-  hipLaunchKernelGGL((batch_step_kernel<R, D>), dim3(grid), dim3(kBlock), 0, s, t);
+  if (refl)
+    hipLaunchKernelGGL((batch_step_kernel<R, D, true>), dim3(grid), dim3(kBlock), 0, s, t);
+  else
+    hipLaunchKernelGGL((batch_step_kernel<R, D, false>), dim3(grid), dim3(kBlock), 0, s, t);
   hipLaunchKernelGGL(batch_advance_kernel, dim3(1), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
 template <int R>
-hipError_t launch_batch_r(int deposit, const BatchTable &t, int32_t grid, hipStream_t s) {
+hipError_t launch_batch_r(int deposit, bool refl, const BatchTable &t, int32_t grid,
+                          hipStream_t s) {
   switch (deposit) {
-    case PIC_DEP_FIXED64: return launch_batch_rd<R, PIC_DEP_FIXED64>(t, grid, s);
-    case PIC_DEP_ATOMIC_FP32: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP32>(t, grid, s);
-    case PIC_DEP_ATOMIC_FP64: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP64>(t, grid, s);
+    case PIC_DEP_FIXED64: return launch_batch_rd<R, PIC_DEP_FIXED64>(refl, t, grid, s);
+    case PIC_DEP_ATOMIC_FP32: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP32>(refl, t, grid, s);
+    case PIC_DEP_ATOMIC_FP64: return launch_batch_rd<R, PIC_DEP_ATOMIC_FP64>(refl, t, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -1701,13 +1705,13 @@ hipError_t launch_batch_flags(const BatchTable &t, int32_t *out, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_batch_step(int repr, int deposit, const BatchTable &t, int32_t grid,
+hipError_t launch_batch_step(int repr, int deposit, bool refl, const BatchTable &t, int32_t grid,
                              hipStream_t s) {
   if (t.nslots <= 0 || grid <= 0) return hipSuccess;
   switch (repr) {
-    case PIC_REPR_FP64: return launch_batch_r<PIC_REPR_FP64>(deposit, t, grid, s);
-    case PIC_REPR_FP32_ABS: return launch_batch_r<PIC_REPR_FP32_ABS>(deposit, t, grid, s);
-    case PIC_REPR_FP32_CELL: return launch_batch_r<PIC_REPR_FP32_CELL>(deposit, t, grid, s);
+    case PIC_REPR_FP64: return launch_batch_r<PIC_REPR_FP64>(deposit, refl, t, grid, s);
+    case PIC_REPR_FP32_ABS: return launch_batch_r<PIC_REPR_FP32_ABS>(deposit, refl, t, grid, s);
+    case PIC_REPR_FP32_CELL: return launch_batch_r<PIC_REPR_FP32_CELL>(deposit, refl, t, grid, s);
   }
   return hipErrorInvalidValue;
 }

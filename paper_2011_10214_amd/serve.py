@@ -141,13 +141,15 @@ class BatchExecutor:
         self.stream = stream
         self.policy = policy
         self.slots = {}   # slot -> (request, context)
+        self.retired = []  # finished (context, bytes), freed once the next run is launched
 
     def footprint(self, req: Request) -> int:
         return pic.footprint_bytes(req.cfg)
 
     def fits(self, req: Request) -> bool:
+        held = sum(b for _, b in self.retired)  # detached, not yet freed
         return (len(self.slots) < self.batch.max_slots and
-                self.batch.used_bytes + req.footprint <= self.batch.budget)
+                self.batch.used_bytes + held + req.footprint <= self.batch.budget)
 
     def admit(self, req: Request) -> None:
         cfg = req.cfg
@@ -185,6 +187,7 @@ class BatchExecutor:
             for k in self.slots:
                 self.batch.set_weight(k, wh if k == head else 1.0)
         self.batch.launch()
+        self._free_retired()
 
     def wait(self) -> list:
         done = []
@@ -193,11 +196,19 @@ class BatchExecutor:
             self.batch.detach(slot)
             if req.collect:
                 req.result = req.collect(ctx)
-            ctx.close()
+            self.retired.append((ctx, req.footprint))
             done.append(req)
+        if not self.slots:
+            self._free_retired()
         return done
 
+    def _free_retired(self):
+        for ctx, _ in self.retired:
+            ctx.close()
+        self.retired.clear()
+
     def close(self):
+        self._free_retired()
         for slot, (_, ctx) in list(self.slots.items()):
             self.batch.detach(slot)
             ctx.close()
@@ -271,7 +282,10 @@ def serve(requests: list, executor, clock: Callable[[], float] = time.perf_count
                 on_admit(r, executor)
 
     while queue or executor.busy():
-        admit_arrived()
+        # with runs in progress the next run is launched first, so that the
+        # GPU does not wait while new requests are created and loaded
+        if not (overlap and executor.busy()):
+            admit_arrived()
         now = clock() - t0
         if executor.busy():
             if overlap:
