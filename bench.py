@@ -229,9 +229,11 @@ def serving_run(args):
     M, P = args.steps_per_run, int(args.ps_per_run)
     prio = dict(policy="priority", backfill=args.backfill, saturation=int(args.saturation))
     for name, kw in [("priority", prio),
-                     ("priority_backfill_5pct", dict(prio, backfill=0.05)),
-                     ("head_half", dict(policy="head")),
-                     ("fair_share", dict(policy="fair"))]:
+                     ("priority_prefetch_2", dict(prio, prefetch=2)),
+                     ("priority_prefetch_4", dict(prio, prefetch=4)),
+                     ("priority_prefetch_8", dict(prio, prefetch=8)),
+                     ("priority_prefetch_120M_particles", dict(prio, prefetch_particles=120_000_000)),
+                     ("priority_fifo", dict(prio, saturation=0))]:
         ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
                            steps_per_run=M, hbm_budget_bytes=budget, particle_steps_per_run=P,
                            **kw)

@@ -53,6 +53,12 @@ __device__ __forceinline__ void f_ijk(const Gd &P, int64_t q, int &i, int &j, in
   i = (int)(rem - jj * sx);
 }
 
+// The operator of a grid: node-centred finite volumes with one permittivity
+// (kOpFV) or with the object as an interface (kOpIF, link permittivities), or
+// immersed finite elements (kOpIFE, the fine grid only; the multigrid's
+// coarser levels keep the finite volumes).
+enum { kOpFV = 0, kOpIF = 1, kOpIFE = 2 };
+
 // Visits the links of node (i, j, k) in the order -x, +x, -y, +y, -z, +z:
 // f(q, w) with q the neighbour's node index.
 // The same, f(q, w, i', j', k') with the neighbour's indices as well.
@@ -131,12 +137,6 @@ __device__ __forceinline__ double f_link_eps(const Gd &L, const FieldParams &P, 
   return nb < q ? f_eps(L.psi[nb], L.psi[q], P.e_in, P.e_out)
                 : f_eps(L.psi[q], L.psi[nb], P.e_in, P.e_out);
 }
-
-// The operator of a grid: node-centred finite volumes with one permittivity
-// (kOpFV) or with the object as an interface (kOpIF, link permittivities), or
-// immersed finite elements (kOpIFE, the fine grid only; the multigrid's
-// coarser levels keep the finite volumes).
-enum { kOpFV = 0, kOpIF = 1, kOpIFE = 2 };
 
 // Visits the links of fine-grid node q = (i, j, k) of the IFE operator:
 // f(nb, c, i', j', k') with c = -A_q,nb. A node away from the box faces whose
@@ -454,9 +454,9 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
     auto e1n = [&](int64_t nb, int a2, int b2, int c2) {
       return f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<OP>(L, a2, b2, c2, nb);
     };
-    if constexpr (OP == kOpIFE) {
-      ife_links(P, i, j, k, q, [&](int64_t nb, double c, int a2, int b2, int c2) {
-        a = a + c * (e1 - e1n(nb, a2, b2, c2));
+    if constexpr (OP == kOpIFE) {  // the neighbours' e1 from mg_e1_kernel
+      ife_links(P, i, j, k, q, [&](int64_t nb, double c, int, int, int) {
+        a = a + c * (e1 - L.e2[nb]);
       });
       L.e[q] = e1 + kOmega * (bq - a) / d;
       continue;
@@ -472,6 +472,21 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
     }
     const double Ae1 = IF ? (uni ? cq * a : a * L.ih2) : L.s * a;
     L.e[q] = e1 + kOmega * (bq - Ae1) / d;
+  }
+}
+
+// IFE finest level: the first (pointwise) sweep from zero, e1 = w b / d, into
+// e2 (unused until the post-smoothing), so that the second sweep of
+// mg_pre_kernel reads it at its up to 18 neighbours instead of evaluating it
+// there (two loads and a division each); the values are the same.
+__global__ __launch_bounds__(kBlock) void mg_e1_kernel(FieldParams P, int l) {
+  if (f_done(f_ctrl(P), P)) return;  // uniform
+  const MgLevel &L = P.lv[l];
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+       q += (int64_t)gridDim.x * kBlock) {
+    int i, j, k;
+    f_ijk(L, q, i, j, k);
+    L.e2[q] = f_dir(L, i, j, k) ? 0.0 : kOmega * L.rhs[q] / mg_D<kOpIFE>(L, i, j, k, q);
   }
 }
 
@@ -910,6 +925,8 @@ static void field_vcycle(const FieldParams &p, int prz, hipStream_t s) {
   const int L = p.levels;
   for (int l = 0; l + 1 < L; ++l) {
     if (l == 0) {
+      if constexpr (O0 == kOpIFE)
+        hipLaunchKernelGGL(mg_e1_kernel, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
       hipLaunchKernelGGL(mg_pre_kernel<O0>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
       hipLaunchKernelGGL(mg_res_kernel<O0>, dim3(p.lv[l].G), dim3(kBlock), 0, s, p, l);
     } else {

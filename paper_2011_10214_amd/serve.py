@@ -118,15 +118,20 @@ class BatchExecutor:
                     on a GPU of ``saturation`` particles (plus ``backfill``
                     times the head's particles, 0 by default), with up to M
                     steps per run each; the others wait paused on the device
-                    (priority_weights).
+                    (priority_weights), at most ``prefetch`` of them (or
+                    ``prefetch_particles`` of their particles) admitted ahead
+                    (None: as many as slots and memory allow).
     """
 
     def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
                  hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0,
                  policy: str = "fair", head_share: float = 0.5, backfill: float = 0.0,
-                 saturation: int = 20_000_000):
+                 saturation: int = 20_000_000, prefetch: Optional[int] = None,
+                 prefetch_particles: Optional[int] = None):
         if policy not in ("fair", "head", "priority"):
             raise ValueError(f"unknown policy {policy!r}")
+        if prefetch is not None and prefetch < 1:
+            raise ValueError("prefetch must be >= 1 (or None)")
         if not 0.0 < head_share < 1.0:
             raise ValueError("head_share must be in (0, 1)")
         if not backfill >= 0.0:
@@ -141,6 +146,15 @@ class BatchExecutor:
         self.stream = stream
         self.policy = policy
         self.slots = {}   # slot -> (request, context)
+        # at most this many admitted requests wait paused (None: no limit):
+        # creating and loading a request that will not run for a while puts
+        # its GPU work in front of the requests ahead of it
+        self.prefetch = prefetch
+        # the same bound on their particles (their loading work): a request is
+        # admitted while the waiting ones and it hold at most this many, or
+        # when none waits
+        self.prefetch_particles = prefetch_particles
+        self.last_w = {}  # slot -> weight of the last launch
         self.retired = []  # finished (context, bytes), freed once the next run is launched
 
     def footprint(self, req: Request) -> int:
@@ -148,6 +162,15 @@ class BatchExecutor:
 
     def fits(self, req: Request) -> bool:
         held = sum(b for _, b in self.retired)  # detached, not yet freed
+        if self.policy == "priority":
+            # slots admitted since the last launch count as waiting
+            waiting = [k for k in self.slots if self.last_w.get(k, 0.0) <= 0.0]
+            if self.prefetch is not None and len(waiting) >= self.prefetch:
+                return False
+            if self.prefetch_particles is not None and waiting:
+                held_n = sum(self.slots[k][0].particles for k in waiting)
+                if held_n + req.particles > self.prefetch_particles:
+                    return False
         return (len(self.slots) < self.batch.max_slots and
                 self.batch.used_bytes + held + req.footprint <= self.batch.budget)
 
@@ -180,6 +203,7 @@ class BatchExecutor:
                                  self.backfill, self.saturation)
             for k, wk in w.items():
                 self.batch.set_weight(k, wk)
+            self.last_w = w
         elif self.policy == "head" and len(self.slots) > 1:
             head = min(self.slots, key=lambda k: (self.slots[k][0].arrival, self.slots[k][0].rid))
             others = len(self.slots) - 1

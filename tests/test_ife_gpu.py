@@ -70,6 +70,25 @@ def test_ife_capacitor_with_a_fractional_interface_matches_the_oracle(precond):
     assert 1e-5 < np.abs(phi - exact).max() < 0.01 * V0
 
 
+@pytest.mark.parametrize("dims", [(15, 12, 24), (16, 13, 8), (15, 15, 15)])
+def test_ife_on_odd_cell_counts_matches_the_oracle(dims):
+    # an even number of nodes along x (odd cell count) gives the enumeration
+    # of the finest level by node parity a padding slot in every row; odd
+    # cell counts elsewhere keep the grid from coarsening (Jacobi-PCG)
+    nx, ny, nz = dims
+    V0, eps_in, z_flat = 1.5, 4.0, 0.37 * nz
+    with empty_crater_context(dims, z_flat) as ctx:
+        ctx.solve_field(ZM | ZP, values=[0, 0, 0, 0, V0, 0], tol=1e-13, max_iter=5000,
+                        eps_object=eps_in, op="ife")
+        phi = ctx.get_phi()
+    obj = oracle.FieldObject(kind="crater", eps_in=eps_in, center=(-1000.0, -1000.0, 0.0),
+                             z_flat=z_flat, rim_radius=1.0, depth=0.5)
+    ref, _, _ = oracle.field_solve(nx, ny, nz, np.zeros((nx + 1) * (ny + 1) * (nz + 1)), ZM | ZP,
+                                   values=[0, 0, 0, 0, V0, 0], tol=1e-13, max_iter=5000, obj=obj,
+                                   op="ife")
+    assert np.abs(phi - ref).max() < 1e-10 * V0
+
+
 def run_and_solve(w, form, patches, nsteps, mask, eps_in, tol, max_iter, precond="multigrid",
                   surface=True):
     sp, x, v, E = inputs(w)

@@ -282,3 +282,51 @@ def test_priority_serving_keeps_every_request_moving_to_completion():
     reqs = _requests(150, 3, rate=30.0)
     st = serve(reqs, Prio(vc, 8, 10 ** 9), clock=vc.clock, sleep=vc.sleep)
     assert st["requests"] == len(reqs)
+
+
+def test_prefetch_limits_the_requests_admitted_to_wait():
+    # the executor's admission test alone (no device): with prefetch 1 a
+    # second request that would wait paused is not admitted; one that runs
+    # (weight > 0 in the last launch) does not count
+    from paper_2011_10214_amd.serve import BatchExecutor
+
+    class FakeBatch:
+        max_slots, used_bytes, budget = 8, 0, 1 << 40
+
+    ex = object.__new__(BatchExecutor)
+    ex.batch, ex.retired, ex.policy, ex.prefetch = FakeBatch(), [], "priority", 1
+    ex.slots, ex.last_w, ex.prefetch_particles = {}, {}, None
+    r = _req(5, 1.0, 1000)
+    r.footprint = 1
+    assert ex.fits(r)                         # nothing waits yet
+    ex.slots = {0: (None, None), 1: (None, None)}
+    ex.last_w = {0: 3.0}                      # slot 1: admitted since the launch
+    assert not ex.fits(r)
+    ex.last_w = {0: 3.0, 1: 2.0}              # both run
+    assert ex.fits(r)
+    ex.last_w = {0: 3.0, 1: 0.0}              # slot 1 waits paused
+    assert not ex.fits(r)
+    ex.prefetch = None
+    assert ex.fits(r)
+    ex.policy, ex.prefetch, ex.last_w = "fair", 1, {}
+    assert ex.fits(r)                         # only the priority policy pauses
+
+
+def test_prefetch_particles_bounds_the_loading_moved_ahead():
+    from paper_2011_10214_amd.serve import BatchExecutor
+
+    class FakeBatch:
+        max_slots, used_bytes, budget = 8, 0, 1 << 40
+
+    ex = object.__new__(BatchExecutor)
+    ex.batch, ex.retired, ex.policy, ex.prefetch = FakeBatch(), [], "priority", None
+    ex.prefetch_particles = 5000
+    big, small = _req(1, 0.1, 4000), _req(2, 0.2, 800)
+    ex.slots = {0: (_req(0, 0.0, 9000), None), 1: (big, None)}
+    ex.last_w = {0: 9000.0, 1: 0.0}           # the large request waits
+    r = _req(3, 0.3, 1500)
+    r.footprint = small.footprint = 1
+    assert not ex.fits(r)                     # 4000 + 1500 > 5000
+    assert ex.fits(small)                     # 4000 + 800
+    ex.last_w = {0: 9000.0, 1: 4000.0}        # nothing waits: any request
+    assert ex.fits(_req(4, 0.4, 10 ** 9))
