@@ -222,18 +222,17 @@ def serving_run(args):
         f"p99 {seq['latency_p99_s']:.2f} s, mean {seq['latency_mean_s']:.2f} s")
     batched = {}
     # priority: the oldest request runs, younger ones beside it only in the
-    # room a small one leaves on the GPU; priority with backfill: and in a
-    # share of a large one's runs; head half: the oldest running request
-    # gets half of a run's particle-steps, the others share the rest; fair
-    # share: equal shares
+    # room a small one leaves on the GPU; prefetch 2: at most two admitted
+    # to wait; fifo: nothing beside the head (strict arrival order); head
+    # half: the oldest running request gets half of a run's particle-steps,
+    # the others share the rest; fair share: equal shares
     M, P = args.steps_per_run, int(args.ps_per_run)
     prio = dict(policy="priority", backfill=args.backfill, saturation=int(args.saturation))
     for name, kw in [("priority", prio),
                      ("priority_prefetch_2", dict(prio, prefetch=2)),
-                     ("priority_prefetch_4", dict(prio, prefetch=4)),
-                     ("priority_prefetch_8", dict(prio, prefetch=8)),
-                     ("priority_prefetch_120M_particles", dict(prio, prefetch_particles=120_000_000)),
-                     ("priority_fifo", dict(prio, saturation=0))]:
+                     ("priority_fifo", dict(prio, saturation=0)),
+                     ("head_half", dict(policy="head")),
+                     ("fair_share", dict(policy="fair"))]:
         ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
                            steps_per_run=M, hbm_budget_bytes=budget, particle_steps_per_run=P,
                            **kw)
