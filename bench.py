@@ -230,6 +230,8 @@ def serving_run(args):
     prio = dict(policy="priority", backfill=args.backfill, saturation=int(args.saturation))
     for name, kw in [("priority", prio),
                      ("priority_prefetch_2", dict(prio, prefetch=2)),
+                     ("priority_prefetch_large_1", dict(prio, prefetch_large=1)),
+                     ("priority_prefetch_large_2", dict(prio, prefetch_large=2)),
                      ("priority_fifo", dict(prio, saturation=0)),
                      ("head_half", dict(policy="head")),
                      ("fair_share", dict(policy="fair"))]:

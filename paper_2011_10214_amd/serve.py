@@ -119,15 +119,17 @@ class BatchExecutor:
                     times the head's particles, 0 by default), with up to M
                     steps per run each; the others wait paused on the device
                     (priority_weights), at most ``prefetch`` of them (or
-                    ``prefetch_particles`` of their particles) admitted ahead
-                    (None: as many as slots and memory allow).
+                    ``prefetch_particles`` of their particles, or
+                    ``prefetch_large`` of those with at least ``saturation``
+                    particles) admitted ahead (None: as many as slots and
+                    memory allow).
     """
 
     def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
                  hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0,
                  policy: str = "fair", head_share: float = 0.5, backfill: float = 0.0,
                  saturation: int = 20_000_000, prefetch: Optional[int] = None,
-                 prefetch_particles: Optional[int] = None):
+                 prefetch_particles: Optional[int] = None, prefetch_large: Optional[int] = None):
         if policy not in ("fair", "head", "priority"):
             raise ValueError(f"unknown policy {policy!r}")
         if prefetch is not None and prefetch < 1:
@@ -154,6 +156,10 @@ class BatchExecutor:
         # admitted while the waiting ones and it hold at most this many, or
         # when none waits
         self.prefetch_particles = prefetch_particles
+        # the same count for the large requests only (at least `saturation`
+        # particles: they can never run beside a head, and their loading is
+        # the expensive one); small ones keep flowing
+        self.prefetch_large = prefetch_large
         self.last_w = {}  # slot -> weight of the last launch
         self.retired = []  # finished (context, bytes), freed once the next run is launched
 
@@ -170,6 +176,10 @@ class BatchExecutor:
             if self.prefetch_particles is not None and waiting:
                 held_n = sum(self.slots[k][0].particles for k in waiting)
                 if held_n + req.particles > self.prefetch_particles:
+                    return False
+            if self.prefetch_large is not None and req.particles >= self.saturation:
+                large = sum(1 for k in waiting if self.slots[k][0].particles >= self.saturation)
+                if large >= self.prefetch_large:
                     return False
         return (len(self.slots) < self.batch.max_slots and
                 self.batch.used_bytes + held + req.footprint <= self.batch.budget)

@@ -295,7 +295,7 @@ def test_prefetch_limits_the_requests_admitted_to_wait():
 
     ex = object.__new__(BatchExecutor)
     ex.batch, ex.retired, ex.policy, ex.prefetch = FakeBatch(), [], "priority", 1
-    ex.slots, ex.last_w, ex.prefetch_particles = {}, {}, None
+    ex.slots, ex.last_w, ex.prefetch_particles, ex.prefetch_large = {}, {}, None, None
     r = _req(5, 1.0, 1000)
     r.footprint = 1
     assert ex.fits(r)                         # nothing waits yet
@@ -320,7 +320,7 @@ def test_prefetch_particles_bounds_the_loading_moved_ahead():
 
     ex = object.__new__(BatchExecutor)
     ex.batch, ex.retired, ex.policy, ex.prefetch = FakeBatch(), [], "priority", None
-    ex.prefetch_particles = 5000
+    ex.prefetch_particles, ex.prefetch_large = 5000, None
     big, small = _req(1, 0.1, 4000), _req(2, 0.2, 800)
     ex.slots = {0: (_req(0, 0.0, 9000), None), 1: (big, None)}
     ex.last_w = {0: 9000.0, 1: 0.0}           # the large request waits
@@ -330,3 +330,23 @@ def test_prefetch_particles_bounds_the_loading_moved_ahead():
     assert ex.fits(small)                     # 4000 + 800
     ex.last_w = {0: 9000.0, 1: 4000.0}        # nothing waits: any request
     assert ex.fits(_req(4, 0.4, 10 ** 9))
+
+
+def test_prefetch_large_counts_only_requests_that_cannot_run_beside_a_head():
+    from paper_2011_10214_amd.serve import BatchExecutor
+
+    class FakeBatch:
+        max_slots, used_bytes, budget = 8, 0, 1 << 40
+
+    ex = object.__new__(BatchExecutor)
+    ex.batch, ex.retired, ex.policy = FakeBatch(), [], "priority"
+    ex.prefetch, ex.prefetch_particles, ex.prefetch_large, ex.saturation = None, None, 1, 1000
+    ex.slots = {0: (_req(0, 0.0, 5000), None), 1: (_req(1, 0.1, 3000), None),
+                2: (_req(2, 0.2, 50), None)}
+    ex.last_w = {0: 5000.0, 1: 0.0, 2: 0.0}    # a large and a small one wait
+    large, small = _req(3, 0.3, 2000), _req(4, 0.4, 60)
+    large.footprint = small.footprint = 1
+    assert not ex.fits(large)                  # one large request waits already
+    assert ex.fits(small)                      # small ones are not counted
+    ex.last_w = {0: 5000.0, 1: 3000.0, 2: 0.0}
+    assert ex.fits(large)
