@@ -43,7 +43,7 @@ def _threads():
     return max(1, min(16, n))
 
 
-# sampled particles per species: 1/64 of sphere_64 (SURVEY's subsample for the
+# sampled particles per species: 1/64 of sphere_64 (the subsample of the
 # FP32 vs FP64 comparison at 64^3 over 100 steps), 2^18 of crater_160
 SAMPLED = {"sphere_64": lambda count: np.arange(0, count, 64),
            "crater_160": None}
