@@ -60,28 +60,32 @@ __device__ __forceinline__ void f_ijk(const Gd &P, int64_t q, int &i, int &j, in
 enum { kOpFV = 0, kOpIF = 1, kOpIFE = 2 };
 
 // Visits the links of node (i, j, k) in the order -x, +x, -y, +y, -z, +z:
-// f(q, w) with q the neighbour's node index.
-// The same, f(q, w, i', j', k') with the neighbour's indices as well.
+// f(q, w, i', j', k') with q the neighbour's node index and (i', j', k') its
+// indices. Every node has all six: a link that would leave the box names the
+// neighbour on the opposite side (every axis of a grid has at least one cell)
+// with weight 0, and every use of it adds an exact zero (a link term is a
+// weight times a finite difference or coefficient). Without a branch per link
+// the loads of a stencil are independent of each other and issue together,
+// instead of one memory latency after another; the stand-in is a node other
+// than the centre so that the compiler cannot reuse the centre's value and
+// turn the load back into a branch.
 template <class Gd, class F>
 __device__ __forceinline__ void f_links_n(const Gd &P, int i, int j, int k, int64_t q0, F f) {
   const double cx = f_c(i, P.n[0]), cy = f_c(j, P.n[1]), cz = f_c(k, P.n[2]);
-  if (i > 0) f(q0 - 1, cy * cz, i - 1, j, k);
-  if (i < P.n[0]) f(q0 + 1, cy * cz, i + 1, j, k);
-  if (j > 0) f(q0 - P.sx, cx * cz, i, j - 1, k);
-  if (j < P.n[1]) f(q0 + P.sx, cx * cz, i, j + 1, k);
-  if (k > 0) f(q0 - P.sy, cx * cy, i, j, k - 1);
-  if (k < P.n[2]) f(q0 + P.sy, cx * cy, i, j, k + 1);
+  const bool xm = i > 0, xp = i < P.n[0], ym = j > 0, yp = j < P.n[1];
+  const bool zm = k > 0, zp = k < P.n[2];
+  f(xm ? q0 - 1 : q0 + 1, xm ? cy * cz : 0.0, xm ? i - 1 : i + 1, j, k);
+  f(xp ? q0 + 1 : q0 - 1, xp ? cy * cz : 0.0, xp ? i + 1 : i - 1, j, k);
+  f(ym ? q0 - P.sx : q0 + P.sx, ym ? cx * cz : 0.0, i, ym ? j - 1 : j + 1, k);
+  f(yp ? q0 + P.sx : q0 - P.sx, yp ? cx * cz : 0.0, i, yp ? j + 1 : j - 1, k);
+  f(zm ? q0 - P.sy : q0 + P.sy, zm ? cx * cy : 0.0, i, j, zm ? k - 1 : k + 1);
+  f(zp ? q0 + P.sy : q0 - P.sy, zp ? cx * cy : 0.0, i, j, zp ? k + 1 : k - 1);
 }
 
+// The same, f(q, w).
 template <class Gd, class F>
 __device__ __forceinline__ void f_links(const Gd &P, int i, int j, int k, int64_t q0, F f) {
-  const double cx = f_c(i, P.n[0]), cy = f_c(j, P.n[1]), cz = f_c(k, P.n[2]);
-  if (i > 0) f(q0 - 1, cy * cz);
-  if (i < P.n[0]) f(q0 + 1, cy * cz);
-  if (j > 0) f(q0 - P.sx, cx * cz);
-  if (j < P.n[1]) f(q0 + P.sx, cx * cz);
-  if (k > 0) f(q0 - P.sy, cx * cy);
-  if (k < P.n[2]) f(q0 + P.sy, cx * cy);
+  f_links_n(P, i, j, k, q0, [&](int64_t nb, double w, int, int, int) { f(nb, w); });
 }
 
 // Sum over the workgroup (fixed tree order); the result in every thread.
@@ -138,46 +142,62 @@ __device__ __forceinline__ double f_link_eps(const Gd &L, const FieldParams &P, 
                 : f_eps(L.psi[q], L.psi[nb], P.e_in, P.e_out);
 }
 
-// Visits the links of fine-grid node q = (i, j, k) of the IFE operator:
-// f(nb, c, i', j', k') with c = -A_q,nb. A node away from the box faces whose
-// tetrahedra the interface does not cut (srow < 0) has eps of its side times
-// the reference links of its parity (a node of odd parity has no face
-// diagonals); the others have their assembled row.
-template <class F>
+// The same for the six links of a node at once: the seven level-set loads
+// first, then the permittivities.
+template <class Gd>
+__device__ __forceinline__ void f_link_eps6(const Gd &L, const FieldParams &P, int64_t q,
+                                            const int64_t nb[6], double eps[6]) {
+  const double pq = L.psi[q];
+  double pn[6];
+#pragma unroll
+  for (int l = 0; l < 6; ++l) pn[l] = L.psi[nb[l]];
+#pragma unroll
+  for (int l = 0; l < 6; ++l)
+    eps[l] = nb[l] < q ? f_eps(pn[l], pq, P.e_in, P.e_out) : f_eps(pq, pn[l], P.e_in, P.e_out);
+}
+
+// Visits the links of fine-grid node q = (i, j, k) of the IFE operator in
+// two passes: first val[l] = v(nb, i', j', k') for each of the 18 links l,
+// the neighbour's index and indices (clamped into the box where the link
+// leaves it), then f(c, val[l], i', j', k') with c = -A_q,nb (0 for a link the
+// node does not have: an exact zero term). The first pass depends on the
+// indices alone, so its loads issue together with the row's. A node away from
+// the box faces whose tetrahedra the interface does not cut (srow < 0) has
+// eps of its side times the reference links of its parity (a node of odd
+// parity has no face diagonals); the others have their assembled row.
+template <class V, class F>
 __device__ __forceinline__ void ife_links(const FieldParams &P, int i, int j, int k, int64_t q,
-                                          F f) {
+                                          V v, F f) {
+  int ni[kIfeLinks], nj[kIfeLinks], nk[kIfeLinks];
+  double val[kIfeLinks];
+#pragma unroll
+  for (int l = 0; l < kIfeLinks; ++l) {
+    int o[3];
+    ife_link_offset(l, o);
+    // (a link leaving the box: its neighbour clamped into the box, a node
+    // other than q, so that the load stays unconditional)
+    ni[l] = min(max(i + o[0], 0), P.n[0]);
+    nj[l] = min(max(j + o[1], 0), P.n[1]);
+    nk[l] = min(max(k + o[2], 0), P.n[2]);
+    val[l] = v(q + (ni[l] - i) + P.sx * (nj[l] - j) + P.sy * (nk[l] - k), ni[l], nj[l], nk[l]);
+  }
   const int32_t r = P.srow[q];
   if (r < 0) {
-    // (the loops are unrolled: offsets and coefficients are constants of
-    // the launch, the parity only selects between two of them)
+    // (the coefficients are constants of the launch, the parity only selects
+    // between two of them)
     const bool odd = ((i + j + k) & 1) != 0;
     const double e = (P.iface && P.psi[q] < 0.0) ? P.e_in : P.e_out;
 #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      int o[3];
-      ife_link_offset(l, o);
-      const double c = e * (odd ? P.rl[1][l] : P.rl[0][l]);
-      f(q + o[0] + P.sx * o[1] + P.sy * o[2], c, i + o[0], j + o[1], k + o[2]);
-    }
-    if (!odd) {  // the face diagonals join nodes of even parity only
+    for (int l = 0; l < 6; ++l)
+      f(e * (odd ? P.rl[1][l] : P.rl[0][l]), val[l], ni[l], nj[l], nk[l]);
 #pragma unroll
-      for (int l = 6; l < kIfeLinks; ++l) {
-        int o[3];
-        ife_link_offset(l, o);
-        f(q + o[0] + P.sx * o[1] + P.sy * o[2], e * P.rl[0][l], i + o[0], j + o[1], k + o[2]);
-      }
-    }
+    for (int l = 6; l < kIfeLinks; ++l)  // the face diagonals join nodes of even parity only
+      f(odd ? 0.0 : e * P.rl[0][l], val[l], ni[l], nj[l], nk[l]);
     return;
   }
   const double *row = P.rows + (int64_t)r * (kIfeLinks + 1);
 #pragma unroll
-  for (int l = 0; l < kIfeLinks; ++l) {
-    const double c = row[l];
-    if (c == 0.0) continue;  // no link (outside the box)
-    int o[3];
-    ife_link_offset(l, o);
-    f(q + o[0] + P.sx * o[1] + P.sy * o[2], c, i + o[0], j + o[1], k + o[2]);
-  }
+  for (int l = 0; l < kIfeLinks; ++l) f(row[l], val[l], ni[l], nj[l], nk[l]);
 }
 
 // (A x) at an unknown node q of a grid (the fine grid or a level)
@@ -187,17 +207,30 @@ __device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const 
   const double xq = x[q];
   double a = 0.0;
   if constexpr (OP == kOpIFE) {
-    ife_links(P, i, j, k, q, [&](int64_t nb, double c, int, int, int) { a = a + c * (xq - x[nb]); });
+    ife_links(
+        P, i, j, k, q, [&](int64_t nb, int, int, int) { return x[nb]; },
+        [&](double c, double xn, int, int, int) { a = a + c * (xq - xn); });
     return a;
   } else if constexpr (OP == kOpIF) {
     const double cq = L.cq[q];
+    int64_t nb[6];
+    double w[6], d[6];
+    int n = 0;
+    f_links(L, i, j, k, q, [&](int64_t m, double wl) {
+      nb[n] = m;
+      w[n] = wl;
+      d[n] = xq - x[m];
+      ++n;
+    });
     if (cq > 0.0) {  // all six links of one permittivity (nearly every node)
-      f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (xq - x[nb]); });
+#pragma unroll
+      for (int l = 0; l < 6; ++l) a = a + w[l] * d[l];
       return cq * a;
     }
-    f_links(L, i, j, k, q, [&](int64_t nb, double w) {
-      a = a + (f_link_eps(L, P, q, nb) * w) * (xq - x[nb]);
-    });
+    double eps[6];
+    f_link_eps6(L, P, q, nb, eps);
+#pragma unroll
+    for (int l = 0; l < 6; ++l) a = a + (eps[l] * w[l]) * d[l];
     return a * L.ih2;
   } else {
     f_links(L, i, j, k, q, [&](int64_t nb, double w) { a = a + w * (xq - x[nb]); });
@@ -226,19 +259,22 @@ __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
     const double rho = f_rho<D>(P, q);
     double ax = 0.0, dsum = 0.0, b = rho;
     if constexpr (OP == kOpIFE) {
-      ife_links(P, i, j, k, q, [&](int64_t nb, double c, int a, int cc, int e) {
-        const bool nd = f_dir(P, a, cc, e);
-        const double xn = nd ? f_gval(P, a, cc, e) : P.x[nb];
-        ax = ax + c * (xq - xn);
-        dsum = dsum + c;
-        if (nd) b = b + c * xn;
-      });
+      ife_links(
+          P, i, j, k, q,
+          [&](int64_t nb, int a, int cc, int e) {
+            const double xl = P.x[nb];
+            return f_dir(P, a, cc, e) ? f_gval(P, a, cc, e) : xl;
+          },
+          [&](double c, double xn, int a, int cc, int e) {
+            ax = ax + c * (xq - xn);
+            dsum = dsum + c;
+            if (f_dir(P, a, cc, e)) b = b + c * xn;
+          });
     } else
-    f_links(P, i, j, k, q, [&](int64_t nb, double w) {
-      int a, c, e;
-      f_ijk(P, nb, a, c, e);
+    f_links_n(P, i, j, k, q, [&](int64_t nb, double w, int a, int c, int e) {
       const bool nd = f_dir(P, a, c, e);
-      const double xn = nd ? f_gval(P, a, c, e) : P.x[nb];
+      const double xl = P.x[nb];
+      const double xn = nd ? f_gval(P, a, c, e) : xl;
       if constexpr (IF) {
         const double cq = P.cq[q];
         const double cw = cq > 0.0 ? cq * w : (f_link_eps(P, P, q, nb) * w) * P.ih2;
@@ -436,7 +472,7 @@ template <int OP>
 __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
   constexpr bool IF = OP == kOpIF;
   if (f_done(f_ctrl(P), P)) return;  // uniform
-  const MgLevel &L = P.lv[l];
+  const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
@@ -451,24 +487,35 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
     double a = 0.0;
     const double cq = IF ? L.cq[q] : 0.0;
     const bool uni = !IF || cq > 0.0;  // one permittivity on all six links
+    // (0 at a Dirichlet neighbour, whose diagonal is positive as well: a
+    // product instead of a branch keeps the loads unconditional)
     auto e1n = [&](int64_t nb, int a2, int b2, int c2) {
-      return f_dir(L, a2, b2, c2) ? 0.0 : kOmega * L.rhs[nb] / mg_D<OP>(L, a2, b2, c2, nb);
+      return ((f_dir(L, a2, b2, c2) ? 0.0 : kOmega) * L.rhs[nb]) / mg_D<OP>(L, a2, b2, c2, nb);
     };
     if constexpr (OP == kOpIFE) {  // the neighbours' e1 from mg_e1_kernel
-      ife_links(P, i, j, k, q, [&](int64_t nb, double c, int, int, int) {
-        a = a + c * (e1 - L.e2[nb]);
-      });
+      ife_links(
+          P, i, j, k, q, [&](int64_t nb, int, int, int) { return L.e2[nb]; },
+          [&](double c, double e1n, int, int, int) { a = a + c * (e1 - e1n); });
       L.e[q] = e1 + kOmega * (bq - a) / d;
       continue;
     }
+    int64_t nbs[6];
+    double w[6], de[6];
+    int n = 0;
+    f_links_n(L, i, j, k, q, [&](int64_t nb, double wl, int a2, int b2, int c2) {
+      nbs[n] = nb;
+      w[n] = wl;
+      de[n] = e1 - e1n(nb, a2, b2, c2);
+      ++n;
+    });
     if (uni) {
-      f_links_n(L, i, j, k, q, [&](int64_t nb, double w, int a2, int b2, int c2) {
-        a = a + w * (e1 - e1n(nb, a2, b2, c2));
-      });
+#pragma unroll
+      for (int m = 0; m < 6; ++m) a = a + w[m] * de[m];
     } else {
-      f_links_n(L, i, j, k, q, [&](int64_t nb, double w, int a2, int b2, int c2) {
-        a = a + (f_link_eps(L, P, q, nb) * w) * (e1 - e1n(nb, a2, b2, c2));
-      });
+      double eps[6];
+      f_link_eps6(L, P, q, nbs, eps);
+#pragma unroll
+      for (int m = 0; m < 6; ++m) a = a + (eps[m] * w[m]) * de[m];
     }
     const double Ae1 = IF ? (uni ? cq * a : a * L.ih2) : L.s * a;
     L.e[q] = e1 + kOmega * (bq - Ae1) / d;
@@ -481,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
 // there (two loads and a division each); the values are the same.
 __global__ __launch_bounds__(kBlock) void mg_e1_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
-  const MgLevel &L = P.lv[l];
+  const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
@@ -494,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void mg_e1_kernel(FieldParams P, int l) {
 template <int OP>
 __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
-  const MgLevel &L = P.lv[l];
+  const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
@@ -507,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
 // of its 3x3x3 fine neighbourhood (in the box) with weights 1 or 1/2 per axis.
 __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
-  const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
+  const MgLevel F = P.lv[l], C = P.lv[l + 1];
   for (int64_t Q = (int64_t)blockIdx.x * kBlock + threadIdx.x; Q < C.nodes;
        Q += (int64_t)gridDim.x * kBlock) {
     int I, J, K;
@@ -516,24 +563,34 @@ __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int 
       C.rhs[Q] = 0.0;
       continue;
     }
+    // (a fine node outside the box contributes weight 0 at the coarse node's
+    // own fine node, so that all 27 loads are unconditional)
     const int i0 = 2 * I, j0 = 2 * J, k0 = 2 * K;
-    double v = 0.0;
+    double r[27], wt[27];
+#pragma unroll
     for (int dk = -1; dk <= 1; ++dk) {
       const int k = k0 + dk;
-      if (k < 0 || k > F.n[2]) continue;
-      const double wk = dk == 0 ? 1.0 : 0.5;
+      const bool kin = k >= 0 && k <= F.n[2];
+      const double wk = !kin ? 0.0 : dk == 0 ? 1.0 : 0.5;
+#pragma unroll
       for (int dj = -1; dj <= 1; ++dj) {
         const int j = j0 + dj;
-        if (j < 0 || j > F.n[1]) continue;
-        const double wjk = wk * (dj == 0 ? 1.0 : 0.5);
-        const double *row = F.res + (int64_t)k * F.sy + (int64_t)j * F.sx;
+        const bool jin = j >= 0 && j <= F.n[1];
+        const double wjk = wk * (!jin ? 0.0 : dj == 0 ? 1.0 : 0.5);
+        const double *row = F.res + (int64_t)(kin ? k : k0) * F.sy + (int64_t)(jin ? j : j0) * F.sx;
+#pragma unroll
         for (int di = -1; di <= 1; ++di) {
           const int i = i0 + di;
-          if (i < 0 || i > F.n[0]) continue;
-          v = v + wjk * (di == 0 ? 1.0 : 0.5) * row[i];
+          const bool iin = i >= 0 && i <= F.n[0];
+          const int t = 9 * (dk + 1) + 3 * (dj + 1) + (di + 1);
+          wt[t] = wjk * (!iin ? 0.0 : di == 0 ? 1.0 : 0.5);
+          r[t] = row[iin ? i : i0];
         }
       }
     }
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) v = v + wt[t] * r[t];
     C.rhs[Q] = v * 0.125;
   }
 }
@@ -542,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int 
 // the right-hand side gathered into LDS.
 __global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
-  const MgLevel &C = P.lv[P.levels - 1];
+  const MgLevel C = P.lv[P.levels - 1];
   __shared__ double sb[kCoarseNodes];
   const int m = P.m;
   for (int v = threadIdx.x; v < m; v += kBlock) sb[v] = C.rhs[P.umap[v]];
@@ -566,21 +623,37 @@ __global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
 // e += P e_c (trilinear: per axis the coarse node itself, or the mean of two)
 __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
-  const MgLevel &F = P.lv[l], &C = P.lv[l + 1];
+  const MgLevel F = P.lv[l], C = P.lv[l + 1];
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < F.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(F, q, i, j, k);
     if (f_dir(F, i, j, k)) continue;
+    // (always 2 x 2 x 2 coarse nodes: along an even axis the second one is
+    // the first again with weight 0, so that the loads are unconditional)
     const int ni = 1 + (i & 1), nj = 1 + (j & 1), nk = 1 + (k & 1);
     const double wi = (i & 1) ? 0.5 : 1.0, wj = (j & 1) ? 0.5 : 1.0, wk = (k & 1) ? 0.5 : 1.0;
-    double v = 0.0;
-    for (int c = 0; c < nk; ++c)
-      for (int b = 0; b < nj; ++b) {
-        const double *row = C.e + (int64_t)(k / 2 + c) * C.sy + (int64_t)(j / 2 + b) * C.sx;
-        for (int a = 0; a < ni; ++a) v = v + (wi * wj * wk) * row[i / 2 + a];
+    const double w = wi * wj * wk;
+    const double eq = F.e[q];
+    double ec[8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double *row = C.e + (int64_t)(k / 2 + (c < nk ? c : 0)) * C.sy +
+                            (int64_t)(j / 2 + (b < nj ? b : 0)) * C.sx;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) ec[4 * c + 2 * b + a] = row[i / 2 + (a < ni ? a : 0)];
       }
-    F.e[q] += v;
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          v = v + ((a < ni && b < nj && c < nk) ? w : 0.0) * ec[4 * c + 2 * b + a];
+    F.e[q] = eq + v;
   }
 }
 
@@ -589,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l
 template <bool Dot, int OP>
 __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, int to_e2, int prz) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
-  const MgLevel &L = P.lv[l];
+  const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
   const double *in = to_e2 ? L.e : L.e2;
   double *out = to_e2 ? L.e2 : L.e;
   double rz = 0.0;
@@ -614,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, 
 
 // Level set of the object at the nodes of level l (< 0 inside; fine cell units).
 __global__ __launch_bounds__(kBlock) void field_psi_kernel(FieldParams P, int l) {
-  const MgLevel &L = P.lv[l];
+  const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
   const FieldGeom &o = P.geo;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
        q += (int64_t)gridDim.x * kBlock) {
@@ -637,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void field_psi_kernel(FieldParams P, int l)
 
 // Diagonal of A at the nodes of level l: sum of the link coefficients.
 __global__ __launch_bounds__(kBlock) void field_diag_kernel(FieldParams P, int l) {
-  const MgLevel &L = P.lv[l];
+  const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
