@@ -1493,9 +1493,9 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
     for (int l = 0; l < nl; ++l) {
       if (c->mg[l].psi) continue;
       void **const outs[3] = {(void **)&c->mg[l].psi, (void **)&c->mg[l].diag,
-                              (void **)&c->mg[l].cq};
+                              (void **)&c->mg[l].side};
       const int64_t b = c->mg[l].nodes * 8;
-      const int64_t bytes[3] = {b, b, b};
+      const int64_t bytes[3] = {b, b, c->mg[l].nodes};
       if (!dmalloc_all(c, 3, outs, bytes))
         return fail(c, PIC_E_NOMEM, "device memory allocation failed");
     }
@@ -1567,7 +1567,7 @@ pic_status pic_solve_field(pic_ctx *c, const pic_field *fs, int32_t *iterations,
   P.geo = geo;
   P.psi = c->mg[0].psi;
   P.diag = c->mg[0].diag;
-  P.cq = c->mg[0].cq;
+  P.side = c->mg[0].side;
   P.ih2 = c->mg[0].ih2;
   const int pe = prof_begin(c, 4);
   if (iface) {  // level sets once, diagonals when the permittivities change

@@ -102,11 +102,47 @@ __device__ double block_sum(double v) {
   return t;
 }
 
-// Sum of G partials, the same value in every workgroup.
+// Sum of G partials, the same value in every workgroup. A thread adds its
+// partials t, t + kBlock, ... in that order; they are loaded eight at a time,
+// so that the loads are in flight together.
 __device__ double sum_partials(const double *part, int G) {
   double v = 0.0;
-  for (int t = threadIdx.x; t < G; t += kBlock) v = v + part[t];
+  int t = threadIdx.x;
+  for (; t + 7 * kBlock < G; t += 8 * kBlock) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = part[t + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v = v + a[u];
+  }
+  for (; t < G; t += kBlock) v = v + part[t];
   return block_sum(v);
+}
+
+// The quotient of two such sums (numerator partials a, denominator b), both
+// loaded before either is added up.
+__device__ double ratio_partials(const double *a, const double *b, int G) {
+  double va = 0.0, vb = 0.0;
+  int t = threadIdx.x;
+  for (; t + 7 * kBlock < G; t += 8 * kBlock) {
+    double xa[8], xb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      xa[u] = a[t + u * kBlock];
+      xb[u] = b[t + u * kBlock];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      va = va + xa[u];
+      vb = vb + xb[u];
+    }
+  }
+  for (; t < G; t += kBlock) {
+    va = va + a[t];
+    vb = vb + b[t];
+  }
+  const double sa = block_sum(va);
+  return sa / block_sum(vb);
 }
 
 // Density at a node: the deposit, plus the surface source when there is one
@@ -154,6 +190,24 @@ __device__ __forceinline__ void f_link_eps6(const Gd &L, const FieldParams &P, i
 #pragma unroll
   for (int l = 0; l < 6; ++l)
     eps[l] = nb[l] < q ? f_eps(pn[l], pq, P.e_in, P.e_out) : f_eps(pq, pn[l], P.e_in, P.e_out);
+}
+
+// eps / h^2 of a node whose links all lie on one side (side 1 or 2)
+template <class Gd>
+__device__ __forceinline__ double f_cside(const FieldParams &P, const Gd &L, int sd) {
+  return (sd == 2 ? P.e_in : P.e_out) * L.ih2;
+}
+
+// The diagonal of A at such a node: its link permittivity times the link
+// weights, added in link order, times 1/h^2, as field_diag_kernel forms it
+// for the stored diagonal (the same value).
+template <class Gd>
+__device__ __forceinline__ double f_dside(const FieldParams &P, const Gd &L, int i, int j, int k,
+                                          int64_t q, int sd) {
+  const double e = sd == 2 ? P.e_in : P.e_out;
+  double d = 0.0;
+  f_links(L, i, j, k, q, [&](int64_t, double w) { d = d + e * w; });
+  return d * L.ih2;
 }
 
 // Visits the links of fine-grid node q = (i, j, k) of the IFE operator in
@@ -212,7 +266,7 @@ __device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const 
         [&](double c, double xn, int, int, int) { a = a + c * (xq - xn); });
     return a;
   } else if constexpr (OP == kOpIF) {
-    const double cq = L.cq[q];
+    const int sd = L.side[q];
     int64_t nb[6];
     double w[6], d[6];
     int n = 0;
@@ -222,10 +276,10 @@ __device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const 
       d[n] = xq - x[m];
       ++n;
     });
-    if (cq > 0.0) {  // all six links of one permittivity (nearly every node)
+    if (sd != 0) {  // all six links of one permittivity (nearly every node)
 #pragma unroll
       for (int l = 0; l < 6; ++l) a = a + w[l] * d[l];
-      return cq * a;
+      return f_cside(P, L, sd) * a;
     }
     double eps[6];
     f_link_eps6(L, P, q, nb, eps);
@@ -276,8 +330,8 @@ __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
       const double xl = P.x[nb];
       const double xn = nd ? f_gval(P, a, c, e) : xl;
       if constexpr (IF) {
-        const double cq = P.cq[q];
-        const double cw = cq > 0.0 ? cq * w : (f_link_eps(P, P, q, nb) * w) * P.ih2;
+        const int sd = P.side[q];
+        const double cw = sd != 0 ? f_cside(P, P, sd) * w : (f_link_eps(P, P, q, nb) * w) * P.ih2;
         ax = ax + cw * (xq - xn);
         dsum = dsum + cw;
         if (nd) b = b + cw * xn;
@@ -359,7 +413,7 @@ template <bool J, int OP>
 __global__ __launch_bounds__(kBlock) void field_update_kernel(FieldParams P, int o) {
   if (f_done(f_ctrl(P), P)) return;  // uniform
   const int n = 1 - o;
-  const double alpha = sum_partials(P.part + (1 + o) * P.G, P.G) / sum_partials(P.part, P.G);
+  const double alpha = ratio_partials(P.part + (1 + o) * P.G, P.part, P.G);
   double rz = 0.0, rr = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
        q += (int64_t)gridDim.x * kBlock) {
@@ -426,8 +480,7 @@ __global__ __launch_bounds__(kBlock) void field_dir_kernel(FieldParams P, int o)
   if constexpr (J) {
     if (f_check(P, c, o, blockIdx.x == 0)) return;  // uniform
   }
-  const double beta = sum_partials(P.part + (1 + n) * P.G, P.G) /
-                      sum_partials(P.part + (1 + o) * P.G, P.G);
+  const double beta = ratio_partials(P.part + (1 + n) * P.G, P.part + (1 + o) * P.G, P.G);
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < P.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
@@ -460,10 +513,30 @@ __device__ __forceinline__ double f_dsum(const Gd &L, int i, int j, int k) {
 }
 
 // diagonal of A at an unknown node of a level
+// (the interface: the stored diagonal only at a node with a link across it;
+// sd the node's side code, already loaded)
 template <int OP>
-__device__ __forceinline__ double mg_D(const MgLevel &L, int i, int j, int k, int64_t q) {
-  if constexpr (OP != kOpFV) return L.diag[q];
-  else return L.s * f_dsum(L, i, j, k);
+__device__ __forceinline__ double mg_Ds(const FieldParams &P, const MgLevel &L, int i, int j,
+                                        int k, int64_t q, int sd) {
+  if constexpr (OP == kOpIF) {
+    if (sd == 0) return L.diag[q];
+    // off the box faces all six weights are 1: the sum is e + e + ... + e
+    if (i > 0 && i < L.n[0] && j > 0 && j < L.n[1] && k > 0 && k < L.n[2]) {
+      const double e = sd == 2 ? P.e_in : P.e_out;
+      return (((((e + e) + e) + e) + e) + e) * L.ih2;
+    }
+    return f_dside(P, L, i, j, k, q, sd);
+  } else if constexpr (OP == kOpIFE) {
+    return L.diag[q];
+  } else {
+    return L.s * f_dsum(L, i, j, k);
+  }
+}
+
+template <int OP>
+__device__ __forceinline__ double mg_D(const FieldParams &P, const MgLevel &L, int i, int j, int k,
+                                       int64_t q) {
+  return mg_Ds<OP>(P, L, i, j, k, q, OP == kOpIF ? L.side[q] : 1);
 }
 
 // e = two sweeps from zero: e1 = w b / d is pointwise, so the second sweep
@@ -481,31 +554,33 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
       L.e[q] = 0.0;
       continue;
     }
-    const double d = mg_D<OP>(L, i, j, k, q);
     const double bq = L.rhs[q];
-    const double e1 = kOmega * bq / d;
+    const int sd = IF ? L.side[q] : 1;
     double a = 0.0;
-    const double cq = IF ? L.cq[q] : 0.0;
-    const bool uni = !IF || cq > 0.0;  // one permittivity on all six links
-    // (0 at a Dirichlet neighbour, whose diagonal is positive as well: a
-    // product instead of a branch keeps the loads unconditional)
-    auto e1n = [&](int64_t nb, int a2, int b2, int c2) {
-      return ((f_dir(L, a2, b2, c2) ? 0.0 : kOmega) * L.rhs[nb]) / mg_D<OP>(L, a2, b2, c2, nb);
-    };
     if constexpr (OP == kOpIFE) {  // the neighbours' e1 from mg_e1_kernel
+      const double d = mg_Ds<OP>(P, L, i, j, k, q, sd);
+      const double e1 = kOmega * bq / d;
       ife_links(
           P, i, j, k, q, [&](int64_t nb, int, int, int) { return L.e2[nb]; },
           [&](double c, double e1n, int, int, int) { a = a + c * (e1 - e1n); });
       L.e[q] = e1 + kOmega * (bq - a) / d;
       continue;
     }
+    const bool uni = sd != 0;  // one permittivity on all six links
+    // (the interface: the stored diagonals, at the node and its neighbours,
+    // all loaded together with the right-hand sides)
+    const double d = IF ? L.diag[q] : mg_Ds<OP>(P, L, i, j, k, q, sd);
+    const double e1 = kOmega * bq / d;
     int64_t nbs[6];
     double w[6], de[6];
     int n = 0;
+    // e1 at a neighbour, 0 at a Dirichlet one (whose diagonal is positive as
+    // well: a product instead of a branch keeps the loads unconditional)
     f_links_n(L, i, j, k, q, [&](int64_t nb, double wl, int a2, int b2, int c2) {
       nbs[n] = nb;
       w[n] = wl;
-      de[n] = e1 - e1n(nb, a2, b2, c2);
+      const double dn = IF ? L.diag[nb] : mg_Ds<OP>(P, L, a2, b2, c2, nb, 1);
+      de[n] = e1 - ((f_dir(L, a2, b2, c2) ? 0.0 : kOmega) * L.rhs[nb]) / dn;
       ++n;
     });
     if (uni) {
@@ -517,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
 #pragma unroll
       for (int m = 0; m < 6; ++m) a = a + (eps[m] * w[m]) * de[m];
     }
-    const double Ae1 = IF ? (uni ? cq * a : a * L.ih2) : L.s * a;
+    const double Ae1 = IF ? (uni ? f_cside(P, L, sd) * a : a * L.ih2) : L.s * a;
     L.e[q] = e1 + kOmega * (bq - Ae1) / d;
   }
 }
@@ -533,7 +608,7 @@ __global__ __launch_bounds__(kBlock) void mg_e1_kernel(FieldParams P, int l) {
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(L, q, i, j, k);
-    L.e2[q] = f_dir(L, i, j, k) ? 0.0 : kOmega * L.rhs[q] / mg_D<kOpIFE>(L, i, j, k, q);
+    L.e2[q] = f_dir(L, i, j, k) ? 0.0 : kOmega * L.rhs[q] / mg_D<kOpIFE>(P, L, i, j, k, q);
   }
 }
 
@@ -675,7 +750,7 @@ __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, 
       continue;
     }
     const double bq = L.rhs[q];
-    const double v = in[q] + kOmega * (bq - f_Ax<OP>(P, L, in, i, j, k, q)) / mg_D<OP>(L, i, j, k, q);
+    const double v = in[q] + kOmega * (bq - f_Ax<OP>(P, L, in, i, j, k, q)) / mg_D<OP>(P, L, i, j, k, q);
     out[q] = v;
     if constexpr (Dot) rz = rz + bq * v;
   }
@@ -723,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void field_diag_kernel(FieldParams P, int l
       uni = uni && ((L.psi[nb] < 0.0) == in);
     });
     L.diag[q] = d * L.ih2;
-    L.cq[q] = uni ? (in ? P.e_in : P.e_out) * L.ih2 : -1.0;
+    L.side[q] = uni ? (in ? 2 : 1) : 0;
   }
 }
 

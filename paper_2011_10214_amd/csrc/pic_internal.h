@@ -272,9 +272,11 @@ struct MgLevel {
   double *e, *e2, *res, *rhs;  // correction (ping-pong), residual, right-hand side
   int32_t G;                   // workgroups of the level's kernels: one node per thread
   // object as an interface: level set and diagonal of A at the level's nodes;
-  // cq: eps / h_l^2 of a node whose six links lie on its side of the
-  // interface (all one permittivity), -1 for a node with a crossing link
-  double *psi, *diag, *cq;
+  // side: 1 for a node whose six links lie outside the object (all of
+  // permittivity eps), 2 for one whose links all lie inside, 0 for a node
+  // with a link across the interface (only these read diag in the solve)
+  double *psi, *diag;
+  int8_t *side;
   double ih2;                  // 1 / h_l^2
   double scale;                // fine cells per cell of the level
 };
@@ -313,7 +315,8 @@ struct FieldParams {
   // the fine level (= lv[0].psi / lv[0].diag), geometry; surface source
   int32_t iface;
   double e_in, e_out;
-  const double *psi, *diag, *cq;
+  const double *psi, *diag;
+  const int8_t *side;
   double ih2;
   FieldGeom geo;
   const int64_t *rho_surf;  // fixed-point surface charge (nullable)
