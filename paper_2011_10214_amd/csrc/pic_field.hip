@@ -254,6 +254,49 @@ __device__ __forceinline__ void ife_links(const FieldParams &P, int i, int j, in
   for (int l = 0; l < kIfeLinks; ++l) f(row[l], val[l], ni[l], nj[l], nk[l]);
 }
 
+// The values of x that (A x) at node q reads at its six links, loaded (the
+// finite-volume operators).
+struct Nb6 {
+  int64_t nb[6];
+  double w[6], xn[6];
+};
+
+template <class Gd>
+__device__ __forceinline__ void f_gather6(const Gd &L, const double *x, int i, int j, int k,
+                                          int64_t q, Nb6 &g) {
+  int n = 0;
+  f_links(L, i, j, k, q, [&](int64_t m, double wl) {
+    g.nb[n] = m;
+    g.w[n] = wl;
+    g.xn[n] = x[m];
+    ++n;
+  });
+}
+
+// (A x) at q from the gathered values: xq = x[q], sd the node's side code
+// (the interface operator).
+template <int OP, class Gd>
+__device__ __forceinline__ double f_Ax6(const FieldParams &P, const Gd &L, int64_t q, double xq,
+                                        int sd, const Nb6 &g) {
+  double a = 0.0;
+  if constexpr (OP == kOpIF) {
+    if (sd != 0) {  // all six links of one permittivity (nearly every node)
+#pragma unroll
+      for (int l = 0; l < 6; ++l) a = a + g.w[l] * (xq - g.xn[l]);
+      return f_cside(P, L, sd) * a;
+    }
+    double eps[6];
+    f_link_eps6(L, P, q, g.nb, eps);
+#pragma unroll
+    for (int l = 0; l < 6; ++l) a = a + (eps[l] * g.w[l]) * (xq - g.xn[l]);
+    return a * L.ih2;
+  } else {
+#pragma unroll
+    for (int l = 0; l < 6; ++l) a = a + g.w[l] * (xq - g.xn[l]);
+    return L.s * a;
+  }
+}
+
 // (A x) at an unknown node q of a grid (the fine grid or a level)
 template <int OP, class Gd>
 __device__ __forceinline__ double f_Ax(const FieldParams &P, const Gd &L, const double *x, int i,
@@ -324,23 +367,45 @@ __global__ __launch_bounds__(kBlock) void field_init_kernel(FieldParams P) {
             dsum = dsum + c;
             if (f_dir(P, a, cc, e)) b = b + c * xn;
           });
-    } else
-    f_links_n(P, i, j, k, q, [&](int64_t nb, double w, int a, int c, int e) {
-      const bool nd = f_dir(P, a, c, e);
-      const double xl = P.x[nb];
-      const double xn = nd ? f_gval(P, a, c, e) : xl;
+    } else {
+      // the neighbours' values first (their loads together), then the terms
+      int64_t nbs[6];
+      double w[6], xn[6], cw[6];
+      bool nd[6];
+      int n = 0;
+      f_links_n(P, i, j, k, q, [&](int64_t nb, double wl, int a, int c, int e) {
+        nbs[n] = nb;
+        w[n] = wl;
+        nd[n] = f_dir(P, a, c, e);
+        const double xl = P.x[nb];
+        xn[n] = nd[n] ? f_gval(P, a, c, e) : xl;
+        ++n;
+      });
       if constexpr (IF) {
         const int sd = P.side[q];
-        const double cw = sd != 0 ? f_cside(P, P, sd) * w : (f_link_eps(P, P, q, nb) * w) * P.ih2;
-        ax = ax + cw * (xq - xn);
-        dsum = dsum + cw;
-        if (nd) b = b + cw * xn;
-      } else {
-        ax = ax + w * (xq - xn);
-        dsum = dsum + w;
-        if (nd) b = b + P.s * w * xn;
+        if (sd != 0) {
+#pragma unroll
+          for (int l = 0; l < 6; ++l) cw[l] = f_cside(P, P, sd) * w[l];
+        } else {
+          double eps[6];
+          f_link_eps6(P, P, q, nbs, eps);
+#pragma unroll
+          for (int l = 0; l < 6; ++l) cw[l] = (eps[l] * w[l]) * P.ih2;
+        }
       }
-    });
+#pragma unroll
+      for (int l = 0; l < 6; ++l) {
+        if constexpr (IF) {
+          ax = ax + cw[l] * (xq - xn[l]);
+          dsum = dsum + cw[l];
+          if (nd[l]) b = b + cw[l] * xn[l];
+        } else {
+          ax = ax + w[l] * (xq - xn[l]);
+          dsum = dsum + w[l];
+          if (nd[l]) b = b + P.s * w[l] * xn[l];
+        }
+      }
+    }
     const double r = OP != kOpFV ? rho - ax : rho - P.s * ax;
     const double z = OP != kOpFV ? r / dsum : r / (P.s * dsum);
     P.r[q] = r;
@@ -387,6 +452,37 @@ __device__ __forceinline__ FieldCtrl f_ctrl(const FieldParams &P) {
 __device__ __forceinline__ bool f_done(const FieldCtrl &c, const FieldParams &P) {
   return c.converged != 0 || c.iters >= P.max_iter;
 }
+
+// The early exit of a kernel that does not write the control block: every
+// thread loads the block itself (no workgroup barrier) with its data, in the
+// same pass over its node, and tests it only after f_issued, so that the two
+// latencies overlap instead of adding up.
+__device__ __forceinline__ int2 f_ctl(const FieldParams &P) {
+  // (converged and iters, the first two words of the block, in one load; an
+  // opaque zero offset keeps the compiler from treating the value as uniform
+  // and moving it to a scalar register at once, which would wait for it)
+  static_assert(offsetof(FieldCtrl, converged) == 0 && offsetof(FieldCtrl, iters) == 4, "");
+  int z = 0;
+  __asm__ __volatile__("" : "+v"(z));
+  return reinterpret_cast<const int2 *>(P.ctrl)[z];
+}
+
+// Compiler barrier: the loads written above it stay above it, and the test of
+// the control block c stays below it (the loads are in flight when the code
+// first waits, for c).
+__device__ __forceinline__ void f_issued(int2 &c) {
+  __asm__ __volatile__("" : "+v"(c.x), "+v"(c.y) : : "memory");
+}
+
+__device__ __forceinline__ bool f_stop(int2 c, const FieldParams &P) {
+  return (c.x != 0) | (c.y >= P.max_iter);
+}
+
+// kFineExit: the kernels on the fine level (l == 0, or restricting from it)
+// still test the block first and return before their loads: a V-cycle
+// enqueued after the solve has converged then costs a few microseconds per
+// fine-level kernel instead of a full pass over 2 M nodes, while on the small
+// coarse levels the overlap saves more than the loads cost.
 
 // Ap = A p; partial p.Ap
 template <int OP>
@@ -544,56 +640,78 @@ __device__ __forceinline__ double mg_D(const FieldParams &P, const MgLevel &L, i
 template <int OP>
 __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
   constexpr bool IF = OP == kOpIF;
-  if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)gridDim.x * kBlock) {
-    int i, j, k;
-    f_ijk(L, q, i, j, k);
-    if (f_dir(L, i, j, k)) {
-      L.e[q] = 0.0;
-      continue;
-    }
-    const double bq = L.rhs[q];
-    const int sd = IF ? L.side[q] : 1;
-    double a = 0.0;
-    if constexpr (OP == kOpIFE) {  // the neighbours' e1 from mg_e1_kernel
-      const double d = mg_Ds<OP>(P, L, i, j, k, q, sd);
+  if constexpr (OP == kOpIFE) {  // the neighbours' e1 from mg_e1_kernel
+    if (f_done(f_ctrl(P), P)) return;  // uniform
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+         q += (int64_t)gridDim.x * kBlock) {
+      int i, j, k;
+      f_ijk(L, q, i, j, k);
+      if (f_dir(L, i, j, k)) {
+        L.e[q] = 0.0;
+        continue;
+      }
+      const double bq = L.rhs[q];
+      const double d = mg_D<OP>(P, L, i, j, k, q);
       const double e1 = kOmega * bq / d;
+      double a = 0.0;
       ife_links(
           P, i, j, k, q, [&](int64_t nb, int, int, int) { return L.e2[nb]; },
           [&](double c, double e1n, int, int, int) { a = a + c * (e1 - e1n); });
       L.e[q] = e1 + kOmega * (bq - a) / d;
-      continue;
     }
-    const bool uni = sd != 0;  // one permittivity on all six links
-    // (the interface: the stored diagonals, at the node and its neighbours,
-    // all loaded together with the right-hand sides)
-    const double d = IF ? L.diag[q] : mg_Ds<OP>(P, L, i, j, k, q, sd);
-    const double e1 = kOmega * bq / d;
-    int64_t nbs[6];
-    double w[6], de[6];
-    int n = 0;
-    // e1 at a neighbour, 0 at a Dirichlet one (whose diagonal is positive as
-    // well: a product instead of a branch keeps the loads unconditional)
-    f_links_n(L, i, j, k, q, [&](int64_t nb, double wl, int a2, int b2, int c2) {
-      nbs[n] = nb;
-      w[n] = wl;
-      const double dn = IF ? L.diag[nb] : mg_Ds<OP>(P, L, a2, b2, c2, nb, 1);
-      de[n] = e1 - ((f_dir(L, a2, b2, c2) ? 0.0 : kOmega) * L.rhs[nb]) / dn;
-      ++n;
-    });
-    if (uni) {
+  } else {
+    if (l == 0 && f_done(f_ctrl(P), P)) return;  // uniform (see kFineExit)
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+         q += (int64_t)gridDim.x * kBlock) {
+      int i, j, k;
+      f_ijk(L, q, i, j, k);
+      int2 ctl = f_ctl(P);
+      if (f_dir(L, i, j, k)) {
+        if (f_stop(ctl, P)) return;  // uniform
+        L.e[q] = 0.0;
+        continue;
+      }
+      // loads: the node's right-hand side, side code and (the interface)
+      // stored diagonal, the same at its neighbours; the finite-volume
+      // diagonals are arithmetic
+      const double bq = L.rhs[q];
+      const int sd = IF ? L.side[q] : 1;
+      const double d = IF ? L.diag[q] : mg_Ds<OP>(P, L, i, j, k, q, sd);
+      int64_t nbs[6];
+      double w[6], bn[6], dn[6];
+      int dirm = 0, n = 0;
+      f_links_n(L, i, j, k, q, [&](int64_t nb, double wl, int a2, int b2, int c2) {
+        nbs[n] = nb;
+        w[n] = wl;
+        bn[n] = L.rhs[nb];
+        dn[n] = IF ? L.diag[nb] : mg_Ds<OP>(P, L, a2, b2, c2, nb, 1);
+        dirm |= f_dir(L, a2, b2, c2) ? 1 << n : 0;
+        ++n;
+      });
+      f_issued(ctl);
+      if (f_stop(ctl, P)) return;  // uniform
+      const double e1 = kOmega * bq / d;
+      // e1 at a neighbour, 0 at a Dirichlet one (whose diagonal is positive
+      // as well: a product instead of a branch)
+      double de[6];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) a = a + w[m] * de[m];
-    } else {
-      double eps[6];
-      f_link_eps6(L, P, q, nbs, eps);
+      for (int m = 0; m < 6; ++m)
+        de[m] = e1 - ((((dirm >> m) & 1) ? 0.0 : kOmega) * bn[m]) / dn[m];
+      double a = 0.0;
+      const bool uni = sd != 0;  // one permittivity on all six links
+      if (uni) {
 #pragma unroll
-      for (int m = 0; m < 6; ++m) a = a + (eps[m] * w[m]) * de[m];
+        for (int m = 0; m < 6; ++m) a = a + w[m] * de[m];
+      } else {
+        double eps[6];
+        f_link_eps6(L, P, q, nbs, eps);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) a = a + (eps[m] * w[m]) * de[m];
+      }
+      const double Ae1 = IF ? (uni ? f_cside(P, L, sd) * a : a * L.ih2) : L.s * a;
+      L.e[q] = e1 + kOmega * (bq - Ae1) / d;
     }
-    const double Ae1 = IF ? (uni ? f_cside(P, L, sd) * a : a * L.ih2) : L.s * a;
-    L.e[q] = e1 + kOmega * (bq - Ae1) / d;
   }
 }
 
@@ -615,26 +733,50 @@ __global__ __launch_bounds__(kBlock) void mg_e1_kernel(FieldParams P, int l) {
 // res = b - A e
 template <int OP>
 __global__ __launch_bounds__(kBlock) void mg_res_kernel(FieldParams P, int l) {
-  if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)gridDim.x * kBlock) {
-    int i, j, k;
-    f_ijk(L, q, i, j, k);
-    L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - f_Ax<OP>(P, L, L.e, i, j, k, q);
+  if constexpr (OP == kOpIFE) {
+    if (f_done(f_ctrl(P), P)) return;  // uniform
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+         q += (int64_t)gridDim.x * kBlock) {
+      int i, j, k;
+      f_ijk(L, q, i, j, k);
+      L.res[q] = f_dir(L, i, j, k) ? 0.0 : L.rhs[q] - f_Ax<OP>(P, L, L.e, i, j, k, q);
+    }
+  } else {
+    if (l == 0 && f_done(f_ctrl(P), P)) return;  // uniform (see kFineExit)
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+         q += (int64_t)gridDim.x * kBlock) {
+      int i, j, k;
+      f_ijk(L, q, i, j, k);
+      int2 ctl = f_ctl(P);
+      if (f_dir(L, i, j, k)) {
+        if (f_stop(ctl, P)) return;  // uniform
+        L.res[q] = 0.0;
+        continue;
+      }
+      const double bq = L.rhs[q], eq = L.e[q];
+      const int sd = OP == kOpIF ? L.side[q] : 1;
+      Nb6 g;
+      f_gather6(L, L.e, i, j, k, q, g);
+      f_issued(ctl);
+      if (f_stop(ctl, P)) return;  // uniform
+      L.res[q] = bq - f_Ax6<OP>(P, L, q, eq, sd, g);
+    }
   }
 }
 
 // rhs of level l + 1 = P^T res / 8: a coarse node gathers the fine residuals
 // of its 3x3x3 fine neighbourhood (in the box) with weights 1 or 1/2 per axis.
 __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int l) {
-  if (f_done(f_ctrl(P), P)) return;  // uniform
+  if (l == 0 && f_done(f_ctrl(P), P)) return;  // uniform (see kFineExit)
   const MgLevel F = P.lv[l], C = P.lv[l + 1];
   for (int64_t Q = (int64_t)blockIdx.x * kBlock + threadIdx.x; Q < C.nodes;
        Q += (int64_t)gridDim.x * kBlock) {
     int I, J, K;
     f_ijk(C, Q, I, J, K);
+    int2 ctl = f_ctl(P);
     if (f_dir(C, I, J, K)) {
+      if (f_stop(ctl, P)) return;  // uniform
       C.rhs[Q] = 0.0;
       continue;
     }
@@ -663,6 +805,8 @@ __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int 
         }
       }
     }
+    f_issued(ctl);
+    if (f_stop(ctl, P)) return;  // uniform
     double v = 0.0;
 #pragma unroll
     for (int t = 0; t < 27; ++t) v = v + wt[t] * r[t];
@@ -673,11 +817,13 @@ __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int 
 // e of the coarsest level = A^-1 rhs on its m unknowns: one wave per row,
 // the right-hand side gathered into LDS.
 __global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
-  if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel C = P.lv[P.levels - 1];
   __shared__ double sb[kCoarseNodes];
   const int m = P.m;
+  int2 ctl = f_ctl(P);
   for (int v = threadIdx.x; v < m; v += kBlock) sb[v] = C.rhs[P.umap[v]];
+  f_issued(ctl);
+  if (f_stop(ctl, P)) return;  // uniform
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < C.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
@@ -697,13 +843,14 @@ __global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
 
 // e += P e_c (trilinear: per axis the coarse node itself, or the mean of two)
 __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l) {
-  if (f_done(f_ctrl(P), P)) return;  // uniform
+  if (l == 0 && f_done(f_ctrl(P), P)) return;  // uniform (see kFineExit)
   const MgLevel F = P.lv[l], C = P.lv[l + 1];
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < F.nodes;
        q += (int64_t)gridDim.x * kBlock) {
     int i, j, k;
     f_ijk(F, q, i, j, k);
     if (f_dir(F, i, j, k)) continue;
+    int2 ctl = f_ctl(P);
     // (always 2 x 2 x 2 coarse nodes: along an even axis the second one is
     // the first again with weight 0, so that the loads are unconditional)
     const int ni = 1 + (i & 1), nj = 1 + (j & 1), nk = 1 + (k & 1);
@@ -720,6 +867,8 @@ __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l
 #pragma unroll
         for (int a = 0; a < 2; ++a) ec[4 * c + 2 * b + a] = row[i / 2 + (a < ni ? a : 0)];
       }
+    f_issued(ctl);
+    if (f_stop(ctl, P)) return;  // uniform
     double v = 0.0;
 #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -736,23 +885,50 @@ __global__ __launch_bounds__(kBlock) void mg_prolong_kernel(FieldParams P, int l
 // post-sweep writes z itself and the partial r.z to part[prz].
 template <bool Dot, int OP>
 __global__ __launch_bounds__(kBlock) void mg_sweep_kernel(FieldParams P, int l, int to_e2, int prz) {
-  if (f_done(f_ctrl(P), P)) return;  // uniform
   const MgLevel L = P.lv[l];  // (a copy: its fields load once, unconditionally)
   const double *in = to_e2 ? L.e : L.e2;
   double *out = to_e2 ? L.e2 : L.e;
   double rz = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
-       q += (int64_t)gridDim.x * kBlock) {
-    int i, j, k;
-    f_ijk(L, q, i, j, k);
-    if (f_dir(L, i, j, k)) {
-      out[q] = 0.0;
-      continue;
+  if constexpr (OP == kOpIFE) {
+    if (f_done(f_ctrl(P), P)) return;  // uniform
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+         q += (int64_t)gridDim.x * kBlock) {
+      int i, j, k;
+      f_ijk(L, q, i, j, k);
+      if (f_dir(L, i, j, k)) {
+        out[q] = 0.0;
+        continue;
+      }
+      const double bq = L.rhs[q];
+      const double v =
+          in[q] + kOmega * (bq - f_Ax<OP>(P, L, in, i, j, k, q)) / mg_D<OP>(P, L, i, j, k, q);
+      out[q] = v;
+      if constexpr (Dot) rz = rz + bq * v;
     }
-    const double bq = L.rhs[q];
-    const double v = in[q] + kOmega * (bq - f_Ax<OP>(P, L, in, i, j, k, q)) / mg_D<OP>(P, L, i, j, k, q);
-    out[q] = v;
-    if constexpr (Dot) rz = rz + bq * v;
+  } else {
+    if (l == 0 && f_done(f_ctrl(P), P)) return;  // uniform (see kFineExit)
+    for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < L.nodes;
+         q += (int64_t)gridDim.x * kBlock) {
+      int i, j, k;
+      f_ijk(L, q, i, j, k);
+      int2 ctl = f_ctl(P);
+      if (f_dir(L, i, j, k)) {
+        if (f_stop(ctl, P)) return;  // uniform
+        out[q] = 0.0;
+        continue;
+      }
+      const double bq = L.rhs[q], inq = in[q];
+      const int sd = OP == kOpIF ? L.side[q] : 1;
+      Nb6 g;
+      f_gather6(L, in, i, j, k, q, g);
+      f_issued(ctl);
+      if (f_stop(ctl, P)) return;  // uniform
+      const double v =
+          inq + kOmega * (bq - f_Ax6<OP>(P, L, q, inq, sd, g)) / mg_Ds<OP>(P, L, i, j, k, q, sd);
+      out[q] = v;
+      if constexpr (Dot) rz = rz + bq * v;
+    }
+    if (f_stop(f_ctl(P), P)) return;  // uniform (the threads without a node)
   }
   if constexpr (Dot) {
     rz = block_sum(rz);
