@@ -210,6 +210,27 @@ __device__ __forceinline__ double f_dside(const FieldParams &P, const Gd &L, int
   return d * L.ih2;
 }
 
+// eps of a fine-grid node without an explicit row (all its tetrahedra on one
+// side): from its side code (one byte) where that is set, which agrees with
+// the sign of its level set there, else from the level set itself
+__device__ __forceinline__ int ife_side(const FieldParams &P, int64_t q) {
+  return P.iface ? P.side[q] : 1;  // (1: outside, without an object)
+}
+
+__device__ __forceinline__ double ife_eps(const FieldParams &P, int64_t q, int sd) {
+  if (sd != 0) return sd == 2 ? P.e_in : P.e_out;
+  return P.psi[q] < 0.0 ? P.e_in : P.e_out;
+}
+
+// The diagonal of the IFE operator at fine-grid node q = (i, j, k) with row
+// index r = srow[q]: eps times the reference diagonal of its parity, or the
+// last entry of its row; the values ife_rows_kernel stores as the diagonal.
+__device__ __forceinline__ double ife_diag(const FieldParams &P, int i, int j, int k, int64_t q,
+                                           int32_t r, int sd) {
+  if (r < 0) return ife_eps(P, q, sd) * P.rld[(i + j + k) & 1];
+  return P.rows[(int64_t)r * (kIfeLinks + 1) + kIfeLinks];
+}
+
 // Visits the links of fine-grid node q = (i, j, k) of the IFE operator in
 // two passes: first val[l] = v(nb, i', j', k') for each of the 18 links l,
 // the neighbour's index and indices (clamped into the box where the link
@@ -219,9 +240,11 @@ __device__ __forceinline__ double f_dside(const FieldParams &P, const Gd &L, int
 // the box faces whose tetrahedra the interface does not cut (srow < 0) has
 // eps of its side times the reference links of its parity (a node of odd
 // parity has no face diagonals); the others have their assembled row.
-template <class V, class F>
+// ready(r, sd) runs between the two passes with the node's row index and
+// side code, loaded with the first pass.
+template <class V, class F, class R>
 __device__ __forceinline__ void ife_links(const FieldParams &P, int i, int j, int k, int64_t q,
-                                          V v, F f) {
+                                          V v, F f, R ready) {
   int ni[kIfeLinks], nj[kIfeLinks], nk[kIfeLinks];
   double val[kIfeLinks];
 #pragma unroll
@@ -236,11 +259,13 @@ __device__ __forceinline__ void ife_links(const FieldParams &P, int i, int j, in
     val[l] = v(q + (ni[l] - i) + P.sx * (nj[l] - j) + P.sy * (nk[l] - k), ni[l], nj[l], nk[l]);
   }
   const int32_t r = P.srow[q];
+  const int sd = ife_side(P, q);
+  ready(r, sd);
   if (r < 0) {
     // (the coefficients are constants of the launch, the parity only selects
     // between two of them)
     const bool odd = ((i + j + k) & 1) != 0;
-    const double e = (P.iface && P.psi[q] < 0.0) ? P.e_in : P.e_out;
+    const double e = ife_eps(P, q, sd);
 #pragma unroll
     for (int l = 0; l < 6; ++l)
       f(e * (odd ? P.rl[1][l] : P.rl[0][l]), val[l], ni[l], nj[l], nk[l]);
@@ -295,6 +320,12 @@ __device__ __forceinline__ double f_Ax6(const FieldParams &P, const Gd &L, int64
     for (int l = 0; l < 6; ++l) a = a + g.w[l] * (xq - g.xn[l]);
     return L.s * a;
   }
+}
+
+template <class V, class F>
+__device__ __forceinline__ void ife_links(const FieldParams &P, int i, int j, int k, int64_t q,
+                                          V v, F f) {
+  ife_links(P, i, j, k, q, v, f, [](int32_t, int) {});
 }
 
 // (A x) at an unknown node q of a grid (the fine grid or a level)
@@ -622,8 +653,8 @@ __device__ __forceinline__ double mg_Ds(const FieldParams &P, const MgLevel &L, 
       return (((((e + e) + e) + e) + e) + e) * L.ih2;
     }
     return f_dside(P, L, i, j, k, q, sd);
-  } else if constexpr (OP == kOpIFE) {
-    return L.diag[q];
+  } else if constexpr (OP == kOpIFE) {  // (the fine level only)
+    return ife_diag(P, i, j, k, q, P.srow[q], ife_side(P, q));
   } else {
     return L.s * f_dsum(L, i, j, k);
   }
@@ -652,12 +683,14 @@ __global__ __launch_bounds__(kBlock) void mg_pre_kernel(FieldParams P, int l) {
         continue;
       }
       const double bq = L.rhs[q];
-      const double d = mg_D<OP>(P, L, i, j, k, q);
-      const double e1 = kOmega * bq / d;
-      double a = 0.0;
+      double a = 0.0, d = 0.0, e1 = 0.0;
       ife_links(
           P, i, j, k, q, [&](int64_t nb, int, int, int) { return L.e2[nb]; },
-          [&](double c, double e1n, int, int, int) { a = a + c * (e1 - e1n); });
+          [&](double c, double e1n, int, int, int) { a = a + c * (e1 - e1n); },
+          [&](int32_t r, int sd) {  // (the diagonal once the row index is in)
+            d = ife_diag(P, i, j, k, q, r, sd);
+            e1 = kOmega * bq / d;
+          });
       L.e[q] = e1 + kOmega * (bq - a) / d;
     }
   } else {
@@ -815,12 +848,26 @@ __global__ __launch_bounds__(kBlock) void mg_restrict_kernel(FieldParams P, int 
 }
 
 // e of the coarsest level = A^-1 rhs on its m unknowns: one wave per row,
-// the right-hand side gathered into LDS.
+// the right-hand side gathered into LDS. The launch has a wave for every row
+// (m / 4 workgroups, rounded up), so each wave loads its row first, with the
+// gather, and adds it up in the order v = lane, lane + 64, ...
 __global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
   const MgLevel C = P.lv[P.levels - 1];
   __shared__ double sb[kCoarseNodes];
+  constexpr int kPer = (int)(kCoarseNodes / 64);  // row elements per lane
   const int m = P.m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int u = blockIdx.x * (kBlock / 64) + wave;
   int2 ctl = f_ctl(P);
+  double r[kPer];
+  if (u < m) {
+    const double *row = P.ainv + (int64_t)u * m;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int v = lane + 64 * t;
+      r[t] = row[v < m ? v : m - 1];  // (past m: an element of the row, unused)
+    }
+  }
   for (int v = threadIdx.x; v < m; v += kBlock) sb[v] = C.rhs[P.umap[v]];
   f_issued(ctl);
   if (f_stop(ctl, P)) return;  // uniform
@@ -831,11 +878,13 @@ __global__ __launch_bounds__(kBlock) void mg_coarse_kernel(FieldParams P) {
     if (f_dir(C, i, j, k)) C.e[q] = 0.0;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int u = blockIdx.x * (kBlock / 64) + wave; u < m; u += gridDim.x * (kBlock / 64)) {
-    const double *row = P.ainv + (int64_t)u * m;
+  if (u < m) {
     double a = 0.0;
-    for (int v = lane; v < m; v += 64) a = a + row[v] * sb[v];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int v = lane + 64 * t;
+      if (v < m) a = a + r[t] * sb[v];
+    }
     for (int o = 32; o >= 1; o >>= 1) a += __shfl_xor(a, o);
     if (lane == 0) C.e[P.umap[u]] = a;
   }
