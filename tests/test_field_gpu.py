@@ -100,6 +100,29 @@ def test_three_level_multigrid_matches_the_oracle(mask, tol, max_iter):
     assert np.abs(phi_n - ref_n).max() <= 1e-9 * np.abs(ref_n).max()
 
 
+@pytest.mark.parametrize("mask", [LUNAR_DIRICHLET, 1 | 2])
+def test_multigrid_with_one_cell_along_an_axis_matches_the_oracle(mask):
+    # 32 x 32 x 2 cells: the coarse level is 16 x 16 x 1, one cell along z,
+    # so that a node there has no z link on one side and its stand-in link
+    # (weight 0) is the node on the other side, a Dirichlet one with the
+    # lunar mask and a zero-Neumann one with phi fixed on the x faces
+    w = synth.scaled(synth.sphere_16(), 32, 32, 2, 4.0, name="thin_32x32x2")
+    ctx, sp, x, v = loaded_context(w, "fp64")
+    with ctx:
+        ctx.step(0)
+        rho, _ = ctx.get_rho()
+        it, rr = ctx.solve_field(mask, tol=1e-11, max_iter=2000)
+        levels = ctx.get_field_levels()
+        phi = ctx.get_phi()
+    info = {}
+    ref, it_ref, rr_ref = oracle.field_solve(w.nx, w.ny, w.nz, rho, mask, tol=1e-11, max_iter=2000,
+                                             info=info)
+    assert levels == info["levels"] == 2
+    assert rr <= 1e-11 and rr_ref <= 1e-11
+    assert abs(it - it_ref) <= 1
+    assert np.abs(phi - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
 def test_paper_settings_converge_and_the_oracle_agrees_on_the_residual():
     # the PCG of the paper's runs: tolerance 1e-6 within 150 iterations, on a
     # 64 x 64 x 32 crater-shaped mesh (4 levels), cold and warm started
