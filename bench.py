@@ -221,20 +221,37 @@ def serving_run(args):
     log(f"one at a time, Poisson {rate:.2f} req/s: p50 {seq['latency_p50_s']:.2f} s, "
         f"p99 {seq['latency_p99_s']:.2f} s, mean {seq['latency_mean_s']:.2f} s")
     batched = {}
-    # priority: the oldest request runs, younger ones beside it only in the
-    # room a small one leaves on the GPU; prefetch 2: at most two admitted
-    # to wait; fifo: nothing beside the head (strict arrival order); head
-    # half: the oldest running request gets half of a run's particle-steps,
-    # the others share the rest; fair share: equal shares
+    # priority (the default here): the oldest request runs, younger ones
+    # beside it only in the room a small one leaves on the GPU and only if
+    # they end no later than it (EASY-style backfill), at most one large
+    # request admitted to wait; priority_any_side: any younger request that
+    # fits the room, no admission bound; prefetch 2: at most two admitted to
+    # wait; fifo: nothing beside the head (strict arrival order); head half:
+    # the oldest running request gets half of a run's particle-steps, the
+    # others share the rest; fair share: equal shares
     M, P = args.steps_per_run, int(args.ps_per_run)
-    prio = dict(policy="priority", backfill=args.backfill, saturation=int(args.saturation))
-    for name, kw in [("priority", prio),
-                     ("priority_prefetch_2", dict(prio, prefetch=2)),
-                     ("priority_prefetch_large_1", dict(prio, prefetch_large=1)),
-                     ("priority_prefetch_large_2", dict(prio, prefetch_large=2)),
-                     ("priority_fifo", dict(prio, saturation=0)),
-                     ("head_half", dict(policy="head")),
-                     ("fair_share", dict(policy="fair"))]:
+    base = dict(policy="priority", backfill=args.backfill, saturation=int(args.saturation))
+    prio = dict(base, within_head=True, prefetch_large=1)
+    variants = [("priority", prio),
+                ("priority_within_head_sat_10M", dict(base, within_head=True,
+                                                      saturation=10_000_000)),
+                ("priority_within_head", dict(base, within_head=True)),
+                ("priority_any_side", base),
+                ("priority_prefetch_2", dict(base, prefetch=2)),
+                ("priority_prefetch_large_1", dict(base, prefetch_large=1)),
+                ("priority_prefetch_large_2", dict(base, prefetch_large=2)),
+                ("priority_sat_10M", dict(base, saturation=10_000_000)),
+                ("priority_sat_5M", dict(base, saturation=5_000_000)),
+                ("priority_fifo", dict(base, saturation=0)),
+                ("head_half", dict(policy="head")),
+                ("fair_share", dict(policy="fair"))]
+    if args.serve_variants:
+        keep = [v.strip() for v in args.serve_variants.split(",") if v.strip()]
+        unknown = set(keep) - {n for n, _ in variants}
+        if unknown:
+            raise SystemExit(f"unknown serving variants: {sorted(unknown)}")
+        variants = [(n, kw) for n, kw in variants if n in keep]
+    for name, kw in variants:
         ex = BatchExecutor(max_slots=args.slots, repr="fp32_cell", deposit="fixed64",
                            steps_per_run=M, hbm_budget_bytes=budget, particle_steps_per_run=P,
                            **kw)
@@ -440,6 +457,8 @@ def main():
     ap.add_argument("--saturation", type=float, default=2e7,
                     help="serving, priority policy: particles that fill the GPU")
     ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--serve-variants", default="",
+                    help="comma-separated batched policies to run (default: all)")
     ap.add_argument("--sweep", default="0.5,1.0",
                     help="--serve: further loads (comma-separated) run one at a time and "
                          "with the default batched policy")

@@ -50,7 +50,7 @@ class Request:
 
 def priority_weights(running: dict, remaining: dict, steps_per_run: int,
                      particle_steps_per_run: int, backfill: float = 0.0,
-                     saturation: int = 20_000_000) -> dict:
+                     saturation: int = 20_000_000, within_head: bool = False) -> dict:
     """Weights of the "priority" policy for the running requests (slot ->
     Request; `remaining`: slot -> steps left), in the units of pic_batch's
     share of a run (the particle-steps each request should take; 0 pauses it).
@@ -65,7 +65,10 @@ def priority_weights(running: dict, remaining: dict, steps_per_run: int,
     at most that fraction of the run's P particle-steps and never more than
     the head leaves of P at M steps (scaled down evenly beyond it); the head
     takes the rest of P (at most M steps). With P = 0 every running request
-    takes M steps."""
+    takes M steps. With ``within_head`` a younger request runs beside the
+    head only if it has no more steps left than the head (it ends no later,
+    so it never runs beside the next head: the rule of EASY backfilling,
+    in runs of M steps)."""
     if not running:
         return {}
     M, P = int(steps_per_run), int(particle_steps_per_run)
@@ -77,6 +80,8 @@ def priority_weights(running: dict, remaining: dict, steps_per_run: int,
     room = max(backfill * nh, saturation - nh)
     side = []
     for k in order[1:]:
+        if within_head and left[k] > left[head]:
+            continue
         if n[k] <= room:
             side.append(k)
             room -= n[k]
@@ -122,14 +127,16 @@ class BatchExecutor:
                     ``prefetch_particles`` of their particles, or
                     ``prefetch_large`` of those with at least ``saturation``
                     particles) admitted ahead (None: as many as slots and
-                    memory allow).
+                    memory allow); with ``within_head`` only requests that
+                    end no later than the head run beside it.
     """
 
     def __init__(self, max_slots: int, repr: str, deposit: str, steps_per_run: int,
                  hbm_budget_bytes: int, stream: int = 0, particle_steps_per_run: int = 0,
                  policy: str = "fair", head_share: float = 0.5, backfill: float = 0.0,
                  saturation: int = 20_000_000, prefetch: Optional[int] = None,
-                 prefetch_particles: Optional[int] = None, prefetch_large: Optional[int] = None):
+                 prefetch_particles: Optional[int] = None, prefetch_large: Optional[int] = None,
+                 within_head: bool = False):
         if policy not in ("fair", "head", "priority"):
             raise ValueError(f"unknown policy {policy!r}")
         if prefetch is not None and prefetch < 1:
@@ -160,6 +167,8 @@ class BatchExecutor:
         # particles: they can never run beside a head, and their loading is
         # the expensive one); small ones keep flowing
         self.prefetch_large = prefetch_large
+        # younger requests beside the head only if they end no later than it
+        self.within_head = bool(within_head)
         self.last_w = {}  # slot -> weight of the last launch
         self.retired = []  # finished (context, bytes), freed once the next run is launched
 
@@ -210,7 +219,7 @@ class BatchExecutor:
             w = priority_weights({k: v[0] for k, v in self.slots.items()},
                                  {k: self.batch.remaining(k) for k in self.slots},
                                  self.steps_per_run, self.particle_steps_per_run,
-                                 self.backfill, self.saturation)
+                                 self.backfill, self.saturation, self.within_head)
             for k, wk in w.items():
                 self.batch.set_weight(k, wk)
             self.last_w = w

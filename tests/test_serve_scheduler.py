@@ -252,6 +252,22 @@ def test_priority_weights_without_saturation_room():
     assert [k for k in w if w[k] > 0] == [0]
 
 
+def test_priority_weights_within_head_backfill_only_what_ends_first():
+    # EASY-style: beside the head only requests with no more steps left
+    running = {0: _req(0, 0.0, 1_000_000), 1: _req(1, 0.1, 2_000_000),
+               2: _req(2, 0.2, 3_000_000), 3: _req(3, 0.3, 4_000_000)}
+    left = {0: 300, 1: 500, 2: 300, 3: 100}
+    P, M = 10 ** 10, 256
+    w = priority_weights(running, left, M, P, saturation=20_000_000, within_head=True)
+    assert w[1] == 0.0 and w[0] > 0 and w[2] > 0 and w[3] > 0
+    # without the rule all three fit in the room beside the 1 M head
+    w = priority_weights(running, left, M, P, saturation=20_000_000)
+    assert min(w.values()) > 0
+    # the room still applies to the ones that end first
+    w = priority_weights(running, left, M, P, saturation=5_000_000, within_head=True)
+    assert w[2] > 0 and w[3] == 0.0 and w[1] == 0.0
+
+
 def test_priority_serving_keeps_every_request_moving_to_completion():
     # a simulated executor with the priority weights: paused requests take no
     # steps; every request completes and the oldest is never paused
