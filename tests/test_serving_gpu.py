@@ -57,17 +57,22 @@ def _same(a, b):
                                                      ("fp64", 150_000, "fair"),
                                                      ("fp32_cell", 150_000, "head"),
                                                      ("fp32_cell", 150_000, "priority"),
-                                                     ("fp64", 0, "priority")])
+                                                     ("fp64", 0, "priority"),
+                                                     ("fp32_cell", 150_000, "priority_within")])
 def test_alone_and_in_the_mix_are_identical(repr_, ps_per_run, policy):
     # ps_per_run > 0: unequal step quotas per run (fair share), so contexts of
     # one run leave the persistent launches at different steps; priority with
     # no saturation room: requests above a tenth of the oldest's size wait
-    # paused between runs
+    # paused between runs; priority_within: the default of the serving bench
+    # (room for all of these small requests beside the head, but only those
+    # with no more steps left than it, at most one large one waiting)
     arrivals = [0.0, 0.0, 0.0, 0.05, 0.1, 0.1, 0.3]
     mix = _requests(repr_, arrivals)
+    kw = dict(policy=policy, saturation=0, backfill=0.1)
+    if policy == "priority_within":
+        kw = dict(policy="priority", within_head=True, prefetch_large=1)
     ex = BatchExecutor(max_slots=3, repr=repr_, deposit="fixed64", steps_per_run=4,
-                       hbm_budget_bytes=64 << 30, particle_steps_per_run=ps_per_run,
-                       policy=policy, saturation=0, backfill=0.1)
+                       hbm_budget_bytes=64 << 30, particle_steps_per_run=ps_per_run, **kw)
     try:
         st = serve(mix, ex)
     finally:
