@@ -109,6 +109,19 @@ def test_crater_interface_with_surface_charge_matches_the_oracle(tol, max_iter):
     assert np.abs(phi_n - ref_n).max() <= 1e-9 * np.abs(ref_n).max()
 
 
+def test_crater_interface_on_a_grid_of_2048_dot_product_workgroups():
+    # 128 x 128 x 32 cells (549 K nodes, 5 levels): the dot-product kernels
+    # run their full 2048 workgroups, so the consumers add their partials
+    # eight at a time (the path of the crater_160 solve)
+    w = synth.scaled(synth.crater_160(), 128, 128, 32, 1.0, steps=2)
+    (phi, it, rr, lv), (ref, it_ref, rr_ref, lv_ref), r = run_and_solve(
+        w, "fp32_cell", 0, 2, ZP, 4.0, 1e-11, 300)
+    assert (w.nx + 1) * (w.ny + 1) * (w.nz + 1) >= 2048 * 256
+    assert r.tally.sum() > 100 and lv == lv_ref == 5
+    assert rr <= 1e-11 and rr_ref <= 1e-11 and abs(it - it_ref) <= 1
+    assert np.abs(phi - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
 def test_permittivity_changes_refresh_the_cached_operator():
     w = synth.scaled(synth.crater_160(), 32, 32, 16, 3.0, steps=10)
     sp, x, v, E = inputs(w)
