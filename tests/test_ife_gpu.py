@@ -145,6 +145,17 @@ def test_ife_crater_with_surface_charge_matches_the_oracle():
     assert np.abs(phi - ref).max() <= 1e-9 * np.abs(ref).max()
 
 
+def test_ife_crater_on_a_grid_of_2048_dot_product_workgroups():
+    # 128 x 128 x 32 cells (549 K nodes, 5 levels): the IFE kernels and the
+    # dot products at their full 2048 workgroups, as in the crater_160 solve
+    w = synth.scaled(synth.crater_160(), 128, 128, 32, 1.0, steps=2)
+    (phi, it, rr, lv, _), (ref, it_ref, rr_ref, lv_ref), r = run_and_solve(
+        w, "fp32_cell", 0, 2, ZP, 4.0, 1e-11, 300)
+    assert r.tally.sum() > 100 and lv == lv_ref == 5
+    assert rr <= 1e-11 and rr_ref <= 1e-11 and abs(it - it_ref) <= 1
+    assert np.abs(phi - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
 def test_ife_crater_at_the_papers_tolerance_follows_the_oracles_iterates():
     # tol 1e-6 (the paper's): both converge within an iteration of each other;
     # then both run exactly the oracle's iteration count (a tolerance neither
