@@ -422,8 +422,10 @@ __device__ __forceinline__ void step_block(const StepParams &P, const int block)
   __shared__ Src sSrc[PIC_MAX_SPECIES];
   __shared__ int32_t sTotal;
   // movers of the current species, staged so that they leave the workgroup as
-  // contiguous runs per destination tile (one reservation per destination)
-  constexpr int kMovers = sizeof(T) == 4 ? 320 : 160;
+  // contiguous runs per destination tile (one reservation per destination);
+  // the rest of a tile's movers reserve one slot each. The 4-byte forms stage
+  // as many as fit with five workgroups per CU (30.6 KB of LDS each).
+  constexpr int kMovers = sizeof(T) == 4 ? 400 : 160;
   __shared__ Particle<T> sMv[PUSH ? kMovers : 1];
   __shared__ int32_t sMvDst[PUSH ? kMovers : 1];   // destination tile
   __shared__ int16_t sMvRel[PUSH ? kMovers : 1];   // its 27-neighbour index, or -1
